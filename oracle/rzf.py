@@ -1,0 +1,309 @@
+"""Plain FP64 CPU oracle of WB-arSVD RZF precoding (complex128, NumPy/LAPACK).
+
+TEST INFRASTRUCTURE.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this module.  It shares no code with the GPU path:
+the two meet only in the seeded input generator (the channel tracks) and in the
+published definition of the sketch generator, which each side implements on
+its own.
+
+Each function follows one passage of the paper, in the paper's order and
+notation (A is the Gram matrix, Delta A its per-step correction):
+
+  gram               Sec. II, eq. (5):   A = H H^H + alpha I_K
+  gram_correction    Sec. III, eq. (9):  Delta A = H dH^H + dH H^H + dH dH^H
+  direct_inverse     Alg. 2, "direct matrix inversion"
+  arsvd              Alg. 1 and the energy rule of eq. (14)
+  woodbury           eq. (12), evaluated in the order of Sec. III-A steps 1-5
+  precoder           eq. (5) with the power constraint ||W||_F^2 = P
+  sum_rate           eq. (15)
+  OracleTrack        Alg. 2, with an optional periodic exact re-inversion
+
+Readings taken where the paper is silent (each is also listed with the design
+notes of the repository):
+  * Delta A = 0 gives r = 0 and leaves the inverse unchanged.
+  * "Non-zero singular values" (Sec. III): components with sigma_j == 0 are
+    dropped from Sigma_r before eq. (12) inverts it.
+  * The switch of Alg. 2 is inclusive: Woodbury when r <= 0.5 K.
+  * The capacitance C is treated as singular when its smallest singular value
+    is at most SINGULAR_RTOL (||Sigma_r^-1||_2 + ||V_r^H A^-1 U_r||_2); the
+    step then inverts A' directly (path FULL_SINGULAR).
+  * I_max (never given) defaults to the smallest I with
+    k_init 2^(I-1) + p >= K, i.e. the doubling reaches d = K.
+  * The row-n channel of eq. (15) is row n of H (H = [h_1 ... h_K]^T), so the
+    received-signal matrix is E = H W.
+  * The periodic exact re-inversion (reset_period) is not part of the paper; it
+    bounds the drift of the stored inverse and is off unless asked for.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional
+
+import numpy as np
+
+from .philox import draw_sketch
+
+PATH_NOOP = 0
+PATH_WB = 1
+PATH_FULL_RANK = 2
+PATH_FULL_SINGULAR = 3
+PATH_RESET = 4
+PATH_NAMES = {PATH_NOOP: "noop", PATH_WB: "wb", PATH_FULL_RANK: "full_rank",
+              PATH_FULL_SINGULAR: "full_singular", PATH_RESET: "reset"}
+
+KINIT_FIXED = 0
+KINIT_WARM = 1
+
+SINGULAR_RTOL = 1e-13
+
+
+def fro2(X: np.ndarray) -> float:
+    """Squared Frobenius norm."""
+    return float(np.sum(X.real ** 2 + X.imag ** 2))
+
+
+def hermitian(X: np.ndarray) -> np.ndarray:
+    return X.conj().T
+
+
+def gram(H: np.ndarray, alpha: float) -> np.ndarray:
+    """A = H H^H + alpha I_K (Sec. II, eq. (5))."""
+    K = H.shape[0]
+    return H @ hermitian(H) + alpha * np.eye(K, dtype=np.complex128)
+
+
+def gram_correction(H: np.ndarray, dH: np.ndarray) -> np.ndarray:
+    """Delta A = H dH^H + dH H^H + dH dH^H (Sec. III, eq. (9))."""
+    return H @ hermitian(dH) + dH @ hermitian(H) + dH @ hermitian(dH)
+
+
+def direct_inverse(A: np.ndarray) -> np.ndarray:
+    """A^{-1} by direct (LU) inversion (Alg. 2)."""
+    return np.linalg.inv(A)
+
+
+def default_imax(K: int, k_init: int, p: int) -> int:
+    """Smallest I with k_init * 2^(I-1) + p >= K."""
+    i, k0 = 1, k_init
+    while k0 + p < K:
+        k0 *= 2
+        i += 1
+    return i
+
+
+@dataclasses.dataclass
+class ArsvdResult:
+    U: np.ndarray          # K x r, U_r
+    s: np.ndarray          # r, diagonal of Sigma_r (descending)
+    V: np.ndarray          # K x r, V_r
+    r: int                 # k_est
+    iters: int             # iterations run
+    d: int                 # subspace dimension of the last iteration
+    sigma: np.ndarray      # all d singular values of the last B
+    energy: float          # ||Delta A||_F^2
+    captured: float        # sum_{j<=r} sigma_j^2
+
+
+def arsvd(dA: np.ndarray, eta: float, k_init: int, p: int, i_max: int,
+          draw: Callable[[int, int, int], np.ndarray],
+          force_iters: Optional[int] = None, force_r: Optional[int] = None) -> ArsvdResult:
+    """Adaptive randomized SVD (Alg. 1).
+
+    draw(i, K, d) returns the K x d CN(0,1) matrix Omega of iteration i.
+    force_iters / force_r replay a run whose rank decisions were taken
+    elsewhere (used only when another implementation's decision fell within
+    rounding distance of the threshold): the loop then runs exactly
+    force_iters iterations and returns rank force_r from the last one.
+    """
+    K = dA.shape[0]
+    energy = fro2(dA)
+    E_target = eta * energy
+    if energy == 0.0:
+        z = np.zeros((K, 0), dtype=np.complex128)
+        return ArsvdResult(z, np.zeros(0), z, 0, 0, 0, np.zeros(0), 0.0, 0.0)
+    k0 = k_init
+    n_iter = i_max if force_iters is None else force_iters
+    for i in range(1, n_iter + 1):
+        d = min(k0 + p, K)
+        Omega = draw(i, K, d)
+        Y = dA @ Omega
+        Q, _ = np.linalg.qr(Y, mode="reduced")          # Q = orth(Y)
+        B = hermitian(Q) @ dA
+        Uh, s, Vh = np.linalg.svd(B, full_matrices=False)
+        U_approx = Q @ Uh
+        V_hat = hermitian(Vh)
+        csum = np.cumsum(s ** 2)
+        last = (i == n_iter)
+        if force_iters is not None:
+            if last and force_r is not None:
+                r = force_r
+                return ArsvdResult(U_approx[:, :r], s[:r], V_hat[:, :r], r, i, d, s,
+                                   energy, float(csum[r - 1]) if r > 0 else 0.0)
+            hit = np.nonzero(csum >= E_target)[0]
+            if last and hit.size:
+                r = int(hit[0]) + 1
+                return ArsvdResult(U_approx[:, :r], s[:r], V_hat[:, :r], r, i, d, s,
+                                   energy, float(csum[r - 1]))
+        else:
+            hit = np.nonzero(csum >= E_target)[0]
+            if hit.size:                                 # smallest r found
+                r = int(hit[0]) + 1
+                return ArsvdResult(U_approx[:, :r], s[:r], V_hat[:, :r], r, i, d, s,
+                                   energy, float(csum[r - 1]))
+        k0 = 2 * k0
+    # no r met the target: return all d components (k_est = d)
+    return ArsvdResult(U_approx[:, :d], s[:d], V_hat[:, :d], d, n_iter, d, s,
+                       energy, float(csum[d - 1]))
+
+
+def woodbury(Ainv: np.ndarray, U: np.ndarray, s: np.ndarray, V: np.ndarray):
+    """(A + U Sigma V^H)^{-1} from A^{-1} by eq. (12), steps 1-5 of Sec. III-A.
+
+    Returns (new inverse, singular) where singular flags a capacitance
+    (Sigma^{-1} + V^H A^{-1} U) too close to singular to invert.
+    """
+    keep = s != 0.0                      # Sigma_r holds the non-zero sigma_j
+    U, s, V = U[:, keep], s[keep], V[:, keep]
+    if s.size == 0:
+        return Ainv.copy(), False
+    Vh = hermitian(V)
+    AU = Ainv @ U                        # step 1: A^{-1} U_r
+    C = np.diag(1.0 / s) + Vh @ AU       # step 2: Sigma_r^{-1} + V_r^H A^{-1} U_r
+    # singular when the smallest singular value of C vanishes next to the
+    # size of its two terms
+    scale = 1.0 / s.min() + np.linalg.norm(Vh @ AU, 2)
+    if np.linalg.svd(C, compute_uv=False).min() <= SINGULAR_RTOL * scale:
+        return None, True
+    Cinv = np.linalg.inv(C)              # step 3
+    VA = Vh @ Ainv
+    T = (AU @ Cinv) @ VA                 # step 4
+    return Ainv - T, False               # step 5
+
+
+def precoder(H: np.ndarray, Ainv: np.ndarray, P: float) -> np.ndarray:
+    """W = H^H A^{-1} scaled so that ||W||_F^2 = P (eq. (5), Sec. II)."""
+    W = hermitian(H) @ Ainv
+    return W * math.sqrt(P / fro2(W))
+
+
+def full_rzf(H: np.ndarray, alpha: float, P: float) -> np.ndarray:
+    """Conventional RZF: full inversion of the Gram matrix every snapshot."""
+    return precoder(H, direct_inverse(gram(H, alpha)), P)
+
+
+def sum_rate(H: np.ndarray, W: np.ndarray, P: float, sigma2: float):
+    """Per-user rates and the sum rate of eq. (15) after scaling ||W||_F^2 = P."""
+    W = W * math.sqrt(P / fro2(W))
+    E = H @ W
+    K = H.shape[0]
+    rates = np.empty(K)
+    for n in range(K):
+        sig = abs(E[n, n]) ** 2
+        interf = sum(abs(E[n, i]) ** 2 for i in range(K) if i != n)
+        rates[n] = math.log2(1.0 + sig / (interf + sigma2))
+    return rates, float(np.sum(rates))
+
+
+@dataclasses.dataclass
+class TrackParams:
+    alpha: float
+    P: float = 1.0
+    k_init: int = 2
+    p: int = 5
+    i_max: int = 0              # 0: default_imax
+    switch_ratio: float = 0.5
+    reset_period: int = 0
+    seed: int = 0
+    track_id: int = 0
+    kinit_policy: int = KINIT_FIXED
+
+
+@dataclasses.dataclass
+class UpdateInfo:
+    r: int
+    iters: int
+    path: int
+    dA_fro2: float
+    captured: float
+    d: int
+
+    @property
+    def energy_ratio(self) -> float:
+        return self.captured / self.dA_fro2 if self.dA_fro2 > 0 else 1.0
+
+
+class OracleTrack:
+    """Alg. 2 on one channel track: the inverse carried across snapshots."""
+
+    def __init__(self, H0: np.ndarray, params: TrackParams):
+        self.params = params
+        self.K, self.N = H0.shape
+        self.Ainv = direct_inverse(gram(H0, params.alpha))
+        self.H_prev = np.array(H0, dtype=np.complex128)
+        self.t = 0
+        self.since_exact = 0
+        self.last_r = 0
+
+    def i_max(self) -> int:
+        p = self.params
+        return p.i_max if p.i_max > 0 else default_imax(self.K, p.k_init, p.p)
+
+    def draw(self, t: int):
+        p = self.params
+        return lambda i, K, d: draw_sketch(p.seed, p.track_id, t, i, K, d)
+
+    def update(self, H: np.ndarray, eta: float, force_iters: Optional[int] = None,
+               force_r: Optional[int] = None):
+        """One snapshot: returns (W, UpdateInfo)."""
+        prm = self.params
+        H = np.asarray(H, dtype=np.complex128)
+        self.t += 1
+        t = self.t
+        dH = H - self.H_prev
+        dA = gram_correction(self.H_prev, dH)            # eq. (9)
+        A_new = gram(H, prm.alpha)                       # eq. (7)
+        energy = fro2(dA)
+        if prm.reset_period > 0 and self.since_exact + 1 >= prm.reset_period:
+            self.Ainv = direct_inverse(A_new)
+            info = UpdateInfo(0, 0, PATH_RESET, energy, 0.0, 0)
+            self.since_exact = 0
+        else:
+            k_init = prm.k_init
+            if prm.kinit_policy == KINIT_WARM:
+                k_init = max(prm.k_init, self.last_r)
+            res = arsvd(dA, eta, k_init, prm.p, self.i_max(), self.draw(t),
+                        force_iters=force_iters, force_r=force_r)
+            info = UpdateInfo(res.r, res.iters, PATH_NOOP, energy, res.captured, res.d)
+            if res.r == 0:
+                info.path = PATH_NOOP
+                self.since_exact += 1
+            elif res.r <= prm.switch_ratio * self.K:   # Alg. 2: k_est/K <= 0.5
+                new, singular = woodbury(self.Ainv, res.U, res.s, res.V)
+                if singular:
+                    self.Ainv = direct_inverse(A_new)
+                    info.path = PATH_FULL_SINGULAR
+                    self.since_exact = 0
+                else:
+                    self.Ainv = new
+                    info.path = PATH_WB
+                    self.since_exact += 1
+            else:
+                self.Ainv = direct_inverse(A_new)
+                info.path = PATH_FULL_RANK
+                self.since_exact = 0
+            self.last_r = res.r
+        self.H_prev = H
+        W = precoder(H, self.Ainv, prm.P)
+        return W, info
+
+    def export_state(self):
+        return dict(Ainv=self.Ainv.copy(), H_prev=self.H_prev.copy(), t=self.t,
+                    since_exact=self.since_exact, last_r=self.last_r)
+
+    def import_state(self, st):
+        self.Ainv = np.array(st["Ainv"], dtype=np.complex128)
+        self.H_prev = np.array(st["H_prev"], dtype=np.complex128)
+        self.t = int(st["t"])
+        self.since_exact = int(st["since_exact"])
+        self.last_r = int(st["last_r"])
