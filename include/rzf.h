@@ -1,0 +1,173 @@
+/*
+ * rzf.h -- C ABI of the MI355X (gfx950) WB-arSVD RZF precoding library.
+ *
+ * Method: Momani, Delamotte, Knopp, "Efficient Precoding for LEO Satellites: A
+ * Low-Complexity Matrix Inversion Method via Woodbury Matrix Identity and
+ * arSVD" (arXiv 2512.16543).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Complex numbers are interleaved single precision (rzf_c32, the layout of
+ *    torch.complex64).
+ *  - H is K x N, row-major, leading dimension ldh >= N: row n is the channel
+ *    h_n^T of user n (Sec. II, eq. (1)).  K users, N transmit antennas; the
+ *    analog combiner of eq. (4) is the identity (fully digital, N_RF = N).
+ *  - W is N x K, row-major, leading dimension ldw >= K: column n is the
+ *    precoding vector of user n (eq. (5)).
+ *  - Every matrix argument is a DEVICE pointer (e.g. a torch tensor's
+ *    data_ptr()).  The caller owns H and W; the library owns the per-track
+ *    state, which it places in the arena given to rzf_ctx_create.
+ *  - Calls that launch work are asynchronous on the context's HIP stream.
+ *    Device-side failures (a non-positive pivot, a non-finite input) are
+ *    recorded on the device and returned by the next rzf_sync; info records
+ *    requested with a host pointer are filled in by that rzf_sync.
+ *  - Nothing throws across this boundary; errors are status codes.  A call
+ *    that returns an error has launched nothing.
+ *  - Supported sizes: 1 <= K <= RZF_KMAX, 1 <= N <= RZF_NMAX.
+ */
+#ifndef RZF_H
+#define RZF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RZF_KMAX 64
+#define RZF_NMAX 4096
+
+typedef struct { float re, im; } rzf_c32;
+
+typedef struct rzf_ctx rzf_ctx;       /* device, stream, arena, error word */
+typedef struct rzf_track rzf_track;   /* state of one channel track        */
+
+typedef enum {
+  RZF_OK = 0,
+  RZF_E_INVALID = 1,    /* bad argument: NULL, alpha < 0, tol outside (0,1], ... */
+  RZF_E_SHAPE = 2,      /* K, N or a leading dimension out of range            */
+  RZF_E_NOMEM = 3,      /* the arena cannot hold the track (admission refused) */
+  RZF_E_NOT_HPD = 4,    /* Gram matrix not Hermitian positive definite         */
+  RZF_E_NONFINITE = 5,  /* NaN or Inf met in an input or a factorisation       */
+  RZF_E_DEVICE = 6      /* a HIP runtime call failed                           */
+} rzf_status;
+
+/* Which branch of Alg. 2 an update took. */
+typedef enum {
+  RZF_PATH_NOOP = 0,          /* Delta A = 0: inverse kept                        */
+  RZF_PATH_WB = 1,            /* k_est/K <= switch: Woodbury update, eq. (12)     */
+  RZF_PATH_FULL_RANK = 2,     /* k_est/K > switch: direct inversion of A'         */
+  RZF_PATH_FULL_SINGULAR = 3, /* capacitance singular (Sec. III): direct inversion */
+  RZF_PATH_RESET = 4          /* periodic FP64 re-inversion (drift bound)          */
+} rzf_path;
+
+typedef enum { RZF_KINIT_FIXED = 0, RZF_KINIT_WARM = 1 } rzf_kinit_policy;
+
+/* Parameters of one track; rzf_params_default fills the paper's values. */
+typedef struct {
+  int k_init;           /* initial rank estimate of Alg. 1 (Table IV: 2)          */
+  int p;                /* oversampling of Alg. 1 (Table IV: 1; workloads use 5)  */
+  int i_max;            /* Alg. 1 iteration cap; 0 = smallest I with
+                           k_init * 2^(I-1) + p >= K                               */
+  double switch_ratio;  /* Alg. 2: Woodbury when k_est <= switch_ratio * K (0.5)  */
+  int reset_period;     /* re-invert A' in FP64 once this many steps have passed
+                           since the last FP64 inversion (init or reset), skipping
+                           Alg. 1 on that step; 0 = never                         */
+  double P;             /* total transmit power, ||W||_F^2 = P (Sec. II)          */
+  uint64_t seed;        /* sketch key word 0                                       */
+  uint64_t track_id;    /* sketch key word 1                                       */
+  int kinit_policy;     /* RZF_KINIT_FIXED: k0 = k_init every step (Alg. 1);
+                           RZF_KINIT_WARM: k0 = max(k_init, previous k_est)        */
+} rzf_params;
+
+/* Outcome of one rzf_update. */
+typedef struct {
+  int r;            /* k_est of Alg. 1 (0 on NOOP and RESET)                     */
+  int iters;        /* Alg. 1 iterations run                                      */
+  int path;         /* rzf_path                                                   */
+  int d;            /* subspace dimension of the last iteration                   */
+  double dA_fro2;   /* ||Delta A||_F^2                                            */
+  double captured;  /* sum_{j<=r} sigma_j^2 (the retained energy of eq. (14))     */
+} rzf_update_info;
+
+const char* rzf_status_string(rzf_status s);
+
+/* Fill *p with k_init=2, p=5, i_max=0, switch_ratio=0.5, reset_period=0,
+ * P=1, seed=0, track_id=0, kinit_policy=FIXED.  RZF_E_INVALID if p is NULL. */
+rzf_status rzf_params_default(rzf_params* p);
+
+/* Bytes of arena one track of size K x N occupies (0 if out of range). */
+size_t rzf_track_bytes(int K, int N);
+
+/* Create a context on HIP device `device`, launching on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  `arena` is device memory of
+ * `arena_bytes` bytes owned by the caller and kept alive until
+ * rzf_ctx_destroy; track state is carved from it.  If arena is NULL the
+ * library allocates arena_bytes itself and frees it in rzf_ctx_destroy. */
+rzf_status rzf_ctx_create(int device, void* hip_stream, void* arena, size_t arena_bytes,
+                          rzf_ctx** out);
+rzf_status rzf_ctx_destroy(rzf_ctx* ctx);
+
+/* Wait for all work on the context's stream, fill pending info records, and
+ * return (then clear) the first device-side error recorded since the last
+ * rzf_sync. */
+rzf_status rzf_sync(rzf_ctx* ctx);
+
+/* Alg. 2, else-branch: build the state of a new track from its first snapshot.
+ * A = H H^H + alpha I_K (eq. (5)) and A^-1 are formed in FP64 and A^-1 is
+ * stored in FP32.  alpha >= 0 (eq. (5)).  Synchronous: returns RZF_E_NOT_HPD
+ * if A is not positive definite, RZF_E_NONFINITE for non-finite H,
+ * RZF_E_NOMEM if the arena is full. */
+rzf_status rzf_init(rzf_ctx* ctx, int K, int N, const rzf_c32* H, int ldh, double alpha,
+                    const rzf_params* params, rzf_track** out);
+
+/* Alg. 2, if-branch, for the next snapshot H_t of the track:
+ *   Delta A from eq. (9); Alg. 1 (arSVD) with energy threshold eta = tol
+ *   (eq. (14)); Woodbury update of A^-1 by eq. (12) when k_est <= switch*K,
+ *   else direct inversion of A'; then W = H_t^H A'^-1 with ||W||_F^2 = P.
+ * tol in (0, 1].  The Woodbury capacitance is factorised in FP64.
+ * `info` (host pointer, may be NULL) is filled by the next rzf_sync. */
+rzf_status rzf_update(rzf_track* tr, const rzf_c32* H_t, int ldh, double tol,
+                      rzf_c32* W, int ldw, rzf_update_info* info);
+
+/* Conventional RZF (the baseline of Sec. V): W = H^H (H H^H + alpha I)^-1,
+ * full FP32 inversion, scaled to ||W||_F^2 = P.  Asynchronous; a
+ * non-positive-definite Gram matrix is reported as RZF_E_NOT_HPD by the next
+ * rzf_sync. */
+rzf_status rzf_full(rzf_ctx* ctx, int K, int N, const rzf_c32* H, int ldh, double alpha,
+                    double P, rzf_c32* W, int ldw);
+
+/* Sum rate of eq. (15): W is first scaled to ||W||_F^2 = P, then E = H W,
+ * SINR_n = |E_nn|^2 / (sum_{i != n} |E_ni|^2 + sigma2), rate_n = log2(1+SINR_n).
+ * rates: device pointer to K floats, or NULL.  sum_rate: host pointer; if not
+ * NULL the call synchronises the stream and stores the FP64 sum. */
+rzf_status rzf_sum_rate(rzf_ctx* ctx, int K, int N, const rzf_c32* H, int ldh,
+                        const rzf_c32* W, int ldw, double P, double sigma2,
+                        float* rates, double* sum_rate);
+
+/* Copy the track's stored inverse (K x K, row-major, ld = K) to device memory
+ * Ainv.  Asynchronous. */
+rzf_status rzf_get_inverse(rzf_track* tr, rzf_c32* Ainv);
+
+/* Host-side view of the track: sizes, step count, steps since the last FP64
+ * inversion, previous k_est.  Synchronises the stream.  NULL outputs are
+ * skipped. */
+rzf_status rzf_track_query(rzf_track* tr, int* K, int* N, int* t, int* since_reset,
+                           int* last_r);
+
+/* Release the track's arena space (after its queued work has finished). */
+rzf_status rzf_track_destroy(rzf_track* tr);
+
+/* The Gaussian sketch Omega of Alg. 1 for (seed, track_id, step t, iteration
+ * it), K x d, written column-major (entry (i, j) at Omega[j*K + i]) as FP32
+ * complex, and the two Philox4x64-10 words behind each entry to words
+ * (uint64, 2*K*d, entry-major; may be NULL).  Both device pointers.  For
+ * checking the generator against an independent implementation. */
+rzf_status rzf_debug_sketch(rzf_ctx* ctx, uint64_t seed, uint64_t track_id, int t, int it,
+                            int K, int d, rzf_c32* Omega, uint64_t* words);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RZF_H */

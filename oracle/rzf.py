@@ -32,7 +32,10 @@ notes of the repository):
   * The row-n channel of eq. (15) is row n of H (H = [h_1 ... h_K]^T), so the
     received-signal matrix is E = H W.
   * The periodic exact re-inversion (reset_period) is not part of the paper; it
-    bounds the drift of the stored inverse and is off unless asked for.
+    bounds the drift of the stored inverse and is off unless asked for.  It
+    fires once reset_period steps have passed since the last FP64 inversion
+    (the initial one or a reset); inversions of A' taken by Alg. 2's own
+    fallback do not restart the count.  A reset step skips Alg. 1.
 """
 from __future__ import annotations
 
@@ -242,7 +245,7 @@ class OracleTrack:
         self.Ainv = direct_inverse(gram(H0, params.alpha))
         self.H_prev = np.array(H0, dtype=np.complex128)
         self.t = 0
-        self.since_exact = 0
+        self.since_reset = 0
         self.last_r = 0
 
     def i_max(self) -> int:
@@ -264,10 +267,10 @@ class OracleTrack:
         dA = gram_correction(self.H_prev, dH)            # eq. (9)
         A_new = gram(H, prm.alpha)                       # eq. (7)
         energy = fro2(dA)
-        if prm.reset_period > 0 and self.since_exact + 1 >= prm.reset_period:
+        if prm.reset_period > 0 and self.since_reset + 1 >= prm.reset_period:
             self.Ainv = direct_inverse(A_new)
-            info = UpdateInfo(0, 0, PATH_RESET, energy, 0.0, 0)
-            self.since_exact = 0
+            info = UpdateInfo(0, 0, PATH_RESET, 0.0, 0.0, 0)
+            self.since_reset = 0
         else:
             k_init = prm.k_init
             if prm.kinit_policy == KINIT_WARM:
@@ -277,21 +280,18 @@ class OracleTrack:
             info = UpdateInfo(res.r, res.iters, PATH_NOOP, energy, res.captured, res.d)
             if res.r == 0:
                 info.path = PATH_NOOP
-                self.since_exact += 1
             elif res.r <= prm.switch_ratio * self.K:   # Alg. 2: k_est/K <= 0.5
                 new, singular = woodbury(self.Ainv, res.U, res.s, res.V)
                 if singular:
                     self.Ainv = direct_inverse(A_new)
                     info.path = PATH_FULL_SINGULAR
-                    self.since_exact = 0
                 else:
                     self.Ainv = new
                     info.path = PATH_WB
-                    self.since_exact += 1
             else:
                 self.Ainv = direct_inverse(A_new)
                 info.path = PATH_FULL_RANK
-                self.since_exact = 0
+            self.since_reset += 1
             self.last_r = res.r
         self.H_prev = H
         W = precoder(H, self.Ainv, prm.P)
@@ -299,11 +299,11 @@ class OracleTrack:
 
     def export_state(self):
         return dict(Ainv=self.Ainv.copy(), H_prev=self.H_prev.copy(), t=self.t,
-                    since_exact=self.since_exact, last_r=self.last_r)
+                    since_reset=self.since_reset, last_r=self.last_r)
 
     def import_state(self, st):
         self.Ainv = np.array(st["Ainv"], dtype=np.complex128)
         self.H_prev = np.array(st["H_prev"], dtype=np.complex128)
         self.t = int(st["t"])
-        self.since_exact = int(st["since_exact"])
+        self.since_reset = int(st["since_reset"])
         self.last_r = int(st["last_r"])

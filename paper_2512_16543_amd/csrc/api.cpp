@@ -1,0 +1,459 @@
+// Host runtime behind rzf.h: context (device, stream, arena, error word),
+// track state in the arena, launch sequences of rzf_init / rzf_update /
+// rzf_full / rzf_sum_rate, and deferred info records.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <set>
+#include <vector>
+
+#include "rzf.h"
+#include "rzf_internal.h"
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int PIN_CHUNK = 4096;   // info records per pinned chunk
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+struct Pending {
+  DevInfo* slot;
+  rzf_update_info* dst;
+};
+
+}  // namespace
+
+struct rzf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  bool own_arena = false;
+  std::map<size_t, size_t> free_blocks;   // offset -> size
+  // fixed scratch at the front of the arena
+  int* d_err = nullptr;
+  float2* d_fullA = nullptr;
+  float2* d_fullAinv = nullptr;
+  double* d_fullwpart = nullptr;
+  double* d_sum = nullptr;
+  // pinned host staging
+  double* h_sum = nullptr;
+  int* h_err = nullptr;
+  std::vector<DevInfo*> pin_chunks;
+  size_t pin_used = 0;
+  std::vector<Pending> pending;
+  std::set<rzf_track*> tracks;
+  std::mutex mu;
+};
+
+struct rzf_track {
+  rzf_ctx* ctx = nullptr;
+  int K = 0, N = 0;
+  rzf_params prm{};
+  double alpha = 0.0;
+  size_t off = 0, bytes = 0;
+  TrackDesc* d_desc = nullptr;
+  TrackDesc h_desc{};
+  int t = 0;
+  int since_reset = 0;
+  int i_max = 0;
+};
+
+namespace {
+
+size_t scratch_bytes() {
+  return align_up(sizeof(int) * 64) + 2 * align_up(sizeof(float2) * KM * KM) +
+         align_up(sizeof(double) * ((RZF_NMAX + 15) / 16)) + align_up(sizeof(double) * 8);
+}
+
+struct Layout {
+  size_t desc, ainv, hprev, anew, da, a64, wpart, total;
+};
+
+Layout track_layout(int K, int N) {
+  Layout L{};
+  size_t o = 0;
+  L.desc = o; o += align_up(sizeof(TrackDesc));
+  L.ainv = o; o += align_up(sizeof(float2) * K * K);
+  L.hprev = o; o += align_up(sizeof(float2) * (size_t)K * N);
+  L.anew = o; o += align_up(sizeof(float2) * K * K);
+  L.da = o; o += align_up(sizeof(float2) * K * K);
+  L.a64 = o; o += align_up(sizeof(double2) * K * K);
+  L.wpart = o; o += align_up(sizeof(double) * precoder_blocks(N));
+  L.total = o;
+  return L;
+}
+
+bool arena_alloc(rzf_ctx* c, size_t bytes, size_t* off) {
+  for (auto it = c->free_blocks.begin(); it != c->free_blocks.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t noff = it->first + bytes;
+      c->free_blocks.erase(it);
+      if (rest) c->free_blocks[noff] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+void arena_free(rzf_ctx* c, size_t off, size_t bytes) {
+  auto it = c->free_blocks.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != c->free_blocks.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    c->free_blocks.erase(nx);
+  }
+  if (it != c->free_blocks.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      c->free_blocks.erase(it);
+    }
+  }
+}
+
+DevInfo* pin_slot(rzf_ctx* c) {
+  const size_t chunk = c->pin_used / PIN_CHUNK, idx = c->pin_used % PIN_CHUNK;
+  if (chunk >= c->pin_chunks.size()) {
+    DevInfo* p = nullptr;
+    if (hipHostMalloc((void**)&p, sizeof(DevInfo) * PIN_CHUNK, hipHostMallocDefault) != hipSuccess)
+      return nullptr;
+    c->pin_chunks.push_back(p);
+  }
+  ++c->pin_used;
+  return c->pin_chunks[chunk] + idx;
+}
+
+rzf_status dev_status(int code) {
+  if (code == DEV_ERR_NOT_HPD) return RZF_E_NOT_HPD;
+  if (code == DEV_ERR_NONFINITE) return RZF_E_NONFINITE;
+  return code ? RZF_E_DEVICE : RZF_OK;
+}
+
+#define HIP_OK(x) do { if ((x) != hipSuccess) return RZF_E_DEVICE; } while (0)
+
+bool params_valid(const rzf_params* p) {
+  return p->k_init >= 1 && p->p >= 0 && p->i_max >= 0 && p->i_max <= 64 &&
+         std::isfinite(p->switch_ratio) && p->switch_ratio > 0.0 && p->switch_ratio <= 1.0 &&
+         p->reset_period >= 0 && std::isfinite(p->P) && p->P > 0.0 &&
+         (p->kinit_policy == RZF_KINIT_FIXED || p->kinit_policy == RZF_KINIT_WARM);
+}
+
+int default_imax(int K, int k_init, int p) {
+  int i = 1;
+  long k0 = k_init;
+  while (k0 + p < K) { k0 *= 2; ++i; }
+  return i;
+}
+
+rzf_status sync_and_collect(rzf_ctx* c) {
+  HIP_OK(hipStreamSynchronize(c->stream));
+  for (const Pending& pd : c->pending) {
+    if (pd.dst) std::memcpy(pd.dst, pd.slot, sizeof(rzf_update_info));
+  }
+  c->pending.clear();
+  c->pin_used = 0;
+  HIP_OK(hipMemcpy(c->h_err, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  const int code = *c->h_err;
+  if (code) {
+    *c->h_err = 0;
+    HIP_OK(hipMemcpy(c->d_err, c->h_err, sizeof(int), hipMemcpyHostToDevice));
+  }
+  return dev_status(code);
+}
+
+}  // namespace
+
+static_assert(sizeof(DevInfo) == sizeof(rzf_update_info), "info layout");
+
+extern "C" {
+
+const char* rzf_status_string(rzf_status s) {
+  switch (s) {
+    case RZF_OK: return "ok";
+    case RZF_E_INVALID: return "invalid argument";
+    case RZF_E_SHAPE: return "size out of range";
+    case RZF_E_NOMEM: return "arena full";
+    case RZF_E_NOT_HPD: return "Gram matrix not positive definite";
+    case RZF_E_NONFINITE: return "non-finite value";
+    case RZF_E_DEVICE: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+rzf_status rzf_params_default(rzf_params* p) {
+  if (!p) return RZF_E_INVALID;
+  std::memset(p, 0, sizeof(*p));
+  p->k_init = 2;
+  p->p = 5;
+  p->i_max = 0;
+  p->switch_ratio = 0.5;
+  p->reset_period = 0;
+  p->P = 1.0;
+  p->seed = 0;
+  p->track_id = 0;
+  p->kinit_policy = RZF_KINIT_FIXED;
+  return RZF_OK;
+}
+
+size_t rzf_track_bytes(int K, int N) {
+  if (K < 1 || K > RZF_KMAX || N < 1 || N > RZF_NMAX) return 0;
+  return track_layout(K, N).total;
+}
+
+rzf_status rzf_ctx_create(int device, void* hip_stream, void* arena, size_t arena_bytes,
+                          rzf_ctx** out) {
+  if (!out) return RZF_E_INVALID;
+  *out = nullptr;
+  const size_t scr = scratch_bytes();
+  if (arena_bytes < scr + ALIGN) return RZF_E_NOMEM;
+  if (arena && (reinterpret_cast<uintptr_t>(arena) % ALIGN)) return RZF_E_INVALID;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RZF_E_DEVICE;
+  HIP_OK(hipSetDevice(device));
+  rzf_ctx* c = new (std::nothrow) rzf_ctx();
+  if (!c) return RZF_E_NOMEM;
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (arena) {
+    c->arena = static_cast<char*>(arena);
+  } else {
+    if (hipMalloc((void**)&c->arena, arena_bytes) != hipSuccess) { delete c; return RZF_E_NOMEM; }
+    c->own_arena = true;
+  }
+  c->arena_bytes = arena_bytes;
+  char* p = c->arena;
+  c->d_err = reinterpret_cast<int*>(p); p += align_up(sizeof(int) * 64);
+  c->d_fullA = reinterpret_cast<float2*>(p); p += align_up(sizeof(float2) * KM * KM);
+  c->d_fullAinv = reinterpret_cast<float2*>(p); p += align_up(sizeof(float2) * KM * KM);
+  c->d_fullwpart = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * ((RZF_NMAX + 15) / 16));
+  c->d_sum = reinterpret_cast<double*>(p);
+  c->free_blocks[scr] = arena_bytes - scr;
+  if (hipHostMalloc((void**)&c->h_sum, sizeof(double) * 8, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_err, sizeof(int) * 8, hipHostMallocDefault) != hipSuccess) {
+    if (c->own_arena) (void)hipFree(c->arena);
+    delete c;
+    return RZF_E_DEVICE;
+  }
+  *c->h_err = 0;
+  if (hipMemcpy(c->d_err, c->h_err, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    if (c->own_arena) (void)hipFree(c->arena);
+    delete c;
+    return RZF_E_DEVICE;
+  }
+  *out = c;
+  return RZF_OK;
+}
+
+rzf_status rzf_ctx_destroy(rzf_ctx* c) {
+  if (!c) return RZF_E_INVALID;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (rzf_track* t : c->tracks) delete t;
+  c->tracks.clear();
+  for (DevInfo* p : c->pin_chunks) (void)hipHostFree(p);
+  if (c->h_sum) (void)hipHostFree(c->h_sum);
+  if (c->h_err) (void)hipHostFree(c->h_err);
+  if (c->own_arena) (void)hipFree(c->arena);
+  delete c;
+  return RZF_OK;
+}
+
+rzf_status rzf_sync(rzf_ctx* c) {
+  if (!c) return RZF_E_INVALID;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  return sync_and_collect(c);
+}
+
+rzf_status rzf_init(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double alpha,
+                    const rzf_params* params, rzf_track** out) {
+  if (!c || !H || !out) return RZF_E_INVALID;
+  *out = nullptr;
+  if (K < 1 || K > RZF_KMAX || N < 1 || N > RZF_NMAX || ldh < N) return RZF_E_SHAPE;
+  if (!std::isfinite(alpha) || alpha < 0.0) return RZF_E_INVALID;
+  rzf_params prm;
+  if (params) prm = *params; else rzf_params_default(&prm);
+  if (!params_valid(&prm)) return RZF_E_INVALID;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  // report and clear any earlier device error before this synchronous call
+  rzf_status st0 = sync_and_collect(c);
+  if (st0 == RZF_E_DEVICE) return st0;
+
+  const Layout L = track_layout(K, N);
+  size_t off = 0;
+  if (!arena_alloc(c, L.total, &off)) return RZF_E_NOMEM;
+  rzf_track* t = new (std::nothrow) rzf_track();
+  if (!t) { arena_free(c, off, L.total); return RZF_E_NOMEM; }
+  char* base = c->arena + off;
+  t->ctx = c; t->K = K; t->N = N; t->prm = prm; t->alpha = alpha; t->off = off; t->bytes = L.total;
+  t->i_max = prm.i_max > 0 ? prm.i_max : default_imax(K, prm.k_init, prm.p);
+  TrackDesc& d = t->h_desc;
+  std::memset(&d, 0, sizeof(d));
+  d.K = K; d.N = N; d.alpha = alpha; d.P = prm.P; d.switch_ratio = prm.switch_ratio;
+  d.k_init = prm.k_init; d.p = prm.p; d.i_max = t->i_max; d.kinit_policy = prm.kinit_policy;
+  d.seed = prm.seed; d.track_id = prm.track_id;
+  d.Ainv = reinterpret_cast<float2*>(base + L.ainv);
+  d.Hprev = reinterpret_cast<float2*>(base + L.hprev);
+  d.Anew = reinterpret_cast<float2*>(base + L.anew);
+  d.dA = reinterpret_cast<float2*>(base + L.da);
+  d.A64 = reinterpret_cast<double2*>(base + L.a64);
+  d.wpart = reinterpret_cast<double*>(base + L.wpart);
+  d.last_r = 0;
+  t->d_desc = reinterpret_cast<TrackDesc*>(base + L.desc);
+  hipStream_t s = c->stream;
+  const float2* Hf = reinterpret_cast<const float2*>(H);
+  bool ok = hipMemcpyAsync(t->d_desc, &d, sizeof(d), hipMemcpyHostToDevice, s) == hipSuccess;
+  if (ok) {
+    launch_gram64(K, N, Hf, ldh, alpha, d.A64, s);
+    launch_inv64(K, d.A64, d.Ainv, c->d_err, nullptr, s);
+    ok = hipMemcpy2DAsync(d.Hprev, sizeof(float2) * N, Hf, sizeof(float2) * ldh,
+                          sizeof(float2) * N, K, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    ok = ok && hipGetLastError() == hipSuccess;
+  }
+  rzf_status st = ok ? sync_and_collect(c) : RZF_E_DEVICE;
+  if (st != RZF_OK) {
+    arena_free(c, off, L.total);
+    delete t;
+    return st;
+  }
+  c->tracks.insert(t);
+  *out = t;
+  return RZF_OK;
+}
+
+rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf_c32* W, int ldw,
+                      rzf_update_info* info) {
+  if (!t || !H_t || !W) return RZF_E_INVALID;
+  if (!(tol > 0.0 && tol <= 1.0)) return RZF_E_INVALID;
+  if (ldh < t->N || ldw < t->K) return RZF_E_SHAPE;
+  rzf_ctx* c = t->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  const int K = t->K, N = t->N;
+  const float2* Hf = reinterpret_cast<const float2*>(H_t);
+  float2* Wf = reinterpret_cast<float2*>(W);
+  const TrackDesc& d = t->h_desc;
+  DevInfo* slot = nullptr;
+  if (info) {
+    slot = pin_slot(c);
+    if (!slot) return RZF_E_DEVICE;
+  }
+  const int step = t->t + 1;
+  const bool reset = t->prm.reset_period > 0 && t->since_reset + 1 >= t->prm.reset_period;
+  if (reset) {
+    launch_gram64(K, N, Hf, ldh, t->alpha, d.A64, s);
+    launch_inv64(K, d.A64, d.Ainv, c->d_err, &t->d_desc->info, s);
+  } else {
+    launch_gram(K, N, Hf, ldh, d.Hprev, N, d.Anew, d.dA, t->alpha, s);
+    launch_arsvd_wb(t->d_desc, K, step, tol, t->i_max, c->d_err, s);
+  }
+  launch_precoder(K, N, Hf, ldh, d.Ainv, Wf, ldw, d.wpart, d.Hprev, s);
+  launch_scale(K, N, Wf, ldw, d.wpart, precoder_blocks(N), d.P, s);
+  if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
+  if (slot) {
+    HIP_OK(hipMemcpyAsync(slot, &t->d_desc->info, sizeof(DevInfo), hipMemcpyDeviceToHost, s));
+    c->pending.push_back(Pending{slot, info});
+  }
+  t->t = step;
+  t->since_reset = reset ? 0 : t->since_reset + 1;
+  return RZF_OK;
+}
+
+rzf_status rzf_full(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double alpha, double P,
+                    rzf_c32* W, int ldw) {
+  if (!c || !H || !W) return RZF_E_INVALID;
+  if (K < 1 || K > RZF_KMAX || N < 1 || N > RZF_NMAX || ldh < N || ldw < K) return RZF_E_SHAPE;
+  if (!std::isfinite(alpha) || alpha < 0.0 || !std::isfinite(P) || P <= 0.0) return RZF_E_INVALID;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  const float2* Hf = reinterpret_cast<const float2*>(H);
+  float2* Wf = reinterpret_cast<float2*>(W);
+  launch_gram(K, N, Hf, ldh, nullptr, 0, c->d_fullA, nullptr, alpha, s);
+  launch_inv32(K, c->d_fullA, c->d_fullAinv, c->d_err, s);
+  launch_precoder(K, N, Hf, ldh, c->d_fullAinv, Wf, ldw, c->d_fullwpart, nullptr, s);
+  launch_scale(K, N, Wf, ldw, c->d_fullwpart, precoder_blocks(N), P, s);
+  return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
+}
+
+rzf_status rzf_sum_rate(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, const rzf_c32* W,
+                        int ldw, double P, double sigma2, float* rates, double* sum_rate) {
+  if (!c || !H || !W) return RZF_E_INVALID;
+  if (K < 1 || K > RZF_KMAX || N < 1 || N > RZF_NMAX || ldh < N || ldw < K) return RZF_E_SHAPE;
+  if (!std::isfinite(P) || P <= 0.0 || !std::isfinite(sigma2) || sigma2 < 0.0) return RZF_E_INVALID;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  launch_sum_rate(K, N, reinterpret_cast<const float2*>(H), ldh, reinterpret_cast<const float2*>(W),
+                  ldw, P, sigma2, rates, c->d_sum, c->d_err, s);
+  if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
+  if (sum_rate) {
+    HIP_OK(hipMemcpyAsync(c->h_sum, c->d_sum, sizeof(double), hipMemcpyDeviceToHost, s));
+    rzf_status st = sync_and_collect(c);
+    if (st != RZF_OK) return st;
+    *sum_rate = *c->h_sum;
+  }
+  return RZF_OK;
+}
+
+rzf_status rzf_get_inverse(rzf_track* t, rzf_c32* Ainv) {
+  if (!t || !Ainv) return RZF_E_INVALID;
+  rzf_ctx* c = t->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  HIP_OK(hipMemcpyAsync(Ainv, t->h_desc.Ainv, sizeof(float2) * t->K * t->K,
+                        hipMemcpyDeviceToDevice, c->stream));
+  return RZF_OK;
+}
+
+rzf_status rzf_track_query(rzf_track* t, int* K, int* N, int* step, int* since_reset, int* last_r) {
+  if (!t) return RZF_E_INVALID;
+  rzf_ctx* c = t->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  if (K) *K = t->K;
+  if (N) *N = t->N;
+  if (step) *step = t->t;
+  if (since_reset) *since_reset = t->since_reset;
+  if (last_r) {
+    int v = 0;
+    HIP_OK(hipMemcpy(&v, &t->d_desc->last_r, sizeof(int), hipMemcpyDeviceToHost));
+    *last_r = v;
+  }
+  return RZF_OK;
+}
+
+rzf_status rzf_track_destroy(rzf_track* t) {
+  if (!t) return RZF_E_INVALID;
+  rzf_ctx* c = t->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  (void)hipSetDevice(c->device);
+  HIP_OK(hipStreamSynchronize(c->stream));
+  c->tracks.erase(t);
+  arena_free(c, t->off, t->bytes);
+  delete t;
+  return RZF_OK;
+}
+
+rzf_status rzf_debug_sketch(rzf_ctx* c, uint64_t seed, uint64_t track_id, int t, int it, int K, int d,
+                            rzf_c32* Omega, uint64_t* words) {
+  if (!c || (!Omega && !words)) return RZF_E_INVALID;
+  if (K < 1 || K > 1024 || d < 1 || d > K || t < 0 || it < 0) return RZF_E_SHAPE;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  launch_debug_sketch(seed, track_id, t, it, K, d, reinterpret_cast<float2*>(Omega), words, c->stream);
+  return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Gram matrix and its per-step correction on the FP32 matrix cores.
+//
+//   A'      = H_t H_t^H + alpha I_K                      (Sec. II, eq. (5); eq. (7))
+//   Delta A = H_{t-1} dH^H + dH H_t^H,  dH = H_t - H_{t-1}
+//
+// The second line is eq. (9), H dH^H + dH H^H + dH dH^H, with the last two
+// terms grouped as dH (H + dH)^H.  Forming Delta A from dH keeps its rounding
+// error proportional to ||Delta A|| rather than to ||A'||, which the
+// difference A' - A would not (the per-step change is ~1e-4 of A).
+//
+// Both outputs are Hermitian, so only the lower 16x16 tiles are computed and
+// mirrored.  A workgroup of four wavefronts owns one output tile and splits
+// the length-N reduction between its waves; the partial tiles are summed in
+// a fixed order (deterministic).
+#include "rzf_device.h"
+#include "rzf_internal.h"
+
+namespace {
+
+__device__ __forceinline__ void mac_conj(float2 x, float2 y, floatx4& dr, floatx4& di) {
+  // D += x * conj(y)
+  dr = mfma4(x.x, y.x, dr);
+  dr = mfma4(x.y, y.y, dr);
+  di = mfma4(x.y, y.x, di);
+  di = mfma4(-x.x, y.y, di);
+}
+
+template <bool DELTA>
+__global__ __launch_bounds__(256) void k_gram(int K, int N, const float2* __restrict__ Ht, int ldh,
+                                              const float2* __restrict__ Hp, int ldp,
+                                              float2* __restrict__ Anew, float2* __restrict__ dA,
+                                              float alpha) {
+  __shared__ float red[4][16][64];
+  // lower-triangular tile index -> (bi, bj), bi >= bj
+  const int tix = blockIdx.x;
+  int bi = (int)((sqrtf(8.0f * tix + 1.0f) - 1.0f) * 0.5f);
+  while ((bi + 1) * (bi + 2) / 2 <= tix) ++bi;
+  while (bi * (bi + 1) / 2 > tix) --bi;
+  const int bj = tix - bi * (bi + 1) / 2;
+  const int i0 = bi * 16, j0 = bj * 16;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int r = lane & 15, kq = lane >> 4;
+  const int ri = i0 + r, rj = j0 + r;
+  const bool oki = ri < K, okj = rj < K;
+
+  floatx4 ar = zero4(), ai = zero4(), gr = zero4(), gi = zero4();
+  for (int n0 = wid * 16; n0 < N; n0 += 64) {
+#pragma unroll
+    for (int k = 0; k < 16; k += 4) {
+      const int n = n0 + k + kq;
+      const bool okn = n < N;
+      const float2 ti = (oki && okn) ? Ht[(size_t)ri * ldh + n] : cz();
+      const float2 tj = (okj && okn) ? Ht[(size_t)rj * ldh + n] : cz();
+      mac_conj(ti, tj, ar, ai);                         // H_t H_t^H
+      if (DELTA) {
+        const float2 pi = (oki && okn) ? Hp[(size_t)ri * ldp + n] : cz();
+        const float2 pj = (okj && okn) ? Hp[(size_t)rj * ldp + n] : cz();
+        const float2 di = csub(ti, pi), dj = csub(tj, pj);
+        mac_conj(pi, dj, gr, gi);                       // H_{t-1} dH^H
+        mac_conj(di, tj, gr, gi);                       // dH H_t^H
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    red[wid][v][lane] = ar[v];
+    red[wid][4 + v][lane] = ai[v];
+    red[wid][8 + v][lane] = gr[v];
+    red[wid][12 + v][lane] = gi[v];
+  }
+  __syncthreads();
+  if (wid != 0) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int w = 0; w < 4; ++w) {
+      s[0] += red[w][v][lane];
+      s[1] += red[w][4 + v][lane];
+      s[2] += red[w][8 + v][lane];
+      s[3] += red[w][12 + v][lane];
+    }
+    const int i = i0 + tile_row(v), j = j0 + tile_col();
+    if (i >= K || j >= K) continue;
+    if (bi == bj && i < j) continue;   // the diagonal tile is mirrored from below
+    float2 a = make_float2(s[0], s[1]);
+    float2 g = make_float2(s[2], s[3]);
+    if (i == j) {
+      a = make_float2(a.x + alpha, 0.f);
+      g.y = 0.f;
+    }
+    Anew[(size_t)i * K + j] = a;
+    if (i != j) Anew[(size_t)j * K + i] = cconj(a);
+    if (DELTA) {
+      dA[(size_t)i * K + j] = g;
+      if (i != j) dA[(size_t)j * K + i] = cconj(g);
+    }
+  }
+}
+
+// FP64 Gram for the exact (re-)inversions: one thread per lower element.
+__global__ __launch_bounds__(256) void k_gram64(int K, int N, const float2* __restrict__ H, int ldh,
+                                                double alpha, double2* __restrict__ A) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nl = K * (K + 1) / 2;
+  if (e >= nl) return;
+  int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= e) ++i;
+  while (i * (i + 1) / 2 > e) --i;
+  const int j = e - i * (i + 1) / 2;
+  const float2* hi = H + (size_t)i * ldh;
+  const float2* hj = H + (size_t)j * ldh;
+  double re = 0.0, im = 0.0;
+  for (int n = 0; n < N; ++n) {
+    const double2 a = f2d(hi[n]), b = f2d(hj[n]);
+    re += a.x * b.x + a.y * b.y;
+    im += a.y * b.x - a.x * b.y;
+  }
+  if (i == j) {
+    A[(size_t)i * K + i] = make_double2(re + alpha, 0.0);
+  } else {
+    A[(size_t)i * K + j] = make_double2(re, im);
+    A[(size_t)j * K + i] = make_double2(re, -im);
+  }
+}
+
+}  // namespace
+
+void launch_gram(int K, int N, const float2* Ht, int ldh, const float2* Hp, int ldp, float2* Anew,
+                 float2* dA, double alpha, hipStream_t s) {
+  const int kt = (K + 15) / 16;
+  const int tiles = kt * (kt + 1) / 2;
+  if (Hp)
+    k_gram<true><<<tiles, 256, 0, s>>>(K, N, Ht, ldh, Hp, ldp, Anew, dA, (float)alpha);
+  else
+    k_gram<false><<<tiles, 256, 0, s>>>(K, N, Ht, ldh, nullptr, 0, Anew, nullptr, (float)alpha);
+}
+
+void launch_gram64(int K, int N, const float2* H, int ldh, double alpha, double2* A64, hipStream_t s) {
+  const int nl = K * (K + 1) / 2;
+  k_gram64<<<(nl + 255) / 256, 256, 0, s>>>(K, N, H, ldh, alpha, A64);
+}

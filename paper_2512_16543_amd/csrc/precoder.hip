@@ -1,0 +1,85 @@
+// Precoder W = H^H X with its power normalisation ||W||_F^2 = P (Sec. II,
+// eq. (5)), where X is the stored inverse of the Gram matrix.
+//
+// W is N x K (row-major).  A workgroup of four wavefronts owns 16 rows of W
+// (16 antennas); wave w computes the 16x16 tiles w, w+4, ... along K with a
+// length-K reduction on the FP32 matrix cores.  The block also writes its
+// partial sum of |W|^2 (FP64) and, for rzf_update, copies the 16 columns of
+// H_t it has read into the track's H_prev.  A second kernel scales W once
+// every partial sum is known (partials are added in a fixed order).
+#include "rzf_device.h"
+#include "rzf_internal.h"
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_precoder(int K, int N, const float2* __restrict__ H, int ldh,
+                                                  const float2* __restrict__ X,
+                                                  float2* __restrict__ W, int ldw,
+                                                  double* __restrict__ wpart,
+                                                  float2* __restrict__ Hcopy) {
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int n0 = blockIdx.x * 16;
+  double acc = 0.0;
+  for (int kt = wid; kt * 16 < K; kt += 4) {
+    const int k0 = kt * 16;
+    floatx4 dr = zero4(), di = zero4();
+    // A(n, i) = conj(H[i][n]);  B(i, k) = X[i][k]
+    auto la = [&](int rr, int i) -> float2 {
+      const int n = n0 + rr;
+      return (n < N && i < K) ? cconj(H[(size_t)i * ldh + n]) : cz();
+    };
+    auto lb = [&](int i, int c) -> float2 {
+      const int k = k0 + c;
+      return (i < K && k < K) ? X[(size_t)i * K + k] : cz();
+    };
+    ctile16(la, lb, 0, K, dr, di);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int n = n0 + tile_row(v), k = k0 + tile_col();
+      if (n < N && k < K) {
+        W[(size_t)n * ldw + k] = make_float2(dr[v], di[v]);
+        acc += (double)dr[v] * dr[v] + (double)di[v] * di[v];
+      }
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) red[wid] = acc;
+  if (Hcopy) {
+    // the 16 columns n0..n0+15 of every row of H_t
+    for (int e = threadIdx.x; e < K * 16; e += blockDim.x) {
+      const int i = e >> 4, n = n0 + (e & 15);
+      if (n < N) Hcopy[(size_t)i * N + n] = H[(size_t)i * ldh + n];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) wpart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_scale(int K, int N, float2* __restrict__ W, int ldw,
+                                               const double* __restrict__ wpart, int nparts,
+                                               double P) {
+  double tot = 0.0;
+  for (int b = 0; b < nparts; ++b) tot += wpart[b];
+  const float s = (tot > 0.0) ? (float)sqrt(P / tot) : 0.f;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * K) return;
+  const int n = e / K, k = e - n * K;
+  float2* w = W + (size_t)n * ldw + k;
+  *w = cscale(*w, s);
+}
+
+}  // namespace
+
+int precoder_blocks(int N) { return (N + 15) / 16; }
+
+void launch_precoder(int K, int N, const float2* H, int ldh, const float2* X, float2* W, int ldw,
+                     double* wpart, float2* Hcopy, hipStream_t s) {
+  k_precoder<<<precoder_blocks(N), 256, 0, s>>>(K, N, H, ldh, X, W, ldw, wpart, Hcopy);
+}
+
+void launch_scale(int K, int N, float2* W, int ldw, const double* wpart, int nparts, double P,
+                  hipStream_t s) {
+  const int n = N * K;
+  k_scale<<<(n + 255) / 256, 256, 0, s>>>(K, N, W, ldw, wpart, nparts, P);
+}

@@ -1,0 +1,148 @@
+// Device-side helpers shared by the gfx950 kernels: complex arithmetic on
+// interleaved float2/double2, wavefront reductions, the Philox4x64-10 sketch
+// generator and a 16x16 complex tile product on the FP32 matrix cores.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+#define RZF_WAVE 64
+
+// ------------------------------------------------------------ complex float
+__device__ __forceinline__ float2 cz() { return make_float2(0.f, 0.f); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+
+__device__ __forceinline__ double2 dz() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ double2 dadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 dconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 dmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double dabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double2 ddiv(double2 a, double2 b) {
+  // Smith's algorithm keeps the intermediate products in range.
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, den = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / den, (a.y - a.x * r) / den);
+  } else {
+    double r = b.x / b.y, den = b.x * r + b.y;
+    return make_double2((a.x * r + a.y) / den, (a.y * r - a.x) / den);
+  }
+}
+__device__ __forceinline__ double2 f2d(float2 a) { return make_double2((double)a.x, (double)a.y); }
+__device__ __forceinline__ float2 d2f(double2 a) { return make_float2((float)a.x, (float)a.y); }
+
+// --------------------------------------------------------- wave reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, RZF_WAVE);
+  return v;
+}
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, RZF_WAVE);
+  return v;
+}
+
+// Sum over the whole workgroup; `red` holds one double per wave.  Every
+// thread returns the total.  Contains two barriers.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];   // same order in every thread
+  __syncthreads();
+  return s;
+}
+
+// ------------------------------------------------ Philox4x64-10 (SC'11)
+// Counter-based generator of Salmon, Moraes, Dror and Shaw; round constants
+// and Weyl increments from that paper.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+    const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+  }
+}
+
+// Sketch entry (row i, column j) of iteration `it` at step `t`: the counter
+// block (q, it, t, 0) with q = (1024 j + i) >> 1 under key (seed, track);
+// words 0,1 serve even rows, words 2,3 odd rows.  Box-Muller in FP64 turns
+// the two 53-bit uniforms into a CN(0,1) sample.
+__device__ __forceinline__ void sketch_words(uint64_t seed, uint64_t track, int t, int it, int i,
+                                             int j, uint64_t* wa, uint64_t* wb) {
+  uint64_t c[4];
+  c[0] = ((uint64_t)j * 1024ull + (uint64_t)i) >> 1;
+  c[1] = (uint64_t)it;
+  c[2] = (uint64_t)t;
+  c[3] = 0ull;
+  philox4x64_10(c, seed, track);
+  if (i & 1) { *wa = c[2]; *wb = c[3]; } else { *wa = c[0]; *wb = c[1]; }
+}
+
+__device__ __forceinline__ float2 words_to_cn(uint64_t wa, uint64_t wb) {
+  const double ua = ((double)(wa >> 11) + 0.5) * 0x1.0p-53;
+  const double ub = ((double)(wb >> 11) + 0.5) * 0x1.0p-53;
+  const double rad = sqrt(-2.0 * log(ua)) / sqrt(2.0);
+  const double ang = 2.0 * 3.141592653589793 * ub;
+  double s, c;
+  sincos(ang, &s, &c);
+  return make_float2((float)(rad * c), (float)(rad * s));
+}
+
+__device__ __forceinline__ float2 sketch_entry(uint64_t seed, uint64_t track, int t, int it, int i, int j) {
+  uint64_t wa, wb;
+  sketch_words(seed, track, t, it, i, j, &wa, &wb);
+  return words_to_cn(wa, wb);
+}
+
+// ------------------------------------------------- complex MFMA 16x16 tile
+// One wavefront accumulates D(16x16) += A(16 x k) * B(k x 16) in FP32 on the
+// matrix cores with v_mfma_f32_16x16x4_f32.  Operand lane layout of that
+// instruction: lane l holds A[l%16][l/16] and B[l/16][l%16] of a 16x4 / 4x16
+// slab; the result lane l holds D[4*(l/16)+v][l%16] in register v.
+// la(i, k) and lb(k, j) return the complex operands (zero outside the matrix;
+// conjugation is the loader's business).  Real and imaginary parts take four
+// real products.
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <class LA, class LB>
+__device__ __forceinline__ void ctile16(const LA& la, const LB& lb, int k0, int k1, floatx4& dr,
+                                        floatx4& di) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, kk = lane >> 4;
+  for (int k = k0; k < k1; k += 4) {
+    const float2 a = la(r, k + kk);
+    const float2 b = lb(k + kk, r);
+    dr = mfma4(a.x, b.x, dr);
+    dr = mfma4(-a.y, b.y, dr);
+    di = mfma4(a.x, b.y, di);
+    di = mfma4(a.y, b.x, di);
+  }
+}
+
+__device__ __forceinline__ floatx4 zero4() { floatx4 z = {0.f, 0.f, 0.f, 0.f}; return z; }
+
+// Row / column of result register v in the calling lane.
+__device__ __forceinline__ int tile_row(int v) { return 4 * ((threadIdx.x & 63) >> 4) + v; }
+__device__ __forceinline__ int tile_col() { return threadIdx.x & 15; }

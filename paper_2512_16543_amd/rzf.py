@@ -1,0 +1,253 @@
+"""Thin ctypes binding over the C ABI of librzf.so (declared in include/rzf.h).
+
+Argument marshalling only: every step of the precoding path runs in the HIP
+library.  PyTorch provides device memory (the arena, H and W tensors) and the
+stream.  Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librzf.so")
+
+RZF_OK = 0
+RZF_E_INVALID = 1
+RZF_E_SHAPE = 2
+RZF_E_NOMEM = 3
+RZF_E_NOT_HPD = 4
+RZF_E_NONFINITE = 5
+RZF_E_DEVICE = 6
+
+PATH_NOOP, PATH_WB, PATH_FULL_RANK, PATH_FULL_SINGULAR, PATH_RESET = 0, 1, 2, 3, 4
+KINIT_FIXED, KINIT_WARM = 0, 1
+KMAX = 64
+NMAX = 4096
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k_init", ctypes.c_int), ("p", ctypes.c_int), ("i_max", ctypes.c_int),
+                ("switch_ratio", ctypes.c_double), ("reset_period", ctypes.c_int),
+                ("P", ctypes.c_double), ("seed", ctypes.c_uint64), ("track_id", ctypes.c_uint64),
+                ("kinit_policy", ctypes.c_int)]
+
+
+class UpdateInfo(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int), ("iters", ctypes.c_int), ("path", ctypes.c_int),
+                ("d", ctypes.c_int), ("dA_fro2", ctypes.c_double), ("captured", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class RzfError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} (status {status})")
+
+
+_lib = None
+
+_SIGS = {
+    "rzf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "rzf_params_default": (ctypes.c_int, [ctypes.POINTER(Params)]),
+    "rzf_track_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+    "rzf_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "rzf_ctx_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rzf_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "rzf_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                ctypes.c_int, ctypes.c_double, ctypes.POINTER(Params),
+                                ctypes.POINTER(ctypes.c_void_p)]),
+    "rzf_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(UpdateInfo)]),
+    "rzf_full": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                ctypes.c_int]),
+    "rzf_sum_rate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "rzf_get_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rzf_track_query": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 5),
+    "rzf_track_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rzf_debug_sketch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+}
+
+
+def lib():
+    """The loaded librzf.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2512_16543_amd.build` (there is no fallback path)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(st: int) -> str:
+    return lib().rzf_status_string(st).decode()
+
+
+def _check(st: int, where: str):
+    if st != RZF_OK:
+        raise RzfError(st, where)
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    _check(lib().rzf_params_default(ctypes.byref(p)), "rzf_params_default")
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def track_bytes(K: int, N: int) -> int:
+    return int(lib().rzf_track_bytes(K, N))
+
+
+def _dev_ptr(x) -> int:
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not x.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    return x.data_ptr()
+
+
+def _mat_args(H, dtype_name="complex64"):
+    import torch
+    if H.dtype != torch.complex64:
+        raise TypeError(f"expected {dtype_name}, got {H.dtype}")
+    if H.dim() != 2 or H.stride(1) != 1:
+        raise ValueError("expected a 2-D row-major matrix")
+    return _dev_ptr(H), int(H.stride(0))
+
+
+class Context:
+    """rzf_ctx: one device, one stream, one arena (a torch uint8 tensor)."""
+
+    def __init__(self, device: int = 0, arena_bytes: int = 64 << 20, stream=None):
+        import torch
+        self.device = device
+        dev = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+        h = ctypes.c_void_p()
+        _check(lib().rzf_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.c_void_p(self.arena.data_ptr()), arena_bytes,
+                                    ctypes.byref(h)), "rzf_ctx_create")
+        self.h = h
+        self._infos = []
+
+    def close(self):
+        if self.h:
+            lib().rzf_ctx_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        _check(lib().rzf_sync(self.h), "rzf_sync")
+        self._infos = []
+
+    def sync_status(self) -> int:
+        st = lib().rzf_sync(self.h)
+        self._infos = []
+        return st
+
+    def init(self, H, alpha: float, params: Optional[Params] = None) -> "Track":
+        ptr, ld = _mat_args(H)
+        K, N = H.shape
+        h = ctypes.c_void_p()
+        _check(lib().rzf_init(self.h, K, N, ctypes.c_void_p(ptr), ld, float(alpha),
+                              ctypes.byref(params) if params is not None else None,
+                              ctypes.byref(h)), "rzf_init")
+        return Track(self, h, K, N)
+
+    def full(self, H, alpha: float, P: float, W):
+        hp, ldh = _mat_args(H)
+        wp, ldw = _mat_args(W)
+        K, N = H.shape
+        _check(lib().rzf_full(self.h, K, N, ctypes.c_void_p(hp), ldh, float(alpha), float(P),
+                              ctypes.c_void_p(wp), ldw), "rzf_full")
+
+    def sum_rate(self, H, W, P: float, sigma2: float, rates=None) -> float:
+        hp, ldh = _mat_args(H)
+        wp, ldw = _mat_args(W)
+        K, N = H.shape
+        rp = None
+        if rates is not None:
+            import torch
+            if rates.dtype != torch.float32 or rates.numel() < K:
+                raise ValueError("rates must be a float32 tensor of K entries")
+            rp = ctypes.c_void_p(_dev_ptr(rates))
+        out = ctypes.c_double()
+        _check(lib().rzf_sum_rate(self.h, K, N, ctypes.c_void_p(hp), ldh, ctypes.c_void_p(wp), ldw,
+                                  float(P), float(sigma2), rp, ctypes.byref(out)), "rzf_sum_rate")
+        return out.value
+
+    def sum_rate_async(self, H, W, P: float, sigma2: float, rates):
+        hp, ldh = _mat_args(H)
+        wp, ldw = _mat_args(W)
+        K, N = H.shape
+        _check(lib().rzf_sum_rate(self.h, K, N, ctypes.c_void_p(hp), ldh, ctypes.c_void_p(wp), ldw,
+                                  float(P), float(sigma2), ctypes.c_void_p(_dev_ptr(rates)), None),
+               "rzf_sum_rate")
+
+    def debug_sketch(self, seed: int, track: int, t: int, it: int, K: int, d: int):
+        import torch
+        dev = torch.device("cuda", self.device)
+        om = torch.empty(d, K, dtype=torch.complex64, device=dev)      # column-major K x d
+        words = torch.empty(K * d * 2, dtype=torch.int64, device=dev)
+        _check(lib().rzf_debug_sketch(self.h, seed, track, t, it, K, d, ctypes.c_void_p(om.data_ptr()),
+                                      ctypes.c_void_p(words.data_ptr())), "rzf_debug_sketch")
+        return om.t(), words.view(K, d, 2)
+
+
+class Track:
+    """rzf_track: one channel track's resident state."""
+
+    def __init__(self, ctx: Context, h, K: int, N: int):
+        self.ctx, self.h, self.K, self.N = ctx, h, K, N
+
+    def update(self, H_t, tol: float, W, want_info: bool = True) -> Optional[UpdateInfo]:
+        hp, ldh = _mat_args(H_t)
+        wp, ldw = _mat_args(W)
+        if tuple(H_t.shape) != (self.K, self.N) or tuple(W.shape) != (self.N, self.K):
+            raise ValueError("shape mismatch")
+        info = UpdateInfo() if want_info else None
+        _check(lib().rzf_update(self.h, ctypes.c_void_p(hp), ldh, float(tol), ctypes.c_void_p(wp), ldw,
+                                ctypes.byref(info) if info is not None else None), "rzf_update")
+        if info is not None:
+            self.ctx._infos.append(info)   # keep alive until rzf_sync fills it
+        return info
+
+    def inverse(self):
+        import torch
+        out = torch.empty(self.K, self.K, dtype=torch.complex64, device=torch.device("cuda", self.ctx.device))
+        _check(lib().rzf_get_inverse(self.h, ctypes.c_void_p(out.data_ptr())), "rzf_get_inverse")
+        return out
+
+    def query(self):
+        vals = [ctypes.c_int() for _ in range(5)]
+        _check(lib().rzf_track_query(self.h, *[ctypes.byref(v) for v in vals]), "rzf_track_query")
+        return dict(zip(("K", "N", "t", "since_reset", "last_r"), (v.value for v in vals)))
+
+    def destroy(self):
+        if self.h:
+            _check(lib().rzf_track_destroy(self.h), "rzf_track_destroy")
+            self.h = ctypes.c_void_p()

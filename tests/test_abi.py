@@ -1,0 +1,77 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/rzf.h, and validates arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2512_16543_amd import rzf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rzf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rzf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert "rzf_init" in names and "rzf_update" in names and "rzf_full" in names
+    assert "rzf_sum_rate" in names
+    L = rzf.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    # the binding wraps every declared function
+    assert set(names) <= set(rzf._SIGS)
+
+
+def test_params_default_values():
+    p = rzf.default_params()
+    assert (p.k_init, p.p, p.i_max, p.switch_ratio, p.reset_period, p.P) == (2, 5, 0, 0.5, 0, 1.0)
+    assert (p.seed, p.track_id, p.kinit_policy) == (0, 0, rzf.KINIT_FIXED)
+    assert rzf.lib().rzf_params_default(None) == rzf.RZF_E_INVALID
+
+
+def test_track_bytes():
+    assert rzf.track_bytes(0, 10) == 0
+    assert rzf.track_bytes(65, 10) == 0
+    assert rzf.track_bytes(4, 0) == 0
+    b = rzf.track_bytes(64, 256)
+    assert b >= 8 * (64 * 64 * 3 + 64 * 256) + 16 * 64 * 64
+    assert rzf.track_bytes(64, 512) > b
+
+
+def test_status_strings():
+    for s in range(7):
+        assert rzf.status_string(s)
+    assert rzf.status_string(rzf.RZF_E_NOT_HPD) == "Gram matrix not positive definite"
+
+
+def test_null_arguments_rejected_without_device():
+    L = rzf.lib()
+    assert L.rzf_sync(None) == rzf.RZF_E_INVALID
+    assert L.rzf_ctx_destroy(None) == rzf.RZF_E_INVALID
+    assert L.rzf_ctx_create(0, None, None, 1 << 20, None) == rzf.RZF_E_INVALID
+    out = ctypes.c_void_p()
+    assert L.rzf_init(None, 4, 4, None, 4, 1.0, None, ctypes.byref(out)) == rzf.RZF_E_INVALID
+    assert L.rzf_update(None, None, 4, 0.9, None, 4, None) == rzf.RZF_E_INVALID
+    assert L.rzf_full(None, 4, 4, None, 4, 1.0, 1.0, None, 4) == rzf.RZF_E_INVALID
+    assert L.rzf_sum_rate(None, 4, 4, None, 4, None, 4, 1.0, 0.1, None, None) == rzf.RZF_E_INVALID
+    assert L.rzf_get_inverse(None, None) == rzf.RZF_E_INVALID
+    assert L.rzf_track_destroy(None) == rzf.RZF_E_INVALID
+    assert L.rzf_debug_sketch(None, 0, 0, 0, 0, 4, 4, None, None) == rzf.RZF_E_INVALID
+
+
+def test_ctx_create_arena_too_small():
+    out = ctypes.c_void_p()
+    assert rzf.lib().rzf_ctx_create(0, None, None, 1024, ctypes.byref(out)) == rzf.RZF_E_NOMEM
+
+
+def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
+    monkeypatch.setattr(rzf, "_lib", None)
+    monkeypatch.setattr(rzf, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no fallback"):
+        rzf.lib()

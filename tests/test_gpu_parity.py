@@ -1,0 +1,323 @@
+"""GPU parity: every entry point of the C ABI against the FP64 oracle.
+
+Inputs are drawn in FP64, rounded to complex64 and handed to both sides, so
+the GPU and the oracle see identical numbers.  Tolerances: relative Frobenius
+error <= 1e-5 for the FP32 inverse and precoder, <= 1e-6 for the FP64-formed
+initial inverse, bit-exact for the sketch generator's integer words.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle.rzf as orz
+from oracle import philox
+from paper_2512_16543_amd import rzf, workload as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+TOL_INIT = 1e-6
+# Rank decisions: GPU (FP32 Delta A) and oracle (FP64) may disagree only when
+# a cumulative energy ratio lies within this distance of eta.
+TIE_BAND = 1e-4
+
+SHAPES = [(16, 64), (64, 256), (13, 37), (1, 1), (1, 5), (7, 300), (33, 33), (64, 1000), (48, 40),
+          (64, 17)]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def c64(H):
+    return np.asarray(H, dtype=np.complex64)
+
+
+def dev(H):
+    return torch.from_numpy(c64(H)).cuda()
+
+
+def host(x):
+    return x.cpu().numpy().astype(np.complex128)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = rzf.Context(0, 256 << 20)
+    yield c
+    c.close()
+
+
+def _channel(K, N, seed):
+    return c64(wl.random_channel(K, N, seed, scale=1.0)).astype(np.complex128)
+
+
+# ------------------------------------------------------------- sketch draw
+
+@pytest.mark.parametrize("seed,track,t,it,K,d", [(2, 0, 1, 1, 64, 7), (1, 3, 17, 4, 16, 16),
+                                                 (5, 9, 999, 6, 64, 64), (0, 0, 0, 0, 1, 1),
+                                                 (7, 1, 3, 2, 1024, 5)])
+def test_sketch_words_and_values(ctx, seed, track, t, it, K, d):
+    om, words = ctx.debug_sketch(seed, track, t, it, K, d)
+    w = words.cpu().numpy().view(np.uint64)
+    ref = philox.sketch_words(seed, track, t, it, K, d)
+    np.testing.assert_array_equal(w, ref)
+    omo = philox.draw_sketch(seed, track, t, it, K, d)
+    assert np.max(np.abs(host(om) - omo)) <= 4 * np.finfo(np.float32).eps * max(1.0, np.abs(omo).max())
+
+
+# ---------------------------------------------------------- init / full
+
+@pytest.mark.parametrize("K,N", SHAPES)
+def test_init_inverse(ctx, K, N):
+    H = _channel(K, N, 1)
+    alpha = 0.3 + K / 50.0
+    tr = ctx.init(dev(H), alpha, rzf.default_params())
+    Ai = host(tr.inverse())
+    ctx.sync()
+    assert rel(Ai, np.linalg.inv(orz.gram(H, alpha))) <= TOL_INIT
+    tr.destroy()
+
+
+@pytest.mark.parametrize("K,N", SHAPES)
+def test_full_precoder(ctx, K, N):
+    H = _channel(K, N, 2)
+    alpha, P = 0.5 + K / 40.0, 2.0
+    W = torch.empty(N, K, dtype=torch.complex64, device="cuda")
+    ctx.full(dev(H), alpha, P, W)
+    ctx.sync()
+    Wo = orz.full_rzf(H, alpha, P)
+    assert rel(host(W), Wo) <= TOL_FP32
+    assert abs(orz.fro2(host(W)) - P) <= 1e-5 * P
+
+
+def test_full_precoder_strided(ctx):
+    K, N = 20, 50
+    H = _channel(K, N, 3)
+    big = torch.zeros(K, N + 6, dtype=torch.complex64, device="cuda")
+    big[:, :N] = dev(H)
+    Wb = torch.zeros(N, K + 3, dtype=torch.complex64, device="cuda")
+    ctx.full(big[:, :N], 1.0, 1.0, Wb[:, :K])
+    ctx.sync()
+    assert rel(host(Wb[:, :K]), orz.full_rzf(H, 1.0, 1.0)) <= TOL_FP32
+    assert torch.all(Wb[:, K:] == 0)
+
+
+@pytest.mark.parametrize("K,N", [(16, 64), (64, 256), (13, 37), (1, 8), (64, 1000)])
+def test_sum_rate(ctx, K, N):
+    H = _channel(K, N, 4)
+    alpha, P, s2 = K / 10.0, 1.0, 0.1
+    Wo = orz.full_rzf(H, alpha, P)
+    Wd = dev(Wo)
+    rates = torch.empty(K, dtype=torch.float32, device="cuda")
+    R = ctx.sum_rate(dev(H), Wd, P, s2, rates)
+    ro, Ro = orz.sum_rate(H, host(Wd), P, s2)
+    assert abs(R - Ro) <= TOL_FP32 * abs(Ro)
+    np.testing.assert_allclose(rates.cpu().numpy(), ro, rtol=2e-5, atol=1e-6)
+
+
+def test_sum_rate_rescales_power(ctx):
+    K, N = 8, 32
+    H = _channel(K, N, 5)
+    W = orz.full_rzf(H, 0.8, 1.0)
+    R1 = ctx.sum_rate(dev(H), dev(W), 1.0, 0.05)
+    R2 = ctx.sum_rate(dev(H), dev(3.0 * W), 1.0, 0.05)
+    assert abs(R1 - R2) <= 1e-6 * abs(R1)
+
+
+# -------------------------------------------------------------- updates
+
+def _params(cfg, **kw):
+    d = dict(k_init=cfg.k_init, p=cfg.p, P=cfg.P, seed=cfg.seed, track_id=0,
+             reset_period=cfg.reset_period)
+    d.update(kw)
+    return d
+
+
+def _oracle_params(cfg, d):
+    return orz.TrackParams(alpha=cfg.alpha, P=d["P"], k_init=d["k_init"], p=d["p"],
+                           i_max=d.get("i_max", 0), switch_ratio=d.get("switch_ratio", 0.5),
+                           reset_period=d["reset_period"], seed=d["seed"], track_id=d["track_id"],
+                           kinit_policy=d.get("kinit_policy", 0))
+
+
+def _energy_ratios(res):
+    c = np.cumsum(res.sigma ** 2) / res.energy
+    return np.concatenate([[0.0], c])
+
+
+def _tie_ok(state, H, eta, gi, io, ot):
+    """GPU decision gi differs from the oracle's io: accept only when, at the
+    first iteration where they can part, a cumulative energy ratio of the
+    oracle lies within TIE_BAND of eta."""
+    dA = orz.gram_correction(state["H_prev"], H - state["H_prev"])
+    prm = ot.params
+    k_init = prm.k_init if prm.kinit_policy == 0 else max(prm.k_init, state["last_r"])
+    it = min(gi.iters, io.iters)
+    res = orz.arsvd(dA, eta, k_init, prm.p, ot.i_max(), ot.draw(state["t"] + 1), force_iters=it)
+    c = np.cumsum(res.sigma ** 2) / res.energy
+    return bool(np.any(np.abs(c - eta) < TIE_BAND))
+
+
+def run_track(ctx, cfg, steps, eta, prm_kw=None, check_every=1):
+    """Run GPU and oracle side by side; before every step the oracle adopts the
+    GPU's state (one-step parity).  Returns per-step records."""
+    prm_kw = prm_kw or {}
+    d = _params(cfg, **prm_kw)
+    Hs = c64(wl.make_track(wl.with_overrides(cfg, steps=steps)).snapshots()).astype(np.complex128)
+    tr = ctx.init(dev(Hs[0]), cfg.alpha, rzf.default_params(**d))
+    ot = orz.OracleTrack(Hs[0], _oracle_params(cfg, d))
+    W = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device="cuda")
+    recs = []
+    for t in range(1, steps + 1):
+        state = ot.export_state()
+        state["Ainv"] = host(tr.inverse())
+        q = tr.query()
+        state["last_r"] = q["last_r"]
+        ot.import_state(state)
+        info = tr.update(dev(Hs[t]), eta, W)
+        ctx.sync()
+        gi = (info.r, info.iters, info.path)
+        Wo, io = ot.update(Hs[t], eta)
+        forced = False
+        if gi != (io.r, io.iters, io.path):
+            assert info.path in (orz.PATH_WB, orz.PATH_FULL_RANK) and io.path in (orz.PATH_WB, orz.PATH_FULL_RANK), \
+                (t, gi, (io.r, io.iters, io.path))
+            assert _tie_ok(state, Hs[t], eta, info, io, ot), (t, gi, (io.r, io.iters, io.path))
+            ot.import_state(state)
+            Wo, io = ot.update(Hs[t], eta, force_iters=info.iters, force_r=info.r)
+            forced = True
+        Ag = host(tr.inverse())
+        Wg = host(W)
+        recs.append(dict(t=t, r=info.r, iters=info.iters, path=info.path, forced=forced,
+                         ainv=rel(Ag, ot.Ainv), w=rel(Wg, Wo),
+                         e=abs(info.dA_fro2 - io.dA_fro2) / max(io.dA_fro2, 1e-300)))
+    tr.destroy()
+    return recs
+
+
+def _assert_recs(recs, tol=TOL_FP32, max_forced=0.05):
+    worst_a = max(r["ainv"] for r in recs)
+    worst_w = max(r["w"] for r in recs)
+    forced = sum(r["forced"] for r in recs)
+    assert worst_a <= tol, worst_a
+    assert worst_w <= tol, worst_w
+    assert forced <= max_forced * len(recs) + 1, forced
+
+
+def test_update_c1_track(ctx):
+    cfg = wl.CONFIGS["c1"]
+    recs = run_track(ctx, cfg, 50, cfg.eta)
+    _assert_recs(recs)
+    paths = {r["path"] for r in recs}
+    assert orz.PATH_WB in paths
+
+
+@pytest.mark.parametrize("eta", [0.999, 0.9, 0.65])
+def test_update_c2_short(ctx, eta):
+    cfg = wl.CONFIGS["c2"]
+    recs = run_track(ctx, cfg, 24, eta, dict(reset_period=10))
+    _assert_recs(recs)
+    assert [r["t"] for r in recs if r["path"] == orz.PATH_RESET] == [10, 20]
+    assert all(r["e"] < 1e-4 for r in recs if r["path"] != orz.PATH_RESET)
+
+
+def test_update_warm_policy(ctx):
+    cfg = wl.CONFIGS["c2"]
+    recs = run_track(ctx, cfg, 12, 0.99, dict(kinit_policy=rzf.KINIT_WARM))
+    _assert_recs(recs)
+    assert max(r["iters"] for r in recs[2:]) <= 2
+
+
+def test_update_full_rank_woodbury_is_exact_inverse(ctx):
+    # d = K and eta ~ 1: Woodbury reproduces inv(A') of the new snapshot
+    cfg = wl.with_overrides(wl.CONFIGS["c1"], K=16)
+    K = cfg.K
+    Hs = c64(wl.make_track(wl.with_overrides(cfg, steps=4)).snapshots()).astype(np.complex128)
+    prm = rzf.default_params(k_init=K, p=0, switch_ratio=1.0, seed=3)
+    tr = ctx.init(dev(Hs[0]), cfg.alpha, prm)
+    W = torch.empty(cfg.N, K, dtype=torch.complex64, device="cuda")
+    for t in range(1, 5):
+        info = tr.update(dev(Hs[t]), 1.0 - 1e-9, W)
+        ctx.sync()
+        assert info.path == rzf.PATH_WB and info.d == K
+        assert rel(host(tr.inverse()), np.linalg.inv(orz.gram(Hs[t], cfg.alpha))) <= TOL_FP32
+        assert rel(host(W), orz.full_rzf(Hs[t], cfg.alpha, cfg.P)) <= TOL_FP32
+    tr.destroy()
+
+
+def test_update_noop_for_static_channel(ctx):
+    cfg = wl.CONFIGS["c1"]
+    H = c64(wl.make_track(cfg).snapshot(0)).astype(np.complex128)
+    tr = ctx.init(dev(H), cfg.alpha, rzf.default_params(seed=1))
+    before = host(tr.inverse())
+    W = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device="cuda")
+    info = tr.update(dev(H), 0.9, W)
+    ctx.sync()
+    assert info.path == rzf.PATH_NOOP and info.r == 0 and info.iters == 0
+    np.testing.assert_array_equal(host(tr.inverse()), before)
+    assert rel(host(W), orz.full_rzf(H, cfg.alpha, cfg.P)) <= TOL_FP32
+    tr.destroy()
+
+
+def test_update_high_rank_change_falls_back(ctx):
+    # an i.i.d. redraw of H makes Delta A full rank: Alg. 2 inverts directly
+    K, N = 32, 128
+    H0, H1 = _channel(K, N, 10), _channel(K, N, 11)
+    tr = ctx.init(dev(H0), 1.0, rzf.default_params(seed=4))
+    W = torch.empty(N, K, dtype=torch.complex64, device="cuda")
+    info = tr.update(dev(H1), 0.999, W)
+    ctx.sync()
+    assert info.path == rzf.PATH_FULL_RANK and info.r > K // 2
+    assert rel(host(tr.inverse()), np.linalg.inv(orz.gram(H1, 1.0))) <= TOL_FP32
+    tr.destroy()
+
+
+# --------------------------------------------------------------- errors
+
+def test_init_not_hpd(ctx):
+    K, N = 8, 4
+    H = _channel(K, N, 6)        # rank 4 < K, alpha = 0: singular Gram matrix
+    with pytest.raises(rzf.RzfError) as e:
+        ctx.init(dev(H), 0.0, rzf.default_params())
+    assert e.value.status == rzf.RZF_E_NOT_HPD
+
+
+def test_init_nonfinite(ctx):
+    H = _channel(4, 8, 7)
+    H[1, 2] = np.nan
+    with pytest.raises(rzf.RzfError) as e:
+        ctx.init(dev(H), 1.0, rzf.default_params())
+    assert e.value.status == rzf.RZF_E_NONFINITE
+
+
+def test_full_not_hpd_reported_at_sync(ctx):
+    K, N = 8, 4
+    H = _channel(K, N, 8)
+    W = torch.empty(N, K, dtype=torch.complex64, device="cuda")
+    ctx.full(dev(H), 0.0, 1.0, W)
+    assert ctx.sync_status() == rzf.RZF_E_NOT_HPD
+    assert ctx.sync_status() == rzf.RZF_OK
+
+
+def test_invalid_arguments(ctx):
+    H = dev(_channel(4, 8, 9))
+    with pytest.raises(rzf.RzfError) as e:
+        ctx.init(H, -1.0, rzf.default_params())
+    assert e.value.status == rzf.RZF_E_INVALID
+    with pytest.raises(rzf.RzfError):
+        ctx.init(H, 1.0, rzf.default_params(switch_ratio=0.0))
+    tr = ctx.init(H, 1.0, rzf.default_params())
+    W = torch.empty(8, 4, dtype=torch.complex64, device="cuda")
+    for bad in (0.0, 1.5, float("nan")):
+        with pytest.raises(rzf.RzfError) as e:
+            tr.update(H, bad, W)
+        assert e.value.status == rzf.RZF_E_INVALID
+    big = dev(_channel(65, 8, 1))
+    with pytest.raises(rzf.RzfError) as e:
+        ctx.init(big, 1.0, rzf.default_params())
+    assert e.value.status == rzf.RZF_E_SHAPE
+    tr.destroy()
