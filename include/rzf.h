@@ -167,6 +167,20 @@ rzf_status rzf_track_destroy(rzf_track* tr);
 rzf_status rzf_debug_sketch(rzf_ctx* ctx, uint64_t seed, uint64_t track_id, int t, int it,
                             int K, int d, rzf_c32* Omega, uint64_t* words);
 
+/* Per-kernel timing with HIP events on the context's stream (for measuring a
+ * kernel's average duration; off by default).  rzf_profile(ctx, 1) clears the
+ * counters and starts recording an event pair around every launch;
+ * rzf_profile(ctx, 0) stops.  rzf_profile_read synchronises the stream and
+ * fills up to `max` entries (kernel name, launches, summed milliseconds),
+ * returning the number of entries in *n. */
+typedef struct {
+  char name[32];
+  int count;
+  double total_ms;
+} rzf_profile_entry;
+rzf_status rzf_profile(rzf_ctx* ctx, int enable);
+rzf_status rzf_profile_read(rzf_ctx* ctx, rzf_profile_entry* out, int max, int* n);
+
 #ifdef __cplusplus
 }
 #endif

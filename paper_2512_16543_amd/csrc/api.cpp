@@ -26,6 +26,16 @@ struct Pending {
   rzf_update_info* dst;
 };
 
+struct ProfRec {
+  int kernel;
+  hipEvent_t a, b;
+};
+
+const char* const KERNEL_NAMES[] = {"gram", "gram64", "inv64", "inv32", "arsvd_wb",
+                                    "precoder", "scale", "sum_rate"};
+enum { KN_GRAM, KN_GRAM64, KN_INV64, KN_INV32, KN_ARSVD, KN_PRECODER, KN_SCALE, KN_SUMRATE,
+       KN_COUNT };
+
 }  // namespace
 
 struct rzf_ctx {
@@ -49,6 +59,12 @@ struct rzf_ctx {
   std::vector<Pending> pending;
   std::set<rzf_track*> tracks;
   std::mutex mu;
+  // event timing
+  bool prof_on = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> ev_pool;
+  int prof_count[KN_COUNT] = {};
+  double prof_ms[KN_COUNT] = {};
 };
 
 struct rzf_track {
@@ -129,6 +145,42 @@ DevInfo* pin_slot(rzf_ctx* c) {
   }
   ++c->pin_used;
   return c->pin_chunks[chunk] + idx;
+}
+
+hipEvent_t ev_get(rzf_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run `launch` between an event pair when timing is on.
+template <class F>
+void timed(rzf_ctx* c, int kernel, F launch) {
+  if (!c->prof_on) { launch(); return; }
+  hipEvent_t a = ev_get(c), b = ev_get(c);
+  if (!a || !b) { launch(); return; }
+  (void)hipEventRecord(a, c->stream);
+  launch();
+  (void)hipEventRecord(b, c->stream);
+  c->prof.push_back(ProfRec{kernel, a, b});
+}
+
+void prof_drain(rzf_ctx* c) {
+  for (const ProfRec& r : c->prof) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->prof_count[r.kernel] += 1;
+      c->prof_ms[r.kernel] += ms;
+    }
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->prof.clear();
 }
 
 rzf_status dev_status(int code) {
@@ -258,6 +310,8 @@ rzf_status rzf_ctx_destroy(rzf_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (rzf_track* t : c->tracks) delete t;
   c->tracks.clear();
+  prof_drain(c);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   for (DevInfo* p : c->pin_chunks) (void)hipHostFree(p);
   if (c->h_sum) (void)hipHostFree(c->h_sum);
   if (c->h_err) (void)hipHostFree(c->h_err);
@@ -351,14 +405,14 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
   const int step = t->t + 1;
   const bool reset = t->prm.reset_period > 0 && t->since_reset + 1 >= t->prm.reset_period;
   if (reset) {
-    launch_gram64(K, N, Hf, ldh, t->alpha, d.A64, s);
-    launch_inv64(K, d.A64, d.Ainv, c->d_err, &t->d_desc->info, s);
+    timed(c, KN_GRAM64, [&] { launch_gram64(K, N, Hf, ldh, t->alpha, d.A64, s); });
+    timed(c, KN_INV64, [&] { launch_inv64(K, d.A64, d.Ainv, c->d_err, &t->d_desc->info, s); });
   } else {
-    launch_gram(K, N, Hf, ldh, d.Hprev, N, d.Anew, d.dA, t->alpha, s);
-    launch_arsvd_wb(t->d_desc, K, step, tol, t->i_max, c->d_err, s);
+    timed(c, KN_GRAM, [&] { launch_gram(K, N, Hf, ldh, d.Hprev, N, d.Anew, d.dA, t->alpha, s); });
+    timed(c, KN_ARSVD, [&] { launch_arsvd_wb(t->d_desc, K, step, tol, t->i_max, c->d_err, s); });
   }
-  launch_precoder(K, N, Hf, ldh, d.Ainv, Wf, ldw, d.wpart, d.Hprev, s);
-  launch_scale(K, N, Wf, ldw, d.wpart, precoder_blocks(N), d.P, s);
+  timed(c, KN_PRECODER, [&] { launch_precoder(K, N, Hf, ldh, d.Ainv, Wf, ldw, d.wpart, d.Hprev, s); });
+  timed(c, KN_SCALE, [&] { launch_scale(K, N, Wf, ldw, d.wpart, precoder_blocks(N), d.P, s); });
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (slot) {
     HIP_OK(hipMemcpyAsync(slot, &t->d_desc->info, sizeof(DevInfo), hipMemcpyDeviceToHost, s));
@@ -379,10 +433,11 @@ rzf_status rzf_full(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   hipStream_t s = c->stream;
   const float2* Hf = reinterpret_cast<const float2*>(H);
   float2* Wf = reinterpret_cast<float2*>(W);
-  launch_gram(K, N, Hf, ldh, nullptr, 0, c->d_fullA, nullptr, alpha, s);
-  launch_inv32(K, c->d_fullA, c->d_fullAinv, c->d_err, s);
-  launch_precoder(K, N, Hf, ldh, c->d_fullAinv, Wf, ldw, c->d_fullwpart, nullptr, s);
-  launch_scale(K, N, Wf, ldw, c->d_fullwpart, precoder_blocks(N), P, s);
+  timed(c, KN_GRAM, [&] { launch_gram(K, N, Hf, ldh, nullptr, 0, c->d_fullA, nullptr, alpha, s); });
+  timed(c, KN_INV32, [&] { launch_inv32(K, c->d_fullA, c->d_fullAinv, c->d_err, s); });
+  timed(c, KN_PRECODER,
+        [&] { launch_precoder(K, N, Hf, ldh, c->d_fullAinv, Wf, ldw, c->d_fullwpart, nullptr, s); });
+  timed(c, KN_SCALE, [&] { launch_scale(K, N, Wf, ldw, c->d_fullwpart, precoder_blocks(N), P, s); });
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
 }
 
@@ -394,8 +449,10 @@ rzf_status rzf_sum_rate(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, con
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
   hipStream_t s = c->stream;
-  launch_sum_rate(K, N, reinterpret_cast<const float2*>(H), ldh, reinterpret_cast<const float2*>(W),
-                  ldw, P, sigma2, rates, c->d_sum, c->d_err, s);
+  timed(c, KN_SUMRATE, [&] {
+    launch_sum_rate(K, N, reinterpret_cast<const float2*>(H), ldh,
+                    reinterpret_cast<const float2*>(W), ldw, P, sigma2, rates, c->d_sum, c->d_err, s);
+  });
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (sum_rate) {
     HIP_OK(hipMemcpyAsync(c->h_sum, c->d_sum, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -454,6 +511,39 @@ rzf_status rzf_debug_sketch(rzf_ctx* c, uint64_t seed, uint64_t track_id, int t,
   HIP_OK(hipSetDevice(c->device));
   launch_debug_sketch(seed, track_id, t, it, K, d, reinterpret_cast<float2*>(Omega), words, c->stream);
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
+}
+
+rzf_status rzf_profile(rzf_ctx* c, int enable) {
+  if (!c) return RZF_E_INVALID;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  if (enable) {
+    prof_drain(c);
+    for (int k = 0; k < KN_COUNT; ++k) { c->prof_count[k] = 0; c->prof_ms[k] = 0.0; }
+  }
+  c->prof_on = enable != 0;
+  return RZF_OK;
+}
+
+rzf_status rzf_profile_read(rzf_ctx* c, rzf_profile_entry* out, int max, int* n) {
+  if (!c || !n || (max > 0 && !out)) return RZF_E_INVALID;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  prof_drain(c);
+  int m = 0;
+  for (int k = 0; k < KN_COUNT; ++k) {
+    if (!c->prof_count[k]) continue;
+    if (m < max) {
+      std::memset(out[m].name, 0, sizeof(out[m].name));
+      std::strncpy(out[m].name, KERNEL_NAMES[k], sizeof(out[m].name) - 1);
+      out[m].count = c->prof_count[k];
+      out[m].total_ms = c->prof_ms[k];
+    }
+    ++m;
+  }
+  *n = m;
+  return RZF_OK;
 }
 
 }  // extern "C"

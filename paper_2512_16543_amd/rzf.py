@@ -42,6 +42,10 @@ class UpdateInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("count", ctypes.c_int), ("total_ms", ctypes.c_double)]
+
+
 class RzfError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -72,6 +76,9 @@ _SIGS = {
     "rzf_get_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rzf_track_query": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 5),
     "rzf_track_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rzf_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "rzf_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ProfileEntry), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]),
     "rzf_debug_sketch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -207,6 +214,15 @@ class Context:
         _check(lib().rzf_sum_rate(self.h, K, N, ctypes.c_void_p(hp), ldh, ctypes.c_void_p(wp), ldw,
                                   float(P), float(sigma2), ctypes.c_void_p(_dev_ptr(rates)), None),
                "rzf_sum_rate")
+
+    def profile(self, enable: bool):
+        _check(lib().rzf_profile(self.h, 1 if enable else 0), "rzf_profile")
+
+    def profile_read(self):
+        arr = (ProfileEntry * 16)()
+        n = ctypes.c_int()
+        _check(lib().rzf_profile_read(self.h, arr, 16, ctypes.byref(n)), "rzf_profile_read")
+        return {arr[i].name.decode(): (arr[i].count, arr[i].total_ms) for i in range(min(n.value, 16))}
 
     def debug_sketch(self, seed: int, track: int, t: int, it: int, K: int, d: int):
         import torch
