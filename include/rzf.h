@@ -167,6 +167,13 @@ rzf_status rzf_track_destroy(rzf_track* tr);
 rzf_status rzf_debug_sketch(rzf_ctx* ctx, uint64_t seed, uint64_t track_id, int t, int it,
                             int K, int d, rzf_c32* Omega, uint64_t* words);
 
+/* Work counters of the track's last update, for tuning: [0] Jacobi sweeps,
+ * [1] Jacobi rounds, [2] Householder columns, [3..6] shader-clock cycles in
+ * sketching, orthogonalisation, SVD and the Woodbury/inversion branch,
+ * [7] constant-rate real-time ticks of the whole arSVD kernel.  Synchronises
+ * the stream; copies min(n, 8) ints to the host array `out`. */
+rzf_status rzf_debug_counters(rzf_track* tr, int* out, int n);
+
 /* Per-kernel timing with HIP events on the context's stream (for measuring a
  * kernel's average duration; off by default).  rzf_profile(ctx, 1) clears the
  * counters and starts recording an event pair around every launch;

@@ -491,6 +491,18 @@ rzf_status rzf_track_query(rzf_track* t, int* K, int* N, int* step, int* since_r
   return RZF_OK;
 }
 
+rzf_status rzf_debug_counters(rzf_track* t, int* out, int n) {
+  if (!t || !out || n < 0) return RZF_E_INVALID;
+  rzf_ctx* c = t->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  int v[8];
+  HIP_OK(hipMemcpy(v, t->d_desc->dbg, sizeof(v), hipMemcpyDeviceToHost));
+  for (int i = 0; i < n && i < 8; ++i) out[i] = v[i];
+  return RZF_OK;
+}
+
 rzf_status rzf_track_destroy(rzf_track* t) {
   if (!t) return RZF_E_INVALID;
   rzf_ctx* c = t->ctx;

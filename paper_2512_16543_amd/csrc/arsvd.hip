@@ -10,14 +10,16 @@
 //   Omega  K x d   CN(0,1) from the counter-based sketch generator
 //   Y      = Delta A Omega                    (matrix cores)
 //   Q      = orth(Y): Householder QR, Q formed explicitly
-//   Z      = Delta A Q                        (matrix cores)
-//   SVD    B = Q^H Delta A = Z^H by one-sided (Hestenes) Jacobi on the
-//          columns of Z; every rotation is applied to the columns of Q as
-//          well, so at convergence z_j = sigma_j v_j and q_j = (Q U_hat)_j.
-//          Hence U_r Sigma_r V_r^H = sum_{j<=r} q_j z_j^H needs no division
-//          by sigma.
-//   r      smallest with sum_{j<=r} sigma_j^2 >= eta ||Delta A||_F^2 (eq. (14));
-//          none: k0 <- 2 k0 and repeat; after I_max iterations r = d.
+//   Z      = Delta A Q                        (matrix cores), so B = Q^H Delta A = Z^H
+//   Some r meets the energy target of eq. (14) exactly when the total
+//   sum_j sigma_j^2 = ||B||_F^2 = ||Z||_F^2 does, so a failing iteration needs
+//   no SVD: k0 <- 2 k0 and the next iteration draws a new sketch.
+//   On success: SVD of B by one-sided (Hestenes) Jacobi on the columns of Z;
+//   every rotation is applied to the columns of Q as well, so at convergence
+//   z_j = sigma_j v_j and q_j = (Q U_hat)_j, and U_r Sigma_r V_r^H =
+//   sum_{j<=r} q_j z_j^H needs no division by sigma.  r is the smallest
+//   count whose leading sigma_j^2 reach eta ||Delta A||_F^2.
+//   After I_max failing iterations r = d and U_r Sigma_r V_r^H = Q Z^H.
 //
 // Woodbury (Sec. III-A, steps 1-5) in the equivalent scaled form with
 // U = [q_j], V~ = [z_j] (V~ = V_r Sigma_r):
@@ -44,12 +46,12 @@ struct Shared {
   float2 b2[KM * KM];            // column-major K x d: Y / reflectors, then Z
   float2 pm[KM * WB_RMAX];       // P = A^-1 U, column-major
   double s2[KM];                 // ||z_j||^2
-  double colj[WB_RMAX];          // Gauss-Jordan: column j before the swap
+  double2 fcol[WB_RMAX];         // Gauss-Jordan: multipliers of column j
   double2 ustash[WB_RMAX + KM];  // Gauss-Jordan: normalised pivot row
   double red[NWV];
   int order[KM];
   int nrot, r, found, piv_row, singular, bad;
-  double pivr, pivi;
+  double pivr, pivi, cap;
 };
 
 // Column pair (p, q) of round k, slot m, of the round-robin ordering over n
@@ -61,31 +63,41 @@ __device__ __forceinline__ void rr_pair(int k, int m, int n, int* p, int* q) {
   *q = (k - m + n1) % n1;
 }
 
-// Wave-level Householder vector of column c (rows >= c) of the column-major
-// matrix `a`; writes the unit vector w (zero above row c) over that column.
-__device__ void reflector(float2* a, int c, int K) {
+// Householder vector of column c (rows >= c) of the column-major matrix `a`
+// from the column's values x held one row per lane; writes the unit vector
+// w (zero above row c) over that column.  H = I - 2 w w^H maps x to
+// beta e_c with beta = -e^{i arg x_c} ||x||.  Wave-level, all lanes active.
+__device__ void reflector_from(float2 x, float2* a, int c, int K) {
   const int lane = threadIdx.x & 63;
-  float2 x = (lane < K && lane >= c) ? a[c * KM + lane] : cz();
+  if (!(lane < K && lane >= c)) x = cz();
   const double s = wave_sum((double)cabs2(x));
-  const float ax = __shfl(x.x, c, 64), ay = __shfl(x.y, c, 64);
+  const float ax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x.x), c));
+  const float ay = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x.y), c));
   float2 w = cz();
   if (s > 0.0) {
-    const double nx = sqrt(s);
-    const double aa = sqrt((double)ax * ax + (double)ay * ay);
-    double ph_r = 1.0, ph_i = 0.0;
-    if (aa > 0.0) { ph_r = ax / aa; ph_i = ay / aa; }
-    const double wn = sqrt(2.0 * nx * (nx + aa));       // ||x - beta e_c||
+    // x is scaled by 1/||x|| (from FP64, so tiny columns do not underflow);
+    // the rest uses FP32 hardware square root / reciprocals, enough for the
+    // working precision of the data
+    const float inx = (float)(1.0 / sqrt(s));
+    const float bx = ax * inx, by = ay * inx;                // x_c / ||x||
+    const float aa = __builtin_amdgcn_sqrtf(bx * bx + by * by);
+    float ph_r = 1.f, ph_i = 0.f;
+    if (aa > 0.f) { const float ia = __builtin_amdgcn_rcpf(aa); ph_r = bx * ia; ph_i = by * ia; }
+    const float iw = __builtin_amdgcn_rsqf(2.f * (1.f + aa));   // 1 / ||x - beta e_c|| (scaled)
     if (lane == c) {
-      w = make_float2((float)(ph_r * (aa + nx) / wn), (float)(ph_i * (aa + nx) / wn));
+      const float m = (aa + 1.f) * iw;
+      w = make_float2(ph_r * m, ph_i * m);
     } else {
-      w = make_float2((float)(x.x / wn), (float)(x.y / wn));
+      const float m = inx * iw;
+      w = make_float2(x.x * m, x.y * m);
     }
   }
   if (lane < K) a[c * KM + lane] = (lane >= c) ? w : cz();
 }
 
-// y <- (I - 2 w w^H) y for column y of `a` and reflector column wc of `wsrc`.
-__device__ __forceinline__ void apply_reflector(const float2* wsrc, int wc, float2* a, int c, int K) {
+// y <- (I - 2 w w^H) y for column c of `a` and reflector column wc of `wsrc`.
+// Returns the updated column value of the calling lane.
+__device__ __forceinline__ float2 apply_reflector(const float2* wsrc, int wc, float2* a, int c, int K) {
   const int lane = threadIdx.x & 63;
   const float2 w = (lane < K) ? wsrc[wc * KM + lane] : cz();
   float2 y = (lane < K) ? a[c * KM + lane] : cz();
@@ -97,6 +109,7 @@ __device__ __forceinline__ void apply_reflector(const float2* wsrc, int wc, floa
   y.x -= w.x * fr - w.y * fi;
   y.y -= w.x * fi + w.y * fr;
   if (lane < K) a[c * KM + lane] = y;
+  return y;
 }
 
 // Tiled complex product over LDS on the matrix cores.  Output M x Nc in
@@ -120,6 +133,111 @@ __device__ __forceinline__ void lds_gemm(int M, int Nc, int Kd, const LA& la, co
   }
 }
 
+// One-sided Jacobi on the d columns of Z (b2), rotating Q (b1) alongside.
+// Each 16-lane row of a wave owns one column pair per round (4 rows of the
+// matrix per lane), so a round of the round-robin ordering is one barrier.
+__device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* rounds_out) {
+  float2* b1 = sm.b1;
+  float2* b2 = sm.b2;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int li = lane & 15, slot = wid * 4 + (lane >> 4);
+  const int n = d + (d & 1);
+  int sweeps = 0, rounds = 0;
+  for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
+    if (threadIdx.x == 0) sm.nrot = 0;
+    __syncthreads();
+    ++sweeps;
+    for (int k = 0; k < n - 1; ++k) {
+      ++rounds;
+      int pp = 0, qq = 0;
+      bool act = slot < n / 2;
+      if (act) {
+        rr_pair(k, slot, n, &pp, &qq);
+        act = pp < d && qq < d;
+      }
+      float2 zp[4], zq[4], qa[4], qb[4];
+      double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int i = li + 16 * m;
+        const bool ok = act && i < K;
+        zp[m] = ok ? b2[pp * KM + i] : cz();
+        zq[m] = ok ? b2[qq * KM + i] : cz();
+        qa[m] = ok ? b1[pp * KM + i] : cz();    // loaded early to overlap latency
+        qb[m] = ok ? b1[qq * KM + i] : cz();
+        al += (double)cabs2(zp[m]);
+        be += (double)cabs2(zq[m]);
+        gr += (double)zp[m].x * zq[m].x + (double)zp[m].y * zq[m].y;
+        gi += (double)zp[m].x * zq[m].y - (double)zp[m].y * zq[m].x;
+      }
+      al = row16_sum(al);
+      be = row16_sum(be);
+      gr = row16_sum(gr);
+      gi = row16_sum(gi);
+      const double g2 = gr * gr + gi * gi;
+      bool rot = act && g2 > 0.0 && g2 > JACOBI_TOL * JACOBI_TOL * al * be;
+      float c = 1.f, s = 0.f;
+      float2 e = make_float2(1.f, 0.f);
+      if (rot) {
+        // rotation parameters in FP32 with hardware rsq/rcp (the columns are
+        // FP32), on sums scaled by 1/max(alpha, beta) so nothing underflows;
+        // a pair whose scaled |gamma|^2 is below the FP32 normal range is
+        // already orthogonal to working precision
+        const double sc = __builtin_amdgcn_rcp(fmax(al, be));
+        const float alf = (float)(al * sc), bef = (float)(be * sc);
+        const float grf = (float)(gr * sc), gif = (float)(gi * sc);
+        const float gg = grf * grf + gif * gif;
+        rot = gg >= 1e-36f;
+        const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));   // 1/|gamma|
+        const float zeta = (bef - alf) * 0.5f * ig;
+        const float az = fabsf(zeta);
+        const float tmag = (az > 1e18f) ? 0.5f * __builtin_amdgcn_rcpf(az)
+                                        : __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(1.f + az * az));
+        const float tt = zeta >= 0.f ? tmag : -tmag;
+        c = __builtin_amdgcn_rsqf(1.f + tt * tt);
+        s = c * tt;
+        e = make_float2(grf * ig, -gif * ig);   // conj(gamma)/|gamma|
+      }
+      if (rot) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int i = li + 16 * m;
+          if (i >= K) continue;
+          const float2 qp = qa[m], qv = qb[m];
+          const float2 zq2 = cmul(e, zq[m]), qv2 = cmul(e, qv);
+          b2[pp * KM + i] = csub(cscale(zp[m], c), cscale(zq2, s));
+          b2[qq * KM + i] = cadd(cscale(zp[m], s), cscale(zq2, c));
+          b1[pp * KM + i] = csub(cscale(qp, c), cscale(qv2, s));
+          b1[qq * KM + i] = cadd(cscale(qp, s), cscale(qv2, c));
+        }
+        if (li == 0) sm.nrot = 1;
+      }
+      __syncthreads();
+    }
+    const bool done = (sm.nrot == 0);
+    __syncthreads();
+    if (done) break;
+  }
+  *sweeps_out += sweeps;
+  *rounds_out += rounds;
+}
+
+// Squared norms of the d columns of Z (b2) into sm.s2, one 16-lane row per column.
+__device__ void column_norms(Shared& sm, int K, int d) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int li = lane & 15, slot = wid * 4 + (lane >> 4);
+  double v = 0.0;
+  if (slot < d) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = li + 16 * m;
+      if (i < K) v += (double)cabs2(sm.b2[slot * KM + i]);
+    }
+  }
+  v = row16_sum(v);
+  if (slot < d && li == 0) sm.s2[slot] = v;
+}
+
 __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, int t, double eta,
                                                   int i_max, int* err) {
   __shared__ Shared sm;
@@ -138,31 +256,28 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
     part += (double)v.x * v.x + (double)v.y * v.y;
   }
   const double E = block_sum(part, sm.red);
-  if (!isfinite(E)) {
+  if (!isfinite(E) || E == 0.0) {
     if (tid == 0) {
-      atomicCAS(err, 0, DEV_ERR_NONFINITE);
+      if (!isfinite(E)) atomicCAS(err, 0, DEV_ERR_NONFINITE);
       td->info.r = 0; td->info.iters = 0; td->info.path = RZF_PATH_NOOP; td->info.d = 0;
       td->info.dA_fro2 = E; td->info.captured = 0.0;
-    }
-    return;
-  }
-  if (E == 0.0) {
-    if (tid == 0) {
-      td->info.r = 0; td->info.iters = 0; td->info.path = RZF_PATH_NOOP; td->info.d = 0;
-      td->info.dA_fro2 = 0.0; td->info.captured = 0.0;
-      td->last_r = 0;
+      if (E == 0.0) td->last_r = 0;
+      td->dbg[0] = 0; td->dbg[1] = 0; td->dbg[2] = 0;
     }
     return;
   }
   const double Et = eta * E;
+  long long t_sk = 0, t_qr = 0, t_jac = 0, t_wb = 0;
+  const long long c_begin = clock64(), r_begin = wall_clock64();
+  long long c_mark = c_begin;
   int k0 = td->k_init;
   if (td->kinit_policy == RZF_KINIT_WARM && td->last_r > k0) k0 = td->last_r;
   const int p = td->p;
   const uint64_t seed = td->seed, trk = td->track_id;
 
-  int d = 0, iters = 0, r = 0;
+  int d = 0, iters = 0, r = 0, sweeps = 0, rounds = 0, qrcols = 0;
   double captured = 0.0;
-  bool found = false;
+  bool found = false, rotated = false;
   for (int it = 1; it <= i_max; ++it) {
     iters = it;
     d = min(k0 + p, K);
@@ -178,15 +293,19 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
              [&](int k, int j) { return (k < K && j < d) ? b1[j * KM + k] : cz(); },
              [&](int i, int j, float2 v) { b2[j * KM + i] = v; });
     __syncthreads();
-    // Householder QR of Y (b2): reflector j lands in column j of b2
-    if (wid == 0) reflector(b2, 0, K);
+    t_sk += clock64() - c_mark; c_mark = clock64();
+    // Householder QR of Y (b2): reflector j lands in column j of b2.  Wave 0
+    // updates column j+1 and immediately forms its reflector (one barrier per
+    // column); the other waves update the remaining columns.
+    if (wid == 0) reflector_from((lane < K) ? b2[lane] : cz(), b2, 0, K);
     for (int j = 0; j < d; ++j) {
       __syncthreads();
       for (int c = j + 1 + wid; c < d; c += NWV) {
-        apply_reflector(b2, j, b2, c, K);
-        if (c == j + 1) reflector(b2, c, K);
+        const float2 y = apply_reflector(b2, j, b2, c, K);
+        if (c == j + 1) reflector_from(y, b2, c, K);
       }
     }
+    qrcols += d;
     // Q = H_0 ... H_{d-1} [I_d; 0] -> b1
     for (int e = tid; e < d * KM; e += NTH) {
       const int j = e / KM, i = e - j * KM;
@@ -202,90 +321,60 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
              [&](int i, int k) { return (i < K && k < K) ? b0[i * KM + k] : cz(); },
              [&](int k, int j) { return (k < K && j < d) ? b1[j * KM + k] : cz(); },
              [&](int i, int j, float2 v) { b2[j * KM + i] = v; });
-    // One-sided Jacobi on the columns of Z, rotating Q alongside
-    const int n = d + (d & 1);
-    for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
-      if (tid == 0) sm.nrot = 0;
+    __syncthreads();
+    // ||B||_F^2 = ||Z||_F^2: does any r reach the target?
+    double zp = 0.0;
+    for (int e = tid; e < K * d; e += NTH) {
+      const int j = e / K, i = e - j * K;
+      zp += (double)cabs2(b2[j * KM + i]);
+    }
+    const double tot = block_sum(zp, sm.red);
+    t_qr += clock64() - c_mark; c_mark = clock64();
+    if (tot >= Et) {
+      found = true;
+      jacobi_svd(sm, K, d, &sweeps, &rounds);
+      t_jac += clock64() - c_mark; c_mark = clock64();
+      rotated = true;
+      column_norms(sm, K, d);
       __syncthreads();
-      for (int k = 0; k < n - 1; ++k) {
-        for (int m = wid; m < n / 2; m += NWV) {
-          int pp, qq;
-          rr_pair(k, m, n, &pp, &qq);
-          if (pp >= d || qq >= d) continue;
-          float2 zp = (lane < K) ? b2[pp * KM + lane] : cz();
-          float2 zq = (lane < K) ? b2[qq * KM + lane] : cz();
-          const double al = wave_sum((double)cabs2(zp));
-          const double be = wave_sum((double)cabs2(zq));
-          const double gr = wave_sum((double)zp.x * zq.x + (double)zp.y * zq.y);
-          const double gi = wave_sum((double)zp.x * zq.y - (double)zp.y * zq.x);
-          const double g = sqrt(gr * gr + gi * gi);
-          if (g > 0.0 && g > JACOBI_TOL * sqrt(al * be)) {
-            const double zeta = (be - al) / (2.0 * g);
-            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + tt * tt);
-            const float c = (float)cs, s = (float)(cs * tt);
-            const float2 e = make_float2((float)(gr / g), (float)(-gi / g));   // conj(gamma)/|gamma|
-            float2 qp = (lane < K) ? b1[pp * KM + lane] : cz();
-            float2 qv = (lane < K) ? b1[qq * KM + lane] : cz();
-            const float2 zq2 = cmul(e, zq), qv2 = cmul(e, qv);
-            const float2 nzp = csub(cscale(zp, c), cscale(zq2, s));
-            const float2 nzq = cadd(cscale(zp, s), cscale(zq2, c));
-            const float2 nqp = csub(cscale(qp, c), cscale(qv2, s));
-            const float2 nqq = cadd(cscale(qp, s), cscale(qv2, c));
-            if (lane < K) {
-              b2[pp * KM + lane] = nzp; b2[qq * KM + lane] = nzq;
-              b1[pp * KM + lane] = nqp; b1[qq * KM + lane] = nqq;
-            }
-            if (lane == 0) sm.nrot = 1;
-          }
+      if (tid < d) {
+        const double v = sm.s2[tid];
+        int rank = 0;
+        for (int k = 0; k < d; ++k) {
+          const double w = sm.s2[k];
+          rank += (w > v) || (w == v && k < tid);
         }
-        __syncthreads();
+        sm.order[rank] = tid;
       }
-      const bool done = (sm.nrot == 0);
       __syncthreads();
-      if (done) break;
-    }
-    // sigma_j^2 = ||z_j||^2, descending order, smallest r meeting the target
-    for (int j = wid; j < d; j += NWV) {
-      const float2 z = (lane < K) ? b2[j * KM + lane] : cz();
-      const double v = wave_sum((double)cabs2(z));
-      if (lane == 0) sm.s2[j] = v;
-    }
-    __syncthreads();
-    if (tid < d) {
-      const double v = sm.s2[tid];
-      int rank = 0;
-      for (int k = 0; k < d; ++k) {
-        const double w = sm.s2[k];
-        rank += (w > v) || (w == v && k < tid);
+      if (tid == 0) {
+        double cs = 0.0;
+        int rr = d;
+        for (int m = 0; m < d; ++m) {
+          cs += sm.s2[sm.order[m]];
+          if (cs >= Et) { rr = m + 1; break; }
+        }
+        sm.r = rr;
+        sm.cap = cs;
       }
-      sm.order[rank] = tid;
+      __syncthreads();
+      r = sm.r;
+      captured = sm.cap;
+      break;
     }
-    __syncthreads();
-    if (tid == 0) {
-      double cs = 0.0;
-      int rr = 0;
-      for (int m = 0; m < d; ++m) {
-        cs += sm.s2[sm.order[m]];
-        if (cs >= Et) { rr = m + 1; break; }
-      }
-      sm.found = rr > 0;
-      sm.r = rr > 0 ? rr : d;
-      // retained energy of the returned components
-      double cap = 0.0;
-      for (int m = 0; m < sm.r; ++m) cap += sm.s2[sm.order[m]];
-      sm.red[0] = cap;
+    if (it == i_max) {
+      r = d;                 // every component: U_r Sigma_r V_r^H = Q Z^H
+      captured = tot;
     }
-    __syncthreads();
-    found = sm.found != 0;
-    r = sm.r;
-    captured = sm.red[0];
-    __syncthreads();
-    if (found) break;
     k0 *= 2;
   }
+  if (!rotated) {
+    if (tid < d) sm.order[tid] = tid;
+    __syncthreads();
+  }
+  (void)found;
 
-  int rmax = (int)floor(td->switch_ratio * (double)K);
+  const int rmax = (int)floor(td->switch_ratio * (double)K);
   bool use_wb = r <= rmax && r <= WB_RMAX;
   int path = use_wb ? RZF_PATH_WB : RZF_PATH_FULL_RANK;
 
@@ -350,33 +439,36 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
     for (int j = 0; j < r; ++j) {
       if (wid == 0) {
         const double2 v = (lane < r) ? aug[lane * ldg + j] : dz();
-        double mag = (lane >= j && lane < r) ? dabs2(v) : -1.0;
-        int idx = lane;
-        for (int off = 32; off > 0; off >>= 1) {
-          const double om = __shfl_xor(mag, off, 64);
-          const int oi = __shfl_xor(idx, off, 64);
-          if (om > mag || (om == mag && oi < idx)) { mag = om; idx = oi; }
-        }
-        if (lane < r) sm.colj[lane] = 0.0;   // placeholder, real values below
-        if (lane == 0) {
+        const double mag = (lane >= j && lane < r) ? dabs2(v) : -1.0;
+        double mx = mag;
+        mx = fmax(mx, dpp_d<DPP_QUAD_1032>(mx));
+        mx = fmax(mx, dpp_d<DPP_QUAD_2301>(mx));
+        mx = fmax(mx, dpp_d<DPP_ROW_ROR4>(mx));
+        mx = fmax(mx, dpp_d<DPP_ROW_ROR8>(mx));
+        mx = fmax(fmax(readlane_d(mx, 0), readlane_d(mx, 16)), fmax(readlane_d(mx, 32), readlane_d(mx, 48)));
+        const unsigned long long hit = __ballot(mag == mx);
+        const int idx = __ffsll((long long)hit) - 1;   // smallest row holding the maximum
+        if (idx < 0) {                                  // NaN column: no maximum
+          if (lane == 0) { sm.piv_row = j; sm.singular = 1; }
+        } else if (lane == idx) {
           sm.piv_row = idx;
-          if (!(sqrt(mag) > SING_TOL) || !isfinite(mag)) sm.singular = 1;
+          sm.pivr = v.x;
+          sm.pivi = v.y;
+          if (!(sqrt(mx) > SING_TOL) || !isfinite(mx)) sm.singular = 1;
         }
-        if (lane == idx) { sm.pivr = v.x; sm.pivi = v.y; }
       }
       __syncthreads();
       if (sm.singular) break;
       const int pr = sm.piv_row;
       const double2 piv = make_double2(sm.pivr, sm.pivi);
-      // multipliers of the rows after the swap, from the column before it
+      // multipliers of the rows after the swap, read before it
       double2 fj = dz();
       if (tid < r) {
         const int src = (tid == j) ? pr : (tid == pr ? j : tid);
         fj = aug[src * ldg + j];
       }
       __syncthreads();
-      double2* fcol = reinterpret_cast<double2*>(sm.s2);   // r <= 32 entries
-      if (tid < r) fcol[tid] = fj;
+      if (tid < r) sm.fcol[tid] = fj;
       for (int c = j + tid; c < ldg; c += NTH) {
         const double2 a = aug[j * ldg + c], b = aug[pr * ldg + c];
         const double2 u = ddiv(b, piv);
@@ -389,7 +481,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
       for (int e = tid; e < r * w; e += NTH) {
         const int i = e / w, c = j + 1 + (e - i * w);
         if (i == j) continue;
-        aug[i * ldg + c] = dsub(aug[i * ldg + c], dmul(fcol[i], sm.ustash[c]));
+        aug[i * ldg + c] = dsub(aug[i * ldg + c], dmul(sm.fcol[i], sm.ustash[c]));
       }
       __syncthreads();
     }
@@ -425,6 +517,11 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
     td->info.r = r; td->info.iters = iters; td->info.path = path; td->info.d = d;
     td->info.dA_fro2 = E; td->info.captured = captured;
     td->last_r = r;
+    td->dbg[0] = sweeps; td->dbg[1] = rounds; td->dbg[2] = qrcols;
+    t_wb = clock64() - c_mark;
+    td->dbg[3] = (int)t_sk; td->dbg[4] = (int)t_qr; td->dbg[5] = (int)t_jac; td->dbg[6] = (int)t_wb;
+    td->dbg[7] = (int)(wall_clock64() - r_begin);
+    (void)c_begin;
   }
 }
 

@@ -43,15 +43,57 @@ __device__ __forceinline__ double2 f2d(float2 a) { return make_double2((double)a
 __device__ __forceinline__ float2 d2f(double2 a) { return make_float2((float)a.x, (float)a.y); }
 
 // --------------------------------------------------------- wave reductions
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, RZF_WAVE);
+// Cross-lane sums with DPP row operations (quad permutations and row
+// rotations inside each 16-lane row) and v_readlane to combine the four rows.
+// All 64 lanes must be active when these are called.
+#define DPP_QUAD_1032 0xB1   // quad_perm [1,0,3,2]
+#define DPP_QUAD_2301 0x4E   // quad_perm [2,3,0,1]
+#define DPP_ROW_ROR4 0x124
+#define DPP_ROW_ROR8 0x128
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over the 16 lanes of each row; every lane of the row gets the row sum.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<DPP_QUAD_1032>(v);
+  v += dpp_d<DPP_QUAD_2301>(v);
+  v += dpp_d<DPP_ROW_ROR4>(v);
+  v += dpp_d<DPP_ROW_ROR8>(v);
   return v;
 }
-__device__ __forceinline__ float wave_sumf(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, RZF_WAVE);
+__device__ __forceinline__ float row16_sumf(float v) {
+  v += dpp_f<DPP_QUAD_1032>(v);
+  v += dpp_f<DPP_QUAD_2301>(v);
+  v += dpp_f<DPP_ROW_ROR4>(v);
+  v += dpp_f<DPP_ROW_ROR8>(v);
   return v;
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over all 64 lanes (same value, same rounding, in every lane).
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row16_sum(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+__device__ __forceinline__ float wave_sumf(float v) {
+  v = row16_sumf(v);
+  return (__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)) +
+          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16))) +
+         (__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32)) +
+          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48)));
 }
 
 // Sum over the whole workgroup; `red` holds one double per wave.  Every

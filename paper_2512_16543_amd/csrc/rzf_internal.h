@@ -35,6 +35,7 @@ struct TrackDesc {
   int last_r;
   int pad_;
   DevInfo info;
+  int dbg[8];      // last update: [0] Jacobi sweeps, [1] Jacobi rounds, [2] QR columns
 };
 
 // Launchers (defined next to their kernels).

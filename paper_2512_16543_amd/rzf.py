@@ -76,6 +76,7 @@ _SIGS = {
     "rzf_get_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rzf_track_query": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 5),
     "rzf_track_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rzf_debug_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "rzf_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "rzf_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ProfileEntry), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]),
@@ -262,6 +263,13 @@ class Track:
         vals = [ctypes.c_int() for _ in range(5)]
         _check(lib().rzf_track_query(self.h, *[ctypes.byref(v) for v in vals]), "rzf_track_query")
         return dict(zip(("K", "N", "t", "since_reset", "last_r"), (v.value for v in vals)))
+
+    def counters(self):
+        arr = (ctypes.c_int * 8)()
+        _check(lib().rzf_debug_counters(self.h, arr, 8), "rzf_debug_counters")
+        return {"jacobi_sweeps": arr[0], "jacobi_rounds": arr[1], "qr_columns": arr[2],
+                "cyc_sketch": arr[3], "cyc_qr": arr[4], "cyc_jacobi": arr[5], "cyc_wb": arr[6],
+                "realtime_ticks": arr[7]}
 
     def destroy(self):
         if self.h:
