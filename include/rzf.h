@@ -174,6 +174,11 @@ rzf_status rzf_debug_sketch(rzf_ctx* ctx, uint64_t seed, uint64_t track_id, int 
  * the stream; copies min(n, 8) ints to the host array `out`. */
 rzf_status rzf_debug_counters(rzf_track* tr, int* out, int n);
 
+/* The sigma_j^2 of the last update's small SVD (Alg. 1, the SVD of B),
+ * descending: copies min(n, d) values to the host array `out` and stores d
+ * in *d_out (0 when the update ran no SVD).  Synchronises the stream. */
+rzf_status rzf_debug_sigma2(rzf_track* tr, double* out, int n, int* d_out);
+
 /* Per-kernel timing with HIP events on the context's stream (for measuring a
  * kernel's average duration; off by default).  rzf_profile(ctx, 1) clears the
  * counters and starts recording an event pair around every launch;

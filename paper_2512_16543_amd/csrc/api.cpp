@@ -51,6 +51,7 @@ struct rzf_ctx {
   float2* d_fullAinv = nullptr;
   double* d_fullwpart = nullptr;
   double* d_sum = nullptr;
+  double* d_srpart = nullptr;
   // pinned host staging
   double* h_sum = nullptr;
   int* h_err = nullptr;
@@ -84,7 +85,8 @@ namespace {
 
 size_t scratch_bytes() {
   return align_up(sizeof(int) * 64) + 2 * align_up(sizeof(float2) * KM * KM) +
-         align_up(sizeof(double) * ((RZF_NMAX + 15) / 16)) + align_up(sizeof(double) * 8);
+         align_up(sizeof(double) * ((RZF_NMAX + 15) / 16)) + align_up(sizeof(double) * 8) +
+         align_up(sizeof(double) * sum_rate_scratch_doubles(KM));
 }
 
 struct Layout {
@@ -286,7 +288,8 @@ rzf_status rzf_ctx_create(int device, void* hip_stream, void* arena, size_t aren
   c->d_fullA = reinterpret_cast<float2*>(p); p += align_up(sizeof(float2) * KM * KM);
   c->d_fullAinv = reinterpret_cast<float2*>(p); p += align_up(sizeof(float2) * KM * KM);
   c->d_fullwpart = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * ((RZF_NMAX + 15) / 16));
-  c->d_sum = reinterpret_cast<double*>(p);
+  c->d_sum = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * 8);
+  c->d_srpart = reinterpret_cast<double*>(p);
   c->free_blocks[scr] = arena_bytes - scr;
   if (hipHostMalloc((void**)&c->h_sum, sizeof(double) * 8, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_err, sizeof(int) * 8, hipHostMallocDefault) != hipSuccess) {
@@ -451,7 +454,8 @@ rzf_status rzf_sum_rate(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, con
   hipStream_t s = c->stream;
   timed(c, KN_SUMRATE, [&] {
     launch_sum_rate(K, N, reinterpret_cast<const float2*>(H), ldh,
-                    reinterpret_cast<const float2*>(W), ldw, P, sigma2, rates, c->d_sum, c->d_err, s);
+                    reinterpret_cast<const float2*>(W), ldw, P, sigma2, rates, c->d_sum,
+                    c->d_srpart, c->d_err, s);
   });
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (sum_rate) {
@@ -500,6 +504,21 @@ rzf_status rzf_debug_counters(rzf_track* t, int* out, int n) {
   int v[8];
   HIP_OK(hipMemcpy(v, t->d_desc->dbg, sizeof(v), hipMemcpyDeviceToHost));
   for (int i = 0; i < n && i < 8; ++i) out[i] = v[i];
+  return RZF_OK;
+}
+
+rzf_status rzf_debug_sigma2(rzf_track* t, double* out, int n, int* d_out) {
+  if (!t || !d_out || (n > 0 && !out)) return RZF_E_INVALID;
+  rzf_ctx* c = t->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  int d = 0;
+  HIP_OK(hipMemcpy(&d, &t->d_desc->nsig, sizeof(int), hipMemcpyDeviceToHost));
+  if (d < 0 || d > KM) d = 0;
+  const int m = n < d ? n : d;
+  if (m > 0) HIP_OK(hipMemcpy(out, t->d_desc->sig2, sizeof(double) * m, hipMemcpyDeviceToHost));
+  *d_out = d;
   return RZF_OK;
 }
 

@@ -40,6 +40,7 @@ constexpr int MAX_SWEEPS = 30;
 constexpr double JACOBI_TOL = 2e-6;
 constexpr double SING_TOL = 1e-12;
 
+
 struct Shared {
   float2 b0[KM * KM];            // Delta A (row-major, ld KM); later A^-1 or A'
   float2 b1[KM * KM];            // column-major K x d: Omega, then Q
@@ -70,15 +71,16 @@ __device__ __forceinline__ void rr_pair(int k, int m, int n, int* p, int* q) {
 __device__ void reflector_from(float2 x, float2* a, int c, int K) {
   const int lane = threadIdx.x & 63;
   if (!(lane < K && lane >= c)) x = cz();
-  const double s = wave_sum((double)cabs2(x));
+  const float s = wave_sumf(cabs2(x));
   const float ax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x.x), c));
   const float ay = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x.y), c));
   float2 w = cz();
-  if (s > 0.0) {
-    // x is scaled by 1/||x|| (from FP64, so tiny columns do not underflow);
-    // the rest uses FP32 hardware square root / reciprocals, enough for the
-    // working precision of the data
-    const float inx = (float)(1.0 / sqrt(s));
+  if (s >= 1e-36f) {
+    // x is scaled by 1/||x||; FP32 hardware square root / reciprocals are
+    // enough for the working precision of the data (a column whose squared
+    // norm is below the FP32 normal range is treated as zero: H = I keeps Q
+    // orthonormal)
+    const float inx = __builtin_amdgcn_rsqf(s);
     const float bx = ax * inx, by = ay * inx;                // x_c / ||x||
     const float aa = __builtin_amdgcn_sqrtf(bx * bx + by * by);
     float ph_r = 1.f, ph_i = 0.f;
@@ -101,11 +103,11 @@ __device__ __forceinline__ float2 apply_reflector(const float2* wsrc, int wc, fl
   const int lane = threadIdx.x & 63;
   const float2 w = (lane < K) ? wsrc[wc * KM + lane] : cz();
   float2 y = (lane < K) ? a[c * KM + lane] : cz();
-  double dr = (double)w.x * y.x + (double)w.y * y.y;     // conj(w) y
-  double di = (double)w.x * y.y - (double)w.y * y.x;
-  dr = wave_sum(dr);
-  di = wave_sum(di);
-  const float fr = (float)(2.0 * dr), fi = (float)(2.0 * di);
+  float dr = w.x * y.x + w.y * y.y;     // conj(w) y
+  float di = w.x * y.y - w.y * y.x;
+  dr = wave_sumf(dr);
+  di = wave_sumf(di);
+  const float fr = 2.f * dr, fi = 2.f * di;
   y.x -= w.x * fr - w.y * fi;
   y.y -= w.x * fi + w.y * fr;
   if (lane < K) a[c * KM + lane] = y;
@@ -136,6 +138,9 @@ __device__ __forceinline__ void lds_gemm(int M, int Nc, int Kd, const LA& la, co
 // One-sided Jacobi on the d columns of Z (b2), rotating Q (b1) alongside.
 // Each 16-lane row of a wave owns one column pair per round (4 rows of the
 // matrix per lane), so a round of the round-robin ordering is one barrier.
+// ||z_p||^2 and ||z_q||^2 are sums of non-negative FP32 terms; the inner
+// product z_p^H z_q, which cancels as the columns become orthogonal, is
+// accumulated in FP64 (FP32 products are exact there).
 __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* rounds_out) {
   float2* b1 = sm.b1;
   float2* b2 = sm.b2;
@@ -149,68 +154,73 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
     ++sweeps;
     for (int k = 0; k < n - 1; ++k) {
       ++rounds;
-      int pp = 0, qq = 0;
-      bool act = slot < n / 2;
-      if (act) {
-        rr_pair(k, slot, n, &pp, &qq);
-        act = pp < d && qq < d;
-      }
-      float2 zp[4], zq[4], qa[4], qb[4];
-      double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int i = li + 16 * m;
-        const bool ok = act && i < K;
-        zp[m] = ok ? b2[pp * KM + i] : cz();
-        zq[m] = ok ? b2[qq * KM + i] : cz();
-        qa[m] = ok ? b1[pp * KM + i] : cz();    // loaded early to overlap latency
-        qb[m] = ok ? b1[qq * KM + i] : cz();
-        al += (double)cabs2(zp[m]);
-        be += (double)cabs2(zq[m]);
-        gr += (double)zp[m].x * zq[m].x + (double)zp[m].y * zq[m].y;
-        gi += (double)zp[m].x * zq[m].y - (double)zp[m].y * zq[m].x;
-      }
-      al = row16_sum(al);
-      be = row16_sum(be);
-      gr = row16_sum(gr);
-      gi = row16_sum(gi);
-      const double g2 = gr * gr + gi * gi;
-      bool rot = act && g2 > 0.0 && g2 > JACOBI_TOL * JACOBI_TOL * al * be;
-      float c = 1.f, s = 0.f;
-      float2 e = make_float2(1.f, 0.f);
-      if (rot) {
-        // rotation parameters in FP32 with hardware rsq/rcp (the columns are
-        // FP32), on sums scaled by 1/max(alpha, beta) so nothing underflows;
-        // a pair whose scaled |gamma|^2 is below the FP32 normal range is
-        // already orthogonal to working precision
-        const double sc = __builtin_amdgcn_rcp(fmax(al, be));
-        const float alf = (float)(al * sc), bef = (float)(be * sc);
-        const float grf = (float)(gr * sc), gif = (float)(gi * sc);
-        const float gg = grf * grf + gif * gif;
-        rot = gg >= 1e-36f;
-        const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));   // 1/|gamma|
-        const float zeta = (bef - alf) * 0.5f * ig;
-        const float az = fabsf(zeta);
-        const float tmag = (az > 1e18f) ? 0.5f * __builtin_amdgcn_rcpf(az)
-                                        : __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(1.f + az * az));
-        const float tt = zeta >= 0.f ? tmag : -tmag;
-        c = __builtin_amdgcn_rsqf(1.f + tt * tt);
-        s = c * tt;
-        e = make_float2(grf * ig, -gif * ig);   // conj(gamma)/|gamma|
-      }
-      if (rot) {
+      if (wid * 4 < n / 2) {          // waves without a pair only take the barrier
+        int pp = 0, qq = 0;
+        bool act = slot < n / 2;
+        if (act) {
+          rr_pair(k, slot, n, &pp, &qq);
+          act = pp < d && qq < d;
+        }
+        float2 zp[4], zq[4], qa[4], qb[4];
+        float al = 0.f, be = 0.f;
+        double gr = 0.0, gi = 0.0;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const int i = li + 16 * m;
-          if (i >= K) continue;
-          const float2 qp = qa[m], qv = qb[m];
-          const float2 zq2 = cmul(e, zq[m]), qv2 = cmul(e, qv);
-          b2[pp * KM + i] = csub(cscale(zp[m], c), cscale(zq2, s));
-          b2[qq * KM + i] = cadd(cscale(zp[m], s), cscale(zq2, c));
-          b1[pp * KM + i] = csub(cscale(qp, c), cscale(qv2, s));
-          b1[qq * KM + i] = cadd(cscale(qp, s), cscale(qv2, c));
+          const bool ok = act && i < K;
+          zp[m] = ok ? b2[pp * KM + i] : cz();
+          zq[m] = ok ? b2[qq * KM + i] : cz();
+          qa[m] = ok ? b1[pp * KM + i] : cz();    // loaded early to overlap latency
+          qb[m] = ok ? b1[qq * KM + i] : cz();
         }
-        if (li == 0) sm.nrot = 1;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          al += cabs2(zp[m]);
+          be += cabs2(zq[m]);
+          gr += (double)zp[m].x * zq[m].x + (double)zp[m].y * zq[m].y;
+          gi += (double)zp[m].x * zq[m].y - (double)zp[m].y * zq[m].x;
+        }
+        al = row16_sum(al);
+        be = row16_sum(be);
+        gr = row16_sum(gr);
+        gi = row16_sum(gi);
+        const float mx = fmaxf(al, be);
+        bool rot = act && mx > 0.f;
+        float c = 1.f, s = 0.f;
+        float2 e = make_float2(1.f, 0.f);
+        if (rot) {
+          // rotation parameters with hardware rsq/rcp on sums scaled by
+          // 1/max(alpha, beta) so nothing underflows; a pair whose scaled
+          // |gamma|^2 is below the FP32 normal range is already orthogonal to
+          // working precision
+          const float sc = __builtin_amdgcn_rcpf(mx);
+          const float alf = al * sc, bef = be * sc;
+          const float grf = (float)gr * sc, gif = (float)gi * sc;
+          const float gg = grf * grf + gif * gif;
+          rot = gg >= 1e-36f && gg > (float)(JACOBI_TOL * JACOBI_TOL) * alf * bef;
+          const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));   // 1/|gamma|
+          const float zeta = (bef - alf) * 0.5f * ig;
+          const float az = fabsf(zeta);
+          const float tmag = (az > 1e18f) ? 0.5f * __builtin_amdgcn_rcpf(az)
+                                          : __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(1.f + az * az));
+          const float tt = zeta >= 0.f ? tmag : -tmag;
+          c = __builtin_amdgcn_rsqf(1.f + tt * tt);
+          s = c * tt;
+          e = make_float2(grf * ig, -gif * ig);   // conj(gamma)/|gamma|
+        }
+        if (rot) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int i = li + 16 * m;
+            if (i >= K) continue;
+            const float2 zq2 = cmul(e, zq[m]), qv2 = cmul(e, qb[m]);
+            b2[pp * KM + i] = csub(cscale(zp[m], c), cscale(zq2, s));
+            b2[qq * KM + i] = cadd(cscale(zp[m], s), cscale(zq2, c));
+            b1[pp * KM + i] = csub(cscale(qa[m], c), cscale(qv2, s));
+            b1[qq * KM + i] = cadd(cscale(qa[m], s), cscale(qv2, c));
+          }
+          if (li == 0) sm.nrot = 1;
+        }
       }
       __syncthreads();
     }
@@ -238,6 +248,41 @@ __device__ void column_norms(Shared& sm, int K, int d) {
   if (slot < d && li == 0) sm.s2[slot] = v;
 }
 
+// After the SVD: sigma_j^2 = ||z_j||^2, their descending order (ties by
+// index) in sm.order, the smallest r whose leading sigma_j^2 reach Et (all d
+// if rounding keeps the sum just below it) and the retained energy.
+__device__ void pick_rank(Shared& sm, int K, int d, double Et, int* r_out, double* cap_out,
+                          double* td_sig2) {
+  const int tid = threadIdx.x;
+  column_norms(sm, K, d);
+  __syncthreads();
+  if (tid < d) {
+    const double v = sm.s2[tid];
+    int rank = 0;
+    for (int k = 0; k < d; ++k) {
+      const double w = sm.s2[k];
+      rank += (w > v) || (w == v && k < tid);
+    }
+    sm.order[rank] = tid;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double cs = 0.0;
+    int rr = d;
+    for (int m = 0; m < d; ++m) {
+      cs += sm.s2[sm.order[m]];
+      if (cs >= Et) { rr = m + 1; break; }
+    }
+    sm.r = rr;
+    sm.cap = cs;
+  }
+  __syncthreads();
+  if (tid < d) td_sig2[tid] = sm.s2[sm.order[tid]];
+  *r_out = sm.r;
+  *cap_out = sm.cap;
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, int t, double eta,
                                                   int i_max, int* err) {
   __shared__ Shared sm;
@@ -263,6 +308,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
       td->info.dA_fro2 = E; td->info.captured = 0.0;
       if (E == 0.0) td->last_r = 0;
       td->dbg[0] = 0; td->dbg[1] = 0; td->dbg[2] = 0;
+      td->nsig = 0;
     }
     return;
   }
@@ -335,31 +381,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
       jacobi_svd(sm, K, d, &sweeps, &rounds);
       t_jac += clock64() - c_mark; c_mark = clock64();
       rotated = true;
-      column_norms(sm, K, d);
-      __syncthreads();
-      if (tid < d) {
-        const double v = sm.s2[tid];
-        int rank = 0;
-        for (int k = 0; k < d; ++k) {
-          const double w = sm.s2[k];
-          rank += (w > v) || (w == v && k < tid);
-        }
-        sm.order[rank] = tid;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        double cs = 0.0;
-        int rr = d;
-        for (int m = 0; m < d; ++m) {
-          cs += sm.s2[sm.order[m]];
-          if (cs >= Et) { rr = m + 1; break; }
-        }
-        sm.r = rr;
-        sm.cap = cs;
-      }
-      __syncthreads();
-      r = sm.r;
-      captured = sm.cap;
+      pick_rank(sm, K, d, Et, &r, &captured, td->sig2);
       break;
     }
     if (it == i_max) {
@@ -506,10 +528,10 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
       b0[i * KM + j] = td->Anew[e];
     }
     __syncthreads();
-    float2* res = gj_inverse_hpd<float2>(b0, b1, K, KM, &sm.bad);
+    gj_inverse_hpd_mfma(b0, K, KM, b1, b1 + 16 * KM, b1 + 32 * KM, &sm.bad);
     for (int e = tid; e < K * K; e += NTH) {
       const int i = e / K, j = e - i * K;
-      td->Ainv[e] = res[i * KM + j];
+      td->Ainv[e] = b0[i * KM + j];
     }
     if (tid == 0 && sm.bad) atomicCAS(err, 0, sm.bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
   }
@@ -518,6 +540,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
     td->info.dA_fro2 = E; td->info.captured = captured;
     td->last_r = r;
     td->dbg[0] = sweeps; td->dbg[1] = rounds; td->dbg[2] = qrcols;
+    td->nsig = rotated ? d : 0;
     t_wb = clock64() - c_mark;
     td->dbg[3] = (int)t_sk; td->dbg[4] = (int)t_qr; td->dbg[5] = (int)t_jac; td->dbg[6] = (int)t_wb;
     td->dbg[7] = (int)(wall_clock64() - r_begin);

@@ -146,3 +146,119 @@ __device__ T* gj_inverse_hpd(T* a, T* b, int K, int ld, int* bad) {
   }
   return a;
 }
+
+// Inverse of a Hermitian positive definite K x K matrix (K <= 64) by
+// Gauss-Jordan exchange steps on 16 x 16 pivot blocks, with the block
+// products on the FP32 matrix cores.  With P the pivot block and R the rest,
+// one step maps (same exchange as above)
+//   a_PP -> P^-1,  a_PR -> X = P^-1 a_PR,  a_RP -> -Y, Y = a_RP P^-1,
+//   a_RR -> a_RR - a_RP X.
+// P^-1 comes from scalar exchange steps by one wavefront (no pivoting: the
+// pivot block of an HPD matrix is HPD).  The matrix is padded to a multiple
+// of 16 with the identity, whose inverse leaves A^-1 in the leading block.
+// `a` (leading dimension ld >= 64) holds A on entry and A^-1 on return;
+// `xs` must hold 16*64 complex values, `ys` 64*16, `pb` 2*16*16.  All 1024
+// threads of the block call it.  *bad (LDS) becomes nonzero if a scalar pivot
+// is not a positive finite number (1: not HPD, 2: non-finite).
+__device__ void gj_inverse_hpd_mfma(float2* a, int K, int ld, float2* xs, float2* ys, float2* pb,
+                                    int* bad) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int KP = (K + 15) & ~15, nb = KP / 16;
+  for (int e = tid; e < KP * KP; e += blockDim.x) {
+    const int i = e / KP, j = e - i * KP;
+    if (i >= K || j >= K) a[i * ld + j] = (i == j) ? make_float2(1.f, 0.f) : cz();
+  }
+  __syncthreads();
+  for (int s = 0; s < nb; ++s) {
+    const int p0 = 16 * s;
+    if (wid == 0) {
+      // P^-1 by 16 scalar exchange steps; lane owns row r, columns c0..c0+3
+      const int r = lane >> 2, c0 = (lane & 3) * 4;
+      float2* x0 = pb;
+      float2* x1 = pb + 256;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x0[r * 16 + c0 + u] = a[(p0 + r) * ld + p0 + c0 + u];
+      bool ok = true, fin = true;
+      for (int q = 0; q < 16; ++q) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const float2 piv = x0[q * 16 + q];
+        fin = fin && isfinite(piv.x) && isfinite(piv.y);
+        ok = ok && piv.x > 0.f;
+        const float dn = __builtin_amdgcn_rcpf(piv.x * piv.x + piv.y * piv.y);
+        const float2 ip = make_float2(piv.x * dn, -piv.y * dn);
+        const float2 xrq = x0[r * 16 + q];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + u;
+          const float2 xqc = x0[q * 16 + c];
+          float2 v;
+          if (r == q && c == q) v = ip;
+          else if (r == q) v = cmul(xqc, ip);
+          else if (c == q) v = make_float2(-(xrq.x * ip.x - xrq.y * ip.y), -(xrq.x * ip.y + xrq.y * ip.x));
+          else v = csub(x0[r * 16 + c], cmul(cmul(xrq, ip), xqc));
+          x1[r * 16 + c] = v;
+        }
+        float2* t = x0; x0 = x1; x1 = t;
+      }
+      if (lane == 0) {
+        if (!fin) *bad = 2;
+        else if (!ok && *bad == 0) *bad = 1;
+      }
+      // after 16 (even) steps the result is back in pb[0..255]
+    }
+    __syncthreads();
+    const float2* pinv = pb;
+    // X = P^-1 a_P,:  (16 x KP, waves 0..nb-1) and Y = a_:,P P^-1 (KP x 16, waves 8..8+nb-1)
+    if (wid < nb) {
+      floatx4 dr = zero4(), di = zero4();
+      const int j0 = 16 * wid;
+      ctile16([&](int i, int k) { return pinv[i * 16 + k]; },
+              [&](int k, int j) { return a[(p0 + k) * ld + j0 + j]; }, 0, 16, dr, di);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xs[tile_row(v) * 64 + j0 + tile_col()] = make_float2(dr[v], di[v]);
+    } else if (wid >= 8 && wid < 8 + nb) {
+      floatx4 dr = zero4(), di = zero4();
+      const int i0 = 16 * (wid - 8);
+      ctile16([&](int i, int k) { return a[(i0 + i) * ld + p0 + k]; },
+              [&](int k, int j) { return pinv[k * 16 + j]; }, 0, 16, dr, di);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ys[(i0 + tile_row(v)) * 16 + tile_col()] = make_float2(dr[v], di[v]);
+    }
+    __syncthreads();
+    // every tile of the new matrix; values stay in registers until all reads are done
+    float2 nv[4];
+    const int ti = wid / 4, tj = wid % 4;
+    const bool mine = ti < nb && tj < nb;
+    if (mine) {
+      const int i0 = 16 * ti, j0 = 16 * tj;
+      if (ti == s && tj == s) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) nv[v] = pinv[tile_row(v) * 16 + tile_col()];
+      } else if (ti == s) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) nv[v] = xs[tile_row(v) * 64 + j0 + tile_col()];
+      } else if (tj == s) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float2 y = ys[(i0 + tile_row(v)) * 16 + tile_col()];
+          nv[v] = make_float2(-y.x, -y.y);
+        }
+      } else {
+        floatx4 dr = zero4(), di = zero4();
+        ctile16([&](int i, int k) { return a[(i0 + i) * ld + p0 + k]; },
+                [&](int k, int j) { return xs[k * 64 + j0 + j]; }, 0, 16, dr, di);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          nv[v] = csub(a[(i0 + tile_row(v)) * ld + j0 + tile_col()], make_float2(dr[v], di[v]));
+      }
+    }
+    __syncthreads();
+    if (mine) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[(16 * ti + tile_row(v)) * ld + 16 * tj + tile_col()] = nv[v];
+    }
+    __syncthreads();
+  }
+}

@@ -77,6 +77,21 @@ __device__ __forceinline__ float row16_sumf(float v) {
   v += dpp_f<DPP_ROW_ROR8>(v);
   return v;
 }
+__device__ __forceinline__ float row16_sum(float v) { return row16_sumf(v); }
+// Sum over each 8-lane half-row (quad permutations, then the half-row mirror).
+#define DPP_ROW_HALF_MIRROR 0x141
+__device__ __forceinline__ double row8_sum(double v) {
+  v += dpp_d<DPP_QUAD_1032>(v);
+  v += dpp_d<DPP_QUAD_2301>(v);
+  v += dpp_d<DPP_ROW_HALF_MIRROR>(v);
+  return v;
+}
+__device__ __forceinline__ float row8_sum(float v) {
+  v += dpp_f<DPP_QUAD_1032>(v);
+  v += dpp_f<DPP_QUAD_2301>(v);
+  v += dpp_f<DPP_ROW_HALF_MIRROR>(v);
+  return v;
+}
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, l);

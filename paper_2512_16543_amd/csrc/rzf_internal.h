@@ -36,6 +36,9 @@ struct TrackDesc {
   int pad_;
   DevInfo info;
   int dbg[8];      // last update: [0] Jacobi sweeps, [1] Jacobi rounds, [2] QR columns
+  int nsig;        // number of sigma^2 below (d of the last SVD, 0 if none)
+  int pad2_;
+  double sig2[KM]; // last SVD: sigma_j^2, descending
 };
 
 // Launchers (defined next to their kernels).
@@ -50,7 +53,9 @@ void launch_precoder(int K, int N, const float2* H, int ldh, const float2* X, fl
 void launch_scale(int K, int N, float2* W, int ldw, const double* wpart, int nparts, double P,
                   hipStream_t s);
 void launch_arsvd_wb(TrackDesc* td, int K, int t, double eta, int i_max, int* err, hipStream_t s);
+size_t sum_rate_scratch_doubles(int K);
 void launch_sum_rate(int K, int N, const float2* H, int ldh, const float2* W, int ldw, double P,
-                     double sigma2, float* rates, double* sum_out, int* err, hipStream_t s);
+                     double sigma2, float* rates, double* sum_out, double* part, int* err,
+                     hipStream_t s);
 void launch_debug_sketch(uint64_t seed, uint64_t track, int t, int it, int K, int d, float2* Omega,
                          uint64_t* words, hipStream_t s);

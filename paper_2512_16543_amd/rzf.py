@@ -76,6 +76,8 @@ _SIGS = {
     "rzf_get_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rzf_track_query": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 5),
     "rzf_track_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rzf_debug_sigma2": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]),
     "rzf_debug_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "rzf_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "rzf_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ProfileEntry), ctypes.c_int,
@@ -270,6 +272,12 @@ class Track:
         return {"jacobi_sweeps": arr[0], "jacobi_rounds": arr[1], "qr_columns": arr[2],
                 "cyc_sketch": arr[3], "cyc_qr": arr[4], "cyc_jacobi": arr[5], "cyc_wb": arr[6],
                 "realtime_ticks": arr[7]}
+
+    def sigma2(self):
+        arr = (ctypes.c_double * KMAX)()
+        d = ctypes.c_int()
+        _check(lib().rzf_debug_sigma2(self.h, arr, KMAX, ctypes.byref(d)), "rzf_debug_sigma2")
+        return [arr[i] for i in range(d.value)]
 
     def destroy(self):
         if self.h:
