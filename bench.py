@@ -43,6 +43,9 @@ def parse():
                     help="budget of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--batch-tracks", type=int, default=512,
+                    help="independent tracks of the same configuration in the batched pass (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -235,6 +238,11 @@ def main():
                        "work": unit_note}
     print(f"[bench] profiled pass done: dominant {dom}", file=sys.stderr, flush=True)
 
+    # batched pass: many independent tracks of the same configuration per launch
+    if a.batch_tracks > 0:
+        out["batched"] = batched(a, cfg, eta, policy)
+        print(f"[bench] batched pass done", file=sys.stderr, flush=True)
+
     # FP64 CPU oracle on a bounded sample of the same track
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, eta, Hs_np, a.cpu_seconds, policy)
@@ -242,6 +250,91 @@ def main():
     ctx.close()
     print(json.dumps(out), flush=True)
     return 0
+
+
+def batched(a, cfg, eta, policy):
+    """B independent tracks of the configuration (track ids 0..B-1), updated
+    together: B x S updates of WB-arSVD, then of the full-inversion baseline,
+    each step followed by the batched sum rate.  Snapshots are resident in HBM
+    before timing starts."""
+    import numpy as np
+    import torch
+    from paper_2512_16543_amd import rzf, workload as wl
+    B, S, Wu = a.batch_tracks, a.batch_steps, 2
+    K, N = cfg.K, cfg.N
+    dev = torch.device("cuda", 0)
+    T = Wu + S + 2          # snapshot 0 inits; 1..Wu warm up; S timed; the last one is profiled
+    Hs = torch.empty(B, T, K, N, dtype=torch.complex64, device=dev)
+    for b in range(B):
+        Hs[b] = torch.from_numpy(wl.make_track(cfg, b).snapshots(0, T).astype(np.complex64)).to(dev)
+    Ws = torch.empty(B, N, K, dtype=torch.complex64, device=dev)
+    rates = torch.empty(B, K, dtype=torch.float32, device=dev)
+    sums = torch.empty(B, dtype=torch.float64, device=dev)
+    per = rzf.track_bytes(K, N)
+    ctx = rzf.Context(0, B * per + (96 << 20))
+
+    def make_tracks():
+        return [ctx.init(Hs[b, 0], cfg.alpha,
+                         rzf.default_params(k_init=cfg.k_init, p=cfg.p, P=cfg.P, seed=cfg.seed,
+                                            track_id=b, reset_period=cfg.reset_period,
+                                            kinit_policy=policy))
+                for b in range(B)]
+
+    trs = make_tracks()
+    Wl = [Ws[b] for b in range(B)]
+    rl = [rates[b] for b in range(B)]
+    upd = [ctx.update_items(trs, [Hs[b, t] for b in range(B)], Wl) for t in range(T)]
+    full = [ctx.full_items([Hs[b, t] for b in range(B)], [cfg.alpha] * B, cfg.P, Wl) for t in range(T)]
+    rt = [ctx.rate_items([Hs[b, t] for b in range(B)], Wl, rl, sums) for t in range(T)]
+
+    def run(kind, t0, t1):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for t in range(t0, t1):
+            if kind == "wb":
+                ctx.update_batch_raw(upd[t], eta)
+            else:
+                ctx.full_batch_raw(full[t])
+            ctx.sum_rate_batch_raw(rt[t], cfg.P, cfg.sigma2)
+        ctx.sync()
+        torch.cuda.synchronize()
+        return time.perf_counter() - s0
+
+    run("wb", 1, 1 + Wu)
+    run("full", 1, 1 + Wu)
+    wb_s = run("wb", 1 + Wu, 1 + Wu + S)
+    full_s = run("full", 1 + Wu, 1 + Wu + S)
+    res = {"tracks": B, "steps": S, "value": B * S / wb_s, "unit": "updates/s",
+           "ms_per_batched_step": 1e3 * wb_s / S,
+           "full_inverse": {"value": B * S / full_s, "unit": "updates/s",
+                            "ms_per_batched_step": 1e3 * full_s / S},
+           "speedup_vs_full_inverse": full_s / wb_s}
+    # dominant kernel of the batched WB pass: HIP events over the next (fresh)
+    # snapshot of every track, with each track's info record for its work
+    ctx.profile(True)
+    infos = ctx.update_batch(trs, [Hs[b, T - 1] for b in range(B)], Wl, eta, want_info=True)
+    ctx.sum_rate_batch_raw(rt[T - 1], cfg.P, cfg.sigma2)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.sync()
+    res["kernels_wb"] = {k: {"launches": c, "avg_us": 1e3 * ms / c} for k, (c, ms) in prof.items()}
+    dom = max(prof, key=lambda k: prof[k][1])
+    dur = prof[dom][1] / prof[dom][0] * 1e-3
+    if dom == "arsvd_wb":
+        fl = sum(arsvd_flops(K, i.as_dict(), cfg.k_init, cfg.p) for i in infos if i.path != 4)
+    elif dom == "gram":
+        fl = B * 12.0 * K * K * N
+    elif dom == "precoder":
+        fl = B * 8.0 * K * K * N
+    else:
+        fl = 0.0
+    res["roofline"] = {"kernel": dom, "bound": "mfma", "achieved": fl / dur / 1e12,
+                       "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": fl / dur / 1e12 / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                       "flops_per_launch": fl, "avg_launch_us": dur * 1e6,
+                       "paths": {str(p): sum(1 for i in infos if i.path == p) for p in range(5)}}
+    ctx.close()
+    return res
 
 
 def cpu_baseline(cfg, eta, Hs_np, budget_s, policy):

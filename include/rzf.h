@@ -131,12 +131,46 @@ rzf_status rzf_init(rzf_ctx* ctx, int K, int N, const rzf_c32* H, int ldh, doubl
 rzf_status rzf_update(rzf_track* tr, const rzf_c32* H_t, int ldh, double tol,
                       rzf_c32* W, int ldw, rzf_update_info* info);
 
+/* One entry of a batched update. */
+typedef struct {
+  rzf_track* track;        /* track to update (each track at most once per batch) */
+  const rzf_c32* H;        /* device: next snapshot, K x N, leading dimension ldh  */
+  int ldh;
+  rzf_c32* W;              /* device: precoder output, N x K, leading dimension ldw */
+  int ldw;
+  rzf_update_info* info;   /* host: filled by the next rzf_sync, or NULL           */
+} rzf_update_item;
+
+#define RZF_BATCH_MAX 2048
+
+/* rzf_update for n independent tracks of this context in one set of launches
+ * (one workgroup per track and tile): the data-parallel form of Alg. 2 over
+ * many channel tracks.  Same semantics per track as rzf_update, same eta for
+ * all.  1 <= n <= RZF_BATCH_MAX; RZF_E_INVALID if a track is NULL, belongs to
+ * another context or appears twice. */
+rzf_status rzf_update_batch(rzf_ctx* ctx, int n, const rzf_update_item* items, double tol);
+
 /* Conventional RZF (the baseline of Sec. V): W = H^H (H H^H + alpha I)^-1,
  * full FP32 inversion, scaled to ||W||_F^2 = P.  Asynchronous; a
  * non-positive-definite Gram matrix is reported as RZF_E_NOT_HPD by the next
  * rzf_sync. */
 rzf_status rzf_full(rzf_ctx* ctx, int K, int N, const rzf_c32* H, int ldh, double alpha,
                     double P, rzf_c32* W, int ldw);
+
+/* One entry of a batched full-inversion RZF. */
+typedef struct {
+  int K, N;
+  const rzf_c32* H;        /* device, K x N, leading dimension ldh */
+  int ldh;
+  double alpha, P;
+  rzf_c32* W;              /* device, N x K, leading dimension ldw */
+  int ldw;
+} rzf_full_item;
+
+/* rzf_full for n independent snapshots in one set of launches.  Scratch for
+ * the Gram matrices comes from the arena (grown on demand, RZF_E_NOMEM if it
+ * cannot).  1 <= n <= RZF_BATCH_MAX. */
+rzf_status rzf_full_batch(rzf_ctx* ctx, int n, const rzf_full_item* items);
 
 /* Sum rate of eq. (15): W is first scaled to ||W||_F^2 = P, then E = H W,
  * SINR_n = |E_nn|^2 / (sum_{i != n} |E_ni|^2 + sigma2), rate_n = log2(1+SINR_n).
@@ -145,6 +179,22 @@ rzf_status rzf_full(rzf_ctx* ctx, int K, int N, const rzf_c32* H, int ldh, doubl
 rzf_status rzf_sum_rate(rzf_ctx* ctx, int K, int N, const rzf_c32* H, int ldh,
                         const rzf_c32* W, int ldw, double P, double sigma2,
                         float* rates, double* sum_rate);
+
+/* One entry of a batched sum-rate evaluation. */
+typedef struct {
+  int K, N;
+  const rzf_c32* H;        /* device, K x N, leading dimension ldh */
+  int ldh;
+  const rzf_c32* W;        /* device, N x K, leading dimension ldw */
+  int ldw;
+  float* rates;            /* device, K floats, or NULL            */
+  double* sum_rate;        /* device, one double, or NULL          */
+} rzf_rate_item;
+
+/* rzf_sum_rate for n independent (H, W) pairs, results left in device
+ * memory (asynchronous).  1 <= n <= RZF_BATCH_MAX. */
+rzf_status rzf_sum_rate_batch(rzf_ctx* ctx, int n, const rzf_rate_item* items, double P,
+                              double sigma2);
 
 /* Copy the track's stored inverse (K x K, row-major, ld = K) to device memory
  * Ainv.  Asynchronous. */

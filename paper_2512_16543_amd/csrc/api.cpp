@@ -3,6 +3,7 @@
 // rzf_full / rzf_sum_rate, and deferred info records.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -18,6 +19,8 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int PIN_CHUNK = 4096;   // info records per pinned chunk
+constexpr int NSTAGE = 4;
+constexpr size_t STAGE_BYTES = 1 << 20;   // per slot
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
@@ -60,6 +63,16 @@ struct rzf_ctx {
   std::vector<Pending> pending;
   std::set<rzf_track*> tracks;
   std::mutex mu;
+  // batched calls: ring of pinned host / device staging slots for job arrays
+  char* h_stage = nullptr;
+  char* d_stage = nullptr;
+  hipEvent_t stage_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool stage_used[4] = {false, false, false, false};
+  int stage_next = 0;
+  double* d_batch_part = nullptr;       // sum-rate scratch of batched calls
+  size_t batch_part_off = 0, batch_part_bytes = 0;
+  char* d_batch_full = nullptr;         // Gram / partial-norm scratch of rzf_full_batch
+  size_t batch_full_off = 0, batch_full_bytes = 0;
   // event timing
   bool prof_on = false;
   std::vector<ProfRec> prof;
@@ -86,7 +99,7 @@ namespace {
 size_t scratch_bytes() {
   return align_up(sizeof(int) * 64) + 2 * align_up(sizeof(float2) * KM * KM) +
          align_up(sizeof(double) * ((RZF_NMAX + 15) / 16)) + align_up(sizeof(double) * 8) +
-         align_up(sizeof(double) * sum_rate_scratch_doubles(KM));
+         align_up(sizeof(double) * sum_rate_scratch_doubles(KM)) + NSTAGE * STAGE_BYTES;
 }
 
 struct Layout {
@@ -289,7 +302,8 @@ rzf_status rzf_ctx_create(int device, void* hip_stream, void* arena, size_t aren
   c->d_fullAinv = reinterpret_cast<float2*>(p); p += align_up(sizeof(float2) * KM * KM);
   c->d_fullwpart = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * ((RZF_NMAX + 15) / 16));
   c->d_sum = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * 8);
-  c->d_srpart = reinterpret_cast<double*>(p);
+  c->d_srpart = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * sum_rate_scratch_doubles(KM));
+  c->d_stage = p;
   c->free_blocks[scr] = arena_bytes - scr;
   if (hipHostMalloc((void**)&c->h_sum, sizeof(double) * 8, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_err, sizeof(int) * 8, hipHostMallocDefault) != hipSuccess) {
@@ -298,7 +312,14 @@ rzf_status rzf_ctx_create(int device, void* hip_stream, void* arena, size_t aren
     return RZF_E_DEVICE;
   }
   *c->h_err = 0;
-  if (hipMemcpy(c->d_err, c->h_err, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+  bool stage_ok = hipHostMalloc((void**)&c->h_stage, NSTAGE * STAGE_BYTES, hipHostMallocDefault) == hipSuccess;
+  for (int k = 0; k < NSTAGE && stage_ok; ++k)
+    stage_ok = hipEventCreateWithFlags(&c->stage_ev[k], hipEventDisableTiming) == hipSuccess;
+  if (!stage_ok || hipMemcpy(c->d_err, c->h_err, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    for (int k = 0; k < NSTAGE; ++k) if (c->stage_ev[k]) (void)hipEventDestroy(c->stage_ev[k]);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    (void)hipHostFree(c->h_sum);
+    (void)hipHostFree(c->h_err);
     if (c->own_arena) (void)hipFree(c->arena);
     delete c;
     return RZF_E_DEVICE;
@@ -315,6 +336,8 @@ rzf_status rzf_ctx_destroy(rzf_ctx* c) {
   c->tracks.clear();
   prof_drain(c);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (int k = 0; k < NSTAGE; ++k) if (c->stage_ev[k]) (void)hipEventDestroy(c->stage_ev[k]);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
   for (DevInfo* p : c->pin_chunks) (void)hipHostFree(p);
   if (c->h_sum) (void)hipHostFree(c->h_sum);
   if (c->h_err) (void)hipHostFree(c->h_err);
@@ -370,8 +393,10 @@ rzf_status rzf_init(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   const float2* Hf = reinterpret_cast<const float2*>(H);
   bool ok = hipMemcpyAsync(t->d_desc, &d, sizeof(d), hipMemcpyHostToDevice, s) == hipSuccess;
   if (ok) {
-    launch_gram64(K, N, Hf, ldh, alpha, d.A64, s);
-    launch_inv64(K, d.A64, d.Ainv, c->d_err, nullptr, s);
+    const Gram64Job gj{Hf, d.A64, K, N, ldh, alpha};
+    launch_gram64(gj, nullptr, 1, K, s);
+    const Inv64Job ij{d.A64, d.Ainv, nullptr, nullptr, K};
+    launch_inv64(ij, nullptr, 1, c->d_err, s);
     ok = hipMemcpy2DAsync(d.Hprev, sizeof(float2) * N, Hf, sizeof(float2) * ldh,
                           sizeof(float2) * N, K, hipMemcpyDeviceToDevice, s) == hipSuccess;
     ok = ok && hipGetLastError() == hipSuccess;
@@ -408,14 +433,20 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
   const int step = t->t + 1;
   const bool reset = t->prm.reset_period > 0 && t->since_reset + 1 >= t->prm.reset_period;
   if (reset) {
-    timed(c, KN_GRAM64, [&] { launch_gram64(K, N, Hf, ldh, t->alpha, d.A64, s); });
-    timed(c, KN_INV64, [&] { launch_inv64(K, d.A64, d.Ainv, c->d_err, &t->d_desc->info, s); });
+    const Gram64Job gj{Hf, d.A64, K, N, ldh, t->alpha};
+    const Inv64Job ij{d.A64, d.Ainv, &t->d_desc->info, nullptr, K};
+    timed(c, KN_GRAM64, [&] { launch_gram64(gj, nullptr, 1, K, s); });
+    timed(c, KN_INV64, [&] { launch_inv64(ij, nullptr, 1, c->d_err, s); });
   } else {
-    timed(c, KN_GRAM, [&] { launch_gram(K, N, Hf, ldh, d.Hprev, N, d.Anew, d.dA, t->alpha, s); });
-    timed(c, KN_ARSVD, [&] { launch_arsvd_wb(t->d_desc, K, step, tol, t->i_max, c->d_err, s); });
+    const GramJob gj{Hf, d.Hprev, d.Anew, d.dA, K, N, ldh, N, (float)t->alpha};
+    const ArsvdJob aj{t->d_desc, nullptr, tol, step, t->i_max};
+    timed(c, KN_GRAM, [&] { launch_gram(gj, nullptr, 1, K, s); });
+    timed(c, KN_ARSVD, [&] { launch_arsvd_wb(aj, nullptr, 1, c->d_err, s); });
   }
-  timed(c, KN_PRECODER, [&] { launch_precoder(K, N, Hf, ldh, d.Ainv, Wf, ldw, d.wpart, d.Hprev, s); });
-  timed(c, KN_SCALE, [&] { launch_scale(K, N, Wf, ldw, d.wpart, precoder_blocks(N), d.P, s); });
+  const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw};
+  const ScaleJob sj{Wf, d.wpart, d.P, K, N, ldw, precoder_blocks(N)};
+  timed(c, KN_PRECODER, [&] { launch_precoder(pj, nullptr, 1, N, s); });
+  timed(c, KN_SCALE, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (slot) {
     HIP_OK(hipMemcpyAsync(slot, &t->d_desc->info, sizeof(DevInfo), hipMemcpyDeviceToHost, s));
@@ -425,6 +456,237 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
   t->since_reset = reset ? 0 : t->since_reset + 1;
   return RZF_OK;
 }
+
+
+}  // extern "C"
+
+namespace {
+
+// Reserve the next staging slot (waits until the launches that last used it
+// have consumed their job arrays).  Returns the slot index or -1.
+int stage_acquire(rzf_ctx* c) {
+  const int k = c->stage_next;
+  c->stage_next = (k + 1) % NSTAGE;
+  if (c->stage_used[k] && hipEventSynchronize(c->stage_ev[k]) != hipSuccess) return -1;
+  c->stage_used[k] = false;
+  return k;
+}
+
+struct Stager {
+  char* h;
+  char* d;
+  size_t used = 0;
+  template <class T>
+  T* put(const T* src, int n, T** dev) {
+    used = (used + 15) & ~size_t(15);
+    T* hp = reinterpret_cast<T*>(h + used);
+    *dev = reinterpret_cast<T*>(d + used);
+    std::memcpy(hp, src, sizeof(T) * n);
+    used += sizeof(T) * n;
+    return hp;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+rzf_status rzf_update_batch(rzf_ctx* c, int n, const rzf_update_item* items, double tol) {
+  if (!c || !items || n < 1 || n > RZF_BATCH_MAX) return RZF_E_INVALID;
+  if (!(tol > 0.0 && tol <= 1.0)) return RZF_E_INVALID;
+  std::set<rzf_track*> seen;
+  for (int i = 0; i < n; ++i) {
+    const rzf_update_item& it = items[i];
+    if (!it.track || !it.H || !it.W || it.track->ctx != c) return RZF_E_INVALID;
+    if (!seen.insert(it.track).second) return RZF_E_INVALID;
+    if (it.ldh < it.track->N || it.ldw < it.track->K) return RZF_E_SHAPE;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  std::vector<GramJob> gj;
+  std::vector<ArsvdJob> aj;
+  std::vector<Gram64Job> g64;
+  std::vector<Inv64Job> i64;
+  std::vector<PrecJob> pj;
+  std::vector<ScaleJob> sj;
+  std::vector<int> reset_flag(n);
+  int maxK = 1, maxN = 1, maxNK = 1, maxKr = 1;
+  for (int i = 0; i < n; ++i) {
+    rzf_track* t = items[i].track;
+    const TrackDesc& d = t->h_desc;
+    const int K = t->K, N = t->N;
+    const float2* Hf = reinterpret_cast<const float2*>(items[i].H);
+    float2* Wf = reinterpret_cast<float2*>(items[i].W);
+    const bool reset = t->prm.reset_period > 0 && t->since_reset + 1 >= t->prm.reset_period;
+    reset_flag[i] = reset;
+    if (reset) {
+      g64.push_back(Gram64Job{Hf, d.A64, K, N, items[i].ldh, t->alpha});
+      i64.push_back(Inv64Job{d.A64, d.Ainv, &t->d_desc->info, nullptr, K});
+      maxKr = std::max(maxKr, K);
+    } else {
+      gj.push_back(GramJob{Hf, d.Hprev, d.Anew, d.dA, K, N, items[i].ldh, N, (float)t->alpha});
+      aj.push_back(ArsvdJob{t->d_desc, nullptr, tol, t->t + 1, t->i_max});
+    }
+    pj.push_back(PrecJob{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, items[i].ldh, items[i].ldw});
+    sj.push_back(ScaleJob{Wf, d.wpart, d.P, K, N, items[i].ldw, precoder_blocks(N)});
+    maxK = std::max(maxK, K);
+    maxN = std::max(maxN, N);
+    maxNK = std::max(maxNK, N * K);
+  }
+  const size_t need = sizeof(GramJob) * gj.size() + sizeof(ArsvdJob) * aj.size() +
+                      sizeof(Gram64Job) * g64.size() + sizeof(Inv64Job) * i64.size() +
+                      sizeof(PrecJob) * pj.size() + sizeof(ScaleJob) * sj.size() + 16 * 8;
+  if (need > STAGE_BYTES) return RZF_E_INVALID;
+  const int slot = stage_acquire(c);
+  if (slot < 0) return RZF_E_DEVICE;
+  Stager st{c->h_stage + slot * STAGE_BYTES, c->d_stage + slot * STAGE_BYTES};
+  GramJob* d_gj = nullptr; ArsvdJob* d_aj = nullptr; Gram64Job* d_g64 = nullptr;
+  Inv64Job* d_i64 = nullptr; PrecJob* d_pj = nullptr; ScaleJob* d_sj = nullptr;
+  if (!gj.empty()) { st.put(gj.data(), (int)gj.size(), &d_gj); st.put(aj.data(), (int)aj.size(), &d_aj); }
+  if (!g64.empty()) { st.put(g64.data(), (int)g64.size(), &d_g64); st.put(i64.data(), (int)i64.size(), &d_i64); }
+  st.put(pj.data(), n, &d_pj);
+  st.put(sj.data(), n, &d_sj);
+  HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
+  if (!gj.empty()) {
+    timed(c, KN_GRAM, [&] { launch_gram(gj[0], d_gj, (int)gj.size(), maxK, s); });
+    timed(c, KN_ARSVD, [&] { launch_arsvd_wb(aj[0], d_aj, (int)aj.size(), c->d_err, s); });
+  }
+  if (!g64.empty()) {
+    timed(c, KN_GRAM64, [&] { launch_gram64(g64[0], d_g64, (int)g64.size(), maxKr, s); });
+    timed(c, KN_INV64, [&] { launch_inv64(i64[0], d_i64, (int)i64.size(), c->d_err, s); });
+  }
+  timed(c, KN_PRECODER, [&] { launch_precoder(pj[0], d_pj, n, maxN, s); });
+  timed(c, KN_SCALE, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
+  HIP_OK(hipEventRecord(c->stage_ev[slot], s));
+  c->stage_used[slot] = true;
+  if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
+  for (int i = 0; i < n; ++i) {
+    rzf_track* t = items[i].track;
+    if (items[i].info) {
+      DevInfo* slotp = pin_slot(c);
+      if (!slotp) return RZF_E_DEVICE;
+      HIP_OK(hipMemcpyAsync(slotp, &t->d_desc->info, sizeof(DevInfo), hipMemcpyDeviceToHost, s));
+      c->pending.push_back(Pending{slotp, items[i].info});
+    }
+    t->t += 1;
+    t->since_reset = reset_flag[i] ? 0 : t->since_reset + 1;
+  }
+  return RZF_OK;
+}
+
+rzf_status rzf_full_batch(rzf_ctx* c, int n, const rzf_full_item* items) {
+  if (!c || !items || n < 1 || n > RZF_BATCH_MAX) return RZF_E_INVALID;
+  int maxK = 1, maxN = 1, maxNK = 1;
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {
+    const rzf_full_item& it = items[i];
+    if (!it.H || !it.W) return RZF_E_INVALID;
+    if (it.K < 1 || it.K > RZF_KMAX || it.N < 1 || it.N > RZF_NMAX || it.ldh < it.N || it.ldw < it.K)
+      return RZF_E_SHAPE;
+    if (!std::isfinite(it.alpha) || it.alpha < 0.0 || !std::isfinite(it.P) || it.P <= 0.0)
+      return RZF_E_INVALID;
+    maxK = std::max(maxK, it.K);
+    maxN = std::max(maxN, it.N);
+    maxNK = std::max(maxNK, it.N * it.K);
+    need += align_up(sizeof(float2) * it.K * it.K) + align_up(sizeof(double) * precoder_blocks(it.N));
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  if (need > c->batch_full_bytes) {
+    // grow: the old region may still be read by queued work
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (c->d_batch_full) arena_free(c, c->batch_full_off, c->batch_full_bytes);
+    c->d_batch_full = nullptr;
+    c->batch_full_bytes = 0;
+    size_t off = 0;
+    if (!arena_alloc(c, need, &off)) return RZF_E_NOMEM;
+    c->batch_full_off = off;
+    c->batch_full_bytes = need;
+    c->d_batch_full = c->arena + off;
+  }
+  std::vector<GramJob> gj(n);
+  std::vector<Inv32Job> vj(n);
+  std::vector<PrecJob> pj(n);
+  std::vector<ScaleJob> sj(n);
+  char* p = c->d_batch_full;
+  for (int i = 0; i < n; ++i) {
+    const rzf_full_item& it = items[i];
+    float2* A = reinterpret_cast<float2*>(p); p += align_up(sizeof(float2) * it.K * it.K);
+    double* wp = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * precoder_blocks(it.N));
+    const float2* Hf = reinterpret_cast<const float2*>(it.H);
+    float2* Wf = reinterpret_cast<float2*>(it.W);
+    gj[i] = GramJob{Hf, nullptr, A, nullptr, it.K, it.N, it.ldh, 0, (float)it.alpha};
+    vj[i] = Inv32Job{A, A, it.K};
+    pj[i] = PrecJob{Hf, A, Wf, wp, nullptr, it.K, it.N, it.ldh, it.ldw};
+    sj[i] = ScaleJob{Wf, wp, it.P, it.K, it.N, it.ldw, precoder_blocks(it.N)};
+  }
+  const size_t bytes = (sizeof(GramJob) + sizeof(Inv32Job) + sizeof(PrecJob) + sizeof(ScaleJob)) * n + 64;
+  if (bytes > STAGE_BYTES) return RZF_E_INVALID;
+  const int slot = stage_acquire(c);
+  if (slot < 0) return RZF_E_DEVICE;
+  Stager st{c->h_stage + slot * STAGE_BYTES, c->d_stage + slot * STAGE_BYTES};
+  GramJob* d_gj = nullptr; Inv32Job* d_vj = nullptr; PrecJob* d_pj = nullptr; ScaleJob* d_sj = nullptr;
+  st.put(gj.data(), n, &d_gj);
+  st.put(vj.data(), n, &d_vj);
+  st.put(pj.data(), n, &d_pj);
+  st.put(sj.data(), n, &d_sj);
+  HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
+  timed(c, KN_GRAM, [&] { launch_gram(gj[0], d_gj, n, maxK, s); });
+  timed(c, KN_INV32, [&] { launch_inv32(vj[0], d_vj, n, c->d_err, s); });
+  timed(c, KN_PRECODER, [&] { launch_precoder(pj[0], d_pj, n, maxN, s); });
+  timed(c, KN_SCALE, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
+  HIP_OK(hipEventRecord(c->stage_ev[slot], s));
+  c->stage_used[slot] = true;
+  return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
+}
+
+rzf_status rzf_sum_rate_batch(rzf_ctx* c, int n, const rzf_rate_item* items, double P, double sigma2) {
+  if (!c || !items || n < 1 || n > RZF_BATCH_MAX) return RZF_E_INVALID;
+  if (!std::isfinite(P) || P <= 0.0 || !std::isfinite(sigma2) || sigma2 < 0.0) return RZF_E_INVALID;
+  int maxK = 1;
+  for (int i = 0; i < n; ++i) {
+    const rzf_rate_item& it = items[i];
+    if (!it.H || !it.W) return RZF_E_INVALID;
+    if (it.K < 1 || it.K > RZF_KMAX || it.N < 1 || it.N > RZF_NMAX || it.ldh < it.N || it.ldw < it.K)
+      return RZF_E_SHAPE;
+    maxK = std::max(maxK, it.K);
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  const size_t per = align_up(sizeof(double) * sum_rate_scratch_doubles(RZF_KMAX));
+  const size_t want = per * RZF_BATCH_MAX;
+  if (!c->d_batch_part) {
+    size_t off = 0;
+    if (!arena_alloc(c, want, &off)) return RZF_E_NOMEM;
+    c->batch_part_off = off;
+    c->batch_part_bytes = want;
+    c->d_batch_part = reinterpret_cast<double*>(c->arena + off);
+  }
+  std::vector<RateJob> rj(n);
+  for (int i = 0; i < n; ++i) {
+    const rzf_rate_item& it = items[i];
+    rj[i] = RateJob{reinterpret_cast<const float2*>(it.H), reinterpret_cast<const float2*>(it.W),
+                    reinterpret_cast<double*>(reinterpret_cast<char*>(c->d_batch_part) + per * i),
+                    it.rates, it.sum_rate, it.K, it.N, it.ldh, it.ldw, P, sigma2};
+  }
+  const int slot = stage_acquire(c);
+  if (slot < 0) return RZF_E_DEVICE;
+  Stager st{c->h_stage + slot * STAGE_BYTES, c->d_stage + slot * STAGE_BYTES};
+  RateJob* d_rj = nullptr;
+  st.put(rj.data(), n, &d_rj);
+  HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
+  timed(c, KN_SUMRATE, [&] { launch_sum_rate(rj[0], d_rj, n, maxK, c->d_err, s); });
+  HIP_OK(hipEventRecord(c->stage_ev[slot], s));
+  c->stage_used[slot] = true;
+  return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 rzf_status rzf_full(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double alpha, double P,
                     rzf_c32* W, int ldw) {
@@ -436,11 +698,14 @@ rzf_status rzf_full(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   hipStream_t s = c->stream;
   const float2* Hf = reinterpret_cast<const float2*>(H);
   float2* Wf = reinterpret_cast<float2*>(W);
-  timed(c, KN_GRAM, [&] { launch_gram(K, N, Hf, ldh, nullptr, 0, c->d_fullA, nullptr, alpha, s); });
-  timed(c, KN_INV32, [&] { launch_inv32(K, c->d_fullA, c->d_fullAinv, c->d_err, s); });
-  timed(c, KN_PRECODER,
-        [&] { launch_precoder(K, N, Hf, ldh, c->d_fullAinv, Wf, ldw, c->d_fullwpart, nullptr, s); });
-  timed(c, KN_SCALE, [&] { launch_scale(K, N, Wf, ldw, c->d_fullwpart, precoder_blocks(N), P, s); });
+  const GramJob gj{Hf, nullptr, c->d_fullA, nullptr, K, N, ldh, 0, (float)alpha};
+  const PrecJob pj{Hf, c->d_fullAinv, Wf, c->d_fullwpart, nullptr, K, N, ldh, ldw};
+  const ScaleJob sj{Wf, c->d_fullwpart, P, K, N, ldw, precoder_blocks(N)};
+  timed(c, KN_GRAM, [&] { launch_gram(gj, nullptr, 1, K, s); });
+  const Inv32Job vj{c->d_fullA, c->d_fullAinv, K};
+  timed(c, KN_INV32, [&] { launch_inv32(vj, nullptr, 1, c->d_err, s); });
+  timed(c, KN_PRECODER, [&] { launch_precoder(pj, nullptr, 1, N, s); });
+  timed(c, KN_SCALE, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
 }
 
@@ -452,11 +717,9 @@ rzf_status rzf_sum_rate(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, con
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
   hipStream_t s = c->stream;
-  timed(c, KN_SUMRATE, [&] {
-    launch_sum_rate(K, N, reinterpret_cast<const float2*>(H), ldh,
-                    reinterpret_cast<const float2*>(W), ldw, P, sigma2, rates, c->d_sum,
-                    c->d_srpart, c->d_err, s);
-  });
+  const RateJob rj{reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(W), c->d_srpart,
+                   rates, c->d_sum, K, N, ldh, ldw, P, sigma2};
+  timed(c, KN_SUMRATE, [&] { launch_sum_rate(rj, nullptr, 1, K, c->d_err, s); });
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (sum_rate) {
     HIP_OK(hipMemcpyAsync(c->h_sum, c->d_sum, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -283,9 +283,13 @@ __device__ void pick_rank(Shared& sm, int K, int d, double Et, int* r_out, doubl
   __syncthreads();
 }
 
-__global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, int t, double eta,
-                                                  int i_max, int* err) {
+template <bool MANY>
+__global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* many, int* err) {
   __shared__ Shared sm;
+  const ArsvdJob& jb = job_of<MANY>(one, many);
+  TrackDesc* __restrict__ td = jb.td;
+  const int t = jb.t, i_max = jb.i_max;
+  const double eta = jb.eta;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int K = td->K;
   float2* b0 = sm.b0;
@@ -306,6 +310,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
       if (!isfinite(E)) atomicCAS(err, 0, DEV_ERR_NONFINITE);
       td->info.r = 0; td->info.iters = 0; td->info.path = RZF_PATH_NOOP; td->info.d = 0;
       td->info.dA_fro2 = E; td->info.captured = 0.0;
+      if (jb.out) *jb.out = td->info;
       if (E == 0.0) td->last_r = 0;
       td->dbg[0] = 0; td->dbg[1] = 0; td->dbg[2] = 0;
       td->nsig = 0;
@@ -538,6 +543,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(TrackDesc* __restrict__ td, in
   if (tid == 0) {
     td->info.r = r; td->info.iters = iters; td->info.path = path; td->info.d = d;
     td->info.dA_fro2 = E; td->info.captured = captured;
+    if (jb.out) *jb.out = td->info;
     td->last_r = r;
     td->dbg[0] = sweeps; td->dbg[1] = rounds; td->dbg[2] = qrcols;
     td->nsig = rotated ? d : 0;
@@ -565,9 +571,9 @@ __global__ void k_debug_sketch(uint64_t seed, uint64_t track, int t, int it, int
 
 }  // namespace
 
-void launch_arsvd_wb(TrackDesc* td, int K, int t, double eta, int i_max, int* err, hipStream_t s) {
-  (void)K;
-  k_arsvd_wb<<<1, NTH, 0, s>>>(td, t, eta, i_max, err);
+void launch_arsvd_wb(const ArsvdJob& one, const ArsvdJob* many, int n, int* err, hipStream_t s) {
+  if (many) k_arsvd_wb<true><<<dim3(1, n), NTH, 0, s>>>(one, many, err);
+  else k_arsvd_wb<false><<<1, NTH, 0, s>>>(one, many, err);
 }
 
 void launch_debug_sketch(uint64_t seed, uint64_t track, int t, int it, int K, int d, float2* Omega,

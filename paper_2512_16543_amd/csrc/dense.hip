@@ -11,10 +11,14 @@
 
 namespace {
 
-__global__ __launch_bounds__(1024) void k_inv32(int K, const float2* __restrict__ A,
-                                                float2* __restrict__ Ainv, int* err) {
+template <bool MANY>
+__global__ __launch_bounds__(1024) void k_inv32(Inv32Job one, const Inv32Job* many, int* err) {
   __shared__ float2 b0[KM * KM], xs[16 * KM], ys[KM * 16], pb[2 * 256];
   __shared__ int bad;
+  const Inv32Job& jb = job_of<MANY>(one, many);
+  const int K = jb.K;
+  const float2* A = jb.A;
+  float2* Ainv = jb.Ainv;
   if (threadIdx.x == 0) bad = 0;
   for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
     const int i = e / K, j = e - i * K;
@@ -29,10 +33,15 @@ __global__ __launch_bounds__(1024) void k_inv32(int K, const float2* __restrict_
   if (threadIdx.x == 0 && bad) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
 }
 
-__global__ __launch_bounds__(1024) void k_inv64(int K, const double2* __restrict__ A,
-                                                float2* __restrict__ Ainv, int* err, DevInfo* info) {
+template <bool MANY>
+__global__ __launch_bounds__(1024) void k_inv64(Inv64Job one, const Inv64Job* many, int* err) {
   __shared__ double2 b0[KM * KM], b1[KM * KM];
   __shared__ int bad;
+  const Inv64Job& jb = job_of<MANY>(one, many);
+  const int K = jb.K;
+  const double2* __restrict__ A = jb.A;
+  float2* __restrict__ Ainv = jb.Ainv;
+  DevInfo* info = jb.info;
   if (threadIdx.x == 0) bad = 0;
   for (int e = threadIdx.x; e < K * K; e += blockDim.x) b0[e] = A[e];
   __syncthreads();
@@ -40,19 +49,22 @@ __global__ __launch_bounds__(1024) void k_inv64(int K, const double2* __restrict
   for (int e = threadIdx.x; e < K * K; e += blockDim.x) Ainv[e] = d2f(res[e]);
   if (threadIdx.x == 0) {
     if (bad) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
-    if (info) {
-      info->r = 0; info->iters = 0; info->path = RZF_PATH_RESET; info->d = 0;
-      info->dA_fro2 = 0.0; info->captured = 0.0;
-    }
+    DevInfo rec;
+    rec.r = 0; rec.iters = 0; rec.path = RZF_PATH_RESET; rec.d = 0;
+    rec.dA_fro2 = 0.0; rec.captured = 0.0;
+    if (info) *info = rec;
+    if (jb.out) *jb.out = rec;
   }
 }
 
 }  // namespace
 
-void launch_inv32(int K, const float2* A, float2* Ainv, int* err, hipStream_t s) {
-  k_inv32<<<1, 1024, 0, s>>>(K, A, Ainv, err);
+void launch_inv32(const Inv32Job& one, const Inv32Job* many, int n, int* err, hipStream_t s) {
+  if (many) k_inv32<true><<<dim3(1, n), 1024, 0, s>>>(one, many, err);
+  else k_inv32<false><<<1, 1024, 0, s>>>(one, many, err);
 }
 
-void launch_inv64(int K, const double2* A64, float2* Ainv, int* err, DevInfo* info, hipStream_t s) {
-  k_inv64<<<1, 1024, 0, s>>>(K, A64, Ainv, err, info);
+void launch_inv64(const Inv64Job& one, const Inv64Job* many, int n, int* err, hipStream_t s) {
+  if (many) k_inv64<true><<<dim3(1, n), 1024, 0, s>>>(one, many, err);
+  else k_inv64<false><<<1, 1024, 0, s>>>(one, many, err);
 }

@@ -25,14 +25,20 @@ __device__ __forceinline__ void mac_conj(float2 x, float2 y, floatx4& dr, floatx
   di = mfma4(-x.x, y.y, di);
 }
 
-template <bool DELTA>
-__global__ __launch_bounds__(256) void k_gram(int K, int N, const float2* __restrict__ Ht, int ldh,
-                                              const float2* __restrict__ Hp, int ldp,
-                                              float2* __restrict__ Anew, float2* __restrict__ dA,
-                                              float alpha) {
+template <bool DELTA, bool MANY>
+__global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) {
   __shared__ float red[4][16][64];
+  const GramJob& jb = job_of<MANY>(one, many);
+  const int K = jb.K, N = jb.N, ldh = jb.ldh, ldp = jb.ldp;
+  const float2* __restrict__ Ht = jb.Ht;
+  const float2* __restrict__ Hp = jb.Hp;
+  float2* __restrict__ Anew = jb.Anew;
+  float2* __restrict__ dA = jb.dA;
+  const float alpha = jb.alpha;
+  const int ktl = (K + 15) / 16;
   // lower-triangular tile index -> (bi, bj), bi >= bj
   const int tix = blockIdx.x;
+  if (tix >= ktl * (ktl + 1) / 2) return;
   int bi = (int)((sqrtf(8.0f * tix + 1.0f) - 1.0f) * 0.5f);
   while ((bi + 1) * (bi + 2) / 2 <= tix) ++bi;
   while (bi * (bi + 1) / 2 > tix) --bi;
@@ -98,8 +104,13 @@ __global__ __launch_bounds__(256) void k_gram(int K, int N, const float2* __rest
 }
 
 // FP64 Gram for the exact (re-)inversions: one thread per lower element.
-__global__ __launch_bounds__(256) void k_gram64(int K, int N, const float2* __restrict__ H, int ldh,
-                                                double alpha, double2* __restrict__ A) {
+template <bool MANY>
+__global__ __launch_bounds__(256) void k_gram64(Gram64Job one, const Gram64Job* many) {
+  const Gram64Job& jb = job_of<MANY>(one, many);
+  const int K = jb.K, N = jb.N, ldh = jb.ldh;
+  const float2* __restrict__ H = jb.H;
+  double2* __restrict__ A = jb.A;
+  const double alpha = jb.alpha;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int nl = K * (K + 1) / 2;
   if (e >= nl) return;
@@ -125,17 +136,22 @@ __global__ __launch_bounds__(256) void k_gram64(int K, int N, const float2* __re
 
 }  // namespace
 
-void launch_gram(int K, int N, const float2* Ht, int ldh, const float2* Hp, int ldp, float2* Anew,
-                 float2* dA, double alpha, hipStream_t s) {
-  const int kt = (K + 15) / 16;
-  const int tiles = kt * (kt + 1) / 2;
-  if (Hp)
-    k_gram<true><<<tiles, 256, 0, s>>>(K, N, Ht, ldh, Hp, ldp, Anew, dA, (float)alpha);
-  else
-    k_gram<false><<<tiles, 256, 0, s>>>(K, N, Ht, ldh, nullptr, 0, Anew, nullptr, (float)alpha);
+void launch_gram(const GramJob& one, const GramJob* many, int n, int maxK, hipStream_t s) {
+  const int kt = (maxK + 15) / 16;
+  const dim3 grid(kt * (kt + 1) / 2, many ? n : 1);
+  const bool delta = one.Hp != nullptr;   // a batch passes its mode in `one`
+  if (delta) {
+    if (many) k_gram<true, true><<<grid, 256, 0, s>>>(one, many);
+    else k_gram<true, false><<<grid, 256, 0, s>>>(one, many);
+  } else {
+    if (many) k_gram<false, true><<<grid, 256, 0, s>>>(one, many);
+    else k_gram<false, false><<<grid, 256, 0, s>>>(one, many);
+  }
 }
 
-void launch_gram64(int K, int N, const float2* H, int ldh, double alpha, double2* A64, hipStream_t s) {
-  const int nl = K * (K + 1) / 2;
-  k_gram64<<<(nl + 255) / 256, 256, 0, s>>>(K, N, H, ldh, alpha, A64);
+void launch_gram64(const Gram64Job& one, const Gram64Job* many, int n, int maxK, hipStream_t s) {
+  const int nl = maxK * (maxK + 1) / 2;
+  const dim3 grid((nl + 255) / 256, many ? n : 1);
+  if (many) k_gram64<true><<<grid, 256, 0, s>>>(one, many);
+  else k_gram64<false><<<grid, 256, 0, s>>>(one, many);
 }

@@ -12,14 +12,19 @@
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_precoder(int K, int N, const float2* __restrict__ H, int ldh,
-                                                  const float2* __restrict__ X,
-                                                  float2* __restrict__ W, int ldw,
-                                                  double* __restrict__ wpart,
-                                                  float2* __restrict__ Hcopy) {
+template <bool MANY>
+__global__ __launch_bounds__(256) void k_precoder(PrecJob one, const PrecJob* many) {
   __shared__ double red[4];
+  const PrecJob& jb = job_of<MANY>(one, many);
+  const int K = jb.K, N = jb.N, ldh = jb.ldh, ldw = jb.ldw;
+  const float2* __restrict__ H = jb.H;
+  const float2* __restrict__ X = jb.X;
+  float2* __restrict__ W = jb.W;
+  double* __restrict__ wpart = jb.wpart;
+  float2* __restrict__ Hcopy = jb.Hcopy;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int n0 = blockIdx.x * 16;
+  if (n0 >= N) return;
   double acc = 0.0;
   for (int kt = wid; kt * 16 < K; kt += 4) {
     const int k0 = kt * 16;
@@ -56,9 +61,14 @@ __global__ __launch_bounds__(256) void k_precoder(int K, int N, const float2* __
   if (threadIdx.x == 0) wpart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ __launch_bounds__(256) void k_scale(int K, int N, float2* __restrict__ W, int ldw,
-                                               const double* __restrict__ wpart, int nparts,
-                                               double P) {
+template <bool MANY>
+__global__ __launch_bounds__(256) void k_scale(ScaleJob one, const ScaleJob* many) {
+  const ScaleJob& jb = job_of<MANY>(one, many);
+  const int K = jb.K, N = jb.N, ldw = jb.ldw, nparts = jb.nparts;
+  float2* __restrict__ W = jb.W;
+  const double* __restrict__ wpart = jb.wpart;
+  const double P = jb.P;
+  if ((int)(blockIdx.x * blockDim.x) >= N * K) return;
   double tot = 0.0;
   for (int b = 0; b < nparts; ++b) tot += wpart[b];
   const float s = (tot > 0.0) ? (float)sqrt(P / tot) : 0.f;
@@ -73,13 +83,14 @@ __global__ __launch_bounds__(256) void k_scale(int K, int N, float2* __restrict_
 
 int precoder_blocks(int N) { return (N + 15) / 16; }
 
-void launch_precoder(int K, int N, const float2* H, int ldh, const float2* X, float2* W, int ldw,
-                     double* wpart, float2* Hcopy, hipStream_t s) {
-  k_precoder<<<precoder_blocks(N), 256, 0, s>>>(K, N, H, ldh, X, W, ldw, wpart, Hcopy);
+void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, hipStream_t s) {
+  const dim3 grid(precoder_blocks(maxN), many ? n : 1);
+  if (many) k_precoder<true><<<grid, 256, 0, s>>>(one, many);
+  else k_precoder<false><<<grid, 256, 0, s>>>(one, many);
 }
 
-void launch_scale(int K, int N, float2* W, int ldw, const double* wpart, int nparts, double P,
-                  hipStream_t s) {
-  const int n = N * K;
-  k_scale<<<(n + 255) / 256, 256, 0, s>>>(K, N, W, ldw, wpart, nparts, P);
+void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, hipStream_t s) {
+  const dim3 grid((maxNK + 255) / 256, many ? n : 1);
+  if (many) k_scale<true><<<grid, 256, 0, s>>>(one, many);
+  else k_scale<false><<<grid, 256, 0, s>>>(one, many);
 }

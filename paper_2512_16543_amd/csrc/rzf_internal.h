@@ -41,21 +41,66 @@ struct TrackDesc {
   double sig2[KM]; // last SVD: sigma_j^2, descending
 };
 
-// Launchers (defined next to their kernels).
-void launch_gram(int K, int N, const float2* Ht, int ldh, const float2* Hp, int ldp, float2* Anew,
-                 float2* dA, double alpha, hipStream_t s);
-void launch_gram64(int K, int N, const float2* H, int ldh, double alpha, double2* A64, hipStream_t s);
-void launch_inv64(int K, const double2* A64, float2* Ainv, int* err, DevInfo* info, hipStream_t s);
-void launch_inv32(int K, const float2* A, float2* Ainv, int* err, hipStream_t s);
+// Work descriptors.  Every kernel takes one descriptor by value (a single
+// call) or a device array of them indexed by blockIdx.y (a batch); blocks
+// beyond a descriptor's own grid extent return at once.  The two forms are
+// separate instantiations (template flag MANY), so profiles tell them apart.
+struct GramJob {
+  const float2* Ht; const float2* Hp; float2* Anew; float2* dA;
+  int K, N, ldh, ldp;
+  float alpha;
+};
+struct Gram64Job {
+  const float2* H; double2* A;
+  int K, N, ldh;
+  double alpha;
+};
+struct Inv64Job {
+  const double2* A; float2* Ainv; DevInfo* info; DevInfo* out;   // out: extra copy of info, or null
+  int K;
+};
+struct Inv32Job {
+  const float2* A; float2* Ainv;   // may alias: A is read into LDS first
+  int K;
+};
+struct ArsvdJob {
+  TrackDesc* td;
+  DevInfo* out;    // extra copy of the step's info (batched calls), or null
+  double eta;
+  int t, i_max;
+};
+struct PrecJob {
+  const float2* H; const float2* X; float2* W; double* wpart; float2* Hcopy;
+  int K, N, ldh, ldw;
+};
+struct ScaleJob {
+  float2* W; const double* wpart;
+  double P;
+  int K, N, ldw, nparts;
+};
+struct RateJob {
+  const float2* H; const float2* W; double* part; float* rates; double* sum;
+  int K, N, ldh, ldw;
+  double P, sigma2;
+};
+
+template <bool MANY, class J>
+__device__ __forceinline__ const J& job_of(const J& one, const J* many) {
+  if constexpr (MANY) return many[blockIdx.y]; else return one;
+}
+
+// Launchers (defined next to their kernels).  `many` == nullptr launches the
+// single job `one`; otherwise `n` jobs read from device memory, with the grid
+// sized by the largest job (`maxK`, `maxN`).
+void launch_gram(const GramJob& one, const GramJob* many, int n, int maxK, hipStream_t s);
+void launch_gram64(const Gram64Job& one, const Gram64Job* many, int n, int maxK, hipStream_t s);
+void launch_inv64(const Inv64Job& one, const Inv64Job* many, int n, int* err, hipStream_t s);
+void launch_inv32(const Inv32Job& one, const Inv32Job* many, int n, int* err, hipStream_t s);
 int precoder_blocks(int N);
-void launch_precoder(int K, int N, const float2* H, int ldh, const float2* X, float2* W, int ldw,
-                     double* wpart, float2* Hcopy, hipStream_t s);
-void launch_scale(int K, int N, float2* W, int ldw, const double* wpart, int nparts, double P,
-                  hipStream_t s);
-void launch_arsvd_wb(TrackDesc* td, int K, int t, double eta, int i_max, int* err, hipStream_t s);
+void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, hipStream_t s);
+void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, hipStream_t s);
+void launch_arsvd_wb(const ArsvdJob& one, const ArsvdJob* many, int n, int* err, hipStream_t s);
 size_t sum_rate_scratch_doubles(int K);
-void launch_sum_rate(int K, int N, const float2* H, int ldh, const float2* W, int ldw, double P,
-                     double sigma2, float* rates, double* sum_out, double* part, int* err,
-                     hipStream_t s);
+void launch_sum_rate(const RateJob& one, const RateJob* many, int n, int maxK, int* err, hipStream_t s);
 void launch_debug_sketch(uint64_t seed, uint64_t track, int t, int it, int K, int d, float2* Omega,
                          uint64_t* words, hipStream_t s);

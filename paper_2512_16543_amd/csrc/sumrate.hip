@@ -16,12 +16,17 @@
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_sr_tiles(int K, int N, const float2* __restrict__ H, int ldh,
-                                                  const float2* __restrict__ W, int ldw,
-                                                  double* __restrict__ part) {
+template <bool MANY>
+__global__ __launch_bounds__(256) void k_sr_tiles(RateJob one, const RateJob* many) {
   __shared__ float red[4][8][64];
   __shared__ double wred[4];
+  const RateJob& jb = job_of<MANY>(one, many);
+  const int K = jb.K, N = jb.N, ldh = jb.ldh, ldw = jb.ldw;
+  const float2* __restrict__ H = jb.H;
+  const float2* __restrict__ W = jb.W;
+  double* __restrict__ part = jb.part;
   const int kt = (K + 15) / 16;
+  if ((int)blockIdx.x >= kt * kt) return;
   const int ti = blockIdx.x / kt, tj = blockIdx.x - ti * kt;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int n0 = ti * 16, m0 = tj * 16;
@@ -78,9 +83,14 @@ __global__ __launch_bounds__(256) void k_sr_tiles(int K, int N, const float2* __
   if (ti == 0 && lane == 0) part[(size_t)K * kt * 2 + tj] = wred[0] + wred[1] + wred[2] + wred[3];
 }
 
-__global__ __launch_bounds__(64) void k_sr_final(int K, double P, double sigma2,
-                                                 const double* __restrict__ part, float* rates,
-                                                 double* sum_out, int* err) {
+template <bool MANY>
+__global__ __launch_bounds__(64) void k_sr_final(RateJob one, const RateJob* many, int* err) {
+  const RateJob& jb = job_of<MANY>(one, many);
+  const int K = jb.K;
+  const double P = jb.P, sigma2 = jb.sigma2;
+  const double* __restrict__ part = jb.part;
+  float* rates = jb.rates;
+  double* sum_out = jb.sum;
   const int kt = (K + 15) / 16;
   double wn = 0.0;
   for (int t = 0; t < kt; ++t) wn += part[(size_t)K * kt * 2 + t];
@@ -108,10 +118,13 @@ size_t sum_rate_scratch_doubles(int K) {
   return (size_t)K * kt * 2 + kt;
 }
 
-void launch_sum_rate(int K, int N, const float2* H, int ldh, const float2* W, int ldw, double P,
-                     double sigma2, float* rates, double* sum_out, double* part, int* err,
-                     hipStream_t s) {
-  const int kt = (K + 15) / 16;
-  k_sr_tiles<<<kt * kt, 256, 0, s>>>(K, N, H, ldh, W, ldw, part);
-  k_sr_final<<<1, 64, 0, s>>>(K, P, sigma2, part, rates, sum_out, err);
+void launch_sum_rate(const RateJob& one, const RateJob* many, int n, int maxK, int* err, hipStream_t s) {
+  const int kt = (maxK + 15) / 16;
+  if (many) {
+    k_sr_tiles<true><<<dim3(kt * kt, n), 256, 0, s>>>(one, many);
+    k_sr_final<true><<<dim3(1, n), 64, 0, s>>>(one, many, err);
+  } else {
+    k_sr_tiles<false><<<kt * kt, 256, 0, s>>>(one, many);
+    k_sr_final<false><<<1, 64, 0, s>>>(one, many, err);
+  }
 }

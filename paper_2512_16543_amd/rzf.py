@@ -42,6 +42,26 @@ class UpdateInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class UpdateItem(ctypes.Structure):
+    _fields_ = [("track", ctypes.c_void_p), ("H", ctypes.c_void_p), ("ldh", ctypes.c_int),
+                ("W", ctypes.c_void_p), ("ldw", ctypes.c_int), ("info", ctypes.POINTER(UpdateInfo))]
+
+
+class FullItem(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int), ("N", ctypes.c_int), ("H", ctypes.c_void_p), ("ldh", ctypes.c_int),
+                ("alpha", ctypes.c_double), ("P", ctypes.c_double), ("W", ctypes.c_void_p),
+                ("ldw", ctypes.c_int)]
+
+
+class RateItem(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int), ("N", ctypes.c_int), ("H", ctypes.c_void_p), ("ldh", ctypes.c_int),
+                ("W", ctypes.c_void_p), ("ldw", ctypes.c_int), ("rates", ctypes.c_void_p),
+                ("sum_rate", ctypes.c_void_p)]
+
+
+BATCH_MAX = 2048
+
+
 class ProfileEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("count", ctypes.c_int), ("total_ms", ctypes.c_double)]
 
@@ -74,6 +94,11 @@ _SIGS = {
                                     ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "rzf_get_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rzf_update_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(UpdateItem),
+                                        ctypes.c_double]),
+    "rzf_full_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(FullItem)]),
+    "rzf_sum_rate_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(RateItem),
+                                          ctypes.c_double, ctypes.c_double]),
     "rzf_track_query": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 5),
     "rzf_track_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "rzf_debug_sigma2": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
@@ -217,6 +242,98 @@ class Context:
         _check(lib().rzf_sum_rate(self.h, K, N, ctypes.c_void_p(hp), ldh, ctypes.c_void_p(wp), ldw,
                                   float(P), float(sigma2), ctypes.c_void_p(_dev_ptr(rates)), None),
                "rzf_sum_rate")
+
+    def update_batch(self, tracks, Hs, Ws, tol: float, want_info: bool = False):
+        """rzf_update_batch over parallel lists of Track, H_t and W tensors."""
+        n = len(tracks)
+        arr = (UpdateItem * n)()
+        infos = [UpdateInfo() for _ in range(n)] if want_info else None
+        for i in range(n):
+            hp, ldh = _mat_args(Hs[i])
+            wp, ldw = _mat_args(Ws[i])
+            it = arr[i]
+            it.track = tracks[i].h
+            it.H, it.ldh, it.W, it.ldw = hp, ldh, wp, ldw
+            if want_info:
+                it.info = ctypes.pointer(infos[i])
+        _check(lib().rzf_update_batch(self.h, n, arr, float(tol)), "rzf_update_batch")
+        if want_info:
+            self._infos.extend(infos)
+        return infos
+
+    @staticmethod
+    def update_items(tracks, Hs, Ws):
+        """Prebuilt rzf_update_item array for update_batch_raw."""
+        n = len(tracks)
+        arr = (UpdateItem * n)()
+        for i in range(n):
+            hp, ldh = _mat_args(Hs[i])
+            wp, ldw = _mat_args(Ws[i])
+            arr[i].track = tracks[i].h
+            arr[i].H, arr[i].ldh, arr[i].W, arr[i].ldw = hp, ldh, wp, ldw
+        return arr
+
+    def update_batch_raw(self, items, tol: float):
+        _check(lib().rzf_update_batch(self.h, len(items), items, float(tol)), "rzf_update_batch")
+
+    @staticmethod
+    def full_items(Hs, alphas, P, Ws):
+        n = len(Hs)
+        arr = (FullItem * n)()
+        for i in range(n):
+            hp, ldh = _mat_args(Hs[i])
+            wp, ldw = _mat_args(Ws[i])
+            K, N = Hs[i].shape
+            arr[i].K, arr[i].N, arr[i].H, arr[i].ldh = K, N, hp, ldh
+            arr[i].alpha, arr[i].P, arr[i].W, arr[i].ldw = float(alphas[i]), float(P), wp, ldw
+        return arr
+
+    def full_batch_raw(self, items):
+        _check(lib().rzf_full_batch(self.h, len(items), items), "rzf_full_batch")
+
+    @staticmethod
+    def rate_items(Hs, Ws, rates=None, sums=None):
+        n = len(Hs)
+        arr = (RateItem * n)()
+        for i in range(n):
+            hp, ldh = _mat_args(Hs[i])
+            wp, ldw = _mat_args(Ws[i])
+            K, N = Hs[i].shape
+            it = arr[i]
+            it.K, it.N, it.H, it.ldh, it.W, it.ldw = K, N, hp, ldh, wp, ldw
+            it.rates = _dev_ptr(rates[i]) if rates is not None else None
+            it.sum_rate = (_dev_ptr(sums) + 8 * i) if sums is not None else None
+        return arr
+
+    def sum_rate_batch_raw(self, items, P: float, sigma2: float):
+        _check(lib().rzf_sum_rate_batch(self.h, len(items), items, float(P), float(sigma2)),
+               "rzf_sum_rate_batch")
+
+    def full_batch(self, Hs, alphas, P: float, Ws):
+        n = len(Hs)
+        arr = (FullItem * n)()
+        for i in range(n):
+            hp, ldh = _mat_args(Hs[i])
+            wp, ldw = _mat_args(Ws[i])
+            K, N = Hs[i].shape
+            it = arr[i]
+            it.K, it.N, it.H, it.ldh = K, N, hp, ldh
+            it.alpha, it.P, it.W, it.ldw = float(alphas[i]), float(P), wp, ldw
+        _check(lib().rzf_full_batch(self.h, n, arr), "rzf_full_batch")
+
+    def sum_rate_batch(self, Hs, Ws, P: float, sigma2: float, rates=None, sums=None):
+        """rates: list of float32 device tensors (or None); sums: float64 device tensor of n."""
+        n = len(Hs)
+        arr = (RateItem * n)()
+        for i in range(n):
+            hp, ldh = _mat_args(Hs[i])
+            wp, ldw = _mat_args(Ws[i])
+            K, N = Hs[i].shape
+            it = arr[i]
+            it.K, it.N, it.H, it.ldh, it.W, it.ldw = K, N, hp, ldh, wp, ldw
+            it.rates = _dev_ptr(rates[i]) if rates is not None else None
+            it.sum_rate = (_dev_ptr(sums) + 8 * i) if sums is not None else None
+        _check(lib().rzf_sum_rate_batch(self.h, n, arr, float(P), float(sigma2)), "rzf_sum_rate_batch")
 
     def profile(self, enable: bool):
         _check(lib().rzf_profile(self.h, 1 if enable else 0), "rzf_profile")

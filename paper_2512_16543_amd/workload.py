@@ -108,31 +108,38 @@ class Track:
         self.mx = np.tile(m, cfg.nx)
         self.my = np.repeat(m, cfg.nx)
 
-    def snapshot(self, t: int) -> np.ndarray:
+    def _snap(self, t: np.ndarray) -> np.ndarray:
+        """H(t) for a vector of step indices t (shape T x K x N)."""
         cfg = self.cfg
-        K, N = cfg.K, cfg.N
-        xs = V_SAT * cfg.dt_s * (t - cfg.steps / 2.0)
-        dx = self.xk - xs
-        dy = self.yk
+        N = cfg.N
+        t = np.asarray(t, dtype=np.float64)
+        xs = V_SAT * cfg.dt_s * (t - cfg.steps / 2.0)                 # T
+        dx = self.xk[None, :] - xs[:, None]                            # T x K
+        dy = np.broadcast_to(self.yk[None, :], dx.shape)
         d = np.sqrt(dx * dx + dy * dy + cfg.height_m ** 2)
         u = dx / d
         v = dy / d
         beta = (cfg.height_m / d) ** 2
-        a = np.exp(1j * np.pi * (np.outer(u, self.mx) + np.outer(v, self.my))) / math.sqrt(N)
+        a = np.exp(1j * np.pi * (u[:, :, None] * self.mx[None, None, :]
+                                 + v[:, :, None] * self.my[None, None, :])) / math.sqrt(N)
         kr = 10.0 ** (cfg.kr_db / 10.0)
-        los = np.exp(1j * self.phase)[:, None] * a
-        nlos = self.g / math.sqrt(N)
-        h = np.sqrt(beta)[:, None] * (math.sqrt(kr / (kr + 1.0)) * los
-                                       + math.sqrt(1.0 / (kr + 1.0)) * nlos)
+        los = np.exp(1j * self.phase)[None, :, None] * a
+        nlos = self.g[None, :, :] / math.sqrt(N)
+        h = np.sqrt(beta)[:, :, None] * (math.sqrt(kr / (kr + 1.0)) * los
+                                          + math.sqrt(1.0 / (kr + 1.0)) * nlos)
         return h.astype(np.complex128)
+
+    def snapshot(self, t: int) -> np.ndarray:
+        return self._snap(np.array([t]))[0]
 
     def snapshots(self, t0: int = 0, count: Optional[int] = None) -> np.ndarray:
         """H(t) for t = t0 .. t0+count-1 (default: the whole pass, steps+1)."""
         if count is None:
             count = self.cfg.steps + 1 - t0
         out = np.empty((count, self.cfg.K, self.cfg.N), dtype=np.complex128)
-        for i in range(count):
-            out[i] = self.snapshot(t0 + i)
+        for c0 in range(0, count, 64):
+            c1 = min(count, c0 + 64)
+            out[c0:c1] = self._snap(np.arange(t0 + c0, t0 + c1))
         return out
 
 

@@ -1,0 +1,141 @@
+"""Batched calls: every track in a batch gives exactly what it gives alone.
+
+Tracks of different sizes (ragged K and N) and different drift-reset phases
+share one set of launches; each track's precoder and stored inverse must be
+bit-identical to the same track updated on its own, and the batch must match
+the FP64 oracle like single calls do.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle.rzf as orz
+from paper_2512_16543_amd import rzf, workload as wl
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(16, 64), (64, 256), (13, 37), (33, 100), (64, 1000), (1, 8), (40, 24)]
+
+
+def walk(K, N, steps, seed):
+    """A channel track whose per-step change is a small low-rank perturbation."""
+    H = [wl.random_channel(K, N, seed)]
+    for t in range(steps):
+        H.append(wl.perturbed_channel(H[-1], seed * 1000 + t, rank=2, scale=0.02))
+    return np.asarray(H, dtype=np.complex64)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = rzf.Context(0, 256 << 20)
+    yield c
+    c.close()
+
+
+def _tracks(ctx, tracks_H, periods):
+    out = []
+    for i, H in enumerate(tracks_H):
+        K = H.shape[1]
+        prm = rzf.default_params(seed=7, track_id=i, reset_period=periods[i])
+        out.append(ctx.init(torch.from_numpy(H[0]).cuda(), 0.2 + K / 20.0, prm))
+    return out
+
+
+def test_batch_equals_alone(ctx):
+    steps = 7
+    Hs = [walk(K, N, steps, 10 + i) for i, (K, N) in enumerate(SIZES)]
+    periods = [0, 3, 0, 5, 2, 0, 4]
+    dev = [torch.from_numpy(H).cuda() for H in Hs]
+    alone = _tracks(ctx, Hs, periods)
+    batch = _tracks(ctx, Hs, periods)
+    Wa = [torch.empty(H.shape[2], H.shape[1], dtype=torch.complex64, device="cuda") for H in Hs]
+    Wb = [torch.empty_like(w) for w in Wa]
+    paths = set()
+    for t in range(1, steps + 1):
+        infos_a = [tr.update(d[t], 0.95, w) for tr, d, w in zip(alone, dev, Wa)]
+        infos_b = ctx.update_batch(batch, [d[t] for d in dev], Wb, 0.95, want_info=True)
+        ctx.sync()
+        for i in range(len(SIZES)):
+            assert torch.equal(Wa[i], Wb[i]), (t, SIZES[i])
+            assert torch.equal(alone[i].inverse(), batch[i].inverse()), (t, SIZES[i])
+            assert infos_a[i].as_dict() == infos_b[i].as_dict(), (t, SIZES[i])
+        paths |= {i.path for i in infos_b}
+    assert rzf.PATH_RESET in paths and rzf.PATH_WB in paths
+    for tr in alone + batch:
+        tr.destroy()
+
+
+def test_batch_matches_oracle(ctx):
+    steps = 5
+    Hs = [walk(K, N, steps, 40 + i).astype(np.complex128) for i, (K, N) in enumerate(SIZES[:5])]
+    trs = _tracks(ctx, [H.astype(np.complex64) for H in Hs], [0] * 5)
+    ots = []
+    for i, H in enumerate(Hs):
+        K = H.shape[1]
+        ots.append(orz.OracleTrack(H[0], orz.TrackParams(alpha=0.2 + K / 20.0, seed=7, track_id=i)))
+    dev = [torch.from_numpy(H.astype(np.complex64)).cuda() for H in Hs]
+    Ws = [torch.empty(H.shape[2], H.shape[1], dtype=torch.complex64, device="cuda") for H in Hs]
+    for t in range(1, steps + 1):
+        for tr, ot in zip(trs, ots):
+            st = ot.export_state()
+            st["Ainv"] = tr.inverse().cpu().numpy().astype(np.complex128)
+            ot.import_state(st)
+        infos = ctx.update_batch(trs, [d[t] for d in dev], Ws, 0.95, want_info=True)
+        ctx.sync()
+        for i, (ot, H) in enumerate(zip(ots, Hs)):
+            Wo, io = ot.update(H[t], 0.95)
+            assert (infos[i].r, infos[i].iters, infos[i].path) == (io.r, io.iters, io.path)
+            Wg = Ws[i].cpu().numpy().astype(np.complex128)
+            assert np.linalg.norm(Wg - Wo) / np.linalg.norm(Wo) <= 1e-5
+    for tr in trs:
+        tr.destroy()
+
+
+def test_full_and_sum_rate_batch_equal_single(ctx):
+    Hs = [walk(K, N, 0, 70 + i)[0] for i, (K, N) in enumerate(SIZES)]
+    dev = [torch.from_numpy(H).cuda() for H in Hs]
+    alphas = [0.3 + H.shape[0] / 30.0 for H in Hs]
+    Ws = [torch.empty(H.shape[1], H.shape[0], dtype=torch.complex64, device="cuda") for H in Hs]
+    Wb = [torch.empty_like(w) for w in Ws]
+    for d, a, w in zip(dev, alphas, Ws):
+        ctx.full(d, a, 1.5, w)
+    ctx.full_batch(dev, alphas, 1.5, Wb)
+    ctx.sync()
+    for i in range(len(Hs)):
+        assert torch.equal(Ws[i], Wb[i]), SIZES[i]
+        Wo = orz.full_rzf(Hs[i].astype(np.complex128), alphas[i], 1.5)
+        assert np.linalg.norm(Wb[i].cpu().numpy() - Wo) / np.linalg.norm(Wo) <= 1e-5
+    rates_s = [torch.empty(H.shape[0], dtype=torch.float32, device="cuda") for H in Hs]
+    rates_b = [torch.empty_like(r) for r in rates_s]
+    sums_s = [ctx.sum_rate(d, w, 1.5, 0.1, r) for d, w, r in zip(dev, Ws, rates_s)]
+    sums_b = torch.empty(len(Hs), dtype=torch.float64, device="cuda")
+    ctx.sum_rate_batch(dev, Wb, 1.5, 0.1, rates_b, sums_b)
+    ctx.sync()
+    for i in range(len(Hs)):
+        assert torch.equal(rates_s[i], rates_b[i])
+        assert sums_b[i].item() == sums_s[i]
+
+
+def test_batch_rejects_bad_items(ctx):
+    H = walk(8, 16, 1, 99)
+    dev = torch.from_numpy(H).cuda()
+    trs = _tracks(ctx, [H, H], [0, 0])
+    W = [torch.empty(16, 8, dtype=torch.complex64, device="cuda") for _ in range(2)]
+    with pytest.raises(rzf.RzfError) as e:
+        ctx.update_batch([trs[0], trs[0]], [dev[1], dev[1]], W, 0.9)
+    assert e.value.status == rzf.RZF_E_INVALID
+    other = rzf.Context(0, 16 << 20)
+    tro = other.init(dev[0], 1.0, rzf.default_params())
+    with pytest.raises(rzf.RzfError) as e:
+        ctx.update_batch([trs[0], tro], [dev[1], dev[1]], W, 0.9)
+    assert e.value.status == rzf.RZF_E_INVALID
+    with pytest.raises(rzf.RzfError):
+        ctx.update_batch([trs[0]], [dev[1]], W[:1], 1.5)
+    assert rzf.lib().rzf_update_batch(ctx.h, 0, None, 0.9) == rzf.RZF_E_INVALID
+    # nothing was launched by the refused calls: the tracks are still at step 0
+    assert trs[0].query()["t"] == 0
+    tro.destroy()
+    other.close()
+    for tr in trs:
+        tr.destroy()
