@@ -1,9 +1,9 @@
-"""Operation-count model of Tables I-III (used to report the paper's savings).
+"""Operation-count model of Tables I-III, used to report the paper's savings.
 
-TEST INFRASTRUCTURE: part of the oracle package.  The paper counts only the
-inverse maintenance: a full inversion costs K^3, the WB-arSVD update
-K^2 + K^2 r + r^3 + r^2 K (Table III; Table I for WB alone, Table II for
-arSVD), with the arSVD iterations and the oversampling left out (Sec. IV-A).
+The paper counts only the inverse maintenance: a full inversion costs K^3,
+the WB-arSVD update K^2 + K^2 r + r^3 + r^2 K (Table III; Table I for WB
+alone, Table II for arSVD), with the arSVD iterations and the oversampling
+left out (Sec. IV-A).  This is a reporting model, not part of the computation.
 """
 
 
