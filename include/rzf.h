@@ -23,7 +23,10 @@
  *    requested with a host pointer are filled in by that rzf_sync.
  *  - Nothing throws across this boundary; errors are status codes.  A call
  *    that returns an error has launched nothing.
- *  - Supported sizes: 1 <= K <= RZF_KMAX, 1 <= N <= RZF_NMAX.
+ *  - Supported sizes: 1 <= K <= RZF_KMAX, 1 <= N <= RZF_NMAX.  Tracks with
+ *    K <= 64 run kernels whose working set sits in LDS; larger tracks run
+ *    blocked kernels on a per-track workspace in the arena (rzf_track_bytes
+ *    includes it).
  */
 #ifndef RZF_H
 #define RZF_H
@@ -35,7 +38,7 @@
 extern "C" {
 #endif
 
-#define RZF_KMAX 64
+#define RZF_KMAX 256
 #define RZF_NMAX 4096
 
 typedef struct { float re, im; } rzf_c32;
@@ -70,7 +73,9 @@ typedef struct {
   int p;                /* oversampling of Alg. 1 (Table IV: 1; workloads use 5)  */
   int i_max;            /* Alg. 1 iteration cap; 0 = smallest I with
                            k_init * 2^(I-1) + p >= K                               */
-  double switch_ratio;  /* Alg. 2: Woodbury when k_est <= switch_ratio * K (0.5)  */
+  double switch_ratio;  /* Alg. 2: Woodbury when k_est <= switch_ratio * K (0.5);
+                           ranks above K/2 always take the direct inversion
+                           (the Woodbury workspace holds K/2 columns)             */
   int reset_period;     /* re-invert A' in FP64 once this many steps have passed
                            since the last FP64 inversion (init or reset), skipping
                            Alg. 1 on that step; 0 = never                         */

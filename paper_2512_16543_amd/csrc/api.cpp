@@ -103,7 +103,7 @@ size_t scratch_bytes() {
 }
 
 struct Layout {
-  size_t desc, ainv, hprev, anew, da, a64, wpart, total;
+  size_t desc, ainv, hprev, anew, da, a64, wpart, ym, qm, zm, pm, aug, total;
 };
 
 Layout track_layout(int K, int N) {
@@ -116,6 +116,14 @@ Layout track_layout(int K, int N) {
   L.da = o; o += align_up(sizeof(float2) * K * K);
   L.a64 = o; o += align_up(sizeof(double2) * K * K);
   L.wpart = o; o += align_up(sizeof(double) * precoder_blocks(N));
+  if (K > KS) {
+    // working set of the large-track kernels
+    L.ym = o; o += align_up(sizeof(float2) * K * K);
+    L.qm = o; o += align_up(sizeof(float2) * K * K);
+    L.zm = o; o += align_up(sizeof(float2) * K * K);
+    L.pm = o; o += align_up(sizeof(float2) * K * (K / 2));
+    L.aug = o; o += align_up(sizeof(double2) * (K / 2) * (K / 2 + K));
+  }
   L.total = o;
   return L;
 }
@@ -205,6 +213,18 @@ rzf_status dev_status(int code) {
 }
 
 #define HIP_OK(x) do { if ((x) != hipSuccess) return RZF_E_DEVICE; } while (0)
+
+// Kernel families by track size: K <= KS keeps the working set in LDS, larger
+// tracks use the blocked kernels on a global workspace.
+void inv64_any(const Inv64Job& j, int* err, hipStream_t s) {
+  if (j.K > KS) launch_inv64_big(j, nullptr, 1, err, s); else launch_inv64(j, nullptr, 1, err, s);
+}
+void inv32_any(const Inv32Job& j, int* err, hipStream_t s) {
+  if (j.K > KS) launch_inv32_big(j, nullptr, 1, err, s); else launch_inv32(j, nullptr, 1, err, s);
+}
+void arsvd_any(const ArsvdJob& j, int K, int* err, hipStream_t s) {
+  if (K > KS) launch_arsvd_big(j, nullptr, 1, err, s); else launch_arsvd_wb(j, nullptr, 1, err, s);
+}
 
 bool params_valid(const rzf_params* p) {
   return p->k_init >= 1 && p->p >= 0 && p->i_max >= 0 && p->i_max <= 64 &&
@@ -387,6 +407,13 @@ rzf_status rzf_init(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   d.dA = reinterpret_cast<float2*>(base + L.da);
   d.A64 = reinterpret_cast<double2*>(base + L.a64);
   d.wpart = reinterpret_cast<double*>(base + L.wpart);
+  if (K > KS) {
+    d.Ym = reinterpret_cast<float2*>(base + L.ym);
+    d.Qm = reinterpret_cast<float2*>(base + L.qm);
+    d.Zm = reinterpret_cast<float2*>(base + L.zm);
+    d.Pm = reinterpret_cast<float2*>(base + L.pm);
+    d.Aug = reinterpret_cast<double2*>(base + L.aug);
+  }
   d.last_r = 0;
   t->d_desc = reinterpret_cast<TrackDesc*>(base + L.desc);
   hipStream_t s = c->stream;
@@ -396,7 +423,7 @@ rzf_status rzf_init(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
     const Gram64Job gj{Hf, d.A64, K, N, ldh, alpha};
     launch_gram64(gj, nullptr, 1, K, s);
     const Inv64Job ij{d.A64, d.Ainv, nullptr, nullptr, K};
-    launch_inv64(ij, nullptr, 1, c->d_err, s);
+    inv64_any(ij, c->d_err, s);
     ok = hipMemcpy2DAsync(d.Hprev, sizeof(float2) * N, Hf, sizeof(float2) * ldh,
                           sizeof(float2) * N, K, hipMemcpyDeviceToDevice, s) == hipSuccess;
     ok = ok && hipGetLastError() == hipSuccess;
@@ -436,12 +463,12 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
     const Gram64Job gj{Hf, d.A64, K, N, ldh, t->alpha};
     const Inv64Job ij{d.A64, d.Ainv, &t->d_desc->info, nullptr, K};
     timed(c, KN_GRAM64, [&] { launch_gram64(gj, nullptr, 1, K, s); });
-    timed(c, KN_INV64, [&] { launch_inv64(ij, nullptr, 1, c->d_err, s); });
+    timed(c, KN_INV64, [&] { inv64_any(ij, c->d_err, s); });
   } else {
     const GramJob gj{Hf, d.Hprev, d.Anew, d.dA, K, N, ldh, N, (float)t->alpha};
     const ArsvdJob aj{t->d_desc, nullptr, tol, step, t->i_max};
     timed(c, KN_GRAM, [&] { launch_gram(gj, nullptr, 1, K, s); });
-    timed(c, KN_ARSVD, [&] { launch_arsvd_wb(aj, nullptr, 1, c->d_err, s); });
+    timed(c, KN_ARSVD, [&] { arsvd_any(aj, K, c->d_err, s); });
   }
   const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw};
   const ScaleJob sj{Wf, d.wpart, d.P, K, N, ldw, precoder_blocks(N)};
@@ -505,9 +532,9 @@ rzf_status rzf_update_batch(rzf_ctx* c, int n, const rzf_update_item* items, dou
   HIP_OK(hipSetDevice(c->device));
   hipStream_t s = c->stream;
   std::vector<GramJob> gj;
-  std::vector<ArsvdJob> aj;
+  std::vector<ArsvdJob> aj, ajb;     // LDS kernels (K <= KS) / large tracks
   std::vector<Gram64Job> g64;
-  std::vector<Inv64Job> i64;
+  std::vector<Inv64Job> i64, i64b;
   std::vector<PrecJob> pj;
   std::vector<ScaleJob> sj;
   std::vector<int> reset_flag(n);
@@ -522,11 +549,11 @@ rzf_status rzf_update_batch(rzf_ctx* c, int n, const rzf_update_item* items, dou
     reset_flag[i] = reset;
     if (reset) {
       g64.push_back(Gram64Job{Hf, d.A64, K, N, items[i].ldh, t->alpha});
-      i64.push_back(Inv64Job{d.A64, d.Ainv, &t->d_desc->info, nullptr, K});
+      (K > KS ? i64b : i64).push_back(Inv64Job{d.A64, d.Ainv, &t->d_desc->info, nullptr, K});
       maxKr = std::max(maxKr, K);
     } else {
       gj.push_back(GramJob{Hf, d.Hprev, d.Anew, d.dA, K, N, items[i].ldh, N, (float)t->alpha});
-      aj.push_back(ArsvdJob{t->d_desc, nullptr, tol, t->t + 1, t->i_max});
+      (K > KS ? ajb : aj).push_back(ArsvdJob{t->d_desc, nullptr, tol, t->t + 1, t->i_max});
     }
     pj.push_back(PrecJob{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, items[i].ldh, items[i].ldw});
     sj.push_back(ScaleJob{Wf, d.wpart, d.P, K, N, items[i].ldw, precoder_blocks(N)});
@@ -534,27 +561,37 @@ rzf_status rzf_update_batch(rzf_ctx* c, int n, const rzf_update_item* items, dou
     maxN = std::max(maxN, N);
     maxNK = std::max(maxNK, N * K);
   }
-  const size_t need = sizeof(GramJob) * gj.size() + sizeof(ArsvdJob) * aj.size() +
-                      sizeof(Gram64Job) * g64.size() + sizeof(Inv64Job) * i64.size() +
+  const size_t need = sizeof(GramJob) * gj.size() + sizeof(ArsvdJob) * (aj.size() + ajb.size()) +
+                      sizeof(Gram64Job) * g64.size() + sizeof(Inv64Job) * (i64.size() + i64b.size()) +
                       sizeof(PrecJob) * pj.size() + sizeof(ScaleJob) * sj.size() + 16 * 8;
   if (need > STAGE_BYTES) return RZF_E_INVALID;
   const int slot = stage_acquire(c);
   if (slot < 0) return RZF_E_DEVICE;
   Stager st{c->h_stage + slot * STAGE_BYTES, c->d_stage + slot * STAGE_BYTES};
-  GramJob* d_gj = nullptr; ArsvdJob* d_aj = nullptr; Gram64Job* d_g64 = nullptr;
-  Inv64Job* d_i64 = nullptr; PrecJob* d_pj = nullptr; ScaleJob* d_sj = nullptr;
-  if (!gj.empty()) { st.put(gj.data(), (int)gj.size(), &d_gj); st.put(aj.data(), (int)aj.size(), &d_aj); }
-  if (!g64.empty()) { st.put(g64.data(), (int)g64.size(), &d_g64); st.put(i64.data(), (int)i64.size(), &d_i64); }
+  GramJob* d_gj = nullptr; ArsvdJob* d_aj = nullptr; ArsvdJob* d_ajb = nullptr; Gram64Job* d_g64 = nullptr;
+  Inv64Job* d_i64 = nullptr; Inv64Job* d_i64b = nullptr; PrecJob* d_pj = nullptr; ScaleJob* d_sj = nullptr;
+  if (!gj.empty()) st.put(gj.data(), (int)gj.size(), &d_gj);
+  if (!aj.empty()) st.put(aj.data(), (int)aj.size(), &d_aj);
+  if (!ajb.empty()) st.put(ajb.data(), (int)ajb.size(), &d_ajb);
+  if (!g64.empty()) st.put(g64.data(), (int)g64.size(), &d_g64);
+  if (!i64.empty()) st.put(i64.data(), (int)i64.size(), &d_i64);
+  if (!i64b.empty()) st.put(i64b.data(), (int)i64b.size(), &d_i64b);
   st.put(pj.data(), n, &d_pj);
   st.put(sj.data(), n, &d_sj);
   HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
   if (!gj.empty()) {
     timed(c, KN_GRAM, [&] { launch_gram(gj[0], d_gj, (int)gj.size(), maxK, s); });
-    timed(c, KN_ARSVD, [&] { launch_arsvd_wb(aj[0], d_aj, (int)aj.size(), c->d_err, s); });
+    timed(c, KN_ARSVD, [&] {
+      if (!aj.empty()) launch_arsvd_wb(aj[0], d_aj, (int)aj.size(), c->d_err, s);
+      if (!ajb.empty()) launch_arsvd_big(ajb[0], d_ajb, (int)ajb.size(), c->d_err, s);
+    });
   }
   if (!g64.empty()) {
     timed(c, KN_GRAM64, [&] { launch_gram64(g64[0], d_g64, (int)g64.size(), maxKr, s); });
-    timed(c, KN_INV64, [&] { launch_inv64(i64[0], d_i64, (int)i64.size(), c->d_err, s); });
+    timed(c, KN_INV64, [&] {
+      if (!i64.empty()) launch_inv64(i64[0], d_i64, (int)i64.size(), c->d_err, s);
+      if (!i64b.empty()) launch_inv64_big(i64b[0], d_i64b, (int)i64b.size(), c->d_err, s);
+    });
   }
   timed(c, KN_PRECODER, [&] { launch_precoder(pj[0], d_pj, n, maxN, s); });
   timed(c, KN_SCALE, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
@@ -607,7 +644,8 @@ rzf_status rzf_full_batch(rzf_ctx* c, int n, const rzf_full_item* items) {
     c->d_batch_full = c->arena + off;
   }
   std::vector<GramJob> gj(n);
-  std::vector<Inv32Job> vj(n);
+  std::vector<Inv32Job> vj, vjb;   // LDS kernel (K <= KS) / large
+  vj.reserve(n);
   std::vector<PrecJob> pj(n);
   std::vector<ScaleJob> sj(n);
   char* p = c->d_batch_full;
@@ -618,7 +656,7 @@ rzf_status rzf_full_batch(rzf_ctx* c, int n, const rzf_full_item* items) {
     const float2* Hf = reinterpret_cast<const float2*>(it.H);
     float2* Wf = reinterpret_cast<float2*>(it.W);
     gj[i] = GramJob{Hf, nullptr, A, nullptr, it.K, it.N, it.ldh, 0, (float)it.alpha};
-    vj[i] = Inv32Job{A, A, it.K};
+    (it.K > KS ? vjb : vj).push_back(Inv32Job{A, A, it.K});
     pj[i] = PrecJob{Hf, A, Wf, wp, nullptr, it.K, it.N, it.ldh, it.ldw};
     sj[i] = ScaleJob{Wf, wp, it.P, it.K, it.N, it.ldw, precoder_blocks(it.N)};
   }
@@ -627,14 +665,19 @@ rzf_status rzf_full_batch(rzf_ctx* c, int n, const rzf_full_item* items) {
   const int slot = stage_acquire(c);
   if (slot < 0) return RZF_E_DEVICE;
   Stager st{c->h_stage + slot * STAGE_BYTES, c->d_stage + slot * STAGE_BYTES};
-  GramJob* d_gj = nullptr; Inv32Job* d_vj = nullptr; PrecJob* d_pj = nullptr; ScaleJob* d_sj = nullptr;
+  GramJob* d_gj = nullptr; Inv32Job* d_vj = nullptr; Inv32Job* d_vjb = nullptr;
+  PrecJob* d_pj = nullptr; ScaleJob* d_sj = nullptr;
   st.put(gj.data(), n, &d_gj);
-  st.put(vj.data(), n, &d_vj);
+  if (!vj.empty()) st.put(vj.data(), (int)vj.size(), &d_vj);
+  if (!vjb.empty()) st.put(vjb.data(), (int)vjb.size(), &d_vjb);
   st.put(pj.data(), n, &d_pj);
   st.put(sj.data(), n, &d_sj);
   HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
   timed(c, KN_GRAM, [&] { launch_gram(gj[0], d_gj, n, maxK, s); });
-  timed(c, KN_INV32, [&] { launch_inv32(vj[0], d_vj, n, c->d_err, s); });
+  timed(c, KN_INV32, [&] {
+    if (!vj.empty()) launch_inv32(vj[0], d_vj, (int)vj.size(), c->d_err, s);
+    if (!vjb.empty()) launch_inv32_big(vjb[0], d_vjb, (int)vjb.size(), c->d_err, s);
+  });
   timed(c, KN_PRECODER, [&] { launch_precoder(pj[0], d_pj, n, maxN, s); });
   timed(c, KN_SCALE, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
   HIP_OK(hipEventRecord(c->stage_ev[slot], s));
@@ -703,7 +746,7 @@ rzf_status rzf_full(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   const ScaleJob sj{Wf, c->d_fullwpart, P, K, N, ldw, precoder_blocks(N)};
   timed(c, KN_GRAM, [&] { launch_gram(gj, nullptr, 1, K, s); });
   const Inv32Job vj{c->d_fullA, c->d_fullAinv, K};
-  timed(c, KN_INV32, [&] { launch_inv32(vj, nullptr, 1, c->d_err, s); });
+  timed(c, KN_INV32, [&] { inv32_any(vj, c->d_err, s); });
   timed(c, KN_PRECODER, [&] { launch_precoder(pj, nullptr, 1, N, s); });
   timed(c, KN_SCALE, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;

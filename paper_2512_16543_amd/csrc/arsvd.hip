@@ -42,27 +42,18 @@ constexpr double SING_TOL = 1e-12;
 
 
 struct Shared {
-  float2 b0[KM * KM];            // Delta A (row-major, ld KM); later A^-1 or A'
-  float2 b1[KM * KM];            // column-major K x d: Omega, then Q
-  float2 b2[KM * KM];            // column-major K x d: Y / reflectors, then Z
-  float2 pm[KM * WB_RMAX];       // P = A^-1 U, column-major
-  double s2[KM];                 // ||z_j||^2
+  float2 b0[KS * KS];            // Delta A (row-major, ld KS); later A^-1 or A'
+  float2 b1[KS * KS];            // column-major K x d: Omega, then Q
+  float2 b2[KS * KS];            // column-major K x d: Y / reflectors, then Z
+  float2 pm[KS * WB_RMAX];       // P = A^-1 U, column-major
+  double s2[KS];                 // ||z_j||^2
   double2 fcol[WB_RMAX];         // Gauss-Jordan: multipliers of column j
-  double2 ustash[WB_RMAX + KM];  // Gauss-Jordan: normalised pivot row
+  double2 ustash[WB_RMAX + KS];  // Gauss-Jordan: normalised pivot row
   double red[NWV];
-  int order[KM];
+  int order[KS];
   int nrot, r, found, piv_row, singular, bad;
   double pivr, pivi, cap;
 };
-
-// Column pair (p, q) of round k, slot m, of the round-robin ordering over n
-// (even) columns: every pair meets once in n-1 rounds.
-__device__ __forceinline__ void rr_pair(int k, int m, int n, int* p, int* q) {
-  if (m == 0) { *p = k; *q = n - 1; return; }
-  const int n1 = n - 1;
-  *p = (k + m) % n1;
-  *q = (k - m + n1) % n1;
-}
 
 // Householder vector of column c (rows >= c) of the column-major matrix `a`
 // from the column's values x held one row per lane; writes the unit vector
@@ -94,15 +85,15 @@ __device__ void reflector_from(float2 x, float2* a, int c, int K) {
       w = make_float2(x.x * m, x.y * m);
     }
   }
-  if (lane < K) a[c * KM + lane] = (lane >= c) ? w : cz();
+  if (lane < K) a[c * KS + lane] = (lane >= c) ? w : cz();
 }
 
 // y <- (I - 2 w w^H) y for column c of `a` and reflector column wc of `wsrc`.
 // Returns the updated column value of the calling lane.
 __device__ __forceinline__ float2 apply_reflector(const float2* wsrc, int wc, float2* a, int c, int K) {
   const int lane = threadIdx.x & 63;
-  const float2 w = (lane < K) ? wsrc[wc * KM + lane] : cz();
-  float2 y = (lane < K) ? a[c * KM + lane] : cz();
+  const float2 w = (lane < K) ? wsrc[wc * KS + lane] : cz();
+  float2 y = (lane < K) ? a[c * KS + lane] : cz();
   float dr = w.x * y.x + w.y * y.y;     // conj(w) y
   float di = w.x * y.y - w.y * y.x;
   dr = wave_sumf(dr);
@@ -110,7 +101,7 @@ __device__ __forceinline__ float2 apply_reflector(const float2* wsrc, int wc, fl
   const float fr = 2.f * dr, fi = 2.f * di;
   y.x -= w.x * fr - w.y * fi;
   y.y -= w.x * fi + w.y * fr;
-  if (lane < K) a[c * KM + lane] = y;
+  if (lane < K) a[c * KS + lane] = y;
   return y;
 }
 
@@ -168,10 +159,10 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
         for (int m = 0; m < 4; ++m) {
           const int i = li + 16 * m;
           const bool ok = act && i < K;
-          zp[m] = ok ? b2[pp * KM + i] : cz();
-          zq[m] = ok ? b2[qq * KM + i] : cz();
-          qa[m] = ok ? b1[pp * KM + i] : cz();    // loaded early to overlap latency
-          qb[m] = ok ? b1[qq * KM + i] : cz();
+          zp[m] = ok ? b2[pp * KS + i] : cz();
+          zq[m] = ok ? b2[qq * KS + i] : cz();
+          qa[m] = ok ? b1[pp * KS + i] : cz();    // loaded early to overlap latency
+          qb[m] = ok ? b1[qq * KS + i] : cz();
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -214,10 +205,10 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
             const int i = li + 16 * m;
             if (i >= K) continue;
             const float2 zq2 = cmul(e, zq[m]), qv2 = cmul(e, qb[m]);
-            b2[pp * KM + i] = csub(cscale(zp[m], c), cscale(zq2, s));
-            b2[qq * KM + i] = cadd(cscale(zp[m], s), cscale(zq2, c));
-            b1[pp * KM + i] = csub(cscale(qa[m], c), cscale(qv2, s));
-            b1[qq * KM + i] = cadd(cscale(qa[m], s), cscale(qv2, c));
+            b2[pp * KS + i] = csub(cscale(zp[m], c), cscale(zq2, s));
+            b2[qq * KS + i] = cadd(cscale(zp[m], s), cscale(zq2, c));
+            b1[pp * KS + i] = csub(cscale(qa[m], c), cscale(qv2, s));
+            b1[qq * KS + i] = cadd(cscale(qa[m], s), cscale(qv2, c));
           }
           if (li == 0) sm.nrot = 1;
         }
@@ -241,7 +232,7 @@ __device__ void column_norms(Shared& sm, int K, int d) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int i = li + 16 * m;
-      if (i < K) v += (double)cabs2(sm.b2[slot * KM + i]);
+      if (i < K) v += (double)cabs2(sm.b2[slot * KS + i]);
     }
   }
   v = row16_sum(v);
@@ -301,7 +292,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   for (int e = tid; e < K * K; e += NTH) {
     const int i = e / K, j = e - i * K;
     const float2 v = td->dA[e];
-    b0[i * KM + j] = v;
+    b0[i * KS + j] = v;
     part += (double)v.x * v.x + (double)v.y * v.y;
   }
   const double E = block_sum(part, sm.red);
@@ -335,14 +326,14 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     // Omega -> b1 (column-major)
     for (int e = tid; e < K * d; e += NTH) {
       const int j = e / K, i = e - j * K;
-      b1[j * KM + i] = sketch_entry(seed, trk, t, it, i, j);
+      b1[j * KS + i] = sketch_entry(seed, trk, t, it, i, j);
     }
     __syncthreads();
     // Y = Delta A Omega -> b2
     lds_gemm(K, d, K,
-             [&](int i, int k) { return (i < K && k < K) ? b0[i * KM + k] : cz(); },
-             [&](int k, int j) { return (k < K && j < d) ? b1[j * KM + k] : cz(); },
-             [&](int i, int j, float2 v) { b2[j * KM + i] = v; });
+             [&](int i, int k) { return (i < K && k < K) ? b0[i * KS + k] : cz(); },
+             [&](int k, int j) { return (k < K && j < d) ? b1[j * KS + k] : cz(); },
+             [&](int i, int j, float2 v) { b2[j * KS + i] = v; });
     __syncthreads();
     t_sk += clock64() - c_mark; c_mark = clock64();
     // Householder QR of Y (b2): reflector j lands in column j of b2.  Wave 0
@@ -358,8 +349,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     }
     qrcols += d;
     // Q = H_0 ... H_{d-1} [I_d; 0] -> b1
-    for (int e = tid; e < d * KM; e += NTH) {
-      const int j = e / KM, i = e - j * KM;
+    for (int e = tid; e < d * KS; e += NTH) {
+      const int j = e / KS, i = e - j * KS;
       b1[e] = (i == j) ? make_float2(1.f, 0.f) : cz();
     }
     for (int j = d - 1; j >= 0; --j) {
@@ -369,15 +360,15 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     __syncthreads();
     // Z = Delta A Q -> b2
     lds_gemm(K, d, K,
-             [&](int i, int k) { return (i < K && k < K) ? b0[i * KM + k] : cz(); },
-             [&](int k, int j) { return (k < K && j < d) ? b1[j * KM + k] : cz(); },
-             [&](int i, int j, float2 v) { b2[j * KM + i] = v; });
+             [&](int i, int k) { return (i < K && k < K) ? b0[i * KS + k] : cz(); },
+             [&](int k, int j) { return (k < K && j < d) ? b1[j * KS + k] : cz(); },
+             [&](int i, int j, float2 v) { b2[j * KS + i] = v; });
     __syncthreads();
     // ||B||_F^2 = ||Z||_F^2: does any r reach the target?
     double zp = 0.0;
     for (int e = tid; e < K * d; e += NTH) {
       const int j = e / K, i = e - j * K;
-      zp += (double)cabs2(b2[j * KM + i]);
+      zp += (double)cabs2(b2[j * KS + i]);
     }
     const double tot = block_sum(zp, sm.red);
     t_qr += clock64() - c_mark; c_mark = clock64();
@@ -409,16 +400,16 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     // A^-1 -> b0
     for (int e = tid; e < K * K; e += NTH) {
       const int i = e / K, j = e - i * K;
-      b0[i * KM + j] = td->Ainv[e];
+      b0[i * KS + j] = td->Ainv[e];
     }
     __syncthreads();
     const int* ord = sm.order;
     float2* pm = sm.pm;
     // step 1: P = A^-1 U
     lds_gemm(K, r, K,
-             [&](int i, int k) { return (i < K && k < K) ? b0[i * KM + k] : cz(); },
-             [&](int k, int c) { return (k < K && c < r) ? b1[ord[c] * KM + k] : cz(); },
-             [&](int i, int c, float2 v) { pm[c * KM + i] = v; });
+             [&](int i, int k) { return (i < K && k < K) ? b0[i * KS + k] : cz(); },
+             [&](int k, int c) { return (k < K && c < r) ? b1[ord[c] * KS + k] : cz(); },
+             [&](int i, int c, float2 v) { pm[c * KS + i] = v; });
     __syncthreads();
     // step 2: C = I + V~^H P (r x r), and V~^H A^-1 (r x K); tiles held in
     // registers until every wave has finished reading U and V~
@@ -433,15 +424,15 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       my_ti = u / ncol; my_tj = u - my_ti * ncol; my_kind = ct ? 0 : 1;
       auto la = [&](int rr, int k) {
         const int a = my_ti * 16 + rr;
-        return (a < r && k < K) ? cconj(b2[ord[a] * KM + k]) : cz();
+        return (a < r && k < K) ? cconj(b2[ord[a] * KS + k]) : cz();
       };
       auto lbc = [&](int k, int cc) {
         const int b = my_tj * 16 + cc;
-        return (k < K && b < r) ? pm[b * KM + k] : cz();
+        return (k < K && b < r) ? pm[b * KS + k] : cz();
       };
       auto lbq = [&](int k, int cc) {
         const int j = my_tj * 16 + cc;
-        return (k < K && j < K) ? b0[k * KM + j] : cz();
+        return (k < K && j < K) ? b0[k * KS + j] : cz();
       };
       if (ct) ctile16(la, lbc, 0, K, dr, di); else ctile16(la, lbq, 0, K, dr, di);
     }
@@ -519,9 +510,9 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       // steps 4-5: A^-1 <- A^-1 - P X
       float2* out = td->Ainv;
       lds_gemm(K, K, r,
-               [&](int i, int a) { return (i < K && a < r) ? pm[a * KM + i] : cz(); },
+               [&](int i, int a) { return (i < K && a < r) ? pm[a * KS + i] : cz(); },
                [&](int a, int j) { return (a < r && j < K) ? d2f(aug[a * ldg + r + j]) : cz(); },
-               [&](int i, int j, float2 v) { out[(size_t)i * K + j] = csub(b0[i * KM + j], v); });
+               [&](int i, int j, float2 v) { out[(size_t)i * K + j] = csub(b0[i * KS + j], v); });
     }
     __syncthreads();
   }
@@ -530,13 +521,13 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     if (tid == 0) sm.bad = 0;
     for (int e = tid; e < K * K; e += NTH) {
       const int i = e / K, j = e - i * K;
-      b0[i * KM + j] = td->Anew[e];
+      b0[i * KS + j] = td->Anew[e];
     }
     __syncthreads();
-    gj_inverse_hpd_mfma(b0, K, KM, b1, b1 + 16 * KM, b1 + 32 * KM, &sm.bad);
+    gj_inverse_hpd_mfma(b0, K, KS, b1, b1 + 16 * KS, b1 + 32 * KS, &sm.bad);
     for (int e = tid; e < K * K; e += NTH) {
       const int i = e / K, j = e - i * K;
-      td->Ainv[e] = b0[i * KM + j];
+      td->Ainv[e] = b0[i * KS + j];
     }
     if (tid == 0 && sm.bad) atomicCAS(err, 0, sm.bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
   }

@@ -1,0 +1,880 @@
+// Alg. 1 + Alg. 2 for the large tracks (64 < K <= 256), and their direct
+// inverses.
+//
+// Same computation and the same order as k_arsvd_wb (arsvd.hip): per
+// iteration Omega -> Y = Delta A Omega -> Q = orth(Y) (Householder) ->
+// Z = Delta A Q, the ||Z||_F^2 test of eq. (14), on success a one-sided
+// Jacobi SVD of B = Z^H with Q rotated alongside, the rank rule, then the
+// Woodbury update of eq. (12) in the scaled form (U = Q columns, V~ = Z
+// columns) or direct inversion of A'.
+//
+// What changes with K: the K x d factors no longer fit in LDS, so each track
+// keeps them in its own global workspace (column-major Y, Q, Z; row-major
+// FP64 capacitance system), which stays resident in L2 while the single
+// workgroup of the track works on it, and the algorithms are blocked so that
+// every pass streams a matrix once:
+//   * Householder QR in 16-column panels: the panel is factored in LDS, its
+//     compact WY form H_0..H_15 = I - V T V^H is applied to the trailing
+//     columns with three 16-wide products on the matrix cores, and Q is
+//     formed by the same blocks in reverse order;
+//   * one-sided block Jacobi: the d columns are cut into blocks of b; a job
+//     loads two blocks of Z and of Q into LDS, sweeps their 2b columns until
+//     they are mutually orthogonal, and writes them back; the blocks meet in
+//     the round-robin order until a full pass rotates nothing (d <= 2b is a
+//     single job, i.e. plain one-sided Jacobi);
+//   * Gauss-Jordan with partial pivoting on [C | V~^H A^-1] in 32-column
+//     panels: the panel is eliminated in LDS, recording its pivots and
+//     multipliers, then every other column replays them;
+//   * 16 x 16 block Gauss-Jordan for the HPD inverses (gj_inverse_hpd_blocked).
+#include "dense_device.h"
+#include "rzf_internal.h"
+
+namespace {
+
+constexpr int NTH = 1024;
+constexpr int NWV = NTH / 64;
+constexpr int MAX_SWEEPS = 30;      // Jacobi passes (single job: sweeps)
+constexpr int MAX_INNER = 8;        // sweeps of one job of a multi-block pass
+constexpr double JACOBI_TOL = 2e-6;
+constexpr double SING_TOL = 1e-12;
+constexpr int JOB_ELEMS = KM * 32;  // LDS entries of one job matrix
+constexpr int GJ_W = 32;            // panel width of the capacitance solve
+constexpr int RB = KM / 2;          // largest Woodbury rank of a large track
+
+struct BigShared {
+  union {
+    struct {
+      float2 pan[KM * 16];            // panel (column-major, ld K)
+      float2 tf[(KM / 16) * 256];     // T of every panel (row-major 16 x 16)
+      float2 ws[NWV * 256];           // per-wave 16 x 16 scratch
+    } qr;
+    struct {
+      float2 z[JOB_ELEMS];            // job columns of Z (column-major, ld K)
+      float2 q[JOB_ELEMS];            // job columns of Q
+    } jac;
+    struct {
+      double2 pan[RB * GJ_W];         // capacitance panel (row-major, ld GJ_W)
+      double2 ustash[GJ_W];
+    } gj;
+    struct {
+      float2 xs[16 * KM];
+      float2 cs[KM * 16];
+      float2 pb[2 * 256];
+    } inv;
+    float2 om[KM * 16];               // one 16-column tile of Omega
+  } u;
+  double s2[KM];
+  double red[NWV];
+  double2 pivv[GJ_W];
+  int order[KM];
+  int pivrow[GJ_W];
+  int nrot, r, singular, bad;
+  double cap;
+};
+
+__device__ __forceinline__ int up4(int k) { return (k + 3) & ~3; }
+
+// ---------------------------------------------------------------- QR
+// Householder vector of panel column c from the column values x[m] (row
+// lane + 64 m), pivot row pr: H = I - 2 w w^H maps x to beta e_pr.  Written
+// over panel column c, zero above pr.  Wave-level, all lanes active.
+__device__ __forceinline__ void reflector_big(const float2 x[4], float2* pan, int c, int pr, int K) {
+  const int lane = threadIdx.x & 63;
+  float sp = 0.f;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int i = lane + 64 * m;
+    if (i < K && i >= pr) sp += cabs2(x[m]);
+  }
+  const float s = wave_sumf(sp);
+  const int ms = pr >> 6, ls = pr & 63;
+  float2 xp = x[0];
+#pragma unroll
+  for (int m = 1; m < 4; ++m) if (m == ms) xp = x[m];
+  const float ax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xp.x), ls));
+  const float ay = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xp.y), ls));
+  float2 w[4] = {cz(), cz(), cz(), cz()};
+  if (s >= 1e-36f) {
+    const float inx = __builtin_amdgcn_rsqf(s);
+    const float bx = ax * inx, by = ay * inx;
+    const float aa = __builtin_amdgcn_sqrtf(bx * bx + by * by);
+    float ph_r = 1.f, ph_i = 0.f;
+    if (aa > 0.f) { const float ia = __builtin_amdgcn_rcpf(aa); ph_r = bx * ia; ph_i = by * ia; }
+    const float iw = __builtin_amdgcn_rsqf(2.f * (1.f + aa));
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = lane + 64 * m;
+      if (i == pr) {
+        const float mm = (aa + 1.f) * iw;
+        w[m] = make_float2(ph_r * mm, ph_i * mm);
+      } else if (i > pr) {
+        const float mm = inx * iw;
+        w[m] = make_float2(x[m].x * mm, x[m].y * mm);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int i = lane + 64 * m;
+    if (i < K) pan[c * K + i] = w[m];
+  }
+}
+
+// Column c of the panel <- (I - 2 w w^H) column c, w = panel column wc.
+__device__ __forceinline__ void apply_reflector_big(float2* pan, int wc, int c, int K, float2 y[4]) {
+  const int lane = threadIdx.x & 63;
+  float2 w[4];
+  float dr = 0.f, di = 0.f;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int i = lane + 64 * m;
+    w[m] = (i < K) ? pan[wc * K + i] : cz();
+    y[m] = (i < K) ? pan[c * K + i] : cz();
+    dr += w[m].x * y[m].x + w[m].y * y[m].y;
+    di += w[m].x * y[m].y - w[m].y * y[m].x;
+  }
+  dr = wave_sumf(dr);
+  di = wave_sumf(di);
+  const float fr = 2.f * dr, fi = 2.f * di;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int i = lane + 64 * m;
+    y[m].x -= w[m].x * fr - w[m].y * fi;
+    y[m].y -= w[m].x * fi + w[m].y * fr;
+    if (i < K) pan[c * K + i] = y[m];
+  }
+}
+
+// Block of 16 reflectors (panel V, factor T) applied to the 16 columns
+// cc0..cc0+15 (< d) of the column-major K x d matrix M, rows >= r0:
+//   M <- M - V op(T) (V^H M),  op(T) = T^H when `adj`, else T.
+__device__ __forceinline__ void apply_block(const float2* pan, const float2* T, float2* ws, float2* M, int K, int d,
+                            int r0, int cc0, bool adj) {
+  floatx4 dr = zero4(), di = zero4();
+  ctile16([&](int i, int k) { return (k < K) ? cconj(pan[i * K + k]) : cz(); },
+          [&](int k, int j) {
+            const int c = cc0 + j;
+            return (k < K && c < d) ? M[(size_t)c * K + k] : cz();
+          },
+          r0 & ~3, up4(K), dr, di);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) ws[tile_row(v) * 16 + tile_col()] = make_float2(dr[v], di[v]);
+  wave_sync();
+  dr = zero4(); di = zero4();
+  if (adj)
+    ctile16([&](int i, int k) { return cconj(T[k * 16 + i]); }, [&](int k, int j) { return ws[k * 16 + j]; },
+            0, 16, dr, di);
+  else
+    ctile16([&](int i, int k) { return T[i * 16 + k]; }, [&](int k, int j) { return ws[k * 16 + j]; },
+            0, 16, dr, di);
+  wave_sync();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) ws[tile_row(v) * 16 + tile_col()] = make_float2(dr[v], di[v]);
+  wave_sync();
+  for (int rc = r0 >> 4; rc * 16 < K; ++rc) {
+    floatx4 er = zero4(), ei = zero4();
+    ctile16([&](int i, int k) {
+              const int row = rc * 16 + i;
+              return (row < K) ? pan[k * K + row] : cz();
+            },
+            [&](int k, int j) { return ws[k * 16 + j]; }, 0, 16, er, ei);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = rc * 16 + tile_row(v), c = cc0 + tile_col();
+      if (row < K && c < d) {
+        float2* p = M + (size_t)c * K + row;
+        *p = csub(*p, make_float2(er[v], ei[v]));
+      }
+    }
+  }
+  wave_sync();
+}
+
+// Householder QR of Y (K x d, in Ym) by 16-column panels: the reflectors
+// replace Y, the T factors stay in LDS, and Q = H_0 ... H_{d-1} [I_d; 0] is
+// formed in Qm.
+__device__ __forceinline__ void qr_big(BigShared& sm, float2* Ym, float2* Qm, int K, int d) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  float2* pan = sm.u.qr.pan;
+  float2* ws = sm.u.qr.ws + wid * 256;
+  const int np = (d + 15) / 16;
+  for (int p = 0; p < np; ++p) {
+    const int c0 = 16 * p, nc = min(16, d - c0);
+    float2* T = sm.u.qr.tf + p * 256;
+    for (int e = tid; e < 16 * K; e += NTH) {
+      const int c = e / K, i = e - c * K;
+      pan[e] = (c < nc) ? Ym[(size_t)(c0 + c) * K + i] : cz();
+    }
+    __syncthreads();
+    if (wid == 0) {
+      float2 x[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int i = lane + 64 * m;
+        x[m] = (i < K) ? pan[i] : cz();
+      }
+      reflector_big(x, pan, 0, c0, K);
+    }
+    for (int j = 0; j < nc; ++j) {
+      __syncthreads();
+      for (int c = j + 1 + wid; c < nc; c += NWV) {
+        float2 y[4];
+        apply_reflector_big(pan, j, c, K, y);
+        if (c == j + 1) reflector_big(y, pan, c, c0 + c, K);
+      }
+    }
+    __syncthreads();
+    if (wid == 0) {
+      // S = V^H V, then T (upper triangular) of H_0 ... H_15 = I - V T V^H:
+      // T_jj = 2, T[0:j, j] = -2 T[0:j, 0:j] S[0:j, j]
+      floatx4 dr = zero4(), di = zero4();
+      ctile16([&](int i, int k) { return (k < K) ? cconj(pan[i * K + k]) : cz(); },
+              [&](int k, int j) { return (k < K) ? pan[j * K + k] : cz(); }, c0, up4(K), dr, di);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ws[tile_row(v) * 16 + tile_col()] = make_float2(dr[v], di[v]);
+      for (int e = lane; e < 256; e += 64) T[e] = cz();
+      wave_sync();
+      for (int j = 0; j < 16; ++j) {
+        if (lane < 16) {
+          const int i = lane;
+          float2 val = cz();
+          if (j < nc) {
+            if (i == j) {
+              val = make_float2(2.f, 0.f);
+            } else if (i < j) {
+              float2 acc = cz();
+              for (int k = i; k < j; ++k) acc = cadd(acc, cmul(T[i * 16 + k], ws[k * 16 + j]));
+              val = make_float2(-2.f * acc.x, -2.f * acc.y);
+            }
+          }
+          T[i * 16 + j] = val;
+        }
+      }
+      wave_sync();
+    }
+    for (int e = tid; e < nc * K; e += NTH) {
+      const int c = e / K, i = e - c * K;
+      Ym[(size_t)(c0 + c) * K + i] = pan[e];
+    }
+    __syncthreads();
+    // trailing columns: C <- (I - V T^H V^H) C
+    const int cs0 = c0 + 16;
+    const int nt = (d > cs0) ? (d - cs0 + 15) / 16 : 0;
+    for (int t = wid; t < nt; t += NWV) apply_block(pan, T, ws, Ym, K, d, c0, cs0 + 16 * t, true);
+    __syncthreads();
+  }
+  for (int e = tid; e < K * d; e += NTH) {
+    const int j = e / K, i = e - j * K;
+    Qm[e] = (i == j) ? make_float2(1.f, 0.f) : cz();
+  }
+  __syncthreads();
+  for (int p = np - 1; p >= 0; --p) {
+    const int c0 = 16 * p, nc = min(16, d - c0);
+    for (int e = tid; e < 16 * K; e += NTH) {
+      const int c = e / K, i = e - c * K;
+      pan[e] = (c < nc) ? Ym[(size_t)(c0 + c) * K + i] : cz();
+    }
+    __syncthreads();
+    const int nt = (d - c0 + 15) / 16;
+    for (int t = wid; t < nt; t += NWV)
+      apply_block(pan, sm.u.qr.tf + p * 256, ws, Qm, K, d, c0, c0 + 16 * t, false);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ Jacobi
+template <int G>
+__device__ __forceinline__ float gsumf(float v) {
+  if constexpr (G == 64) return wave_sumf(v);
+  v = row16_sumf(v);
+  return v + __shfl_xor(v, 16);
+}
+template <int G>
+__device__ __forceinline__ double gsumd(double v) {
+  if constexpr (G == 64) return wave_sum(v);
+  v = row16_sum(v);
+  return v + __shfl_xor(v, 16);
+}
+
+// One-sided Jacobi on the nc job columns held in LDS (Z in sm.u.jac.z, Q in
+// sm.u.jac.q, column c at c*K).  A group of G lanes owns one column pair per
+// round (rows gl + G m, m < 4).  Sweeps until a sweep rotates nothing or
+// max_sweeps.  Returns whether the first sweep rotated anything.
+template <int G>
+__device__ __forceinline__ bool jacobi_job(BigShared& sm, int K, int nc, int max_sweeps, int* sweeps, int* rounds) {
+  float2* zb = sm.u.jac.z;
+  float2* qb = sm.u.jac.q;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int gl = lane & (G - 1), slot = threadIdx.x / G;
+  const int n = nc + (nc & 1);
+  const int wave_slots = 64 / G;
+  bool first = false;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) sm.nrot = 0;
+    __syncthreads();
+    ++*sweeps;
+    for (int k = 0; k < n - 1; ++k) {
+      ++*rounds;
+      if (wid * wave_slots < n / 2) {
+        int pp = 0, qq = 0;
+        bool act = slot < n / 2;
+        if (act) {
+          rr_pair(k, slot, n, &pp, &qq);
+          act = pp < nc && qq < nc;
+        }
+        float2 zp[4], zq[4], qa[4], qv[4];
+        float al = 0.f, be = 0.f;
+        double gr = 0.0, gi = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int i = gl + G * m;
+          const bool ok = act && i < K;
+          zp[m] = ok ? zb[pp * K + i] : cz();
+          zq[m] = ok ? zb[qq * K + i] : cz();
+          qa[m] = ok ? qb[pp * K + i] : cz();
+          qv[m] = ok ? qb[qq * K + i] : cz();
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          al += cabs2(zp[m]);
+          be += cabs2(zq[m]);
+          gr += (double)zp[m].x * zq[m].x + (double)zp[m].y * zq[m].y;
+          gi += (double)zp[m].x * zq[m].y - (double)zp[m].y * zq[m].x;
+        }
+        al = gsumf<G>(al);
+        be = gsumf<G>(be);
+        gr = gsumd<G>(gr);
+        gi = gsumd<G>(gi);
+        const float mx = fmaxf(al, be);
+        bool rot = act && mx > 0.f;
+        float c = 1.f, s = 0.f;
+        float2 e = make_float2(1.f, 0.f);
+        if (rot) {
+          // same rotation as the LDS kernel: sums scaled by 1/max(alpha, beta)
+          const float sc = __builtin_amdgcn_rcpf(mx);
+          const float alf = al * sc, bef = be * sc;
+          const float grf = (float)gr * sc, gif = (float)gi * sc;
+          const float gg = grf * grf + gif * gif;
+          rot = gg >= 1e-36f && gg > (float)(JACOBI_TOL * JACOBI_TOL) * alf * bef;
+          const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));
+          const float zeta = (bef - alf) * 0.5f * ig;
+          const float az = fabsf(zeta);
+          const float tmag = (az > 1e18f) ? 0.5f * __builtin_amdgcn_rcpf(az)
+                                          : __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(1.f + az * az));
+          const float tt = zeta >= 0.f ? tmag : -tmag;
+          c = __builtin_amdgcn_rsqf(1.f + tt * tt);
+          s = c * tt;
+          e = make_float2(grf * ig, -gif * ig);
+        }
+        if (rot) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int i = gl + G * m;
+            if (i >= K) continue;
+            const float2 zq2 = cmul(e, zq[m]), qv2 = cmul(e, qv[m]);
+            zb[pp * K + i] = csub(cscale(zp[m], c), cscale(zq2, s));
+            zb[qq * K + i] = cadd(cscale(zp[m], s), cscale(zq2, c));
+            qb[pp * K + i] = csub(cscale(qa[m], c), cscale(qv2, s));
+            qb[qq * K + i] = cadd(cscale(qa[m], s), cscale(qv2, c));
+          }
+          if (gl == 0) sm.nrot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const bool done = (sm.nrot == 0);
+    if (sweep == 0) first = !done;
+    __syncthreads();
+    if (done) break;
+  }
+  return first;
+}
+
+// Job columns <-> global columns: block bp supplies job columns [0, np),
+// block bq [np, np + nq).
+__device__ __forceinline__ int job_col(int c, int np, int bp, int bq, int b) {
+  return (c < np) ? bp * b + c : bq * b + (c - np);
+}
+
+template <int G>
+__device__ __forceinline__ void jacobi_big(BigShared& sm, float2* Zm, float2* Qm, int K, int d, int* sweeps,
+                           int* rounds) {
+  constexpr int NCMAX = 2048 / G;    // 64 columns (G = 32) or 32 (G = 64)
+  const int tid = threadIdx.x;
+  const int b = NCMAX / 2;
+  const int nblk = (d <= NCMAX) ? 1 : (d + b - 1) / b;
+  if (nblk == 1) {
+    for (int e = tid; e < d * K; e += NTH) { sm.u.jac.z[e] = Zm[e]; sm.u.jac.q[e] = Qm[e]; }
+    __syncthreads();
+    jacobi_job<G>(sm, K, d, MAX_SWEEPS, sweeps, rounds);
+    for (int e = tid; e < d * K; e += NTH) { Zm[e] = sm.u.jac.z[e]; Qm[e] = sm.u.jac.q[e]; }
+    __syncthreads();
+    return;
+  }
+  const int nbe = nblk + (nblk & 1);
+  for (int pass = 0; pass < MAX_SWEEPS; ++pass) {
+    bool any = false;
+    int inner = 0;
+    for (int k = 0; k < nbe - 1; ++k) {
+      for (int m = 0; m < nbe / 2; ++m) {
+        int bp = 0, bq = 0;
+        rr_pair(k, m, nbe, &bp, &bq);
+        const int np = (bp < nblk) ? min(b, d - bp * b) : 0;
+        const int nq = (bq < nblk) ? min(b, d - bq * b) : 0;
+        const int nc = np + nq;
+        for (int e = tid; e < nc * K; e += NTH) {
+          const int c = e / K, i = e - c * K;
+          const size_t g = (size_t)job_col(c, np, bp, bq, b) * K + i;
+          sm.u.jac.z[e] = Zm[g];
+          sm.u.jac.q[e] = Qm[g];
+        }
+        __syncthreads();
+        any = jacobi_job<G>(sm, K, nc, MAX_INNER, &inner, rounds) || any;
+        for (int e = tid; e < nc * K; e += NTH) {
+          const int c = e / K, i = e - c * K;
+          const size_t g = (size_t)job_col(c, np, bp, bq, b) * K + i;
+          Zm[g] = sm.u.jac.z[e];
+          Qm[g] = sm.u.jac.q[e];
+        }
+        __syncthreads();
+      }
+    }
+    ++*sweeps;
+    if (!any) break;
+  }
+}
+
+// sigma_j^2 = ||z_j||^2 (FP64), their descending order, the smallest r whose
+// leading sigma_j^2 reach Et (all d if rounding keeps the sum below it).
+__device__ __forceinline__ void pick_rank_big(BigShared& sm, const float2* Zm, int K, int d, double Et, int* r_out,
+                              double* cap_out, double* td_sig2) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int c = wid; c < d; c += NWV) {
+    double v = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = lane + 64 * m;
+      if (i < K) v += (double)cabs2(Zm[(size_t)c * K + i]);
+    }
+    v = wave_sum(v);
+    if (lane == 0) sm.s2[c] = v;
+  }
+  __syncthreads();
+  if (tid < d) {
+    const double v = sm.s2[tid];
+    int rank = 0;
+    for (int k = 0; k < d; ++k) {
+      const double w = sm.s2[k];
+      rank += (w > v) || (w == v && k < tid);
+    }
+    sm.order[rank] = tid;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double cs = 0.0;
+    int rr = d;
+    for (int m = 0; m < d; ++m) {
+      cs += sm.s2[sm.order[m]];
+      if (cs >= Et) { rr = m + 1; break; }
+    }
+    sm.r = rr;
+    sm.cap = cs;
+  }
+  __syncthreads();
+  if (tid < d) td_sig2[tid] = sm.s2[sm.order[tid]];
+  *r_out = sm.r;
+  *cap_out = sm.cap;
+  __syncthreads();
+}
+
+// ---------------------------------------------------- capacitance solve
+// Gauss-Jordan with partial pivoting on the r x (r + K) FP64 system
+// aug = [C | M] (row-major, ld ldg) so that its last K columns become
+// C^-1 M.  Returns false (and leaves aug partly eliminated) if a pivot's
+// modulus is not above SING_TOL or is not finite.
+__device__ __forceinline__ bool solve_capacitance(BigShared& sm, double2* aug, int r, int ldg) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double2* gp = sm.u.gj.pan;
+  if (tid == 0) sm.singular = 0;
+  for (int j0 = 0; j0 < r; j0 += GJ_W) {
+    const int nc = min(GJ_W, r - j0);
+    for (int e = tid; e < r * GJ_W; e += NTH) {
+      const int i = e / GJ_W, c = e - i * GJ_W;
+      gp[e] = (c < nc) ? aug[(size_t)i * ldg + j0 + c] : dz();
+    }
+    __syncthreads();
+    for (int k = 0; k < nc; ++k) {
+      const int j = j0 + k;
+      if (wid == 0) {
+        // rows lane and lane + 64; the smallest row index holding the maximum modulus
+        const double2 v0 = (lane < r) ? gp[lane * GJ_W + k] : dz();
+        const double2 v1 = (lane + 64 < r) ? gp[(lane + 64) * GJ_W + k] : dz();
+        const double m0 = (lane >= j && lane < r) ? dabs2(v0) : -1.0;
+        const double m1 = (lane + 64 >= j && lane + 64 < r) ? dabs2(v1) : -1.0;
+        double mx = fmax(m0, m1);
+        mx = fmax(mx, dpp_d<DPP_QUAD_1032>(mx));
+        mx = fmax(mx, dpp_d<DPP_QUAD_2301>(mx));
+        mx = fmax(mx, dpp_d<DPP_ROW_ROR4>(mx));
+        mx = fmax(mx, dpp_d<DPP_ROW_ROR8>(mx));
+        mx = fmax(fmax(readlane_d(mx, 0), readlane_d(mx, 16)), fmax(readlane_d(mx, 32), readlane_d(mx, 48)));
+        const unsigned long long h0 = __ballot(m0 == mx);
+        const unsigned long long h1 = __ballot(m1 == mx);
+        int prow = -1;
+        if (h0) prow = __ffsll((long long)h0) - 1;
+        else if (h1) prow = 64 + __ffsll((long long)h1) - 1;
+        if (lane == 0) {
+          if (prow < 0) {
+            sm.pivrow[k] = j;
+            sm.singular = 1;
+          } else {
+            sm.pivrow[k] = prow;
+            if (!(sqrt(mx) > SING_TOL) || !isfinite(mx)) sm.singular = 1;
+          }
+        }
+        if (prow >= 0) {
+          const double2 pv = (prow < 64) ? v0 : v1;
+          if (lane == (prow & 63)) sm.pivv[k] = pv;
+        }
+      }
+      __syncthreads();
+      if (sm.singular) return false;
+      const int pr = sm.pivrow[k];
+      const double2 piv = sm.pivv[k];
+      // row exchange j <-> pr in panel columns k.., the normalised pivot row;
+      // column k keeps the multipliers (row j: 1 / pivot)
+      if (tid < nc - k) {
+        const int c = k + tid;
+        const double2 a = gp[j * GJ_W + c], bb = gp[pr * GJ_W + c];
+        if (c == k) {
+          gp[pr * GJ_W + k] = a;
+          gp[j * GJ_W + k] = ddiv(make_double2(1.0, 0.0), piv);
+        } else {
+          const double2 u = ddiv(bb, piv);
+          gp[pr * GJ_W + c] = a;
+          gp[j * GJ_W + c] = u;
+          sm.u.gj.ustash[c] = u;
+        }
+      }
+      __syncthreads();
+      const int w = nc - k - 1;
+      for (int e = tid; e < r * w; e += NTH) {
+        const int i = e / w, c = k + 1 + (e - i * w);
+        if (i == j) continue;
+        gp[i * GJ_W + c] = dsub(gp[i * GJ_W + c], dmul(gp[i * GJ_W + k], sm.u.gj.ustash[c]));
+      }
+      __syncthreads();
+    }
+    // replay the panel's exchanges and eliminations on every later column
+    for (int c = j0 + nc + wid; c < ldg; c += NWV) {
+      double2 x0 = (lane < r) ? aug[(size_t)lane * ldg + c] : dz();
+      double2 x1 = (lane + 64 < r) ? aug[(size_t)(lane + 64) * ldg + c] : dz();
+      for (int k = 0; k < nc; ++k) {
+        const int j = j0 + k, pr = sm.pivrow[k];
+        const double2 sj = (j < 64) ? x0 : x1;
+        const double2 sp = (pr < 64) ? x0 : x1;
+        const double2 vj = make_double2(readlane_d(sj.x, j & 63), readlane_d(sj.y, j & 63));
+        const double2 vp = make_double2(readlane_d(sp.x, pr & 63), readlane_d(sp.y, pr & 63));
+        const double2 u = dmul(vp, gp[j * GJ_W + k]);
+        // row pr takes the old row j (then is eliminated like any other row)
+        if (pr != j) {
+          if (pr < 64) { if (lane == pr) x0 = vj; } else { if (lane == pr - 64) x1 = vj; }
+        }
+        if (lane < r) x0 = (lane == j) ? u : dsub(x0, dmul(gp[lane * GJ_W + k], u));
+        if (lane + 64 < r) x1 = (lane + 64 == j) ? u : dsub(x1, dmul(gp[(lane + 64) * GJ_W + k], u));
+      }
+      if (lane < r) aug[(size_t)lane * ldg + c] = x0;
+      if (lane + 64 < r) aug[(size_t)(lane + 64) * ldg + c] = x1;
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+template <bool MANY>
+__global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob* many, int* err) {
+  __shared__ BigShared sm;
+  const ArsvdJob& jb = job_of<MANY>(one, many);
+  TrackDesc* __restrict__ td = jb.td;
+  const int t = jb.t, i_max = jb.i_max;
+  const double eta = jb.eta;
+  const int tid = threadIdx.x, wid = tid >> 6;
+  const int K = td->K;
+  const float2* __restrict__ dA = td->dA;
+  float2* Ym = td->Ym;
+  float2* Qm = td->Qm;
+  float2* Zm = td->Zm;
+
+  double part = 0.0;
+  for (int e = tid; e < K * K; e += NTH) {
+    const float2 v = dA[e];
+    part += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  const double E = block_sum(part, sm.red);
+  if (!isfinite(E) || E == 0.0) {
+    if (tid == 0) {
+      if (!isfinite(E)) atomicCAS(err, 0, DEV_ERR_NONFINITE);
+      td->info.r = 0; td->info.iters = 0; td->info.path = RZF_PATH_NOOP; td->info.d = 0;
+      td->info.dA_fro2 = E; td->info.captured = 0.0;
+      if (jb.out) *jb.out = td->info;
+      if (E == 0.0) td->last_r = 0;
+      td->dbg[0] = 0; td->dbg[1] = 0; td->dbg[2] = 0;
+      td->nsig = 0;
+    }
+    return;
+  }
+  const double Et = eta * E;
+  long long t_sk = 0, t_qr = 0, t_jac = 0, t_wb = 0;
+  const long long r_begin = wall_clock64();
+  long long c_mark = clock64();
+  int k0 = td->k_init;
+  if (td->kinit_policy == RZF_KINIT_WARM && td->last_r > k0) k0 = td->last_r;
+  const int p = td->p;
+  const uint64_t seed = td->seed, trk = td->track_id;
+  const int ktl = (K + 15) / 16;
+
+  int d = 0, iters = 0, r = 0, sweeps = 0, rounds = 0, qrcols = 0;
+  double captured = 0.0;
+  bool rotated = false;
+  for (int it = 1; it <= i_max; ++it) {
+    iters = it;
+    d = min(k0 + p, K);
+    // Y = Delta A Omega, one 16-column tile of Omega at a time
+    for (int ct = 0; ct * 16 < d; ++ct) {
+      const int j0 = 16 * ct;
+      for (int e = tid; e < 16 * K; e += NTH) {
+        const int jj = e / K, i = e - jj * K;
+        sm.u.om[e] = (j0 + jj < d) ? sketch_entry(seed, trk, t, it, i, j0 + jj) : cz();
+      }
+      __syncthreads();
+      for (int rt = wid; rt < ktl; rt += NWV) {
+        floatx4 dr = zero4(), di = zero4();
+        ctile16([&](int i, int k) {
+                  const int row = rt * 16 + i;
+                  return (row < K && k < K) ? dA[(size_t)row * K + k] : cz();
+                },
+                [&](int k, int jj) { return (k < K) ? sm.u.om[jj * K + k] : cz(); }, 0, up4(K), dr, di);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = rt * 16 + tile_row(v), c = j0 + tile_col();
+          if (row < K && c < d) Ym[(size_t)c * K + row] = make_float2(dr[v], di[v]);
+        }
+      }
+      __syncthreads();
+    }
+    t_sk += clock64() - c_mark; c_mark = clock64();
+    qr_big(sm, Ym, Qm, K, d);
+    qrcols += d;
+    // Z = Delta A Q and ||Z||_F^2
+    double zp = 0.0;
+    const int dtl = (d + 15) / 16;
+    for (int tt = wid; tt < ktl * dtl; tt += NWV) {
+      const int ti = tt / dtl, tj = tt - ti * dtl;
+      floatx4 dr = zero4(), di = zero4();
+      ctile16([&](int i, int k) {
+                const int row = ti * 16 + i;
+                return (row < K && k < K) ? dA[(size_t)row * K + k] : cz();
+              },
+              [&](int k, int jj) {
+                const int c = tj * 16 + jj;
+                return (k < K && c < d) ? Qm[(size_t)c * K + k] : cz();
+              },
+              0, up4(K), dr, di);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * 16 + tile_row(v), c = tj * 16 + tile_col();
+        if (row < K && c < d) {
+          Zm[(size_t)c * K + row] = make_float2(dr[v], di[v]);
+          zp += (double)dr[v] * dr[v] + (double)di[v] * di[v];
+        }
+      }
+    }
+    const double tot = block_sum(zp, sm.red);
+    t_qr += clock64() - c_mark; c_mark = clock64();
+    if (tot >= Et) {
+      if (K <= 128) jacobi_big<32>(sm, Zm, Qm, K, d, &sweeps, &rounds);
+      else jacobi_big<64>(sm, Zm, Qm, K, d, &sweeps, &rounds);
+      t_jac += clock64() - c_mark; c_mark = clock64();
+      rotated = true;
+      pick_rank_big(sm, Zm, K, d, Et, &r, &captured, td->sig2);
+      break;
+    }
+    if (it == i_max) {
+      r = d;
+      captured = tot;
+    }
+    k0 *= 2;
+  }
+  if (!rotated) {
+    if (tid < d) sm.order[tid] = tid;
+    __syncthreads();
+  }
+
+  const int rmax = (int)floor(td->switch_ratio * (double)K);
+  bool use_wb = r <= rmax && r <= K / 2;
+  int path = use_wb ? RZF_PATH_WB : RZF_PATH_FULL_RANK;
+  float2* Ainv = td->Ainv;
+  if (use_wb) {
+    const int* ord = sm.order;
+    float2* Pm = td->Pm;
+    double2* aug = td->Aug;
+    const int rtl = (r + 15) / 16;
+    // step 1: P = A^-1 U
+    for (int tt = wid; tt < ktl * rtl; tt += NWV) {
+      const int ti = tt / rtl, tj = tt - ti * rtl;
+      floatx4 dr = zero4(), di = zero4();
+      ctile16([&](int i, int k) {
+                const int row = ti * 16 + i;
+                return (row < K && k < K) ? Ainv[(size_t)row * K + k] : cz();
+              },
+              [&](int k, int c) {
+                const int cc = tj * 16 + c;
+                return (k < K && cc < r) ? Qm[(size_t)ord[cc] * K + k] : cz();
+              },
+              0, up4(K), dr, di);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * 16 + tile_row(v), c = tj * 16 + tile_col();
+        if (row < K && c < r) Pm[(size_t)c * K + row] = make_float2(dr[v], di[v]);
+      }
+    }
+    __syncthreads();
+    // step 2: [C | M] = [I + V~^H P | V~^H A^-1] in FP64
+    const int ldg = r + K;
+    for (int tt = wid; tt < rtl * (rtl + ktl); tt += NWV) {
+      const int ti = tt / (rtl + ktl), tj = tt - ti * (rtl + ktl);
+      const bool ct = tj < rtl;
+      floatx4 dr = zero4(), di = zero4();
+      auto la = [&](int i, int k) {
+        const int a = ti * 16 + i;
+        return (a < r && k < K) ? cconj(Zm[(size_t)ord[a] * K + k]) : cz();
+      };
+      if (ct)
+        ctile16(la, [&](int k, int c) {
+                  const int b = tj * 16 + c;
+                  return (k < K && b < r) ? Pm[(size_t)b * K + k] : cz();
+                }, 0, up4(K), dr, di);
+      else
+        ctile16(la, [&](int k, int c) {
+                  const int j = (tj - rtl) * 16 + c;
+                  return (k < K && j < K) ? Ainv[(size_t)k * K + j] : cz();
+                }, 0, up4(K), dr, di);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = ti * 16 + tile_row(v);
+        if (a >= r) continue;
+        if (ct) {
+          const int c = tj * 16 + tile_col();
+          if (c < r) aug[(size_t)a * ldg + c] = make_double2((a == c ? 1.0 : 0.0) + (double)dr[v], (double)di[v]);
+        } else {
+          const int j = (tj - rtl) * 16 + tile_col();
+          if (j < K) aug[(size_t)a * ldg + r + j] = make_double2((double)dr[v], (double)di[v]);
+        }
+      }
+    }
+    __syncthreads();
+    // step 3: X = C^-1 (V~^H A^-1)
+    if (!solve_capacitance(sm, aug, r, ldg)) {
+      use_wb = false;
+      path = RZF_PATH_FULL_SINGULAR;
+    } else {
+      // steps 4-5: A^-1 <- A^-1 - P X (each wave rewrites its own tiles)
+      for (int tt = wid; tt < ktl * ktl; tt += NWV) {
+        const int ti = tt / ktl, tj = tt - ti * ktl;
+        floatx4 dr = zero4(), di = zero4();
+        ctile16([&](int i, int a) {
+                  const int row = ti * 16 + i;
+                  return (row < K && a < r) ? Pm[(size_t)a * K + row] : cz();
+                },
+                [&](int a, int c) {
+                  const int j = tj * 16 + c;
+                  return (a < r && j < K) ? d2f(aug[(size_t)a * ldg + r + j]) : cz();
+                },
+                0, up4(r), dr, di);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = ti * 16 + tile_row(v), j = tj * 16 + tile_col();
+          if (row < K && j < K) {
+            float2* q = Ainv + (size_t)row * K + j;
+            *q = csub(*q, make_float2(dr[v], di[v]));
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!use_wb) {
+    if (tid == 0) sm.bad = 0;
+    for (int e = tid; e < K * K; e += NTH) Ainv[e] = td->Anew[e];
+    __syncthreads();
+    gj_inverse_hpd_blocked<float2>(Ainv, K, K, sm.u.inv.xs, sm.u.inv.cs, sm.u.inv.pb, &sm.bad);
+    if (tid == 0 && sm.bad) atomicCAS(err, 0, sm.bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
+  }
+  if (tid == 0) {
+    td->info.r = r; td->info.iters = iters; td->info.path = path; td->info.d = d;
+    td->info.dA_fro2 = E; td->info.captured = captured;
+    if (jb.out) *jb.out = td->info;
+    td->last_r = r;
+    td->dbg[0] = sweeps; td->dbg[1] = rounds; td->dbg[2] = qrcols;
+    td->nsig = rotated ? d : 0;
+    t_wb = clock64() - c_mark;
+    td->dbg[3] = (int)t_sk; td->dbg[4] = (int)t_qr; td->dbg[5] = (int)t_jac; td->dbg[6] = (int)t_wb;
+    td->dbg[7] = (int)(wall_clock64() - r_begin);
+  }
+}
+
+// FP64 inverse of the init / reset Gram matrix for a large track, in place
+// in the FP64 buffer, rounded to the FP32 state.
+template <bool MANY>
+__global__ __launch_bounds__(NTH) void k_inv64_big(Inv64Job one, const Inv64Job* many, int* err) {
+  __shared__ double2 xs[16 * KM], cs[KM * 16], pb[2 * 256];
+  __shared__ int bad;
+  const Inv64Job& jb = job_of<MANY>(one, many);
+  const int K = jb.K;
+  double2* A = const_cast<double2*>(jb.A);
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  gj_inverse_hpd_blocked<double2>(A, K, K, xs, cs, pb, &bad);
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) jb.Ainv[e] = d2f(A[e]);
+  if (threadIdx.x == 0) {
+    if (bad) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
+    DevInfo rec;
+    rec.r = 0; rec.iters = 0; rec.path = RZF_PATH_RESET; rec.d = 0;
+    rec.dA_fro2 = 0.0; rec.captured = 0.0;
+    if (jb.info) *jb.info = rec;
+    if (jb.out) *jb.out = rec;
+  }
+}
+
+// FP32 inverse for rzf_full on a large track: A is copied to Ainv (unless
+// they alias) and inverted there in place.
+template <bool MANY>
+__global__ __launch_bounds__(NTH) void k_inv32_big(Inv32Job one, const Inv32Job* many, int* err) {
+  __shared__ float2 xs[16 * KM], cs[KM * 16], pb[2 * 256];
+  __shared__ int bad;
+  const Inv32Job& jb = job_of<MANY>(one, many);
+  const int K = jb.K;
+  float2* Ainv = jb.Ainv;
+  if (threadIdx.x == 0) bad = 0;
+  if (jb.A != Ainv)
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) Ainv[e] = jb.A[e];
+  __syncthreads();
+  gj_inverse_hpd_blocked<float2>(Ainv, K, K, xs, cs, pb, &bad);
+  if (threadIdx.x == 0 && bad) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
+}
+
+}  // namespace
+
+void launch_arsvd_big(const ArsvdJob& one, const ArsvdJob* many, int n, int* err, hipStream_t s) {
+  if (many) k_arsvd_big<true><<<dim3(1, n), NTH, 0, s>>>(one, many, err);
+  else k_arsvd_big<false><<<1, NTH, 0, s>>>(one, many, err);
+}
+
+void launch_inv64_big(const Inv64Job& one, const Inv64Job* many, int n, int* err, hipStream_t s) {
+  if (many) k_inv64_big<true><<<dim3(1, n), NTH, 0, s>>>(one, many, err);
+  else k_inv64_big<false><<<1, NTH, 0, s>>>(one, many, err);
+}
+
+void launch_inv32_big(const Inv32Job& one, const Inv32Job* many, int n, int* err, hipStream_t s) {
+  if (many) k_inv32_big<true><<<dim3(1, n), NTH, 0, s>>>(one, many, err);
+  else k_inv32_big<false><<<1, NTH, 0, s>>>(one, many, err);
+}

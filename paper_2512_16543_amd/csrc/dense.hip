@@ -13,7 +13,7 @@ namespace {
 
 template <bool MANY>
 __global__ __launch_bounds__(1024) void k_inv32(Inv32Job one, const Inv32Job* many, int* err) {
-  __shared__ float2 b0[KM * KM], xs[16 * KM], ys[KM * 16], pb[2 * 256];
+  __shared__ float2 b0[KS * KS], xs[16 * KS], ys[KS * 16], pb[2 * 256];
   __shared__ int bad;
   const Inv32Job& jb = job_of<MANY>(one, many);
   const int K = jb.K;
@@ -22,20 +22,20 @@ __global__ __launch_bounds__(1024) void k_inv32(Inv32Job one, const Inv32Job* ma
   if (threadIdx.x == 0) bad = 0;
   for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
     const int i = e / K, j = e - i * K;
-    b0[i * KM + j] = A[e];
+    b0[i * KS + j] = A[e];
   }
   __syncthreads();
-  gj_inverse_hpd_mfma(b0, K, KM, xs, ys, pb, &bad);
+  gj_inverse_hpd_mfma(b0, K, KS, xs, ys, pb, &bad);
   for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
     const int i = e / K, j = e - i * K;
-    Ainv[e] = b0[i * KM + j];
+    Ainv[e] = b0[i * KS + j];
   }
   if (threadIdx.x == 0 && bad) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
 }
 
 template <bool MANY>
 __global__ __launch_bounds__(1024) void k_inv64(Inv64Job one, const Inv64Job* many, int* err) {
-  __shared__ double2 b0[KM * KM], b1[KM * KM];
+  __shared__ double2 b0[KS * KS], b1[KS * KS];
   __shared__ int bad;
   const Inv64Job& jb = job_of<MANY>(one, many);
   const int K = jb.K;

@@ -1,7 +1,17 @@
-// Workgroup-level dense kernels on matrices held in LDS.
+// Workgroup-level dense kernels: Gauss-Jordan inverses of HPD matrices and
+// the round-robin pair ordering of the Jacobi sweeps.
 #pragma once
 
 #include "rzf_device.h"
+
+// Column pair (p, q) of round k, slot m, of the round-robin ordering over n
+// (even) columns: every pair meets once in n-1 rounds.
+__device__ __forceinline__ void rr_pair(int k, int m, int n, int* p, int* q) {
+  if (m == 0) { *p = k; *q = n - 1; return; }
+  const int n1 = n - 1;
+  *p = (k + m) % n1;
+  *q = (k - m + n1) % n1;
+}
 
 template <class T> struct CX;
 template <> struct CX<float2> {
@@ -258,6 +268,137 @@ __device__ void gj_inverse_hpd_mfma(float2* a, int K, int ld, float2* xs, float2
     if (mine) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) a[(16 * ti + tile_row(v)) * ld + 16 * tj + tile_col()] = nv[v];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------
+// Inverse of a Hermitian positive definite K x K matrix for any K (the large
+// tracks, 64 < K <= 256), in place, by the same Gauss-Jordan exchange on
+// 16 x 16 pivot blocks as gj_inverse_hpd_mfma.  The matrix may sit in global
+// memory (it then stays in L2 between steps) or in LDS; only the strips of
+// the current step are staged in LDS:
+//   xs (16 x KP)  X = P^-1 a_P,:         (new pivot block row)
+//   cs (KP x 16)  a_:,P before the step  (old pivot block column)
+// so every 16 x 16 tile is read and rewritten by the wavefront that owns it:
+//   a_PP -> P^-1,  a_PR -> X_R,  a_RP -> -a_RP P^-1,  a_RR -> a_RR - a_RP X_R.
+// T = float2 multiplies on the FP32 matrix cores, T = double2 on the FP64
+// vector units.  Indices past K read as the identity and are never written.
+// All threads of the block (a multiple of 64, at most 1024) call it; pb holds
+// 2 * 256 values.  *bad (LDS) becomes 1 (pivot not positive) or 2 (not finite).
+template <class T, class LA, class LB>
+__device__ __forceinline__ void tile16_any(const LA& la, const LB& lb, int k0, int k1, T acc[4]) {
+  if constexpr (sizeof(T) == sizeof(float2)) {
+    floatx4 dr = zero4(), di = zero4();
+    ctile16(la, lb, k0, k1, dr, di);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = make_float2(dr[v], di[v]);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = dz();
+    dtile16(la, lb, k0, k1, acc);
+  }
+}
+
+// 16 x 16 pivot-block inverse by scalar exchange steps in one wavefront.
+// ld(r, c) loads the block; the inverse is left in pb[0..255] (row-major).
+template <class T, class LD>
+__device__ __forceinline__ void pivot_inverse16(const LD& ld, T* pb, int* bad) {
+  typedef CX<T> C;
+  const int lane = threadIdx.x & 63;
+  const int r = lane >> 2, c0 = (lane & 3) * 4;
+  T* x0 = pb;
+  T* x1 = pb + 256;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) x0[r * 16 + c0 + u] = ld(r, c0 + u);
+  bool ok = true, fin = true;
+  for (int q = 0; q < 16; ++q) {
+    wave_sync();
+    const T piv = x0[q * 16 + q];
+    fin = fin && C::finite(piv);
+    ok = ok && C::re(piv) > 0.0;
+    const T ip = C::inv(piv);
+    const T xrq = x0[r * 16 + q];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u;
+      const T xqc = x0[q * 16 + c];
+      T v;
+      if (r == q && c == q) v = ip;
+      else if (r == q) v = C::mul(xqc, ip);
+      else if (c == q) v = C::neg(C::mul(xrq, ip));
+      else v = C::sub(x0[r * 16 + c], C::mul(C::mul(xrq, ip), xqc));
+      x1[r * 16 + c] = v;
+    }
+    T* t = x0; x0 = x1; x1 = t;
+  }
+  wave_sync();
+  if (lane == 0) {
+    if (!fin) *bad = 2;
+    else if (!ok && *bad == 0) *bad = 1;
+  }
+  // 16 steps (even): the result is back in pb[0..255]
+}
+
+template <class T>
+__device__ __forceinline__ void gj_inverse_hpd_blocked(T* a, int K, int ld, T* xs, T* cs, T* pb, int* bad) {
+  typedef CX<T> C;
+  const int tid = threadIdx.x, wid = tid >> 6, nwv = blockDim.x >> 6;
+  const int KP = (K + 15) & ~15, nb = KP / 16;
+  auto at = [&](int i, int j) -> T {
+    return (i < K && j < K) ? a[(size_t)i * ld + j] : (i == j ? C::one() : C::zero());
+  };
+  for (int s = 0; s < nb; ++s) {
+    const int p0 = 16 * s;
+    if (wid == 0) pivot_inverse16<T>([&](int r, int c) { return at(p0 + r, p0 + c); }, pb, bad);
+    __syncthreads();
+    const T* pinv = pb;
+    // strips: X_j = P^-1 a_P,j (tiles 0..nb-1) and a copy of a_:,P (tiles nb..2nb-1)
+    for (int t = wid; t < 2 * nb; t += nwv) {
+      if (t < nb) {
+        const int j0 = 16 * t;
+        T acc[4];
+        tile16_any<T>([&](int i, int k) { return pinv[i * 16 + k]; },
+                      [&](int k, int j) { return at(p0 + k, j0 + j); }, 0, 16, acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xs[tile_row(v) * KP + j0 + tile_col()] = acc[v];
+      } else {
+        const int i0 = 16 * (t - nb);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          cs[(i0 + tile_row(v)) * 16 + tile_col()] = at(i0 + tile_row(v), p0 + tile_col());
+      }
+    }
+    __syncthreads();
+    for (int t = wid; t < nb * nb; t += nwv) {
+      const int ti = t / nb, tj = t - ti * nb;
+      const int i0 = 16 * ti, j0 = 16 * tj;
+      T nv[4];
+      if (ti == s && tj == s) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) nv[v] = pinv[tile_row(v) * 16 + tile_col()];
+      } else if (ti == s) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) nv[v] = xs[tile_row(v) * KP + j0 + tile_col()];
+      } else if (tj == s) {
+        T acc[4];
+        tile16_any<T>([&](int i, int k) { return cs[(i0 + i) * 16 + k]; },
+                      [&](int k, int j) { return pinv[k * 16 + j]; }, 0, 16, acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) nv[v] = C::neg(acc[v]);
+      } else {
+        T acc[4];
+        tile16_any<T>([&](int i, int k) { return cs[(i0 + i) * 16 + k]; },
+                      [&](int k, int j) { return xs[k * KP + j0 + j]; }, 0, 16, acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) nv[v] = C::sub(at(i0 + tile_row(v), j0 + tile_col()), acc[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + tile_row(v), j = j0 + tile_col();
+        if (i < K && j < K) a[(size_t)i * ld + j] = nv[v];
+      }
     }
     __syncthreads();
   }

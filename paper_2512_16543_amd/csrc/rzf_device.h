@@ -200,6 +200,27 @@ __device__ __forceinline__ void ctile16(const LA& la, const LB& lb, int k0, int 
 
 __device__ __forceinline__ floatx4 zero4() { floatx4 z = {0.f, 0.f, 0.f, 0.f}; return z; }
 
+// FP64 counterpart of ctile16 on the vector units, with the same result
+// layout: acc[v] += sum_k la(tile_row(v), k) lb(k, tile_col()).
+template <class LA, class LB>
+__device__ __forceinline__ void dtile16(const LA& la, const LB& lb, int k0, int k1, double2 acc[4]) {
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 15, rb = 4 * (lane >> 4);
+  for (int k = k0; k < k1; ++k) {
+    const double2 b = lb(k, c);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = dadd(acc[v], dmul(la(rb + v, k), b));
+  }
+}
+
+// Orders the LDS accesses of one wavefront around a point where its lanes
+// exchange data through LDS.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Row / column of result register v in the calling lane.
 __device__ __forceinline__ int tile_row(int v) { return 4 * ((threadIdx.x & 63) >> 4) + v; }
 __device__ __forceinline__ int tile_col() { return threadIdx.x & 15; }

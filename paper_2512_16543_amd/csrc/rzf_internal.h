@@ -6,8 +6,9 @@
 
 #include "rzf.h"
 
-#define KM RZF_KMAX     // largest K held in one workgroup's LDS
-#define WB_RMAX 32      // largest Woodbury rank handled in LDS (= KM / 2)
+#define KM RZF_KMAX     // largest K of any track
+#define KS 64           // largest K whose working set fits one workgroup's LDS
+#define WB_RMAX 32      // largest Woodbury rank of the LDS kernels (= KS / 2)
 
 // Device-side error codes (first one wins; rzf_sync maps them to rzf_status).
 #define DEV_ERR_NOT_HPD 1
@@ -31,6 +32,13 @@ struct TrackDesc {
   float2* dA;      // K x K, ld K: Delta A of the current step
   double2* A64;    // K x K, ld K: FP64 Gram for init / reset
   double* wpart;   // partial ||W||^2 of the precoder blocks
+  // working set of the large-track kernels (K > KS), null otherwise; all
+  // column-major with leading dimension K
+  float2* Ym;      // K x K: sketch Y, then the Householder vectors
+  float2* Qm;      // K x K: Q, rotated by the Jacobi sweeps
+  float2* Zm;      // K x K: Z = Delta A Q, rotated by the Jacobi sweeps
+  float2* Pm;      // K x K/2: P = A^-1 U
+  double2* Aug;    // (K/2) x (K/2 + K), row-major: [C | V~^H A^-1] in FP64
   // written by the device
   int last_r;
   int pad_;
@@ -100,6 +108,11 @@ int precoder_blocks(int N);
 void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, hipStream_t s);
 void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, hipStream_t s);
 void launch_arsvd_wb(const ArsvdJob& one, const ArsvdJob* many, int n, int* err, hipStream_t s);
+// Large tracks (KS < K <= KM): one workgroup per track, working set in the
+// track's global workspace.
+void launch_arsvd_big(const ArsvdJob& one, const ArsvdJob* many, int n, int* err, hipStream_t s);
+void launch_inv64_big(const Inv64Job& one, const Inv64Job* many, int n, int* err, hipStream_t s);
+void launch_inv32_big(const Inv32Job& one, const Inv32Job* many, int n, int* err, hipStream_t s);
 size_t sum_rate_scratch_doubles(int K);
 void launch_sum_rate(const RateJob& one, const RateJob* many, int n, int maxK, int* err, hipStream_t s);
 void launch_debug_sketch(uint64_t seed, uint64_t track, int t, int it, int K, int d, float2* Omega,

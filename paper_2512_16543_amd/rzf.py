@@ -23,7 +23,7 @@ RZF_E_DEVICE = 6
 
 PATH_NOOP, PATH_WB, PATH_FULL_RANK, PATH_FULL_SINGULAR, PATH_RESET = 0, 1, 2, 3, 4
 KINIT_FIXED, KINIT_WARM = 0, 1
-KMAX = 64
+KMAX = 256
 NMAX = 4096
 
 

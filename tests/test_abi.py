@@ -37,7 +37,9 @@ def test_params_default_values():
 
 def test_track_bytes():
     assert rzf.track_bytes(0, 10) == 0
-    assert rzf.track_bytes(65, 10) == 0
+    assert rzf.track_bytes(257, 10) == 0
+    # large tracks carry the blocked kernels' workspace
+    assert rzf.track_bytes(65, 10) > rzf.track_bytes(64, 10) + 3 * 65 * 65 * 8
     assert rzf.track_bytes(4, 0) == 0
     b = rzf.track_bytes(64, 256)
     assert b >= 8 * (64 * 64 * 3 + 64 * 256) + 16 * 64 * 64

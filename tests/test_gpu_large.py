@@ -1,0 +1,179 @@
+"""GPU parity of the large-track kernels (64 < K <= 256) against the FP64 oracle.
+
+Shapes follow the multi-track mix (K up to 128 with N in {64, 256, 1024}) and
+the single large track (K = 256, N = 1024), plus ragged K (not a multiple of
+16) and the sizes that switch between single-job and multi-block Jacobi
+(more than 64 columns at K <= 128, more than 32 at K > 128) and between one
+and several 32-column panels of the capacitance solve (rank above 32).
+Tolerances are those of the K <= 64 kernels.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle.rzf as orz
+from paper_2512_16543_amd import rzf, workload as wl
+from tests.test_gpu_parity import (TOL_FP32, TOL_INIT, _assert_recs, c64, dev, host, rel,
+                                   run_snapshots, run_track)
+
+pytestmark = pytest.mark.gpu
+
+LARGE = [(65, 64), (100, 256), (128, 1024), (128, 128), (200, 300), (256, 1024), (256, 256), (97, 33)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = rzf.Context(0, 1 << 30)
+    yield c
+    c.close()
+
+
+def _channel(K, N, seed):
+    return c64(wl.random_channel(K, N, seed, scale=1.0)).astype(np.complex128)
+
+
+def _params(K, **kw):
+    d = dict(k_init=2, p=5, P=1.0, seed=11, track_id=K, reset_period=0)
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("K,N", LARGE)
+def test_init_inverse_large(ctx, K, N):
+    H = _channel(K, N, 21)
+    alpha = 0.3 + K / 50.0
+    print(f"init K={K} N={N}", flush=True)
+    tr = ctx.init(dev(H), alpha, rzf.default_params())
+    Ai = host(tr.inverse())
+    ctx.sync()
+    assert rel(Ai, np.linalg.inv(orz.gram(H, alpha))) <= TOL_INIT
+    tr.destroy()
+
+
+@pytest.mark.parametrize("K,N", LARGE)
+def test_full_precoder_large(ctx, K, N):
+    H = _channel(K, N, 22)
+    alpha, P = 0.5 + K / 40.0, 2.0
+    W = torch.empty(N, K, dtype=torch.complex64, device="cuda")
+    print(f"full K={K} N={N}", flush=True)
+    ctx.full(dev(H), alpha, P, W)
+    ctx.sync()
+    assert rel(host(W), orz.full_rzf(H, alpha, P)) <= TOL_FP32
+
+
+@pytest.mark.parametrize("K,N", [(128, 1024), (256, 1024), (97, 33)])
+def test_sum_rate_large(ctx, K, N):
+    H = _channel(K, N, 23)
+    alpha, P, s2 = K / 10.0, 1.0, 0.1
+    Wd = dev(orz.full_rzf(H, alpha, P))
+    rates = torch.empty(K, dtype=torch.float32, device="cuda")
+    R = ctx.sum_rate(dev(H), Wd, P, s2, rates)
+    ro, Ro = orz.sum_rate(H, host(Wd), P, s2)
+    assert abs(R - Ro) <= TOL_FP32 * abs(Ro)
+    np.testing.assert_allclose(rates.cpu().numpy(), ro, rtol=2e-5, atol=1e-6)
+
+
+def _walk(K, N, steps, seed, rank, scale=0.02):
+    H = [wl.random_channel(K, N, seed)]
+    for t in range(steps):
+        H.append(wl.perturbed_channel(H[-1], seed * 1000 + t, rank=rank, scale=scale))
+    return c64(np.asarray(H)).astype(np.complex128)
+
+
+# (K, N, rank of the per-step change dH): Delta A has rank <= 2 rank(dH), so
+# the ranks below reach d = 21, 37 and 69 and Woodbury ranks above 32
+@pytest.mark.parametrize("K,N,rank", [(100, 256, 4), (128, 256, 30), (256, 1024, 20), (200, 300, 9),
+                                      (65, 64, 2)])
+def test_update_low_rank_walk(ctx, K, N, rank):
+    Hs = _walk(K, N, 4, 30 + K, rank)
+    print(f"walk K={K} N={N} rank={rank}", flush=True)
+    recs = run_snapshots(ctx, Hs, 0.4 + K / 40.0, _params(K), 0.999)
+    print([(r["path"], r["r"], r["iters"]) for r in recs], flush=True)
+    _assert_recs(recs)
+    assert any(r["path"] == orz.PATH_WB for r in recs), [(r["path"], r["r"]) for r in recs]
+    if rank >= 20:   # d = 69: several Jacobi blocks, and two capacitance panels
+        assert any(r["iters"] == 6 and r["r"] > 32 for r in recs)
+
+
+@pytest.mark.parametrize("eta", [0.999, 0.9])
+def test_update_k128_track(ctx, eta):
+    # 16 x 16 array, 128 users: the largest size of the multi-track mix
+    cfg = wl.with_overrides(wl.CONFIGS["c2"], K=128, seed=3)
+    print(f"k128 track eta={eta}", flush=True)
+    recs = run_track(ctx, cfg, 6, eta, dict(reset_period=4))
+    print([(r["path"], r["r"], r["iters"]) for r in recs], flush=True)
+    _assert_recs(recs)
+    assert [r["t"] for r in recs if r["path"] == orz.PATH_RESET] == [4]
+
+
+@pytest.mark.parametrize("eta", [0.999, 0.9])
+def test_update_c5_track(ctx, eta):
+    cfg = wl.CONFIGS["c5"]
+    print(f"c5 track eta={eta}", flush=True)
+    recs = run_track(ctx, cfg, 4, eta, dict(reset_period=3))
+    print([(r["path"], r["r"], r["iters"]) for r in recs], flush=True)
+    _assert_recs(recs)
+    if eta == 0.9:   # d = 133, Woodbury rank near 90: three capacitance panels
+        assert any(r["path"] == orz.PATH_WB and r["r"] > 64 for r in recs)
+    assert [r["t"] for r in recs if r["path"] == orz.PATH_RESET] == [3]
+
+
+def test_update_large_falls_back(ctx):
+    K, N = 160, 512
+    H0, H1 = _channel(K, N, 40), _channel(K, N, 41)
+    tr = ctx.init(dev(H0), 1.0, rzf.default_params(seed=4))
+    W = torch.empty(N, K, dtype=torch.complex64, device="cuda")
+    info = tr.update(dev(H1), 0.999, W)
+    ctx.sync()
+    assert info.path == rzf.PATH_FULL_RANK and info.r > K // 2
+    assert rel(host(tr.inverse()), np.linalg.inv(orz.gram(H1, 1.0))) <= TOL_FP32
+    assert rel(host(W), orz.full_rzf(H1, 1.0, 1.0)) <= TOL_FP32
+    tr.destroy()
+
+
+def test_update_large_woodbury_at_d_equal_k(ctx):
+    # k_init = K, p = 0: the only iteration has d = K = 96 (three Jacobi blocks
+    # of 32); the change has rank <= 40, so eta = 0.9999 keeps r near 40 and
+    # the capacitance solve spans two 32-column panels
+    K, N = 96, 192
+    Hs = _walk(K, N, 3, 50, rank=20, scale=0.05)
+    recs = run_snapshots(ctx, Hs, 1.5, _params(K, k_init=K, p=0, switch_ratio=1.0), 0.9999)
+    _assert_recs(recs)
+    assert all(r["path"] == orz.PATH_WB and 32 < r["r"] <= K // 2 for r in recs), \
+        [(r["path"], r["r"]) for r in recs]
+
+
+def test_batch_mixed_sizes_equal_alone(ctx):
+    sizes = [(48, 64), (128, 256), (256, 1024), (100, 64)]
+    steps = 3
+    Hs = [_walk(K, N, steps, 60 + i, rank=3) for i, (K, N) in enumerate(sizes)]
+    dv = [torch.from_numpy(c64(H)).cuda() for H in Hs]
+
+    def make():
+        return [ctx.init(d[0], 0.2 + K / 20.0, rzf.default_params(seed=5, track_id=i, reset_period=2))
+                for i, (d, (K, N)) in enumerate(zip(dv, sizes))]
+
+    alone, batch = make(), make()
+    Wa = [torch.empty(N, K, dtype=torch.complex64, device="cuda") for K, N in sizes]
+    Wb = [torch.empty_like(w) for w in Wa]
+    for t in range(1, steps + 1):
+        for tr, d, w in zip(alone, dv, Wa):
+            tr.update(d[t], 0.95, w)
+        ctx.update_batch(batch, [d[t] for d in dv], Wb, 0.95)
+        ctx.sync()
+        for i in range(len(sizes)):
+            assert torch.equal(Wa[i], Wb[i]), (t, sizes[i])
+            assert torch.equal(alone[i].inverse(), batch[i].inverse()), (t, sizes[i])
+    for tr in alone + batch:
+        tr.destroy()
+
+
+def test_full_batch_mixed_sizes(ctx):
+    sizes = [(32, 64), (160, 512), (256, 256)]
+    Hd = [dev(_channel(K, N, 70 + K)) for K, N in sizes]
+    Ws = [torch.empty(N, K, dtype=torch.complex64, device="cuda") for K, N in sizes]
+    ctx.full_batch(Hd, [0.5 + K / 40.0 for K, _ in sizes], 1.0, Ws)
+    ctx.sync()
+    for (K, N), h, w in zip(sizes, Hd, Ws):
+        assert rel(host(w), orz.full_rzf(host(h), 0.5 + K / 40.0, 1.0)) <= TOL_FP32

@@ -138,7 +138,11 @@ def _params(cfg, **kw):
 
 
 def _oracle_params(cfg, d):
-    return orz.TrackParams(alpha=cfg.alpha, P=d["P"], k_init=d["k_init"], p=d["p"],
+    return _oracle_params_a(cfg.alpha, d)
+
+
+def _oracle_params_a(alpha, d):
+    return orz.TrackParams(alpha=alpha, P=d["P"], k_init=d["k_init"], p=d["p"],
                            i_max=d.get("i_max", 0), switch_ratio=d.get("switch_ratio", 0.5),
                            reset_period=d["reset_period"], seed=d["seed"], track_id=d["track_id"],
                            kinit_policy=d.get("kinit_policy", 0))
@@ -162,15 +166,23 @@ def _tie_ok(state, H, eta, gi, io, ot):
     return bool(np.any(np.abs(c - eta) < TIE_BAND))
 
 
-def run_track(ctx, cfg, steps, eta, prm_kw=None, check_every=1):
-    """Run GPU and oracle side by side; before every step the oracle adopts the
-    GPU's state (one-step parity).  Returns per-step records."""
+def run_track(ctx, cfg, steps, eta, prm_kw=None):
+    """Run GPU and oracle side by side over a synthetic pass of `cfg`."""
     prm_kw = prm_kw or {}
     d = _params(cfg, **prm_kw)
     Hs = c64(wl.make_track(wl.with_overrides(cfg, steps=steps)).snapshots()).astype(np.complex128)
-    tr = ctx.init(dev(Hs[0]), cfg.alpha, rzf.default_params(**d))
-    ot = orz.OracleTrack(Hs[0], _oracle_params(cfg, d))
-    W = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device="cuda")
+    return run_snapshots(ctx, Hs, cfg.alpha, d, eta)
+
+
+def run_snapshots(ctx, Hs, alpha, d, eta):
+    """GPU and oracle side by side over the snapshots Hs (complex64 values);
+    before every step the oracle adopts the GPU's state (one-step parity).
+    `d` holds the track parameters.  Returns per-step records."""
+    K, N = Hs[0].shape
+    steps = len(Hs) - 1
+    tr = ctx.init(dev(Hs[0]), alpha, rzf.default_params(**d))
+    ot = orz.OracleTrack(Hs[0], _oracle_params_a(alpha, d))
+    W = torch.empty(N, K, dtype=torch.complex64, device="cuda")
     recs = []
     for t in range(1, steps + 1):
         state = ot.export_state()
@@ -316,7 +328,7 @@ def test_invalid_arguments(ctx):
         with pytest.raises(rzf.RzfError) as e:
             tr.update(H, bad, W)
         assert e.value.status == rzf.RZF_E_INVALID
-    big = dev(_channel(65, 8, 1))
+    big = dev(_channel(257, 8, 1))
     with pytest.raises(rzf.RzfError) as e:
         ctx.init(big, 1.0, rzf.default_params())
     assert e.value.status == rzf.RZF_E_SHAPE
