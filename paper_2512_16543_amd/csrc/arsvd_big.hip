@@ -17,11 +17,9 @@
 //     compact WY form H_0..H_15 = I - V T V^H is applied to the trailing
 //     columns with three 16-wide products on the matrix cores, and Q is
 //     formed by the same blocks in reverse order;
-//   * one-sided block Jacobi: the d columns are cut into blocks of b; a job
-//     loads two blocks of Z and of Q into LDS, sweeps their 2b columns until
-//     they are mutually orthogonal, and writes them back; the blocks meet in
-//     the round-robin order until a full pass rotates nothing (d <= 2b is a
-//     single job, i.e. plain one-sided Jacobi);
+//   * one-sided Jacobi in column blocks: block pairs of Z and Q are staged
+//     in LDS and every column pair is rotated once per pass (d <= 2b: all
+//     columns in LDS, plain cyclic sweeps);
 //   * Gauss-Jordan with partial pivoting on [C | V~^H A^-1] in 32-column
 //     panels: the panel is eliminated in LDS, recording its pivots and
 //     multipliers, then every other column replays them;
@@ -33,8 +31,7 @@ namespace {
 
 constexpr int NTH = 1024;
 constexpr int NWV = NTH / 64;
-constexpr int MAX_SWEEPS = 30;      // Jacobi passes (single job: sweeps)
-constexpr int MAX_INNER = 8;        // sweeps of one job of a multi-block pass
+constexpr int MAX_SWEEPS = 30;      // Jacobi passes
 constexpr double JACOBI_TOL = 2e-6;
 constexpr double SING_TOL = 1e-12;
 constexpr int JOB_ELEMS = KM * 32;  // LDS entries of one job matrix
@@ -296,151 +293,164 @@ __device__ __forceinline__ double gsumd(double v) {
   return v + __shfl_xor(v, 16);
 }
 
-// One-sided Jacobi on the nc job columns held in LDS (Z in sm.u.jac.z, Q in
-// sm.u.jac.q, column c at c*K).  A group of G lanes owns one column pair per
-// round (rows gl + G m, m < 4).  Sweeps until a sweep rotates nothing or
-// max_sweeps.  Returns whether the first sweep rotated anything.
+// Rotation of the job column pair (pp, qq) held in LDS (Z in sm.u.jac.z, Q
+// in sm.u.jac.q, column c at c*K) by the calling group of G lanes (rows
+// gl + G m, m < 4): the one-sided Jacobi step that makes z_p and z_q
+// orthogonal, applied to q_p and q_q as well.  ||z_p||^2 and ||z_q||^2 are
+// sums of non-negative FP32 terms; the inner product z_p^H z_q, which cancels
+// as the columns become orthogonal, is accumulated in FP64.  A pair already
+// orthogonal to JACOBI_TOL is left alone.  Sets sm.nrot when it rotates.
+// Every lane of the wave calls it (act = false for an idle group).
 template <int G>
-__device__ __forceinline__ bool jacobi_job(BigShared& sm, int K, int nc, int max_sweeps, int* sweeps, int* rounds) {
+__device__ __forceinline__ void jacobi_pair(BigShared& sm, int K, int pp, int qq, bool act) {
   float2* zb = sm.u.jac.z;
   float2* qb = sm.u.jac.q;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int gl = lane & (G - 1), slot = threadIdx.x / G;
-  const int n = nc + (nc & 1);
-  const int wave_slots = 64 / G;
-  bool first = false;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    if (threadIdx.x == 0) sm.nrot = 0;
-    __syncthreads();
-    ++*sweeps;
-    for (int k = 0; k < n - 1; ++k) {
-      ++*rounds;
-      if (wid * wave_slots < n / 2) {
-        int pp = 0, qq = 0;
-        bool act = slot < n / 2;
-        if (act) {
-          rr_pair(k, slot, n, &pp, &qq);
-          act = pp < nc && qq < nc;
-        }
-        float2 zp[4], zq[4], qa[4], qv[4];
-        float al = 0.f, be = 0.f;
-        double gr = 0.0, gi = 0.0;
+  const int gl = threadIdx.x & (G - 1);
+  float2 zp[4], zq[4], qa[4], qv[4];
+  float al = 0.f, be = 0.f;
+  double gr = 0.0, gi = 0.0;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int i = gl + G * m;
-          const bool ok = act && i < K;
-          zp[m] = ok ? zb[pp * K + i] : cz();
-          zq[m] = ok ? zb[qq * K + i] : cz();
-          qa[m] = ok ? qb[pp * K + i] : cz();
-          qv[m] = ok ? qb[qq * K + i] : cz();
-        }
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          al += cabs2(zp[m]);
-          be += cabs2(zq[m]);
-          gr += (double)zp[m].x * zq[m].x + (double)zp[m].y * zq[m].y;
-          gi += (double)zp[m].x * zq[m].y - (double)zp[m].y * zq[m].x;
-        }
-        al = gsumf<G>(al);
-        be = gsumf<G>(be);
-        gr = gsumd<G>(gr);
-        gi = gsumd<G>(gi);
-        const float mx = fmaxf(al, be);
-        bool rot = act && mx > 0.f;
-        float c = 1.f, s = 0.f;
-        float2 e = make_float2(1.f, 0.f);
-        if (rot) {
-          // same rotation as the LDS kernel: sums scaled by 1/max(alpha, beta)
-          const float sc = __builtin_amdgcn_rcpf(mx);
-          const float alf = al * sc, bef = be * sc;
-          const float grf = (float)gr * sc, gif = (float)gi * sc;
-          const float gg = grf * grf + gif * gif;
-          rot = gg >= 1e-36f && gg > (float)(JACOBI_TOL * JACOBI_TOL) * alf * bef;
-          const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));
-          const float zeta = (bef - alf) * 0.5f * ig;
-          const float az = fabsf(zeta);
-          const float tmag = (az > 1e18f) ? 0.5f * __builtin_amdgcn_rcpf(az)
-                                          : __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(1.f + az * az));
-          const float tt = zeta >= 0.f ? tmag : -tmag;
-          c = __builtin_amdgcn_rsqf(1.f + tt * tt);
-          s = c * tt;
-          e = make_float2(grf * ig, -gif * ig);
-        }
-        if (rot) {
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int i = gl + G * m;
-            if (i >= K) continue;
-            const float2 zq2 = cmul(e, zq[m]), qv2 = cmul(e, qv[m]);
-            zb[pp * K + i] = csub(cscale(zp[m], c), cscale(zq2, s));
-            zb[qq * K + i] = cadd(cscale(zp[m], s), cscale(zq2, c));
-            qb[pp * K + i] = csub(cscale(qa[m], c), cscale(qv2, s));
-            qb[qq * K + i] = cadd(cscale(qa[m], s), cscale(qv2, c));
-          }
-          if (gl == 0) sm.nrot = 1;
-        }
-      }
-      __syncthreads();
-    }
-    const bool done = (sm.nrot == 0);
-    if (sweep == 0) first = !done;
-    __syncthreads();
-    if (done) break;
+  for (int m = 0; m < 4; ++m) {
+    const int i = gl + G * m;
+    const bool ok = act && i < K;
+    zp[m] = ok ? zb[pp * K + i] : cz();
+    zq[m] = ok ? zb[qq * K + i] : cz();
+    qa[m] = ok ? qb[pp * K + i] : cz();
+    qv[m] = ok ? qb[qq * K + i] : cz();
   }
-  return first;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    al += cabs2(zp[m]);
+    be += cabs2(zq[m]);
+    gr += (double)zp[m].x * zq[m].x + (double)zp[m].y * zq[m].y;
+    gi += (double)zp[m].x * zq[m].y - (double)zp[m].y * zq[m].x;
+  }
+  al = gsumf<G>(al);
+  be = gsumf<G>(be);
+  gr = gsumd<G>(gr);
+  gi = gsumd<G>(gi);
+  const float mx = fmaxf(al, be);
+  bool rot = act && mx > 0.f;
+  float c = 1.f, s = 0.f;
+  float2 e = make_float2(1.f, 0.f);
+  if (rot) {
+    // same rotation as the LDS kernel: sums scaled by 1/max(alpha, beta)
+    const float sc = __builtin_amdgcn_rcpf(mx);
+    const float alf = al * sc, bef = be * sc;
+    const float grf = (float)gr * sc, gif = (float)gi * sc;
+    const float gg = grf * grf + gif * gif;
+    rot = gg >= 1e-36f && gg > (float)(JACOBI_TOL * JACOBI_TOL) * alf * bef;
+    const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));
+    const float zeta = (bef - alf) * 0.5f * ig;
+    const float az = fabsf(zeta);
+    const float tmag = (az > 1e18f) ? 0.5f * __builtin_amdgcn_rcpf(az)
+                                    : __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(1.f + az * az));
+    const float tt = zeta >= 0.f ? tmag : -tmag;
+    c = __builtin_amdgcn_rsqf(1.f + tt * tt);
+    s = c * tt;
+    e = make_float2(grf * ig, -gif * ig);
+  }
+  if (rot) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = gl + G * m;
+      if (i >= K) continue;
+      const float2 zq2 = cmul(e, zq[m]), qv2 = cmul(e, qv[m]);
+      zb[pp * K + i] = csub(cscale(zp[m], c), cscale(zq2, s));
+      zb[qq * K + i] = cadd(cscale(zp[m], s), cscale(zq2, c));
+      qb[pp * K + i] = csub(cscale(qa[m], c), cscale(qv2, s));
+      qb[qq * K + i] = cadd(cscale(qa[m], s), cscale(qv2, c));
+    }
+    if (gl == 0) sm.nrot = 1;
+  }
 }
 
-// Job columns <-> global columns: block bp supplies job columns [0, np),
-// block bq [np, np + nq).
-__device__ __forceinline__ int job_col(int c, int np, int bp, int bq, int b) {
-  return (c < np) ? bp * b + c : bq * b + (c - np);
-}
-
+// One sweep of the cyclic (round-robin) ordering over the job columns
+// c0 .. c0+nc-1: nc-1 rounds (nc even, else nc), a barrier after each.
 template <int G>
-__device__ __forceinline__ void jacobi_big(BigShared& sm, float2* Zm, float2* Qm, int K, int d, int* sweeps,
-                           int* rounds) {
-  constexpr int NCMAX = 2048 / G;    // 64 columns (G = 32) or 32 (G = 64)
-  const int tid = threadIdx.x;
-  const int b = NCMAX / 2;
-  const int nblk = (d <= NCMAX) ? 1 : (d + b - 1) / b;
-  if (nblk == 1) {
-    for (int e = tid; e < d * K; e += NTH) { sm.u.jac.z[e] = Zm[e]; sm.u.jac.q[e] = Qm[e]; }
+__device__ __forceinline__ void jacobi_sweep(BigShared& sm, int K, int c0, int nc, int* rounds) {
+  const int wid = threadIdx.x >> 6, slot = threadIdx.x / G;
+  const int n = nc + (nc & 1);
+  for (int k = 0; k < n - 1; ++k) {
+    ++*rounds;
+    if (wid * (64 / G) < n / 2) {
+      int pp = 0, qq = 0;
+      bool act = slot < n / 2;
+      if (act) {
+        rr_pair(k, slot, n, &pp, &qq);
+        act = pp < nc && qq < nc;
+      }
+      jacobi_pair<G>(sm, K, c0 + pp, c0 + qq, act);
+    }
     __syncthreads();
-    jacobi_job<G>(sm, K, d, MAX_SWEEPS, sweeps, rounds);
-    for (int e = tid; e < d * K; e += NTH) { Zm[e] = sm.u.jac.z[e]; Qm[e] = sm.u.jac.q[e]; }
+  }
+}
+
+// One-sided Jacobi SVD of B = Z^H with Q rotated alongside; every pass
+// rotates each column pair once, and the passes stop when one rotates
+// nothing (or after MAX_SWEEPS).
+//   d <= NCMAX: all d columns sit in LDS; a pass is one cyclic sweep.
+//   d > NCMAX: blocks of b = NCMAX/2 columns.  For each block A in turn,
+//     A is loaded, its own pairs take one cyclic sweep, then every later
+//     block B is streamed through: b rounds whose round s pairs column i of
+//     A with column (i + s) mod b of B, so every pair (A_i, B_j) meets once.
+//     A ordering of the cyclic kind, pass by pass like the single-block one.
+template <int G>
+__device__ __forceinline__ void jacobi_big(BigShared& sm, float2* Zm, float2* Qm, int K, int d,
+                                           int* sweeps, int* rounds) {
+  constexpr int NCMAX = 2048 / G;    // 64 columns (G = 32) or 32 (G = 64)
+  const int tid = threadIdx.x, wid = tid >> 6, slot = tid / G;
+  float2* zb = sm.u.jac.z;
+  float2* qb = sm.u.jac.q;
+  if (d <= NCMAX) {
+    for (int e = tid; e < d * K; e += NTH) { zb[e] = Zm[e]; qb[e] = Qm[e]; }
+    for (int pass = 0; pass < MAX_SWEEPS; ++pass) {
+      if (tid == 0) sm.nrot = 0;
+      __syncthreads();
+      ++*sweeps;
+      jacobi_sweep<G>(sm, K, 0, d, rounds);
+      const bool done = sm.nrot == 0;
+      __syncthreads();
+      if (done) break;
+    }
+    for (int e = tid; e < d * K; e += NTH) { Zm[e] = zb[e]; Qm[e] = qb[e]; }
     __syncthreads();
     return;
   }
-  const int nbe = nblk + (nblk & 1);
+  const int b = NCMAX / 2;
+  const int nblk = (d + b - 1) / b;
   for (int pass = 0; pass < MAX_SWEEPS; ++pass) {
-    bool any = false;
-    int inner = 0;
-    for (int k = 0; k < nbe - 1; ++k) {
-      for (int m = 0; m < nbe / 2; ++m) {
-        int bp = 0, bq = 0;
-        rr_pair(k, m, nbe, &bp, &bq);
-        const int np = (bp < nblk) ? min(b, d - bp * b) : 0;
-        const int nq = (bq < nblk) ? min(b, d - bq * b) : 0;
-        const int nc = np + nq;
-        for (int e = tid; e < nc * K; e += NTH) {
-          const int c = e / K, i = e - c * K;
-          const size_t g = (size_t)job_col(c, np, bp, bq, b) * K + i;
-          sm.u.jac.z[e] = Zm[g];
-          sm.u.jac.q[e] = Qm[g];
-        }
+    if (tid == 0) sm.nrot = 0;
+    ++*sweeps;
+    for (int A = 0; A < nblk; ++A) {
+      const int na = min(b, d - A * b);
+      const size_t ga = (size_t)A * b * K;
+      for (int e = tid; e < na * K; e += NTH) { zb[e] = Zm[ga + e]; qb[e] = Qm[ga + e]; }
+      __syncthreads();
+      jacobi_sweep<G>(sm, K, 0, na, rounds);
+      for (int B = A + 1; B < nblk; ++B) {
+        const int nb = min(b, d - B * b);
+        const size_t gb = (size_t)B * b * K;
+        for (int e = tid; e < nb * K; e += NTH) { zb[b * K + e] = Zm[gb + e]; qb[b * K + e] = Qm[gb + e]; }
         __syncthreads();
-        any = jacobi_job<G>(sm, K, nc, MAX_INNER, &inner, rounds) || any;
-        for (int e = tid; e < nc * K; e += NTH) {
-          const int c = e / K, i = e - c * K;
-          const size_t g = (size_t)job_col(c, np, bp, bq, b) * K + i;
-          Zm[g] = sm.u.jac.z[e];
-          Qm[g] = sm.u.jac.q[e];
+        for (int s = 0; s < b; ++s) {
+          ++*rounds;
+          if (wid * (64 / G) < b) {
+            const int qi = (slot + s) % b;
+            const bool act = slot < na && qi < nb;
+            jacobi_pair<G>(sm, K, slot, b + qi, act);
+          }
+          __syncthreads();
         }
+        for (int e = tid; e < nb * K; e += NTH) { Zm[gb + e] = zb[b * K + e]; Qm[gb + e] = qb[b * K + e]; }
         __syncthreads();
       }
+      for (int e = tid; e < na * K; e += NTH) { Zm[ga + e] = zb[e]; Qm[ga + e] = qb[e]; }
+      __syncthreads();
     }
-    ++*sweeps;
-    if (!any) break;
+    const bool done = sm.nrot == 0;
+    __syncthreads();
+    if (done) break;
   }
 }
 
