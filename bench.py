@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c2",
+                    help="c2 (default), c1, c5 (K=256 N=1024 track) or mix (multi-track batch)")
     ap.add_argument("--eta", type=float, default=None)
     ap.add_argument("--policy", choices=["fixed", "warm"], default="fixed")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -89,6 +90,9 @@ def main():
 
     if a.table_v:
         print(json.dumps(table_v(a)), flush=True)
+        return 0
+    if a.config == "mix":
+        print(json.dumps(mix(a, rzf.KINIT_WARM if a.policy == "warm" else rzf.KINIT_FIXED)), flush=True)
         return 0
 
     cfg = wl.CONFIGS[a.config]
@@ -247,7 +251,7 @@ def main():
 
     # batched pass: many independent tracks of the same configuration per launch
     if a.batch_tracks > 0:
-        out["batched"] = batched(a, cfg, eta, policy)
+        out["batched"] = batched(a, [cfg] * a.batch_tracks, eta, policy)
         print(f"[bench] batched pass done", file=sys.stderr, flush=True)
 
     # FP64 CPU oracle on a bounded sample of the same track
@@ -259,40 +263,33 @@ def main():
     return 0
 
 
-def batched(a, cfg, eta, policy):
-    """B independent tracks of the configuration (track ids 0..B-1), updated
-    together: B x S updates of WB-arSVD, then of the full-inversion baseline,
-    each step followed by the batched sum rate.  Snapshots are resident in HBM
-    before timing starts."""
+def batched(a, cfgs, eta, policy):
+    """len(cfgs) independent tracks (track ids 0..B-1; each its own size, SNR
+    and regularisation) updated together: B x S updates of WB-arSVD, then of
+    the full-inversion baseline, each step followed by the batched sum rate.
+    Snapshots are resident in HBM before timing starts."""
     import numpy as np
     import torch
     from paper_2512_16543_amd import rzf, workload as wl
-    B, S, Wu = a.batch_tracks, a.batch_steps, 2
-    K, N = cfg.K, cfg.N
+    B, S, Wu = len(cfgs), a.batch_steps, 2
     dev = torch.device("cuda", 0)
     T = Wu + S + 2          # snapshot 0 inits; 1..Wu warm up; S timed; the last one is profiled
-    Hs = torch.empty(B, T, K, N, dtype=torch.complex64, device=dev)
-    for b in range(B):
-        Hs[b] = torch.from_numpy(wl.make_track(cfg, b).snapshots(0, T).astype(np.complex64)).to(dev)
-    Ws = torch.empty(B, N, K, dtype=torch.complex64, device=dev)
-    rates = torch.empty(B, K, dtype=torch.float32, device=dev)
+    Hs = [torch.from_numpy(wl.make_track(c, b).snapshots(0, T).astype(np.complex64)).to(dev)
+          for b, c in enumerate(cfgs)]
+    Wl = [torch.empty(c.N, c.K, dtype=torch.complex64, device=dev) for c in cfgs]
+    rl = [torch.empty(c.K, dtype=torch.float32, device=dev) for c in cfgs]
     sums = torch.empty(B, dtype=torch.float64, device=dev)
-    per = rzf.track_bytes(K, N)
-    ctx = rzf.Context(0, B * per + (96 << 20))
-
-    def make_tracks():
-        return [ctx.init(Hs[b, 0], cfg.alpha,
-                         rzf.default_params(k_init=cfg.k_init, p=cfg.p, P=cfg.P, seed=cfg.seed,
-                                            track_id=b, reset_period=cfg.reset_period,
-                                            kinit_policy=policy))
-                for b in range(B)]
-
-    trs = make_tracks()
-    Wl = [Ws[b] for b in range(B)]
-    rl = [rates[b] for b in range(B)]
-    upd = [ctx.update_items(trs, [Hs[b, t] for b in range(B)], Wl) for t in range(T)]
-    full = [ctx.full_items([Hs[b, t] for b in range(B)], [cfg.alpha] * B, cfg.P, Wl) for t in range(T)]
-    rt = [ctx.rate_items([Hs[b, t] for b in range(B)], Wl, rl, sums) for t in range(T)]
+    arena = sum(rzf.track_bytes(c.K, c.N) for c in cfgs) + (128 << 20)
+    ctx = rzf.Context(0, arena)
+    trs = [ctx.init(Hs[b][0], c.alpha,
+                    rzf.default_params(k_init=c.k_init, p=c.p, P=c.P, seed=c.seed, track_id=b,
+                                       reset_period=c.reset_period, kinit_policy=policy))
+           for b, c in enumerate(cfgs)]
+    P = cfgs[0].P
+    s2 = [c.sigma2 for c in cfgs]
+    upd = [ctx.update_items(trs, [Hs[b][t] for b in range(B)], Wl) for t in range(T)]
+    full = [ctx.full_items([Hs[b][t] for b in range(B)], [c.alpha for c in cfgs], P, Wl) for t in range(T)]
+    rt = [ctx.rate_items([Hs[b][t] for b in range(B)], Wl, rl, sums, s2) for t in range(T)]
 
     def run(kind, t0, t1):
         torch.cuda.synchronize()
@@ -302,7 +299,7 @@ def batched(a, cfg, eta, policy):
                 ctx.update_batch_raw(upd[t], eta)
             else:
                 ctx.full_batch_raw(full[t])
-            ctx.sum_rate_batch_raw(rt[t], cfg.P, cfg.sigma2)
+            ctx.sum_rate_batch_raw(rt[t], P, s2[0])
         ctx.sync()
         torch.cuda.synchronize()
         return time.perf_counter() - s0
@@ -319,8 +316,8 @@ def batched(a, cfg, eta, policy):
     # dominant kernel of the batched WB pass: HIP events over the next (fresh)
     # snapshot of every track, with each track's info record for its work
     ctx.profile(True)
-    infos = ctx.update_batch(trs, [Hs[b, T - 1] for b in range(B)], Wl, eta, want_info=True)
-    ctx.sum_rate_batch_raw(rt[T - 1], cfg.P, cfg.sigma2)
+    infos = ctx.update_batch(trs, [Hs[b][T - 1] for b in range(B)], Wl, eta, want_info=True)
+    ctx.sum_rate_batch_raw(rt[T - 1], P, s2[0])
     prof = ctx.profile_read()
     ctx.profile(False)
     ctx.sync()
@@ -328,11 +325,11 @@ def batched(a, cfg, eta, policy):
     dom = max(prof, key=lambda k: prof[k][1])
     dur = prof[dom][1] / prof[dom][0] * 1e-3
     if dom == "arsvd_wb":
-        fl = sum(arsvd_flops(K, i.as_dict(), cfg.k_init, cfg.p) for i in infos if i.path != 4)
+        fl = sum(arsvd_flops(c.K, i.as_dict(), c.k_init, c.p) for c, i in zip(cfgs, infos) if i.path != 4)
     elif dom == "gram":
-        fl = B * 12.0 * K * K * N
+        fl = sum(12.0 * c.K * c.K * c.N for c in cfgs)
     elif dom == "precoder":
-        fl = B * 8.0 * K * K * N
+        fl = sum(8.0 * c.K * c.K * c.N for c in cfgs)
     else:
         fl = 0.0
     res["roofline"] = {"kernel": dom, "bound": "mfma", "achieved": fl / dur / 1e12,
@@ -342,6 +339,32 @@ def batched(a, cfg, eta, policy):
                        "paths": {str(p): sum(1 for i in infos if i.path == p) for p in range(5)}}
     ctx.close()
     return res
+
+
+def mix(a, policy):
+    """Multi-track mix: B tracks, K uniform on 16..128, N in {64, 256, 1024},
+    SNR uniform on 0..20 dB, all updated by one batched call per step."""
+    import numpy as np
+    from paper_2512_16543_amd import workload as wl
+    eta = 0.999 if a.eta is None else a.eta
+    cfgs = wl.mix_configs(a.batch_tracks, seed=3, eta=eta)
+    res = batched(a, cfgs, eta, policy)
+    Ks = np.array([c.K for c in cfgs])
+    Ns = np.array([c.N for c in cfgs])
+    out = {
+        "metric": "RZF precoder updates/s, multi-track mix (K 16..128, N 64/256/1024), WB-arSVD vs full inverse",
+        "value": res["value"], "unit": "updates/s", "n_gpus": 1, "steps": res["steps"],
+        "warmup": 2, "ms_per_step": res["ms_per_batched_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic (seeded LEO channel tracks)",
+        "config": {"workload": (f"mix: {len(cfgs)} tracks, K uniform 16..128 (mean {Ks.mean():.1f}, "
+                                f"{int((Ks > 64).sum())} above 64), N in {{64, 256, 1024}} "
+                                f"(mean {Ns.mean():.0f}), SNR 0..20 dB, eta={eta}, FP64 reset every 100 steps; "
+                                f"step = one batched update of every track + batched sum rate"),
+                   "tracks": len(cfgs), "eta": eta},
+    }
+    out.update({k: v for k, v in res.items() if k not in ("value", "unit", "steps")})
+    return out
 
 
 def table_v(a):

@@ -74,8 +74,9 @@ typedef struct {
   int i_max;            /* Alg. 1 iteration cap; 0 = smallest I with
                            k_init * 2^(I-1) + p >= K                               */
   double switch_ratio;  /* Alg. 2: Woodbury when k_est <= switch_ratio * K (0.5);
-                           ranks above K/2 always take the direct inversion
-                           (the Woodbury workspace holds K/2 columns)             */
+                           ranks above max(32, K/2) always take the direct
+                           inversion (the end of the Woodbury workspace; only a
+                           ratio above 0.5 reaches it)                            */
   int reset_period;     /* re-invert A' in FP64 once this many steps have passed
                            since the last FP64 inversion (init or reset), skipping
                            Alg. 1 on that step; 0 = never                         */
@@ -194,6 +195,8 @@ typedef struct {
   int ldw;
   float* rates;            /* device, K floats, or NULL            */
   double* sum_rate;        /* device, one double, or NULL          */
+  double sigma2;           /* this item's noise power; a negative value
+                              takes the sigma2 of the call           */
 } rzf_rate_item;
 
 /* rzf_sum_rate for n independent (H, W) pairs, results left in device

@@ -208,6 +208,13 @@ def sum_rate(H: np.ndarray, W: np.ndarray, P: float, sigma2: float):
     return rates, float(np.sum(rates))
 
 
+def wb_rank_cap(K: int) -> int:
+    """Largest rank the Woodbury branch takes: max(32, floor(K/2)).  Alg. 2
+    switches at k_est/K <= 0.5, which this never binds; it only limits a
+    switch ratio above 0.5, where the library's Woodbury workspace ends."""
+    return max(32, K // 2)
+
+
 @dataclasses.dataclass
 class TrackParams:
     alpha: float
@@ -280,7 +287,7 @@ class OracleTrack:
             info = UpdateInfo(res.r, res.iters, PATH_NOOP, energy, res.captured, res.d)
             if res.r == 0:
                 info.path = PATH_NOOP
-            elif res.r <= prm.switch_ratio * self.K:   # Alg. 2: k_est/K <= 0.5
+            elif res.r <= prm.switch_ratio * self.K and res.r <= wb_rank_cap(self.K):   # Alg. 2
                 new, singular = woodbury(self.Ainv, res.U, res.s, res.V)
                 if singular:
                     self.Ainv = direct_inverse(A_new)

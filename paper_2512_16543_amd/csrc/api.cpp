@@ -689,19 +689,25 @@ rzf_status rzf_sum_rate_batch(rzf_ctx* c, int n, const rzf_rate_item* items, dou
   if (!c || !items || n < 1 || n > RZF_BATCH_MAX) return RZF_E_INVALID;
   if (!std::isfinite(P) || P <= 0.0 || !std::isfinite(sigma2) || sigma2 < 0.0) return RZF_E_INVALID;
   int maxK = 1;
+  size_t want = 0;   // per-item partial sums, packed
   for (int i = 0; i < n; ++i) {
     const rzf_rate_item& it = items[i];
     if (!it.H || !it.W) return RZF_E_INVALID;
     if (it.K < 1 || it.K > RZF_KMAX || it.N < 1 || it.N > RZF_NMAX || it.ldh < it.N || it.ldw < it.K)
       return RZF_E_SHAPE;
+    if (std::isnan(it.sigma2)) return RZF_E_INVALID;
     maxK = std::max(maxK, it.K);
+    want += align_up(sizeof(double) * sum_rate_scratch_doubles(it.K));
   }
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
   hipStream_t s = c->stream;
-  const size_t per = align_up(sizeof(double) * sum_rate_scratch_doubles(RZF_KMAX));
-  const size_t want = per * RZF_BATCH_MAX;
-  if (!c->d_batch_part) {
+  if (want > c->batch_part_bytes) {
+    // grow: the old region may still be read by queued work
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (c->d_batch_part) arena_free(c, c->batch_part_off, c->batch_part_bytes);
+    c->d_batch_part = nullptr;
+    c->batch_part_bytes = 0;
     size_t off = 0;
     if (!arena_alloc(c, want, &off)) return RZF_E_NOMEM;
     c->batch_part_off = off;
@@ -709,11 +715,14 @@ rzf_status rzf_sum_rate_batch(rzf_ctx* c, int n, const rzf_rate_item* items, dou
     c->d_batch_part = reinterpret_cast<double*>(c->arena + off);
   }
   std::vector<RateJob> rj(n);
+  size_t off = 0;
   for (int i = 0; i < n; ++i) {
     const rzf_rate_item& it = items[i];
     rj[i] = RateJob{reinterpret_cast<const float2*>(it.H), reinterpret_cast<const float2*>(it.W),
-                    reinterpret_cast<double*>(reinterpret_cast<char*>(c->d_batch_part) + per * i),
-                    it.rates, it.sum_rate, it.K, it.N, it.ldh, it.ldw, P, sigma2};
+                    reinterpret_cast<double*>(reinterpret_cast<char*>(c->d_batch_part) + off),
+                    it.rates, it.sum_rate, it.K, it.N, it.ldh, it.ldw, P,
+                    it.sigma2 >= 0.0 ? it.sigma2 : sigma2};
+    off += align_up(sizeof(double) * sum_rate_scratch_doubles(it.K));
   }
   const int slot = stage_acquire(c);
   if (slot < 0) return RZF_E_DEVICE;

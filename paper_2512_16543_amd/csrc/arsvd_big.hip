@@ -720,7 +720,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
   }
 
   const int rmax = (int)floor(td->switch_ratio * (double)K);
-  bool use_wb = r <= rmax && r <= K / 2;
+  bool use_wb = r <= rmax && r <= K / 2;   // K / 2 = max(32, K / 2) for K > 64
   int path = use_wb ? RZF_PATH_WB : RZF_PATH_FULL_RANK;
   float2* Ainv = td->Ainv;
   if (use_wb) {

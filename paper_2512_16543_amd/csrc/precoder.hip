@@ -61,6 +61,10 @@ __global__ __launch_bounds__(256) void k_precoder(PrecJob one, const PrecJob* ma
   if (threadIdx.x == 0) wpart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// Blocks stride over the N x K entries of W (SCALE_BLOCKS per track at most),
+// so a batch of small and large tracks launches few empty blocks.
+constexpr int SCALE_BLOCKS = 32;
+
 template <bool MANY>
 __global__ __launch_bounds__(256) void k_scale(ScaleJob one, const ScaleJob* many) {
   const ScaleJob& jb = job_of<MANY>(one, many);
@@ -68,15 +72,16 @@ __global__ __launch_bounds__(256) void k_scale(ScaleJob one, const ScaleJob* man
   float2* __restrict__ W = jb.W;
   const double* __restrict__ wpart = jb.wpart;
   const double P = jb.P;
-  if ((int)(blockIdx.x * blockDim.x) >= N * K) return;
+  const int NK = N * K;
+  if ((int)(blockIdx.x * blockDim.x) >= NK) return;
   double tot = 0.0;
   for (int b = 0; b < nparts; ++b) tot += wpart[b];
   const float s = (tot > 0.0) ? (float)sqrt(P / tot) : 0.f;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= N * K) return;
-  const int n = e / K, k = e - n * K;
-  float2* w = W + (size_t)n * ldw + k;
-  *w = cscale(*w, s);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NK; e += gridDim.x * blockDim.x) {
+    const int n = e / K, k = e - n * K;
+    float2* w = W + (size_t)n * ldw + k;
+    *w = cscale(*w, s);
+  }
 }
 
 }  // namespace
@@ -90,7 +95,8 @@ void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, h
 }
 
 void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, hipStream_t s) {
-  const dim3 grid((maxNK + 255) / 256, many ? n : 1);
+  const int blocks = (maxNK + 255) / 256 < SCALE_BLOCKS ? (maxNK + 255) / 256 : SCALE_BLOCKS;
+  const dim3 grid(blocks, many ? n : 1);
   if (many) k_scale<true><<<grid, 256, 0, s>>>(one, many);
   else k_scale<false><<<grid, 256, 0, s>>>(one, many);
 }

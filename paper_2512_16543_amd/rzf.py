@@ -56,7 +56,7 @@ class FullItem(ctypes.Structure):
 class RateItem(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int), ("N", ctypes.c_int), ("H", ctypes.c_void_p), ("ldh", ctypes.c_int),
                 ("W", ctypes.c_void_p), ("ldw", ctypes.c_int), ("rates", ctypes.c_void_p),
-                ("sum_rate", ctypes.c_void_p)]
+                ("sum_rate", ctypes.c_void_p), ("sigma2", ctypes.c_double)]
 
 
 BATCH_MAX = 2048
@@ -292,7 +292,8 @@ class Context:
         _check(lib().rzf_full_batch(self.h, len(items), items), "rzf_full_batch")
 
     @staticmethod
-    def rate_items(Hs, Ws, rates=None, sums=None):
+    def rate_items(Hs, Ws, rates=None, sums=None, sigma2s=None):
+        """sigma2s: per-item noise powers (None: every item takes the call's)."""
         n = len(Hs)
         arr = (RateItem * n)()
         for i in range(n):
@@ -303,6 +304,7 @@ class Context:
             it.K, it.N, it.H, it.ldh, it.W, it.ldw = K, N, hp, ldh, wp, ldw
             it.rates = _dev_ptr(rates[i]) if rates is not None else None
             it.sum_rate = (_dev_ptr(sums) + 8 * i) if sums is not None else None
+            it.sigma2 = float(sigma2s[i]) if sigma2s is not None else -1.0
         return arr
 
     def sum_rate_batch_raw(self, items, P: float, sigma2: float):
@@ -321,19 +323,12 @@ class Context:
             it.alpha, it.P, it.W, it.ldw = float(alphas[i]), float(P), wp, ldw
         _check(lib().rzf_full_batch(self.h, n, arr), "rzf_full_batch")
 
-    def sum_rate_batch(self, Hs, Ws, P: float, sigma2: float, rates=None, sums=None):
-        """rates: list of float32 device tensors (or None); sums: float64 device tensor of n."""
-        n = len(Hs)
-        arr = (RateItem * n)()
-        for i in range(n):
-            hp, ldh = _mat_args(Hs[i])
-            wp, ldw = _mat_args(Ws[i])
-            K, N = Hs[i].shape
-            it = arr[i]
-            it.K, it.N, it.H, it.ldh, it.W, it.ldw = K, N, hp, ldh, wp, ldw
-            it.rates = _dev_ptr(rates[i]) if rates is not None else None
-            it.sum_rate = (_dev_ptr(sums) + 8 * i) if sums is not None else None
-        _check(lib().rzf_sum_rate_batch(self.h, n, arr, float(P), float(sigma2)), "rzf_sum_rate_batch")
+    def sum_rate_batch(self, Hs, Ws, P: float, sigma2: float, rates=None, sums=None, sigma2s=None):
+        """rates: list of float32 device tensors (or None); sums: float64 device
+        tensor of n; sigma2s: per-item noise powers (None: all take sigma2)."""
+        arr = self.rate_items(Hs, Ws, rates, sums, sigma2s)
+        _check(lib().rzf_sum_rate_batch(self.h, len(Hs), arr, float(P), float(sigma2)),
+               "rzf_sum_rate_batch")
 
     def profile(self, enable: bool):
         _check(lib().rzf_profile(self.h, 1 if enable else 0), "rzf_profile")

@@ -89,6 +89,28 @@ def with_overrides(cfg: TrackConfig, **kw) -> TrackConfig:
     return dataclasses.replace(cfg, **kw)
 
 
+# Multi-track mix: every track draws its own size and SNR.  The array side
+# (8, 16 or 32 elements, N = 64, 256 or 1024) fixes the user-disk radius
+# (50, 100 or 200 km); K is uniform on 16..128, the SNR uniform on 0..20 dB;
+# K-factor 10 dB, 10 ms between snapshots, 200 steps, FP64 drift reset every
+# 100 steps.
+MIX_SIDES = (8, 16, 32)
+MIX_RADIUS_M = {8: 50e3, 16: 100e3, 32: 200e3}
+
+
+def mix_configs(n: int, seed: int = 3, k_range=(16, 128), eta: float = 0.999) -> list:
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 777]))
+    out = []
+    for i in range(n):
+        nx = int(MIX_SIDES[rng.integers(0, len(MIX_SIDES))])
+        K = int(rng.integers(k_range[0], k_range[1] + 1))
+        snr = float(rng.uniform(0.0, 20.0))
+        out.append(TrackConfig(f"mix{i}", seed=seed, nx=nx, K=K, height_m=550e3,
+                               radius_m=MIX_RADIUS_M[nx], dt_s=0.01, steps=200, kr_db=10.0,
+                               snr_db=snr, eta=eta, p=5, k_init=2, reset_period=100))
+    return out
+
+
 class Track:
     """Static geometry of one track; `snapshot(t)` returns H(t) (K x N)."""
 

@@ -115,6 +115,14 @@ def test_full_and_sum_rate_batch_equal_single(ctx):
     for i in range(len(Hs)):
         assert torch.equal(rates_s[i], rates_b[i])
         assert sums_b[i].item() == sums_s[i]
+    # per-item noise powers: each item as if evaluated alone with its own
+    s2 = [0.02 * (i + 1) for i in range(len(Hs))]
+    sums_i = [ctx.sum_rate(d, w, 1.5, v, r) for d, w, r, v in zip(dev, Ws, rates_s, s2)]
+    ctx.sum_rate_batch(dev, Wb, 1.5, 0.1, rates_b, sums_b, sigma2s=s2)
+    ctx.sync()
+    for i in range(len(Hs)):
+        assert torch.equal(rates_s[i], rates_b[i])
+        assert sums_b[i].item() == sums_i[i]
 
 
 def test_batch_rejects_bad_items(ctx):

@@ -509,3 +509,9 @@ def test_track_warm_start_policy():
     # warm start begins at k0 = previous rank, so the first d is r_prev + p
     assert i2.iters <= i1.iters
     assert i2.d >= min(i1.r + prm.p, cfg.K) or i2.iters > 1
+
+
+def test_woodbury_rank_cap_reading():
+    # Alg. 2's switch at 0.5 K never reaches the cap; only larger ratios do
+    assert [orz.wb_rank_cap(K) for K in (1, 16, 64, 65, 100, 256)] == [32, 32, 32, 32, 50, 128]
+    assert all(math.floor(0.5 * K) <= orz.wb_rank_cap(K) for K in range(1, 257))   # integer ranks
