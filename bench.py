@@ -50,6 +50,14 @@ def parse():
     ap.add_argument("--table-v", action="store_true",
                     help="run the Table V / Fig. 2 analog instead (prints its own JSON line)")
     ap.add_argument("--passes", type=int, default=16, help="Monte Carlo passes of --table-v")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the serving experiment instead (prints its own JSON line)")
+    ap.add_argument("--serve-tracks", type=int, default=2048)
+    ap.add_argument("--serve-ring", type=int, default=8, help="device-resident snapshots per track")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[1e4, 3e4, 1e5])
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="trace length per rate")
+    ap.add_argument("--serve-batch", type=int, default=1024)
+    ap.add_argument("--serve-wait-us", type=float, default=1000.0)
     return ap.parse_args()
 
 
@@ -90,6 +98,9 @@ def main():
 
     if a.table_v:
         print(json.dumps(table_v(a)), flush=True)
+        return 0
+    if a.serve:
+        print(json.dumps(serve(a)), flush=True)
         return 0
     if a.config == "mix":
         print(json.dumps(mix(a, rzf.KINIT_WARM if a.policy == "warm" else rzf.KINIT_FIXED)), flush=True)
@@ -365,6 +376,84 @@ def mix(a, policy):
     }
     out.update({k: v for k, v in res.items() if k not in ("value", "unit", "steps")})
     return out
+
+
+def serve(a):
+    """Serving loop: resident tracks of the multi-track size mix receive update
+    requests as Poisson arrivals (aggregate rate lambda, each request for a
+    uniformly drawn track), replayed on time by the library's request server.
+    Each track cycles through a device-resident ring of consecutive snapshots
+    (forward, then back).  Per rate: latency percentiles (completion minus
+    submission, server clock) and achieved throughput of the WB-arSVD server,
+    then of the full-inversion server on the same trace."""
+    import numpy as np
+    import torch
+    from paper_2512_16543_amd import rzf, workload as wl
+    B, R = a.serve_tracks, a.serve_ring
+    cfgs = wl.mix_configs(B, seed=4, eta=0.999 if a.eta is None else a.eta)
+    eta = cfgs[0].eta
+    dev = torch.device("cuda", 0)
+    Hs = [torch.from_numpy(wl.make_track(c, b).snapshots(0, R).astype(np.complex64)).to(dev)
+          for b, c in enumerate(cfgs)]
+    Ws = [torch.empty(c.N, c.K, dtype=torch.complex64, device=dev) for c in cfgs]
+    ctx = rzf.Context(0, sum(rzf.track_bytes(c.K, c.N) for c in cfgs) + (256 << 20))
+    trs = [ctx.init(Hs[b][0], c.alpha,
+                    rzf.default_params(k_init=c.k_init, p=c.p, P=c.P, seed=c.seed, track_id=b,
+                                       reset_period=c.reset_period))
+           for b, c in enumerate(cfgs)]
+    print(f"[serve] {B} tracks resident", file=sys.stderr, flush=True)
+    period = 2 * (R - 1)
+    step = np.zeros(B, dtype=np.int64)
+
+    def ring(k):       # snapshot index of a track's k-th update (k >= 1): 1..R-1, R-2..0, 1..
+        m = k % period
+        return m if m <= R - 1 else period - m
+
+    rows = []
+    rng = np.random.default_rng(np.random.SeedSequence([4, 4242]))
+    for lam in a.serve_rates:
+        n = int(rng.poisson(lam * a.serve_seconds))
+        t_arr = np.cumsum(rng.exponential(1e6 / lam, n))
+        who = rng.integers(0, B, n)
+        idx = np.empty(n, dtype=np.int64)
+        for j in range(n):
+            step[who[j]] += 1
+            idx[j] = ring(int(step[who[j]]))
+        reqs = rzf.Server.requests([trs[b] for b in who], [Hs[b][k] for b, k in zip(who, idx)],
+                                   [Ws[b] for b in who], range(n), t_arr)
+        row = {"rate_per_s": lam, "requests": n, "seconds": a.serve_seconds}
+        for mode, name in ((rzf.SERVE_UPDATE, "wb"), (rzf.SERVE_FULL, "full")):
+            srv = rzf.Server(ctx, rzf.server_params(mode=mode, tol=eta, max_batch=a.serve_batch,
+                                                    max_wait_us=a.serve_wait_us))
+            srv.replay(reqs)
+            srv.drain()
+            done = []
+            while True:
+                got = srv.poll(65536)
+                if not got:
+                    break
+                done += got
+            srv.close()
+            ctx.sync()
+            lat = np.array([c.t_done_us - c.t_submit_us for c in done]) * 1e-3
+            t_first = min(c.t_submit_us for c in done)
+            t_last = max(c.t_done_us for c in done)
+            launches = len({c.t_launch_us for c in done})
+            row[name] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                         "p999_ms": float(np.percentile(lat, 99.9)), "mean_ms": float(lat.mean()),
+                         "achieved_per_s": len(done) / ((t_last - t_first) * 1e-6),
+                         "mean_batch": len(done) / max(launches, 1),
+                         "errors": int(sum(c.status != 0 for c in done))}
+            print(f"[serve] rate {lam:g}/s {name}: p50 {row[name]['p50_ms']:.2f} ms, "
+                  f"p99 {row[name]['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+        rows.append(row)
+    Ks = np.array([c.K for c in cfgs])
+    ctx.close()
+    return {"experiment": "serving", "tracks": B, "snapshot_ring": R, "eta": eta,
+            "k_mean": float(Ks.mean()), "k_above_64": int((Ks > 64).sum()),
+            "max_batch": a.serve_batch, "max_wait_us": a.serve_wait_us,
+            "latency": "completion minus submission on the server clock; submission is on the arrival time",
+            "rows": rows}
 
 
 def table_v(a):

@@ -217,6 +217,72 @@ rzf_status rzf_track_query(rzf_track* tr, int* K, int* N, int* t, int* since_res
 /* Release the track's arena space (after its queued work has finished). */
 rzf_status rzf_track_destroy(rzf_track* tr);
 
+/* Checkpoint / resume of a track (the state Alg. 2 carries between
+ * snapshots: A^-1 and the previous snapshot, plus the step counters and the
+ * previous k_est).  rzf_track_export with buf == NULL stores the blob size in
+ * *bytes; otherwise it synchronises the context's stream and writes the blob
+ * (host memory, *bytes >= that size, else RZF_E_INVALID with the size in
+ * *bytes).  rzf_track_import creates a new track in `ctx` from a blob written
+ * by this library version (RZF_E_INVALID for a foreign or truncated blob,
+ * RZF_E_NOMEM if the arena is full); its next rzf_update gives the same result
+ * as the exported track's would.  Both are synchronous. */
+rzf_status rzf_track_export(rzf_track* tr, void* buf, size_t* bytes);
+rzf_status rzf_track_import(rzf_ctx* ctx, const void* buf, size_t bytes, rzf_track** out);
+
+/* ------------------------------------------------------ request server
+ * Serving loop over resident tracks: requests (track, H_t, W) are submitted
+ * from any thread; a dispatcher thread gathers pending requests into
+ * batched launches on the context's stream, at most one request per track
+ * per launch and in submission order per track, launching when max_batch
+ * requests are pending or the oldest has waited max_wait_us; a completion
+ * thread records each request when its launch has finished.
+ *   RZF_SERVE_UPDATE: each request is one rzf_update of its track (Alg. 2).
+ *   RZF_SERVE_FULL:   each request computes the full-inversion RZF of H_t
+ *                     with the track's alpha and P; the track is not changed
+ *                     (the conventional baseline on the same requests).
+ * The caller keeps H_t and W alive until the request completes.  Device-side
+ * errors are reported by the next rzf_sync as for other calls. */
+typedef struct rzf_server rzf_server;
+typedef enum { RZF_SERVE_UPDATE = 0, RZF_SERVE_FULL = 1 } rzf_serve_mode;
+typedef struct {
+  int max_batch;        /* requests per launch, 1..RZF_BATCH_MAX (512)            */
+  double max_wait_us;   /* longest wait of the oldest request for a fuller batch  */
+  double tol;           /* eta of every update (0.999)                            */
+  int mode;             /* rzf_serve_mode                                         */
+  int max_inflight;     /* launches queued on the stream at once, 1..8 (2)        */
+} rzf_server_params;
+typedef struct {
+  uint64_t tag;         /* as submitted                                           */
+  int status;           /* rzf_status of the launch                               */
+  int pad;
+  rzf_update_info info; /* the update's outcome (RZF_SERVE_UPDATE)                */
+  double t_submit_us, t_launch_us, t_done_us;   /* server clock                   */
+} rzf_completion;
+typedef struct {
+  rzf_track* track;
+  const rzf_c32* H;     /* device, K x N, leading dimension ldh                   */
+  int ldh;
+  rzf_c32* W;           /* device, N x K, leading dimension ldw                   */
+  int ldw;
+  uint64_t tag;
+  double t_arrival_us;  /* offset from the start of rzf_server_replay, ascending  */
+} rzf_serve_request;
+
+rzf_status rzf_server_params_default(rzf_server_params* p);
+rzf_status rzf_server_create(rzf_ctx* ctx, const rzf_server_params* p, rzf_server** out);
+rzf_status rzf_server_submit(rzf_server* s, rzf_track* tr, const rzf_c32* H_t, int ldh, rzf_c32* W,
+                             int ldw, uint64_t tag);
+/* Submit n requests, each at its arrival time (blocks until the last one is
+ * submitted); completions are collected with rzf_server_poll. */
+rzf_status rzf_server_replay(rzf_server* s, int n, const rzf_serve_request* reqs);
+/* Move up to `max` finished requests into out[], oldest first. */
+rzf_status rzf_server_poll(rzf_server* s, rzf_completion* out, int max, int* n_out);
+/* Block until every submitted request has completed. */
+rzf_status rzf_server_drain(rzf_server* s);
+double rzf_server_now_us(rzf_server* s);
+/* Dispatch what is pending, wait for it, stop the threads, free the server. */
+rzf_status rzf_server_destroy(rzf_server* s);
+
 /* The Gaussian sketch Omega of Alg. 1 for (seed, track_id, step t, iteration
  * it), K x d, written column-major (entry (i, j) at Omega[j*K + i]) as FP32
  * complex, and the two Philox4x64-10 words behind each entry to words

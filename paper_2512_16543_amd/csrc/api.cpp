@@ -12,87 +12,16 @@
 #include <set>
 #include <vector>
 
-#include "rzf.h"
-#include "rzf_internal.h"
+#include "runtime.h"
+
+using namespace rzfrt;
 
 namespace {
 
-constexpr size_t ALIGN = 256;
-constexpr int PIN_CHUNK = 4096;   // info records per pinned chunk
-constexpr int NSTAGE = 4;
-constexpr size_t STAGE_BYTES = 1 << 20;   // per slot
-
-size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
-
-struct Pending {
-  DevInfo* slot;
-  rzf_update_info* dst;
-};
-
-struct ProfRec {
-  int kernel;
-  hipEvent_t a, b;
-};
-
 const char* const KERNEL_NAMES[] = {"gram", "gram64", "inv64", "inv32", "arsvd_wb",
                                     "precoder", "scale", "sum_rate"};
-enum { KN_GRAM, KN_GRAM64, KN_INV64, KN_INV32, KN_ARSVD, KN_PRECODER, KN_SCALE, KN_SUMRATE,
-       KN_COUNT };
 
 }  // namespace
-
-struct rzf_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  char* arena = nullptr;
-  size_t arena_bytes = 0;
-  bool own_arena = false;
-  std::map<size_t, size_t> free_blocks;   // offset -> size
-  // fixed scratch at the front of the arena
-  int* d_err = nullptr;
-  float2* d_fullA = nullptr;
-  float2* d_fullAinv = nullptr;
-  double* d_fullwpart = nullptr;
-  double* d_sum = nullptr;
-  double* d_srpart = nullptr;
-  // pinned host staging
-  double* h_sum = nullptr;
-  int* h_err = nullptr;
-  std::vector<DevInfo*> pin_chunks;
-  size_t pin_used = 0;
-  std::vector<Pending> pending;
-  std::set<rzf_track*> tracks;
-  std::mutex mu;
-  // batched calls: ring of pinned host / device staging slots for job arrays
-  char* h_stage = nullptr;
-  char* d_stage = nullptr;
-  hipEvent_t stage_ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool stage_used[4] = {false, false, false, false};
-  int stage_next = 0;
-  double* d_batch_part = nullptr;       // sum-rate scratch of batched calls
-  size_t batch_part_off = 0, batch_part_bytes = 0;
-  char* d_batch_full = nullptr;         // Gram / partial-norm scratch of rzf_full_batch
-  size_t batch_full_off = 0, batch_full_bytes = 0;
-  // event timing
-  bool prof_on = false;
-  std::vector<ProfRec> prof;
-  std::vector<hipEvent_t> ev_pool;
-  int prof_count[KN_COUNT] = {};
-  double prof_ms[KN_COUNT] = {};
-};
-
-struct rzf_track {
-  rzf_ctx* ctx = nullptr;
-  int K = 0, N = 0;
-  rzf_params prm{};
-  double alpha = 0.0;
-  size_t off = 0, bytes = 0;
-  TrackDesc* d_desc = nullptr;
-  TrackDesc h_desc{};
-  int t = 0;
-  int since_reset = 0;
-  int i_max = 0;
-};
 
 namespace {
 
@@ -258,6 +187,62 @@ rzf_status sync_and_collect(rzf_ctx* c) {
 
 }  // namespace
 
+namespace {
+
+// Arena space and host descriptor of a new track (no device work; the
+// caller fills the state and uploads the descriptor).  nullptr if the arena
+// or the host heap is full.
+rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alpha) {
+  const Layout L = track_layout(K, N);
+  size_t off = 0;
+  if (!arena_alloc(c, L.total, &off)) return nullptr;
+  rzf_track* t = new (std::nothrow) rzf_track();
+  if (!t) { arena_free(c, off, L.total); return nullptr; }
+  char* base = c->arena + off;
+  t->ctx = c; t->K = K; t->N = N; t->prm = prm; t->alpha = alpha; t->off = off; t->bytes = L.total;
+  t->i_max = prm.i_max > 0 ? prm.i_max : default_imax(K, prm.k_init, prm.p);
+  TrackDesc& d = t->h_desc;
+  std::memset(&d, 0, sizeof(d));
+  d.K = K; d.N = N; d.alpha = alpha; d.P = prm.P; d.switch_ratio = prm.switch_ratio;
+  d.k_init = prm.k_init; d.p = prm.p; d.i_max = t->i_max; d.kinit_policy = prm.kinit_policy;
+  d.seed = prm.seed; d.track_id = prm.track_id;
+  d.Ainv = reinterpret_cast<float2*>(base + L.ainv);
+  d.Hprev = reinterpret_cast<float2*>(base + L.hprev);
+  d.Anew = reinterpret_cast<float2*>(base + L.anew);
+  d.dA = reinterpret_cast<float2*>(base + L.da);
+  d.A64 = reinterpret_cast<double2*>(base + L.a64);
+  d.wpart = reinterpret_cast<double*>(base + L.wpart);
+  if (K > KS) {
+    d.Ym = reinterpret_cast<float2*>(base + L.ym);
+    d.Qm = reinterpret_cast<float2*>(base + L.qm);
+    d.Zm = reinterpret_cast<float2*>(base + L.zm);
+    d.Pm = reinterpret_cast<float2*>(base + L.pm);
+    d.Aug = reinterpret_cast<double2*>(base + L.aug);
+  }
+  d.last_r = 0;
+  t->d_desc = reinterpret_cast<TrackDesc*>(base + L.desc);
+  return t;
+}
+
+// Checkpoint blob of one track: this header, then A^-1 (K x K) and H_prev
+// (K x N), complex64 row-major.
+struct TrackBlob {
+  char magic[8];
+  uint32_t version, header_bytes;
+  int32_t K, N;
+  rzf_params prm;
+  double alpha;
+  int32_t step, since_reset, last_r, pad;
+};
+const char BLOB_MAGIC[8] = {'R', 'Z', 'F', 'T', 'R', 'A', 'C', 'K'};
+constexpr uint32_t BLOB_VERSION = 1;
+
+size_t blob_bytes(int K, int N) {
+  return sizeof(TrackBlob) + sizeof(float2) * ((size_t)K * K + (size_t)K * N);
+}
+
+}  // namespace
+
 static_assert(sizeof(DevInfo) == sizeof(rzf_update_info), "info layout");
 
 extern "C" {
@@ -388,34 +373,9 @@ rzf_status rzf_init(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   rzf_status st0 = sync_and_collect(c);
   if (st0 == RZF_E_DEVICE) return st0;
 
-  const Layout L = track_layout(K, N);
-  size_t off = 0;
-  if (!arena_alloc(c, L.total, &off)) return RZF_E_NOMEM;
-  rzf_track* t = new (std::nothrow) rzf_track();
-  if (!t) { arena_free(c, off, L.total); return RZF_E_NOMEM; }
-  char* base = c->arena + off;
-  t->ctx = c; t->K = K; t->N = N; t->prm = prm; t->alpha = alpha; t->off = off; t->bytes = L.total;
-  t->i_max = prm.i_max > 0 ? prm.i_max : default_imax(K, prm.k_init, prm.p);
-  TrackDesc& d = t->h_desc;
-  std::memset(&d, 0, sizeof(d));
-  d.K = K; d.N = N; d.alpha = alpha; d.P = prm.P; d.switch_ratio = prm.switch_ratio;
-  d.k_init = prm.k_init; d.p = prm.p; d.i_max = t->i_max; d.kinit_policy = prm.kinit_policy;
-  d.seed = prm.seed; d.track_id = prm.track_id;
-  d.Ainv = reinterpret_cast<float2*>(base + L.ainv);
-  d.Hprev = reinterpret_cast<float2*>(base + L.hprev);
-  d.Anew = reinterpret_cast<float2*>(base + L.anew);
-  d.dA = reinterpret_cast<float2*>(base + L.da);
-  d.A64 = reinterpret_cast<double2*>(base + L.a64);
-  d.wpart = reinterpret_cast<double*>(base + L.wpart);
-  if (K > KS) {
-    d.Ym = reinterpret_cast<float2*>(base + L.ym);
-    d.Qm = reinterpret_cast<float2*>(base + L.qm);
-    d.Zm = reinterpret_cast<float2*>(base + L.zm);
-    d.Pm = reinterpret_cast<float2*>(base + L.pm);
-    d.Aug = reinterpret_cast<double2*>(base + L.aug);
-  }
-  d.last_r = 0;
-  t->d_desc = reinterpret_cast<TrackDesc*>(base + L.desc);
+  rzf_track* t = track_new(c, K, N, prm, alpha);
+  if (!t) return RZF_E_NOMEM;
+  const TrackDesc& d = t->h_desc;
   hipStream_t s = c->stream;
   const float2* Hf = reinterpret_cast<const float2*>(H);
   bool ok = hipMemcpyAsync(t->d_desc, &d, sizeof(d), hipMemcpyHostToDevice, s) == hipSuccess;
@@ -430,7 +390,7 @@ rzf_status rzf_init(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   }
   rzf_status st = ok ? sync_and_collect(c) : RZF_E_DEVICE;
   if (st != RZF_OK) {
-    arena_free(c, off, L.total);
+    arena_free(c, t->off, t->bytes);
     delete t;
     return st;
   }
@@ -516,9 +476,9 @@ struct Stager {
 
 }  // namespace
 
-extern "C" {
+namespace rzfrt {
 
-rzf_status rzf_update_batch(rzf_ctx* c, int n, const rzf_update_item* items, double tol) {
+rzf_status check_update_items(rzf_ctx* c, int n, const rzf_update_item* items, double tol) {
   if (!c || !items || n < 1 || n > RZF_BATCH_MAX) return RZF_E_INVALID;
   if (!(tol > 0.0 && tol <= 1.0)) return RZF_E_INVALID;
   std::set<rzf_track*> seen;
@@ -528,8 +488,11 @@ rzf_status rzf_update_batch(rzf_ctx* c, int n, const rzf_update_item* items, dou
     if (!seen.insert(it.track).second) return RZF_E_INVALID;
     if (it.ldh < it.track->N || it.ldw < it.track->K) return RZF_E_SHAPE;
   }
-  std::lock_guard<std::mutex> lk(c->mu);
-  HIP_OK(hipSetDevice(c->device));
+  return RZF_OK;
+}
+
+rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, double tol,
+                               DevInfo* const* slots) {
   hipStream_t s = c->stream;
   std::vector<GramJob> gj;
   std::vector<ArsvdJob> aj, ajb;     // LDS kernels (K <= KS) / large tracks
@@ -600,22 +563,17 @@ rzf_status rzf_update_batch(rzf_ctx* c, int n, const rzf_update_item* items, dou
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   for (int i = 0; i < n; ++i) {
     rzf_track* t = items[i].track;
-    if (items[i].info) {
-      DevInfo* slotp = pin_slot(c);
-      if (!slotp) return RZF_E_DEVICE;
-      HIP_OK(hipMemcpyAsync(slotp, &t->d_desc->info, sizeof(DevInfo), hipMemcpyDeviceToHost, s));
-      c->pending.push_back(Pending{slotp, items[i].info});
-    }
+    if (slots[i])
+      HIP_OK(hipMemcpyAsync(slots[i], &t->d_desc->info, sizeof(DevInfo), hipMemcpyDeviceToHost, s));
     t->t += 1;
     t->since_reset = reset_flag[i] ? 0 : t->since_reset + 1;
   }
   return RZF_OK;
 }
 
-rzf_status rzf_full_batch(rzf_ctx* c, int n, const rzf_full_item* items) {
-  if (!c || !items || n < 1 || n > RZF_BATCH_MAX) return RZF_E_INVALID;
-  int maxK = 1, maxN = 1, maxNK = 1;
-  size_t need = 0;
+
+rzf_status check_full_items(int n, const rzf_full_item* items) {
+  if (!items || n < 1 || n > RZF_BATCH_MAX) return RZF_E_INVALID;
   for (int i = 0; i < n; ++i) {
     const rzf_full_item& it = items[i];
     if (!it.H || !it.W) return RZF_E_INVALID;
@@ -623,13 +581,20 @@ rzf_status rzf_full_batch(rzf_ctx* c, int n, const rzf_full_item* items) {
       return RZF_E_SHAPE;
     if (!std::isfinite(it.alpha) || it.alpha < 0.0 || !std::isfinite(it.P) || it.P <= 0.0)
       return RZF_E_INVALID;
+  }
+  return RZF_OK;
+}
+
+rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items) {
+  int maxK = 1, maxN = 1, maxNK = 1;
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {
+    const rzf_full_item& it = items[i];
     maxK = std::max(maxK, it.K);
     maxN = std::max(maxN, it.N);
     maxNK = std::max(maxNK, it.N * it.K);
     need += align_up(sizeof(float2) * it.K * it.K) + align_up(sizeof(double) * precoder_blocks(it.N));
   }
-  std::lock_guard<std::mutex> lk(c->mu);
-  HIP_OK(hipSetDevice(c->device));
   hipStream_t s = c->stream;
   if (need > c->batch_full_bytes) {
     // grow: the old region may still be read by queued work
@@ -683,6 +648,37 @@ rzf_status rzf_full_batch(rzf_ctx* c, int n, const rzf_full_item* items) {
   HIP_OK(hipEventRecord(c->stage_ev[slot], s));
   c->stage_used[slot] = true;
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
+}
+
+}  // namespace rzfrt
+
+extern "C" {
+
+rzf_status rzf_update_batch(rzf_ctx* c, int n, const rzf_update_item* items, double tol) {
+  const rzf_status st = check_update_items(c, n, items, tol);
+  if (st != RZF_OK) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  std::vector<DevInfo*> slots(n, nullptr);
+  for (int i = 0; i < n; ++i) {
+    if (!items[i].info) continue;
+    slots[i] = pin_slot(c);
+    if (!slots[i]) return RZF_E_DEVICE;
+  }
+  const rzf_status s2 = update_batch_locked(c, n, items, tol, slots.data());
+  if (s2 != RZF_OK) return s2;
+  for (int i = 0; i < n; ++i)
+    if (slots[i]) c->pending.push_back(Pending{slots[i], items[i].info});
+  return RZF_OK;
+}
+
+rzf_status rzf_full_batch(rzf_ctx* c, int n, const rzf_full_item* items) {
+  if (!c) return RZF_E_INVALID;
+  const rzf_status st = check_full_items(n, items);
+  if (st != RZF_OK) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  return full_batch_locked(c, n, items);
 }
 
 rzf_status rzf_sum_rate_batch(rzf_ctx* c, int n, const rzf_rate_item* items, double P, double sigma2) {
@@ -834,6 +830,71 @@ rzf_status rzf_debug_sigma2(rzf_track* t, double* out, int n, int* d_out) {
   const int m = n < d ? n : d;
   if (m > 0) HIP_OK(hipMemcpy(out, t->d_desc->sig2, sizeof(double) * m, hipMemcpyDeviceToHost));
   *d_out = d;
+  return RZF_OK;
+}
+
+rzf_status rzf_track_export(rzf_track* t, void* buf, size_t* bytes) {
+  if (!t || !bytes) return RZF_E_INVALID;
+  const size_t need = blob_bytes(t->K, t->N);
+  if (!buf) { *bytes = need; return RZF_OK; }
+  if (*bytes < need) { *bytes = need; return RZF_E_INVALID; }
+  rzf_ctx* c = t->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  TrackBlob h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, BLOB_MAGIC, sizeof(h.magic));
+  h.version = BLOB_VERSION;
+  h.header_bytes = sizeof(TrackBlob);
+  h.K = t->K; h.N = t->N; h.prm = t->prm; h.alpha = t->alpha;
+  h.step = t->t; h.since_reset = t->since_reset;
+  HIP_OK(hipMemcpy(&h.last_r, &t->d_desc->last_r, sizeof(int), hipMemcpyDeviceToHost));
+  char* p = static_cast<char*>(buf);
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  HIP_OK(hipMemcpy(p, t->h_desc.Ainv, sizeof(float2) * t->K * t->K, hipMemcpyDeviceToHost));
+  p += sizeof(float2) * t->K * t->K;
+  HIP_OK(hipMemcpy(p, t->h_desc.Hprev, sizeof(float2) * (size_t)t->K * t->N, hipMemcpyDeviceToHost));
+  *bytes = need;
+  return RZF_OK;
+}
+
+rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track** out) {
+  if (!c || !buf || !out) return RZF_E_INVALID;
+  *out = nullptr;
+  if (bytes < sizeof(TrackBlob)) return RZF_E_INVALID;
+  TrackBlob h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, BLOB_MAGIC, sizeof(h.magic)) != 0 || h.version != BLOB_VERSION ||
+      h.header_bytes != sizeof(TrackBlob))
+    return RZF_E_INVALID;
+  if (h.K < 1 || h.K > RZF_KMAX || h.N < 1 || h.N > RZF_NMAX) return RZF_E_SHAPE;
+  if (bytes < blob_bytes(h.K, h.N)) return RZF_E_INVALID;
+  if (!params_valid(&h.prm) || !std::isfinite(h.alpha) || h.alpha < 0.0 || h.step < 0 ||
+      h.since_reset < 0 || h.last_r < 0 || h.last_r > h.K)
+    return RZF_E_INVALID;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  rzf_status st0 = sync_and_collect(c);
+  if (st0 == RZF_E_DEVICE) return st0;
+  rzf_track* t = track_new(c, h.K, h.N, h.prm, h.alpha);
+  if (!t) return RZF_E_NOMEM;
+  t->t = h.step;
+  t->since_reset = h.since_reset;
+  t->h_desc.last_r = h.last_r;
+  const char* p = static_cast<const char*>(buf) + sizeof(h);
+  bool ok = hipMemcpy(t->d_desc, &t->h_desc, sizeof(TrackDesc), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(t->h_desc.Ainv, p, sizeof(float2) * h.K * h.K, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(t->h_desc.Hprev, p + sizeof(float2) * h.K * h.K, sizeof(float2) * (size_t)h.K * h.N,
+                      hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    arena_free(c, t->off, t->bytes);
+    delete t;
+    return RZF_E_DEVICE;
+  }
+  c->tracks.insert(t);
+  *out = t;
   return RZF_OK;
 }
 

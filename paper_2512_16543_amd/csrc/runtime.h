@@ -1,0 +1,107 @@
+// Host runtime state behind rzf.h, shared by the entry points (api.cpp) and
+// the request server (server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <set>
+#include <vector>
+
+#include "rzf.h"
+#include "rzf_internal.h"
+
+namespace rzfrt {
+
+constexpr size_t ALIGN = 256;
+constexpr int PIN_CHUNK = 4096;   // info records per pinned chunk
+constexpr int NSTAGE = 4;
+constexpr size_t STAGE_BYTES = 1 << 20;   // per slot
+
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+struct Pending {
+  DevInfo* slot;
+  rzf_update_info* dst;
+};
+
+struct ProfRec {
+  int kernel;
+  hipEvent_t a, b;
+};
+
+enum { KN_GRAM, KN_GRAM64, KN_INV64, KN_INV32, KN_ARSVD, KN_PRECODER, KN_SCALE, KN_SUMRATE,
+       KN_COUNT };
+
+}  // namespace rzfrt
+
+struct rzf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  bool own_arena = false;
+  std::map<size_t, size_t> free_blocks;   // offset -> size
+  // fixed scratch at the front of the arena
+  int* d_err = nullptr;
+  float2* d_fullA = nullptr;
+  float2* d_fullAinv = nullptr;
+  double* d_fullwpart = nullptr;
+  double* d_sum = nullptr;
+  double* d_srpart = nullptr;
+  // pinned host staging
+  double* h_sum = nullptr;
+  int* h_err = nullptr;
+  std::vector<DevInfo*> pin_chunks;
+  size_t pin_used = 0;
+  std::vector<rzfrt::Pending> pending;
+  std::set<rzf_track*> tracks;
+  std::mutex mu;
+  // batched calls: ring of pinned host / device staging slots for job arrays
+  char* h_stage = nullptr;
+  char* d_stage = nullptr;
+  hipEvent_t stage_ev[rzfrt::NSTAGE] = {};
+  bool stage_used[rzfrt::NSTAGE] = {};
+  int stage_next = 0;
+  double* d_batch_part = nullptr;       // sum-rate scratch of batched calls
+  size_t batch_part_off = 0, batch_part_bytes = 0;
+  char* d_batch_full = nullptr;         // Gram / partial-norm scratch of rzf_full_batch
+  size_t batch_full_off = 0, batch_full_bytes = 0;
+  // event timing
+  bool prof_on = false;
+  std::vector<rzfrt::ProfRec> prof;
+  std::vector<hipEvent_t> ev_pool;
+  int prof_count[rzfrt::KN_COUNT] = {};
+  double prof_ms[rzfrt::KN_COUNT] = {};
+};
+
+struct rzf_track {
+  rzf_ctx* ctx = nullptr;
+  int K = 0, N = 0;
+  rzf_params prm{};
+  double alpha = 0.0;
+  size_t off = 0, bytes = 0;
+  TrackDesc* d_desc = nullptr;
+  TrackDesc h_desc{};
+  int t = 0;
+  int since_reset = 0;
+  int i_max = 0;
+};
+
+namespace rzfrt {
+
+// Argument checks of rzf_update_batch / rzf_full_batch (no device work).
+rzf_status check_update_items(rzf_ctx* c, int n, const rzf_update_item* items, double tol);
+rzf_status check_full_items(int n, const rzf_full_item* items);
+
+// Launch one batched update (c->mu held, items checked).  For every i with
+// slots[i] != nullptr the step's info record is copied into that pinned
+// host slot on the context stream after the update; the caller decides when
+// it is valid (an event, or rzf_sync).
+rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, double tol,
+                               DevInfo* const* slots);
+// Launch one batched full-inversion RZF (c->mu held, items checked).
+rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items);
+
+}  // namespace rzfrt

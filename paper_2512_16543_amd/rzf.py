@@ -60,6 +60,24 @@ class RateItem(ctypes.Structure):
 
 
 BATCH_MAX = 2048
+SERVE_UPDATE, SERVE_FULL = 0, 1
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int), ("max_wait_us", ctypes.c_double), ("tol", ctypes.c_double),
+                ("mode", ctypes.c_int), ("max_inflight", ctypes.c_int)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("pad", ctypes.c_int),
+                ("info", UpdateInfo), ("t_submit_us", ctypes.c_double), ("t_launch_us", ctypes.c_double),
+                ("t_done_us", ctypes.c_double)]
+
+
+class ServeRequest(ctypes.Structure):
+    _fields_ = [("track", ctypes.c_void_p), ("H", ctypes.c_void_p), ("ldh", ctypes.c_int),
+                ("W", ctypes.c_void_p), ("ldw", ctypes.c_int), ("tag", ctypes.c_uint64),
+                ("t_arrival_us", ctypes.c_double)]
 
 
 class ProfileEntry(ctypes.Structure):
@@ -101,6 +119,20 @@ _SIGS = {
                                           ctypes.c_double, ctypes.c_double]),
     "rzf_track_query": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 5),
     "rzf_track_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rzf_server_params_default": (ctypes.c_int, [ctypes.POINTER(ServerParams)]),
+    "rzf_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerParams),
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "rzf_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64]),
+    "rzf_server_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ServeRequest)]),
+    "rzf_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Completion), ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int)]),
+    "rzf_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
+    "rzf_server_now_us": (ctypes.c_double, [ctypes.c_void_p]),
+    "rzf_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rzf_track_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "rzf_track_import": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
     "rzf_debug_sigma2": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]),
     "rzf_debug_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
@@ -203,6 +235,16 @@ class Context:
         st = lib().rzf_sync(self.h)
         self._infos = []
         return st
+
+    def import_track(self, blob: bytes) -> "Track":
+        """A new track in this context from a checkpoint blob (rzf_track_import)."""
+        h = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(lib().rzf_track_import(self.h, buf, len(blob), ctypes.byref(h)), "rzf_track_import")
+        K, N = [ctypes.c_int() for _ in range(2)]
+        _check(lib().rzf_track_query(h, ctypes.byref(K), ctypes.byref(N), None, None, None),
+               "rzf_track_query")
+        return Track(self, h, K.value, N.value)
 
     def init(self, H, alpha: float, params: Optional[Params] = None) -> "Track":
         ptr, ld = _mat_args(H)
@@ -391,7 +433,73 @@ class Track:
         _check(lib().rzf_debug_sigma2(self.h, arr, KMAX, ctypes.byref(d)), "rzf_debug_sigma2")
         return [arr[i] for i in range(d.value)]
 
+    def export(self) -> bytes:
+        """Checkpoint blob of the track (rzf_track_export)."""
+        n = ctypes.c_size_t()
+        _check(lib().rzf_track_export(self.h, None, ctypes.byref(n)), "rzf_track_export")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().rzf_track_export(self.h, buf, ctypes.byref(n)), "rzf_track_export")
+        return buf.raw[:n.value]
+
     def destroy(self):
         if self.h:
             _check(lib().rzf_track_destroy(self.h), "rzf_track_destroy")
+            self.h = ctypes.c_void_p()
+
+
+def server_params(**kw) -> ServerParams:
+    p = ServerParams()
+    _check(lib().rzf_server_params_default(ctypes.byref(p)), "rzf_server_params_default")
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Server:
+    """rzf_server: batched serving of update (or full-inversion) requests."""
+
+    def __init__(self, ctx: Context, params: Optional[ServerParams] = None):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        p = params if params is not None else server_params()
+        _check(lib().rzf_server_create(ctx.h, ctypes.byref(p), ctypes.byref(h)), "rzf_server_create")
+        self.h = h
+
+    def submit(self, track: Track, H_t, W, tag: int = 0):
+        hp, ldh = _mat_args(H_t)
+        wp, ldw = _mat_args(W)
+        _check(lib().rzf_server_submit(self.h, track.h, ctypes.c_void_p(hp), ldh, ctypes.c_void_p(wp), ldw,
+                                       int(tag)), "rzf_server_submit")
+
+    @staticmethod
+    def requests(tracks, Hs, Ws, tags, t_arrival_us):
+        """A ServeRequest array for replay (tracks, H_t and W tensors, tags, arrival offsets)."""
+        n = len(tracks)
+        arr = (ServeRequest * n)()
+        for i in range(n):
+            hp, ldh = _mat_args(Hs[i])
+            wp, ldw = _mat_args(Ws[i])
+            r = arr[i]
+            r.track, r.H, r.ldh, r.W, r.ldw = tracks[i].h.value, hp, ldh, wp, ldw
+            r.tag, r.t_arrival_us = int(tags[i]), float(t_arrival_us[i])
+        return arr
+
+    def replay(self, reqs):
+        _check(lib().rzf_server_replay(self.h, len(reqs), reqs), "rzf_server_replay")
+
+    def poll(self, max_n: int = 4096):
+        arr = (Completion * max_n)()
+        n = ctypes.c_int()
+        _check(lib().rzf_server_poll(self.h, arr, max_n, ctypes.byref(n)), "rzf_server_poll")
+        return [arr[i] for i in range(n.value)]
+
+    def drain(self):
+        _check(lib().rzf_server_drain(self.h), "rzf_server_drain")
+
+    def now_us(self) -> float:
+        return float(lib().rzf_server_now_us(self.h))
+
+    def close(self):
+        if self.h:
+            _check(lib().rzf_server_destroy(self.h), "rzf_server_destroy")
             self.h = ctypes.c_void_p()

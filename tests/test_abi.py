@@ -65,6 +65,17 @@ def test_null_arguments_rejected_without_device():
     assert L.rzf_get_inverse(None, None) == rzf.RZF_E_INVALID
     assert L.rzf_track_destroy(None) == rzf.RZF_E_INVALID
     assert L.rzf_debug_sketch(None, 0, 0, 0, 0, 4, 4, None, None) == rzf.RZF_E_INVALID
+    n = ctypes.c_size_t(0)
+    assert L.rzf_track_export(None, None, ctypes.byref(n)) == rzf.RZF_E_INVALID
+    blob = ctypes.create_string_buffer(64)
+    assert L.rzf_track_import(None, blob, 64, ctypes.byref(out)) == rzf.RZF_E_INVALID
+    assert L.rzf_server_params_default(None) == rzf.RZF_E_INVALID
+    sp = rzf.server_params()
+    assert (sp.max_batch, sp.max_wait_us, sp.tol, sp.mode, sp.max_inflight) == (512, 1000.0, 0.999, 0, 2)
+    assert L.rzf_server_create(None, ctypes.byref(sp), ctypes.byref(out)) == rzf.RZF_E_INVALID
+    assert L.rzf_server_submit(None, None, None, 4, None, 4, 0) == rzf.RZF_E_INVALID
+    assert L.rzf_server_drain(None) == rzf.RZF_E_INVALID
+    assert L.rzf_server_destroy(None) == rzf.RZF_E_INVALID
 
 
 def test_ctx_create_arena_too_small():

@@ -1,0 +1,66 @@
+"""Checkpoint / resume of a track: an imported track continues exactly as
+the exported one (bit-identical precoders and inverses), in the same or in
+another context; foreign or truncated blobs are refused."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2512_16543_amd import rzf, workload as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def walk(K, N, steps, seed):
+    H = [wl.random_channel(K, N, seed)]
+    for t in range(steps):
+        H.append(wl.perturbed_channel(H[-1], seed * 1000 + t, rank=3, scale=0.02))
+    return torch.from_numpy(np.asarray(H, dtype=np.complex64)).cuda()
+
+
+@pytest.mark.parametrize("K,N,period,policy", [(24, 80, 4, rzf.KINIT_FIXED), (64, 256, 0, rzf.KINIT_WARM),
+                                               (100, 128, 3, rzf.KINIT_WARM)])
+def test_resume_is_bit_identical(K, N, period, policy):
+    Hs = walk(K, N, 9, 5 + K)
+    ctx = rzf.Context(0, 64 << 20)
+    other = rzf.Context(0, 64 << 20)
+    prm = rzf.default_params(seed=9, track_id=2, reset_period=period, kinit_policy=policy)
+    a = ctx.init(Hs[0], 0.5 + K / 30.0, prm)
+    Wa = torch.empty(N, K, dtype=torch.complex64, device="cuda")
+    Wb = torch.empty_like(Wa)
+    for t in range(1, 5):
+        a.update(Hs[t], 0.95, Wa)
+    ctx.sync()
+    blob = a.export()
+    b1 = ctx.import_track(blob)
+    b2 = other.import_track(blob)
+    assert (b1.K, b1.N) == (K, N) and b1.query()["t"] == 4
+    assert b1.query() == a.query()
+    assert torch.equal(b1.inverse(), a.inverse())
+    for t in range(5, 10):
+        ia = a.update(Hs[t], 0.95, Wa)
+        ib = b1.update(Hs[t], 0.95, Wb)
+        ctx.sync()
+        assert (ia.r, ia.iters, ia.path) == (ib.r, ib.iters, ib.path), t
+        assert torch.equal(Wa, Wb), t
+        assert torch.equal(a.inverse(), b1.inverse()), t
+        b2.update(Hs[t], 0.95, Wb)
+        other.sync()
+        assert torch.equal(Wa, Wb), t
+    for tr in (a, b1, b2):
+        tr.destroy()
+    ctx.close()
+    other.close()
+
+
+def test_import_rejects_bad_blobs():
+    Hs = walk(8, 16, 1, 3)
+    ctx = rzf.Context(0, 16 << 20)
+    tr = ctx.init(Hs[0], 1.0, rzf.default_params())
+    blob = tr.export()
+    for bad in (blob[:40], blob[:-8], b"XXXXXXXX" + blob[8:]):
+        with pytest.raises(rzf.RzfError) as e:
+            ctx.import_track(bad)
+        assert e.value.status == rzf.RZF_E_INVALID
+    tr.destroy()
+    ctx.close()
