@@ -40,6 +40,8 @@ def parse():
                     help="c2 (default), c1, c5 (K=256 N=1024 track) or mix (multi-track batch)")
     ap.add_argument("--eta", type=float, default=None)
     ap.add_argument("--policy", choices=["fixed", "warm"], default="fixed")
+    ap.add_argument("--early-fallback", action="store_true",
+                    help="policy: end Alg. 1 once d passes the Woodbury limit without success")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -126,7 +128,7 @@ def main():
     def params(track_id):
         return rzf.default_params(k_init=cfg.k_init, p=cfg.p, P=cfg.P, seed=cfg.seed,
                                   track_id=track_id, reset_period=cfg.reset_period,
-                                  kinit_policy=policy)
+                                  kinit_policy=policy, early_fallback=int(a.early_fallback))
 
     def run_wb(H, steps, track_id, want_info=False, per_step_sync=False):
         tr = ctx.init(H[0], cfg.alpha, params(track_id))
@@ -194,7 +196,8 @@ def main():
             "workload": (f"{a.config}: single LEO track, K={K} users, N={N} antennas "
                          f"({cfg.nx}x{cfg.nx} UPA), {tcfg.steps} snapshots of {cfg.dt_s * 1e3:g} ms, "
                          f"eta={eta}, FP64 re-inversion every {cfg.reset_period} steps, "
-                         f"k_init={cfg.k_init}, p={cfg.p}, {a.policy} k_init policy; "
+                         f"k_init={cfg.k_init}, p={cfg.p}, {a.policy} k_init policy"
+                         f"{', early fallback' if a.early_fallback else ''}; "
                          f"step = update + sum rate, batch of 1 track"),
             "K": K, "N": N, "eta": eta, "batch_tracks": 1, "reset_period": cfg.reset_period,
         },
@@ -267,7 +270,7 @@ def main():
 
     # FP64 CPU oracle on a bounded sample of the same track
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, eta, Hs_np, a.cpu_seconds, policy)
+        out["cpu_baseline"] = cpu_baseline(cfg, eta, Hs_np, a.cpu_seconds, policy, int(a.early_fallback))
         print(f"[bench] cpu baseline done", file=sys.stderr, flush=True)
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -294,7 +297,8 @@ def batched(a, cfgs, eta, policy):
     ctx = rzf.Context(0, arena)
     trs = [ctx.init(Hs[b][0], c.alpha,
                     rzf.default_params(k_init=c.k_init, p=c.p, P=c.P, seed=c.seed, track_id=b,
-                                       reset_period=c.reset_period, kinit_policy=policy))
+                                       reset_period=c.reset_period, kinit_policy=policy,
+                                       early_fallback=int(a.early_fallback)))
            for b, c in enumerate(cfgs)]
     P = cfgs[0].P
     s2 = [c.sigma2 for c in cfgs]
@@ -557,7 +561,7 @@ def table_v(a):
             "rows": rows}
 
 
-def cpu_baseline(cfg, eta, Hs_np, budget_s, policy):
+def cpu_baseline(cfg, eta, Hs_np, budget_s, policy, early_fallback=0):
     import numpy as np
     import oracle.rzf as orz
     try:
@@ -568,7 +572,7 @@ def cpu_baseline(cfg, eta, Hs_np, budget_s, policy):
     H = Hs_np.astype(np.complex128)
     prm = orz.TrackParams(alpha=cfg.alpha, P=cfg.P, k_init=cfg.k_init, p=cfg.p,
                           reset_period=cfg.reset_period, seed=cfg.seed, track_id=0,
-                          kinit_policy=policy)
+                          kinit_policy=policy, early_fallback=early_fallback)
     ot = orz.OracleTrack(H[0], prm)
     t0 = time.perf_counter()
     n = 0

@@ -85,6 +85,10 @@ typedef struct {
   uint64_t track_id;    /* sketch key word 1                                       */
   int kinit_policy;     /* RZF_KINIT_FIXED: k0 = k_init every step (Alg. 1);
                            RZF_KINIT_WARM: k0 = max(k_init, previous k_est)        */
+  int early_fallback;   /* 0: Alg. 1 as printed.  1: an iteration whose d already
+                           exceeds the Woodbury limit (switch_ratio * K and the
+                           rank cap) and misses the energy target ends Alg. 1;
+                           the step inverts directly (path FULL_RANK, k_est = d)  */
 } rzf_params;
 
 /* Outcome of one rzf_update. */
@@ -100,7 +104,8 @@ typedef struct {
 const char* rzf_status_string(rzf_status s);
 
 /* Fill *p with k_init=2, p=5, i_max=0, switch_ratio=0.5, reset_period=0,
- * P=1, seed=0, track_id=0, kinit_policy=FIXED.  RZF_E_INVALID if p is NULL. */
+ * P=1, seed=0, track_id=0, kinit_policy=FIXED, early_fallback=0.
+ * RZF_E_INVALID if p is NULL. */
 rzf_status rzf_params_default(rzf_params* p);
 
 /* Bytes of arena one track of size K x N occupies (0 if out of range). */

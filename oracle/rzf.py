@@ -110,7 +110,8 @@ class ArsvdResult:
 
 def arsvd(dA: np.ndarray, eta: float, k_init: int, p: int, i_max: int,
           draw: Callable[[int, int, int], np.ndarray],
-          force_iters: Optional[int] = None, force_r: Optional[int] = None) -> ArsvdResult:
+          force_iters: Optional[int] = None, force_r: Optional[int] = None,
+          stop_d: Optional[int] = None) -> ArsvdResult:
     """Adaptive randomized SVD (Alg. 1).
 
     draw(i, K, d) returns the K x d CN(0,1) matrix Omega of iteration i.
@@ -118,6 +119,9 @@ def arsvd(dA: np.ndarray, eta: float, k_init: int, p: int, i_max: int,
     elsewhere (used only when another implementation's decision fell within
     rounding distance of the threshold): the loop then runs exactly
     force_iters iterations and returns rank force_r from the last one.
+    stop_d (early-fallback policy, not in the paper): an iteration with
+    d > stop_d that misses the target ends the loop like the last one does,
+    returning all d components (k_est = d).
     """
     K = dA.shape[0]
     energy = fro2(dA)
@@ -154,6 +158,9 @@ def arsvd(dA: np.ndarray, eta: float, k_init: int, p: int, i_max: int,
                 r = int(hit[0]) + 1
                 return ArsvdResult(U_approx[:, :r], s[:r], V_hat[:, :r], r, i, d, s,
                                    energy, float(csum[r - 1]))
+            if stop_d is not None and d > stop_d:        # early fallback
+                return ArsvdResult(U_approx[:, :d], s[:d], V_hat[:, :d], d, i, d, s,
+                                   energy, float(csum[d - 1]))
         k0 = 2 * k0
     # no r met the target: return all d components (k_est = d)
     return ArsvdResult(U_approx[:, :d], s[:d], V_hat[:, :d], d, n_iter, d, s,
@@ -227,6 +234,7 @@ class TrackParams:
     seed: int = 0
     track_id: int = 0
     kinit_policy: int = KINIT_FIXED
+    early_fallback: int = 0     # policy: stop Alg. 1 once d passes the Woodbury limit
 
 
 @dataclasses.dataclass
@@ -282,12 +290,14 @@ class OracleTrack:
             k_init = prm.k_init
             if prm.kinit_policy == KINIT_WARM:
                 k_init = max(prm.k_init, self.last_r)
+            limit = min(math.floor(prm.switch_ratio * self.K), wb_rank_cap(self.K))
             res = arsvd(dA, eta, k_init, prm.p, self.i_max(), self.draw(t),
-                        force_iters=force_iters, force_r=force_r)
+                        force_iters=force_iters, force_r=force_r,
+                        stop_d=limit if prm.early_fallback else None)
             info = UpdateInfo(res.r, res.iters, PATH_NOOP, energy, res.captured, res.d)
             if res.r == 0:
                 info.path = PATH_NOOP
-            elif res.r <= prm.switch_ratio * self.K and res.r <= wb_rank_cap(self.K):   # Alg. 2
+            elif res.r <= limit:                         # Alg. 2: k_est <= switch * K
                 new, singular = woodbury(self.Ainv, res.U, res.s, res.V)
                 if singular:
                     self.Ainv = direct_inverse(A_new)

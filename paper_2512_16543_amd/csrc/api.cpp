@@ -159,7 +159,8 @@ bool params_valid(const rzf_params* p) {
   return p->k_init >= 1 && p->p >= 0 && p->i_max >= 0 && p->i_max <= 64 &&
          std::isfinite(p->switch_ratio) && p->switch_ratio > 0.0 && p->switch_ratio <= 1.0 &&
          p->reset_period >= 0 && std::isfinite(p->P) && p->P > 0.0 &&
-         (p->kinit_policy == RZF_KINIT_FIXED || p->kinit_policy == RZF_KINIT_WARM);
+         (p->kinit_policy == RZF_KINIT_FIXED || p->kinit_policy == RZF_KINIT_WARM) &&
+         (p->early_fallback == 0 || p->early_fallback == 1);
 }
 
 int default_imax(int K, int k_init, int p) {
@@ -206,6 +207,9 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
   d.K = K; d.N = N; d.alpha = alpha; d.P = prm.P; d.switch_ratio = prm.switch_ratio;
   d.k_init = prm.k_init; d.p = prm.p; d.i_max = t->i_max; d.kinit_policy = prm.kinit_policy;
   d.seed = prm.seed; d.track_id = prm.track_id;
+  d.early_fallback = prm.early_fallback;
+  // Alg. 2's switch and the end of the Woodbury workspace (max(32, K/2) ranks)
+  d.wb_limit = std::min((int)std::floor(prm.switch_ratio * K), std::max(WB_RMAX, K / 2));
   d.Ainv = reinterpret_cast<float2*>(base + L.ainv);
   d.Hprev = reinterpret_cast<float2*>(base + L.hprev);
   d.Anew = reinterpret_cast<float2*>(base + L.anew);

@@ -380,9 +380,12 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       pick_rank(sm, K, d, Et, &r, &captured, td->sig2);
       break;
     }
-    if (it == i_max) {
+    // after the last iteration, or (early-fallback policy) once d is past
+    // the Woodbury limit: every component, k_est = d, and the step inverts
+    if (it == i_max || (td->early_fallback && d > td->wb_limit)) {
       r = d;                 // every component: U_r Sigma_r V_r^H = Q Z^H
       captured = tot;
+      break;
     }
     k0 *= 2;
   }
@@ -392,8 +395,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   }
   (void)found;
 
-  const int rmax = (int)floor(td->switch_ratio * (double)K);
-  bool use_wb = r <= rmax && r <= WB_RMAX;
+  // Alg. 2's switch k_est <= switch * K, within the Woodbury workspace
+  bool use_wb = r <= td->wb_limit;
   int path = use_wb ? RZF_PATH_WB : RZF_PATH_FULL_RANK;
 
   if (use_wb) {

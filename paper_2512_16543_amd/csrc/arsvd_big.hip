@@ -708,9 +708,12 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
       pick_rank_big(sm, Zm, K, d, Et, &r, &captured, td->sig2);
       break;
     }
-    if (it == i_max) {
+    // after the last iteration, or (early-fallback policy) once d is past
+    // the Woodbury limit: every component, k_est = d, and the step inverts
+    if (it == i_max || (td->early_fallback && d > td->wb_limit)) {
       r = d;
       captured = tot;
+      break;
     }
     k0 *= 2;
   }
@@ -719,8 +722,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
     __syncthreads();
   }
 
-  const int rmax = (int)floor(td->switch_ratio * (double)K);
-  bool use_wb = r <= rmax && r <= K / 2;   // K / 2 = max(32, K / 2) for K > 64
+  // Alg. 2's switch k_est <= switch * K, within the Woodbury workspace
+  bool use_wb = r <= td->wb_limit;
   int path = use_wb ? RZF_PATH_WB : RZF_PATH_FULL_RANK;
   float2* Ainv = td->Ainv;
   if (use_wb) {

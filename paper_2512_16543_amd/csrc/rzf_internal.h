@@ -25,6 +25,7 @@ struct TrackDesc {
   int K, N;
   double alpha, P, switch_ratio;
   int k_init, p, i_max, kinit_policy;
+  int early_fallback, wb_limit;   // policy flag; largest rank the Woodbury branch takes
   uint64_t seed, track_id;
   float2* Ainv;    // K x K, ld K: stored inverse
   float2* Hprev;   // K x N, ld N: previous snapshot

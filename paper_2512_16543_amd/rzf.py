@@ -31,7 +31,7 @@ class Params(ctypes.Structure):
     _fields_ = [("k_init", ctypes.c_int), ("p", ctypes.c_int), ("i_max", ctypes.c_int),
                 ("switch_ratio", ctypes.c_double), ("reset_period", ctypes.c_int),
                 ("P", ctypes.c_double), ("seed", ctypes.c_uint64), ("track_id", ctypes.c_uint64),
-                ("kinit_policy", ctypes.c_int)]
+                ("kinit_policy", ctypes.c_int), ("early_fallback", ctypes.c_int)]
 
 
 class UpdateInfo(ctypes.Structure):

@@ -119,6 +119,16 @@ def test_update_c5_track(ctx, eta):
     assert [r["t"] for r in recs if r["path"] == orz.PATH_RESET] == [3]
 
 
+@pytest.mark.parametrize("cfgname,K", [("c2", 128), ("c5", 256)])
+def test_update_large_early_fallback(ctx, cfgname, K):
+    cfg = wl.with_overrides(wl.CONFIGS[cfgname], K=K, seed=3)
+    recs = run_track(ctx, cfg, 3, 0.999, dict(early_fallback=1, reset_period=0))
+    print([(r["path"], r["r"], r["iters"]) for r in recs], flush=True)
+    _assert_recs(recs)
+    # the first iteration past K/2 that misses the target ends Alg. 1
+    assert all(r["path"] != orz.PATH_FULL_RANK or r["r"] > K // 2 for r in recs)
+
+
 def test_update_large_falls_back(ctx):
     K, N = 160, 512
     H0, H1 = _channel(K, N, 40), _channel(K, N, 41)

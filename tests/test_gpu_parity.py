@@ -145,7 +145,7 @@ def _oracle_params_a(alpha, d):
     return orz.TrackParams(alpha=alpha, P=d["P"], k_init=d["k_init"], p=d["p"],
                            i_max=d.get("i_max", 0), switch_ratio=d.get("switch_ratio", 0.5),
                            reset_period=d["reset_period"], seed=d["seed"], track_id=d["track_id"],
-                           kinit_policy=d.get("kinit_policy", 0))
+                           kinit_policy=d.get("kinit_policy", 0), early_fallback=d.get("early_fallback", 0))
 
 
 def _energy_ratios(res):
@@ -161,7 +161,7 @@ def _tie_ok(state, H, eta, gi, io, ot):
     prm = ot.params
     k_init = prm.k_init if prm.kinit_policy == 0 else max(prm.k_init, state["last_r"])
     it = min(gi.iters, io.iters)
-    res = orz.arsvd(dA, eta, k_init, prm.p, ot.i_max(), ot.draw(state["t"] + 1), force_iters=it)
+    res = orz.arsvd(dA, eta, k_init, prm.p, ot.i_max(), ot.draw(state["t"] + 1), force_iters=it)   # no early stop
     c = np.cumsum(res.sigma ** 2) / res.energy
     return bool(np.any(np.abs(c - eta) < TIE_BAND))
 
@@ -235,6 +235,16 @@ def test_update_c2_short(ctx, eta):
     _assert_recs(recs)
     assert [r["t"] for r in recs if r["path"] == orz.PATH_RESET] == [10, 20]
     assert all(r["e"] < 1e-4 for r in recs if r["path"] != orz.PATH_RESET)
+
+
+def test_update_early_fallback_policy(ctx):
+    # eta = 0.999 at K = 64: d = 37 > K/2 misses the target, so the policy
+    # inverts directly there instead of running on to d = 64
+    cfg = wl.CONFIGS["c2"]
+    recs = run_track(ctx, cfg, 10, 0.999, dict(early_fallback=1, reset_period=0))
+    _assert_recs(recs)
+    assert all(r["path"] == orz.PATH_FULL_RANK and r["iters"] == 5 and r["r"] == 37 for r in recs), \
+        [(r["path"], r["iters"], r["r"]) for r in recs]
 
 
 def test_update_warm_policy(ctx):

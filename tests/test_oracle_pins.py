@@ -515,3 +515,27 @@ def test_woodbury_rank_cap_reading():
     # Alg. 2's switch at 0.5 K never reaches the cap; only larger ratios do
     assert [orz.wb_rank_cap(K) for K in (1, 16, 64, 65, 100, 256)] == [32, 32, 32, 32, 50, 128]
     assert all(math.floor(0.5 * K) <= orz.wb_rank_cap(K) for K in range(1, 257))   # integer ranks
+
+
+def test_track_early_fallback_policy():
+    # an i.i.d. redraw makes Delta A full rank: no iteration reaches eta = 0.999
+    # until d = K.  With the policy, the first iteration past the Woodbury
+    # limit (K/2 = 8 for K = 16: d = 9, the second) ends Alg. 1 and the step
+    # inverts directly; without it the loop runs on to d = K.
+    K, N = 16, 64
+    H0 = wl.random_channel(K, N, 1)
+    H1 = wl.random_channel(K, N, 2)
+    dA = orz.gram_correction(H0, H1 - H0)
+    draw = lambda i, K_, d: orz.draw_sketch(3, 0, 1, i, K_, d)
+    full = orz.arsvd(dA, 0.999, 2, 5, 4, draw)
+    early = orz.arsvd(dA, 0.999, 2, 5, 4, draw, stop_d=8)
+    assert (full.iters, full.d) == (4, 16) and full.r > 8
+    assert (early.iters, early.d, early.r) == (2, 9, 9)
+    # the first iteration is identical in both runs (same sketch), so the
+    # policy only cuts the loop short
+    assert early.energy == full.energy
+    for pol, (it_exp, r_exp) in ((0, (full.iters, full.r)), (1, (2, 9))):
+        ot = orz.OracleTrack(H0, orz.TrackParams(alpha=1.0, seed=3, early_fallback=pol))
+        W, info = ot.update(H1, 0.999)
+        assert info.path == orz.PATH_FULL_RANK and (info.iters, info.r) == (it_exp, r_exp)
+        assert rel(ot.Ainv, np.linalg.inv(orz.gram(H1, 1.0))) < 1e-13
