@@ -35,6 +35,10 @@
 namespace {
 
 constexpr int NTH = 1024;
+// LDS leading dimension of the K x K buffers: one element of padding puts
+// the 16 rows (or columns) read by one matrix-core operand load on distinct
+// banks (a stride of 64 complex values maps them all to the same bank)
+constexpr int LDK = KS + 1;
 constexpr int NWV = NTH / 64;
 constexpr int MAX_SWEEPS = 30;
 constexpr double JACOBI_TOL = 2e-6;
@@ -42,10 +46,10 @@ constexpr double SING_TOL = 1e-12;
 
 
 struct Shared {
-  float2 b0[KS * KS];            // Delta A (row-major, ld KS); later A^-1 or A'
-  float2 b1[KS * KS];            // column-major K x d: Omega, then Q
-  float2 b2[KS * KS];            // column-major K x d: Y / reflectors, then Z
-  float2 pm[KS * WB_RMAX];       // P = A^-1 U, column-major
+  float2 b0[KS * LDK];           // Delta A (row-major, ld LDK); later A^-1 or A'
+  float2 b1[KS * LDK];           // column-major K x d (ld LDK): Omega, then Q
+  float2 b2[KS * LDK];           // column-major K x d (ld LDK): Y / reflectors, then Z
+  float2 pm[WB_RMAX * LDK];      // P = A^-1 U, column-major
   double s2[KS];                 // ||z_j||^2
   double2 fcol[WB_RMAX];         // Gauss-Jordan: multipliers of column j
   double2 ustash[WB_RMAX + KS];  // Gauss-Jordan: normalised pivot row
@@ -85,15 +89,17 @@ __device__ void reflector_from(float2 x, float2* a, int c, int K) {
       w = make_float2(x.x * m, x.y * m);
     }
   }
-  if (lane < K) a[c * KS + lane] = (lane >= c) ? w : cz();
+  if (lane < K) a[c * LDK + lane] = (lane >= c) ? w : cz();
 }
 
 // y <- (I - 2 w w^H) y for column c of `a` and reflector column wc of `wsrc`.
+// Rows K..KS-1 of both are zero and stay zero, so all 64 lanes take part.
 // Returns the updated column value of the calling lane.
 __device__ __forceinline__ float2 apply_reflector(const float2* wsrc, int wc, float2* a, int c, int K) {
   const int lane = threadIdx.x & 63;
-  const float2 w = (lane < K) ? wsrc[wc * KS + lane] : cz();
-  float2 y = (lane < K) ? a[c * KS + lane] : cz();
+  (void)K;
+  const float2 w = wsrc[wc * LDK + lane];
+  float2 y = a[c * LDK + lane];
   float dr = w.x * y.x + w.y * y.y;     // conj(w) y
   float di = w.x * y.y - w.y * y.x;
   dr = wave_sumf(dr);
@@ -101,7 +107,7 @@ __device__ __forceinline__ float2 apply_reflector(const float2* wsrc, int wc, fl
   const float fr = 2.f * dr, fi = 2.f * di;
   y.x -= w.x * fr - w.y * fi;
   y.y -= w.x * fi + w.y * fr;
-  if (lane < K) a[c * KS + lane] = y;
+  a[c * LDK + lane] = y;
   return y;
 }
 
@@ -152,17 +158,22 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
           rr_pair(k, slot, n, &pp, &qq);
           act = pp < d && qq < d;
         }
+        if (!act) pp = qq = 0;        // an idle group reads column 0 and never stores
+        // rows K..KS-1 of Z and Q are zero (they stay zero under rotation), so
+        // every lane takes its four rows without a bound check
+        float2* zpc = b2 + pp * LDK + li;
+        float2* zqc = b2 + qq * LDK + li;
+        float2* qpc = b1 + pp * LDK + li;
+        float2* qqc = b1 + qq * LDK + li;
         float2 zp[4], zq[4], qa[4], qb[4];
         float al = 0.f, be = 0.f;
         double gr = 0.0, gi = 0.0;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          const int i = li + 16 * m;
-          const bool ok = act && i < K;
-          zp[m] = ok ? b2[pp * KS + i] : cz();
-          zq[m] = ok ? b2[qq * KS + i] : cz();
-          qa[m] = ok ? b1[pp * KS + i] : cz();    // loaded early to overlap latency
-          qb[m] = ok ? b1[qq * KS + i] : cz();
+          zp[m] = zpc[16 * m];
+          zq[m] = zqc[16 * m];
+          qa[m] = qpc[16 * m];     // loaded early to overlap latency
+          qb[m] = qqc[16 * m];
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -202,13 +213,11 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
         if (rot) {
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            const int i = li + 16 * m;
-            if (i >= K) continue;
             const float2 zq2 = cmul(e, zq[m]), qv2 = cmul(e, qb[m]);
-            b2[pp * KS + i] = csub(cscale(zp[m], c), cscale(zq2, s));
-            b2[qq * KS + i] = cadd(cscale(zp[m], s), cscale(zq2, c));
-            b1[pp * KS + i] = csub(cscale(qa[m], c), cscale(qv2, s));
-            b1[qq * KS + i] = cadd(cscale(qa[m], s), cscale(qv2, c));
+            zpc[16 * m] = csub(cscale(zp[m], c), cscale(zq2, s));
+            zqc[16 * m] = cadd(cscale(zp[m], s), cscale(zq2, c));
+            qpc[16 * m] = csub(cscale(qa[m], c), cscale(qv2, s));
+            qqc[16 * m] = cadd(cscale(qa[m], s), cscale(qv2, c));
           }
           if (li == 0) sm.nrot = 1;
         }
@@ -232,7 +241,7 @@ __device__ void column_norms(Shared& sm, int K, int d) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int i = li + 16 * m;
-      if (i < K) v += (double)cabs2(sm.b2[slot * KS + i]);
+      if (i < K) v += (double)cabs2(sm.b2[slot * LDK + i]);
     }
   }
   v = row16_sum(v);
@@ -287,12 +296,16 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   float2* b1 = sm.b1;
   float2* b2 = sm.b2;
 
+  // Z / reflector buffer cleared: its rows K..KS-1 stay zero for the whole
+  // launch (the products and reflectors only write rows < K), which the
+  // Jacobi sweeps rely on
+  for (int e = tid; e < KS * LDK; e += NTH) b2[e] = cz();
   // Delta A -> LDS, E = ||Delta A||_F^2 in FP64
   double part = 0.0;
   for (int e = tid; e < K * K; e += NTH) {
     const int i = e / K, j = e - i * K;
     const float2 v = td->dA[e];
-    b0[i * KS + j] = v;
+    b0[i * LDK + j] = v;
     part += (double)v.x * v.x + (double)v.y * v.y;
   }
   const double E = block_sum(part, sm.red);
@@ -326,14 +339,14 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     // Omega -> b1 (column-major)
     for (int e = tid; e < K * d; e += NTH) {
       const int j = e / K, i = e - j * K;
-      b1[j * KS + i] = sketch_entry(seed, trk, t, it, i, j);
+      b1[j * LDK + i] = sketch_entry(seed, trk, t, it, i, j);
     }
     __syncthreads();
     // Y = Delta A Omega -> b2
     lds_gemm(K, d, K,
-             [&](int i, int k) { return (i < K && k < K) ? b0[i * KS + k] : cz(); },
-             [&](int k, int j) { return (k < K && j < d) ? b1[j * KS + k] : cz(); },
-             [&](int i, int j, float2 v) { b2[j * KS + i] = v; });
+             [&](int i, int k) { return (i < K && k < K) ? b0[i * LDK + k] : cz(); },
+             [&](int k, int j) { return (k < K && j < d) ? b1[j * LDK + k] : cz(); },
+             [&](int i, int j, float2 v) { b2[j * LDK + i] = v; });
     __syncthreads();
     t_sk += clock64() - c_mark; c_mark = clock64();
     // Householder QR of Y (b2): reflector j lands in column j of b2.  Wave 0
@@ -349,8 +362,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     }
     qrcols += d;
     // Q = H_0 ... H_{d-1} [I_d; 0] -> b1
-    for (int e = tid; e < d * KS; e += NTH) {
-      const int j = e / KS, i = e - j * KS;
+    for (int e = tid; e < d * LDK; e += NTH) {
+      const int j = e / LDK, i = e - j * LDK;
       b1[e] = (i == j) ? make_float2(1.f, 0.f) : cz();
     }
     for (int j = d - 1; j >= 0; --j) {
@@ -360,15 +373,15 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     __syncthreads();
     // Z = Delta A Q -> b2
     lds_gemm(K, d, K,
-             [&](int i, int k) { return (i < K && k < K) ? b0[i * KS + k] : cz(); },
-             [&](int k, int j) { return (k < K && j < d) ? b1[j * KS + k] : cz(); },
-             [&](int i, int j, float2 v) { b2[j * KS + i] = v; });
+             [&](int i, int k) { return (i < K && k < K) ? b0[i * LDK + k] : cz(); },
+             [&](int k, int j) { return (k < K && j < d) ? b1[j * LDK + k] : cz(); },
+             [&](int i, int j, float2 v) { b2[j * LDK + i] = v; });
     __syncthreads();
     // ||B||_F^2 = ||Z||_F^2: does any r reach the target?
     double zp = 0.0;
     for (int e = tid; e < K * d; e += NTH) {
       const int j = e / K, i = e - j * K;
-      zp += (double)cabs2(b2[j * KS + i]);
+      zp += (double)cabs2(b2[j * LDK + i]);
     }
     const double tot = block_sum(zp, sm.red);
     t_qr += clock64() - c_mark; c_mark = clock64();
@@ -403,16 +416,16 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     // A^-1 -> b0
     for (int e = tid; e < K * K; e += NTH) {
       const int i = e / K, j = e - i * K;
-      b0[i * KS + j] = td->Ainv[e];
+      b0[i * LDK + j] = td->Ainv[e];
     }
     __syncthreads();
     const int* ord = sm.order;
     float2* pm = sm.pm;
     // step 1: P = A^-1 U
     lds_gemm(K, r, K,
-             [&](int i, int k) { return (i < K && k < K) ? b0[i * KS + k] : cz(); },
-             [&](int k, int c) { return (k < K && c < r) ? b1[ord[c] * KS + k] : cz(); },
-             [&](int i, int c, float2 v) { pm[c * KS + i] = v; });
+             [&](int i, int k) { return (i < K && k < K) ? b0[i * LDK + k] : cz(); },
+             [&](int k, int c) { return (k < K && c < r) ? b1[ord[c] * LDK + k] : cz(); },
+             [&](int i, int c, float2 v) { pm[c * LDK + i] = v; });
     __syncthreads();
     // step 2: C = I + V~^H P (r x r), and V~^H A^-1 (r x K); tiles held in
     // registers until every wave has finished reading U and V~
@@ -427,15 +440,15 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       my_ti = u / ncol; my_tj = u - my_ti * ncol; my_kind = ct ? 0 : 1;
       auto la = [&](int rr, int k) {
         const int a = my_ti * 16 + rr;
-        return (a < r && k < K) ? cconj(b2[ord[a] * KS + k]) : cz();
+        return (a < r && k < K) ? cconj(b2[ord[a] * LDK + k]) : cz();
       };
       auto lbc = [&](int k, int cc) {
         const int b = my_tj * 16 + cc;
-        return (k < K && b < r) ? pm[b * KS + k] : cz();
+        return (k < K && b < r) ? pm[b * LDK + k] : cz();
       };
       auto lbq = [&](int k, int cc) {
         const int j = my_tj * 16 + cc;
-        return (k < K && j < K) ? b0[k * KS + j] : cz();
+        return (k < K && j < K) ? b0[k * LDK + j] : cz();
       };
       if (ct) ctile16(la, lbc, 0, K, dr, di); else ctile16(la, lbq, 0, K, dr, di);
     }
@@ -513,9 +526,9 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       // steps 4-5: A^-1 <- A^-1 - P X
       float2* out = td->Ainv;
       lds_gemm(K, K, r,
-               [&](int i, int a) { return (i < K && a < r) ? pm[a * KS + i] : cz(); },
+               [&](int i, int a) { return (i < K && a < r) ? pm[a * LDK + i] : cz(); },
                [&](int a, int j) { return (a < r && j < K) ? d2f(aug[a * ldg + r + j]) : cz(); },
-               [&](int i, int j, float2 v) { out[(size_t)i * K + j] = csub(b0[i * KS + j], v); });
+               [&](int i, int j, float2 v) { out[(size_t)i * K + j] = csub(b0[i * LDK + j], v); });
     }
     __syncthreads();
   }
@@ -524,13 +537,13 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     if (tid == 0) sm.bad = 0;
     for (int e = tid; e < K * K; e += NTH) {
       const int i = e / K, j = e - i * K;
-      b0[i * KS + j] = td->Anew[e];
+      b0[i * LDK + j] = td->Anew[e];
     }
     __syncthreads();
-    gj_inverse_hpd_mfma(b0, K, KS, b1, b1 + 16 * KS, b1 + 32 * KS, &sm.bad);
+    gj_inverse_hpd_mfma(b0, K, LDK, b1, b1 + 16 * KS, b1 + 32 * KS, &sm.bad);
     for (int e = tid; e < K * K; e += NTH) {
       const int i = e / K, j = e - i * K;
-      td->Ainv[e] = b0[i * KS + j];
+      td->Ainv[e] = b0[i * LDK + j];
     }
     if (tid == 0 && sm.bad) atomicCAS(err, 0, sm.bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
   }

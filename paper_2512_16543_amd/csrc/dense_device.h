@@ -6,11 +6,17 @@
 
 // Column pair (p, q) of round k, slot m, of the round-robin ordering over n
 // (even) columns: every pair meets once in n-1 rounds.
+// With 0 <= k < n-1 and 0 < m < n/2 both sums stay within one period, so a
+// conditional add or subtract replaces the modulo (an integer division is
+// dozens of VALU instructions).
 __device__ __forceinline__ void rr_pair(int k, int m, int n, int* p, int* q) {
   if (m == 0) { *p = k; *q = n - 1; return; }
   const int n1 = n - 1;
-  *p = (k + m) % n1;
-  *q = (k - m + n1) % n1;
+  int a = k + m, b = k - m;
+  if (a >= n1) a -= n1;
+  if (b < 0) b += n1;
+  *p = a;
+  *q = b;
 }
 
 template <class T> struct CX;
