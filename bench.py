@@ -71,6 +71,23 @@ def d_sequence(iters, k0, p, K):
     return out
 
 
+def measured_traffic(kernel_file_stem):
+    """HBM bytes per launch from the committed counter summary
+    (profiles/traffic_<stem>.json: FETCH_SIZE and WRITE_SIZE per dispatch,
+    scaled by a copy of known size), or None when the kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_file_stem}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_2512_16543_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def arsvd_flops(K, info, k_init, p):
     """Algorithmic real flops of one arSVD/Woodbury launch: the two sketch
     products (Delta A Omega, Delta A Q: 8 K^2 d each) per iteration, and on
@@ -256,9 +273,13 @@ def main():
         per_launch = 0.0
         unit_note = "n/a"
     achieved = per_launch / avg_s / 1e12
+    traffic = None
+    if dom == "arsvd_wb" and (K, N) == (64, 256) and a.config == "c2":
+        traffic = measured_traffic("k_arsvd_wb_k64_n256")
     out["roofline"] = {"kernel": dom, "bound": "mfma", "achieved": achieved,
                        "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                       "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": traffic,
+                       "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                        "flops_per_launch": per_launch, "avg_launch_us": avg_s * 1e6,
                        "work": unit_note}
     print(f"[bench] profiled pass done: dominant {dom}", file=sys.stderr, flush=True)
