@@ -40,6 +40,8 @@ def parse():
                     help="c2 (default), c1, c5 (K=256 N=1024 track) or mix (multi-track batch)")
     ap.add_argument("--eta", type=float, default=None)
     ap.add_argument("--policy", choices=["fixed", "warm"], default="fixed")
+    ap.add_argument("--precision", choices=["fp32", "bf16", "bf16x3"], default="fp32",
+                    help="operand format of the Gram and precoder products")
     ap.add_argument("--early-fallback", action="store_true",
                     help="policy: end Alg. 1 once d passes the Woodbury limit without success")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -61,6 +63,9 @@ def parse():
     ap.add_argument("--serve-batch", type=int, default=1024)
     ap.add_argument("--serve-wait-us", type=float, default=1000.0)
     return ap.parse_args()
+
+
+PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 
 
 def d_sequence(iters, k0, p, K):
@@ -145,7 +150,8 @@ def main():
     def params(track_id):
         return rzf.default_params(k_init=cfg.k_init, p=cfg.p, P=cfg.P, seed=cfg.seed,
                                   track_id=track_id, reset_period=cfg.reset_period,
-                                  kinit_policy=policy, early_fallback=int(a.early_fallback))
+                                  kinit_policy=policy, early_fallback=int(a.early_fallback),
+                                  precision=PRECISIONS[a.precision])
 
     def run_wb(H, steps, track_id, want_info=False, per_step_sync=False):
         tr = ctx.init(H[0], cfg.alpha, params(track_id))
@@ -172,9 +178,14 @@ def main():
         lat, Rs = [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        prec = PRECISIONS[a.precision]
+        items = [ctx.full_items([H[t]], [cfg.alpha], cfg.P, [W], prec) for t in range(steps + 1)] if prec else None
         for t in range(1, steps + 1):
             ts = time.perf_counter()
-            ctx.full(H[t], cfg.alpha, cfg.P, W)
+            if items is None:
+                ctx.full(H[t], cfg.alpha, cfg.P, W)
+            else:
+                ctx.full_batch_raw(items[t])
             if per_step_sync:
                 Rs.append(ctx.sum_rate(H[t], W, cfg.P, cfg.sigma2, rates))
                 lat.append(time.perf_counter() - ts)
@@ -207,7 +218,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32",
+        "dtype": "fp32" if a.precision == "fp32" else f"fp32 ({a.precision} Gram/precoder operands)",
         "data": "synthetic (seeded LEO channel track standing in for the paper's simulated pass)",
         "config": {
             "workload": (f"{a.config}: single LEO track, K={K} users, N={N} antennas "
@@ -319,12 +330,14 @@ def batched(a, cfgs, eta, policy):
     trs = [ctx.init(Hs[b][0], c.alpha,
                     rzf.default_params(k_init=c.k_init, p=c.p, P=c.P, seed=c.seed, track_id=b,
                                        reset_period=c.reset_period, kinit_policy=policy,
-                                       early_fallback=int(a.early_fallback)))
+                                       early_fallback=int(a.early_fallback),
+                                       precision=PRECISIONS[a.precision]))
            for b, c in enumerate(cfgs)]
     P = cfgs[0].P
     s2 = [c.sigma2 for c in cfgs]
     upd = [ctx.update_items(trs, [Hs[b][t] for b in range(B)], Wl) for t in range(T)]
-    full = [ctx.full_items([Hs[b][t] for b in range(B)], [c.alpha for c in cfgs], P, Wl) for t in range(T)]
+    full = [ctx.full_items([Hs[b][t] for b in range(B)], [c.alpha for c in cfgs], P, Wl, PRECISIONS[a.precision])
+            for t in range(T)]
     rt = [ctx.rate_items([Hs[b][t] for b in range(B)], Wl, rl, sums, s2) for t in range(T)]
 
     def run(kind, t0, t1):
@@ -391,11 +404,13 @@ def mix(a, policy):
         "metric": "RZF precoder updates/s, multi-track mix (K 16..128, N 64/256/1024), WB-arSVD vs full inverse",
         "value": res["value"], "unit": "updates/s", "n_gpus": 1, "steps": res["steps"],
         "warmup": 2, "ms_per_step": res["ms_per_batched_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32" if a.precision == "fp32" else f"fp32 ({a.precision} Gram/precoder operands)",
         "data": "synthetic (seeded LEO channel tracks)",
         "config": {"workload": (f"mix: {len(cfgs)} tracks, K uniform 16..128 (mean {Ks.mean():.1f}, "
                                 f"{int((Ks > 64).sum())} above 64), N in {{64, 256, 1024}} "
-                                f"(mean {Ns.mean():.0f}), SNR 0..20 dB, eta={eta}, FP64 reset every 100 steps; "
+                                f"(mean {Ns.mean():.0f}), SNR 0..20 dB, eta={eta}, FP64 reset every 100 steps, "
+                                f"{a.precision} operands; "
                                 f"step = one batched update of every track + batched sum rate"),
                    "tracks": len(cfgs), "eta": eta},
     }

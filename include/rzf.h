@@ -67,6 +67,11 @@ typedef enum {
 
 typedef enum { RZF_KINIT_FIXED = 0, RZF_KINIT_WARM = 1 } rzf_kinit_policy;
 
+/* Operand format of the Gram (eqs. (7)-(9)) and precoder (eq. (5)) products;
+ * inputs and outputs stay complex64, accumulation FP32.  BF16X3 splits each
+ * operand into BF16 hi + lo and forms hi*hi + hi*lo + lo*hi. */
+typedef enum { RZF_PREC_FP32 = 0, RZF_PREC_BF16 = 1, RZF_PREC_BF16X3 = 2 } rzf_precision;
+
 /* Parameters of one track; rzf_params_default fills the paper's values. */
 typedef struct {
   int k_init;           /* initial rank estimate of Alg. 1 (Table IV: 2)          */
@@ -89,6 +94,7 @@ typedef struct {
                            exceeds the Woodbury limit (switch_ratio * K and the
                            rank cap) and misses the energy target ends Alg. 1;
                            the step inverts directly (path FULL_RANK, k_est = d)  */
+  int precision;        /* rzf_precision of the Gram and precoder products (FP32) */
 } rzf_params;
 
 /* Outcome of one rzf_update. */
@@ -104,7 +110,8 @@ typedef struct {
 const char* rzf_status_string(rzf_status s);
 
 /* Fill *p with k_init=2, p=5, i_max=0, switch_ratio=0.5, reset_period=0,
- * P=1, seed=0, track_id=0, kinit_policy=FIXED, early_fallback=0.
+ * P=1, seed=0, track_id=0, kinit_policy=FIXED, early_fallback=0,
+ * precision=FP32.
  * RZF_E_INVALID if p is NULL. */
 rzf_status rzf_params_default(rzf_params* p);
 
@@ -176,9 +183,11 @@ typedef struct {
   double alpha, P;
   rzf_c32* W;              /* device, N x K, leading dimension ldw */
   int ldw;
+  int precision;           /* rzf_precision of the Gram and precoder products */
 } rzf_full_item;
 
-/* rzf_full for n independent snapshots in one set of launches.  Scratch for
+/* rzf_full for n independent snapshots in one set of launches (each item with
+ * its own operand precision; rzf_full itself is FP32).  Scratch for
  * the Gram matrices comes from the arena (grown on demand, RZF_E_NOMEM if it
  * cannot).  1 <= n <= RZF_BATCH_MAX. */
 rzf_status rzf_full_batch(rzf_ctx* ctx, int n, const rzf_full_item* items);

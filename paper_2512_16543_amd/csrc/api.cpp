@@ -160,7 +160,8 @@ bool params_valid(const rzf_params* p) {
          std::isfinite(p->switch_ratio) && p->switch_ratio > 0.0 && p->switch_ratio <= 1.0 &&
          p->reset_period >= 0 && std::isfinite(p->P) && p->P > 0.0 &&
          (p->kinit_policy == RZF_KINIT_FIXED || p->kinit_policy == RZF_KINIT_WARM) &&
-         (p->early_fallback == 0 || p->early_fallback == 1);
+         (p->early_fallback == 0 || p->early_fallback == 1) &&
+         p->precision >= RZF_PREC_FP32 && p->precision <= RZF_PREC_BF16X3;
 }
 
 int default_imax(int K, int k_init, int p) {
@@ -208,6 +209,7 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
   d.k_init = prm.k_init; d.p = prm.p; d.i_max = t->i_max; d.kinit_policy = prm.kinit_policy;
   d.seed = prm.seed; d.track_id = prm.track_id;
   d.early_fallback = prm.early_fallback;
+  d.prec = prm.precision;
   // Alg. 2's switch and the end of the Woodbury workspace (max(32, K/2) ranks)
   d.wb_limit = std::min((int)std::floor(prm.switch_ratio * K), std::max(WB_RMAX, K / 2));
   d.Ainv = reinterpret_cast<float2*>(base + L.ainv);
@@ -239,7 +241,7 @@ struct TrackBlob {
   int32_t step, since_reset, last_r, pad;
 };
 const char BLOB_MAGIC[8] = {'R', 'Z', 'F', 'T', 'R', 'A', 'C', 'K'};
-constexpr uint32_t BLOB_VERSION = 1;
+constexpr uint32_t BLOB_VERSION = 2;   // 2: rzf_params gained early_fallback and precision
 
 size_t blob_bytes(int K, int N) {
   return sizeof(TrackBlob) + sizeof(float2) * ((size_t)K * K + (size_t)K * N);
@@ -429,12 +431,12 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
     timed(c, KN_GRAM64, [&] { launch_gram64(gj, nullptr, 1, K, s); });
     timed(c, KN_INV64, [&] { inv64_any(ij, c->d_err, s); });
   } else {
-    const GramJob gj{Hf, d.Hprev, d.Anew, d.dA, K, N, ldh, N, (float)t->alpha};
+    const GramJob gj{Hf, d.Hprev, d.Anew, d.dA, K, N, ldh, N, (float)t->alpha, d.prec};
     const ArsvdJob aj{t->d_desc, nullptr, tol, step, t->i_max};
     timed(c, KN_GRAM, [&] { launch_gram(gj, nullptr, 1, K, s); });
     timed(c, KN_ARSVD, [&] { arsvd_any(aj, K, c->d_err, s); });
   }
-  const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw};
+  const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw, d.prec};
   const ScaleJob sj{Wf, d.wpart, d.P, K, N, ldw, precoder_blocks(N)};
   timed(c, KN_PRECODER, [&] { launch_precoder(pj, nullptr, 1, N, s); });
   timed(c, KN_SCALE, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
@@ -519,10 +521,10 @@ rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, 
       (K > KS ? i64b : i64).push_back(Inv64Job{d.A64, d.Ainv, &t->d_desc->info, nullptr, K});
       maxKr = std::max(maxKr, K);
     } else {
-      gj.push_back(GramJob{Hf, d.Hprev, d.Anew, d.dA, K, N, items[i].ldh, N, (float)t->alpha});
+      gj.push_back(GramJob{Hf, d.Hprev, d.Anew, d.dA, K, N, items[i].ldh, N, (float)t->alpha, d.prec});
       (K > KS ? ajb : aj).push_back(ArsvdJob{t->d_desc, nullptr, tol, t->t + 1, t->i_max});
     }
-    pj.push_back(PrecJob{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, items[i].ldh, items[i].ldw});
+    pj.push_back(PrecJob{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, items[i].ldh, items[i].ldw, d.prec});
     sj.push_back(ScaleJob{Wf, d.wpart, d.P, K, N, items[i].ldw, precoder_blocks(N)});
     maxK = std::max(maxK, K);
     maxN = std::max(maxN, N);
@@ -585,6 +587,7 @@ rzf_status check_full_items(int n, const rzf_full_item* items) {
       return RZF_E_SHAPE;
     if (!std::isfinite(it.alpha) || it.alpha < 0.0 || !std::isfinite(it.P) || it.P <= 0.0)
       return RZF_E_INVALID;
+    if (it.precision < RZF_PREC_FP32 || it.precision > RZF_PREC_BF16X3) return RZF_E_INVALID;
   }
   return RZF_OK;
 }
@@ -624,9 +627,9 @@ rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items) {
     double* wp = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * precoder_blocks(it.N));
     const float2* Hf = reinterpret_cast<const float2*>(it.H);
     float2* Wf = reinterpret_cast<float2*>(it.W);
-    gj[i] = GramJob{Hf, nullptr, A, nullptr, it.K, it.N, it.ldh, 0, (float)it.alpha};
+    gj[i] = GramJob{Hf, nullptr, A, nullptr, it.K, it.N, it.ldh, 0, (float)it.alpha, it.precision};
     (it.K > KS ? vjb : vj).push_back(Inv32Job{A, A, it.K});
-    pj[i] = PrecJob{Hf, A, Wf, wp, nullptr, it.K, it.N, it.ldh, it.ldw};
+    pj[i] = PrecJob{Hf, A, Wf, wp, nullptr, it.K, it.N, it.ldh, it.ldw, it.precision};
     sj[i] = ScaleJob{Wf, wp, it.P, it.K, it.N, it.ldw, precoder_blocks(it.N)};
   }
   const size_t bytes = (sizeof(GramJob) + sizeof(Inv32Job) + sizeof(PrecJob) + sizeof(ScaleJob)) * n + 64;
@@ -750,8 +753,8 @@ rzf_status rzf_full(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   hipStream_t s = c->stream;
   const float2* Hf = reinterpret_cast<const float2*>(H);
   float2* Wf = reinterpret_cast<float2*>(W);
-  const GramJob gj{Hf, nullptr, c->d_fullA, nullptr, K, N, ldh, 0, (float)alpha};
-  const PrecJob pj{Hf, c->d_fullAinv, Wf, c->d_fullwpart, nullptr, K, N, ldh, ldw};
+  const GramJob gj{Hf, nullptr, c->d_fullA, nullptr, K, N, ldh, 0, (float)alpha, RZF_PREC_FP32};
+  const PrecJob pj{Hf, c->d_fullAinv, Wf, c->d_fullwpart, nullptr, K, N, ldh, ldw, RZF_PREC_FP32};
   const ScaleJob sj{Wf, c->d_fullwpart, P, K, N, ldw, precoder_blocks(N)};
   timed(c, KN_GRAM, [&] { launch_gram(gj, nullptr, 1, K, s); });
   const Inv32Job vj{c->d_fullA, c->d_fullAinv, K};

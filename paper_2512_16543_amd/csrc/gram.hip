@@ -8,6 +8,9 @@
 // error proportional to ||Delta A|| rather than to ||A'||, which the
 // difference A' - A would not (the per-step change is ~1e-4 of A).
 //
+// With the BF16 precision options the products take BF16 operands (or
+// BF16 hi/lo splits, three products each) with FP32 accumulation.
+//
 // Both outputs are Hermitian, so only the lower 16x16 tiles are computed and
 // mirrored.  A workgroup of four wavefronts owns one output tile and splits
 // the length-N reduction between its waves; the partial tiles are summed in
@@ -50,20 +53,52 @@ __global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) 
   const bool oki = ri < K, okj = rj < K;
 
   floatx4 ar = zero4(), ai = zero4(), gr = zero4(), gi = zero4();
-  for (int n0 = wid * 16; n0 < N; n0 += 64) {
+  if (jb.prec == RZF_PREC_FP32) {
+    for (int n0 = wid * 16; n0 < N; n0 += 64) {
 #pragma unroll
-    for (int k = 0; k < 16; k += 4) {
-      const int n = n0 + k + kq;
-      const bool okn = n < N;
-      const float2 ti = (oki && okn) ? Ht[(size_t)ri * ldh + n] : cz();
-      const float2 tj = (okj && okn) ? Ht[(size_t)rj * ldh + n] : cz();
-      mac_conj(ti, tj, ar, ai);                         // H_t H_t^H
+      for (int k = 0; k < 16; k += 4) {
+        const int n = n0 + k + kq;
+        const bool okn = n < N;
+        const float2 ti = (oki && okn) ? Ht[(size_t)ri * ldh + n] : cz();
+        const float2 tj = (okj && okn) ? Ht[(size_t)rj * ldh + n] : cz();
+        mac_conj(ti, tj, ar, ai);                         // H_t H_t^H
+        if (DELTA) {
+          const float2 pi = (oki && okn) ? Hp[(size_t)ri * ldp + n] : cz();
+          const float2 pj = (okj && okn) ? Hp[(size_t)rj * ldp + n] : cz();
+          const float2 di = csub(ti, pi), dj = csub(tj, pj);
+          mac_conj(pi, dj, gr, gi);                       // H_{t-1} dH^H
+          mac_conj(di, tj, gr, gi);                       // dH H_t^H
+        }
+      }
+    }
+  } else {
+    // BF16 operands, 32 antennas per product; dH is formed in FP32 before
+    // rounding, so the correction keeps its error relative to ||Delta A||
+    const bool x3 = jb.prec == RZF_PREC_BF16X3;
+    for (int n0 = wid * 32; n0 < N; n0 += 128) {
+      const int nb = n0 + 8 * kq;
+      float2 ti[8], tj[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int n = nb + e;
+        const bool okn = n < N;
+        ti[e] = (oki && okn) ? Ht[(size_t)ri * ldh + n] : cz();
+        tj[e] = (okj && okn) ? Ht[(size_t)rj * ldh + n] : cz();
+      }
+      cmac8_bf16(ti, tj, false, true, x3, ar, ai);       // H_t H_t^H
       if (DELTA) {
-        const float2 pi = (oki && okn) ? Hp[(size_t)ri * ldp + n] : cz();
-        const float2 pj = (okj && okn) ? Hp[(size_t)rj * ldp + n] : cz();
-        const float2 di = csub(ti, pi), dj = csub(tj, pj);
-        mac_conj(pi, dj, gr, gi);                       // H_{t-1} dH^H
-        mac_conj(di, tj, gr, gi);                       // dH H_t^H
+        float2 pi[8], dj[8], di[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int n = nb + e;
+          const bool okn = n < N;
+          pi[e] = (oki && okn) ? Hp[(size_t)ri * ldp + n] : cz();
+          const float2 pj = (okj && okn) ? Hp[(size_t)rj * ldp + n] : cz();
+          di[e] = csub(ti[e], pi[e]);
+          dj[e] = csub(tj[e], pj);
+        }
+        cmac8_bf16(pi, dj, false, true, x3, gr, gi);     // H_{t-1} dH^H
+        cmac8_bf16(di, tj, false, true, x3, gr, gi);     // dH H_t^H
       }
     }
   }

@@ -1,6 +1,9 @@
 // Precoder W = H^H X with its power normalisation ||W||_F^2 = P (Sec. II,
 // eq. (5)), where X is the stored inverse of the Gram matrix.
 //
+// With the BF16 precision options the product takes BF16 operands (or BF16
+// hi/lo splits, three products each) with FP32 accumulation.
+//
 // W is N x K (row-major).  A workgroup of four wavefronts owns 16 rows of W
 // (16 antennas); wave w computes the 16x16 tiles w, w+4, ... along K with a
 // length-K reduction on the FP32 matrix cores.  The block also writes its
@@ -29,16 +32,33 @@ __global__ __launch_bounds__(256) void k_precoder(PrecJob one, const PrecJob* ma
   for (int kt = wid; kt * 16 < K; kt += 4) {
     const int k0 = kt * 16;
     floatx4 dr = zero4(), di = zero4();
-    // A(n, i) = conj(H[i][n]);  B(i, k) = X[i][k]
-    auto la = [&](int rr, int i) -> float2 {
-      const int n = n0 + rr;
-      return (n < N && i < K) ? cconj(H[(size_t)i * ldh + n]) : cz();
-    };
-    auto lb = [&](int i, int c) -> float2 {
-      const int k = k0 + c;
-      return (i < K && k < K) ? X[(size_t)i * K + k] : cz();
-    };
-    ctile16(la, lb, 0, K, dr, di);
+    if (jb.prec == RZF_PREC_FP32) {
+      // A(n, i) = conj(H[i][n]);  B(i, k) = X[i][k]
+      auto la = [&](int rr, int i) -> float2 {
+        const int n = n0 + rr;
+        return (n < N && i < K) ? cconj(H[(size_t)i * ldh + n]) : cz();
+      };
+      auto lb = [&](int i, int c) -> float2 {
+        const int k = k0 + c;
+        return (i < K && k < K) ? X[(size_t)i * K + k] : cz();
+      };
+      ctile16(la, lb, 0, K, dr, di);
+    } else {
+      // BF16 operands, 32 users of the reduction per product
+      const bool x3 = jb.prec == RZF_PREC_BF16X3;
+      const int rr = lane & 15, kq = lane >> 4;
+      const int n = n0 + rr, k = k0 + rr;
+      for (int i0 = 0; i0 < K; i0 += 32) {
+        float2 a[8], b[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int i = i0 + 8 * kq + e;
+          a[e] = (n < N && i < K) ? H[(size_t)i * ldh + n] : cz();
+          b[e] = (i < K && k < K) ? X[(size_t)i * K + k] : cz();
+        }
+        cmac8_bf16(a, b, true, false, x3, dr, di);
+      }
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int n = n0 + tile_row(v), k = k0 + tile_col();

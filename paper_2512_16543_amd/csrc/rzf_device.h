@@ -224,3 +224,56 @@ __device__ __forceinline__ void wave_sync() {
 // Row / column of result register v in the calling lane.
 __device__ __forceinline__ int tile_row(int v) { return 4 * ((threadIdx.x & 63) >> 4) + v; }
 __device__ __forceinline__ int tile_col() { return threadIdx.x & 15; }
+
+// ------------------------------------------- BF16 operands (precision option)
+// v_mfma_f32_16x16x32_bf16: lane l supplies A[l%16][8*(l/16)+e] and
+// B[8*(l/16)+e][l%16], e = 0..7, and receives D[4*(l/16)+v][l%16] (the FP32
+// instruction's result layout).  FP32 operands are rounded to BF16 (one
+// product per real product), or split x = hi + lo with hi = bf16(x) and
+// lo = bf16(x - hi) and multiplied as hi*hi + hi*lo + lo*hi (three products),
+// which carries about 16 significant bits per operand.  Accumulation is FP32.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct Bf16Pair { bf16x8 h, l; };
+
+__device__ __forceinline__ Bf16Pair bf16_split8(const float v[8], bool x3) {
+  Bf16Pair p;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)v[e];
+    p.h[e] = h;
+    p.l[e] = x3 ? (__bf16)(v[e] - (float)h) : (__bf16)0.0f;
+  }
+  return p;
+}
+
+__device__ __forceinline__ floatx4 mfma_bf16x(const Bf16Pair& a, const Bf16Pair& b, floatx4 c, bool x3) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
+  if (x3) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, c, 0, 0, 0);
+  }
+  return c;
+}
+
+// D += op(A) op(B) for the calling lane's 8-element slices a[e] = A[row][k+e]
+// and b[e] = B[k+e][col] of a complex 16 x 32 by 32 x 16 product; op
+// conjugates when the flag is set.
+__device__ __forceinline__ void cmac8_bf16(const float2 a[8], const float2 b[8], bool conja, bool conjb,
+                                           bool x3, floatx4& dr, floatx4& di) {
+  float ar[8], ai[8], nai[8], br[8], bi[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    ar[e] = a[e].x;
+    ai[e] = conja ? -a[e].y : a[e].y;
+    nai[e] = -ai[e];
+    br[e] = b[e].x;
+    bi[e] = conjb ? -b[e].y : b[e].y;
+  }
+  const Bf16Pair Ar = bf16_split8(ar, x3), Ai = bf16_split8(ai, x3), nAi = bf16_split8(nai, x3);
+  const Bf16Pair Br = bf16_split8(br, x3), Bi = bf16_split8(bi, x3);
+  dr = mfma_bf16x(Ar, Br, dr, x3);
+  dr = mfma_bf16x(nAi, Bi, dr, x3);
+  di = mfma_bf16x(Ar, Bi, di, x3);
+  di = mfma_bf16x(Ai, Br, di, x3);
+}

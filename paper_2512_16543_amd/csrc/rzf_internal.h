@@ -26,6 +26,7 @@ struct TrackDesc {
   double alpha, P, switch_ratio;
   int k_init, p, i_max, kinit_policy;
   int early_fallback, wb_limit;   // policy flag; largest rank the Woodbury branch takes
+  int prec, pad0_;                // rzf_precision of the Gram and precoder operands
   uint64_t seed, track_id;
   float2* Ainv;    // K x K, ld K: stored inverse
   float2* Hprev;   // K x N, ld N: previous snapshot
@@ -58,6 +59,7 @@ struct GramJob {
   const float2* Ht; const float2* Hp; float2* Anew; float2* dA;
   int K, N, ldh, ldp;
   float alpha;
+  int prec;        // rzf_precision of the operands
 };
 struct Gram64Job {
   const float2* H; double2* A;
@@ -81,6 +83,7 @@ struct ArsvdJob {
 struct PrecJob {
   const float2* H; const float2* X; float2* W; double* wpart; float2* Hcopy;
   int K, N, ldh, ldw;
+  int prec;        // rzf_precision of the operands
 };
 struct ScaleJob {
   float2* W; const double* wpart;

@@ -107,7 +107,8 @@ void dispatch_loop(rzf_server* S) {
         std::vector<rzf_full_item> items(n);
         for (int i = 0; i < n; ++i) {
           const Request& r = b.reqs[i];
-          items[i] = rzf_full_item{r.tr->K, r.tr->N, r.H, r.ldh, r.tr->alpha, r.tr->prm.P, r.W, r.ldw};
+          items[i] = rzf_full_item{r.tr->K, r.tr->N, r.H, r.ldh, r.tr->alpha, r.tr->prm.P, r.W, r.ldw,
+                                   r.tr->prm.precision};
         }
         b.st = full_batch_locked(c, n, items.data());
       } else {

@@ -23,6 +23,7 @@ RZF_E_DEVICE = 6
 
 PATH_NOOP, PATH_WB, PATH_FULL_RANK, PATH_FULL_SINGULAR, PATH_RESET = 0, 1, 2, 3, 4
 KINIT_FIXED, KINIT_WARM = 0, 1
+PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
 KMAX = 256
 NMAX = 4096
 
@@ -31,7 +32,7 @@ class Params(ctypes.Structure):
     _fields_ = [("k_init", ctypes.c_int), ("p", ctypes.c_int), ("i_max", ctypes.c_int),
                 ("switch_ratio", ctypes.c_double), ("reset_period", ctypes.c_int),
                 ("P", ctypes.c_double), ("seed", ctypes.c_uint64), ("track_id", ctypes.c_uint64),
-                ("kinit_policy", ctypes.c_int), ("early_fallback", ctypes.c_int)]
+                ("kinit_policy", ctypes.c_int), ("early_fallback", ctypes.c_int), ("precision", ctypes.c_int)]
 
 
 class UpdateInfo(ctypes.Structure):
@@ -50,7 +51,7 @@ class UpdateItem(ctypes.Structure):
 class FullItem(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int), ("N", ctypes.c_int), ("H", ctypes.c_void_p), ("ldh", ctypes.c_int),
                 ("alpha", ctypes.c_double), ("P", ctypes.c_double), ("W", ctypes.c_void_p),
-                ("ldw", ctypes.c_int)]
+                ("ldw", ctypes.c_int), ("precision", ctypes.c_int)]
 
 
 class RateItem(ctypes.Structure):
@@ -319,7 +320,7 @@ class Context:
         _check(lib().rzf_update_batch(self.h, len(items), items, float(tol)), "rzf_update_batch")
 
     @staticmethod
-    def full_items(Hs, alphas, P, Ws):
+    def full_items(Hs, alphas, P, Ws, precision: int = 0):
         n = len(Hs)
         arr = (FullItem * n)()
         for i in range(n):
@@ -328,6 +329,7 @@ class Context:
             K, N = Hs[i].shape
             arr[i].K, arr[i].N, arr[i].H, arr[i].ldh = K, N, hp, ldh
             arr[i].alpha, arr[i].P, arr[i].W, arr[i].ldw = float(alphas[i]), float(P), wp, ldw
+            arr[i].precision = int(precision)
         return arr
 
     def full_batch_raw(self, items):
@@ -353,17 +355,9 @@ class Context:
         _check(lib().rzf_sum_rate_batch(self.h, len(items), items, float(P), float(sigma2)),
                "rzf_sum_rate_batch")
 
-    def full_batch(self, Hs, alphas, P: float, Ws):
-        n = len(Hs)
-        arr = (FullItem * n)()
-        for i in range(n):
-            hp, ldh = _mat_args(Hs[i])
-            wp, ldw = _mat_args(Ws[i])
-            K, N = Hs[i].shape
-            it = arr[i]
-            it.K, it.N, it.H, it.ldh = K, N, hp, ldh
-            it.alpha, it.P, it.W, it.ldw = float(alphas[i]), float(P), wp, ldw
-        _check(lib().rzf_full_batch(self.h, n, arr), "rzf_full_batch")
+    def full_batch(self, Hs, alphas, P: float, Ws, precision: int = 0):
+        arr = self.full_items(Hs, alphas, P, Ws, precision)
+        _check(lib().rzf_full_batch(self.h, len(Hs), arr), "rzf_full_batch")
 
     def sum_rate_batch(self, Hs, Ws, P: float, sigma2: float, rates=None, sums=None, sigma2s=None):
         """rates: list of float32 device tensors (or None); sums: float64 device

@@ -153,7 +153,7 @@ def _energy_ratios(res):
     return np.concatenate([[0.0], c])
 
 
-def _tie_ok(state, H, eta, gi, io, ot):
+def _tie_ok(state, H, eta, gi, io, ot, band=TIE_BAND):
     """GPU decision gi differs from the oracle's io: accept only when, at the
     first iteration where they can part, a cumulative energy ratio of the
     oracle lies within TIE_BAND of eta."""
@@ -163,7 +163,7 @@ def _tie_ok(state, H, eta, gi, io, ot):
     it = min(gi.iters, io.iters)
     res = orz.arsvd(dA, eta, k_init, prm.p, ot.i_max(), ot.draw(state["t"] + 1), force_iters=it)   # no early stop
     c = np.cumsum(res.sigma ** 2) / res.energy
-    return bool(np.any(np.abs(c - eta) < TIE_BAND))
+    return bool(np.any(np.abs(c - eta) < band))
 
 
 def run_track(ctx, cfg, steps, eta, prm_kw=None):
@@ -174,7 +174,7 @@ def run_track(ctx, cfg, steps, eta, prm_kw=None):
     return run_snapshots(ctx, Hs, cfg.alpha, d, eta)
 
 
-def run_snapshots(ctx, Hs, alpha, d, eta):
+def run_snapshots(ctx, Hs, alpha, d, eta, tie_band=TIE_BAND):
     """GPU and oracle side by side over the snapshots Hs (complex64 values);
     before every step the oracle adopts the GPU's state (one-step parity).
     `d` holds the track parameters.  Returns per-step records."""
@@ -198,7 +198,7 @@ def run_snapshots(ctx, Hs, alpha, d, eta):
         if gi != (io.r, io.iters, io.path):
             assert info.path in (orz.PATH_WB, orz.PATH_FULL_RANK) and io.path in (orz.PATH_WB, orz.PATH_FULL_RANK), \
                 (t, gi, (io.r, io.iters, io.path))
-            assert _tie_ok(state, Hs[t], eta, info, io, ot), (t, gi, (io.r, io.iters, io.path))
+            assert _tie_ok(state, Hs[t], eta, info, io, ot, tie_band), (t, gi, (io.r, io.iters, io.path))
             ot.import_state(state)
             Wo, io = ot.update(Hs[t], eta, force_iters=info.iters, force_r=info.r)
             forced = True
