@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--policy", choices=["fixed", "warm"], default="fixed")
     ap.add_argument("--precision", choices=["fp32", "bf16", "bf16x3"], default="fp32",
                     help="operand format of the Gram and precoder products")
+    ap.add_argument("--error-feedback", action="store_true",
+                    help="policy: sketch Delta A plus the residual earlier truncations left out")
     ap.add_argument("--early-fallback", action="store_true",
                     help="policy: end Alg. 1 once d passes the Woodbury limit without success")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -151,7 +153,7 @@ def main():
         return rzf.default_params(k_init=cfg.k_init, p=cfg.p, P=cfg.P, seed=cfg.seed,
                                   track_id=track_id, reset_period=cfg.reset_period,
                                   kinit_policy=policy, early_fallback=int(a.early_fallback),
-                                  precision=PRECISIONS[a.precision])
+                                  precision=PRECISIONS[a.precision], error_feedback=int(a.error_feedback))
 
     def run_wb(H, steps, track_id, want_info=False, per_step_sync=False):
         tr = ctx.init(H[0], cfg.alpha, params(track_id))
@@ -225,7 +227,8 @@ def main():
                          f"({cfg.nx}x{cfg.nx} UPA), {tcfg.steps} snapshots of {cfg.dt_s * 1e3:g} ms, "
                          f"eta={eta}, FP64 re-inversion every {cfg.reset_period} steps, "
                          f"k_init={cfg.k_init}, p={cfg.p}, {a.policy} k_init policy"
-                         f"{', early fallback' if a.early_fallback else ''}; "
+                         f"{', early fallback' if a.early_fallback else ''}"
+                         f"{', error feedback' if a.error_feedback else ''}; "
                          f"step = update + sum rate, batch of 1 track"),
             "K": K, "N": N, "eta": eta, "batch_tracks": 1, "reset_period": cfg.reset_period,
         },
@@ -302,7 +305,8 @@ def main():
 
     # FP64 CPU oracle on a bounded sample of the same track
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, eta, Hs_np, a.cpu_seconds, policy, int(a.early_fallback))
+        out["cpu_baseline"] = cpu_baseline(cfg, eta, Hs_np, a.cpu_seconds, policy, int(a.early_fallback),
+                                           int(a.error_feedback))
         print(f"[bench] cpu baseline done", file=sys.stderr, flush=True)
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -331,7 +335,8 @@ def batched(a, cfgs, eta, policy):
                     rzf.default_params(k_init=c.k_init, p=c.p, P=c.P, seed=c.seed, track_id=b,
                                        reset_period=c.reset_period, kinit_policy=policy,
                                        early_fallback=int(a.early_fallback),
-                                       precision=PRECISIONS[a.precision]))
+                                       precision=PRECISIONS[a.precision],
+                                       error_feedback=int(a.error_feedback)))
            for b, c in enumerate(cfgs)]
     P = cfgs[0].P
     s2 = [c.sigma2 for c in cfgs]
@@ -597,7 +602,7 @@ def table_v(a):
             "rows": rows}
 
 
-def cpu_baseline(cfg, eta, Hs_np, budget_s, policy, early_fallback=0):
+def cpu_baseline(cfg, eta, Hs_np, budget_s, policy, early_fallback=0, error_feedback=0):
     import numpy as np
     import oracle.rzf as orz
     try:
@@ -608,7 +613,8 @@ def cpu_baseline(cfg, eta, Hs_np, budget_s, policy, early_fallback=0):
     H = Hs_np.astype(np.complex128)
     prm = orz.TrackParams(alpha=cfg.alpha, P=cfg.P, k_init=cfg.k_init, p=cfg.p,
                           reset_period=cfg.reset_period, seed=cfg.seed, track_id=0,
-                          kinit_policy=policy, early_fallback=early_fallback)
+                          kinit_policy=policy, early_fallback=early_fallback,
+                          error_feedback=error_feedback)
     ot = orz.OracleTrack(H[0], prm)
     t0 = time.perf_counter()
     n = 0

@@ -95,6 +95,11 @@ typedef struct {
                            rank cap) and misses the energy target ends Alg. 1;
                            the step inverts directly (path FULL_RANK, k_est = d)  */
   int precision;        /* rzf_precision of the Gram and precoder products (FP32) */
+  int error_feedback;   /* 0: Alg. 2 as printed.  1: the track keeps R, A' minus
+                           the Gram matrix whose inverse is stored (what earlier
+                           truncated updates left out); Alg. 1 sketches
+                           Delta A + R and a Woodbury step leaves R = Delta A + R
+                           - U_r Sigma_r V_r^H; any direct inversion clears R    */
 } rzf_params;
 
 /* Outcome of one rzf_update. */
@@ -111,7 +116,7 @@ const char* rzf_status_string(rzf_status s);
 
 /* Fill *p with k_init=2, p=5, i_max=0, switch_ratio=0.5, reset_period=0,
  * P=1, seed=0, track_id=0, kinit_policy=FIXED, early_fallback=0,
- * precision=FP32.
+ * precision=FP32, error_feedback=0.
  * RZF_E_INVALID if p is NULL. */
 rzf_status rzf_params_default(rzf_params* p);
 

@@ -235,6 +235,7 @@ class TrackParams:
     track_id: int = 0
     kinit_policy: int = KINIT_FIXED
     early_fallback: int = 0     # policy: stop Alg. 1 once d passes the Woodbury limit
+    error_feedback: int = 0     # policy: sketch Delta A + R, R the residual not yet applied
 
 
 @dataclasses.dataclass
@@ -262,6 +263,9 @@ class OracleTrack:
         self.t = 0
         self.since_reset = 0
         self.last_r = 0
+        # error feedback: R = A' of the last step minus the Gram matrix whose
+        # inverse is stored (zero after every direct inversion)
+        self.R = np.zeros((self.K, self.K), dtype=np.complex128)
 
     def i_max(self) -> int:
         p = self.params
@@ -280,12 +284,15 @@ class OracleTrack:
         t = self.t
         dH = H - self.H_prev
         dA = gram_correction(self.H_prev, dH)            # eq. (9)
+        if prm.error_feedback:
+            dA = dA + self.R                             # the change the inverse still lacks
         A_new = gram(H, prm.alpha)                       # eq. (7)
         energy = fro2(dA)
         if prm.reset_period > 0 and self.since_reset + 1 >= prm.reset_period:
             self.Ainv = direct_inverse(A_new)
             info = UpdateInfo(0, 0, PATH_RESET, 0.0, 0.0, 0)
             self.since_reset = 0
+            self.R[:] = 0.0
         else:
             k_init = prm.k_init
             if prm.kinit_policy == KINIT_WARM:
@@ -308,6 +315,13 @@ class OracleTrack:
             else:
                 self.Ainv = direct_inverse(A_new)
                 info.path = PATH_FULL_RANK
+            if prm.error_feedback:
+                if info.path == PATH_WB:                 # what the rank-r update left out
+                    self.R = dA - (res.U * res.s) @ hermitian(res.V)
+                elif info.path == PATH_NOOP:             # nothing applied (dA is zero)
+                    self.R = dA.copy()
+                else:                                    # an exact inverse of A'
+                    self.R[:] = 0.0
             self.since_reset += 1
             self.last_r = res.r
         self.H_prev = H
@@ -316,7 +330,7 @@ class OracleTrack:
 
     def export_state(self):
         return dict(Ainv=self.Ainv.copy(), H_prev=self.H_prev.copy(), t=self.t,
-                    since_reset=self.since_reset, last_r=self.last_r)
+                    since_reset=self.since_reset, last_r=self.last_r, R=self.R.copy())
 
     def import_state(self, st):
         self.Ainv = np.array(st["Ainv"], dtype=np.complex128)
@@ -324,3 +338,5 @@ class OracleTrack:
         self.t = int(st["t"])
         self.since_reset = int(st["since_reset"])
         self.last_r = int(st["last_r"])
+        if "R" in st:
+            self.R = np.array(st["R"], dtype=np.complex128)

@@ -32,7 +32,7 @@ size_t scratch_bytes() {
 }
 
 struct Layout {
-  size_t desc, ainv, hprev, anew, da, a64, wpart, ym, qm, zm, pm, aug, total;
+  size_t desc, ainv, hprev, anew, da, a64, wpart, rfb, ym, qm, zm, pm, aug, total;
 };
 
 Layout track_layout(int K, int N) {
@@ -45,6 +45,7 @@ Layout track_layout(int K, int N) {
   L.da = o; o += align_up(sizeof(float2) * K * K);
   L.a64 = o; o += align_up(sizeof(double2) * K * K);
   L.wpart = o; o += align_up(sizeof(double) * precoder_blocks(N));
+  L.rfb = o; o += align_up(sizeof(float2) * K * K);
   if (K > KS) {
     // working set of the large-track kernels
     L.ym = o; o += align_up(sizeof(float2) * K * K);
@@ -161,7 +162,8 @@ bool params_valid(const rzf_params* p) {
          p->reset_period >= 0 && std::isfinite(p->P) && p->P > 0.0 &&
          (p->kinit_policy == RZF_KINIT_FIXED || p->kinit_policy == RZF_KINIT_WARM) &&
          (p->early_fallback == 0 || p->early_fallback == 1) &&
-         p->precision >= RZF_PREC_FP32 && p->precision <= RZF_PREC_BF16X3;
+         p->precision >= RZF_PREC_FP32 && p->precision <= RZF_PREC_BF16X3 &&
+         (p->error_feedback == 0 || p->error_feedback == 1);
 }
 
 int default_imax(int K, int k_init, int p) {
@@ -210,6 +212,7 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
   d.seed = prm.seed; d.track_id = prm.track_id;
   d.early_fallback = prm.early_fallback;
   d.prec = prm.precision;
+  d.error_feedback = prm.error_feedback;
   // Alg. 2's switch and the end of the Woodbury workspace (max(32, K/2) ranks)
   d.wb_limit = std::min((int)std::floor(prm.switch_ratio * K), std::max(WB_RMAX, K / 2));
   d.Ainv = reinterpret_cast<float2*>(base + L.ainv);
@@ -218,6 +221,7 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
   d.dA = reinterpret_cast<float2*>(base + L.da);
   d.A64 = reinterpret_cast<double2*>(base + L.a64);
   d.wpart = reinterpret_cast<double*>(base + L.wpart);
+  d.Rfb = reinterpret_cast<float2*>(base + L.rfb);
   if (K > KS) {
     d.Ym = reinterpret_cast<float2*>(base + L.ym);
     d.Qm = reinterpret_cast<float2*>(base + L.qm);
@@ -241,10 +245,11 @@ struct TrackBlob {
   int32_t step, since_reset, last_r, pad;
 };
 const char BLOB_MAGIC[8] = {'R', 'Z', 'F', 'T', 'R', 'A', 'C', 'K'};
-constexpr uint32_t BLOB_VERSION = 2;   // 2: rzf_params gained early_fallback and precision
+constexpr uint32_t BLOB_VERSION = 3;   // 3: params gained early_fallback, precision, error
+                                       // feedback; the residual R follows H_prev
 
 size_t blob_bytes(int K, int N) {
-  return sizeof(TrackBlob) + sizeof(float2) * ((size_t)K * K + (size_t)K * N);
+  return sizeof(TrackBlob) + sizeof(float2) * (2 * (size_t)K * K + (size_t)K * N);
 }
 
 }  // namespace
@@ -388,7 +393,7 @@ rzf_status rzf_init(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   if (ok) {
     const Gram64Job gj{Hf, d.A64, K, N, ldh, alpha};
     launch_gram64(gj, nullptr, 1, K, s);
-    const Inv64Job ij{d.A64, d.Ainv, nullptr, nullptr, K};
+    const Inv64Job ij{d.A64, d.Ainv, nullptr, nullptr, K, d.Rfb};
     inv64_any(ij, c->d_err, s);
     ok = hipMemcpy2DAsync(d.Hprev, sizeof(float2) * N, Hf, sizeof(float2) * ldh,
                           sizeof(float2) * N, K, hipMemcpyDeviceToDevice, s) == hipSuccess;
@@ -427,7 +432,7 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
   const bool reset = t->prm.reset_period > 0 && t->since_reset + 1 >= t->prm.reset_period;
   if (reset) {
     const Gram64Job gj{Hf, d.A64, K, N, ldh, t->alpha};
-    const Inv64Job ij{d.A64, d.Ainv, &t->d_desc->info, nullptr, K};
+    const Inv64Job ij{d.A64, d.Ainv, &t->d_desc->info, nullptr, K, d.Rfb};
     timed(c, KN_GRAM64, [&] { launch_gram64(gj, nullptr, 1, K, s); });
     timed(c, KN_INV64, [&] { inv64_any(ij, c->d_err, s); });
   } else {
@@ -518,7 +523,7 @@ rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, 
     reset_flag[i] = reset;
     if (reset) {
       g64.push_back(Gram64Job{Hf, d.A64, K, N, items[i].ldh, t->alpha});
-      (K > KS ? i64b : i64).push_back(Inv64Job{d.A64, d.Ainv, &t->d_desc->info, nullptr, K});
+      (K > KS ? i64b : i64).push_back(Inv64Job{d.A64, d.Ainv, &t->d_desc->info, nullptr, K, d.Rfb});
       maxKr = std::max(maxKr, K);
     } else {
       gj.push_back(GramJob{Hf, d.Hprev, d.Anew, d.dA, K, N, items[i].ldh, N, (float)t->alpha, d.prec});
@@ -863,6 +868,8 @@ rzf_status rzf_track_export(rzf_track* t, void* buf, size_t* bytes) {
   HIP_OK(hipMemcpy(p, t->h_desc.Ainv, sizeof(float2) * t->K * t->K, hipMemcpyDeviceToHost));
   p += sizeof(float2) * t->K * t->K;
   HIP_OK(hipMemcpy(p, t->h_desc.Hprev, sizeof(float2) * (size_t)t->K * t->N, hipMemcpyDeviceToHost));
+  p += sizeof(float2) * (size_t)t->K * t->N;
+  HIP_OK(hipMemcpy(p, t->h_desc.Rfb, sizeof(float2) * t->K * t->K, hipMemcpyDeviceToHost));
   *bytes = need;
   return RZF_OK;
 }
@@ -894,7 +901,9 @@ rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track
   bool ok = hipMemcpy(t->d_desc, &t->h_desc, sizeof(TrackDesc), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(t->h_desc.Ainv, p, sizeof(float2) * h.K * h.K, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(t->h_desc.Hprev, p + sizeof(float2) * h.K * h.K, sizeof(float2) * (size_t)h.K * h.N,
-                      hipMemcpyHostToDevice) == hipSuccess;
+                      hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(t->h_desc.Rfb, p + sizeof(float2) * ((size_t)h.K * h.K + (size_t)h.K * h.N),
+                      sizeof(float2) * h.K * h.K, hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
     arena_free(c, t->off, t->bytes);
     delete t;

@@ -10,7 +10,7 @@
 //   Omega  K x d   CN(0,1) from the counter-based sketch generator
 //   Y      = Delta A Omega                    (matrix cores)
 //   Q      = orth(Y): Householder QR, Q formed explicitly
-//   Z      = Delta A Q                        (matrix cores), so B = Q^H Delta A = Z^H
+//   Z      = Delta A^H Q                      (matrix cores), so B = Q^H Delta A = Z^H
 //   Some r meets the energy target of eq. (14) exactly when the total
 //   sum_j sigma_j^2 = ||B||_F^2 = ||Z||_F^2 does, so a failing iteration needs
 //   no SVD: k0 <- 2 k0 and the next iteration draws a new sketch.
@@ -302,14 +302,18 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   for (int e = tid; e < KS * LDK; e += NTH) b2[e] = cz();
   // Delta A -> LDS, E = ||Delta A||_F^2 in FP64
   double part = 0.0;
+  const bool fb = td->error_feedback != 0;   // sketch Delta A + R
   for (int e = tid; e < K * K; e += NTH) {
     const int i = e / K, j = e - i * K;
-    const float2 v = td->dA[e];
+    float2 v = td->dA[e];
+    if (fb) v = cadd(v, td->Rfb[e]);
     b0[i * LDK + j] = v;
     part += (double)v.x * v.x + (double)v.y * v.y;
   }
   const double E = block_sum(part, sm.red);
   if (!isfinite(E) || E == 0.0) {
+    if (fb && E == 0.0)                      // nothing to apply: the residual is zero
+      for (int e = tid; e < K * K; e += NTH) td->Rfb[e] = cz();
     if (tid == 0) {
       if (!isfinite(E)) atomicCAS(err, 0, DEV_ERR_NONFINITE);
       td->info.r = 0; td->info.iters = 0; td->info.path = RZF_PATH_NOOP; td->info.d = 0;
@@ -371,9 +375,10 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       for (int c = j + wid; c < d; c += NWV) apply_reflector(b2, j, b1, c, K);
     }
     __syncthreads();
-    // Z = Delta A Q -> b2
+    // Z = Delta A^H Q = B^H -> b2 (Delta A is Hermitian unless error feedback
+    // has added its residual, so the conjugate transpose is taken explicitly)
     lds_gemm(K, d, K,
-             [&](int i, int k) { return (i < K && k < K) ? b0[i * LDK + k] : cz(); },
+             [&](int i, int k) { return (i < K && k < K) ? cconj(b0[k * LDK + i]) : cz(); },
              [&](int k, int j) { return (k < K && j < d) ? b1[j * LDK + k] : cz(); },
              [&](int i, int j, float2 v) { b2[j * LDK + i] = v; });
     __syncthreads();
@@ -411,6 +416,17 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   // Alg. 2's switch k_est <= switch * K, within the Woodbury workspace
   bool use_wb = r <= td->wb_limit;
   int path = use_wb ? RZF_PATH_WB : RZF_PATH_FULL_RANK;
+  if (fb && use_wb) {
+    // residual of the rank-r update: R = (Delta A + R) - U V~^H, read from b0
+    // before the Woodbury step reuses it (a direct inversion clears R below)
+    float2* R = td->Rfb;
+    const int* ord = sm.order;
+    lds_gemm(K, K, r,
+             [&](int i, int c) { return (i < K && c < r) ? b1[ord[c] * LDK + i] : cz(); },
+             [&](int c, int j) { return (c < r && j < K) ? cconj(b2[ord[c] * LDK + j]) : cz(); },
+             [&](int i, int j, float2 v) { R[(size_t)i * K + j] = csub(b0[i * LDK + j], v); });
+    __syncthreads();
+  }
 
   if (use_wb) {
     // A^-1 -> b0
@@ -534,6 +550,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   }
   if (!use_wb) {
     // direct inversion of A' (FP32)
+    if (fb)
+      for (int e = tid; e < K * K; e += NTH) td->Rfb[e] = cz();
     if (tid == 0) sm.bad = 0;
     for (int e = tid; e < K * K; e += NTH) {
       const int i = e / K, j = e - i * K;

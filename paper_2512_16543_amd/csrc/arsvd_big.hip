@@ -3,7 +3,7 @@
 //
 // Same computation and the same order as k_arsvd_wb (arsvd.hip): per
 // iteration Omega -> Y = Delta A Omega -> Q = orth(Y) (Householder) ->
-// Z = Delta A Q, the ||Z||_F^2 test of eq. (14), on success a one-sided
+// Z = Delta A^H Q, the ||Z||_F^2 test of eq. (14), on success a one-sided
 // Jacobi SVD of B = Z^H with Q rotated alongside, the rank rule, then the
 // Woodbury update of eq. (12) in the scaled form (U = Q columns, V~ = Z
 // columns) or direct inversion of A'.
@@ -609,18 +609,25 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
   const double eta = jb.eta;
   const int tid = threadIdx.x, wid = tid >> 6;
   const int K = td->K;
-  const float2* __restrict__ dA = td->dA;
+  float2* dA = td->dA;       // Delta A (+ R under error feedback, formed in place below)
   float2* Ym = td->Ym;
   float2* Qm = td->Qm;
   float2* Zm = td->Zm;
 
+  const bool fb = td->error_feedback != 0;   // sketch Delta A + R
   double part = 0.0;
   for (int e = tid; e < K * K; e += NTH) {
-    const float2 v = dA[e];
+    float2 v = dA[e];
+    if (fb) {
+      v = cadd(v, td->Rfb[e]);
+      dA[e] = v;
+    }
     part += (double)v.x * v.x + (double)v.y * v.y;
   }
   const double E = block_sum(part, sm.red);
   if (!isfinite(E) || E == 0.0) {
+    if (fb && E == 0.0)
+      for (int e = tid; e < K * K; e += NTH) td->Rfb[e] = cz();
     if (tid == 0) {
       if (!isfinite(E)) atomicCAS(err, 0, DEV_ERR_NONFINITE);
       td->info.r = 0; td->info.iters = 0; td->info.path = RZF_PATH_NOOP; td->info.d = 0;
@@ -674,7 +681,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
     t_sk += clock64() - c_mark; c_mark = clock64();
     qr_big(sm, Ym, Qm, K, d);
     qrcols += d;
-    // Z = Delta A Q and ||Z||_F^2
+    // Z = Delta A^H Q = B^H and ||Z||_F^2 (Delta A + R need not be Hermitian)
     double zp = 0.0;
     const int dtl = (d + 15) / 16;
     for (int tt = wid; tt < ktl * dtl; tt += NWV) {
@@ -682,7 +689,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
       floatx4 dr = zero4(), di = zero4();
       ctile16([&](int i, int k) {
                 const int row = ti * 16 + i;
-                return (row < K && k < K) ? dA[(size_t)row * K + k] : cz();
+                return (row < K && k < K) ? cconj(dA[(size_t)k * K + row]) : cz();
               },
               [&](int k, int jj) {
                 const int c = tj * 16 + jj;
@@ -726,6 +733,32 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
   bool use_wb = r <= td->wb_limit;
   int path = use_wb ? RZF_PATH_WB : RZF_PATH_FULL_RANK;
   float2* Ainv = td->Ainv;
+  if (fb && use_wb) {
+    // residual of the rank-r update: R = (Delta A + R) - U V~^H (a direct
+    // inversion clears R below)
+    const int* ord = sm.order;
+    float2* R = td->Rfb;
+    for (int tt = wid; tt < ktl * ktl; tt += NWV) {
+      const int ti = tt / ktl, tj = tt - ti * ktl;
+      floatx4 dr = zero4(), di = zero4();
+      ctile16([&](int i, int c) {
+                const int row = ti * 16 + i;
+                return (row < K && c < r) ? Qm[(size_t)ord[c] * K + row] : cz();
+              },
+              [&](int c, int j) {
+                const int col = tj * 16 + j;
+                return (c < r && col < K) ? cconj(Zm[(size_t)ord[c] * K + col]) : cz();
+              },
+              0, up4(r), dr, di);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * 16 + tile_row(v), col = tj * 16 + tile_col();
+        if (row < K && col < K)
+          R[(size_t)row * K + col] = csub(dA[(size_t)row * K + col], make_float2(dr[v], di[v]));
+      }
+    }
+    __syncthreads();
+  }
   if (use_wb) {
     const int* ord = sm.order;
     float2* Pm = td->Pm;
@@ -817,6 +850,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
   }
   if (!use_wb) {
     if (tid == 0) sm.bad = 0;
+    if (fb)
+      for (int e = tid; e < K * K; e += NTH) td->Rfb[e] = cz();
     for (int e = tid; e < K * K; e += NTH) Ainv[e] = td->Anew[e];
     __syncthreads();
     gj_inverse_hpd_blocked<float2>(Ainv, K, K, sm.u.inv.xs, sm.u.inv.cs, sm.u.inv.pb, &sm.bad);
@@ -847,7 +882,10 @@ __global__ __launch_bounds__(NTH) void k_inv64_big(Inv64Job one, const Inv64Job*
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   gj_inverse_hpd_blocked<double2>(A, K, K, xs, cs, pb, &bad);
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x) jb.Ainv[e] = d2f(A[e]);
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+    jb.Ainv[e] = d2f(A[e]);
+    if (jb.zero) jb.zero[e] = cz();
+  }
   if (threadIdx.x == 0) {
     if (bad) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
     DevInfo rec;

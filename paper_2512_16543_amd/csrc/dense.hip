@@ -46,7 +46,10 @@ __global__ __launch_bounds__(1024) void k_inv64(Inv64Job one, const Inv64Job* ma
   for (int e = threadIdx.x; e < K * K; e += blockDim.x) b0[e] = A[e];
   __syncthreads();
   double2* res = gj_inverse_hpd<double2, 2>(b0, b1, K, K, &bad);
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x) Ainv[e] = d2f(res[e]);
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+    Ainv[e] = d2f(res[e]);
+    if (jb.zero) jb.zero[e] = cz();
+  }
   if (threadIdx.x == 0) {
     if (bad) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
     DevInfo rec;

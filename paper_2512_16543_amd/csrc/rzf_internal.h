@@ -26,7 +26,8 @@ struct TrackDesc {
   double alpha, P, switch_ratio;
   int k_init, p, i_max, kinit_policy;
   int early_fallback, wb_limit;   // policy flag; largest rank the Woodbury branch takes
-  int prec, pad0_;                // rzf_precision of the Gram and precoder operands
+  int prec, error_feedback;       // rzf_precision of the Gram and precoder operands; policy
+  float2* Rfb;     // K x K, ld K: error-feedback residual (zero unless the policy is on)
   uint64_t seed, track_id;
   float2* Ainv;    // K x K, ld K: stored inverse
   float2* Hprev;   // K x N, ld N: previous snapshot
@@ -69,6 +70,7 @@ struct Gram64Job {
 struct Inv64Job {
   const double2* A; float2* Ainv; DevInfo* info; DevInfo* out;   // out: extra copy of info, or null
   int K;
+  float2* zero;    // K x K cleared alongside (the error-feedback residual), or null
 };
 struct Inv32Job {
   const float2* A; float2* Ainv;   // may alias: A is read into LDS first

@@ -32,7 +32,8 @@ class Params(ctypes.Structure):
     _fields_ = [("k_init", ctypes.c_int), ("p", ctypes.c_int), ("i_max", ctypes.c_int),
                 ("switch_ratio", ctypes.c_double), ("reset_period", ctypes.c_int),
                 ("P", ctypes.c_double), ("seed", ctypes.c_uint64), ("track_id", ctypes.c_uint64),
-                ("kinit_policy", ctypes.c_int), ("early_fallback", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("kinit_policy", ctypes.c_int), ("early_fallback", ctypes.c_int), ("precision", ctypes.c_int),
+                ("error_feedback", ctypes.c_int)]
 
 
 class UpdateInfo(ctypes.Structure):
@@ -434,6 +435,14 @@ class Track:
         buf = ctypes.create_string_buffer(n.value)
         _check(lib().rzf_track_export(self.h, buf, ctypes.byref(n)), "rzf_track_export")
         return buf.raw[:n.value]
+
+    def residual(self):
+        """The error-feedback residual R (K x K complex64 numpy array): the
+        last K*K entries of the checkpoint blob."""
+        import numpy as np
+        blob = self.export()
+        n = self.K * self.K * 8
+        return np.frombuffer(blob[len(blob) - n:], dtype=np.complex64).reshape(self.K, self.K).copy()
 
     def destroy(self):
         if self.h:

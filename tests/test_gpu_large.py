@@ -129,6 +129,12 @@ def test_update_large_early_fallback(ctx, cfgname, K):
     assert all(r["path"] != orz.PATH_FULL_RANK or r["r"] > K // 2 for r in recs)
 
 
+def test_update_large_error_feedback(ctx):
+    cfg = wl.with_overrides(wl.CONFIGS["c2"], K=128, seed=3)
+    recs = run_track(ctx, cfg, 4, 0.9, dict(error_feedback=1, reset_period=0))
+    _assert_recs(recs)
+
+
 def test_update_large_falls_back(ctx):
     K, N = 160, 512
     H0, H1 = _channel(K, N, 40), _channel(K, N, 41)

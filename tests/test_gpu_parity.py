@@ -145,7 +145,8 @@ def _oracle_params_a(alpha, d):
     return orz.TrackParams(alpha=alpha, P=d["P"], k_init=d["k_init"], p=d["p"],
                            i_max=d.get("i_max", 0), switch_ratio=d.get("switch_ratio", 0.5),
                            reset_period=d["reset_period"], seed=d["seed"], track_id=d["track_id"],
-                           kinit_policy=d.get("kinit_policy", 0), early_fallback=d.get("early_fallback", 0))
+                           kinit_policy=d.get("kinit_policy", 0), early_fallback=d.get("early_fallback", 0),
+                           error_feedback=d.get("error_feedback", 0))
 
 
 def _energy_ratios(res):
@@ -159,6 +160,8 @@ def _tie_ok(state, H, eta, gi, io, ot, band=TIE_BAND):
     oracle lies within TIE_BAND of eta."""
     dA = orz.gram_correction(state["H_prev"], H - state["H_prev"])
     prm = ot.params
+    if prm.error_feedback:
+        dA = dA + state["R"]
     k_init = prm.k_init if prm.kinit_policy == 0 else max(prm.k_init, state["last_r"])
     it = min(gi.iters, io.iters)
     res = orz.arsvd(dA, eta, k_init, prm.p, ot.i_max(), ot.draw(state["t"] + 1), force_iters=it)   # no early stop
@@ -187,6 +190,8 @@ def run_snapshots(ctx, Hs, alpha, d, eta, tie_band=TIE_BAND):
     for t in range(1, steps + 1):
         state = ot.export_state()
         state["Ainv"] = host(tr.inverse())
+        if d.get("error_feedback"):
+            state["R"] = tr.residual().astype(np.complex128)
         q = tr.query()
         state["last_r"] = q["last_r"]
         ot.import_state(state)
@@ -245,6 +250,39 @@ def test_update_early_fallback_policy(ctx):
     _assert_recs(recs)
     assert all(r["path"] == orz.PATH_FULL_RANK and r["iters"] == 5 and r["r"] == 37 for r in recs), \
         [(r["path"], r["iters"], r["r"]) for r in recs]
+
+
+@pytest.mark.parametrize("eta", [0.9, 0.999])
+def test_update_error_feedback(ctx, eta):
+    cfg = wl.CONFIGS["c2"]
+    recs = run_track(ctx, cfg, 12, eta, dict(error_feedback=1, reset_period=7))
+    _assert_recs(recs)
+    assert [r["t"] for r in recs if r["path"] == orz.PATH_RESET] == [7]
+
+
+def test_update_error_feedback_residual(ctx):
+    # the GPU's residual follows the oracle's when both start from the same state
+    cfg = wl.with_overrides(wl.CONFIGS["c1"], steps=6)
+    Hs = c64(wl.make_track(cfg).snapshots()).astype(np.complex128)
+    d = _params(cfg, error_feedback=1)
+    tr = ctx.init(dev(Hs[0]), cfg.alpha, rzf.default_params(**d))
+    ot = orz.OracleTrack(Hs[0], _oracle_params(cfg, d))
+    W = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device="cuda")
+    assert np.all(tr.residual() == 0)
+    for t in range(1, 7):
+        st = ot.export_state()
+        st["Ainv"] = host(tr.inverse())
+        st["R"] = tr.residual().astype(np.complex128)
+        ot.import_state(st)
+        info = tr.update(dev(Hs[t]), 0.9, W)
+        ctx.sync()
+        _, io = ot.update(Hs[t], 0.9)
+        if (info.r, info.path) != (io.r, io.path):
+            continue                            # a rounding tie; run_track covers those
+        Rg = tr.residual().astype(np.complex128)
+        scale = max(np.linalg.norm(ot.R), 1e-30)
+        assert np.linalg.norm(Rg - ot.R) <= 1e-3 * scale + 1e-6 * info.dA_fro2 ** 0.5, t
+    tr.destroy()
 
 
 def test_update_warm_policy(ctx):

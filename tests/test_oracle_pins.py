@@ -539,3 +539,38 @@ def test_track_early_fallback_policy():
         W, info = ot.update(H1, 0.999)
         assert info.path == orz.PATH_FULL_RANK and (info.iters, info.r) == (it_exp, r_exp)
         assert rel(ot.Ainv, np.linalg.inv(orz.gram(H1, 1.0))) < 1e-13
+
+
+def test_track_error_feedback_bookkeeping():
+    # R is A' of the step minus the Gram matrix whose inverse is stored, so it
+    # equals A'_t - inv(A^-1_t) after every step; a truncated step leaves a
+    # nonzero R, a direct inversion or a reset clears it
+    cfg, Hs = _track_inputs(steps=12)
+    prm = orz.TrackParams(alpha=cfg.alpha, seed=4, error_feedback=1, reset_period=9)
+    ot = orz.OracleTrack(Hs[0], prm)
+    seen_wb = False
+    for t in range(1, 13):
+        W, info = ot.update(Hs[t], 0.9)
+        A_t = orz.gram(Hs[t], cfg.alpha)
+        implied = np.linalg.inv(ot.Ainv)
+        assert np.linalg.norm(ot.R - (A_t - implied)) <= 1e-9 * np.linalg.norm(A_t), t
+        if info.path == orz.PATH_WB:
+            seen_wb = True
+            assert np.linalg.norm(ot.R) > 0.0
+        else:
+            assert np.linalg.norm(ot.R) == 0.0
+    assert seen_wb
+
+
+def test_track_error_feedback_bounds_drift():
+    # without feedback the discarded energy of every truncated step stays in
+    # the inverse; with it, each step re-sketches what is missing
+    cfg, Hs = _track_inputs(steps=30)
+    errs = {}
+    for fb in (0, 1):
+        ot = orz.OracleTrack(Hs[0], orz.TrackParams(alpha=cfg.alpha, seed=4, error_feedback=fb))
+        for t in range(1, 31):
+            ot.update(Hs[t], 0.9)
+        ref = np.linalg.inv(orz.gram(Hs[30], cfg.alpha))
+        errs[fb] = rel(ot.Ainv, ref)
+    assert errs[1] < 0.5 * errs[0], errs
