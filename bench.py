@@ -548,7 +548,7 @@ def table_v(a):
     for eta in (0.9, 0.8, 0.65, 0.999):
         trs = [ctx.init(Hs[b, 0], base.alpha,
                         rzf.default_params(k_init=base.k_init, p=base.p, P=base.P, seed=base.seed,
-                                           track_id=b, reset_period=0))
+                                           track_id=b, reset_period=0, error_feedback=int(a.error_feedback)))
                for b in range(B)]
         upd = [ctx.update_items(trs, [Hs[b, t] for b in range(B)], Wl) for t in range(T + 1)]
         # timed pass (no info records), then an identical pass that records ranks
@@ -564,7 +564,7 @@ def table_v(a):
             tr.destroy()
         trs = [ctx.init(Hs[b, 0], base.alpha,
                         rzf.default_params(k_init=base.k_init, p=base.p, P=base.P, seed=base.seed,
-                                           track_id=b, reset_period=0))
+                                           track_id=b, reset_period=0, error_feedback=int(a.error_feedback)))
                for b in range(B)]
         ranks, paths, iters = [], [], []
         for t in range(1, T + 1):
@@ -594,7 +594,8 @@ def table_v(a):
             tr.destroy()
         print(f"[table-v] eta={eta} done", file=sys.stderr, flush=True)
     ctx.close()
-    return {"experiment": "table_v_analog", "passes": B, "steps_per_pass": T, "K": K, "N": N,
+    return {"experiment": "table_v_analog", "error_feedback": bool(a.error_feedback),
+            "passes": B, "steps_per_pass": T, "K": K, "N": N,
             "update_interval_s": base.dt_s, "full_ms_per_batched_step": 1e3 * full_s / T,
             "paper_table_v": [{"eta": 0.90, "savings": 0.306, "sr_degradation": 0.016},
                               {"eta": 0.80, "savings": 0.477, "sr_degradation": 0.058},
