@@ -16,6 +16,9 @@ notation (A is the Gram matrix, Delta A its per-step correction):
   woodbury           eq. (12), evaluated in the order of Sec. III-A steps 1-5
   precoder           eq. (5) with the power constraint ||W||_F^2 = P
   sum_rate           eq. (15)
+  dft_codebook       eq. (4): the DFT codebook of the UPA
+  beamspace          eq. (4): best-power beam choice and H_eff = H~ F_RF
+  beam_channel       eq. (15): H F_RF for given beams
   OracleTrack        Alg. 2, with an optional periodic exact re-inversion
 
 Readings taken where the paper is silent (each is also listed with the design
@@ -31,6 +34,10 @@ notes of the repository):
     k_init 2^(I-1) + p >= K, i.e. the doubling reaches d = K.
   * The row-n channel of eq. (15) is row n of H (H = [h_1 ... h_K]^T), so the
     received-signal matrix is E = H W.
+  * The best-power criterion of eq. (4) (its rule is only cited): users in
+    index order each take the strongest codebook beam not yet taken, lowest
+    index on ties; chains beyond K take the untaken beams of largest total
+    power.  The codebook sign is +j (the other sign only relabels beams).
   * The periodic exact re-inversion (reset_period) is not part of the paper; it
     bounds the drift of the stored inverse and is off unless asked for.  It
     fires once reset_period steps have passed since the last FP64 inversion
@@ -213,6 +220,56 @@ def sum_rate(H: np.ndarray, W: np.ndarray, P: float, sigma2: float):
         interf = sum(abs(E[n, i]) ** 2 for i in range(K) if i != n)
         rates[n] = math.log2(1.0 + sig / (interf + sigma2))
     return rates, float(np.sum(rates))
+
+
+def dft_codebook(nx: int, ny: int) -> np.ndarray:
+    """The N x N DFT codebook of an nx x ny UPA (N = nx ny, element index
+    m_y nx + m_x): beam b = (q, p) = divmod(b, nx) has entries
+    exp(+j 2 pi (p m_x / nx + q m_y / ny)) / sqrt(N) (eq. (4)'s analog beams;
+    distinct beams are orthonormal)."""
+    N = nx * ny
+    mx = np.tile(np.arange(nx), ny)
+    my = np.repeat(np.arange(ny), nx)
+    b = np.arange(N)
+    p, q = b % nx, b // nx
+    ph = 2.0 * np.pi * (np.outer(mx, p) / nx + np.outer(my, q) / ny)
+    return np.exp(1j * ph) / math.sqrt(N)
+
+
+def beamspace(Ht: np.ndarray, nx: int, ny: int, n_rf: int):
+    """Analog beam selection and H_eff = H~ F_RF of eq. (4).
+
+    Best-power rule (reading: the cited rule is not available): user n in
+    turn takes the codebook beam b maximising |(H~ F)_{n,b}|^2 among the beams
+    not yet taken (lowest index on ties); the remaining n_rf - K chains take
+    the untaken beams of largest total power sum_n |(H~ F)_{n,b}|^2.  Returns
+    (beams, H_eff): the n_rf selected beam indices (users' beams first) and
+    the K x n_rf matrix H~ F_RF."""
+    K, N = Ht.shape
+    assert N == nx * ny and K <= n_rf <= N
+    G = Ht @ dft_codebook(nx, ny)                 # every beam's response, K x N
+    pw = np.abs(G) ** 2
+    taken = np.zeros(N, dtype=bool)
+    beams = []
+    for n in range(K):
+        cand = np.where(taken, -1.0, pw[n])
+        b = int(np.argmax(cand))                  # first index of the maximum
+        taken[b] = True
+        beams.append(b)
+    tot = pw.sum(axis=0)
+    for _ in range(n_rf - K):
+        cand = np.where(taken, -1.0, tot)
+        b = int(np.argmax(cand))
+        taken[b] = True
+        beams.append(b)
+    beams = np.array(beams, dtype=np.int64)
+    return beams, G[:, beams]
+
+
+def beam_channel(H: np.ndarray, nx: int, ny: int, beams) -> np.ndarray:
+    """H F_RF for given codebook beams: the channel seen through the analog
+    stage, as in the numerator and interference terms of eq. (15)."""
+    return H @ dft_codebook(nx, ny)[:, np.asarray(beams, dtype=np.int64)]
 
 
 def wb_rank_cap(K: int) -> int:

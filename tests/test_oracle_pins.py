@@ -6,6 +6,7 @@ different library routine, or a printed value.  `test_oracle_mutants.py`
 plants plausible mistakes in copies of the oracle and checks that these pins
 catch them.
 """
+import cmath
 import json
 import math
 import os
@@ -574,3 +575,109 @@ def test_track_error_feedback_bounds_drift():
         ref = np.linalg.inv(orz.gram(Hs[30], cfg.alpha))
         errs[fb] = rel(ot.Ainv, ref)
     assert errs[1] < 0.5 * errs[0], errs
+
+
+# ---------------------------------------------------------------- hybrid front end, eq. (4)
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (4, 2), (3, 5), (16, 16)])
+def test_dft_codebook_orthonormal(nx, ny):
+    F = orz.dft_codebook(nx, ny)
+    N = nx * ny
+    assert F.shape == (N, N)
+    assert rel(F.conj().T @ F, np.eye(N)) <= 1e-13
+    assert np.allclose(np.abs(F), 1.0 / math.sqrt(N), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("nx,ny", [(4, 2), (3, 5), (16, 16)])
+def test_dft_codebook_is_inverse_fft(nx, ny):
+    # h F at beam b = q nx + p is N / sqrt(N) times numpy's inverse 2-D FFT of
+    # h laid out as ny x nx (rows m_y, columns m_x), read at [q, p]
+    rng = np.random.default_rng(41)
+    K, N = 3, nx * ny
+    H = crandn(rng, K, N)
+    G = H @ orz.dft_codebook(nx, ny)
+    ref = np.fft.ifft2(H.reshape(K, ny, nx), axes=(1, 2)) * (N / math.sqrt(N))
+    assert rel(G, ref.reshape(K, N)) <= 1e-13
+
+
+def _beamspace_bruteforce(H, nx, ny, n_rf):
+    """Pure-Python loops over the definition: every beam's response by its
+    sum, then the greedy choice with strict comparisons."""
+    K, N = H.shape
+    G = [[0j] * N for _ in range(K)]
+    for n in range(K):
+        for b in range(N):
+            q, p = divmod(b, nx)
+            acc = 0j
+            for m in range(N):
+                my, mx = divmod(m, nx)
+                acc += H[n, m] * cmath.exp(2j * math.pi * (p * mx / nx + q * my / ny))
+            G[n][b] = acc / math.sqrt(N)
+    taken, beams = set(), []
+    for c in range(n_rf):
+        best, bi = -1.0, None
+        for b in range(N):
+            if b in taken:
+                continue
+            v = abs(G[c][b]) ** 2 if c < K else sum(abs(G[u][b]) ** 2 for u in range(K))
+            if v > best:
+                best, bi = v, b
+        taken.add(bi)
+        beams.append(bi)
+    return beams, np.array([[G[n][b] for b in beams] for n in range(K)])
+
+
+@pytest.mark.parametrize("K,nx,ny,n_rf,seed", [(3, 2, 2, 3, 1), (2, 3, 2, 5, 2), (4, 4, 2, 6, 3)])
+def test_beamspace_bruteforce(K, nx, ny, n_rf, seed):
+    rng = np.random.default_rng(seed)
+    H = crandn(rng, K, nx * ny)
+    beams, Heff = orz.beamspace(H, nx, ny, n_rf)
+    bb, Hb = _beamspace_bruteforce(H, nx, ny, n_rf)
+    assert list(beams) == bb
+    assert rel(Heff, Hb) <= 1e-13
+    assert rel(orz.beam_channel(H, nx, ny, beams), Heff) <= 1e-13
+
+
+def test_beamspace_on_grid_users():
+    # users whose channels are conjugate codebook beams see exactly one beam:
+    # each takes its own beam and H_eff = I
+    nx, ny = 8, 4
+    F = orz.dft_codebook(nx, ny)
+    own = [5, 17, 0, 30]
+    H = F[:, own].conj().T
+    beams, Heff = orz.beamspace(H, nx, ny, len(own))
+    assert list(beams) == own
+    assert rel(Heff, np.eye(len(own))) <= 1e-13
+
+
+def test_beamspace_conflict_and_ties():
+    nx, ny = 4, 2
+    F = orz.dft_codebook(nx, ny)
+    f = lambda b: F[:, b].conj()
+    # user 1's strongest beam (5) is user 0's: it takes its second (2); the
+    # extra chains then go by total power: beam 7, then beam 0
+    H = np.array([f(5) + 0.1 * f(7), 0.9 * f(5) + 0.5 * f(2) + 0.45 * f(7) + 0.4 * f(0)])
+    beams, _ = orz.beamspace(H, nx, ny, 4)
+    assert list(beams) == [5, 2, 7, 0]
+    # an exact tie (two elements, h = [1, 0] sees both beams with power 1/2):
+    # the lower index first, then the other one
+    H2 = np.array([[1.0, 0.0], [1.0, 0.0]], dtype=complex)
+    beams2, Heff2 = orz.beamspace(H2, 2, 1, 2)
+    assert list(beams2) == [0, 1]
+    assert np.allclose(np.abs(Heff2) ** 2, 0.5, rtol=0, atol=1e-15)
+
+
+def test_hybrid_power_constraint():
+    # eq. (4): the codebook columns are orthonormal, so scaling F_BB to
+    # ||F_BB||_F^2 = P gives ||F_RF F_BB||_F^2 = P
+    rng = np.random.default_rng(7)
+    nx, ny, K, n_rf = 8, 8, 6, 10
+    H = crandn(rng, K, nx * ny)
+    beams, Heff = orz.beamspace(H, nx, ny, n_rf)
+    Fbb = orz.full_rzf(Heff, 0.3, 2.0)
+    Frf = orz.dft_codebook(nx, ny)[:, beams]
+    assert abs(np.linalg.norm(Frf @ Fbb) ** 2 - 2.0) <= 1e-12
+    # the sum rate through the analog stage equals the one on H F_RF
+    _, R1 = orz.sum_rate(H @ Frf, Fbb, 2.0, 0.1)
+    _, R2 = orz.sum_rate(orz.beam_channel(H, nx, ny, beams), Fbb, 2.0, 0.1)
+    assert abs(R1 - R2) <= 1e-12 * abs(R1)
