@@ -56,6 +56,12 @@ def parse():
     ap.add_argument("--table-v", action="store_true",
                     help="run the Table V / Fig. 2 analog instead (prints its own JSON line)")
     ap.add_argument("--passes", type=int, default=16, help="Monte Carlo passes of --table-v")
+    ap.add_argument("--hybrid", action="store_true",
+                    help="--table-v through the hybrid front end of eq. (4) (16 RF chains)")
+    ap.add_argument("--counters", action="store_true",
+                    help="counter target for rocprofv3 --pmc: one 1 GiB elementwise copy (the "
+                         "calibration of FETCH_SIZE / WRITE_SIZE), then --steps updates of the "
+                         "configuration's track at its eta; prints one line, times nothing")
     ap.add_argument("--serve", action="store_true",
                     help="run the serving experiment instead (prints its own JSON line)")
     ap.add_argument("--serve-tracks", type=int, default=2048)
@@ -68,6 +74,7 @@ def parse():
 
 
 PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+ECDF_Q = (0.05, 0.25, 0.5, 0.75, 0.95)   # sum-rate quantiles reported for Fig. 2's ECDFs
 
 
 def d_sequence(iters, k0, p, K):
@@ -122,6 +129,9 @@ def main():
 
     from paper_2512_16543_amd import rzf, workload as wl
 
+    if a.counters:
+        counters_target(a)
+        return 0
     if a.table_v:
         print(json.dumps(table_v(a)), flush=True)
         return 0
@@ -290,7 +300,10 @@ def main():
     traffic = None
     if dom == "arsvd_wb" and (K, N) == (64, 256) and a.config == "c2":
         traffic = measured_traffic("k_arsvd_wb_k64_n256")
-    out["roofline"] = {"kernel": dom, "bound": "mfma", "achieved": achieved,
+    # k_arsvd_wb's instruction mix is VALU (counters: SQ_INSTS_VALU against SQ_INSTS_MFMA); its
+    # peak is the FP32 vector rate, 256 CUs x 4 SIMD x 16 lanes x 2 x 2.4 GHz = 157.3 TFLOP/s
+    bound = "alu" if dom == "arsvd_wb" else "mfma"
+    out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved,
                        "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": traffic,
                        "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
@@ -501,6 +514,36 @@ def serve(a):
             "rows": rows}
 
 
+def counters_target(a):
+    """Work for a hardware-counter pass: a plain copy of known size first
+    (1 GiB in, 1 GiB out, so each counter's scale can be read off it), then
+    a.steps updates of one track of the configuration, nothing else."""
+    import numpy as np
+    import torch
+    from paper_2512_16543_amd import rzf, workload as wl
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+    cfg = wl.CONFIGS[a.config]
+    eta = cfg.eta if a.eta is None else a.eta
+    Hs = torch.from_numpy(wl.make_track(wl.with_overrides(cfg, steps=max(cfg.steps, a.steps)))
+                          .snapshots(0, a.steps + 1).astype(np.complex64)).cuda()
+    ctx = rzf.Context(0, 64 << 20)
+    tr = ctx.init(Hs[0], cfg.alpha, rzf.default_params(k_init=cfg.k_init, p=cfg.p, P=cfg.P, seed=cfg.seed,
+                                                       reset_period=0,
+                                                       precision=PRECISIONS[a.precision],
+                                                       error_feedback=int(a.error_feedback),
+                                                       early_fallback=int(a.early_fallback)))
+    W = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device="cuda")
+    for t in range(1, a.steps + 1):
+        tr.update(Hs[t], eta, W, want_info=False)
+    ctx.sync()
+    ctx.close()
+    print(f"counters target: 1 GiB copy, {a.steps} updates of {a.config} at eta={eta}", flush=True)
+
+
 def table_v(a):
     """Analog of the paper's Table V / Fig. 2 on synthetic passes.
 
@@ -515,26 +558,70 @@ def table_v(a):
         against K^3 per step, with the observed k_est (steps that fall back
         to direct inversion count K^3);
       * the measured GPU time of the batched passes against full inversion.
+
+    With --hybrid the precoder runs on H_eff = H~ F_RF of eq. (4) (the
+    configuration "h1": users spread over a 250 km disk so that most have a
+    beam of their own): every snapshot's beams are chosen on the GPU from the
+    users' array manifolds, and eq. (15) is scored on H(t) F_RF.  The front
+    end runs once per snapshot before the timed passes (it is the same for
+    both precoders) and is timed on its own.
     """
     import numpy as np
     import torch
     from paper_2512_16543_amd import rzf, workload as wl
     from paper_2512_16543_amd import opcount as cx    # Table III operation count
-    base = wl.TrackConfig("table_v", seed=15, nx=16, K=16, height_m=600e3, radius_m=50e3,
-                          dt_s=0.05, steps=2400, kr_db=10.0, snr_db=10.0, eta=0.9, p=1, k_init=2,
-                          reset_period=0)
+    if a.hybrid:
+        base = wl.CONFIGS["h1"]
+    else:
+        base = wl.TrackConfig("table_v", seed=15, nx=16, K=16, height_m=600e3, radius_m=50e3,
+                              dt_s=0.05, steps=2400, kr_db=10.0, snr_db=10.0, eta=0.9, p=1, k_init=2,
+                              reset_period=0)
     B, T = a.passes, base.steps
     K, N = base.K, base.N
+    Np = base.n_rf if a.hybrid else N        # columns the precoder sees
     dev = torch.device("cuda", 0)
+    ctx = rzf.Context(0, B * rzf.track_bytes(K, Np) + (64 << 20))
     Hs = torch.empty(B, T + 1, K, N, dtype=torch.complex64, device=dev)
     for b in range(B):
         Hs[b] = torch.from_numpy(wl.make_track(base, b).snapshots().astype(np.complex64)).to(dev)
-    ctx = rzf.Context(0, B * rzf.track_bytes(K, N) + (64 << 20))
-    Wl = [torch.empty(N, K, dtype=torch.complex64, device=dev) for _ in range(B)]
+    front = {}
+    if a.hybrid:
+        Ms = torch.empty(B, T + 1, K, N, dtype=torch.complex64, device=dev)
+        for b in range(B):
+            Ms[b] = torch.from_numpy(wl.make_track(base, b).snapshots(manifold=True).astype(np.complex64)).to(dev)
+        Hp = torch.empty(B, T + 1, K, Np, dtype=torch.complex64, device=dev)   # H~ F_RF
+        Hr = torch.empty(B, T + 1, K, Np, dtype=torch.complex64, device=dev)   # H F_RF
+        beams = torch.empty(B, T + 1, Np, dtype=torch.int32, device=dev)
+        def front_end(b, t):
+            ctx.beamspace(Ms[b, t], base.nx, base.nx, beams[b, t], Hp[b, t])
+            ctx.beamspace(Hs[b, t], base.nx, base.nx, beams[b, t], Hr[b, t], select=False)
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in range(B):
+            for t in range(T + 1):
+                front_end(b, t)
+        ctx.sync()
+        fe_s = time.perf_counter() - t0
+        ctx.profile(True)            # kernel averages over a few hundred repeated snapshots
+        for t in range(min(T + 1, 300)):
+            front_end(0, t)
+        prof = {k: 1e3 * ms / max(n, 1) for k, (n, ms) in ctx.profile_read().items()}   # avg us
+        ctx.profile(False)
+        del Ms
+        bh = beams.cpu().numpy()
+        front = {"front_end_ms_per_snapshot": 1e3 * fe_s / (B * (T + 1)),
+                 "beam_resp_us": prof.get("beam_resp"), "beam_select_us": prof.get("beam_select"),
+                 "beam_switches_per_step": float(np.mean(np.sum(bh[:, 1:] != bh[:, :-1], axis=2))),
+                 "n_rf": Np, "N_t": N}
+        print(f"[table-v] front end {front}", file=sys.stderr, flush=True)
+    else:
+        Hp = Hr = Hs
+    Wl = [torch.empty(Np, K, dtype=torch.complex64, device=dev) for _ in range(B)]
     sums = torch.empty(T + 1, B, dtype=torch.float64, device=dev)
-    full_items = [ctx.full_items([Hs[b, t] for b in range(B)], [base.alpha] * B, base.P, Wl)
+    full_items = [ctx.full_items([Hp[b, t] for b in range(B)], [base.alpha] * B, base.P, Wl)
                   for t in range(T + 1)]
-    rate_items = [ctx.rate_items([Hs[b, t] for b in range(B)], Wl, None, sums[t]) for t in range(T + 1)]
+    rate_items = [ctx.rate_items([Hr[b, t] for b in range(B)], Wl, None, sums[t]) for t in range(T + 1)]
     # full-inversion RZF reference
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -546,11 +633,11 @@ def table_v(a):
     R_full = sums[1:].cpu().numpy().copy()
     rows = []
     for eta in (0.9, 0.8, 0.65, 0.999):
-        trs = [ctx.init(Hs[b, 0], base.alpha,
+        trs = [ctx.init(Hp[b, 0], base.alpha,
                         rzf.default_params(k_init=base.k_init, p=base.p, P=base.P, seed=base.seed,
                                            track_id=b, reset_period=0, error_feedback=int(a.error_feedback)))
                for b in range(B)]
-        upd = [ctx.update_items(trs, [Hs[b, t] for b in range(B)], Wl) for t in range(T + 1)]
+        upd = [ctx.update_items(trs, [Hp[b, t] for b in range(B)], Wl) for t in range(T + 1)]
         # timed pass (no info records), then an identical pass that records ranks
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -562,13 +649,13 @@ def table_v(a):
         R_wb = sums[1:].cpu().numpy().copy()
         for tr in trs:
             tr.destroy()
-        trs = [ctx.init(Hs[b, 0], base.alpha,
+        trs = [ctx.init(Hp[b, 0], base.alpha,
                         rzf.default_params(k_init=base.k_init, p=base.p, P=base.P, seed=base.seed,
                                            track_id=b, reset_period=0, error_feedback=int(a.error_feedback)))
                for b in range(B)]
         ranks, paths, iters = [], [], []
         for t in range(1, T + 1):
-            infos = ctx.update_batch(trs, [Hs[b, t] for b in range(B)], Wl, eta, want_info=True)
+            infos = ctx.update_batch(trs, [Hp[b, t] for b in range(B)], Wl, eta, want_info=True)
             if t % 200 == 0 or t == T:
                 ctx.sync()
             ranks.append(infos)
@@ -582,6 +669,7 @@ def table_v(a):
         cost = np.where(pa == rzf.PATH_WB, [cx.wb_arsvd_ops(K, r) for r in rs], float(K) ** 3)
         rows.append({
             "eta": eta,
+            "sr_ecdf_quantiles": [float(x) for x in np.quantile(R_wb, ECDF_Q)],
             "sr_degradation": float(1.0 - R_wb.mean() / R_full.mean()),
             "opcount_savings": float(1.0 - cost.mean() / float(K) ** 3),
             "k_est_mean": float(rs.mean()),
@@ -594,9 +682,11 @@ def table_v(a):
             tr.destroy()
         print(f"[table-v] eta={eta} done", file=sys.stderr, flush=True)
     ctx.close()
-    return {"experiment": "table_v_analog", "error_feedback": bool(a.error_feedback),
-            "passes": B, "steps_per_pass": T, "K": K, "N": N,
+    return {"experiment": "table_v_analog", "hybrid": bool(a.hybrid), **front,
+            "error_feedback": bool(a.error_feedback),
+            "passes": B, "steps_per_pass": T, "K": K, "N": Np,
             "update_interval_s": base.dt_s, "full_ms_per_batched_step": 1e3 * full_s / T,
+            "ecdf_q": list(ECDF_Q), "sr_ecdf_quantiles_full": [float(x) for x in np.quantile(R_full, ECDF_Q)],
             "paper_table_v": [{"eta": 0.90, "savings": 0.306, "sr_degradation": 0.016},
                               {"eta": 0.80, "savings": 0.477, "sr_degradation": 0.058},
                               {"eta": 0.65, "savings": 0.612, "sr_degradation": 0.095}],

@@ -11,7 +11,8 @@
  *    torch.complex64).
  *  - H is K x N, row-major, leading dimension ldh >= N: row n is the channel
  *    h_n^T of user n (Sec. II, eq. (1)).  K users, N transmit antennas; the
- *    analog combiner of eq. (4) is the identity (fully digital, N_RF = N).
+ *    analog combiner of eq. (4) is the identity (fully digital, N_RF = N),
+ *    or H is the effective channel H~ F_RF made by rzf_beamspace (N = N_RF).
  *  - W is N x K, row-major, leading dimension ldw >= K: column n is the
  *    precoding vector of user n (eq. (5)).
  *  - Every matrix argument is a DEVICE pointer (e.g. a torch tensor's
@@ -222,6 +223,26 @@ typedef struct {
  * memory (asynchronous).  1 <= n <= RZF_BATCH_MAX. */
 rzf_status rzf_sum_rate_batch(rzf_ctx* ctx, int n, const rzf_rate_item* items, double P,
                               double sigma2);
+
+/* Hybrid front end of eq. (4): H_eff = H~ F_RF with F_RF made of n_rf beams
+ * of the DFT codebook of an nx x ny UPA (N = nx ny, element index m_y nx + m_x;
+ * beam b = q nx + p has entries exp(+j 2 pi (p m_x / nx + q m_y / ny)) / sqrt(N),
+ * so F_RF has orthonormal columns and ||F_RF F_BB||_F = ||F_BB||_F).
+ *  - H: device, K x N, leading dimension ldh >= N (rows h~_n^T of eq. (4)).
+ *  - select = 1: choose the beams by the best-power criterion (Sec. II; the
+ *    rule it cites is not given, so: user n = 0 .. K-1 in turn takes the
+ *    not-yet-taken beam of largest |h~_n^T f_b|^2, lowest index on ties; the
+ *    other n_rf - K chains take the untaken beams of largest total power
+ *    sum_n |h~_n^T f_b|^2) and write them to beams (device, n_rf ints, users'
+ *    beams first).  Needs K <= n_rf <= N.
+ *  - select = 0: beams (device, n_rf ints) is an input, e.g. the choice made
+ *    on another channel; 1 <= n_rf <= N.  An index outside [0, N) gives a zero
+ *    column and RZF_E_INVALID at the next rzf_sync.
+ *  - H_eff: device, K x n_rf, leading dimension ld_eff >= n_rf.
+ * Asynchronous; uses K N complex values of context scratch (RZF_E_NOMEM if the
+ * arena cannot hold them).  1 <= K <= RZF_KMAX, N <= RZF_NMAX. */
+rzf_status rzf_beamspace(rzf_ctx* ctx, int K, int nx, int ny, const rzf_c32* H, int ldh, int n_rf,
+                         int select, int* beams, rzf_c32* H_eff, int ld_eff);
 
 /* Copy the track's stored inverse (K x K, row-major, ld = K) to device memory
  * Ainv.  Asynchronous. */

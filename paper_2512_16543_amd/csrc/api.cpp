@@ -19,7 +19,8 @@ using namespace rzfrt;
 namespace {
 
 const char* const KERNEL_NAMES[] = {"gram", "gram64", "inv64", "inv32", "arsvd_wb",
-                                    "precoder", "scale", "sum_rate"};
+                                    "precoder", "scale", "sum_rate", "beam_resp", "beam_select"};
+static_assert(sizeof(KERNEL_NAMES) / sizeof(KERNEL_NAMES[0]) == KN_COUNT, "one name per kernel");
 
 }  // namespace
 
@@ -139,6 +140,7 @@ void prof_drain(rzf_ctx* c) {
 rzf_status dev_status(int code) {
   if (code == DEV_ERR_NOT_HPD) return RZF_E_NOT_HPD;
   if (code == DEV_ERR_NONFINITE) return RZF_E_NONFINITE;
+  if (code == DEV_ERR_BEAM) return RZF_E_INVALID;
   return code ? RZF_E_DEVICE : RZF_OK;
 }
 
@@ -788,6 +790,37 @@ rzf_status rzf_sum_rate(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, con
     *sum_rate = *c->h_sum;
   }
   return RZF_OK;
+}
+
+rzf_status rzf_beamspace(rzf_ctx* c, int K, int nx, int ny, const rzf_c32* H, int ldh, int n_rf,
+                         int select, int* beams, rzf_c32* H_eff, int ld_eff) {
+  if (!c || !H || !beams || !H_eff || (select != 0 && select != 1)) return RZF_E_INVALID;
+  if (K < 1 || K > RZF_KMAX || nx < 1 || ny < 1 || nx > RZF_NMAX || ny > RZF_NMAX / nx) return RZF_E_SHAPE;
+  const int N = nx * ny;
+  if (ldh < N || n_rf < (select ? K : 1) || n_rf > N || ld_eff < n_rf) return RZF_E_SHAPE;
+  std::lock_guard<std::mutex> lk(c->mu);
+  HIP_OK(hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  const size_t want = sizeof(float2) * (size_t)K * N;
+  if (want > c->beam_g_bytes) {
+    // grow: the old region may still be read by queued work
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (c->d_beam_g) arena_free(c, c->beam_g_off, c->beam_g_bytes);
+    c->d_beam_g = nullptr;
+    c->beam_g_bytes = 0;
+    size_t off = 0;
+    if (!arena_alloc(c, want, &off)) return RZF_E_NOMEM;
+    c->beam_g_off = off;
+    c->beam_g_bytes = want;
+    c->d_beam_g = reinterpret_cast<float2*>(c->arena + off);
+  }
+  const float2* Hf = reinterpret_cast<const float2*>(H);
+  timed(c, KN_BEAM_RESP, [&] { launch_beam_resp(Hf, ldh, K, nx, ny, c->d_beam_g, s); });
+  timed(c, KN_BEAM_SELECT, [&] {
+    launch_beam_select(c->d_beam_g, K, N, n_rf, select, beams, reinterpret_cast<float2*>(H_eff), ld_eff,
+                       c->d_err, s);
+  });
+  return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
 }
 
 rzf_status rzf_get_inverse(rzf_track* t, rzf_c32* Ainv) {

@@ -32,7 +32,7 @@ struct ProfRec {
 };
 
 enum { KN_GRAM, KN_GRAM64, KN_INV64, KN_INV32, KN_ARSVD, KN_PRECODER, KN_SCALE, KN_SUMRATE,
-       KN_COUNT };
+       KN_BEAM_RESP, KN_BEAM_SELECT, KN_COUNT };
 
 }  // namespace rzfrt
 
@@ -68,6 +68,8 @@ struct rzf_ctx {
   size_t batch_part_off = 0, batch_part_bytes = 0;
   char* d_batch_full = nullptr;         // Gram / partial-norm scratch of rzf_full_batch
   size_t batch_full_off = 0, batch_full_bytes = 0;
+  float2* d_beam_g = nullptr;           // beam responses of rzf_beamspace
+  size_t beam_g_off = 0, beam_g_bytes = 0;
   // event timing
   bool prof_on = false;
   std::vector<rzfrt::ProfRec> prof;

@@ -13,6 +13,7 @@
 // Device-side error codes (first one wins; rzf_sync maps them to rzf_status).
 #define DEV_ERR_NOT_HPD 1
 #define DEV_ERR_NONFINITE 2
+#define DEV_ERR_BEAM 3        // a given beam index outside the codebook
 
 // Per-update outcome, same layout as rzf_update_info.
 struct DevInfo {
@@ -121,5 +122,10 @@ void launch_inv64_big(const Inv64Job& one, const Inv64Job* many, int n, int* err
 void launch_inv32_big(const Inv32Job& one, const Inv32Job* many, int n, int* err, hipStream_t s);
 size_t sum_rate_scratch_doubles(int K);
 void launch_sum_rate(const RateJob& one, const RateJob* many, int n, int maxK, int* err, hipStream_t s);
+// Hybrid front end: every codebook beam's response G (K x nx ny), then the
+// beam choice and H_eff.
+void launch_beam_resp(const float2* H, int ldh, int K, int nx, int ny, float2* G, hipStream_t s);
+void launch_beam_select(const float2* G, int K, int N, int n_rf, int select, int* beams, float2* Heff,
+                        int ld_eff, int* err, hipStream_t s);
 void launch_debug_sketch(uint64_t seed, uint64_t track, int t, int it, int K, int d, float2* Omega,
                          uint64_t* words, hipStream_t s);

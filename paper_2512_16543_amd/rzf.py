@@ -113,6 +113,9 @@ _SIGS = {
     "rzf_sum_rate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                     ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "rzf_beamspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "rzf_get_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rzf_update_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(UpdateItem),
                                         ctypes.c_double]),
@@ -286,6 +289,22 @@ class Context:
         _check(lib().rzf_sum_rate(self.h, K, N, ctypes.c_void_p(hp), ldh, ctypes.c_void_p(wp), ldw,
                                   float(P), float(sigma2), ctypes.c_void_p(_dev_ptr(rates)), None),
                "rzf_sum_rate")
+
+    def beamspace(self, H, nx: int, ny: int, beams, H_eff, select: bool = True):
+        """rzf_beamspace: H_eff = H F_RF over the DFT codebook of an nx x ny UPA.
+        beams is a device int32 tensor of n_rf = H_eff.shape[1] entries, written
+        when select is True and read otherwise (asynchronous)."""
+        import torch
+        hp, ldh = _mat_args(H)
+        ep, lde = _mat_args(H_eff)
+        K, n_rf = H_eff.shape
+        if H.shape[0] != K:
+            raise ValueError("H and H_eff must have the same number of rows")
+        if beams.dtype != torch.int32 or not beams.is_contiguous() or beams.numel() != n_rf:
+            raise ValueError("beams must be a contiguous int32 tensor of n_rf entries")
+        _check(lib().rzf_beamspace(self.h, K, int(nx), int(ny), ctypes.c_void_p(hp), ldh, n_rf,
+                                   1 if select else 0, ctypes.c_void_p(_dev_ptr(beams)),
+                                   ctypes.c_void_p(ep), lde), "rzf_beamspace")
 
     def update_batch(self, tracks, Hs, Ws, tol: float, want_info: bool = False):
         """rzf_update_batch over parallel lists of Track, H_t and W tensors."""

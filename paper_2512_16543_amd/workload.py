@@ -14,7 +14,9 @@ Channel model (Sec. II):
 Readings where the paper leaves the scenario open (the paper's link budget and
 analog codebook are not given in full, so the pass is synthetic):
   * Fully digital array, N = N_t (the analog combiner F_RF of eq. (4) is the
-    identity).
+    identity), except for configurations with n_rf > 0: those feed the
+    manifolds H~(t) (`snapshots(manifold=True)`) to the hybrid front end and
+    score eq. (15) on H(t) F_RF.
   * Square half-wavelength UPA in the satellite's x-y plane, boresight at
     nadir, so kappa . r_m = pi (m_x u + m_y v) with direction cosines
     u = (x_k - x_s)/d_k and v = y_k/d_k.
@@ -55,6 +57,7 @@ class TrackConfig:
     k_init: int = 2
     reset_period: int = 0  # steps between FP64 re-inversions (0 = never)
     P: float = 1.0
+    n_rf: int = 0        # RF chains of the hybrid front end of eq. (4) (0: fully digital)
 
     @property
     def N(self) -> int:
@@ -82,6 +85,13 @@ CONFIGS: Dict[str, TrackConfig] = {
     "c5": TrackConfig("c5", seed=5, nx=32, K=256, height_m=550e3, radius_m=200e3,
                       dt_s=0.005, steps=500, kr_db=3.0, snr_db=10.0, eta=0.999,
                       p=5, k_init=2, reset_period=50),
+    # Hybrid front end (the paper's simulation table): 16 x 16 array, 16 RF
+    # chains, 16 users, 600 km orbit, 50 ms updates over a 120 s pass, p = 1.
+    # The users' disk (250 km) spreads them over about 36 beams of the 16 x 16
+    # DFT grid, so most users get a beam of their own.
+    "h1": TrackConfig("h1", seed=16, nx=16, K=16, height_m=600e3, radius_m=250e3,
+                      dt_s=0.05, steps=2400, kr_db=10.0, snr_db=10.0, eta=0.9,
+                      p=1, k_init=2, reset_period=0, n_rf=16),
 }
 
 
@@ -130,8 +140,10 @@ class Track:
         self.mx = np.tile(m, cfg.nx)
         self.my = np.repeat(m, cfg.nx)
 
-    def _snap(self, t: np.ndarray) -> np.ndarray:
-        """H(t) for a vector of step indices t (shape T x K x N)."""
+    def _snap(self, t: np.ndarray, manifold: bool = False) -> np.ndarray:
+        """H(t) for a vector of step indices t (shape T x K x N); with
+        manifold, the array manifolds a(theta_n, phi_n) alone (the rows of
+        H~ in eq. (4), no gain and no NLOS term)."""
         cfg = self.cfg
         N = cfg.N
         t = np.asarray(t, dtype=np.float64)
@@ -144,6 +156,8 @@ class Track:
         beta = (cfg.height_m / d) ** 2
         a = np.exp(1j * np.pi * (u[:, :, None] * self.mx[None, None, :]
                                  + v[:, :, None] * self.my[None, None, :])) / math.sqrt(N)
+        if manifold:
+            return a.astype(np.complex128)
         kr = 10.0 ** (cfg.kr_db / 10.0)
         los = np.exp(1j * self.phase)[None, :, None] * a
         nlos = self.g[None, :, :] / math.sqrt(N)
@@ -154,14 +168,15 @@ class Track:
     def snapshot(self, t: int) -> np.ndarray:
         return self._snap(np.array([t]))[0]
 
-    def snapshots(self, t0: int = 0, count: Optional[int] = None) -> np.ndarray:
-        """H(t) for t = t0 .. t0+count-1 (default: the whole pass, steps+1)."""
+    def snapshots(self, t0: int = 0, count: Optional[int] = None, manifold: bool = False) -> np.ndarray:
+        """H(t) (or the manifolds H~(t)) for t = t0 .. t0+count-1 (default:
+        the whole pass, steps+1)."""
         if count is None:
             count = self.cfg.steps + 1 - t0
         out = np.empty((count, self.cfg.K, self.cfg.N), dtype=np.complex128)
         for c0 in range(0, count, 64):
             c1 = min(count, c0 + 64)
-            out[c0:c1] = self._snap(np.arange(t0 + c0, t0 + c1))
+            out[c0:c1] = self._snap(np.arange(t0 + c0, t0 + c1), manifold)
         return out
 
 

@@ -1,0 +1,236 @@
+"""GPU parity of the hybrid front end of eq. (4) (rzf_beamspace) against the
+FP64 oracle, and of the whole hybrid chain: beams and H_eff from the array
+manifolds, Alg. 2 on H_eff, eq. (15) on H F_RF.
+
+Tolerances from the arithmetic: each response is two FP32 sums, of nx and of
+ny twiddled terms; as the codebook is unitary, the error of G relative to
+||h|| is about eps32 (sqrt(nx) + sqrt(ny)) for sums in order, plus an ulp per
+twiddle.  tol_eff = 8 eps32 (sqrt(nx) + sqrt(ny) + 2) bounds H_eff against
+the oracle's H F_RF (relative Frobenius), and a beam's FP32 power |G|^2 is off
+by at most about 2 |G| that, i.e. band = 4 eps32 (sqrt(nx) + sqrt(ny) + 2)
+relative to ||h_n||^2 (plus K eps32 for the total power of extra chains).
+
+Beam choices are integers decided from FP32 powers on the GPU and FP64 powers
+in the oracle: every choice the GPU makes must be a valid greedy step in FP64
+given its earlier choices (its power within the band of the best untaken
+beam), so the two agree exactly wherever the best beam leads by more than the
+band.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle.rzf as orz
+from paper_2512_16543_amd import rzf, workload as wl
+from tests.test_gpu_parity import TOL_FP32, _assert_recs, c64, dev, host, rel, run_snapshots
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -24
+
+
+def tol_eff(nx, ny):
+    return 8 * EPS32 * (math.sqrt(nx) + math.sqrt(ny) + 2)
+
+
+def band(nx, ny):
+    return 4 * EPS32 * (math.sqrt(nx) + math.sqrt(ny) + 2)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = rzf.Context(0, 256 << 20)
+    yield c
+    c.close()
+
+
+def _channel(K, N, seed):
+    return c64(wl.random_channel(K, N, seed, scale=1.0)).astype(np.complex128)
+
+
+def _gpu_beamspace(ctx, H, nx, ny, n_rf):
+    K = H.shape[0]
+    beams = torch.full((n_rf,), -7, dtype=torch.int32, device="cuda")
+    Heff = torch.empty(K, n_rf, dtype=torch.complex64, device="cuda")
+    ctx.beamspace(dev(H), nx, ny, beams, Heff)
+    ctx.sync()
+    return beams.cpu().numpy().astype(np.int64), Heff
+
+
+def check_greedy(H, nx, ny, beams):
+    """Every GPU choice is a greedy step of the best-power rule in FP64 given
+    the earlier choices; returns how many steps differed from the oracle's
+    own choice (near-ties)."""
+    K, N = H.shape
+    bd = band(nx, ny)
+    n_rf = len(beams)
+    assert len(set(beams.tolist())) == n_rf and beams.min() >= 0 and beams.max() < N
+    pw = np.abs(H @ orz.dft_codebook(nx, ny)) ** 2
+    tot = pw.sum(axis=0)
+    taken = np.zeros(N, dtype=bool)
+    ties = 0
+    for c, b in enumerate(beams):
+        v = pw[c] if c < K else tot
+        lim = bd * np.sum(np.abs(H[c]) ** 2) if c < K else (bd + K * EPS32) * np.sum(np.abs(H) ** 2)
+        cand = np.where(taken, -1.0, v)
+        best = int(np.argmax(cand))
+        assert not taken[b], (c, b)
+        assert cand[best] - v[b] <= lim, (c, b, best, cand[best], v[b])
+        ties += int(b != best)
+        taken[b] = True
+    return ties
+
+
+# (K, nx, ny, n_rf): the paper's 16 x 16 array with 16 chains, extra chains,
+# ragged and one-sided arrays (N up to RZF_NMAX, nx + ny = N + 1), K up to 256
+SHAPES = [(16, 16, 16, 16), (5, 8, 4, 9), (1, 1, 1, 1), (3, 5, 3, 7), (64, 32, 32, 100),
+          (256, 64, 64, 256), (2, 4096, 1, 3), (4, 1, 64, 4), (7, 13, 11, 30)]
+
+
+@pytest.mark.parametrize("K,nx,ny,n_rf", SHAPES)
+def test_beamspace_random_channel(ctx, K, nx, ny, n_rf):
+    H = _channel(K, nx * ny, 300 + K + nx)
+    print(f"beamspace K={K} nx={nx} ny={ny} n_rf={n_rf}", flush=True)
+    beams, Heff = _gpu_beamspace(ctx, H, nx, ny, n_rf)
+    ties = check_greedy(H, nx, ny, beams)
+    bo, _ = orz.beamspace(H, nx, ny, n_rf)
+    assert ties <= max(1, n_rf // 50)
+    if ties == 0:
+        assert np.array_equal(beams, bo)
+    err = rel(host(Heff), orz.beam_channel(H, nx, ny, beams))
+    print(f"  ties={ties} rel={err:.2e} tol={tol_eff(nx, ny):.2e}", flush=True)
+    assert err <= tol_eff(nx, ny)
+
+
+@pytest.mark.parametrize("t", [0, 700, 2400])
+def test_beamspace_manifolds(ctx, t):
+    # LoS manifolds of the hybrid configuration: the front end's real input
+    cfg = wl.CONFIGS["h1"]
+    M = wl.make_track(cfg, 0).snapshots(t, 1, manifold=True)[0]
+    M = c64(M).astype(np.complex128)
+    beams, Heff = _gpu_beamspace(ctx, M, cfg.nx, cfg.nx, cfg.n_rf)
+    bo, He = orz.beamspace(M, cfg.nx, cfg.nx, cfg.n_rf)
+    assert check_greedy(M, cfg.nx, cfg.nx, beams) == 0
+    assert np.array_equal(beams, bo)
+    assert rel(host(Heff), He) <= tol_eff(cfg.nx, cfg.nx)
+
+
+def test_beamspace_on_grid_users_and_exact_tie(ctx):
+    nx, ny = 8, 4
+    F = orz.dft_codebook(nx, ny)
+    own = [5, 17, 0, 30]
+    H = c64(F[:, own].conj().T).astype(np.complex128)
+    beams, Heff = _gpu_beamspace(ctx, H, nx, ny, 4)
+    assert beams.tolist() == own
+    assert rel(host(Heff), np.eye(4)) <= tol_eff(nx, ny)
+    # h = [1, 0] on two elements has power 1/2 in both beams, exactly in FP32
+    H2 = np.array([[1.0, 0.0], [1.0, 0.0]], dtype=complex)
+    beams2, Heff2 = _gpu_beamspace(ctx, H2, 2, 1, 2)
+    assert beams2.tolist() == [0, 1]
+    np.testing.assert_allclose(np.abs(host(Heff2)) ** 2, 0.5, rtol=1e-6)
+
+
+def test_beamspace_given_beams(ctx):
+    K, nx, ny = 6, 8, 8
+    H = _channel(K, nx * ny, 11)
+    sel = np.array([63, 0, 5, 5, 17, 40, 2], dtype=np.int32)   # a repeated beam is allowed
+    beams = torch.from_numpy(sel).cuda()
+    Heff = torch.empty(K, len(sel), dtype=torch.complex64, device="cuda")
+    ctx.beamspace(dev(H), nx, ny, beams, Heff, select=False)
+    ctx.sync()
+    assert np.array_equal(beams.cpu().numpy(), sel)    # an input: left as given
+    assert rel(host(Heff), orz.beam_channel(H, nx, ny, sel)) <= tol_eff(nx, ny)
+
+
+def test_beamspace_strided(ctx):
+    K, nx, ny, n_rf = 9, 4, 8, 12
+    H = _channel(K, nx * ny, 12)
+    Hbig = torch.zeros(K, nx * ny + 5, dtype=torch.complex64, device="cuda")
+    Hbig[:, : nx * ny] = dev(H)
+    Ebig = torch.full((K, n_rf + 3), 7 + 7j, dtype=torch.complex64, device="cuda")
+    beams = torch.empty(n_rf, dtype=torch.int32, device="cuda")
+    ctx.beamspace(Hbig[:, : nx * ny], nx, ny, beams, Ebig[:, :n_rf])
+    ctx.sync()
+    b = beams.cpu().numpy().astype(np.int64)
+    check_greedy(H, nx, ny, b)
+    assert rel(host(Ebig[:, :n_rf]), orz.beam_channel(H, nx, ny, b)) <= tol_eff(nx, ny)
+    assert torch.all(Ebig[:, n_rf:] == 7 + 7j)
+
+
+def test_beamspace_bad_beam_reported_at_sync(ctx):
+    K, nx, ny = 3, 4, 4
+    H = _channel(K, nx * ny, 13)
+    beams = torch.tensor([1, 16, 2], dtype=torch.int32, device="cuda")
+    Heff = torch.full((K, 3), 1 + 1j, dtype=torch.complex64, device="cuda")
+    ctx.beamspace(dev(H), nx, ny, beams, Heff, select=False)
+    assert ctx.sync_status() == rzf.RZF_E_INVALID
+    E = host(Heff)
+    assert np.all(E[:, 1] == 0)
+    assert rel(E[:, [0, 2]], orz.beam_channel(H, nx, ny, [1, 2])) <= tol_eff(nx, ny)
+    ctx.sync()   # the error word was cleared
+
+
+def test_beamspace_invalid_arguments(ctx):
+    L = rzf.lib()
+    H = torch.zeros(4, 16, dtype=torch.complex64, device="cuda")
+    E = torch.zeros(4, 8, dtype=torch.complex64, device="cuda")
+    b = torch.zeros(8, dtype=torch.int32, device="cuda")
+    hp, ep, bp = H.data_ptr(), E.data_ptr(), b.data_ptr()
+    call = lambda K, nx, ny, ldh, n_rf, sel, lde: L.rzf_beamspace(ctx.h, K, nx, ny, hp, ldh, n_rf, sel, bp,
+                                                                  ep, lde)
+    assert call(4, 4, 4, 16, 8, 1, 8) == rzf.RZF_OK
+    ctx.sync()
+    assert call(4, 4, 4, 16, 3, 1, 8) == rzf.RZF_E_SHAPE       # n_rf < K when selecting
+    assert call(4, 4, 4, 16, 3, 0, 8) == rzf.RZF_OK            # fine for given beams
+    ctx.sync()
+    assert call(4, 4, 4, 16, 17, 0, 17) == rzf.RZF_E_SHAPE     # n_rf > N
+    assert call(4, 4, 4, 15, 8, 1, 8) == rzf.RZF_E_SHAPE       # ldh < N
+    assert call(4, 4, 4, 16, 8, 1, 7) == rzf.RZF_E_SHAPE       # ld_eff < n_rf
+    assert call(0, 4, 4, 16, 8, 1, 8) == rzf.RZF_E_SHAPE
+    assert call(257, 4, 4, 16, 8, 1, 8) == rzf.RZF_E_SHAPE
+    assert call(4, 128, 64, 8192, 8, 1, 8) == rzf.RZF_E_SHAPE  # N > RZF_NMAX
+    assert call(4, 0, 4, 16, 8, 1, 8) == rzf.RZF_E_SHAPE
+    assert call(4, 4, 4, 16, 8, 2, 8) == rzf.RZF_E_INVALID
+    assert L.rzf_beamspace(ctx.h, 4, 4, 4, None, 16, 8, 1, bp, ep, 8) == rzf.RZF_E_INVALID
+    assert L.rzf_beamspace(None, 4, 4, 4, hp, 16, 8, 1, bp, ep, 8) == rzf.RZF_E_INVALID
+
+
+@pytest.mark.parametrize("eta,dt", [(0.9, 0.5), (0.999, 0.05)])
+def test_hybrid_track(ctx, eta, dt):
+    """The whole hybrid chain against the oracle's: the GPU's beams and H_eff
+    from the manifolds feed its track; the oracle runs its own front end (the
+    GPU's beam indices only where a near-tie made them differ) and Alg. 2 in
+    FP64; eq. (15) is scored on H(t) F_RF on both sides."""
+    cfg = wl.with_overrides(wl.CONFIGS["h1"], dt_s=dt, steps=400)
+    steps, t0 = 10, 150
+    tr = wl.make_track(cfg, 1)
+    Ms = c64(tr.snapshots(t0, steps + 1, manifold=True)).astype(np.complex128)
+    Hs = c64(tr.snapshots(t0, steps + 1)).astype(np.complex128)
+    nx = cfg.nx
+    heff_o, heff_g, beams_g = [], [], []
+    for t in range(steps + 1):
+        b, He = _gpu_beamspace(ctx, Ms[t], nx, nx, cfg.n_rf)
+        ties = check_greedy(Ms[t], nx, nx, b)
+        bo, Ho = orz.beamspace(Ms[t], nx, nx, cfg.n_rf)
+        heff_o.append(Ho if ties == 0 else orz.beam_channel(Ms[t], nx, nx, b))
+        assert rel(host(He), heff_o[-1]) <= tol_eff(nx, nx)
+        heff_g.append(He)
+        beams_g.append(b)
+    switched = sum(not np.array_equal(beams_g[t], beams_g[t - 1]) for t in range(1, steps + 1))
+    d = dict(k_init=cfg.k_init, p=cfg.p, P=cfg.P, seed=cfg.seed, track_id=1, reset_period=0)
+    recs = run_snapshots(ctx, heff_o, cfg.alpha, d, eta, dev_inputs=heff_g)
+    print([(r["path"], r["r"], r["iters"]) for r in recs], "beam switches", switched, flush=True)
+    _assert_recs(recs)
+    if dt >= 0.5:
+        assert switched >= 3
+    # eq. (15) through the analog stage, for the last precoder
+    W = dev(orz.full_rzf(heff_o[-1], cfg.alpha, cfg.P))
+    Ht = torch.empty(cfg.K, cfg.n_rf, dtype=torch.complex64, device="cuda")
+    ctx.beamspace(dev(Hs[-1]), nx, nx, torch.from_numpy(beams_g[-1].astype(np.int32)).cuda(), Ht,
+                  select=False)
+    R = ctx.sum_rate(Ht, W, cfg.P, cfg.sigma2)
+    _, Ro = orz.sum_rate(orz.beam_channel(Hs[-1], nx, nx, beams_g[-1]), host(W), cfg.P, cfg.sigma2)
+    assert abs(R - Ro) <= 10 * TOL_FP32 * abs(Ro)

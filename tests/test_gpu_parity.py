@@ -177,13 +177,16 @@ def run_track(ctx, cfg, steps, eta, prm_kw=None):
     return run_snapshots(ctx, Hs, cfg.alpha, d, eta)
 
 
-def run_snapshots(ctx, Hs, alpha, d, eta, tie_band=TIE_BAND):
+def run_snapshots(ctx, Hs, alpha, d, eta, tie_band=TIE_BAND, dev_inputs=None):
     """GPU and oracle side by side over the snapshots Hs (complex64 values);
     before every step the oracle adopts the GPU's state (one-step parity).
-    `d` holds the track parameters.  Returns per-step records."""
+    `d` holds the track parameters.  dev_inputs, if given, are the device
+    matrices the GPU side consumes in place of Hs (a front end's own output
+    for the same snapshots).  Returns per-step records."""
     K, N = Hs[0].shape
     steps = len(Hs) - 1
-    tr = ctx.init(dev(Hs[0]), alpha, rzf.default_params(**d))
+    gin = dev_inputs if dev_inputs is not None else [None] * len(Hs)
+    tr = ctx.init(gin[0] if gin[0] is not None else dev(Hs[0]), alpha, rzf.default_params(**d))
     ot = orz.OracleTrack(Hs[0], _oracle_params_a(alpha, d))
     W = torch.empty(N, K, dtype=torch.complex64, device="cuda")
     recs = []
@@ -195,7 +198,7 @@ def run_snapshots(ctx, Hs, alpha, d, eta, tie_band=TIE_BAND):
         q = tr.query()
         state["last_r"] = q["last_r"]
         ot.import_state(state)
-        info = tr.update(dev(Hs[t]), eta, W)
+        info = tr.update(gin[t] if gin[t] is not None else dev(Hs[t]), eta, W)
         ctx.sync()
         gi = (info.r, info.iters, info.path)
         Wo, io = ot.update(Hs[t], eta)

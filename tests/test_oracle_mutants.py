@@ -102,6 +102,43 @@ def m_words_to_cn_unscaled(wa, wb):
     return rad * np.exp(2j * np.pi * ub)
 
 
+def _codebook_variant(kind):
+    def f(nx, ny):
+        N = nx * ny
+        mx = np.tile(np.arange(nx), ny)
+        my = np.repeat(np.arange(ny), nx)
+        b = np.arange(N)
+        p, q = b % nx, b // nx
+        if kind == "swap_axes":
+            p, q = b // ny, b % ny
+        sgn = -1.0 if kind == "minus_j" else 1.0
+        ph = sgn * 2.0 * np.pi * (np.outer(mx, p) / nx + np.outer(my, q) / ny)
+        return np.exp(1j * ph) / (1.0 if kind == "unnormalised" else math.sqrt(N))
+    return f
+
+
+def _beamspace_variant(kind):
+    def f(Ht, nx, ny, n_rf):
+        K, N = Ht.shape
+        G = Ht @ orz.dft_codebook(nx, ny)
+        pw = np.abs(G) ** 2
+        taken = np.zeros(N, dtype=bool)
+        beams = []
+        for n in range(K):
+            cand = pw[n] if kind == "no_exclusion" else np.where(taken, -1.0, pw[n])
+            b = int(N - 1 - np.argmax(cand[::-1])) if kind == "last_on_tie" else int(np.argmax(cand))
+            taken[b] = True
+            beams.append(b)
+        score = pw.max(axis=0) if kind == "extra_by_max" else pw.sum(axis=0)
+        for _ in range(n_rf - K):
+            b = int(np.argmax(np.where(taken, -1.0, score)))
+            taken[b] = True
+            beams.append(b)
+        beams = np.array(beams, dtype=np.int64)
+        return beams, G[:, beams]
+    return f
+
+
 MUTANTS = [
     ("gram_no_alpha", orz, "gram", m_gram_no_alpha, ["test_gram_bruteforce", "test_gram_hermitian_positive_definite"]),
     ("gram_transposed", orz, "gram", m_gram_transposed, ["test_gram_bruteforce"]),
@@ -121,6 +158,15 @@ MUTANTS = [
     ("philox_m0", philox, "PHILOX_M0", philox.PHILOX_M0 ^ 1, ["test_philox_known_answers"]),
     ("philox_w1", philox, "PHILOX_W1", philox.PHILOX_W1 + 2, ["test_philox_known_answers"]),
     ("box_muller_unscaled", philox, "words_to_cn", m_words_to_cn_unscaled, ["test_sketch_is_standard_complex_gaussian"]),
+    ("codebook_minus_j", orz, "dft_codebook", _codebook_variant("minus_j"),
+     [("test_dft_codebook_is_inverse_fft", dict(nx=4, ny=2))]),
+    ("codebook_swap_axes", orz, "dft_codebook", _codebook_variant("swap_axes"),
+     [("test_dft_codebook_is_inverse_fft", dict(nx=3, ny=5))]),
+    ("codebook_unnormalised", orz, "dft_codebook", _codebook_variant("unnormalised"),
+     [("test_dft_codebook_orthonormal", dict(nx=4, ny=2))]),
+    ("beamspace_no_exclusion", orz, "beamspace", _beamspace_variant("no_exclusion"), ["test_beamspace_conflict_and_ties"]),
+    ("beamspace_last_on_tie", orz, "beamspace", _beamspace_variant("last_on_tie"), ["test_beamspace_conflict_and_ties"]),
+    ("beamspace_extra_by_max", orz, "beamspace", _beamspace_variant("extra_by_max"), ["test_beamspace_conflict_and_ties"]),
 ]
 
 
@@ -129,12 +175,13 @@ def test_pins_reject_mutant(name, mod, attr, repl, pin_names, monkeypatch, golde
     monkeypatch.setattr(mod, attr, repl)
     caught = False
     for pn in pin_names:
+        pn, kw = pn if isinstance(pn, tuple) else (pn, {})
         fn = getattr(pins, pn)
         try:
             if "golden_dir" in fn.__code__.co_varnames[:fn.__code__.co_argcount]:
-                fn(golden_dir)
+                fn(golden_dir, **kw)
             else:
-                fn()
+                fn(**kw)
         except (AssertionError, ValueError, np.linalg.LinAlgError, IndexError):
             caught = True
     assert caught, f"mutant {name} survived pins {pin_names}"

@@ -655,8 +655,9 @@ def test_beamspace_conflict_and_ties():
     F = orz.dft_codebook(nx, ny)
     f = lambda b: F[:, b].conj()
     # user 1's strongest beam (5) is user 0's: it takes its second (2); the
-    # extra chains then go by total power: beam 7, then beam 0
-    H = np.array([f(5) + 0.1 * f(7), 0.9 * f(5) + 0.5 * f(2) + 0.45 * f(7) + 0.4 * f(0)])
+    # extra chains then go by total power: beam 7 (0.09 + 0.09), then beam 0
+    # (0.16, the larger single-user power)
+    H = np.array([f(5) + 0.3 * f(7), 0.9 * f(5) + 0.5 * f(2) + 0.3 * f(7) + 0.4 * f(0)])
     beams, _ = orz.beamspace(H, nx, ny, 4)
     assert list(beams) == [5, 2, 7, 0]
     # an exact tie (two elements, h = [1, 0] sees both beams with power 1/2):
