@@ -14,11 +14,13 @@
 //   Some r meets the energy target of eq. (14) exactly when the total
 //   sum_j sigma_j^2 = ||B||_F^2 = ||Z||_F^2 does, so a failing iteration needs
 //   no SVD: k0 <- 2 k0 and the next iteration draws a new sketch.
-//   On success: SVD of B by one-sided (Hestenes) Jacobi on the columns of Z;
-//   every rotation is applied to the columns of Q as well, so at convergence
-//   z_j = sigma_j v_j and q_j = (Q U_hat)_j, and U_r Sigma_r V_r^H =
-//   sum_{j<=r} q_j z_j^H needs no division by sigma.  r is the smallest
-//   count whose leading sigma_j^2 reach eta ||Delta A||_F^2.
+//   On success: SVD of B by one-sided (Hestenes) Jacobi on the columns of Z:
+//   Z J has orthogonal columns z_j = sigma_j v_j (V_hat = Z J Sigma^-1, and
+//   U_hat = J).  r is the smallest count whose leading sigma_j^2 reach
+//   eta ||Delta A||_F^2.  J itself is never formed: B V_hat = U_hat Sigma
+//   gives the retained left vectors as U_r = Q U_hat_r = Q Q^H Delta A Z_r
+//   Sigma_r^-2 (three small matrix-core products, only when the step takes
+//   the Woodbury branch), so U_r Sigma_r V_r^H = sum_{j<=r} u_j z_j^H.
 //   After I_max failing iterations r = d and U_r Sigma_r V_r^H = Q Z^H.
 //
 // Woodbury (Sec. III-A, steps 1-5) in the equivalent scaled form with
@@ -49,7 +51,8 @@ struct Shared {
   float2 b0[KS * LDK];           // Delta A (row-major, ld LDK); later A^-1 or A'
   float2 b1[KS * LDK];           // column-major K x d (ld LDK): Omega, then Q
   float2 b2[KS * LDK];           // column-major K x d (ld LDK): Y / reflectors, then Z
-  float2 pm[WB_RMAX * LDK];      // P = A^-1 U, column-major
+  float2 pm[WB_RMAX * LDK];      // U (after the SVD), column-major
+  float2 tm[WB_RMAX * LDK];      // Q^H Delta A Z_r, then P = A^-1 U, column-major
   double s2[KS];                 // ||z_j||^2
   double2 fcol[WB_RMAX];         // Gauss-Jordan: multipliers of column j
   double2 ustash[WB_RMAX + KS];  // Gauss-Jordan: normalised pivot row
@@ -132,14 +135,15 @@ __device__ __forceinline__ void lds_gemm(int M, int Nc, int Kd, const LA& la, co
   }
 }
 
-// One-sided Jacobi on the d columns of Z (b2), rotating Q (b1) alongside.
+// One-sided Jacobi on the d columns of Z (b2).
 // Each 16-lane row of a wave owns one column pair per round (4 rows of the
 // matrix per lane), so a round of the round-robin ordering is one barrier.
-// ||z_p||^2 and ||z_q||^2 are sums of non-negative FP32 terms; the inner
-// product z_p^H z_q, which cancels as the columns become orthogonal, is
-// accumulated in FP64 (FP32 products are exact there).
+// ||z_p||^2 and ||z_q||^2 are sums of non-negative FP32 terms.  The inner
+// product z_p^H z_q cancels as the columns become orthogonal: each lane
+// forms its 4-row share in FP32 (error about 2^-24 ||z_p|| ||z_q||, a few
+// percent of the rotation threshold 2e-6 ||z_p|| ||z_q||) and the 16 shares
+// are added in FP64.
 __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* rounds_out) {
-  float2* b1 = sm.b1;
   float2* b2 = sm.b2;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int li = lane & 15, slot = wid * 4 + (lane >> 4);
@@ -163,29 +167,24 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
         // every lane takes its four rows without a bound check
         float2* zpc = b2 + pp * LDK + li;
         float2* zqc = b2 + qq * LDK + li;
-        float2* qpc = b1 + pp * LDK + li;
-        float2* qqc = b1 + qq * LDK + li;
-        float2 zp[4], zq[4], qa[4], qb[4];
-        float al = 0.f, be = 0.f;
-        double gr = 0.0, gi = 0.0;
+        float2 zp[4], zq[4];
+        float al = 0.f, be = 0.f, grf32 = 0.f, gif32 = 0.f;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           zp[m] = zpc[16 * m];
           zq[m] = zqc[16 * m];
-          qa[m] = qpc[16 * m];     // loaded early to overlap latency
-          qb[m] = qqc[16 * m];
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           al += cabs2(zp[m]);
           be += cabs2(zq[m]);
-          gr += (double)zp[m].x * zq[m].x + (double)zp[m].y * zq[m].y;
-          gi += (double)zp[m].x * zq[m].y - (double)zp[m].y * zq[m].x;
+          grf32 = fmaf(zp[m].x, zq[m].x, fmaf(zp[m].y, zq[m].y, grf32));
+          gif32 = fmaf(zp[m].x, zq[m].y, fmaf(-zp[m].y, zq[m].x, gif32));
         }
         al = row16_sum(al);
         be = row16_sum(be);
-        gr = row16_sum(gr);
-        gi = row16_sum(gi);
+        const double gr = row16_sum((double)grf32);
+        const double gi = row16_sum((double)gif32);
         const float mx = fmaxf(al, be);
         bool rot = act && mx > 0.f;
         float c = 1.f, s = 0.f;
@@ -213,11 +212,9 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
         if (rot) {
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            const float2 zq2 = cmul(e, zq[m]), qv2 = cmul(e, qb[m]);
+            const float2 zq2 = cmul(e, zq[m]);
             zpc[16 * m] = csub(cscale(zp[m], c), cscale(zq2, s));
             zqc[16 * m] = cadd(cscale(zp[m], s), cscale(zq2, c));
-            qpc[16 * m] = csub(cscale(qa[m], c), cscale(qv2, s));
-            qqc[16 * m] = cadd(cscale(qa[m], s), cscale(qv2, c));
           }
           if (li == 0) sm.nrot = 1;
         }
@@ -416,13 +413,39 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   // Alg. 2's switch k_est <= switch * K, within the Woodbury workspace
   bool use_wb = r <= td->wb_limit;
   int path = use_wb ? RZF_PATH_WB : RZF_PATH_FULL_RANK;
+  float2* pm = sm.pm;
+  float2* tm = sm.tm;
+  if (rotated && use_wb) {
+    // U_r = Q U_hat_r = Q Q^H Delta A Z_r Sigma_r^-2 (B V_hat = U_hat Sigma with
+    // V_hat = Z Sigma^-1); every retained sigma_j is positive
+    const int* ord = sm.order;
+    lds_gemm(K, r, K,
+             [&](int i, int k) { return (i < K && k < K) ? b0[i * LDK + k] : cz(); },
+             [&](int k, int c) { return (k < K && c < r) ? b2[ord[c] * LDK + k] : cz(); },
+             [&](int i, int c, float2 v) { pm[c * LDK + i] = v; });
+    __syncthreads();
+    lds_gemm(d, r, K,
+             [&](int j, int k) { return (j < d && k < K) ? cconj(b1[j * LDK + k]) : cz(); },
+             [&](int k, int c) { return (k < K && c < r) ? pm[c * LDK + k] : cz(); },
+             [&](int j, int c, float2 v) { tm[c * LDK + j] = v; });
+    __syncthreads();
+    lds_gemm(K, r, d,
+             [&](int i, int j) { return (i < K && j < d) ? b1[j * LDK + i] : cz(); },
+             [&](int j, int c) { return (j < d && c < r) ? tm[c * LDK + j] : cz(); },
+             [&](int i, int c, float2 v) {
+               const double s2 = sm.s2[ord[c]];
+               pm[c * LDK + i] = make_float2((float)(v.x / s2), (float)(v.y / s2));
+             });
+    __syncthreads();
+  }
+  const float2* Ub = rotated ? pm : b1;   // column c of U at Ub[c * LDK]
   if (fb && use_wb) {
     // residual of the rank-r update: R = (Delta A + R) - U V~^H, read from b0
     // before the Woodbury step reuses it (a direct inversion clears R below)
     float2* R = td->Rfb;
     const int* ord = sm.order;
     lds_gemm(K, K, r,
-             [&](int i, int c) { return (i < K && c < r) ? b1[ord[c] * LDK + i] : cz(); },
+             [&](int i, int c) { return (i < K && c < r) ? Ub[c * LDK + i] : cz(); },
              [&](int c, int j) { return (c < r && j < K) ? cconj(b2[ord[c] * LDK + j]) : cz(); },
              [&](int i, int j, float2 v) { R[(size_t)i * K + j] = csub(b0[i * LDK + j], v); });
     __syncthreads();
@@ -436,12 +459,11 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     }
     __syncthreads();
     const int* ord = sm.order;
-    float2* pm = sm.pm;
     // step 1: P = A^-1 U
     lds_gemm(K, r, K,
              [&](int i, int k) { return (i < K && k < K) ? b0[i * LDK + k] : cz(); },
-             [&](int k, int c) { return (k < K && c < r) ? b1[ord[c] * LDK + k] : cz(); },
-             [&](int i, int c, float2 v) { pm[c * LDK + i] = v; });
+             [&](int k, int c) { return (k < K && c < r) ? Ub[c * LDK + k] : cz(); },
+             [&](int i, int c, float2 v) { tm[c * LDK + i] = v; });
     __syncthreads();
     // step 2: C = I + V~^H P (r x r), and V~^H A^-1 (r x K); tiles held in
     // registers until every wave has finished reading U and V~
@@ -460,7 +482,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       };
       auto lbc = [&](int k, int cc) {
         const int b = my_tj * 16 + cc;
-        return (k < K && b < r) ? pm[b * LDK + k] : cz();
+        return (k < K && b < r) ? tm[b * LDK + k] : cz();
       };
       auto lbq = [&](int k, int cc) {
         const int j = my_tj * 16 + cc;
@@ -542,7 +564,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       // steps 4-5: A^-1 <- A^-1 - P X
       float2* out = td->Ainv;
       lds_gemm(K, K, r,
-               [&](int i, int a) { return (i < K && a < r) ? pm[a * LDK + i] : cz(); },
+               [&](int i, int a) { return (i < K && a < r) ? tm[a * LDK + i] : cz(); },
                [&](int a, int j) { return (a < r && j < K) ? d2f(aug[a * ldg + r + j]) : cz(); },
                [&](int i, int j, float2 v) { out[(size_t)i * K + j] = csub(b0[i * LDK + j], v); });
     }
