@@ -4,9 +4,9 @@
 // Same computation and the same order as k_arsvd_wb (arsvd.hip): per
 // iteration Omega -> Y = Delta A Omega -> Q = orth(Y) (Householder) ->
 // Z = Delta A^H Q, the ||Z||_F^2 test of eq. (14), on success a one-sided
-// Jacobi SVD of B = Z^H with Q rotated alongside, the rank rule, then the
-// Woodbury update of eq. (12) in the scaled form (U = Q columns, V~ = Z
-// columns) or direct inversion of A'.
+// Jacobi SVD of B = Z^H, the rank rule, U_r rebuilt as Q Q^H Delta A Z_r
+// Sigma_r^-2, then the Woodbury update of eq. (12) in the scaled form (U_r,
+// V~ = Z columns) or direct inversion of A'.
 //
 // What changes with K: the K x d factors no longer fit in LDS, so each track
 // keeps them in its own global workspace (column-major Y, Q, Z; row-major
@@ -17,9 +17,9 @@
 //     compact WY form H_0..H_15 = I - V T V^H is applied to the trailing
 //     columns with three 16-wide products on the matrix cores, and Q is
 //     formed by the same blocks in reverse order;
-//   * one-sided Jacobi in column blocks: block pairs of Z and Q are staged
-//     in LDS and every column pair is rotated once per pass (d <= 2b: all
-//     columns in LDS, plain cyclic sweeps);
+//   * one-sided Jacobi in column blocks: block pairs of Z are staged in LDS
+//     and every column pair is rotated once per pass (d <= 2b: all columns
+//     in LDS, plain cyclic sweeps);
 //   * Gauss-Jordan with partial pivoting on [C | V~^H A^-1] in 32-column
 //     panels: the panel is eliminated in LDS, recording its pivots and
 //     multipliers, then every other column replays them;
@@ -46,8 +46,7 @@ struct BigShared {
       float2 ws[NWV * 256];           // per-wave 16 x 16 scratch
     } qr;
     struct {
-      float2 z[JOB_ELEMS];            // job columns of Z (column-major, ld K)
-      float2 q[JOB_ELEMS];            // job columns of Q
+      float2 z[2 * JOB_ELEMS];        // job columns of Z (column-major, ld K)
     } jac;
     struct {
       double2 pan[RB * GJ_W];         // capacitance panel (row-major, ld GJ_W)
@@ -282,53 +281,51 @@ __device__ __forceinline__ void qr_big(BigShared& sm, float2* Ym, float2* Qm, in
 // ------------------------------------------------------------ Jacobi
 template <int G>
 __device__ __forceinline__ float gsumf(float v) {
-  if constexpr (G == 64) return wave_sumf(v);
   v = row16_sumf(v);
+  if constexpr (G == 16) return v;
   return v + __shfl_xor(v, 16);
 }
 template <int G>
 __device__ __forceinline__ double gsumd(double v) {
-  if constexpr (G == 64) return wave_sum(v);
   v = row16_sum(v);
+  if constexpr (G == 16) return v;
   return v + __shfl_xor(v, 16);
 }
 
-// Rotation of the job column pair (pp, qq) held in LDS (Z in sm.u.jac.z, Q
-// in sm.u.jac.q, column c at c*K) by the calling group of G lanes (rows
-// gl + G m, m < 4): the one-sided Jacobi step that makes z_p and z_q
-// orthogonal, applied to q_p and q_q as well.  ||z_p||^2 and ||z_q||^2 are
-// sums of non-negative FP32 terms; the inner product z_p^H z_q, which cancels
-// as the columns become orthogonal, is accumulated in FP64.  A pair already
+// Rotation of the job column pair (pp, qq) of Z held in LDS (sm.u.jac.z,
+// column c at c*K) by the calling group of G lanes (rows gl + G m, m < JR):
+// the one-sided Jacobi step that makes z_p and z_q orthogonal.  ||z_p||^2
+// and ||z_q||^2 are sums of non-negative FP32 terms.  The inner product
+// z_p^H z_q cancels as the columns become orthogonal: each lane forms its
+// share in FP32 (error about 2^-24 ||z_p|| ||z_q||, a few percent of the
+// rotation threshold) and the G shares are added in FP64.  A pair already
 // orthogonal to JACOBI_TOL is left alone.  Sets sm.nrot when it rotates.
 // Every lane of the wave calls it (act = false for an idle group).
+constexpr int JR = 8;   // rows per lane: G = 16 covers K <= 128, G = 32 K <= 256
 template <int G>
 __device__ __forceinline__ void jacobi_pair(BigShared& sm, int K, int pp, int qq, bool act) {
   float2* zb = sm.u.jac.z;
-  float2* qb = sm.u.jac.q;
   const int gl = threadIdx.x & (G - 1);
-  float2 zp[4], zq[4], qa[4], qv[4];
-  float al = 0.f, be = 0.f;
-  double gr = 0.0, gi = 0.0;
+  float2 zp[JR], zq[JR];
+  float al = 0.f, be = 0.f, grs = 0.f, gis = 0.f;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
+  for (int m = 0; m < JR; ++m) {
     const int i = gl + G * m;
     const bool ok = act && i < K;
     zp[m] = ok ? zb[pp * K + i] : cz();
     zq[m] = ok ? zb[qq * K + i] : cz();
-    qa[m] = ok ? qb[pp * K + i] : cz();
-    qv[m] = ok ? qb[qq * K + i] : cz();
   }
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
+  for (int m = 0; m < JR; ++m) {
     al += cabs2(zp[m]);
     be += cabs2(zq[m]);
-    gr += (double)zp[m].x * zq[m].x + (double)zp[m].y * zq[m].y;
-    gi += (double)zp[m].x * zq[m].y - (double)zp[m].y * zq[m].x;
+    grs = fmaf(zp[m].x, zq[m].x, fmaf(zp[m].y, zq[m].y, grs));
+    gis = fmaf(zp[m].x, zq[m].y, fmaf(-zp[m].y, zq[m].x, gis));
   }
   al = gsumf<G>(al);
   be = gsumf<G>(be);
-  gr = gsumd<G>(gr);
-  gi = gsumd<G>(gi);
+  const double gr = gsumd<G>((double)grs);
+  const double gi = gsumd<G>((double)gis);
   const float mx = fmaxf(al, be);
   bool rot = act && mx > 0.f;
   float c = 1.f, s = 0.f;
@@ -352,14 +349,12 @@ __device__ __forceinline__ void jacobi_pair(BigShared& sm, int K, int pp, int qq
   }
   if (rot) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < JR; ++m) {
       const int i = gl + G * m;
       if (i >= K) continue;
-      const float2 zq2 = cmul(e, zq[m]), qv2 = cmul(e, qv[m]);
+      const float2 zq2 = cmul(e, zq[m]);
       zb[pp * K + i] = csub(cscale(zp[m], c), cscale(zq2, s));
       zb[qq * K + i] = cadd(cscale(zp[m], s), cscale(zq2, c));
-      qb[pp * K + i] = csub(cscale(qa[m], c), cscale(qv2, s));
-      qb[qq * K + i] = cadd(cscale(qa[m], s), cscale(qv2, c));
     }
     if (gl == 0) sm.nrot = 1;
   }
@@ -386,9 +381,10 @@ __device__ __forceinline__ void jacobi_sweep(BigShared& sm, int K, int c0, int n
   }
 }
 
-// One-sided Jacobi SVD of B = Z^H with Q rotated alongside; every pass
-// rotates each column pair once, and the passes stop when one rotates
-// nothing (or after MAX_SWEEPS).
+// One-sided Jacobi SVD of B = Z^H (Z rotated in place; the rotations are
+// not accumulated); every pass rotates each column pair once, and the passes
+// stop when one rotates nothing (or after MAX_SWEEPS).  A round pairs up to
+// NTH / G columns; LDS holds NCMAX = 2 NTH / G columns (NCMAX K <= 2 JOB_ELEMS).
 //   d <= NCMAX: all d columns sit in LDS; a pass is one cyclic sweep.
 //   d > NCMAX: blocks of b = NCMAX/2 columns.  For each block A in turn,
 //     A is loaded, its own pairs take one cyclic sweep, then every later
@@ -396,14 +392,13 @@ __device__ __forceinline__ void jacobi_sweep(BigShared& sm, int K, int c0, int n
 //     A with column (i + s) mod b of B, so every pair (A_i, B_j) meets once.
 //     A ordering of the cyclic kind, pass by pass like the single-block one.
 template <int G>
-__device__ __forceinline__ void jacobi_big(BigShared& sm, float2* Zm, float2* Qm, int K, int d,
-                                           int* sweeps, int* rounds) {
-  constexpr int NCMAX = 2048 / G;    // 64 columns (G = 32) or 32 (G = 64)
+__device__ __forceinline__ void jacobi_big(BigShared& sm, float2* Zm, int K, int d, int* sweeps, int* rounds) {
+  constexpr int NCMAX = 2 * NTH / G;   // 128 columns (G = 16, K <= 128) or 64 (G = 32)
+  static_assert(NCMAX * (G * JR) <= 2 * JOB_ELEMS, "job columns exceed the LDS buffer");
   const int tid = threadIdx.x, wid = tid >> 6, slot = tid / G;
   float2* zb = sm.u.jac.z;
-  float2* qb = sm.u.jac.q;
   if (d <= NCMAX) {
-    for (int e = tid; e < d * K; e += NTH) { zb[e] = Zm[e]; qb[e] = Qm[e]; }
+    for (int e = tid; e < d * K; e += NTH) zb[e] = Zm[e];
     for (int pass = 0; pass < MAX_SWEEPS; ++pass) {
       if (tid == 0) sm.nrot = 0;
       __syncthreads();
@@ -413,7 +408,7 @@ __device__ __forceinline__ void jacobi_big(BigShared& sm, float2* Zm, float2* Qm
       __syncthreads();
       if (done) break;
     }
-    for (int e = tid; e < d * K; e += NTH) { Zm[e] = zb[e]; Qm[e] = qb[e]; }
+    for (int e = tid; e < d * K; e += NTH) Zm[e] = zb[e];
     __syncthreads();
     return;
   }
@@ -425,13 +420,13 @@ __device__ __forceinline__ void jacobi_big(BigShared& sm, float2* Zm, float2* Qm
     for (int A = 0; A < nblk; ++A) {
       const int na = min(b, d - A * b);
       const size_t ga = (size_t)A * b * K;
-      for (int e = tid; e < na * K; e += NTH) { zb[e] = Zm[ga + e]; qb[e] = Qm[ga + e]; }
+      for (int e = tid; e < na * K; e += NTH) zb[e] = Zm[ga + e];
       __syncthreads();
       jacobi_sweep<G>(sm, K, 0, na, rounds);
       for (int B = A + 1; B < nblk; ++B) {
         const int nb = min(b, d - B * b);
         const size_t gb = (size_t)B * b * K;
-        for (int e = tid; e < nb * K; e += NTH) { zb[b * K + e] = Zm[gb + e]; qb[b * K + e] = Qm[gb + e]; }
+        for (int e = tid; e < nb * K; e += NTH) zb[b * K + e] = Zm[gb + e];
         __syncthreads();
         for (int s = 0; s < b; ++s) {
           ++*rounds;
@@ -442,10 +437,10 @@ __device__ __forceinline__ void jacobi_big(BigShared& sm, float2* Zm, float2* Qm
           }
           __syncthreads();
         }
-        for (int e = tid; e < nb * K; e += NTH) { Zm[gb + e] = zb[b * K + e]; Qm[gb + e] = qb[b * K + e]; }
+        for (int e = tid; e < nb * K; e += NTH) Zm[gb + e] = zb[b * K + e];
         __syncthreads();
       }
-      for (int e = tid; e < na * K; e += NTH) { Zm[ga + e] = zb[e]; Qm[ga + e] = qb[e]; }
+      for (int e = tid; e < na * K; e += NTH) Zm[ga + e] = zb[e];
       __syncthreads();
     }
     const bool done = sm.nrot == 0;
@@ -708,8 +703,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
     const double tot = block_sum(zp, sm.red);
     t_qr += clock64() - c_mark; c_mark = clock64();
     if (tot >= Et) {
-      if (K <= 128) jacobi_big<32>(sm, Zm, Qm, K, d, &sweeps, &rounds);
-      else jacobi_big<64>(sm, Zm, Qm, K, d, &sweeps, &rounds);
+      if (K <= 128) jacobi_big<16>(sm, Zm, K, d, &sweeps, &rounds);
+      else jacobi_big<32>(sm, Zm, K, d, &sweeps, &rounds);
       t_jac += clock64() - c_mark; c_mark = clock64();
       rotated = true;
       pick_rank_big(sm, Zm, K, d, Et, &r, &captured, td->sig2);
@@ -733,6 +728,78 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
   bool use_wb = r <= td->wb_limit;
   int path = use_wb ? RZF_PATH_WB : RZF_PATH_FULL_RANK;
   float2* Ainv = td->Ainv;
+  float2* Pm = td->Pm;
+  if (rotated && use_wb) {
+    // U_r = Q U_hat_r = Q Q^H Delta A Z_r Sigma_r^-2 (B V_hat = U_hat Sigma
+    // with V_hat = Z Sigma^-1): T1 = Delta A Z_r -> Pm, T2 = Q^H T1 -> Ym (the
+    // reflectors are no longer needed), U -> Pm; every retained sigma_j > 0
+    const int* ord = sm.order;
+    const int rtl = (r + 15) / 16, dtl = (d + 15) / 16;
+    for (int tt = wid; tt < ktl * rtl; tt += NWV) {
+      const int ti = tt / rtl, tj = tt - ti * rtl;
+      floatx4 dr = zero4(), di = zero4();
+      ctile16([&](int i, int k) {
+                const int row = ti * 16 + i;
+                return (row < K && k < K) ? dA[(size_t)row * K + k] : cz();
+              },
+              [&](int k, int c) {
+                const int cc = tj * 16 + c;
+                return (k < K && cc < r) ? Zm[(size_t)ord[cc] * K + k] : cz();
+              },
+              0, up4(K), dr, di);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * 16 + tile_row(v), c = tj * 16 + tile_col();
+        if (row < K && c < r) Pm[(size_t)c * K + row] = make_float2(dr[v], di[v]);
+      }
+    }
+    __syncthreads();
+    for (int tt = wid; tt < dtl * rtl; tt += NWV) {
+      const int ti = tt / rtl, tj = tt - ti * rtl;
+      floatx4 dr = zero4(), di = zero4();
+      ctile16([&](int i, int k) {
+                const int j = ti * 16 + i;
+                return (j < d && k < K) ? cconj(Qm[(size_t)j * K + k]) : cz();
+              },
+              [&](int k, int c) {
+                const int cc = tj * 16 + c;
+                return (k < K && cc < r) ? Pm[(size_t)cc * K + k] : cz();
+              },
+              0, up4(K), dr, di);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = ti * 16 + tile_row(v), c = tj * 16 + tile_col();
+        if (j < d && c < r) Ym[(size_t)c * K + j] = make_float2(dr[v], di[v]);
+      }
+    }
+    __syncthreads();
+    for (int tt = wid; tt < ktl * rtl; tt += NWV) {
+      const int ti = tt / rtl, tj = tt - ti * rtl;
+      floatx4 dr = zero4(), di = zero4();
+      ctile16([&](int i, int j) {
+                const int row = ti * 16 + i;
+                return (row < K && j < d) ? Qm[(size_t)j * K + row] : cz();
+              },
+              [&](int j, int c) {
+                const int cc = tj * 16 + c;
+                return (j < d && cc < r) ? Ym[(size_t)cc * K + j] : cz();
+              },
+              0, up4(d), dr, di);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * 16 + tile_row(v), c = tj * 16 + tile_col();
+        if (row < K && c < r) {
+          const double s2 = sm.s2[ord[c]];
+          Pm[(size_t)c * K + row] = make_float2((float)(dr[v] / s2), (float)(di[v] / s2));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // column c of U at Ub[c * K]: the rebuilt vectors, or Q itself (unrotated,
+  // sm.order is the identity); P = A^-1 U goes to Ym
+  const float2* Ub = rotated ? Pm : Qm;
+  float2* Pw = Ym;
   if (fb && use_wb) {
     // residual of the rank-r update: R = (Delta A + R) - U V~^H (a direct
     // inversion clears R below)
@@ -743,7 +810,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
       floatx4 dr = zero4(), di = zero4();
       ctile16([&](int i, int c) {
                 const int row = ti * 16 + i;
-                return (row < K && c < r) ? Qm[(size_t)ord[c] * K + row] : cz();
+                return (row < K && c < r) ? Ub[(size_t)c * K + row] : cz();
               },
               [&](int c, int j) {
                 const int col = tj * 16 + j;
@@ -761,7 +828,6 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
   }
   if (use_wb) {
     const int* ord = sm.order;
-    float2* Pm = td->Pm;
     double2* aug = td->Aug;
     const int rtl = (r + 15) / 16;
     // step 1: P = A^-1 U
@@ -774,13 +840,13 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
               },
               [&](int k, int c) {
                 const int cc = tj * 16 + c;
-                return (k < K && cc < r) ? Qm[(size_t)ord[cc] * K + k] : cz();
+                return (k < K && cc < r) ? Ub[(size_t)cc * K + k] : cz();
               },
               0, up4(K), dr, di);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = ti * 16 + tile_row(v), c = tj * 16 + tile_col();
-        if (row < K && c < r) Pm[(size_t)c * K + row] = make_float2(dr[v], di[v]);
+        if (row < K && c < r) Pw[(size_t)c * K + row] = make_float2(dr[v], di[v]);
       }
     }
     __syncthreads();
@@ -797,7 +863,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
       if (ct)
         ctile16(la, [&](int k, int c) {
                   const int b = tj * 16 + c;
-                  return (k < K && b < r) ? Pm[(size_t)b * K + k] : cz();
+                  return (k < K && b < r) ? Pw[(size_t)b * K + k] : cz();
                 }, 0, up4(K), dr, di);
       else
         ctile16(la, [&](int k, int c) {
@@ -829,7 +895,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
         floatx4 dr = zero4(), di = zero4();
         ctile16([&](int i, int a) {
                   const int row = ti * 16 + i;
-                  return (row < K && a < r) ? Pm[(size_t)a * K + row] : cz();
+                  return (row < K && a < r) ? Pw[(size_t)a * K + row] : cz();
                 },
                 [&](int a, int c) {
                   const int j = tj * 16 + c;

@@ -38,10 +38,10 @@ struct TrackDesc {
   double* wpart;   // partial ||W||^2 of the precoder blocks
   // working set of the large-track kernels (K > KS), null otherwise; all
   // column-major with leading dimension K
-  float2* Ym;      // K x K: sketch Y, then the Householder vectors
-  float2* Qm;      // K x K: Q, rotated by the Jacobi sweeps
+  float2* Ym;      // K x K: sketch Y, the Householder vectors, Q^H Delta A Z_r, then P = A^-1 U
+  float2* Qm;      // K x K: Q
   float2* Zm;      // K x K: Z = Delta A Q, rotated by the Jacobi sweeps
-  float2* Pm;      // K x K/2: P = A^-1 U
+  float2* Pm;      // K x K/2: Delta A Z_r, then U_r
   double2* Aug;    // (K/2) x (K/2 + K), row-major: [C | V~^H A^-1] in FP64
   // written by the device
   int last_r;
