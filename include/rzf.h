@@ -151,7 +151,11 @@ rzf_status rzf_init(rzf_ctx* ctx, int K, int N, const rzf_c32* H, int ldh, doubl
  *   (eq. (14)); Woodbury update of A^-1 by eq. (12) when k_est <= switch*K,
  *   else direct inversion of A'; then W = H_t^H A'^-1 with ||W||_F^2 = P.
  * tol in (0, 1].  The Woodbury capacitance is factorised in FP64.
- * `info` (host pointer, may be NULL) is filled by the next rzf_sync. */
+ * `info` (host pointer, may be NULL) is filled by the next rzf_sync.
+ * For K <= 64 the iterations of Alg. 1 that the track's previous step
+ * predicts (its iteration count plus one) are computed at once on otherwise
+ * idle CUs before the decision; the results are bit-identical to the same
+ * update through rzf_update_batch, which runs them one after another. */
 rzf_status rzf_update(rzf_track* tr, const rzf_c32* H_t, int ldh, double tol,
                       rzf_c32* W, int ldw, rzf_update_info* info);
 

@@ -29,7 +29,8 @@ namespace {
 size_t scratch_bytes() {
   return align_up(sizeof(int) * 64) + 2 * align_up(sizeof(float2) * KM * KM) +
          align_up(sizeof(double) * ((RZF_NMAX + 15) / 16)) + align_up(sizeof(double) * 8) +
-         align_up(sizeof(double) * sum_rate_scratch_doubles(KM)) + NSTAGE * STAGE_BYTES;
+         align_up(sizeof(double) * sum_rate_scratch_doubles(KM)) + align_up(SPEC_BYTES) +
+         NSTAGE * STAGE_BYTES;
 }
 
 struct Layout {
@@ -154,8 +155,16 @@ void inv64_any(const Inv64Job& j, int* err, hipStream_t s) {
 void inv32_any(const Inv32Job& j, int* err, hipStream_t s) {
   if (j.K > KS) launch_inv32_big(j, nullptr, 1, err, s); else launch_inv32(j, nullptr, 1, err, s);
 }
-void arsvd_any(const ArsvdJob& j, int K, int* err, hipStream_t s) {
-  if (K > KS) launch_arsvd_big(j, nullptr, 1, err, s); else launch_arsvd_wb(j, nullptr, 1, err, s);
+// A single track's step: K <= KS tracks run the two-phase form, whose
+// speculated iterations of Alg. 1 use otherwise idle CUs (same results as
+// the one-launch form); larger tracks run the blocked kernel.
+void arsvd_single(rzf_ctx* c, ArsvdJob j, int K, hipStream_t s) {
+  if (K > KS) {
+    launch_arsvd_big(j, nullptr, 1, c->d_err, s);
+  } else {
+    j.spec = c->d_spec;
+    launch_arsvd_wb_spec(j, c->d_err, s);
+  }
 }
 
 bool params_valid(const rzf_params* p) {
@@ -321,6 +330,7 @@ rzf_status rzf_ctx_create(int device, void* hip_stream, void* arena, size_t aren
   c->d_fullwpart = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * ((RZF_NMAX + 15) / 16));
   c->d_sum = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * 8);
   c->d_srpart = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * sum_rate_scratch_doubles(KM));
+  c->d_spec = reinterpret_cast<float2*>(p); p += align_up(SPEC_BYTES);
   c->d_stage = p;
   c->free_blocks[scr] = arena_bytes - scr;
   if (hipHostMalloc((void**)&c->h_sum, sizeof(double) * 8, hipHostMallocDefault) != hipSuccess ||
@@ -441,7 +451,7 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
     const GramJob gj{Hf, d.Hprev, d.Anew, d.dA, K, N, ldh, N, (float)t->alpha, d.prec};
     const ArsvdJob aj{t->d_desc, nullptr, tol, step, t->i_max};
     timed(c, KN_GRAM, [&] { launch_gram(gj, nullptr, 1, K, s); });
-    timed(c, KN_ARSVD, [&] { arsvd_any(aj, K, c->d_err, s); });
+    timed(c, KN_ARSVD, [&] { arsvd_single(c, aj, K, s); });
   }
   const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw, d.prec};
   const ScaleJob sj{Wf, d.wpart, d.P, K, N, ldw, precoder_blocks(N)};

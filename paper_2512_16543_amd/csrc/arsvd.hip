@@ -280,7 +280,12 @@ __device__ void pick_rank(Shared& sm, int K, int d, double Et, int* r_out, doubl
   __syncthreads();
 }
 
-template <bool MANY>
+// PH = 0: the whole step (single track or batch).  Two-phase single-track
+// form: PH = 1, one workgroup per speculated iteration (blockIdx.x + 1) up to
+// the energy test, its Q, Z and ||Z||_F^2 written to jb.spec; PH = 2, the
+// decision over those iterations in order (continuing one by one if none
+// decides), then the SVD and the branch, exactly as PH = 0 computes them.
+template <bool MANY, int PH>
 __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* many, int* err) {
   __shared__ Shared sm;
   const ArsvdJob& jb = job_of<MANY>(one, many);
@@ -309,6 +314,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   }
   const double E = block_sum(part, sm.red);
   if (!isfinite(E) || E == 0.0) {
+    if (PH == 1) return;                     // the second phase records the step
     if (fb && E == 0.0)                      // nothing to apply: the residual is zero
       for (int e = tid; e < K * K; e += NTH) td->Rfb[e] = cz();
     if (tid == 0) {
@@ -334,13 +340,15 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   int d = 0, iters = 0, r = 0, sweeps = 0, rounds = 0, qrcols = 0;
   double captured = 0.0;
   bool found = false, rotated = false;
-  for (int it = 1; it <= i_max; ++it) {
-    iters = it;
-    d = min(k0 + p, K);
+  // iterations computed ahead in the two-phase form: the last count plus one
+  const int n_spec = PH == 0 ? 0 : min(min(i_max, SPEC_MAX), max(td->spec_hint, 0) + 1);
+  // one iteration of Alg. 1 up to the energy test: Omega, Y, Q (b1), Z (b2),
+  // returning ||Z||_F^2
+  auto sketch_iteration = [&](int itn, int d) -> double {
     // Omega -> b1 (column-major)
     for (int e = tid; e < K * d; e += NTH) {
       const int j = e / K, i = e - j * K;
-      b1[j * LDK + i] = sketch_entry(seed, trk, t, it, i, j);
+      b1[j * LDK + i] = sketch_entry(seed, trk, t, itn, i, j);
     }
     __syncthreads();
     // Y = Delta A Omega -> b2
@@ -387,22 +395,84 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     }
     const double tot = block_sum(zp, sm.red);
     t_qr += clock64() - c_mark; c_mark = clock64();
-    if (tot >= Et) {
-      found = true;
-      jacobi_svd(sm, K, d, &sweeps, &rounds);
-      t_jac += clock64() - c_mark; c_mark = clock64();
-      rotated = true;
-      pick_rank(sm, K, d, Et, &r, &captured, td->sig2);
-      break;
+    return tot;
+  };
+  if constexpr (PH == 1) {
+    const int itn = blockIdx.x + 1;
+    if (itn > n_spec) return;
+    int kk = k0;
+    for (int m = 1; m < itn; ++m) kk = min(2 * kk, K);   // d depends on min(k0 + p, K) only
+    const int dd = min(kk + p, K);
+    const double tot = sketch_iteration(itn, dd);
+    float2* Qw = jb.spec + (size_t)(itn - 1) * 2 * KS * KS;
+    float2* Zw = Qw + KS * KS;
+    for (int e = tid; e < K * dd; e += NTH) {
+      const int j = e / K, i = e - j * K;
+      Qw[j * KS + i] = b1[j * LDK + i];
+      Zw[j * KS + i] = b2[j * LDK + i];
     }
-    // after the last iteration, or (early-fallback policy) once d is past
-    // the Woodbury limit: every component, k_est = d, and the step inverts
-    if (it == i_max || (td->early_fallback && d > td->wb_limit)) {
-      r = d;                 // every component: U_r Sigma_r V_r^H = Q Z^H
-      captured = tot;
-      break;
+    if (tid == 0) reinterpret_cast<double*>(jb.spec + (size_t)2 * KS * KS * SPEC_MAX)[itn - 1] = tot;
+    return;
+  }
+  int it0 = 1;
+  bool decided = false;
+  if constexpr (PH == 2) {
+    const double* totw = reinterpret_cast<const double*>(jb.spec + (size_t)2 * KS * KS * SPEC_MAX);
+    for (int it = 1; it <= n_spec; ++it) {
+      iters = it;
+      d = min(k0 + p, K);
+      qrcols += d;
+      const double tot = totw[it - 1];
+      const bool hit = tot >= Et;
+      if (hit || it == i_max || (td->early_fallback && d > td->wb_limit)) {
+        const float2* Qw = jb.spec + (size_t)(it - 1) * 2 * KS * KS;
+        const float2* Zw = Qw + KS * KS;
+        for (int e = tid; e < K * d; e += NTH) {
+          const int j = e / K, i = e - j * K;
+          b1[j * LDK + i] = Qw[j * KS + i];
+          b2[j * LDK + i] = Zw[j * KS + i];
+        }
+        __syncthreads();
+        c_mark = clock64();
+        if (hit) {
+          found = true;
+          jacobi_svd(sm, K, d, &sweeps, &rounds);
+          t_jac += clock64() - c_mark; c_mark = clock64();
+          rotated = true;
+          pick_rank(sm, K, d, Et, &r, &captured, td->sig2);
+        } else {
+          r = d;
+          captured = tot;
+        }
+        decided = true;
+        break;
+      }
+      k0 = min(2 * k0, K);   // d = min(k0 + p, K) is unchanged by the cap
     }
-    k0 *= 2;
+    it0 = n_spec + 1;
+  }
+  if (!decided) {
+    for (int it = it0; it <= i_max; ++it) {
+      iters = it;
+      d = min(k0 + p, K);
+      const double tot = sketch_iteration(it, d);
+      if (tot >= Et) {
+        found = true;
+        jacobi_svd(sm, K, d, &sweeps, &rounds);
+        t_jac += clock64() - c_mark; c_mark = clock64();
+        rotated = true;
+        pick_rank(sm, K, d, Et, &r, &captured, td->sig2);
+        break;
+      }
+      // after the last iteration, or (early-fallback policy) once d is past
+      // the Woodbury limit: every component, k_est = d, and the step inverts
+      if (it == i_max || (td->early_fallback && d > td->wb_limit)) {
+        r = d;                 // every component: U_r Sigma_r V_r^H = Q Z^H
+        captured = tot;
+        break;
+      }
+      k0 = min(2 * k0, K);   // d = min(k0 + p, K) is unchanged by the cap
+    }
   }
   if (!rotated) {
     if (tid < d) sm.order[tid] = tid;
@@ -592,6 +662,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     td->info.dA_fro2 = E; td->info.captured = captured;
     if (jb.out) *jb.out = td->info;
     td->last_r = r;
+    td->spec_hint = iters;
     td->dbg[0] = sweeps; td->dbg[1] = rounds; td->dbg[2] = qrcols;
     td->nsig = rotated ? d : 0;
     t_wb = clock64() - c_mark;
@@ -619,8 +690,13 @@ __global__ void k_debug_sketch(uint64_t seed, uint64_t track, int t, int it, int
 }  // namespace
 
 void launch_arsvd_wb(const ArsvdJob& one, const ArsvdJob* many, int n, int* err, hipStream_t s) {
-  if (many) k_arsvd_wb<true><<<dim3(1, n), NTH, 0, s>>>(one, many, err);
-  else k_arsvd_wb<false><<<1, NTH, 0, s>>>(one, many, err);
+  if (many) k_arsvd_wb<true, 0><<<dim3(1, n), NTH, 0, s>>>(one, many, err);
+  else k_arsvd_wb<false, 0><<<1, NTH, 0, s>>>(one, many, err);
+}
+
+void launch_arsvd_wb_spec(const ArsvdJob& one, int* err, hipStream_t s) {
+  k_arsvd_wb<false, 1><<<SPEC_MAX, NTH, 0, s>>>(one, nullptr, err);
+  k_arsvd_wb<false, 2><<<1, NTH, 0, s>>>(one, nullptr, err);
 }
 
 void launch_debug_sketch(uint64_t seed, uint64_t track, int t, int it, int K, int d, float2* Omega,

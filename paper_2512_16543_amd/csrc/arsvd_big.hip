@@ -717,7 +717,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
       captured = tot;
       break;
     }
-    k0 *= 2;
+    k0 = min(2 * k0, K);   // d = min(k0 + p, K) is unchanged by the cap
   }
   if (!rotated) {
     if (tid < d) sm.order[tid] = tid;

@@ -50,6 +50,7 @@ struct rzf_ctx {
   double* d_fullwpart = nullptr;
   double* d_sum = nullptr;
   double* d_srpart = nullptr;
+  float2* d_spec = nullptr;             // speculated iterations of a single-track arSVD step
   // pinned host staging
   double* h_sum = nullptr;
   int* h_err = nullptr;

@@ -45,7 +45,7 @@ struct TrackDesc {
   double2* Aug;    // (K/2) x (K/2 + K), row-major: [C | V~^H A^-1] in FP64
   // written by the device
   int last_r;
-  int pad_;
+  int spec_hint;   // Alg. 1 iterations of the last step that ran it (speculation depth)
   DevInfo info;
   int dbg[8];      // last update: [0] Jacobi sweeps, [1] Jacobi rounds, [2] QR columns
   int nsig;        // number of sigma^2 below (d of the last SVD, 0 if none)
@@ -82,7 +82,13 @@ struct ArsvdJob {
   DevInfo* out;    // extra copy of the step's info (batched calls), or null
   double eta;
   int t, i_max;
+  float2* spec;    // speculative-iteration workspace (SPEC_BYTES), two-phase single-track form only
 };
+// Two-phase single-track form of the K <= KS arSVD kernel: up to SPEC_MAX
+// iterations of Alg. 1 are computed at once, one workgroup each, into
+// [SPEC_MAX][Q, Z][KS x KS] complex values followed by SPEC_MAX doubles.
+#define SPEC_MAX 8
+#define SPEC_BYTES (sizeof(float2) * 2 * KS * KS * SPEC_MAX + sizeof(double) * SPEC_MAX)
 struct PrecJob {
   const float2* H; const float2* X; float2* W; double* wpart; float2* Hcopy;
   int K, N, ldh, ldw;
@@ -115,6 +121,10 @@ int precoder_blocks(int N);
 void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, hipStream_t s);
 void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, hipStream_t s);
 void launch_arsvd_wb(const ArsvdJob& one, const ArsvdJob* many, int n, int* err, hipStream_t s);
+// The same step for one track in two launches (one.spec set): the iterations
+// of Alg. 1 that the previous step's count predicts, in parallel, then the
+// decision, the SVD and the branch of Alg. 2.  Bit-identical results.
+void launch_arsvd_wb_spec(const ArsvdJob& one, int* err, hipStream_t s);
 // Large tracks (KS < K <= KM): one workgroup per track, working set in the
 // track's global workspace.
 void launch_arsvd_big(const ArsvdJob& one, const ArsvdJob* many, int n, int* err, hipStream_t s);
