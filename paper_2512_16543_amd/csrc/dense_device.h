@@ -163,6 +163,88 @@ __device__ T* gj_inverse_hpd(T* a, T* b, int K, int ld, int* bad) {
   return a;
 }
 
+// Lane moves of one complex value (FP32 or FP64 parts).
+__device__ __forceinline__ float2 lane_read(float2 v, int l) {
+  return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), l)),
+                     __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), l)));
+}
+__device__ __forceinline__ double2 lane_read(double2 v, int l) {
+  return make_double2(readlane_d(v.x, l), readlane_d(v.y, l));
+}
+__device__ __forceinline__ float2 lane_shfl(float2 v, int src) {
+  return make_float2(__shfl(v.x, src), __shfl(v.y, src));
+}
+__device__ __forceinline__ double2 lane_shfl(double2 v, int src) {
+  return make_double2(__shfl(v.x, src), __shfl(v.y, src));
+}
+// value of quad lane k (0..3) to every lane of its quad
+template <int K4>
+__device__ __forceinline__ float2 quad_bcast(float2 v) {
+  constexpr int c = K4 | (K4 << 2) | (K4 << 4) | (K4 << 6);
+  return make_float2(dpp_f<c>(v.x), dpp_f<c>(v.y));
+}
+template <int K4>
+__device__ __forceinline__ double2 quad_bcast(double2 v) {
+  constexpr int c = K4 | (K4 << 2) | (K4 << 4) | (K4 << 6);
+  return make_double2(dpp_d<c>(v.x), dpp_d<c>(v.y));
+}
+template <class T>
+__device__ __forceinline__ T quad_bcast_any(T v, int k) {
+  switch (k) {
+    case 0: return quad_bcast<0>(v);
+    case 1: return quad_bcast<1>(v);
+    case 2: return quad_bcast<2>(v);
+    default: return quad_bcast<3>(v);
+  }
+}
+
+// 16 x 16 pivot-block inverse by scalar exchange steps in one wavefront,
+// held in registers: lane l keeps row r = l / 4, columns 4 (l % 4) .. +3 (so
+// a row is one quad).  Step q reads the pivot from its lane, x[r][q] from the
+// quad and the pivot row x[q][:] by a lane permute.  ld(r, c) loads the
+// block; the inverse is left in pb[0..255] (row-major).
+template <class T, class LD>
+__device__ __forceinline__ void pivot_inverse16(const LD& ld, T* pb, int* bad) {
+  typedef CX<T> C;
+  const int lane = threadIdx.x & 63;
+  const int r = lane >> 2, c0 = (lane & 3) * 4;
+  T x[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) x[u] = ld(r, c0 + u);
+  bool ok = true, fin = true;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int qu = q & 3;
+    const T piv = lane_read(x[qu], 4 * q + (q >> 2));
+    fin = fin && C::finite(piv);
+    ok = ok && C::re(piv) > 0.0;
+    const T ip = C::inv(piv);
+    const T xrq = quad_bcast_any(x[qu], q >> 2);          // x[r][q]
+    T xq[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xq[u] = lane_shfl(x[u], 4 * q + (lane & 3));   // x[q][c0 + u]
+    const T f = C::mul(xrq, ip);
+    const T nf = C::neg(f);
+    const bool rq = r == q;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool cq = c0 + u == q;
+      const T row = C::mul(xq[u], ip);               // pivot row
+      const T rest = C::sub(x[u], C::mul(f, xq[u]));
+      const T a = rq ? ip : nf;                      // pivot column
+      const T b = rq ? row : rest;
+      x[u] = cq ? a : b;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) pb[r * 16 + c0 + u] = x[u];
+  wave_sync();
+  if (lane == 0) {
+    if (!fin) *bad = 2;
+    else if (!ok && *bad == 0) *bad = 1;
+  }
+}
+
 // Inverse of a Hermitian positive definite K x K matrix (K <= 64) by
 // Gauss-Jordan exchange steps on 16 x 16 pivot blocks, with the block
 // products on the FP32 matrix cores.  With P the pivot block and R the rest,
@@ -187,43 +269,7 @@ __device__ void gj_inverse_hpd_mfma(float2* a, int K, int ld, float2* xs, float2
   __syncthreads();
   for (int s = 0; s < nb; ++s) {
     const int p0 = 16 * s;
-    if (wid == 0) {
-      // P^-1 by 16 scalar exchange steps; lane owns row r, columns c0..c0+3
-      const int r = lane >> 2, c0 = (lane & 3) * 4;
-      float2* x0 = pb;
-      float2* x1 = pb + 256;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) x0[r * 16 + c0 + u] = a[(p0 + r) * ld + p0 + c0 + u];
-      bool ok = true, fin = true;
-      for (int q = 0; q < 16; ++q) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const float2 piv = x0[q * 16 + q];
-        fin = fin && isfinite(piv.x) && isfinite(piv.y);
-        ok = ok && piv.x > 0.f;
-        const float dn = __builtin_amdgcn_rcpf(piv.x * piv.x + piv.y * piv.y);
-        const float2 ip = make_float2(piv.x * dn, -piv.y * dn);
-        const float2 xrq = x0[r * 16 + q];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int c = c0 + u;
-          const float2 xqc = x0[q * 16 + c];
-          float2 v;
-          if (r == q && c == q) v = ip;
-          else if (r == q) v = cmul(xqc, ip);
-          else if (c == q) v = make_float2(-(xrq.x * ip.x - xrq.y * ip.y), -(xrq.x * ip.y + xrq.y * ip.x));
-          else v = csub(x0[r * 16 + c], cmul(cmul(xrq, ip), xqc));
-          x1[r * 16 + c] = v;
-        }
-        float2* t = x0; x0 = x1; x1 = t;
-      }
-      if (lane == 0) {
-        if (!fin) *bad = 2;
-        else if (!ok && *bad == 0) *bad = 1;
-      }
-      // after 16 (even) steps the result is back in pb[0..255]
-    }
+    if (wid == 0) pivot_inverse16<float2>([&](int r, int c) { return a[(p0 + r) * ld + p0 + c]; }, pb, bad);
     __syncthreads();
     const float2* pinv = pb;
     // X = P^-1 a_P,:  (16 x KP, waves 0..nb-1) and Y = a_:,P P^-1 (KP x 16, waves 8..8+nb-1)
@@ -305,46 +351,6 @@ __device__ __forceinline__ void tile16_any(const LA& la, const LB& lb, int k0, i
     for (int v = 0; v < 4; ++v) acc[v] = dz();
     dtile16(la, lb, k0, k1, acc);
   }
-}
-
-// 16 x 16 pivot-block inverse by scalar exchange steps in one wavefront.
-// ld(r, c) loads the block; the inverse is left in pb[0..255] (row-major).
-template <class T, class LD>
-__device__ __forceinline__ void pivot_inverse16(const LD& ld, T* pb, int* bad) {
-  typedef CX<T> C;
-  const int lane = threadIdx.x & 63;
-  const int r = lane >> 2, c0 = (lane & 3) * 4;
-  T* x0 = pb;
-  T* x1 = pb + 256;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) x0[r * 16 + c0 + u] = ld(r, c0 + u);
-  bool ok = true, fin = true;
-  for (int q = 0; q < 16; ++q) {
-    wave_sync();
-    const T piv = x0[q * 16 + q];
-    fin = fin && C::finite(piv);
-    ok = ok && C::re(piv) > 0.0;
-    const T ip = C::inv(piv);
-    const T xrq = x0[r * 16 + q];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = c0 + u;
-      const T xqc = x0[q * 16 + c];
-      T v;
-      if (r == q && c == q) v = ip;
-      else if (r == q) v = C::mul(xqc, ip);
-      else if (c == q) v = C::neg(C::mul(xrq, ip));
-      else v = C::sub(x0[r * 16 + c], C::mul(C::mul(xrq, ip), xqc));
-      x1[r * 16 + c] = v;
-    }
-    T* t = x0; x0 = x1; x1 = t;
-  }
-  wave_sync();
-  if (lane == 0) {
-    if (!fin) *bad = 2;
-    else if (!ok && *bad == 0) *bad = 1;
-  }
-  // 16 steps (even): the result is back in pb[0..255]
 }
 
 template <class T>
