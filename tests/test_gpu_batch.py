@@ -147,3 +147,49 @@ def test_batch_rejects_bad_items(ctx):
     other.close()
     for tr in trs:
         tr.destroy()
+
+
+# (params, per-step tol): the single-track call speculates the iterations of
+# Alg. 1 that the previous step's count predicts, the batched call runs them
+# one by one; changing tol makes the prediction too short and too long, tol =
+# 1 can end at I_max, and I_max = 12 with k_init = 1, p = 0 goes past the eight
+# speculated iterations
+SPEC_CASES = [
+    (dict(), [0.999, 0.9, 0.5, 0.999, 0.9999, 0.65]),
+    (dict(early_fallback=1), [0.999, 0.9, 0.999, 0.5]),
+    (dict(error_feedback=1), [0.9, 0.8, 0.999, 0.9]),
+    (dict(kinit_policy=rzf.KINIT_WARM), [0.9, 0.999, 0.65, 0.9]),
+    (dict(i_max=2), [0.999, 0.9, 0.999]),
+    (dict(k_init=1, p=0, i_max=12), [1.0, 0.999, 1.0, 0.9]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SPEC_CASES)))
+def test_speculated_single_equals_batched(ctx, case):
+    prm_kw, tols = SPEC_CASES[case]
+    cfg = wl.CONFIGS["c2"]
+    Hs = wl.make_track(cfg, 3).snapshots(0, len(tols) + 1).astype(np.complex64)
+    Hr = walk(40, 96, len(tols), 90 + case)
+    dev = [torch.from_numpy(Hs).cuda(), torch.from_numpy(Hr).cuda()]
+
+    def make():
+        return [ctx.init(d[0], a, rzf.default_params(seed=5, track_id=i, **prm_kw))
+                for i, (d, a) in enumerate(zip(dev, (cfg.alpha, 1.1)))]
+
+    alone, batch = make(), make()
+    Wa = [torch.empty(d.shape[2], d.shape[1], dtype=torch.complex64, device="cuda") for d in dev]
+    Wb = [torch.empty_like(w) for w in Wa]
+    seen = set()
+    for t, tol in enumerate(tols, start=1):
+        ia = [tr.update(d[t], tol, w) for tr, d, w in zip(alone, dev, Wa)]
+        ib = ctx.update_batch(batch, [d[t] for d in dev], Wb, tol, want_info=True)
+        ctx.sync()
+        for i in range(2):
+            a, b = ia[i], ib[i]
+            assert (a.r, a.iters, a.path, a.d, a.captured) == (b.r, b.iters, b.path, b.d, b.captured), (t, i)
+            assert torch.equal(Wa[i], Wb[i]), (t, i)
+            assert torch.equal(alone[i].inverse(), batch[i].inverse()), (t, i)
+            seen.add(a.iters)
+    assert len(seen) > 1, seen    # the iteration count changed along the way
+    for tr in alone + batch:
+        tr.destroy()
