@@ -399,7 +399,8 @@ def batched(a, cfgs, eta, policy):
         fl = sum(8.0 * c.K * c.K * c.N for c in cfgs)
     else:
         fl = 0.0
-    res["roofline"] = {"kernel": dom, "bound": "mfma", "achieved": fl / dur / 1e12,
+    res["roofline"] = {"kernel": dom, "bound": "alu" if dom == "arsvd_wb" else "mfma",
+                       "achieved": fl / dur / 1e12,
                        "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": fl / dur / 1e12 / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
                        "flops_per_launch": fl, "avg_launch_us": dur * 1e6,
