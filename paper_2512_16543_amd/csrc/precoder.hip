@@ -6,9 +6,10 @@
 //
 // W is N x K (row-major).  A workgroup of four wavefronts owns 16 rows of W
 // (16 antennas); wave w computes the 16x16 tiles w, w+4, ... along K with a
-// length-K reduction on the FP32 matrix cores.  The block also writes its
-// partial sum of |W|^2 (FP64) and, for rzf_update, copies the 16 columns of
-// H_t it has read into the track's H_prev.  A second kernel scales W once
+// length-K reduction on the FP32 matrix cores.  The FP32 path reads the
+// block's 16 columns of H_t into LDS once (all of its tiles share them).  The
+// block also writes its partial sum of |W|^2 (FP64) and, for rzf_update,
+// copies the 16 columns of H_t it has read into the track's H_prev.  A second kernel scales W once
 // every partial sum is known (partials are added in a fixed order).
 #include "rzf_device.h"
 #include "rzf_internal.h"
@@ -18,6 +19,7 @@ namespace {
 template <bool MANY>
 __global__ __launch_bounds__(256) void k_precoder(PrecJob one, const PrecJob* many) {
   __shared__ double red[4];
+  __shared__ float2 hs[KM * 16];   // FP32 path: H[i][n0 + c] at hs[16 i + c]
   const PrecJob& jb = job_of<MANY>(one, many);
   const int K = jb.K, N = jb.N, ldh = jb.ldh, ldw = jb.ldw;
   const float2* __restrict__ H = jb.H;
@@ -29,20 +31,27 @@ __global__ __launch_bounds__(256) void k_precoder(PrecJob one, const PrecJob* ma
   const int n0 = blockIdx.x * 16;
   if (n0 >= N) return;
   double acc = 0.0;
+  const bool fp32 = jb.prec == RZF_PREC_FP32;
+  if (fp32) {
+    // the block's 16 columns of H, read once (and copied to H_prev here)
+    for (int e = threadIdx.x; e < K * 16; e += blockDim.x) {
+      const int i = e >> 4, n = n0 + (e & 15);
+      const float2 v = n < N ? H[(size_t)i * ldh + n] : cz();
+      hs[e] = v;
+      if (Hcopy && n < N) Hcopy[(size_t)i * N + n] = v;
+    }
+    __syncthreads();
+  }
   for (int kt = wid; kt * 16 < K; kt += 4) {
     const int k0 = kt * 16;
     floatx4 dr = zero4(), di = zero4();
-    if (jb.prec == RZF_PREC_FP32) {
-      // A(n, i) = conj(H[i][n]);  B(i, k) = X[i][k]
-      auto la = [&](int rr, int i) -> float2 {
-        const int n = n0 + rr;
-        return (n < N && i < K) ? cconj(H[(size_t)i * ldh + n]) : cz();
-      };
-      auto lb = [&](int i, int c) -> float2 {
-        const int k = k0 + c;
-        return (i < K && k < K) ? X[(size_t)i * K + k] : cz();
-      };
-      ctile16(la, lb, 0, K, dr, di);
+    if (fp32) {
+      // A(n, i) = conj(H[i][n]) from LDS;  B(i, k) = X[i][k]
+      const int col = k0 + (lane & 15);
+      const bool okc = col < K;
+      const float2* xc = X + col;
+      ctile16([&](int rr, int i) { return i < K ? cconj(hs[i * 16 + rr]) : cz(); },
+              [&](int i, int) { return (i < K && okc) ? xc[(size_t)i * K] : cz(); }, 0, K, dr, di);
     } else {
       // BF16 operands, 32 users of the reduction per product
       const bool x3 = jb.prec == RZF_PREC_BF16X3;
@@ -70,7 +79,7 @@ __global__ __launch_bounds__(256) void k_precoder(PrecJob one, const PrecJob* ma
   }
   acc = wave_sum(acc);
   if (lane == 0) red[wid] = acc;
-  if (Hcopy) {
+  if (Hcopy && !fp32) {
     // the 16 columns n0..n0+15 of every row of H_t
     for (int e = threadIdx.x; e < K * 16; e += blockDim.x) {
       const int i = e >> 4, n = n0 + (e & 15);
