@@ -51,15 +51,18 @@ __device__ __forceinline__ float2 d2f(double2 a) { return make_float2((float)a.x
 #define DPP_ROW_ROR4 0x124
 #define DPP_ROW_ROR8 0x128
 
+// Lanes whose DPP source is out of range read zero (bound_ctrl), so no
+// "old" value has to be set up first; the permutations used here (quad
+// permutes, row rotates, the half-row mirror) have no such lanes anyway.
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 // Sum over the 16 lanes of each row; every lane of the row gets the row sum.
