@@ -135,92 +135,140 @@ __device__ __forceinline__ void lds_gemm(int M, int Nc, int Kd, const LA& la, co
   }
 }
 
-// One-sided Jacobi on the d columns of Z (b2).
-// Each 16-lane row of a wave owns one column pair per round (4 rows of the
-// matrix per lane), so a round of the round-robin ordering is one barrier.
-// ||z_p||^2 and ||z_q||^2 are sums of non-negative FP32 terms.  The inner
-// product z_p^H z_q cancels as the columns become orthogonal: each lane
-// forms its 4-row share in FP32 (error about 2^-24 ||z_p|| ||z_q||, a few
-// percent of the rotation threshold 2e-6 ||z_p|| ||z_q||) and the 16 shares
-// are added in FP64.
+// One-sided Jacobi on the d columns of Z (b2), in blocks of 4 columns that
+// wavefronts hold in registers.  A 16-lane row of a wave (row group g) owns
+// one column of a pair at a time, 4 rows of the matrix per lane.
+// A pass (sweep) over all column pairs:
+//   * own pairs: wave w takes blocks 2w and 2w+1 and rotates the 6 pairs
+//     inside each block (3 rounds; the columns move through the wave's own
+//     LDS columns, no workgroup barrier);
+//   * cross pairs: nb - 1 super-rounds pair the blocks round-robin; wave w
+//     loads its blocks A and B, row group g keeps column g of A and meets
+//     the 4 columns of B in turn, which move one row group up after every
+//     round by a lane permute; then both blocks go back to LDS (one barrier
+//     per super-round).
+// Pairs rotate when |z_p^H z_q| > JACOBI_TOL ||z_p|| ||z_q||; passes stop
+// when one rotates nothing.  Columns d .. 4 nb - 1 are zero and never rotate.
+__device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], bool act, bool& rotated) {
+  float al = 0.f, be = 0.f, grf32 = 0.f, gif32 = 0.f;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    al += cabs2(zp[m]);
+    be += cabs2(zq[m]);
+    grf32 = fmaf(zp[m].x, zq[m].x, fmaf(zp[m].y, zq[m].y, grf32));
+    gif32 = fmaf(zp[m].x, zq[m].y, fmaf(-zp[m].y, zq[m].x, gif32));
+  }
+  al = row16_sum(al);
+  be = row16_sum(be);
+  const double gr = row16_sum((double)grf32);
+  const double gi = row16_sum((double)gif32);
+  const float mx = fmaxf(al, be);
+  bool rot = act && mx > 0.f;
+  float c = 1.f, s = 0.f;
+  float2 e = make_float2(1.f, 0.f);
+  if (rot) {
+    // rotation parameters with hardware rsq/rcp on sums scaled by
+    // 1/max(alpha, beta) so nothing underflows; a pair whose scaled
+    // |gamma|^2 is below the FP32 normal range is already orthogonal to
+    // working precision
+    const float sc = __builtin_amdgcn_rcpf(mx);
+    const float alf = al * sc, bef = be * sc;
+    const float grf = (float)gr * sc, gif = (float)gi * sc;
+    const float gg = grf * grf + gif * gif;
+    rot = gg >= 1e-36f && gg > (float)(JACOBI_TOL * JACOBI_TOL) * alf * bef;
+    const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));   // 1/|gamma|
+    const float zeta = (bef - alf) * 0.5f * ig;
+    const float az = fabsf(zeta);
+    const float tmag = (az > 1e18f) ? 0.5f * __builtin_amdgcn_rcpf(az)
+                                    : __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(1.f + az * az));
+    const float tt = zeta >= 0.f ? tmag : -tmag;
+    c = __builtin_amdgcn_rsqf(1.f + tt * tt);
+    s = c * tt;
+    e = make_float2(grf * ig, -gif * ig);   // conj(gamma)/|gamma|
+  }
+  if (rot) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const float2 zq2 = cmul(e, zq[m]);
+      const float2 np = csub(cscale(zp[m], c), cscale(zq2, s));
+      zq[m] = cadd(cscale(zp[m], s), cscale(zq2, c));
+      zp[m] = np;
+    }
+    rotated = true;
+  }
+}
+
 __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* rounds_out) {
   float2* b2 = sm.b2;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int li = lane & 15, slot = wid * 4 + (lane >> 4);
-  const int n = d + (d & 1);
+  const int li = lane & 15, g = lane >> 4;
+  const int nb = ((d + 3) / 4 + 1) & ~1;   // blocks of 4 columns, an even number (<= 16)
+  const int nw = nb / 2;                   // waves holding a block pair
+  for (int e = threadIdx.x; e < (4 * nb - d) * LDK; e += NTH) b2[d * LDK + e] = cz();
   int sweeps = 0, rounds = 0;
   for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
     if (threadIdx.x == 0) sm.nrot = 0;
     __syncthreads();
     ++sweeps;
-    for (int k = 0; k < n - 1; ++k) {
-      ++rounds;
-      if (wid * 4 < n / 2) {          // waves without a pair only take the barrier
-        int pp = 0, qq = 0;
-        bool act = slot < n / 2;
-        if (act) {
-          rr_pair(k, slot, n, &pp, &qq);
-          act = pp < d && qq < d;
-        }
-        if (!act) pp = qq = 0;        // an idle group reads column 0 and never stores
-        // rows K..KS-1 of Z and Q are zero (they stay zero under rotation), so
-        // every lane takes its four rows without a bound check
-        float2* zpc = b2 + pp * LDK + li;
-        float2* zqc = b2 + qq * LDK + li;
+    bool rotated = false;
+    // own pairs of blocks 2w (row groups 0, 1) and 2w + 1 (row groups 2, 3)
+    if (wid < nw) {
+      const int c0 = 4 * (2 * wid + (g >> 1)), m = g & 1;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        int p, q;
+        rr_pair(t, m, 4, &p, &q);
+        float2* zpc = b2 + (c0 + p) * LDK + li;
+        float2* zqc = b2 + (c0 + q) * LDK + li;
         float2 zp[4], zq[4];
-        float al = 0.f, be = 0.f, grf32 = 0.f, gif32 = 0.f;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          zp[m] = zpc[16 * m];
-          zq[m] = zqc[16 * m];
+        for (int mm = 0; mm < 4; ++mm) {
+          zp[mm] = zpc[16 * mm];
+          zq[mm] = zqc[16 * mm];
+        }
+        jacobi_rotate(zp, zq, true, rotated);
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm) {
+          zpc[16 * mm] = zp[mm];
+          zqc[16 * mm] = zq[mm];
+        }
+        wave_sync();
+      }
+    }
+    rounds += 3;
+    __syncthreads();
+    // cross pairs, one super-round per round-robin pairing of the blocks
+    for (int sr = 0; sr < nb - 1; ++sr) {
+      if (wid < nw) {
+        int A, B;
+        rr_pair(sr, wid, nb, &A, &B);
+        float2* zac = b2 + (4 * A + g) * LDK + li;
+        float2* zbc = b2 + (4 * B + g) * LDK + li;
+        float2 za[4], zb[4];
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm) {
+          za[mm] = zac[16 * mm];
+          zb[mm] = zbc[16 * mm];
+        }
+        const int up = (lane + 16) & 63;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          jacobi_rotate(za, zb, true, rotated);   // column 4A + g with column 4B + (g + t) % 4
+#pragma unroll
+          for (int mm = 0; mm < 4; ++mm)
+            zb[mm] = make_float2(__shfl(zb[mm].x, up), __shfl(zb[mm].y, up));
         }
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          al += cabs2(zp[m]);
-          be += cabs2(zq[m]);
-          grf32 = fmaf(zp[m].x, zq[m].x, fmaf(zp[m].y, zq[m].y, grf32));
-          gif32 = fmaf(zp[m].x, zq[m].y, fmaf(-zp[m].y, zq[m].x, gif32));
-        }
-        al = row16_sum(al);
-        be = row16_sum(be);
-        const double gr = row16_sum((double)grf32);
-        const double gi = row16_sum((double)gif32);
-        const float mx = fmaxf(al, be);
-        bool rot = act && mx > 0.f;
-        float c = 1.f, s = 0.f;
-        float2 e = make_float2(1.f, 0.f);
-        if (rot) {
-          // rotation parameters with hardware rsq/rcp on sums scaled by
-          // 1/max(alpha, beta) so nothing underflows; a pair whose scaled
-          // |gamma|^2 is below the FP32 normal range is already orthogonal to
-          // working precision
-          const float sc = __builtin_amdgcn_rcpf(mx);
-          const float alf = al * sc, bef = be * sc;
-          const float grf = (float)gr * sc, gif = (float)gi * sc;
-          const float gg = grf * grf + gif * gif;
-          rot = gg >= 1e-36f && gg > (float)(JACOBI_TOL * JACOBI_TOL) * alf * bef;
-          const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));   // 1/|gamma|
-          const float zeta = (bef - alf) * 0.5f * ig;
-          const float az = fabsf(zeta);
-          const float tmag = (az > 1e18f) ? 0.5f * __builtin_amdgcn_rcpf(az)
-                                          : __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(1.f + az * az));
-          const float tt = zeta >= 0.f ? tmag : -tmag;
-          c = __builtin_amdgcn_rsqf(1.f + tt * tt);
-          s = c * tt;
-          e = make_float2(grf * ig, -gif * ig);   // conj(gamma)/|gamma|
-        }
-        if (rot) {
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const float2 zq2 = cmul(e, zq[m]);
-            zpc[16 * m] = csub(cscale(zp[m], c), cscale(zq2, s));
-            zqc[16 * m] = cadd(cscale(zp[m], s), cscale(zq2, c));
-          }
-          if (li == 0) sm.nrot = 1;
+        for (int mm = 0; mm < 4; ++mm) {
+          zac[16 * mm] = za[mm];
+          zbc[16 * mm] = zb[mm];
         }
       }
+      rounds += 4;
       __syncthreads();
     }
+    if (rotated && li == 0) sm.nrot = 1;
+    __syncthreads();
     const bool done = (sm.nrot == 0);
     __syncthreads();
     if (done) break;
