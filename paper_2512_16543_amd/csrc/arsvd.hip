@@ -23,8 +23,12 @@
 //   the Woodbury branch), so U_r Sigma_r V_r^H = sum_{j<=r} u_j z_j^H.
 //   After I_max failing iterations r = d and U_r Sigma_r V_r^H = Q Z^H.
 //
+// Single-track updates run the kernel in two launches (PH = 1, 2 below): the
+// iterations the previous step predicts are computed at once, one workgroup
+// each, and the second launch takes the first that decides.
+//
 // Woodbury (Sec. III-A, steps 1-5) in the equivalent scaled form with
-// U = [q_j], V~ = [z_j] (V~ = V_r Sigma_r):
+// U = [u_j] (orthonormal), V~ = [z_j] (V~ = V_r Sigma_r):
 //   P  = A^-1 U                (step 1)
 //   C  = I_r + V~^H P          (step 2; Sigma_r (Sigma_r^-1 + V_r^H A^-1 U_r))
 //   X  = C^-1 (V~^H A^-1)      (step 3, FP64 Gauss-Jordan with partial pivoting)
@@ -93,25 +97,6 @@ __device__ void reflector_from(float2 x, float2* a, int c, int K) {
     }
   }
   if (lane < K) a[c * LDK + lane] = (lane >= c) ? w : cz();
-}
-
-// y <- (I - 2 w w^H) y for column c of `a` and reflector column wc of `wsrc`.
-// Rows K..KS-1 of both are zero and stay zero, so all 64 lanes take part.
-// Returns the updated column value of the calling lane.
-__device__ __forceinline__ float2 apply_reflector(const float2* wsrc, int wc, float2* a, int c, int K) {
-  const int lane = threadIdx.x & 63;
-  (void)K;
-  const float2 w = wsrc[wc * LDK + lane];
-  float2 y = a[c * LDK + lane];
-  float dr = w.x * y.x + w.y * y.y;     // conj(w) y
-  float di = w.x * y.y - w.y * y.x;
-  dr = wave_sumf(dr);
-  di = wave_sumf(di);
-  const float fr = 2.f * dr, fi = 2.f * di;
-  y.x -= w.x * fr - w.y * fi;
-  y.y -= w.x * fi + w.y * fr;
-  a[c * LDK + lane] = y;
-  return y;
 }
 
 // Tiled complex product over LDS on the matrix cores.  Output M x Nc in
@@ -409,23 +394,65 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     // Householder QR of Y (b2): reflector j lands in column j of b2.  Wave 0
     // updates column j+1 and immediately forms its reflector (one barrier per
     // column); the other waves update the remaining columns.
+    // Each wave updates its (at most 4) columns c with H_j = I - 2 w w^H,
+    // y <- y - 2 w (w^H y), all of them together so that their reductions
+    // overlap.  Rows K..KS-1 of w and y are zero and stay zero.
     if (wid == 0) reflector_from((lane < K) ? b2[lane] : cz(), b2, 0, K);
     for (int j = 0; j < d; ++j) {
       __syncthreads();
-      for (int c = j + 1 + wid; c < d; c += NWV) {
-        const float2 y = apply_reflector(b2, j, b2, c, K);
-        if (c == j + 1) reflector_from(y, b2, c, K);
+      const float2 w = b2[j * LDK + lane];
+      float2 y[KS / NWV];
+      float dr[KS / NWV], di[KS / NWV];
+#pragma unroll
+      for (int q = 0; q < KS / NWV; ++q) {
+        const int c = j + 1 + wid + NWV * q;
+        y[q] = c < d ? b2[c * LDK + lane] : cz();
+        dr[q] = w.x * y[q].x + w.y * y[q].y;     // conj(w) y
+        di[q] = w.x * y[q].y - w.y * y[q].x;
       }
+#pragma unroll
+      for (int q = 0; q < KS / NWV; ++q) {
+        const int c = j + 1 + wid + NWV * q;
+        if (c >= d) break;
+        const float fr = 2.f * wave_sumf(dr[q]), fi = 2.f * wave_sumf(di[q]);
+        y[q].x -= w.x * fr - w.y * fi;
+        y[q].y -= w.x * fi + w.y * fr;
+        b2[c * LDK + lane] = y[q];
+      }
+      if (wid == 0 && j + 1 < d) reflector_from(y[0], b2, j + 1, K);
     }
     qrcols += d;
-    // Q = H_0 ... H_{d-1} [I_d; 0] -> b1
-    for (int e = tid; e < d * LDK; e += NTH) {
-      const int j = e / LDK, i = e - j * LDK;
-      b1[e] = (i == j) ? make_float2(1.f, 0.f) : cz();
-    }
-    for (int j = d - 1; j >= 0; --j) {
-      __syncthreads();
-      for (int c = j + wid; c < d; c += NWV) apply_reflector(b2, j, b1, c, K);
+    // Q = H_0 ... H_{d-1} [I_d; 0] -> b1.  Column c is H_0 ... H_c e_c (H_j
+    // leaves e_c alone for j > c: w_j is zero above row j), so every wave
+    // forms its own columns c = wid, wid + 16, ... with no barrier, the
+    // reflectors applied in the same order as to the whole of Q.
+    {
+      float2 y[KS / NWV];
+      int cmax = -1;
+#pragma unroll
+      for (int q = 0; q < KS / NWV; ++q) {
+        const int c = wid + NWV * q;
+        y[q] = (lane == c) ? make_float2(1.f, 0.f) : cz();
+        if (c < d) cmax = c;
+      }
+      for (int j = cmax; j >= 0; --j) {
+        const float2 w = b2[j * LDK + lane];
+#pragma unroll
+        for (int q = 0; q < KS / NWV; ++q) {
+          const int c = wid + NWV * q;
+          if (c >= d || c < j) continue;          // no column, or H_j leaves it alone
+          float dr = w.x * y[q].x + w.y * y[q].y;  // conj(w) y
+          float di = w.x * y[q].y - w.y * y[q].x;
+          dr = wave_sumf(dr);
+          di = wave_sumf(di);
+          const float fr = 2.f * dr, fi = 2.f * di;
+          y[q].x -= w.x * fr - w.y * fi;
+          y[q].y -= w.x * fi + w.y * fr;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < KS / NWV; ++q)
+        if (wid + NWV * q < d) b1[(wid + NWV * q) * LDK + lane] = y[q];
     }
     __syncthreads();
     // Z = Delta A^H Q = B^H -> b2 (Delta A is Hermitian unless error feedback
