@@ -58,12 +58,14 @@ struct Shared {
   float2 pm[WB_RMAX * LDK];      // U (after the SVD), column-major
   float2 tm[WB_RMAX * LDK];      // Q^H Delta A Z_r, then P = A^-1 U, column-major
   double s2[KS];                 // ||z_j||^2
-  double2 fcol[WB_RMAX];         // Gauss-Jordan: multipliers of column j
-  double2 ustash[WB_RMAX + KS];  // Gauss-Jordan: normalised pivot row
+  double2 gjm[2][WB_RMAX];       // Gauss-Jordan: column j of step j (two steps in flight)
+  double2 gjinv[2];              // Gauss-Jordan: 1 / pivot
   double red[NWV];
   int order[KS];
-  int nrot, r, found, piv_row, singular, bad;
-  double pivr, pivi, cap;
+  int gjperm[WB_RMAX];           // Gauss-Jordan: pivot row of step j
+  int gjpr[2], gjsing[2];
+  int nrot, r, found, bad;
+  double cap;
 };
 
 // Householder vector of column c (rows >= c) of the column-major matrix `a`
@@ -134,6 +136,9 @@ __device__ __forceinline__ void lds_gemm(int M, int Nc, int Kd, const LA& la, co
 //     per super-round).
 // Pairs rotate when |z_p^H z_q| > JACOBI_TOL ||z_p|| ||z_q||; passes stop
 // when one rotates nothing.  Columns d .. 4 nb - 1 are zero and never rotate.
+// The norms and z_p^H z_q are summed in FP32 (rounding error a few 2^-24
+// ||z_p|| ||z_q||, well under the threshold); the row sums are bit-identical
+// in the 16 lanes, so they all take the same decision and the same rotation.
 __device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], bool act, bool& rotated) {
   float al = 0.f, be = 0.f, grf32 = 0.f, gif32 = 0.f;
 #pragma unroll
@@ -143,10 +148,10 @@ __device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], bool a
     grf32 = fmaf(zp[m].x, zq[m].x, fmaf(zp[m].y, zq[m].y, grf32));
     gif32 = fmaf(zp[m].x, zq[m].y, fmaf(-zp[m].y, zq[m].x, gif32));
   }
-  al = row16_sum(al);
-  be = row16_sum(be);
-  const double gr = row16_sum((double)grf32);
-  const double gi = row16_sum((double)gif32);
+  al = row16_sumf(al);
+  be = row16_sumf(be);
+  const float gr = row16_sumf(grf32);
+  const float gi = row16_sumf(gif32);
   const float mx = fmaxf(al, be);
   bool rot = act && mx > 0.f;
   float c = 1.f, s = 0.f;
@@ -158,7 +163,7 @@ __device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], bool a
     // working precision
     const float sc = __builtin_amdgcn_rcpf(mx);
     const float alf = al * sc, bef = be * sc;
-    const float grf = (float)gr * sc, gif = (float)gi * sc;
+    const float grf = gr * sc, gif = gi * sc;
     const float gg = grf * grf + gif * gif;
     rot = gg >= 1e-36f && gg > (float)(JACOBI_TOL * JACOBI_TOL) * alf * bef;
     const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));   // 1/|gamma|
@@ -283,34 +288,129 @@ __device__ void column_norms(Shared& sm, int K, int d) {
 // if rounding keeps the sum just below it) and the retained energy.
 __device__ void pick_rank(Shared& sm, int K, int d, double Et, int* r_out, double* cap_out,
                           double* td_sig2) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   column_norms(sm, K, d);
   __syncthreads();
-  if (tid < d) {
-    const double v = sm.s2[tid];
+  if (tid < 64) {
+    // wave 0, lane j holds sigma_j^2; its rank counts the larger values
+    // (and the equal ones of lower index)
+    const double v = lane < d ? sm.s2[lane] : -1.0;
     int rank = 0;
     for (int k = 0; k < d; ++k) {
-      const double w = sm.s2[k];
-      rank += (w > v) || (w == v && k < tid);
+      const double w = readlane_d(v, k);
+      rank += (w > v) || (w == v && k < lane);
     }
-    sm.order[rank] = tid;
-  }
-  __syncthreads();
-  if (tid == 0) {
+    if (lane < d) sm.order[rank] = lane;
+    wave_sync();
+    const double sv = lane < d ? sm.s2[sm.order[lane]] : 0.0;   // descending
+    // running sum in descending order, one term at a time
     double cs = 0.0;
     int rr = d;
     for (int m = 0; m < d; ++m) {
-      cs += sm.s2[sm.order[m]];
+      cs += readlane_d(sv, m);
       if (cs >= Et) { rr = m + 1; break; }
     }
-    sm.r = rr;
-    sm.cap = cs;
+    if (lane == 0) {
+      sm.r = rr;
+      sm.cap = cs;
+    }
+    if (lane < d) td_sig2[lane] = sv;
   }
   __syncthreads();
-  if (tid < d) td_sig2[tid] = sm.s2[sm.order[tid]];
   *r_out = sm.r;
   *cap_out = sm.cap;
   __syncthreads();
+}
+
+// Gauss-Jordan with partial pivoting on the r x ldg FP64 system
+// aug = [C | M] (row-major), r <= WB_RMAX: afterwards row gjperm[j] holds row
+// j of C^-1 M in columns r .. ldg - 1.  Rows are never exchanged: step j
+// takes as pivot the not yet used row with the largest |aug[i, j]| (the
+// lowest such row), scales it and eliminates column j from every other row.
+// Half-wave h = 2 wid + (lane >> 5) holds columns h, h + 32, h + 64 in
+// registers, row lane & 31.  Half-wave j + 1 owns column j + 1: after the
+// barrier of step j it updates that column first, at raised wave priority,
+// and publishes the next pivot (row, 1 / pivot and the column) in the other
+// of two LDS slots before its remaining columns, so a step costs one
+// workgroup barrier and the serial part is one column update and one
+// half-wave maximum.  Returns false (every thread alike) if a pivot's squared
+// modulus is not above SING_TOL^2 or is not finite.
+__device__ bool gj_solve_small(Shared& sm, double2* aug, int r, int ldg) {
+  constexpr int SLOTS = (WB_RMAX + KS + 31) / 32;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int row = lane & 31, hw = 2 * wid + (lane >> 5), base = lane & 32;
+  double2 x[SLOTS];
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) {
+    const int c = hw + 32 * q;
+    x[q] = (c < ldg && row < r) ? aug[row * ldg + c] : dz();
+  }
+  bool used = false;
+  // pivot of column j (slot 0 of half-wave j, the only active half of its
+  // wave here), published in slot j & 1
+  auto publish = [&](int j) {
+    const int b = j & 1;
+    const int hb = __builtin_amdgcn_readfirstlane(base);
+    const double mag = (!used && row < r) ? dabs2(x[0]) : -1.0;
+    double mx = mag;   // maximum over the 16-lane rows, then over the two rows
+    mx = fmax(mx, dpp_d<DPP_QUAD_1032>(mx));
+    mx = fmax(mx, dpp_d<DPP_QUAD_2301>(mx));
+    mx = fmax(mx, dpp_d<DPP_ROW_HALF_MIRROR>(mx));
+    mx = fmax(mx, dpp_d<DPP_ROW_MIRROR>(mx));
+    mx = fmax(readlane_d(mx, hb), readlane_d(mx, hb + 16));
+    const unsigned int hit = (unsigned int)(__ballot(mag == mx) >> hb);
+    const int pr = __ffs((int)hit) - 1;   // -1: NaN column, no maximum
+    const int pu = pr < 0 ? 0 : pr;
+    const double2 p = lane_read(x[0], hb + pu);
+    if (row < r) sm.gjm[b][row] = x[0];
+    if (row == 0) {
+      const bool sing = pr < 0 || !(mx > SING_TOL * SING_TOL) || !isfinite(mx);
+      // 1 / |p|^2: hardware reciprocal and one Newton step
+      const double a2 = sing ? 1.0 : dabs2(p);
+      double id = __builtin_amdgcn_rcp(a2);
+      id = fma(id, fma(-a2, id, 1.0), id);
+      sm.gjinv[b] = make_double2(p.x * id, -p.y * id);
+      sm.gjpr[b] = pu;
+      sm.gjsing[b] = sing;
+      sm.gjperm[j] = pu;
+    }
+  };
+  if (hw == 0) publish(0);
+  bool ok = true;
+  for (int j = 0; j < r; ++j) {
+    __syncthreads();
+    const int b = j & 1;
+    if (sm.gjsing[b]) { ok = false; break; }
+    const int pr = __builtin_amdgcn_readfirstlane(sm.gjpr[b]);
+    const double2 inv = sm.gjinv[b];
+    const double2 m = (row < r) ? sm.gjm[b][row] : dz();
+    used = used || row == pr;
+    const bool owner = hw == j + 1 && j + 1 < r;
+    if (owner) {
+      __builtin_amdgcn_s_setprio(2);
+      const double2 u = dmul(lane_read(x[0], __builtin_amdgcn_readfirstlane(base) + pr), inv);
+      x[0] = (row == pr) ? u : dsub(x[0], dmul(m, u));
+      publish(j + 1);
+      __builtin_amdgcn_s_setprio(0);
+    }
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+      const int c = hw + 32 * q;
+      if (c > j && c < ldg && !(owner && q == 0)) {
+        const double2 u = dmul(lane_shfl(x[q], base + pr), inv);
+        x[q] = (row == pr) ? u : dsub(x[q], dmul(m, u));
+      }
+    }
+  }
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+      const int c = hw + 32 * q;
+      if (c >= r && c < ldg && row < r) aug[row * ldg + c] = x[q];
+    }
+  }
+  __syncthreads();
+  return ok;
 }
 
 // PH = 0: the whole step (single track or batch).  Two-phase single-track
@@ -650,59 +750,10 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
         }
       }
     }
-    if (tid == 0) sm.singular = 0;
     __syncthreads();
     // step 3: Gauss-Jordan with partial pivoting on [C | V~^H A^-1]
-    for (int j = 0; j < r; ++j) {
-      if (wid == 0) {
-        const double2 v = (lane < r) ? aug[lane * ldg + j] : dz();
-        const double mag = (lane >= j && lane < r) ? dabs2(v) : -1.0;
-        double mx = mag;
-        mx = fmax(mx, dpp_d<DPP_QUAD_1032>(mx));
-        mx = fmax(mx, dpp_d<DPP_QUAD_2301>(mx));
-        mx = fmax(mx, dpp_d<DPP_ROW_ROR4>(mx));
-        mx = fmax(mx, dpp_d<DPP_ROW_ROR8>(mx));
-        mx = fmax(fmax(readlane_d(mx, 0), readlane_d(mx, 16)), fmax(readlane_d(mx, 32), readlane_d(mx, 48)));
-        const unsigned long long hit = __ballot(mag == mx);
-        const int idx = __ffsll((long long)hit) - 1;   // smallest row holding the maximum
-        if (idx < 0) {                                  // NaN column: no maximum
-          if (lane == 0) { sm.piv_row = j; sm.singular = 1; }
-        } else if (lane == idx) {
-          sm.piv_row = idx;
-          sm.pivr = v.x;
-          sm.pivi = v.y;
-          if (!(sqrt(mx) > SING_TOL) || !isfinite(mx)) sm.singular = 1;
-        }
-      }
-      __syncthreads();
-      if (sm.singular) break;
-      const int pr = sm.piv_row;
-      const double2 piv = make_double2(sm.pivr, sm.pivi);
-      // multipliers of the rows after the swap, read before it
-      double2 fj = dz();
-      if (tid < r) {
-        const int src = (tid == j) ? pr : (tid == pr ? j : tid);
-        fj = aug[src * ldg + j];
-      }
-      __syncthreads();
-      if (tid < r) sm.fcol[tid] = fj;
-      for (int c = j + tid; c < ldg; c += NTH) {
-        const double2 a = aug[j * ldg + c], b = aug[pr * ldg + c];
-        const double2 u = ddiv(b, piv);
-        aug[pr * ldg + c] = a;
-        aug[j * ldg + c] = u;
-        sm.ustash[c] = u;
-      }
-      __syncthreads();
-      const int w = ldg - j - 1;
-      for (int e = tid; e < r * w; e += NTH) {
-        const int i = e / w, c = j + 1 + (e - i * w);
-        if (i == j) continue;
-        aug[i * ldg + c] = dsub(aug[i * ldg + c], dmul(sm.fcol[i], sm.ustash[c]));
-      }
-      __syncthreads();
-    }
-    if (sm.singular) {
+    const bool solved = gj_solve_small(sm, aug, r, ldg);
+    if (!solved) {
       use_wb = false;
       path = RZF_PATH_FULL_SINGULAR;
     } else {
@@ -710,7 +761,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       float2* out = td->Ainv;
       lds_gemm(K, K, r,
                [&](int i, int a) { return (i < K && a < r) ? tm[a * LDK + i] : cz(); },
-               [&](int a, int j) { return (a < r && j < K) ? d2f(aug[a * ldg + r + j]) : cz(); },
+               [&](int a, int j) { return (a < r && j < K) ? d2f(aug[sm.gjperm[a] * ldg + r + j]) : cz(); },
                [&](int i, int j, float2 v) { out[(size_t)i * K + j] = csub(b0[i * LDK + j], v); });
     }
     __syncthreads();

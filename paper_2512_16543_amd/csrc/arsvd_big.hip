@@ -285,21 +285,16 @@ __device__ __forceinline__ float gsumf(float v) {
   if constexpr (G == 16) return v;
   return v + __shfl_xor(v, 16);
 }
-template <int G>
-__device__ __forceinline__ double gsumd(double v) {
-  v = row16_sum(v);
-  if constexpr (G == 16) return v;
-  return v + __shfl_xor(v, 16);
-}
 
 // Rotation of the job column pair (pp, qq) of Z held in LDS (sm.u.jac.z,
 // column c at c*K) by the calling group of G lanes (rows gl + G m, m < JR):
 // the one-sided Jacobi step that makes z_p and z_q orthogonal.  ||z_p||^2
 // and ||z_q||^2 are sums of non-negative FP32 terms.  The inner product
 // z_p^H z_q cancels as the columns become orthogonal: each lane forms its
-// share in FP32 (error about 2^-24 ||z_p|| ||z_q||, a few percent of the
-// rotation threshold) and the G shares are added in FP64.  A pair already
-// orthogonal to JACOBI_TOL is left alone.  Sets sm.nrot when it rotates.
+// share in FP32 and the G shares are added in FP32 too (rounding error at
+// most about 13 x 2^-24 ||z_p|| ||z_q||, under half the rotation threshold);
+// every lane of the group forms the same bits, so the group applies one
+// rotation.  A pair already orthogonal to JACOBI_TOL is left alone.  Sets sm.nrot when it rotates.
 // Every lane of the wave calls it (act = false for an idle group).
 constexpr int JR = 8;   // rows per lane: G = 16 covers K <= 128, G = 32 K <= 256
 template <int G>
@@ -324,8 +319,8 @@ __device__ __forceinline__ void jacobi_pair(BigShared& sm, int K, int pp, int qq
   }
   al = gsumf<G>(al);
   be = gsumf<G>(be);
-  const double gr = gsumd<G>((double)grs);
-  const double gi = gsumd<G>((double)gis);
+  const float gr = gsumf<G>(grs);
+  const float gi = gsumf<G>(gis);
   const float mx = fmaxf(al, be);
   bool rot = act && mx > 0.f;
   float c = 1.f, s = 0.f;
@@ -334,7 +329,7 @@ __device__ __forceinline__ void jacobi_pair(BigShared& sm, int K, int pp, int qq
     // same rotation as the LDS kernel: sums scaled by 1/max(alpha, beta)
     const float sc = __builtin_amdgcn_rcpf(mx);
     const float alf = al * sc, bef = be * sc;
-    const float grf = (float)gr * sc, gif = (float)gi * sc;
+    const float grf = gr * sc, gif = gi * sc;
     const float gg = grf * grf + gif * gif;
     rot = gg >= 1e-36f && gg > (float)(JACOBI_TOL * JACOBI_TOL) * alf * bef;
     const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));

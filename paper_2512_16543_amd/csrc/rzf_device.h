@@ -43,17 +43,24 @@ __device__ __forceinline__ double2 f2d(float2 a) { return make_double2((double)a
 __device__ __forceinline__ float2 d2f(double2 a) { return make_float2((float)a.x, (float)a.y); }
 
 // --------------------------------------------------------- wave reductions
-// Cross-lane sums with DPP row operations (quad permutations and row
-// rotations inside each 16-lane row) and v_readlane to combine the four rows.
-// All 64 lanes must be active when these are called.
-#define DPP_QUAD_1032 0xB1   // quad_perm [1,0,3,2]
-#define DPP_QUAD_2301 0x4E   // quad_perm [2,3,0,1]
+// Cross-lane sums with DPP row operations (quad permutations and mirrors
+// inside each 16-lane row, row broadcasts across rows).  Each step adds a
+// lane's value to its partner's under a pairing that is its own inverse, so
+// both partners form the same sum (a + b == b + a) and every lane of a row
+// ends with bit-identical results, in FP32 too.  All 64 lanes must be active
+// when these are called.
+#define DPP_QUAD_1032 0xB1        // quad_perm [1,0,3,2]
+#define DPP_QUAD_2301 0x4E        // quad_perm [2,3,0,1]
 #define DPP_ROW_ROR4 0x124
 #define DPP_ROW_ROR8 0x128
+#define DPP_ROW_MIRROR 0x140      // lane i <-> 15 - i within the row
+#define DPP_ROW_HALF_MIRROR 0x141 // lane i <-> 7 - i within each half-row
+#define DPP_ROW_BCAST15 0x142     // lane 15 of row k to every lane of row k + 1
+#define DPP_ROW_BCAST31 0x143     // lane 31 to every lane of rows 2 and 3
 
 // Lanes whose DPP source is out of range read zero (bound_ctrl), so no
 // "old" value has to be set up first; the permutations used here (quad
-// permutes, row rotates, the half-row mirror) have no such lanes anyway.
+// permutes, row rotates and mirrors) have no such lanes anyway.
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
@@ -65,24 +72,37 @@ __device__ __forceinline__ double dpp_d(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-// Sum over the 16 lanes of each row; every lane of the row gets the row sum.
+// A row broadcast written only to the rows in ROWS (a 4-bit row mask); the
+// other lanes read zero.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_rows_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over the 16 lanes of each row; every lane of the row gets the row sum
+// ((q0 + q1) + (q2 + q3) over the quad sums q).
 __device__ __forceinline__ double row16_sum(double v) {
   v += dpp_d<DPP_QUAD_1032>(v);
   v += dpp_d<DPP_QUAD_2301>(v);
-  v += dpp_d<DPP_ROW_ROR4>(v);
-  v += dpp_d<DPP_ROW_ROR8>(v);
+  v += dpp_d<DPP_ROW_HALF_MIRROR>(v);
+  v += dpp_d<DPP_ROW_MIRROR>(v);
   return v;
 }
 __device__ __forceinline__ float row16_sumf(float v) {
   v += dpp_f<DPP_QUAD_1032>(v);
   v += dpp_f<DPP_QUAD_2301>(v);
-  v += dpp_f<DPP_ROW_ROR4>(v);
-  v += dpp_f<DPP_ROW_ROR8>(v);
+  v += dpp_f<DPP_ROW_HALF_MIRROR>(v);
+  v += dpp_f<DPP_ROW_MIRROR>(v);
   return v;
 }
 __device__ __forceinline__ float row16_sum(float v) { return row16_sumf(v); }
 // Sum over each 8-lane half-row (quad permutations, then the half-row mirror).
-#define DPP_ROW_HALF_MIRROR 0x141
 __device__ __forceinline__ double row8_sum(double v) {
   v += dpp_d<DPP_QUAD_1032>(v);
   v += dpp_d<DPP_QUAD_2301>(v);
@@ -101,17 +121,20 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-// Sum over all 64 lanes (same value, same rounding, in every lane).
+// Sum over all 64 lanes, (r3 + r2) + (r1 + r0) over the row sums r: the row
+// broadcasts fold rows 0 into 1 and 2 into 3, then rows 0-1 into 3; lane 63
+// holds the total and every lane returns it.
 __device__ __forceinline__ double wave_sum(double v) {
   v = row16_sum(v);
-  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+  v += dpp_rows_d<DPP_ROW_BCAST15, 0xA>(v);
+  v += dpp_rows_d<DPP_ROW_BCAST31, 0xC>(v);
+  return readlane_d(v, 63);
 }
 __device__ __forceinline__ float wave_sumf(float v) {
   v = row16_sumf(v);
-  return (__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)) +
-          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16))) +
-         (__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32)) +
-          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48)));
+  v += dpp_rows_f<DPP_ROW_BCAST15, 0xA>(v);
+  v += dpp_rows_f<DPP_ROW_BCAST31, 0xC>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // Sum over the whole workgroup; `red` holds one double per wave.  Every
