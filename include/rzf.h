@@ -155,7 +155,13 @@ rzf_status rzf_init(rzf_ctx* ctx, int K, int N, const rzf_c32* H, int ldh, doubl
  * For K <= 64 the iterations of Alg. 1 that the track's previous step
  * predicts (its iteration count plus one) are computed at once on otherwise
  * idle CUs before the decision; the results are bit-identical to the same
- * update through rzf_update_batch, which runs them one after another. */
+ * update through rzf_update_batch, which runs them one after another.
+ * For K <= 64 an iteration whose sketch spans all K columns (d = K, Q
+ * unitary, so the SVD of B gives the truncated SVD of Delta A for any Q)
+ * starts its Jacobi SVD from the track's left singular basis of its last
+ * such iteration instead of a fresh Q: the same result up to rounding,
+ * reached in about half the Jacobi passes.  The basis is part of the track's
+ * state (and of its checkpoint). */
 rzf_status rzf_update(rzf_track* tr, const rzf_c32* H_t, int ldh, double tol,
                       rzf_c32* W, int ldw, rzf_update_info* info);
 
@@ -262,8 +268,8 @@ rzf_status rzf_track_query(rzf_track* tr, int* K, int* N, int* t, int* since_res
 rzf_status rzf_track_destroy(rzf_track* tr);
 
 /* Checkpoint / resume of a track (the state Alg. 2 carries between
- * snapshots: A^-1 and the previous snapshot, plus the step counters and the
- * previous k_est).  rzf_track_export with buf == NULL stores the blob size in
+ * snapshots: A^-1 and the previous snapshot, plus the step counters, the
+ * previous k_est, the error-feedback residual and the full-width SVD basis).  rzf_track_export with buf == NULL stores the blob size in
  * *bytes; otherwise it synchronises the context's stream and writes the blob
  * (host memory, *bytes >= that size, else RZF_E_INVALID with the size in
  * *bytes).  rzf_track_import creates a new track in `ctx` from a blob written

@@ -34,7 +34,7 @@ size_t scratch_bytes() {
 }
 
 struct Layout {
-  size_t desc, ainv, hprev, anew, da, a64, wpart, rfb, ym, qm, zm, pm, aug, total;
+  size_t desc, ainv, hprev, anew, da, a64, wpart, rfb, xw, ym, qm, zm, pm, aug, total;
 };
 
 Layout track_layout(int K, int N) {
@@ -48,6 +48,9 @@ Layout track_layout(int K, int N) {
   L.a64 = o; o += align_up(sizeof(double2) * K * K);
   L.wpart = o; o += align_up(sizeof(double) * precoder_blocks(N));
   L.rfb = o; o += align_up(sizeof(float2) * K * K);
+  if (K <= KS) {
+    L.xw = o; o += align_up(sizeof(float2) * K * K);   // full-width SVD basis
+  }
   if (K > KS) {
     // working set of the large-track kernels
     L.ym = o; o += align_up(sizeof(float2) * K * K);
@@ -233,6 +236,7 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
   d.A64 = reinterpret_cast<double2*>(base + L.a64);
   d.wpart = reinterpret_cast<double*>(base + L.wpart);
   d.Rfb = reinterpret_cast<float2*>(base + L.rfb);
+  if (K <= KS) d.Xw = reinterpret_cast<float2*>(base + L.xw);
   if (K > KS) {
     d.Ym = reinterpret_cast<float2*>(base + L.ym);
     d.Qm = reinterpret_cast<float2*>(base + L.qm);
@@ -246,21 +250,24 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
 }
 
 // Checkpoint blob of one track: this header, then A^-1 (K x K) and H_prev
-// (K x N), complex64 row-major.
+// (K x N) row-major, the error-feedback residual R (K x K, row-major) and
+// the full-width SVD basis (K x K, column-major; zero for K > KS), all
+// complex64.
 struct TrackBlob {
   char magic[8];
   uint32_t version, header_bytes;
   int32_t K, N;
   rzf_params prm;
   double alpha;
-  int32_t step, since_reset, last_r, pad;
+  int32_t step, since_reset, last_r, warm, warm_age, pad;
 };
 const char BLOB_MAGIC[8] = {'R', 'Z', 'F', 'T', 'R', 'A', 'C', 'K'};
-constexpr uint32_t BLOB_VERSION = 3;   // 3: params gained early_fallback, precision, error
-                                       // feedback; the residual R follows H_prev
+constexpr uint32_t BLOB_VERSION = 4;   // 3: params gained early_fallback, precision, error
+                                       // feedback; the residual R follows H_prev.
+                                       // 4: the full-width SVD basis follows R
 
 size_t blob_bytes(int K, int N) {
-  return sizeof(TrackBlob) + sizeof(float2) * (2 * (size_t)K * K + (size_t)K * N);
+  return sizeof(TrackBlob) + sizeof(float2) * (3 * (size_t)K * K + (size_t)K * N);
 }
 
 }  // namespace
@@ -905,6 +912,8 @@ rzf_status rzf_track_export(rzf_track* t, void* buf, size_t* bytes) {
   h.K = t->K; h.N = t->N; h.prm = t->prm; h.alpha = t->alpha;
   h.step = t->t; h.since_reset = t->since_reset;
   HIP_OK(hipMemcpy(&h.last_r, &t->d_desc->last_r, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(&h.warm, &t->d_desc->warm, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(&h.warm_age, &t->d_desc->warm_age, sizeof(int), hipMemcpyDeviceToHost));
   char* p = static_cast<char*>(buf);
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
@@ -913,6 +922,11 @@ rzf_status rzf_track_export(rzf_track* t, void* buf, size_t* bytes) {
   HIP_OK(hipMemcpy(p, t->h_desc.Hprev, sizeof(float2) * (size_t)t->K * t->N, hipMemcpyDeviceToHost));
   p += sizeof(float2) * (size_t)t->K * t->N;
   HIP_OK(hipMemcpy(p, t->h_desc.Rfb, sizeof(float2) * t->K * t->K, hipMemcpyDeviceToHost));
+  p += sizeof(float2) * t->K * t->K;
+  if (t->h_desc.Xw)
+    HIP_OK(hipMemcpy(p, t->h_desc.Xw, sizeof(float2) * t->K * t->K, hipMemcpyDeviceToHost));
+  else
+    std::memset(p, 0, sizeof(float2) * t->K * t->K);
   *bytes = need;
   return RZF_OK;
 }
@@ -929,7 +943,8 @@ rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track
   if (h.K < 1 || h.K > RZF_KMAX || h.N < 1 || h.N > RZF_NMAX) return RZF_E_SHAPE;
   if (bytes < blob_bytes(h.K, h.N)) return RZF_E_INVALID;
   if (!params_valid(&h.prm) || !std::isfinite(h.alpha) || h.alpha < 0.0 || h.step < 0 ||
-      h.since_reset < 0 || h.last_r < 0 || h.last_r > h.K)
+      h.since_reset < 0 || h.last_r < 0 || h.last_r > h.K || (h.warm != 0 && h.warm != 1) ||
+      h.warm_age < 0 || (h.warm && h.K > KS))
     return RZF_E_INVALID;
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
@@ -940,13 +955,18 @@ rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track
   t->t = h.step;
   t->since_reset = h.since_reset;
   t->h_desc.last_r = h.last_r;
+  t->h_desc.warm = h.warm;
+  t->h_desc.warm_age = h.warm_age;
   const char* p = static_cast<const char*>(buf) + sizeof(h);
   bool ok = hipMemcpy(t->d_desc, &t->h_desc, sizeof(TrackDesc), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(t->h_desc.Ainv, p, sizeof(float2) * h.K * h.K, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(t->h_desc.Hprev, p + sizeof(float2) * h.K * h.K, sizeof(float2) * (size_t)h.K * h.N,
                       hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(t->h_desc.Rfb, p + sizeof(float2) * ((size_t)h.K * h.K + (size_t)h.K * h.N),
-                      sizeof(float2) * h.K * h.K, hipMemcpyHostToDevice) == hipSuccess;
+                      sizeof(float2) * h.K * h.K, hipMemcpyHostToDevice) == hipSuccess &&
+            (!t->h_desc.Xw ||
+             hipMemcpy(t->h_desc.Xw, p + sizeof(float2) * (2 * (size_t)h.K * h.K + (size_t)h.K * h.N),
+                       sizeof(float2) * h.K * h.K, hipMemcpyHostToDevice) == hipSuccess);
   if (!ok) {
     arena_free(c, t->off, t->bytes);
     delete t;

@@ -47,6 +47,10 @@ constexpr int NTH = 1024;
 constexpr int LDK = KS + 1;
 constexpr int NWV = NTH / 64;
 constexpr int MAX_SWEEPS = 30;
+// a track's full-width basis is re-orthonormalised (one Newton-Schulz step)
+// before its use once it has taken this many SVDs' rotations
+constexpr int POLISH_EVERY = 8;
+static_assert(2 * WB_RMAX >= KS, "pm and tm together hold a K x K matrix");
 constexpr double JACOBI_TOL = 2e-6;
 constexpr double SING_TOL = 1e-12;
 
@@ -139,7 +143,9 @@ __device__ __forceinline__ void lds_gemm(int M, int Nc, int Kd, const LA& la, co
 // The norms and z_p^H z_q are summed in FP32 (rounding error a few 2^-24
 // ||z_p|| ||z_q||, well under the threshold); the row sums are bit-identical
 // in the 16 lanes, so they all take the same decision and the same rotation.
-__device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], bool act, bool& rotated) {
+template <bool ACC>
+__device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], float2 xp[4], float2 xq[4], bool act,
+                                              bool& rotated) {
   float al = 0.f, be = 0.f, grf32 = 0.f, gif32 = 0.f;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
@@ -184,18 +190,33 @@ __device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], bool a
       zq[m] = cadd(cscale(zp[m], s), cscale(zq2, c));
       zp[m] = np;
     }
+    if constexpr (ACC) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const float2 xq2 = cmul(e, xq[m]);
+        const float2 np = csub(cscale(xp[m], c), cscale(xq2, s));
+        xq[m] = cadd(cscale(xp[m], s), cscale(xq2, c));
+        xp[m] = np;
+      }
+    }
     rotated = true;
   }
 }
 
+template <bool ACC>
 __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* rounds_out) {
+  float2* b1 = sm.b1;
   float2* b2 = sm.b2;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int nb = ((d + 3) / 4 + 1) & ~1;   // blocks of 4 columns, an even number (<= 16)
   const int nw = nb / 2;                   // waves holding a block pair
-  for (int e = threadIdx.x; e < (4 * nb - d) * LDK; e += NTH) b2[d * LDK + e] = cz();
+  for (int e = threadIdx.x; e < (4 * nb - d) * LDK; e += NTH) {
+    b2[d * LDK + e] = cz();
+    if constexpr (ACC) b1[d * LDK + e] = cz();
+  }
   int sweeps = 0, rounds = 0;
+  float2 xp[4], xq[4];   // basis columns (ACC), moved like the Z columns
   for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
     if (threadIdx.x == 0) sm.nrot = 0;
     __syncthreads();
@@ -210,17 +231,27 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
         rr_pair(t, m, 4, &p, &q);
         float2* zpc = b2 + (c0 + p) * LDK + li;
         float2* zqc = b2 + (c0 + q) * LDK + li;
+        float2* xpc = b1 + (c0 + p) * LDK + li;
+        float2* xqc = b1 + (c0 + q) * LDK + li;
         float2 zp[4], zq[4];
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
           zp[mm] = zpc[16 * mm];
           zq[mm] = zqc[16 * mm];
+          if constexpr (ACC) {
+            xp[mm] = xpc[16 * mm];
+            xq[mm] = xqc[16 * mm];
+          }
         }
-        jacobi_rotate(zp, zq, true, rotated);
+        jacobi_rotate<ACC>(zp, zq, xp, xq, true, rotated);
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
           zpc[16 * mm] = zp[mm];
           zqc[16 * mm] = zq[mm];
+          if constexpr (ACC) {
+            xpc[16 * mm] = xp[mm];
+            xqc[16 * mm] = xq[mm];
+          }
         }
         wave_sync();
       }
@@ -234,24 +265,36 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
         rr_pair(sr, wid, nb, &A, &B);
         float2* zac = b2 + (4 * A + g) * LDK + li;
         float2* zbc = b2 + (4 * B + g) * LDK + li;
+        float2* xac = b1 + (4 * A + g) * LDK + li;
+        float2* xbc = b1 + (4 * B + g) * LDK + li;
         float2 za[4], zb[4];
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
           za[mm] = zac[16 * mm];
           zb[mm] = zbc[16 * mm];
+          if constexpr (ACC) {
+            xp[mm] = xac[16 * mm];
+            xq[mm] = xbc[16 * mm];
+          }
         }
         const int up = (lane + 16) & 63;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          jacobi_rotate(za, zb, true, rotated);   // column 4A + g with column 4B + (g + t) % 4
+          jacobi_rotate<ACC>(za, zb, xp, xq, true, rotated);   // column 4A + g with column 4B + (g + t) % 4
 #pragma unroll
-          for (int mm = 0; mm < 4; ++mm)
+          for (int mm = 0; mm < 4; ++mm) {
             zb[mm] = make_float2(__shfl(zb[mm].x, up), __shfl(zb[mm].y, up));
+            if constexpr (ACC) xq[mm] = make_float2(__shfl(xq[mm].x, up), __shfl(xq[mm].y, up));
+          }
         }
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
           zac[16 * mm] = za[mm];
           zbc[16 * mm] = zb[mm];
+          if constexpr (ACC) {
+            xac[16 * mm] = xp[mm];
+            xbc[16 * mm] = xq[mm];
+          }
         }
       }
       rounds += 4;
@@ -475,9 +518,46 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   bool found = false, rotated = false;
   // iterations computed ahead in the two-phase form: the last count plus one
   const int n_spec = PH == 0 ? 0 : min(min(i_max, SPEC_MAX), max(td->spec_hint, 0) + 1);
+  // a full-width sketch (d = K) has a unitary Q, and the SVD of B = Q^H Delta A
+  // then yields the truncated SVD of Delta A whatever Q is: such an iteration
+  // starts from the track's basis of its last full-width SVD when it has one
+  const bool warm_ok = td->warm != 0;
+  const bool polish = warm_ok && td->warm_age >= POLISH_EVERY;
+  bool basis = false;   // the SVD ran at d = K and rotated b1 along with Z
   // one iteration of Alg. 1 up to the energy test: Omega, Y, Q (b1), Z (b2),
   // returning ||Z||_F^2
   auto sketch_iteration = [&](int itn, int d) -> double {
+    if (d == K && warm_ok) {
+    // the track's basis -> b1
+    for (int e = tid; e < K * K; e += NTH) {
+      const int j = e / K, i = e - j * K;
+      b1[j * LDK + i] = td->Xw[e];
+    }
+    __syncthreads();
+    if (polish) {
+      // X <- X (3 I - X^H X) / 2 (one Newton-Schulz step towards the nearest
+      // unitary matrix): M -> b2, X M -> pm:tm, then back to b1
+      float2* xs = sm.pm;
+      lds_gemm(K, K, K,
+               [&](int i, int k) { return (i < K && k < K) ? cconj(b1[i * LDK + k]) : cz(); },
+               [&](int k, int j) { return (k < K && j < K) ? b1[j * LDK + k] : cz(); },
+               [&](int i, int j, float2 v) {
+                 b2[j * LDK + i] = make_float2((i == j ? 1.5f : 0.f) - 0.5f * v.x, -0.5f * v.y);
+               });
+      __syncthreads();
+      lds_gemm(K, K, K,
+               [&](int i, int k) { return (i < K && k < K) ? b1[k * LDK + i] : cz(); },
+               [&](int k, int j) { return (k < K && j < K) ? b2[j * LDK + k] : cz(); },
+               [&](int i, int j, float2 v) { xs[j * LDK + i] = v; });
+      __syncthreads();
+      for (int e = tid; e < K * K; e += NTH) {
+        const int j = e / K, i = e - j * K;
+        b1[j * LDK + i] = xs[j * LDK + i];
+      }
+      __syncthreads();
+    }
+    t_sk += clock64() - c_mark; c_mark = clock64();
+    } else {
     // Omega -> b1 (column-major)
     for (int e = tid; e < K * d; e += NTH) {
       const int j = e / K, i = e - j * K;
@@ -555,6 +635,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
         if (wid + NWV * q < d) b1[(wid + NWV * q) * LDK + lane] = y[q];
     }
     __syncthreads();
+    }
     // Z = Delta A^H Q = B^H -> b2 (Delta A is Hermitian unless error feedback
     // has added its residual, so the conjugate transpose is taken explicitly)
     lds_gemm(K, d, K,
@@ -596,7 +677,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     for (int it = 1; it <= n_spec; ++it) {
       iters = it;
       d = min(k0 + p, K);
-      qrcols += d;
+      if (!(d == K && warm_ok)) qrcols += d;
       const double tot = totw[it - 1];
       const bool hit = tot >= Et;
       if (hit || it == i_max || (td->early_fallback && d > td->wb_limit)) {
@@ -611,7 +692,9 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
         c_mark = clock64();
         if (hit) {
           found = true;
-          jacobi_svd(sm, K, d, &sweeps, &rounds);
+          basis = d == K;
+          if (basis) jacobi_svd<true>(sm, K, d, &sweeps, &rounds);
+          else jacobi_svd<false>(sm, K, d, &sweeps, &rounds);
           t_jac += clock64() - c_mark; c_mark = clock64();
           rotated = true;
           pick_rank(sm, K, d, Et, &r, &captured, td->sig2);
@@ -633,7 +716,9 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       const double tot = sketch_iteration(it, d);
       if (tot >= Et) {
         found = true;
-        jacobi_svd(sm, K, d, &sweeps, &rounds);
+        basis = d == K;
+        if (basis) jacobi_svd<true>(sm, K, d, &sweeps, &rounds);
+        else jacobi_svd<false>(sm, K, d, &sweeps, &rounds);
         t_jac += clock64() - c_mark; c_mark = clock64();
         rotated = true;
         pick_rank(sm, K, d, Et, &r, &captured, td->sig2);
@@ -660,7 +745,23 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   int path = use_wb ? RZF_PATH_WB : RZF_PATH_FULL_RANK;
   float2* pm = sm.pm;
   float2* tm = sm.tm;
-  if (rotated && use_wb) {
+  if (basis) {
+    // b1 = Q times the Jacobi rotations: the left singular vectors of
+    // Delta A, kept as the track's next full-width starting basis
+    for (int e = tid; e < K * K; e += NTH) {
+      const int j = e / K, i = e - j * K;
+      td->Xw[e] = b1[j * LDK + i];
+    }
+  }
+  if (rotated && use_wb && basis) {
+    // U_r = Q U_hat_r: the rotated basis columns in descending sigma order
+    const int* ord = sm.order;
+    for (int e = tid; e < K * r; e += NTH) {
+      const int c = e / K, i = e - c * K;
+      pm[c * LDK + i] = b1[ord[c] * LDK + i];
+    }
+    __syncthreads();
+  } else if (rotated && use_wb) {
     // U_r = Q U_hat_r = Q Q^H Delta A Z_r Sigma_r^-2 (B V_hat = U_hat Sigma with
     // V_hat = Z Sigma^-1); every retained sigma_j is positive
     const int* ord = sm.order;
@@ -789,6 +890,10 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     if (jb.out) *jb.out = td->info;
     td->last_r = r;
     td->spec_hint = iters;
+    if (basis) {
+      td->warm_age = (warm_ok && !polish) ? td->warm_age + 1 : 1;
+      td->warm = 1;
+    }
     td->dbg[0] = sweeps; td->dbg[1] = rounds; td->dbg[2] = qrcols;
     td->nsig = rotated ? d : 0;
     t_wb = clock64() - c_mark;

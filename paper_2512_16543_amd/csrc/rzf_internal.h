@@ -29,6 +29,8 @@ struct TrackDesc {
   int early_fallback, wb_limit;   // policy flag; largest rank the Woodbury branch takes
   int prec, error_feedback;       // rzf_precision of the Gram and precoder operands; policy
   float2* Rfb;     // K x K, ld K: error-feedback residual (zero unless the policy is on)
+  float2* Xw;      // K x K, column-major ld K (K <= KS): left singular basis of the last
+                   // full-width (d = K) SVD, the next one's starting point
   uint64_t seed, track_id;
   float2* Ainv;    // K x K, ld K: stored inverse
   float2* Hprev;   // K x N, ld N: previous snapshot
@@ -46,6 +48,9 @@ struct TrackDesc {
   // written by the device
   int last_r;
   int spec_hint;   // Alg. 1 iterations of the last step that ran it (speculation depth)
+  int warm;        // Xw holds a basis
+  int warm_age;    // full-width SVDs whose rotations Xw has taken since it was last
+                   // orthonormal to working precision
   DevInfo info;
   int dbg[8];      // last update: [0] Jacobi sweeps, [1] Jacobi rounds, [2] QR columns
   int nsig;        // number of sigma^2 below (d of the last SVD, 0 if none)

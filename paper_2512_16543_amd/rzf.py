@@ -457,11 +457,13 @@ class Track:
 
     def residual(self):
         """The error-feedback residual R (K x K complex64 numpy array): the
-        last K*K entries of the checkpoint blob."""
+        K*K entries of the checkpoint blob before its last K*K (the
+        full-width SVD basis)."""
         import numpy as np
         blob = self.export()
         n = self.K * self.K * 8
-        return np.frombuffer(blob[len(blob) - n:], dtype=np.complex64).reshape(self.K, self.K).copy()
+        return np.frombuffer(blob[len(blob) - 2 * n:len(blob) - n],
+                             dtype=np.complex64).reshape(self.K, self.K).copy()
 
     def destroy(self):
         if self.h:

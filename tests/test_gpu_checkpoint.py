@@ -53,6 +53,39 @@ def test_resume_is_bit_identical(K, N, period, policy):
     other.close()
 
 
+def test_resume_keeps_full_width_basis():
+    # the K = 64 track at eta = 0.999 ends every step at d = K, where the SVD
+    # starts from the track's stored basis: the blob carries it, so the
+    # resumed track (including its re-orthonormalisation schedule) continues
+    # bit for bit
+    cfg = wl.CONFIGS["c2"]
+    Hs = torch.from_numpy(wl.make_track(wl.with_overrides(cfg, steps=14)).snapshots()
+                          .astype(np.complex64)).cuda()
+    ctx = rzf.Context(0, 64 << 20)
+    prm = rzf.default_params(k_init=cfg.k_init, p=cfg.p, seed=cfg.seed, reset_period=0)
+    a = ctx.init(Hs[0], cfg.alpha, prm)
+    Wa = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device="cuda")
+    Wb = torch.empty_like(Wa)
+    for t in range(1, 6):
+        a.update(Hs[t], 0.999, Wa)
+    ctx.sync()
+    b = ctx.import_track(a.export())
+    for t in range(6, 15):
+        ia = a.update(Hs[t], 0.999, Wa)
+        ib = b.update(Hs[t], 0.999, Wb)
+        ctx.sync()
+        assert (ia.r, ia.iters, ia.path) == (ib.r, ib.iters, ib.path), t
+        assert torch.equal(Wa, Wb), t
+        assert torch.equal(a.inverse(), b.inverse()), t
+        ca, cb = a.counters(), b.counters()
+        assert ca["qr_columns"] == cb["qr_columns"], t
+        if ia.iters == 6:
+            assert ca["qr_columns"] == 7 + 9 + 13 + 21 + 37, t   # no QR at d = K
+    a.destroy()
+    b.destroy()
+    ctx.close()
+
+
 def test_import_rejects_bad_blobs():
     Hs = walk(8, 16, 1, 3)
     ctx = rzf.Context(0, 16 << 20)

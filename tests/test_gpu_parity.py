@@ -245,6 +245,31 @@ def test_update_c2_short(ctx, eta):
     assert all(r["e"] < 1e-4 for r in recs if r["path"] != orz.PATH_RESET)
 
 
+def test_update_c2_full_width_basis(ctx):
+    # eta = 0.999 at K = 64 always ends at d = K: from the second such step on
+    # the SVD starts from the track's basis (no QR at d = K, fewer passes),
+    # and every eighth use re-orthonormalises it first; one-step parity with
+    # the oracle holds throughout
+    cfg = wl.CONFIGS["c2"]
+    recs = run_track(ctx, cfg, 40, 0.999, dict(reset_period=0))
+    _assert_recs(recs)
+    assert sum(r["iters"] == 6 for r in recs) >= 30
+    Hs = dev(c64(wl.make_track(wl.with_overrides(cfg, steps=12)).snapshots()))
+    tr = ctx.init(Hs[0], cfg.alpha, rzf.default_params(**_params(cfg, reset_period=0)))
+    W = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device="cuda")
+    full = []   # counters of the steps that ran Alg. 1 up to d = K = 64
+    for t in range(1, 13):
+        info = tr.update(Hs[t], 0.999, W)
+        ctx.sync()
+        if info.iters == 6:
+            full.append(tr.counters())
+    tr.destroy()
+    assert len(full) >= 8
+    assert full[0]["qr_columns"] == 7 + 9 + 13 + 21 + 37 + 64
+    assert all(c["qr_columns"] == 7 + 9 + 13 + 21 + 37 for c in full[1:])
+    assert np.mean([c["jacobi_sweeps"] for c in full[1:]]) < 0.8 * full[0]["jacobi_sweeps"]
+
+
 def test_update_early_fallback_policy(ctx):
     # eta = 0.999 at K = 64: d = 37 > K/2 misses the target, so the policy
     # inverts directly there instead of running on to d = 64
