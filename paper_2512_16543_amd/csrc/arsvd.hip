@@ -52,6 +52,10 @@ constexpr int MAX_SWEEPS = 30;
 constexpr int POLISH_EVERY = 8;
 static_assert(2 * WB_RMAX >= KS, "pm and tm together hold a K x K matrix");
 constexpr double JACOBI_TOL = 2e-6;
+// passes stop after one whose largest |z_p^H z_q| / (||z_p|| ||z_q||) is below
+// JACOBI_QSTOP: near convergence a pass squares that measure, so the next
+// one would only rotate pairs at about JACOBI_QSTOP^2, the FP32 noise level
+constexpr double JACOBI_QSTOP = 1e-3;
 constexpr double SING_TOL = 1e-12;
 
 
@@ -139,13 +143,14 @@ __device__ __forceinline__ void lds_gemm(int M, int Nc, int Kd, const LA& la, co
 //     round by a lane permute; then both blocks go back to LDS (one barrier
 //     per super-round).
 // Pairs rotate when |z_p^H z_q| > JACOBI_TOL ||z_p|| ||z_q||; passes stop
-// when one rotates nothing.  Columns d .. 4 nb - 1 are zero and never rotate.
+// after one in which no pair had |z_p^H z_q| > JACOBI_QSTOP ||z_p|| ||z_q||
+// (`moved`).  Columns d .. 4 nb - 1 are zero and never rotate.
 // The norms and z_p^H z_q are summed in FP32 (rounding error a few 2^-24
 // ||z_p|| ||z_q||, well under the threshold); the row sums are bit-identical
 // in the 16 lanes, so they all take the same decision and the same rotation.
 template <bool ACC>
 __device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], float2 xp[4], float2 xq[4], bool act,
-                                              bool& rotated) {
+                                              bool& moved) {
   float al = 0.f, be = 0.f, grf32 = 0.f, gif32 = 0.f;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
@@ -172,6 +177,7 @@ __device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], float2
     const float grf = gr * sc, gif = gi * sc;
     const float gg = grf * grf + gif * gif;
     rot = gg >= 1e-36f && gg > (float)(JACOBI_TOL * JACOBI_TOL) * alf * bef;
+    moved = moved || gg > (float)(JACOBI_QSTOP * JACOBI_QSTOP) * alf * bef;
     const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));   // 1/|gamma|
     const float zeta = (bef - alf) * 0.5f * ig;
     const float az = fabsf(zeta);
@@ -199,7 +205,6 @@ __device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], float2
         xp[m] = np;
       }
     }
-    rotated = true;
   }
 }
 
@@ -221,7 +226,7 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
     if (threadIdx.x == 0) sm.nrot = 0;
     __syncthreads();
     ++sweeps;
-    bool rotated = false;
+    bool moved = false;
     // own pairs of blocks 2w (row groups 0, 1) and 2w + 1 (row groups 2, 3)
     if (wid < nw) {
       const int c0 = 4 * (2 * wid + (g >> 1)), m = g & 1;
@@ -243,7 +248,7 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
             xq[mm] = xqc[16 * mm];
           }
         }
-        jacobi_rotate<ACC>(zp, zq, xp, xq, true, rotated);
+        jacobi_rotate<ACC>(zp, zq, xp, xq, true, moved);
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
           zpc[16 * mm] = zp[mm];
@@ -280,7 +285,7 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
         const int up = (lane + 16) & 63;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          jacobi_rotate<ACC>(za, zb, xp, xq, true, rotated);   // column 4A + g with column 4B + (g + t) % 4
+          jacobi_rotate<ACC>(za, zb, xp, xq, true, moved);   // column 4A + g with column 4B + (g + t) % 4
 #pragma unroll
           for (int mm = 0; mm < 4; ++mm) {
             zb[mm] = make_float2(__shfl(zb[mm].x, up), __shfl(zb[mm].y, up));
@@ -300,7 +305,7 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
       rounds += 4;
       __syncthreads();
     }
-    if (rotated && li == 0) sm.nrot = 1;
+    if (moved && li == 0) sm.nrot = 1;
     __syncthreads();
     const bool done = (sm.nrot == 0);
     __syncthreads();
@@ -365,36 +370,30 @@ __device__ void pick_rank(Shared& sm, int K, int d, double Et, int* r_out, doubl
   __syncthreads();
 }
 
-// Gauss-Jordan with partial pivoting on the r x ldg FP64 system
-// aug = [C | M] (row-major), r <= WB_RMAX: afterwards row gjperm[j] holds row
-// j of C^-1 M in columns r .. ldg - 1.  Rows are never exchanged: step j
-// takes as pivot the not yet used row with the largest |aug[i, j]| (the
-// lowest such row), scales it and eliminates column j from every other row.
-// Half-wave h = 2 wid + (lane >> 5) holds columns h, h + 32, h + 64 in
-// registers, row lane & 31.  Half-wave j + 1 owns column j + 1: after the
-// barrier of step j it updates that column first, at raised wave priority,
-// and publishes the next pivot (row, 1 / pivot and the column) in the other
-// of two LDS slots before its remaining columns, so a step costs one
-// workgroup barrier and the serial part is one column update and one
-// half-wave maximum.  Returns false (every thread alike) if a pivot's squared
-// modulus is not above SING_TOL^2 or is not finite.
-__device__ bool gj_solve_small(Shared& sm, double2* aug, int r, int ldg) {
-  constexpr int SLOTS = (WB_RMAX + KS + 31) / 32;
+// In-place Gauss-Jordan inversion with partial pivoting of the r x r FP64
+// capacitance C held in columns 0 .. r - 1 of aug (row-major, ld ldg),
+// r <= WB_RMAX.  Rows are never exchanged: step j takes as pivot the not yet
+// used row p_j with the largest |C[i, j]| (the lowest such row).  Run on the
+// row-permuted matrix, the in-place steps leave S with S[p_j, c] =
+// C^-1[j, p_c]; S is written back over C and p_j to sm.gjperm[j].
+// Half-wave h = 2 wid + (lane >> 5) holds column h in registers, row
+// lane & 31.  Half-wave j + 1 owns the next pivot column: after the barrier
+// of step j it updates that column first, at raised wave priority, and
+// publishes the next pivot (row, 1 / pivot and the column) in the other of
+// two LDS slots, so a step costs one workgroup barrier.  Returns false
+// (every thread alike) if a pivot's squared modulus is not above SING_TOL^2
+// or is not finite.
+__device__ bool gj_invert_small(Shared& sm, double2* aug, int r, int ldg) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int row = lane & 31, hw = 2 * wid + (lane >> 5), base = lane & 32;
-  double2 x[SLOTS];
-#pragma unroll
-  for (int q = 0; q < SLOTS; ++q) {
-    const int c = hw + 32 * q;
-    x[q] = (c < ldg && row < r) ? aug[row * ldg + c] : dz();
-  }
+  double2 x = (hw < r && row < r) ? aug[row * ldg + hw] : dz();
   bool used = false;
-  // pivot of column j (slot 0 of half-wave j, the only active half of its
-  // wave here), published in slot j & 1
+  // pivot of column j (half-wave j, the only active half of its wave here),
+  // published in slot j & 1
   auto publish = [&](int j) {
     const int b = j & 1;
     const int hb = __builtin_amdgcn_readfirstlane(base);
-    const double mag = (!used && row < r) ? dabs2(x[0]) : -1.0;
+    const double mag = (!used && row < r) ? dabs2(x) : -1.0;
     double mx = mag;   // maximum over the 16-lane rows, then over the two rows
     mx = fmax(mx, dpp_d<DPP_QUAD_1032>(mx));
     mx = fmax(mx, dpp_d<DPP_QUAD_2301>(mx));
@@ -404,8 +403,8 @@ __device__ bool gj_solve_small(Shared& sm, double2* aug, int r, int ldg) {
     const unsigned int hit = (unsigned int)(__ballot(mag == mx) >> hb);
     const int pr = __ffs((int)hit) - 1;   // -1: NaN column, no maximum
     const int pu = pr < 0 ? 0 : pr;
-    const double2 p = lane_read(x[0], hb + pu);
-    if (row < r) sm.gjm[b][row] = x[0];
+    const double2 p = lane_read(x, hb + pu);
+    if (row < r) sm.gjm[b][row] = x;
     if (row == 0) {
       const bool sing = pr < 0 || !(mx > SING_TOL * SING_TOL) || !isfinite(mx);
       // 1 / |p|^2: hardware reciprocal and one Newton step
@@ -426,32 +425,25 @@ __device__ bool gj_solve_small(Shared& sm, double2* aug, int r, int ldg) {
     if (sm.gjsing[b]) { ok = false; break; }
     const int pr = __builtin_amdgcn_readfirstlane(sm.gjpr[b]);
     const double2 inv = sm.gjinv[b];
-    const double2 m = (row < r) ? sm.gjm[b][row] : dz();
+    const double2 m = (row < r) ? sm.gjm[b][row] : dz();   // column j before this step
     used = used || row == pr;
-    const bool owner = hw == j + 1 && j + 1 < r;
-    if (owner) {
+    if (hw == j + 1 && j + 1 < r) {
       __builtin_amdgcn_s_setprio(2);
-      const double2 u = dmul(lane_read(x[0], __builtin_amdgcn_readfirstlane(base) + pr), inv);
-      x[0] = (row == pr) ? u : dsub(x[0], dmul(m, u));
+      const double2 u = dmul(lane_read(x, __builtin_amdgcn_readfirstlane(base) + pr), inv);
+      x = (row == pr) ? u : dsub(x, dmul(m, u));
       publish(j + 1);
       __builtin_amdgcn_s_setprio(0);
-    }
-#pragma unroll
-    for (int q = 0; q < SLOTS; ++q) {
-      const int c = hw + 32 * q;
-      if (c > j && c < ldg && !(owner && q == 0)) {
-        const double2 u = dmul(lane_shfl(x[q], base + pr), inv);
-        x[q] = (row == pr) ? u : dsub(x[q], dmul(m, u));
-      }
-    }
-  }
-  if (ok) {
-#pragma unroll
-    for (int q = 0; q < SLOTS; ++q) {
-      const int c = hw + 32 * q;
-      if (c >= r && c < ldg && row < r) aug[row * ldg + c] = x[q];
+    } else if (hw == j) {
+      // the pivot column becomes column j of the inverse: 1 / pivot at the
+      // pivot row, -C[i, j] / pivot elsewhere
+      const double2 v = dmul(x, inv);
+      x = (row == pr) ? inv : make_double2(-v.x, -v.y);
+    } else if (hw < r) {
+      const double2 u = dmul(lane_shfl(x, base + pr), inv);
+      x = (row == pr) ? u : dsub(x, dmul(m, u));
     }
   }
+  if (ok && hw < r && row < r) aug[row * ldg + hw] = x;
   __syncthreads();
   return ok;
 }
@@ -852,8 +844,35 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       }
     }
     __syncthreads();
-    // step 3: Gauss-Jordan with partial pivoting on [C | V~^H A^-1]
-    const bool solved = gj_solve_small(sm, aug, r, ldg);
+    // step 3: C^-1 by Gauss-Jordan with partial pivoting, then
+    // X = C^-1 V~^H A^-1 = S_p M_p (S_p[a, c] = S[p_a, c], M_p[c, :] = M[p_c, :]
+    // for the M = V~^H A^-1 in columns r.. of aug), both in FP64; X replaces M
+    const bool solved = gj_invert_small(sm, aug, r, ldg);
+    if (solved) {
+      const int* pv = sm.gjperm;
+      const int xt = (r + 15) / 16, yt = (K + 15) / 16;
+      double2 acc[4] = {dz(), dz(), dz(), dz()};
+      const int ti = wid / yt, tj = wid - (wid / yt) * yt;
+      if (wid < xt * yt)
+        dtile16([&](int i, int c) {
+                  const int a = ti * 16 + i;
+                  return (a < r && c < r) ? aug[pv[a] * ldg + c] : dz();
+                },
+                [&](int c, int j) {
+                  const int jj = tj * 16 + j;
+                  return (c < r && jj < K) ? aug[pv[c] * ldg + r + jj] : dz();
+                },
+                0, r, acc);
+      __syncthreads();
+      if (wid < xt * yt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = ti * 16 + tile_row(v), j = tj * 16 + tile_col();
+          if (a < r && j < K) aug[a * ldg + r + j] = acc[v];
+        }
+      }
+      __syncthreads();
+    }
     if (!solved) {
       use_wb = false;
       path = RZF_PATH_FULL_SINGULAR;
@@ -862,7 +881,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       float2* out = td->Ainv;
       lds_gemm(K, K, r,
                [&](int i, int a) { return (i < K && a < r) ? tm[a * LDK + i] : cz(); },
-               [&](int a, int j) { return (a < r && j < K) ? d2f(aug[sm.gjperm[a] * ldg + r + j]) : cz(); },
+               [&](int a, int j) { return (a < r && j < K) ? d2f(aug[a * ldg + r + j]) : cz(); },
                [&](int i, int j, float2 v) { out[(size_t)i * K + j] = csub(b0[i * LDK + j], v); });
     }
     __syncthreads();

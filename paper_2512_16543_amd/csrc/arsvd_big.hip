@@ -33,6 +33,7 @@ constexpr int NTH = 1024;
 constexpr int NWV = NTH / 64;
 constexpr int MAX_SWEEPS = 30;      // Jacobi passes
 constexpr double JACOBI_TOL = 2e-6;
+constexpr double JACOBI_QSTOP = 1e-3;   // passes stop after one with no pair above it
 constexpr double SING_TOL = 1e-12;
 constexpr int JOB_ELEMS = KM * 32;  // LDS entries of one job matrix
 constexpr int GJ_W = 32;            // panel width of the capacitance solve
@@ -294,7 +295,10 @@ __device__ __forceinline__ float gsumf(float v) {
 // share in FP32 and the G shares are added in FP32 too (rounding error at
 // most about 13 x 2^-24 ||z_p|| ||z_q||, under half the rotation threshold);
 // every lane of the group forms the same bits, so the group applies one
-// rotation.  A pair already orthogonal to JACOBI_TOL is left alone.  Sets sm.nrot when it rotates.
+// rotation.  A pair already orthogonal to JACOBI_TOL is left alone.  Sets
+// sm.nrot when |z_p^H z_q| > JACOBI_QSTOP ||z_p|| ||z_q||: near convergence a
+// pass squares that measure, so after a pass with no such pair the next one
+// would rotate at the FP32 noise level only, and the passes stop.
 // Every lane of the wave calls it (act = false for an idle group).
 constexpr int JR = 8;   // rows per lane: G = 16 covers K <= 128, G = 32 K <= 256
 template <int G>
@@ -332,6 +336,7 @@ __device__ __forceinline__ void jacobi_pair(BigShared& sm, int K, int pp, int qq
     const float grf = gr * sc, gif = gi * sc;
     const float gg = grf * grf + gif * gif;
     rot = gg >= 1e-36f && gg > (float)(JACOBI_TOL * JACOBI_TOL) * alf * bef;
+    if (gg > (float)(JACOBI_QSTOP * JACOBI_QSTOP) * alf * bef && gl == 0) sm.nrot = 1;
     const float ig = __builtin_amdgcn_rsqf(fmaxf(gg, 1e-36f));
     const float zeta = (bef - alf) * 0.5f * ig;
     const float az = fabsf(zeta);
@@ -351,7 +356,6 @@ __device__ __forceinline__ void jacobi_pair(BigShared& sm, int K, int pp, int qq
       zb[pp * K + i] = csub(cscale(zp[m], c), cscale(zq2, s));
       zb[qq * K + i] = cadd(cscale(zp[m], s), cscale(zq2, c));
     }
-    if (gl == 0) sm.nrot = 1;
   }
 }
 
@@ -378,7 +382,7 @@ __device__ __forceinline__ void jacobi_sweep(BigShared& sm, int K, int c0, int n
 
 // One-sided Jacobi SVD of B = Z^H (Z rotated in place; the rotations are
 // not accumulated); every pass rotates each column pair once, and the passes
-// stop when one rotates nothing (or after MAX_SWEEPS).  A round pairs up to
+// stop after one with no pair above JACOBI_QSTOP (or after MAX_SWEEPS).  A round pairs up to
 // NTH / G columns; LDS holds NCMAX = 2 NTH / G columns (NCMAX K <= 2 JOB_ELEMS).
 //   d <= NCMAX: all d columns sit in LDS; a pass is one cyclic sweep.
 //   d > NCMAX: blocks of b = NCMAX/2 columns.  For each block A in turn,
