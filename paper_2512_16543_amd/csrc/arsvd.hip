@@ -22,16 +22,27 @@
 //   Sigma_r^-2 (three small matrix-core products, only when the step takes
 //   the Woodbury branch), so U_r Sigma_r V_r^H = sum_{j<=r} u_j z_j^H.
 //   After I_max failing iterations r = d and U_r Sigma_r V_r^H = Q Z^H.
+// Full width (d = K): Q is unitary, so B = Q^H Delta A has the singular
+// values of Delta A and Q U_hat its left singular vectors whatever Q is.
+//   Such an iteration takes as Q the track's basis from its previous
+//   full-width SVD (re-orthonormalised every POLISH_EVERY uses) instead of a
+//   fresh Householder Q, and the Jacobi sweeps rotate it along with Z: Q J
+//   is then U_hat itself, U_r its leading columns and the next step's start.
+//   Consecutive Delta A differ little, so about half the passes suffice.
 //
 // Single-track updates run the kernel in two launches (PH = 1, 2 below): the
 // iterations the previous step predicts are computed at once, one workgroup
-// each, and the second launch takes the first that decides.
+// each, and the second launch takes the first that decides.  The workgroup
+// of the first full-width iteration carries the whole step through when its
+// energy test passes (into a staging area), so that when the second launch
+// finds the earlier iterations failing it only commits those results.
 //
 // Woodbury (Sec. III-A, steps 1-5) in the equivalent scaled form with
 // U = [u_j] (orthonormal), V~ = [z_j] (V~ = V_r Sigma_r):
 //   P  = A^-1 U                (step 1)
 //   C  = I_r + V~^H P          (step 2; Sigma_r (Sigma_r^-1 + V_r^H A^-1 U_r))
-//   X  = C^-1 (V~^H A^-1)      (step 3, FP64 Gauss-Jordan with partial pivoting)
+//   X  = C^-1 (V~^H A^-1)      (step 3, FP64: Gauss-Jordan inversion with partial
+//                               pivoting, then the product)
 //   A^-1 <- A^-1 - P X         (steps 4-5)
 // C is nonsingular exactly when the capacitance of eq. (12) is; a pivot below
 // SING_TOL sends the step to direct inversion (path FULL_SINGULAR).
@@ -450,9 +461,12 @@ __device__ bool gj_invert_small(Shared& sm, double2* aug, int r, int ldg) {
 
 // PH = 0: the whole step (single track or batch).  Two-phase single-track
 // form: PH = 1, one workgroup per speculated iteration (blockIdx.x + 1) up to
-// the energy test, its Q, Z and ||Z||_F^2 written to jb.spec; PH = 2, the
-// decision over those iterations in order (continuing one by one if none
-// decides), then the SVD and the branch, exactly as PH = 0 computes them.
+// the energy test, its Q, Z and ||Z||_F^2 written to jb.spec (the first
+// full-width iteration, when it passes, goes on through the SVD and the
+// branch into the staging area instead); PH = 2, the decision over those
+// iterations in order (continuing one by one if none decides), then the SVD
+// and the branch, or the commit of the staged results, exactly as PH = 0
+// computes them.
 template <bool MANY, int PH>
 __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* many, int* err) {
   __shared__ Shared sm;
@@ -516,6 +530,33 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   const bool warm_ok = td->warm != 0;
   const bool polish = warm_ok && td->warm_age >= POLISH_EVERY;
   bool basis = false;   // the SVD ran at d = K and rotated b1 along with Z
+  // the first iteration whose sketch spans all K columns (0: none that the
+  // step can reach: past i_max, or after the early-fallback policy's end)
+  int kfull = 0;
+  {
+    int kk = k0;
+    for (int it = 1; it <= i_max; ++it) {
+      const int dd = min(kk + p, K);
+      if (dd == K) { kfull = it; break; }
+      if (td->early_fallback && dd > td->wb_limit) break;
+      kk = min(2 * kk, K);
+    }
+  }
+  // two-phase form: the first phase's workgroup of that iteration carries the
+  // step through (its results to the staging area) when the test passes there
+  const bool stage_ok = PH != 0 && kfull > 0 && kfull <= n_spec;
+  char* const stage = PH != 0 ? reinterpret_cast<char*>(jb.spec) + SPEC_STAGE_OFF : nullptr;
+  SpecStage* const st_h = reinterpret_cast<SpecStage*>(stage);
+  double* const st_sig2 = reinterpret_cast<double*>(stage + sizeof(SpecStage));
+  float2* const st_Ainv = reinterpret_cast<float2*>(stage + sizeof(SpecStage) + sizeof(double) * KS);
+  float2* const st_R = st_Ainv + KS * KS;
+  float2* const st_Xw = st_R + KS * KS;
+  // where the step's results go: the track, or the staging area
+  float2* o_Ainv = td->Ainv;
+  float2* o_R = td->Rfb;
+  float2* o_Xw = td->Xw;
+  double* o_sig2 = td->sig2;
+  bool staged = false;
   // one iteration of Alg. 1 up to the energy test: Omega, Y, Q (b1), Z (b2),
   // returning ||Z||_F^2
   auto sketch_iteration = [&](int itn, int d) -> double {
@@ -645,6 +686,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     t_qr += clock64() - c_mark; c_mark = clock64();
     return tot;
   };
+  int it0 = 1;
+  bool decided = false;
   if constexpr (PH == 1) {
     const int itn = blockIdx.x + 1;
     if (itn > n_spec) return;
@@ -652,18 +695,33 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     for (int m = 1; m < itn; ++m) kk = min(2 * kk, K);   // d depends on min(k0 + p, K) only
     const int dd = min(kk + p, K);
     const double tot = sketch_iteration(itn, dd);
-    float2* Qw = jb.spec + (size_t)(itn - 1) * 2 * KS * KS;
-    float2* Zw = Qw + KS * KS;
-    for (int e = tid; e < K * dd; e += NTH) {
-      const int j = e / K, i = e - j * K;
-      Qw[j * KS + i] = b1[j * LDK + i];
-      Zw[j * KS + i] = b2[j * LDK + i];
-    }
     if (tid == 0) reinterpret_cast<double*>(jb.spec + (size_t)2 * KS * KS * SPEC_MAX)[itn - 1] = tot;
-    return;
+    if (!(stage_ok && itn == kfull && tot >= Et)) {
+      float2* Qw = jb.spec + (size_t)(itn - 1) * 2 * KS * KS;
+      float2* Zw = Qw + KS * KS;
+      for (int e = tid; e < K * dd; e += NTH) {
+        const int j = e / K, i = e - j * K;
+        Qw[j * KS + i] = b1[j * LDK + i];
+        Zw[j * KS + i] = b2[j * LDK + i];
+      }
+      return;
+    }
+    // the full-width iteration passes the test: the step goes on here, as
+    // the second phase would take it from this iteration, into the staging area
+    staged = true;
+    o_Ainv = st_Ainv; o_R = st_R; o_Xw = st_Xw; o_sig2 = st_sig2;
+    if (tid == 0) st_h->err = 0;
+    iters = itn;
+    d = dd;
+    found = true;
+    basis = true;
+    c_mark = clock64();
+    jacobi_svd<true>(sm, K, d, &sweeps, &rounds);
+    t_jac += clock64() - c_mark; c_mark = clock64();
+    rotated = true;
+    pick_rank(sm, K, d, Et, &r, &captured, o_sig2);
+    decided = true;
   }
-  int it0 = 1;
-  bool decided = false;
   if constexpr (PH == 2) {
     const double* totw = reinterpret_cast<const double*>(jb.spec + (size_t)2 * KS * KS * SPEC_MAX);
     for (int it = 1; it <= n_spec; ++it) {
@@ -673,6 +731,28 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       const double tot = totw[it - 1];
       const bool hit = tot >= Et;
       if (hit || it == i_max || (td->early_fallback && d > td->wb_limit)) {
+        if (hit && stage_ok && it == kfull) {
+          // carried through by the first phase: commit its results
+          for (int e = tid; e < K * K; e += NTH) {
+            td->Ainv[e] = st_Ainv[e];
+            td->Xw[e] = st_Xw[e];
+            if (fb) td->Rfb[e] = st_R[e];
+          }
+          for (int e = tid; e < K; e += NTH) td->sig2[e] = st_sig2[e];
+          if (tid == 0) {
+            td->info = st_h->info;
+            if (jb.out) *jb.out = st_h->info;
+            td->last_r = st_h->info.r;
+            td->spec_hint = it;
+            td->warm = 1;
+            td->warm_age = st_h->warm_age;
+            for (int q = 0; q < 8; ++q) td->dbg[q] = st_h->dbg[q];
+            td->dbg[2] = qrcols;
+            td->nsig = st_h->nsig;
+            if (st_h->err) atomicCAS(err, 0, st_h->err);
+          }
+          return;
+        }
         const float2* Qw = jb.spec + (size_t)(it - 1) * 2 * KS * KS;
         const float2* Zw = Qw + KS * KS;
         for (int e = tid; e < K * d; e += NTH) {
@@ -689,7 +769,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
           else jacobi_svd<false>(sm, K, d, &sweeps, &rounds);
           t_jac += clock64() - c_mark; c_mark = clock64();
           rotated = true;
-          pick_rank(sm, K, d, Et, &r, &captured, td->sig2);
+          pick_rank(sm, K, d, Et, &r, &captured, o_sig2);
         } else {
           r = d;
           captured = tot;
@@ -713,7 +793,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
         else jacobi_svd<false>(sm, K, d, &sweeps, &rounds);
         t_jac += clock64() - c_mark; c_mark = clock64();
         rotated = true;
-        pick_rank(sm, K, d, Et, &r, &captured, td->sig2);
+        pick_rank(sm, K, d, Et, &r, &captured, o_sig2);
         break;
       }
       // after the last iteration, or (early-fallback policy) once d is past
@@ -742,7 +822,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     // Delta A, kept as the track's next full-width starting basis
     for (int e = tid; e < K * K; e += NTH) {
       const int j = e / K, i = e - j * K;
-      td->Xw[e] = b1[j * LDK + i];
+      o_Xw[e] = b1[j * LDK + i];
     }
   }
   if (rotated && use_wb && basis) {
@@ -780,7 +860,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   if (fb && use_wb) {
     // residual of the rank-r update: R = (Delta A + R) - U V~^H, read from b0
     // before the Woodbury step reuses it (a direct inversion clears R below)
-    float2* R = td->Rfb;
+    float2* R = o_R;
     const int* ord = sm.order;
     lds_gemm(K, K, r,
              [&](int i, int c) { return (i < K && c < r) ? Ub[c * LDK + i] : cz(); },
@@ -878,7 +958,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       path = RZF_PATH_FULL_SINGULAR;
     } else {
       // steps 4-5: A^-1 <- A^-1 - P X
-      float2* out = td->Ainv;
+      float2* out = o_Ainv;
       lds_gemm(K, K, r,
                [&](int i, int a) { return (i < K && a < r) ? tm[a * LDK + i] : cz(); },
                [&](int a, int j) { return (a < r && j < K) ? d2f(aug[a * ldg + r + j]) : cz(); },
@@ -889,7 +969,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   if (!use_wb) {
     // direct inversion of A' (FP32)
     if (fb)
-      for (int e = tid; e < K * K; e += NTH) td->Rfb[e] = cz();
+      for (int e = tid; e < K * K; e += NTH) o_R[e] = cz();
     if (tid == 0) sm.bad = 0;
     for (int e = tid; e < K * K; e += NTH) {
       const int i = e / K, j = e - i * K;
@@ -899,25 +979,39 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     gj_inverse_hpd_mfma(b0, K, LDK, b1, b1 + 16 * KS, b1 + 32 * KS, &sm.bad);
     for (int e = tid; e < K * K; e += NTH) {
       const int i = e / K, j = e - i * K;
-      td->Ainv[e] = b0[i * LDK + j];
+      o_Ainv[e] = b0[i * LDK + j];
     }
-    if (tid == 0 && sm.bad) atomicCAS(err, 0, sm.bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
+    if (tid == 0 && sm.bad) {
+      const int code = sm.bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD;
+      if (staged) st_h->err = code;
+      else atomicCAS(err, 0, code);
+    }
   }
   if (tid == 0) {
-    td->info.r = r; td->info.iters = iters; td->info.path = path; td->info.d = d;
-    td->info.dA_fro2 = E; td->info.captured = captured;
-    if (jb.out) *jb.out = td->info;
-    td->last_r = r;
-    td->spec_hint = iters;
-    if (basis) {
-      td->warm_age = (warm_ok && !polish) ? td->warm_age + 1 : 1;
-      td->warm = 1;
-    }
-    td->dbg[0] = sweeps; td->dbg[1] = rounds; td->dbg[2] = qrcols;
-    td->nsig = rotated ? d : 0;
+    DevInfo inf;
+    inf.r = r; inf.iters = iters; inf.path = path; inf.d = d;
+    inf.dA_fro2 = E; inf.captured = captured;
+    const int age = (warm_ok && !polish) ? td->warm_age + 1 : 1;
     t_wb = clock64() - c_mark;
-    td->dbg[3] = (int)t_sk; td->dbg[4] = (int)t_qr; td->dbg[5] = (int)t_jac; td->dbg[6] = (int)t_wb;
-    td->dbg[7] = (int)(wall_clock64() - r_begin);
+    int* dbg = staged ? st_h->dbg : td->dbg;
+    dbg[0] = sweeps; dbg[1] = rounds; dbg[2] = qrcols;
+    dbg[3] = (int)t_sk; dbg[4] = (int)t_qr; dbg[5] = (int)t_jac; dbg[6] = (int)t_wb;
+    dbg[7] = (int)(wall_clock64() - r_begin);
+    if (staged) {
+      st_h->info = inf;
+      st_h->warm_age = age;
+      st_h->nsig = d;
+    } else {
+      td->info = inf;
+      if (jb.out) *jb.out = inf;
+      td->last_r = r;
+      td->spec_hint = iters;
+      if (basis) {
+        td->warm_age = age;
+        td->warm = 1;
+      }
+      td->nsig = rotated ? d : 0;
+    }
     (void)c_begin;
   }
 }

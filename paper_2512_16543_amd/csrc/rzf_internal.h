@@ -91,9 +91,21 @@ struct ArsvdJob {
 };
 // Two-phase single-track form of the K <= KS arSVD kernel: up to SPEC_MAX
 // iterations of Alg. 1 are computed at once, one workgroup each, into
-// [SPEC_MAX][Q, Z][KS x KS] complex values followed by SPEC_MAX doubles.
+// [SPEC_MAX][Q, Z][KS x KS] complex values followed by SPEC_MAX doubles
+// (||Z||_F^2).  The workgroup of the first full-width iteration (d = K) also
+// carries the step through when its energy test passes, into a staging area
+// that the second phase copies to the track if that iteration decides:
+// SpecStage, sigma^2 (KS doubles), then A'^-1 and R (K x K, ld K, row-major)
+// and the rotated basis (K x K, ld K, column-major).
 #define SPEC_MAX 8
-#define SPEC_BYTES (sizeof(float2) * 2 * KS * KS * SPEC_MAX + sizeof(double) * SPEC_MAX)
+struct SpecStage {
+  DevInfo info;
+  int warm_age, nsig, err, pad_;
+  int dbg[8];
+};
+#define SPEC_STAGE_OFF (sizeof(float2) * 2 * KS * KS * SPEC_MAX + sizeof(double) * SPEC_MAX)
+#define SPEC_BYTES \
+  (SPEC_STAGE_OFF + sizeof(SpecStage) + sizeof(double) * KS + sizeof(float2) * 3 * KS * KS)
 struct PrecJob {
   const float2* H; const float2* X; float2* W; double* wpart; float2* Hcopy;
   int K, N, ldh, ldw;
