@@ -41,8 +41,9 @@
 // U = [u_j] (orthonormal), V~ = [z_j] (V~ = V_r Sigma_r):
 //   P  = A^-1 U                (step 1)
 //   C  = I_r + V~^H P          (step 2; Sigma_r (Sigma_r^-1 + V_r^H A^-1 U_r))
-//   X  = C^-1 (V~^H A^-1)      (step 3, FP64: Gauss-Jordan inversion with partial
-//                               pivoting, then the product)
+//   X  = C^-1 (V~^H A^-1)      (step 3, FP64: passes X <- M - E X when C = I + E is
+//                               close to I, else Gauss-Jordan inversion with
+//                               partial pivoting and the product)
 //   A^-1 <- A^-1 - P X         (steps 4-5)
 // C is nonsingular exactly when the capacitance of eq. (12) is; a pivot below
 // SING_TOL sends the step to direct inversion (path FULL_SINGULAR).
@@ -61,6 +62,41 @@ constexpr int MAX_SWEEPS = 30;
 // a track's full-width basis is re-orthonormalised (one Newton-Schulz step)
 // before its use once it has taken this many SVDs' rotations
 constexpr int POLISH_EVERY = 8;
+// capacitance C = I + E: with ||E||_F <= NEUMANN_MAX the system C X = M is
+// solved by X <- M - E X, the error shrinking by ||E||_F per pass, until it
+// is below 2^-NEUMANN_BITS of X (under the FP32 rounding X then takes),
+// else by Gauss-Jordan with partial pivoting
+constexpr double NEUMANN_MAX = 0.25;
+constexpr int NEUMANN_BITS = 30;
+
+// acc[v] -= sum_{k < kn} E[row(v), k] X[k, col] for one 16 x 16 tile (rows
+// row0 + tile_row(v), columns col0 + tile_col()) of FP64 complex matrices in
+// LDS.  The loads are not bounds-checked: rows past the matrix read other
+// LDS words, and only the in-range results are kept.  Two k at a time, so
+// that ten loads are in flight together.
+__device__ __forceinline__ void dtile16_neg(const double2* E, int lde, const double2* X, int ldx, int row0,
+                                           int col0, int kn, double2 acc[4]) {
+  const int lane = threadIdx.x & 63;
+  const double2* er = E + (size_t)(row0 + 4 * (lane >> 4)) * lde;
+  const double2* xc = X + col0 + (lane & 15);
+  int k = 0;
+  for (; k + 2 <= kn; k += 2) {
+    const double2 b0 = xc[k * ldx], b1 = xc[(k + 1) * ldx];
+    double2 a0[4], a1[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      a0[v] = er[v * lde + k];
+      a1[v] = er[v * lde + k + 1];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = dsub(dsub(acc[v], dmul(a0[v], b0)), dmul(a1[v], b1));
+  }
+  if (k < kn) {
+    const double2 b0 = xc[k * ldx];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = dsub(acc[v], dmul(er[v * lde + k], b0));
+  }
+}
 static_assert(2 * WB_RMAX >= KS, "pm and tm together hold a K x K matrix");
 constexpr double JACOBI_TOL = 2e-6;
 // passes stop after one whose largest |z_p^H z_q| / (||z_p|| ||z_q||) is below
@@ -429,31 +465,34 @@ __device__ bool gj_invert_small(Shared& sm, double2* aug, int r, int ldg) {
     }
   };
   if (hw == 0) publish(0);
-  bool ok = true;
+  bool sing = false;
   for (int j = 0; j < r; ++j) {
     __syncthreads();
     const int b = j & 1;
-    if (sm.gjsing[b]) { ok = false; break; }
+    // the published step (a singular pivot only spoils values that are then
+    // discarded, so it is checked once, after the loop)
+    sing = sing || sm.gjsing[b] != 0;
     const int pr = __builtin_amdgcn_readfirstlane(sm.gjpr[b]);
     const double2 inv = sm.gjinv[b];
     const double2 m = (row < r) ? sm.gjm[b][row] : dz();   // column j before this step
     used = used || row == pr;
-    if (hw == j + 1 && j + 1 < r) {
-      __builtin_amdgcn_s_setprio(2);
-      const double2 u = dmul(lane_read(x, __builtin_amdgcn_readfirstlane(base) + pr), inv);
-      x = (row == pr) ? u : dsub(x, dmul(m, u));
-      publish(j + 1);
-      __builtin_amdgcn_s_setprio(0);
-    } else if (hw == j) {
+    const bool owner_wave = wid == ((j + 1) >> 1) && j + 1 < r;
+    if (owner_wave) __builtin_amdgcn_s_setprio(2);
+    if (hw == j) {
       // the pivot column becomes column j of the inverse: 1 / pivot at the
       // pivot row, -C[i, j] / pivot elsewhere
-      const double2 v = dmul(x, inv);
+      const double2 v = dmul(m, inv);
       x = (row == pr) ? inv : make_double2(-v.x, -v.y);
     } else if (hw < r) {
-      const double2 u = dmul(lane_shfl(x, base + pr), inv);
+      // this column's pivot-row entry, read from this half-wave's lanes
+      const double2 lo = lane_read(x, pr), hi = lane_read(x, 32 + pr);
+      const double2 u = dmul(base ? hi : lo, inv);
       x = (row == pr) ? u : dsub(x, dmul(m, u));
     }
+    if (hw == j + 1 && j + 1 < r) publish(j + 1);
+    if (owner_wave) __builtin_amdgcn_s_setprio(0);
   }
+  const bool ok = !sing;
   if (ok && hw < r && row < r) aug[row * ldg + hw] = x;
   __syncthreads();
   return ok;
@@ -924,34 +963,74 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       }
     }
     __syncthreads();
-    // step 3: C^-1 by Gauss-Jordan with partial pivoting, then
-    // X = C^-1 V~^H A^-1 = S_p M_p (S_p[a, c] = S[p_a, c], M_p[c, :] = M[p_c, :]
-    // for the M = V~^H A^-1 in columns r.. of aug), both in FP64; X replaces M
-    const bool solved = gj_invert_small(sm, aug, r, ldg);
-    if (solved) {
-      const int* pv = sm.gjperm;
-      const int xt = (r + 15) / 16, yt = (K + 15) / 16;
-      double2 acc[4] = {dz(), dz(), dz(), dz()};
-      const int ti = wid / yt, tj = wid - (wid / yt) * yt;
-      if (wid < xt * yt)
-        dtile16([&](int i, int c) {
-                  const int a = ti * 16 + i;
-                  return (a < r && c < r) ? aug[pv[a] * ldg + c] : dz();
-                },
-                [&](int c, int j) {
-                  const int jj = tj * 16 + j;
-                  return (c < r && jj < K) ? aug[pv[c] * ldg + r + jj] : dz();
-                },
-                0, r, acc);
-      __syncthreads();
-      if (wid < xt * yt) {
+    // step 3: X = C^-1 V~^H A^-1 in FP64 (M = V~^H A^-1 in columns r.. of
+    // aug; X replaces it).  C = I + E with E = V~^H A^-1 U, and
+    // ||E|| <= ||Delta A_r|| ||A^-1||, small for a small update: then X <- M - E X
+    // from X = M (the error shrinks by ||E||_F per pass, to FP64 rounding);
+    // otherwise C^-1 by Gauss-Jordan with partial pivoting, then
+    // X = C^-1 M = S_p M_p (S_p[a, c] = S[p_a, c], M_p[c, :] = M[p_c, :]).
+    double e2 = 0.0;
+    for (int e = tid; e < r * r; e += NTH) {
+      const int a = e / r, c = e - a * r;
+      const double2 v = aug[a * ldg + c];
+      const double re = v.x - (a == c ? 1.0 : 0.0);
+      e2 += re * re + v.y * v.y;
+    }
+    const double eps2 = block_sum(e2, sm.red);
+    const int xt = (r + 15) / 16, yt = (K + 15) / 16;
+    const int ti = wid / yt, tj = wid - (wid / yt) * yt;
+    const bool xtile = wid < xt * yt;   // one 16 x 16 tile of X per wave
+    bool solved;
+    if (eps2 <= NEUMANN_MAX * NEUMANN_MAX) {
+      // passes for ||E||_F^n <= 2^-NEUMANN_BITS (at most 15 at ||E||_F = 1/4)
+      const int nit = eps2 > 0.0 ? (int)ceil(-NEUMANN_BITS * 0.6931471805599453 / (0.5 * log(eps2))) : 1;
+      double2 mreg[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = ti * 16 + tile_row(v), j = tj * 16 + tile_col();
-          if (a < r && j < K) aug[a * ldg + r + j] = acc[v];
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int a = ti * 16 + tile_row(v), j = tj * 16 + tile_col();
+        mreg[v] = (xtile && a < r && j < K) ? aug[a * ldg + r + j] : dz();
       }
+      for (int a = tid; a < r; a += NTH) aug[a * ldg + a].x -= 1.0;   // C -> E
       __syncthreads();
+      for (int it = 0; it < nit; ++it) {
+        double2 acc[4] = {mreg[0], mreg[1], mreg[2], mreg[3]};
+        if (xtile) dtile16_neg(aug, ldg, aug + r, ldg, ti * 16, tj * 16, r, acc);
+        __syncthreads();
+        if (xtile) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int a = ti * 16 + tile_row(v), j = tj * 16 + tile_col();
+            if (a < r && j < K) aug[a * ldg + r + j] = acc[v];
+          }
+        }
+        __syncthreads();
+      }
+      solved = true;
+    } else {
+      solved = gj_invert_small(sm, aug, r, ldg);
+      if (solved) {
+        const int* pv = sm.gjperm;
+        double2 acc[4] = {dz(), dz(), dz(), dz()};
+        if (xtile)
+          dtile16([&](int i, int c) {
+                    const int a = ti * 16 + i;
+                    return (a < r && c < r) ? aug[pv[a] * ldg + c] : dz();
+                  },
+                  [&](int c, int j) {
+                    const int jj = tj * 16 + j;
+                    return (c < r && jj < K) ? aug[pv[c] * ldg + r + jj] : dz();
+                  },
+                  0, r, acc);
+        __syncthreads();
+        if (xtile) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int a = ti * 16 + tile_row(v), j = tj * 16 + tile_col();
+            if (a < r && j < K) aug[a * ldg + r + j] = acc[v];
+          }
+        }
+        __syncthreads();
+      }
     }
     if (!solved) {
       use_wb = false;

@@ -337,6 +337,25 @@ def test_update_full_rank_woodbury_is_exact_inverse(ctx):
     tr.destroy()
 
 
+@pytest.mark.parametrize("scale", [0.02, 0.3])
+def test_update_capacitance_solvers(ctx, scale):
+    # a rank-1 change of H (rank-2 Delta A, so the Woodbury branch): at scale
+    # 0.02 the capacitance C = I + E has ||E||_F ~ 0.04 and X = C^-1 M comes
+    # from the passes X <- M - E X; at 0.3, ||E||_F ~ 1.4 takes the pivoted
+    # Gauss-Jordan inversion.  ||E||_F is checked here from the FP64 SVD.
+    K, N, alpha = 16, 48, 0.5
+    H0 = _channel(K, N, 21)
+    H1 = c64(wl.perturbed_channel(H0, 7, 1, scale)).astype(np.complex128)
+    dA = orz.gram(H1, alpha) - orz.gram(H0, alpha)
+    U, s, Vh = np.linalg.svd(dA)
+    E = (s[:2, None] * Vh[:2]) @ np.linalg.inv(orz.gram(H0, alpha)) @ U[:, :2]
+    assert (np.linalg.norm(E) < 0.25) == (scale < 0.1)
+    d = dict(k_init=2, p=5, P=1.0, seed=5, track_id=0, reset_period=0)
+    recs = run_snapshots(ctx, np.stack([H0, H1, H0]), alpha, d, 0.999)
+    _assert_recs(recs)
+    assert all(r["path"] == orz.PATH_WB and r["r"] == 2 for r in recs), recs
+
+
 def test_update_noop_for_static_channel(ctx):
     cfg = wl.CONFIGS["c1"]
     H = c64(wl.make_track(cfg).snapshot(0)).astype(np.complex128)
