@@ -166,6 +166,7 @@ void arsvd_single(rzf_ctx* c, ArsvdJob j, int K, hipStream_t s) {
     launch_arsvd_big(j, nullptr, 1, c->d_err, s);
   } else {
     j.spec = c->d_spec;
+    j.stage = reinterpret_cast<char*>(c->d_spec) + SPEC_STAGE_OFF;
     launch_arsvd_wb_spec(j, c->d_err, s);
   }
 }

@@ -523,17 +523,30 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   // launch (the products and reflectors only write rows < K), which the
   // Jacobi sweeps rely on
   for (int e = tid; e < KS * LDK; e += NTH) b2[e] = cz();
-  // Delta A -> LDS, E = ||Delta A||_F^2 in FP64
-  double part = 0.0;
+  // Delta A -> LDS, returning E = ||Delta A||_F^2 in FP64 (every thread)
   const bool fb = td->error_feedback != 0;   // sketch Delta A + R
-  for (int e = tid; e < K * K; e += NTH) {
-    const int i = e / K, j = e - i * K;
-    float2 v = td->dA[e];
-    if (fb) v = cadd(v, td->Rfb[e]);
-    b0[i * LDK + j] = v;
-    part += (double)v.x * v.x + (double)v.y * v.y;
+  auto load_dA = [&]() -> double {
+    double part = 0.0;
+    for (int e = tid; e < K * K; e += NTH) {
+      const int i = e / K, j = e - i * K;
+      float2 v = td->dA[e];
+      if (fb) v = cadd(v, td->Rfb[e]);
+      b0[i * LDK + j] = v;
+      part += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    return block_sum(part, sm.red);
+  };
+  // the second phase takes E from the first (the same sum of the same
+  // values) and loads Delta A only when it goes on past a commit
+  double* const spec_d = PH == 0 ? nullptr : reinterpret_cast<double*>(jb.spec + (size_t)2 * KS * KS * SPEC_MAX);
+  bool dA_in = PH != 2;
+  double E;
+  if constexpr (PH == 2) {
+    E = spec_d[SPEC_MAX];
+  } else {
+    E = load_dA();
+    if (PH == 1 && blockIdx.x == 0 && tid == 0) spec_d[SPEC_MAX] = E;
   }
-  const double E = block_sum(part, sm.red);
   if (!isfinite(E) || E == 0.0) {
     if (PH == 1) return;                     // the second phase records the step
     if (fb && E == 0.0)                      // nothing to apply: the residual is zero
@@ -583,13 +596,13 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   }
   // two-phase form: the first phase's workgroup of that iteration carries the
   // step through (its results to the staging area) when the test passes there
-  const bool stage_ok = PH != 0 && kfull > 0 && kfull <= n_spec;
-  char* const stage = PH != 0 ? reinterpret_cast<char*>(jb.spec) + SPEC_STAGE_OFF : nullptr;
+  const bool stage_ok = PH != 0 && kfull > 0 && kfull <= n_spec && jb.stage != nullptr;
+  char* const stage = stage_ok ? jb.stage : nullptr;
   SpecStage* const st_h = reinterpret_cast<SpecStage*>(stage);
   double* const st_sig2 = reinterpret_cast<double*>(stage + sizeof(SpecStage));
   float2* const st_Ainv = reinterpret_cast<float2*>(stage + sizeof(SpecStage) + sizeof(double) * KS);
-  float2* const st_R = st_Ainv + KS * KS;
-  float2* const st_Xw = st_R + KS * KS;
+  float2* const st_R = st_Ainv + K * K;
+  float2* const st_Xw = st_R + K * K;
   // where the step's results go: the track, or the staging area
   float2* o_Ainv = td->Ainv;
   float2* o_R = td->Rfb;
@@ -725,6 +738,28 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     t_qr += clock64() - c_mark; c_mark = clock64();
     return tot;
   };
+  // the first phase carried the full-width iteration `it` through: copy its
+  // results to the track
+  auto commit_stage = [&](int it) {
+    for (int e = tid; e < K * K; e += NTH) {
+      td->Ainv[e] = st_Ainv[e];
+      td->Xw[e] = st_Xw[e];
+      if (fb) td->Rfb[e] = st_R[e];
+    }
+    for (int e = tid; e < K; e += NTH) td->sig2[e] = st_sig2[e];
+    if (tid == 0) {
+      td->info = st_h->info;
+      if (jb.out) *jb.out = st_h->info;
+      td->last_r = st_h->info.r;
+      td->spec_hint = it;
+      td->warm = 1;
+      td->warm_age = st_h->warm_age;
+      for (int q = 0; q < 8; ++q) td->dbg[q] = st_h->dbg[q];
+      td->dbg[2] = qrcols;
+      td->nsig = st_h->nsig;
+      if (st_h->err) atomicCAS(err, 0, st_h->err);
+    }
+  };
   int it0 = 1;
   bool decided = false;
   if constexpr (PH == 1) {
@@ -771,26 +806,12 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       const bool hit = tot >= Et;
       if (hit || it == i_max || (td->early_fallback && d > td->wb_limit)) {
         if (hit && stage_ok && it == kfull) {
-          // carried through by the first phase: commit its results
-          for (int e = tid; e < K * K; e += NTH) {
-            td->Ainv[e] = st_Ainv[e];
-            td->Xw[e] = st_Xw[e];
-            if (fb) td->Rfb[e] = st_R[e];
-          }
-          for (int e = tid; e < K; e += NTH) td->sig2[e] = st_sig2[e];
-          if (tid == 0) {
-            td->info = st_h->info;
-            if (jb.out) *jb.out = st_h->info;
-            td->last_r = st_h->info.r;
-            td->spec_hint = it;
-            td->warm = 1;
-            td->warm_age = st_h->warm_age;
-            for (int q = 0; q < 8; ++q) td->dbg[q] = st_h->dbg[q];
-            td->dbg[2] = qrcols;
-            td->nsig = st_h->nsig;
-            if (st_h->err) atomicCAS(err, 0, st_h->err);
-          }
+          commit_stage(it);
           return;
+        }
+        if (!dA_in) {
+          load_dA();
+          dA_in = true;
         }
         const float2* Qw = jb.spec + (size_t)(it - 1) * 2 * KS * KS;
         const float2* Zw = Qw + KS * KS;
@@ -821,6 +842,10 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     it0 = n_spec + 1;
   }
   if (!decided) {
+    if (!dA_in) {
+      load_dA();
+      dA_in = true;
+    }
     for (int it = it0; it <= i_max; ++it) {
       iters = it;
       d = min(k0 + p, K);

@@ -88,24 +88,27 @@ struct ArsvdJob {
   double eta;
   int t, i_max;
   float2* spec;    // speculative-iteration workspace (SPEC_BYTES), two-phase single-track form only
+  char* stage;     // staging area of the job's full-width step (two-phase form), or null
 };
 // Two-phase single-track form of the K <= KS arSVD kernel: up to SPEC_MAX
 // iterations of Alg. 1 are computed at once, one workgroup each, into
 // [SPEC_MAX][Q, Z][KS x KS] complex values followed by SPEC_MAX doubles
-// (||Z||_F^2).  The workgroup of the first full-width iteration (d = K) also
+// (||Z||_F^2) and one more (||Delta A||_F^2).  The workgroup of the first full-width iteration (d = K) also
 // carries the step through when its energy test passes, into a staging area
-// that the second phase copies to the track if that iteration decides:
-// SpecStage, sigma^2 (KS doubles), then A'^-1 and R (K x K, ld K, row-major)
-// and the rotated basis (K x K, ld K, column-major).
+// (after those doubles) that the second phase copies to the track if that
+// iteration decides: SpecStage, sigma^2 (KS doubles), then A'^-1 and R
+// (K x K, ld K, row-major) and the rotated basis (K x K, ld K, column-major).
 #define SPEC_MAX 8
 struct SpecStage {
   DevInfo info;
   int warm_age, nsig, err, pad_;
   int dbg[8];
 };
-#define SPEC_STAGE_OFF (sizeof(float2) * 2 * KS * KS * SPEC_MAX + sizeof(double) * SPEC_MAX)
-#define SPEC_BYTES \
-  (SPEC_STAGE_OFF + sizeof(SpecStage) + sizeof(double) * KS + sizeof(float2) * 3 * KS * KS)
+inline constexpr size_t stage_bytes(int K) {
+  return (sizeof(SpecStage) + sizeof(double) * KS + sizeof(float2) * 3 * (size_t)K * K + 255) & ~size_t(255);
+}
+#define SPEC_STAGE_OFF (sizeof(float2) * 2 * KS * KS * SPEC_MAX + sizeof(double) * (SPEC_MAX + 1))
+#define SPEC_BYTES (SPEC_STAGE_OFF + stage_bytes(KS))
 struct PrecJob {
   const float2* H; const float2* X; float2* W; double* wpart; float2* Hcopy;
   int K, N, ldh, ldw;
