@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-switch", action="store_true",
+                    help="Alg. 2's switch ratio from rzf_tune_switch (measured costs) instead of 0.5")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--batch-tracks", type=int, default=512,
                     help="independent tracks of the same configuration in the batched pass (0: skip)")
@@ -159,11 +161,17 @@ def main():
     ctx = rzf.Context(0, 64 << 20)
     policy = rzf.KINIT_WARM if a.policy == "warm" else rzf.KINIT_FIXED
 
+    tuned = ctx.tune_switch(K, N, PRECISIONS[a.precision]) if a.tune_switch else None
+    switch_ratio = tuned["switch_ratio"] if tuned else 0.5
+    if tuned and switch_ratio <= 0.0:
+        switch_ratio = 0.5 / K   # the Woodbury branch never pays: every rank inverts
+
     def params(track_id):
         return rzf.default_params(k_init=cfg.k_init, p=cfg.p, P=cfg.P, seed=cfg.seed,
                                   track_id=track_id, reset_period=cfg.reset_period,
                                   kinit_policy=policy, early_fallback=int(a.early_fallback),
-                                  precision=PRECISIONS[a.precision], error_feedback=int(a.error_feedback))
+                                  precision=PRECISIONS[a.precision], error_feedback=int(a.error_feedback),
+                                  switch_ratio=switch_ratio)
 
     def run_wb(H, steps, track_id, want_info=False, per_step_sync=False):
         tr = ctx.init(H[0], cfg.alpha, params(track_id))
@@ -241,6 +249,7 @@ def main():
                          f"{', error feedback' if a.error_feedback else ''}; "
                          f"step = update + sum rate, batch of 1 track"),
             "K": K, "N": N, "eta": eta, "batch_tracks": 1, "reset_period": cfg.reset_period,
+            "switch_ratio": switch_ratio,
         },
         "full_inverse": {"value": K_steps / full_s, "unit": "updates/s",
                          "ms_per_step": 1e3 * full_s / K_steps},
@@ -316,10 +325,12 @@ def main():
         out["batched"] = batched(a, [cfg] * a.batch_tracks, eta, policy)
         print(f"[bench] batched pass done", file=sys.stderr, flush=True)
 
+    if tuned:
+        out["switch_tuning"] = tuned   # rzf_tune_switch's fit (cycles after the SVD)
     # FP64 CPU oracle on a bounded sample of the same track
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, eta, Hs_np, a.cpu_seconds, policy, int(a.early_fallback),
-                                           int(a.error_feedback))
+                                           int(a.error_feedback), switch_ratio)
         print(f"[bench] cpu baseline done", file=sys.stderr, flush=True)
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -694,7 +705,7 @@ def table_v(a):
             "rows": rows}
 
 
-def cpu_baseline(cfg, eta, Hs_np, budget_s, policy, early_fallback=0, error_feedback=0):
+def cpu_baseline(cfg, eta, Hs_np, budget_s, policy, early_fallback=0, error_feedback=0, switch_ratio=0.5):
     import numpy as np
     import oracle.rzf as orz
     try:
@@ -706,7 +717,7 @@ def cpu_baseline(cfg, eta, Hs_np, budget_s, policy, early_fallback=0, error_feed
     prm = orz.TrackParams(alpha=cfg.alpha, P=cfg.P, k_init=cfg.k_init, p=cfg.p,
                           reset_period=cfg.reset_period, seed=cfg.seed, track_id=0,
                           kinit_policy=policy, early_fallback=early_fallback,
-                          error_feedback=error_feedback)
+                          error_feedback=error_feedback, switch_ratio=switch_ratio)
     ot = orz.OracleTrack(H[0], prm)
     t0 = time.perf_counter()
     n = 0

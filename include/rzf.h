@@ -254,6 +254,23 @@ rzf_status rzf_sum_rate_batch(rzf_ctx* ctx, int n, const rzf_rate_item* items, d
 rzf_status rzf_beamspace(rzf_ctx* ctx, int K, int nx, int ny, const rzf_c32* H, int ldh, int n_rf,
                          int select, int* beams, rzf_c32* H_eff, int ld_eff);
 
+/* Adaptive Woodbury / direct-inversion breakpoint (the paper's future-work
+ * item of choosing Alg. 2's switch from measured costs instead of 0.5).
+ * Times, on this context's device, the part of an update that follows the
+ * SVD (the rank rule and then Alg. 2's branch, from the kernel's cycle
+ * counters) for a K x N track with the given precision: the direct inversion
+ * once, and the Woodbury update at several ranks r (synthetic channels whose
+ * small change gives Delta A rank r, eta = 1 - 1e-4; the capacitance then
+ * takes the X <- M - E X passes, as for a slowly varying channel).  The Woodbury cost is fitted as
+ * a + b r; *switch_ratio is the largest r/K (r a whole number) at which it is
+ * not above the direct inversion's, 0 if none, capped at the Woodbury
+ * workspace (max(32, K/2) ranks).  Use it as rzf_params.switch_ratio.
+ * Optional outputs: *direct_cycles, *wb_cycles_a and *wb_cycles_b (the fit).
+ * Synchronous; uses temporary tracks and 3 K N complex values of the arena.
+ * 2 <= K <= RZF_KMAX, K <= N <= RZF_NMAX. */
+rzf_status rzf_tune_switch(rzf_ctx* ctx, int K, int N, int precision, double* switch_ratio,
+                           double* direct_cycles, double* wb_cycles_a, double* wb_cycles_b);
+
 /* Copy the track's stored inverse (K x K, row-major, ld = K) to device memory
  * Ainv.  Asynchronous. */
 rzf_status rzf_get_inverse(rzf_track* tr, rzf_c32* Ainv);

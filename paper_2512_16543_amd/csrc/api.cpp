@@ -810,6 +810,135 @@ rzf_status rzf_sum_rate(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, con
   return RZF_OK;
 }
 
+rzf_status rzf_tune_switch(rzf_ctx* c, int K, int N, int precision, double* switch_ratio,
+                           double* direct_cycles, double* wb_cycles_a, double* wb_cycles_b) {
+  if (!c || !switch_ratio || K < 2 || K > RZF_KMAX || N < K || N > RZF_NMAX ||
+      precision < RZF_PREC_FP32 || precision > RZF_PREC_BF16X3)
+    return RZF_E_INVALID;
+  const size_t kn = (size_t)K * N;
+  // synthetic inputs from a fixed 64-bit LCG: H0 with entries uniform in
+  // [-1/2, 1/2)^2, and per rank m the change X Y^H / 1000 (X K x m, Y N x m),
+  // with alpha = 100: a small change, so that ||V~^H A^-1 U|| stays well
+  // below 1/4 and the Woodbury step solves its capacitance by the passes, as
+  // on a slowly varying channel.  eta = 1 - 1e-4 keeps the 2m components of
+  // Delta A (their energy is known to FP32 accuracy, about 1e-6 relative)
+  // and none of those of the FP32 rounding of H1 (about 1e-8 of the energy)
+  uint64_t rs = 0x2545F4914F6CDD1Dull;
+  auto unif = [&rs]() {
+    rs = rs * 6364136223846793005ull + 1442695040888963407ull;
+    return (double)(rs >> 11) * 0x1.0p-53 - 0.5;
+  };
+  std::vector<rzf_c32> h0(kn), h1(kn);
+  for (rzf_c32& v : h0) {
+    v.re = (float)unif();
+    v.im = (float)unif();
+  }
+  size_t off = 0;
+  const size_t bytes = align_up(sizeof(rzf_c32) * 3 * kn);
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!arena_alloc(c, bytes, &off)) return RZF_E_NOMEM;
+  }
+  rzf_c32* dH0 = reinterpret_cast<rzf_c32*>(c->arena + off);
+  rzf_c32* dH1 = dH0 + kn;
+  rzf_c32* dW = dH1 + kn;   // N x K
+  rzf_status st = RZF_OK;
+  // cycles after the SVD of one update H0 -> H1 (fresh track, d = K at the
+  // first iteration), the least of three runs; the rank and path it took
+  auto measure = [&](double ratio, double* cyc, int* r_out, int* path_out) -> rzf_status {
+    rzf_params prm;
+    rzf_params_default(&prm);
+    prm.k_init = K;
+    prm.p = 0;
+    prm.switch_ratio = ratio;
+    prm.precision = precision;
+    double best = 0.0;
+    for (int rep = 0; rep < 3; ++rep) {
+      rzf_track* t = nullptr;
+      rzf_status s1 = rzf_init(c, K, N, dH0, N, 100.0, &prm, &t);
+      if (s1 != RZF_OK) return s1;
+      rzf_update_info info;
+      s1 = rzf_update(t, dH1, N, 1.0 - 1e-4, dW, K, &info);
+      if (s1 == RZF_OK) s1 = rzf_sync(c);
+      int v[8] = {0};
+      if (s1 == RZF_OK) s1 = rzf_debug_counters(t, v, 8);
+      rzf_track_destroy(t);
+      if (s1 != RZF_OK) return s1;
+      const double cy = (double)(unsigned)v[6];
+      if (rep == 0 || cy < best) best = cy;
+      *r_out = info.r;
+      *path_out = info.path;
+    }
+    *cyc = best;
+    return RZF_OK;
+  };
+  auto set_change = [&](int m) -> rzf_status {
+    std::vector<rzf_c32> X((size_t)K * m), Y((size_t)N * m);
+    for (rzf_c32& v : X) { v.re = (float)unif(); v.im = (float)unif(); }
+    for (rzf_c32& v : Y) { v.re = (float)unif(); v.im = (float)unif(); }
+    for (int i = 0; i < K; ++i)
+      for (int n = 0; n < N; ++n) {
+        double re = h0[(size_t)i * N + n].re, im = h0[(size_t)i * N + n].im;
+        for (int q = 0; q < m; ++q) {   // + X[i, q] conj(Y[n, q]) / 1000
+          const rzf_c32 x = X[(size_t)i * m + q], y = Y[(size_t)n * m + q];
+          re += 1e-3 * ((double)x.re * y.re + (double)x.im * y.im);
+          im += 1e-3 * ((double)x.im * y.re - (double)x.re * y.im);
+        }
+        h1[(size_t)i * N + n].re = (float)re;
+        h1[(size_t)i * N + n].im = (float)im;
+      }
+    if (hipSetDevice(c->device) != hipSuccess ||
+        hipMemcpy(dH1, h1.data(), sizeof(rzf_c32) * kn, hipMemcpyHostToDevice) != hipSuccess)
+      return RZF_E_DEVICE;
+    return RZF_OK;
+  };
+  const int cap = std::min(K, std::max(WB_RMAX, K / 2));   // Woodbury workspace
+  std::vector<double> rr, cc;
+  double direct = 0.0;
+  int r = 0, path = 0;
+  if (hipSetDevice(c->device) != hipSuccess ||
+      hipMemcpy(dH0, h0.data(), sizeof(rzf_c32) * kn, hipMemcpyHostToDevice) != hipSuccess)
+    st = RZF_E_DEVICE;
+  // the direct inversion (switch below 1/K: every rank inverts), at the largest change
+  if (st == RZF_OK) st = set_change(std::max(1, cap / 2));
+  if (st == RZF_OK) st = measure(0.5 / K, &direct, &r, &path);
+  if (st == RZF_OK && path != RZF_PATH_FULL_RANK) st = RZF_E_DEVICE;
+  // the Woodbury branch at change ranks m (Delta A of rank 2m)
+  for (int m = 1; st == RZF_OK && 2 * m <= cap; m = (m < 4) ? 2 * m : m + 4) {
+    st = set_change(m);
+    double cy = 0.0;
+    if (st == RZF_OK) st = measure(1.0, &cy, &r, &path);
+    if (st == RZF_OK && path == RZF_PATH_WB && r > 0) {
+      rr.push_back(r);
+      cc.push_back(cy);
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) st = RZF_E_DEVICE;
+    arena_free(c, off, bytes);
+  }
+  if (st != RZF_OK) return st;
+  if (rr.size() < 2) return RZF_E_DEVICE;
+  // least-squares line through (r, cycles)
+  double sr = 0, sc = 0, srr = 0, src = 0;
+  const double n = (double)rr.size();
+  for (size_t i = 0; i < rr.size(); ++i) {
+    sr += rr[i]; sc += cc[i]; srr += rr[i] * rr[i]; src += rr[i] * cc[i];
+  }
+  const double den = n * srr - sr * sr;
+  const double b = den != 0.0 ? (n * src - sr * sc) / den : 0.0;
+  const double a = (sc - b * sr) / n;
+  int rstar = 0;   // largest whole rank with a + b r <= direct
+  for (int k = 1; k <= cap; ++k)
+    if (a + b * k <= direct) rstar = k;
+  *switch_ratio = (double)rstar / K;
+  if (direct_cycles) *direct_cycles = direct;
+  if (wb_cycles_a) *wb_cycles_a = a;
+  if (wb_cycles_b) *wb_cycles_b = b;
+  return RZF_OK;
+}
+
 rzf_status rzf_beamspace(rzf_ctx* c, int K, int nx, int ny, const rzf_c32* H, int ldh, int n_rf,
                          int select, int* beams, rzf_c32* H_eff, int ld_eff) {
   if (!c || !H || !beams || !H_eff || (select != 0 && select != 1)) return RZF_E_INVALID;

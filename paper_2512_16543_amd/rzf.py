@@ -97,6 +97,9 @@ _lib = None
 _SIGS = {
     "rzf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rzf_params_default": (ctypes.c_int, [ctypes.POINTER(Params)]),
+    "rzf_tune_switch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "rzf_track_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
     "rzf_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                       ctypes.POINTER(ctypes.c_void_p)]),
@@ -305,6 +308,15 @@ class Context:
         _check(lib().rzf_beamspace(self.h, K, int(nx), int(ny), ctypes.c_void_p(hp), ldh, n_rf,
                                    1 if select else 0, ctypes.c_void_p(_dev_ptr(beams)),
                                    ctypes.c_void_p(ep), lde), "rzf_beamspace")
+
+    def tune_switch(self, K: int, N: int, precision: int = 0) -> dict:
+        """rzf_tune_switch: Alg. 2's switch ratio from measured branch costs on
+        this device, with the cycle counts it was fitted from."""
+        out = [ctypes.c_double() for _ in range(4)]
+        _check(lib().rzf_tune_switch(self.h, int(K), int(N), int(precision),
+                                     *[ctypes.byref(v) for v in out]), "rzf_tune_switch")
+        return dict(zip(("switch_ratio", "direct_cycles", "wb_cycles_a", "wb_cycles_b"),
+                        (v.value for v in out)))
 
     def update_batch(self, tracks, Hs, Ws, tol: float, want_info: bool = False):
         """rzf_update_batch over parallel lists of Track, H_t and W tensors."""

@@ -65,6 +65,8 @@ def test_null_arguments_rejected_without_device():
     assert L.rzf_get_inverse(None, None) == rzf.RZF_E_INVALID
     assert L.rzf_track_destroy(None) == rzf.RZF_E_INVALID
     assert L.rzf_debug_sketch(None, 0, 0, 0, 0, 4, 4, None, None) == rzf.RZF_E_INVALID
+    r = ctypes.c_double()
+    assert L.rzf_tune_switch(None, 64, 256, 0, ctypes.byref(r), None, None, None) == rzf.RZF_E_INVALID
     n = ctypes.c_size_t(0)
     assert L.rzf_track_export(None, None, ctypes.byref(n)) == rzf.RZF_E_INVALID
     blob = ctypes.create_string_buffer(64)

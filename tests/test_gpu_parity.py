@@ -356,6 +356,23 @@ def test_update_capacitance_solvers(ctx, scale):
     assert all(r["path"] == orz.PATH_WB and r["r"] == 2 for r in recs), recs
 
 
+def test_tune_switch_and_use(ctx):
+    # the measured breakpoint: a whole rank, within the Woodbury workspace,
+    # Woodbury cost rising with the rank; a track run with it keeps one-step
+    # parity with the oracle under the same switch
+    K, N = 64, 256
+    t = ctx.tune_switch(K, N)
+    ratio = t["switch_ratio"]
+    assert 0.0 <= ratio <= 0.5 and abs(ratio * K - round(ratio * K)) < 1e-9, t
+    assert t["direct_cycles"] > 0 and t["wb_cycles_b"] > 0, t
+    if ratio > 0:
+        cfg = wl.CONFIGS["c2"]
+        recs = run_track(ctx, cfg, 6, 0.999, dict(reset_period=0, switch_ratio=ratio))
+        _assert_recs(recs)
+        lim = int(round(ratio * K))
+        assert all((r["path"] == orz.PATH_WB) == (r["r"] <= lim) for r in recs), (lim, recs)
+
+
 def test_update_noop_for_static_channel(ctx):
     cfg = wl.CONFIGS["c1"]
     H = c64(wl.make_track(cfg).snapshot(0)).astype(np.complex128)
