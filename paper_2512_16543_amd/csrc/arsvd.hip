@@ -510,7 +510,8 @@ template <bool MANY, int PH>
 __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* many, int* err) {
   __shared__ Shared sm;
   const ArsvdJob& jb = job_of<MANY>(one, many);
-  TrackDesc* __restrict__ td = jb.td;
+  GTrackDesc* __restrict__ td = (GTrackDesc*)jb.td;
+  TrackDesc* const tdg = (TrackDesc*)td;    // the same, for whole-struct copies
   const int t = jb.t, i_max = jb.i_max;
   const double eta = jb.eta;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -555,7 +556,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       if (!isfinite(E)) atomicCAS(err, 0, DEV_ERR_NONFINITE);
       td->info.r = 0; td->info.iters = 0; td->info.path = RZF_PATH_NOOP; td->info.d = 0;
       td->info.dA_fro2 = E; td->info.captured = 0.0;
-      if (jb.out) *jb.out = td->info;
+      if (jb.out) *jb.out = tdg->info;
       if (E == 0.0) td->last_r = 0;
       td->dbg[0] = 0; td->dbg[1] = 0; td->dbg[2] = 0;
       td->nsig = 0;
@@ -607,7 +608,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   float2* o_Ainv = td->Ainv;
   float2* o_R = td->Rfb;
   float2* o_Xw = td->Xw;
-  double* o_sig2 = td->sig2;
+  double* o_sig2 = tdg->sig2;
   bool staged = false;
   // one iteration of Alg. 1 up to the energy test: Omega, Y, Q (b1), Z (b2),
   // returning ||Z||_F^2
@@ -748,7 +749,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     }
     for (int e = tid; e < K; e += NTH) td->sig2[e] = st_sig2[e];
     if (tid == 0) {
-      td->info = st_h->info;
+      tdg->info = st_h->info;
       if (jb.out) *jb.out = st_h->info;
       td->last_r = st_h->info.r;
       td->spec_hint = it;
@@ -1097,7 +1098,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     inf.dA_fro2 = E; inf.captured = captured;
     const int age = (warm_ok && !polish) ? td->warm_age + 1 : 1;
     t_wb = clock64() - c_mark;
-    int* dbg = staged ? st_h->dbg : td->dbg;
+    int* dbg = staged ? st_h->dbg : tdg->dbg;
     dbg[0] = sweeps; dbg[1] = rounds; dbg[2] = qrcols;
     dbg[3] = (int)t_sk; dbg[4] = (int)t_qr; dbg[5] = (int)t_jac; dbg[6] = (int)t_wb;
     dbg[7] = (int)(wall_clock64() - r_begin);
@@ -1106,7 +1107,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       st_h->warm_age = age;
       st_h->nsig = d;
     } else {
-      td->info = inf;
+      tdg->info = inf;
       if (jb.out) *jb.out = inf;
       td->last_r = r;
       td->spec_hint = iters;

@@ -598,7 +598,8 @@ template <bool MANY>
 __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob* many, int* err) {
   __shared__ BigShared sm;
   const ArsvdJob& jb = job_of<MANY>(one, many);
-  TrackDesc* __restrict__ td = jb.td;
+  GTrackDesc* __restrict__ td = (GTrackDesc*)jb.td;
+  TrackDesc* const tdg = (TrackDesc*)td;    // the same, for whole-struct copies
   const int t = jb.t, i_max = jb.i_max;
   const double eta = jb.eta;
   const int tid = threadIdx.x, wid = tid >> 6;
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
       if (!isfinite(E)) atomicCAS(err, 0, DEV_ERR_NONFINITE);
       td->info.r = 0; td->info.iters = 0; td->info.path = RZF_PATH_NOOP; td->info.d = 0;
       td->info.dA_fro2 = E; td->info.captured = 0.0;
-      if (jb.out) *jb.out = td->info;
+      if (jb.out) *jb.out = tdg->info;
       if (E == 0.0) td->last_r = 0;
       td->dbg[0] = 0; td->dbg[1] = 0; td->dbg[2] = 0;
       td->nsig = 0;
@@ -706,7 +707,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
       else jacobi_big<32>(sm, Zm, K, d, &sweeps, &rounds);
       t_jac += clock64() - c_mark; c_mark = clock64();
       rotated = true;
-      pick_rank_big(sm, Zm, K, d, Et, &r, &captured, td->sig2);
+      pick_rank_big(sm, Zm, K, d, Et, &r, &captured, tdg->sig2);
       break;
     }
     // after the last iteration, or (early-fallback policy) once d is past
@@ -925,7 +926,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
   if (tid == 0) {
     td->info.r = r; td->info.iters = iters; td->info.path = path; td->info.d = d;
     td->info.dA_fro2 = E; td->info.captured = captured;
-    if (jb.out) *jb.out = td->info;
+    if (jb.out) *jb.out = tdg->info;
     td->last_r = r;
     td->dbg[0] = sweeps; td->dbg[1] = rounds; td->dbg[2] = qrcols;
     td->nsig = rotated ? d : 0;

@@ -58,6 +58,13 @@ struct TrackDesc {
   double sig2[KM]; // last SVD: sigma_j^2, descending
 };
 
+// A track descriptor addressed as global memory.  A descriptor pointer read
+// from a job array in device memory is a generic pointer, and a generic load
+// may reach per-lane scratch, so every field read through it would count as a
+// per-lane value and occupy vector registers; through this type the fields
+// stay in scalar registers.  Whole-struct copies go through the plain type.
+using GTrackDesc = __attribute__((address_space(1))) TrackDesc;
+
 // Work descriptors.  Every kernel takes one descriptor by value (a single
 // call) or a device array of them indexed by blockIdx.y (a batch); blocks
 // beyond a descriptor's own grid extent return at once.  The two forms are
