@@ -30,7 +30,12 @@ __device__ __forceinline__ void mac_conj(float2 x, float2 y, floatx4& dr, floatx
 
 template <bool DELTA, bool MANY>
 __global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) {
-  __shared__ float red[4][16][64];
+  // FP32 path: chunks of GC antennas staged through LDS (rows i0.. and j0.. of
+  // H_t, then of H_{t-1}); the row stride GLD keeps the MFMA operand reads at
+  // two lanes per bank.  The partial tiles reuse the same memory afterwards.
+  constexpr int GC = 64, GLD = GC + 4;
+  __shared__ float2 st[4][16][GLD];
+  float (*red)[16][64] = reinterpret_cast<float (*)[16][64]>(&st[0][0][0]);
   const GramJob& jb = job_of<MANY>(one, many);
   const int K = jb.K, N = jb.N, ldh = jb.ldh, ldp = jb.ldp;
   const float2* __restrict__ Ht = jb.Ht;
@@ -54,22 +59,52 @@ __global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) 
 
   floatx4 ar = zero4(), ai = zero4(), gr = zero4(), gi = zero4();
   if (jb.prec == RZF_PREC_FP32) {
-    for (int n0 = wid * 16; n0 < N; n0 += 64) {
+    // A wavefront's load reads 64 consecutive antennas of one row (four cache
+    // lines instead of sixteen).  Wave w takes antennas 16 w .. 16 w + 15 of
+    // every chunk, four per product step, in increasing order; the next
+    // chunk's loads are in flight while this one is multiplied.
+    constexpr int NM = DELTA ? 4 : 2;
+    float2 pre[NM][4];
+    auto fetch = [&](int c0) {
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        const float2* src = m < 2 ? Ht : Hp;
+        const int ld = m < 2 ? ldh : ldp;
+        const int rb = (m & 1) ? j0 : i0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int idx = threadIdx.x + 256 * e;   // 16 rows x 64 antennas
+          const int row = rb + (idx >> 6), n = c0 + (idx & 63);
+          pre[m][e] = (row < K && n < N) ? src[(size_t)row * ld + n] : cz();
+        }
+      }
+    };
+    fetch(0);
+    for (int c0 = 0; c0 < N; c0 += GC) {
+#pragma unroll
+      for (int m = 0; m < NM; ++m)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int idx = threadIdx.x + 256 * e;
+          st[m][idx >> 6][idx & 63] = pre[m][e];
+        }
+      __syncthreads();
+      if (c0 + GC < N) fetch(c0 + GC);
 #pragma unroll
       for (int k = 0; k < 16; k += 4) {
-        const int n = n0 + k + kq;
-        const bool okn = n < N;
-        const float2 ti = (oki && okn) ? Ht[(size_t)ri * ldh + n] : cz();
-        const float2 tj = (okj && okn) ? Ht[(size_t)rj * ldh + n] : cz();
+        const int nn = wid * 16 + k + kq;
+        const float2 ti = st[0][r][nn];
+        const float2 tj = st[1][r][nn];
         mac_conj(ti, tj, ar, ai);                         // H_t H_t^H
         if (DELTA) {
-          const float2 pi = (oki && okn) ? Hp[(size_t)ri * ldp + n] : cz();
-          const float2 pj = (okj && okn) ? Hp[(size_t)rj * ldp + n] : cz();
+          const float2 pi = st[2][r][nn];
+          const float2 pj = st[3][r][nn];
           const float2 di = csub(ti, pi), dj = csub(tj, pj);
           mac_conj(pi, dj, gr, gi);                       // H_{t-1} dH^H
           mac_conj(di, tj, gr, gi);                       // dH H_t^H
         }
       }
+      __syncthreads();
     }
   } else {
     // BF16 operands, 32 antennas per product; dH is formed in FP32 before
