@@ -65,38 +65,12 @@ constexpr int POLISH_EVERY = 8;
 // capacitance C = I + E: with ||E||_F <= NEUMANN_MAX the system C X = M is
 // solved by X <- M - E X, the error shrinking by ||E||_F per pass, until it
 // is below 2^-NEUMANN_BITS of X (under the FP32 rounding X then takes),
-// else by Gauss-Jordan with partial pivoting
+// else by Gauss-Jordan with partial pivoting.  The passes take E X on the
+// FP32 matrix cores and keep X in FP64: the product's rounding, about
+// 2^-24 ||E|| ||X|| <= 2^-26 ||X|| per pass, stays below X's FP32 rounding.
 constexpr double NEUMANN_MAX = 0.25;
 constexpr int NEUMANN_BITS = 30;
 
-// acc[v] -= sum_{k < kn} E[row(v), k] X[k, col] for one 16 x 16 tile (rows
-// row0 + tile_row(v), columns col0 + tile_col()) of FP64 complex matrices in
-// LDS.  The loads are not bounds-checked: rows past the matrix read other
-// LDS words, and only the in-range results are kept.  Two k at a time, so
-// that ten loads are in flight together.
-__device__ __forceinline__ void dtile16_neg(const double2* E, int lde, const double2* X, int ldx, int row0,
-                                           int col0, int kn, double2 acc[4]) {
-  const int lane = threadIdx.x & 63;
-  const double2* er = E + (size_t)(row0 + 4 * (lane >> 4)) * lde;
-  const double2* xc = X + col0 + (lane & 15);
-  int k = 0;
-  for (; k + 2 <= kn; k += 2) {
-    const double2 b0 = xc[k * ldx], b1 = xc[(k + 1) * ldx];
-    double2 a0[4], a1[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      a0[v] = er[v * lde + k];
-      a1[v] = er[v * lde + k + 1];
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] = dsub(dsub(acc[v], dmul(a0[v], b0)), dmul(a1[v], b1));
-  }
-  if (k < kn) {
-    const double2 b0 = xc[k * ldx];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] = dsub(acc[v], dmul(er[v * lde + k], b0));
-  }
-}
 static_assert(2 * WB_RMAX >= KS, "pm and tm together hold a K x K matrix");
 constexpr double JACOBI_TOL = 2e-6;
 // passes stop after one whose largest |z_p^H z_q| / (||z_p|| ||z_q||) is below
@@ -116,6 +90,7 @@ struct Shared {
   double2 gjm[2][WB_RMAX];       // Gauss-Jordan: column j of step j (two steps in flight)
   double2 gjinv[2];              // Gauss-Jordan: 1 / pivot
   double red[NWV];
+  double totv[SPEC_MAX];         // second phase: ||Z||_F^2 of the speculated iterations
   int order[KS];
   int gjperm[WB_RMAX];           // Gauss-Jordan: pivot row of step j
   int gjpr[2], gjsing[2];
@@ -742,12 +717,35 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   // the first phase carried the full-width iteration `it` through: copy its
   // results to the track
   auto commit_stage = [&](int it) {
-    for (int e = tid; e < K * K; e += NTH) {
-      td->Ainv[e] = st_Ainv[e];
-      td->Xw[e] = st_Xw[e];
-      if (fb) td->Rfb[e] = st_R[e];
+    // every load is issued before the first store (the compiler cannot tell
+    // the staging area from the track's buffers), so the copy waits on one
+    // round trip to memory rather than one per element
+    constexpr int PER = (KS * KS + NTH - 1) / NTH;
+    float2* const Ai = td->Ainv;
+    float2* const Xw = td->Xw;
+    float2* const Rf = td->Rfb;
+    float2 va[PER], vx[PER], vr[PER];
+    double vs = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NTH;
+      if (e < K * K) {
+        va[q] = st_Ainv[e];
+        vx[q] = st_Xw[e];
+        if (fb) vr[q] = st_R[e];
+      }
     }
-    for (int e = tid; e < K; e += NTH) td->sig2[e] = st_sig2[e];
+    if (tid < K) vs = st_sig2[tid];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NTH;
+      if (e < K * K) {
+        Ai[e] = va[q];
+        Xw[e] = vx[q];
+        if (fb) Rf[e] = vr[q];
+      }
+    }
+    if (tid < K) td->sig2[tid] = vs;
     if (tid == 0) {
       tdg->info = st_h->info;
       if (jb.out) *jb.out = st_h->info;
@@ -798,12 +796,15 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     decided = true;
   }
   if constexpr (PH == 2) {
+    // the speculated iterations' ||Z||_F^2, read in one round trip
     const double* totw = reinterpret_cast<const double*>(jb.spec + (size_t)2 * KS * KS * SPEC_MAX);
+    if (tid < n_spec) sm.totv[tid] = totw[tid];
+    __syncthreads();
     for (int it = 1; it <= n_spec; ++it) {
       iters = it;
       d = min(k0 + p, K);
       if (!(d == K && warm_ok)) qrcols += d;
-      const double tot = totw[it - 1];
+      const double tot = sm.totv[it - 1];
       const bool hit = tot >= Et;
       if (hit || it == i_max || (td->early_fallback && d > td->wb_limit)) {
         if (hit && stage_ok && it == kfull) {
@@ -1020,7 +1021,20 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       __syncthreads();
       for (int it = 0; it < nit; ++it) {
         double2 acc[4] = {mreg[0], mreg[1], mreg[2], mreg[3]};
-        if (xtile) dtile16_neg(aug, ldg, aug + r, ldg, ti * 16, tj * 16, r, acc);
+        if (xtile) {
+          floatx4 dr = zero4(), di = zero4();
+          ctile16([&](int rr, int k) {
+                    const int a = ti * 16 + rr;
+                    return (a < r && k < r) ? d2f(aug[a * ldg + k]) : cz();
+                  },
+                  [&](int k, int cc) {
+                    const int j = tj * 16 + cc;
+                    return (k < r && j < K) ? d2f(aug[k * ldg + r + j]) : cz();
+                  },
+                  0, r, dr, di);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[v] = make_double2(acc[v].x - (double)dr[v], acc[v].y - (double)di[v]);
+        }
         __syncthreads();
         if (xtile) {
 #pragma unroll
