@@ -150,7 +150,9 @@ rzf_status rzf_init(rzf_ctx* ctx, int K, int N, const rzf_c32* H, int ldh, doubl
  *   Delta A from eq. (9); Alg. 1 (arSVD) with energy threshold eta = tol
  *   (eq. (14)); Woodbury update of A^-1 by eq. (12) when k_est <= switch*K,
  *   else direct inversion of A'; then W = H_t^H A'^-1 with ||W||_F^2 = P.
- * tol in (0, 1].  The Woodbury capacitance is factorised in FP64.
+ * tol in (0, 1].  The Woodbury capacitance system is solved with its unknown
+ * held in FP64 (FP64 Gauss-Jordan, or correction passes whose small product
+ * E X is taken in FP32).
  * `info` (host pointer, may be NULL) is filled by the next rzf_sync.
  * For K <= 64 the iterations of Alg. 1 that the track's previous step
  * predicts (its iteration count plus one) are computed at once on otherwise

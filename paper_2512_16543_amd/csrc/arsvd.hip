@@ -41,9 +41,9 @@
 // U = [u_j] (orthonormal), V~ = [z_j] (V~ = V_r Sigma_r):
 //   P  = A^-1 U                (step 1)
 //   C  = I_r + V~^H P          (step 2; Sigma_r (Sigma_r^-1 + V_r^H A^-1 U_r))
-//   X  = C^-1 (V~^H A^-1)      (step 3, FP64: passes X <- M - E X when C = I + E is
-//                               close to I, else Gauss-Jordan inversion with
-//                               partial pivoting and the product)
+//   X  = C^-1 (V~^H A^-1)      (step 3, X in FP64: passes X <- M - E X when
+//                               C = I + E is close to I, else FP64 Gauss-Jordan
+//                               inversion with partial pivoting and the product)
 //   A^-1 <- A^-1 - P X         (steps 4-5)
 // C is nonsingular exactly when the capacitance of eq. (12) is; a pivot below
 // SING_TOL sends the step to direct inversion (path FULL_SINGULAR).
@@ -993,7 +993,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     // step 3: X = C^-1 V~^H A^-1 in FP64 (M = V~^H A^-1 in columns r.. of
     // aug; X replaces it).  C = I + E with E = V~^H A^-1 U, and
     // ||E|| <= ||Delta A_r|| ||A^-1||, small for a small update: then X <- M - E X
-    // from X = M (the error shrinks by ||E||_F per pass, to FP64 rounding);
+    // from X = M (the error shrinks by ||E||_F per pass, down to the rounding
+    // of the FP32 product E X);
     // otherwise C^-1 by Gauss-Jordan with partial pivoting, then
     // X = C^-1 M = S_p M_p (S_p[a, c] = S[p_a, c], M_p[c, :] = M[p_c, :]).
     double e2 = 0.0;
