@@ -170,19 +170,30 @@ __device__ __forceinline__ void lds_gemm(int M, int Nc, int Kd, const LA& la, co
 // The norms and z_p^H z_q are summed in FP32 (rounding error a few 2^-24
 // ||z_p|| ||z_q||, well under the threshold); the row sums are bit-identical
 // in the 16 lanes, so they all take the same decision and the same rotation.
-template <bool ACC>
+// With FRESH the squared norms are summed from the columns and returned in
+// alt, bet; otherwise alt, bet carry them in from the previous rotation and
+// leave updated by the rotation's exact effect on them: ||z_p||^2 - t |gamma|
+// and ||z_q||^2 + t |gamma| (the pair's energy moves by t |gamma|).
+template <bool ACC, bool FRESH>
 __device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], float2 xp[4], float2 xq[4], bool act,
-                                              bool& moved) {
+                                              bool& moved, float& alt, float& bet) {
   float al = 0.f, be = 0.f, grf32 = 0.f, gif32 = 0.f;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    al += cabs2(zp[m]);
-    be += cabs2(zq[m]);
+    if constexpr (FRESH) {
+      al += cabs2(zp[m]);
+      be += cabs2(zq[m]);
+    }
     grf32 = fmaf(zp[m].x, zq[m].x, fmaf(zp[m].y, zq[m].y, grf32));
     gif32 = fmaf(zp[m].x, zq[m].y, fmaf(-zp[m].y, zq[m].x, gif32));
   }
-  al = row16_sumf(al);
-  be = row16_sumf(be);
+  if constexpr (FRESH) {
+    al = row16_sumf(al);
+    be = row16_sumf(be);
+  } else {
+    al = alt;
+    be = bet;
+  }
   const float gr = row16_sumf(grf32);
   const float gi = row16_sumf(gif32);
   const float mx = fmaxf(al, be);
@@ -209,7 +220,14 @@ __device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], float2
     c = __builtin_amdgcn_rsqf(1.f + tt * tt);
     s = c * tt;
     e = make_float2(grf * ig, -gif * ig);   // conj(gamma)/|gamma|
+    if (rot) {
+      const float tg = tt * gg * ig * mx;   // t |gamma|
+      al = fmaxf(al - tg, 0.f);
+      be = be + tg;
+    }
   }
+  alt = al;
+  bet = be;
   if (rot) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -270,7 +288,8 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
             xq[mm] = xqc[16 * mm];
           }
         }
-        jacobi_rotate<ACC>(zp, zq, xp, xq, true, moved);
+        float alt, bet;
+        jacobi_rotate<ACC, true>(zp, zq, xp, xq, true, moved, alt, bet);
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
           zpc[16 * mm] = zp[mm];
@@ -305,14 +324,20 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
           }
         }
         const int up = (lane + 16) & 63;
+        // the norms are summed at the first step of the super-round and
+        // carried through the next three (B's move up with its columns)
+        float alt, bet;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          jacobi_rotate<ACC>(za, zb, xp, xq, true, moved);   // column 4A + g with column 4B + (g + t) % 4
+          // column 4A + g with column 4B + (g + t) % 4
+          if (t == 0) jacobi_rotate<ACC, true>(za, zb, xp, xq, true, moved, alt, bet);
+          else jacobi_rotate<ACC, false>(za, zb, xp, xq, true, moved, alt, bet);
 #pragma unroll
           for (int mm = 0; mm < 4; ++mm) {
             zb[mm] = make_float2(__shfl(zb[mm].x, up), __shfl(zb[mm].y, up));
             if constexpr (ACC) xq[mm] = make_float2(__shfl(xq[mm].x, up), __shfl(xq[mm].y, up));
           }
+          bet = __shfl(bet, up);
         }
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
