@@ -272,13 +272,6 @@ def beam_channel(H: np.ndarray, nx: int, ny: int, beams) -> np.ndarray:
     return H @ dft_codebook(nx, ny)[:, np.asarray(beams, dtype=np.int64)]
 
 
-def wb_rank_cap(K: int) -> int:
-    """Largest rank the Woodbury branch takes: max(32, floor(K/2)).  Alg. 2
-    switches at k_est/K <= 0.5, which this never binds; it only limits a
-    switch ratio above 0.5, where the library's Woodbury workspace ends."""
-    return max(32, K // 2)
-
-
 @dataclasses.dataclass
 class TrackParams:
     alpha: float
@@ -323,10 +316,19 @@ class OracleTrack:
         # error feedback: R = A' of the last step minus the Gram matrix whose
         # inverse is stored (zero after every direct inversion)
         self.R = np.zeros((self.K, self.K), dtype=np.complex128)
+        self.last_arsvd: Optional[ArsvdResult] = None   # Alg. 1's result of the last step
 
     def i_max(self) -> int:
         p = self.params
         return p.i_max if p.i_max > 0 else default_imax(self.K, p.k_init, p.p)
+
+    def first_k0(self) -> int:
+        """k0 of the first iteration of Alg. 1: k_init (the paper), or under
+        the warm-start policy max(k_init, previous k_est)."""
+        p = self.params
+        if p.kinit_policy == KINIT_WARM:
+            return max(p.k_init, self.last_r)
+        return p.k_init
 
     def draw(self, t: int):
         p = self.params
@@ -345,19 +347,19 @@ class OracleTrack:
             dA = dA + self.R                             # the change the inverse still lacks
         A_new = gram(H, prm.alpha)                       # eq. (7)
         energy = fro2(dA)
+        self.last_arsvd = None
         if prm.reset_period > 0 and self.since_reset + 1 >= prm.reset_period:
             self.Ainv = direct_inverse(A_new)
             info = UpdateInfo(0, 0, PATH_RESET, 0.0, 0.0, 0)
             self.since_reset = 0
             self.R[:] = 0.0
         else:
-            k_init = prm.k_init
-            if prm.kinit_policy == KINIT_WARM:
-                k_init = max(prm.k_init, self.last_r)
-            limit = min(math.floor(prm.switch_ratio * self.K), wb_rank_cap(self.K))
+            k_init = self.first_k0()
+            limit = math.floor(prm.switch_ratio * self.K)  # Alg. 2: k_est <= switch * K
             res = arsvd(dA, eta, k_init, prm.p, self.i_max(), self.draw(t),
                         force_iters=force_iters, force_r=force_r,
                         stop_d=limit if prm.early_fallback else None)
+            self.last_arsvd = res
             info = UpdateInfo(res.r, res.iters, PATH_NOOP, energy, res.captured, res.d)
             if res.r == 0:
                 info.path = PATH_NOOP

@@ -139,6 +139,15 @@ def _beamspace_variant(kind):
     return f
 
 
+def m_first_k0_plus_one(self):
+    p = self.params
+    return max(p.k_init, self.last_r + 1) if p.kinit_policy == orz.KINIT_WARM else p.k_init
+
+
+def m_first_k0_always_warm(self):
+    return max(self.params.k_init, self.last_r)
+
+
 MUTANTS = [
     ("gram_no_alpha", orz, "gram", m_gram_no_alpha, ["test_gram_bruteforce", "test_gram_hermitian_positive_definite"]),
     ("gram_transposed", orz, "gram", m_gram_transposed, ["test_gram_bruteforce"]),
@@ -167,6 +176,8 @@ MUTANTS = [
     ("beamspace_no_exclusion", orz, "beamspace", _beamspace_variant("no_exclusion"), ["test_beamspace_conflict_and_ties"]),
     ("beamspace_last_on_tie", orz, "beamspace", _beamspace_variant("last_on_tie"), ["test_beamspace_conflict_and_ties"]),
     ("beamspace_extra_by_max", orz, "beamspace", _beamspace_variant("extra_by_max"), ["test_beamspace_conflict_and_ties"]),
+    ("warm_k0_plus_one", orz.OracleTrack, "first_k0", m_first_k0_plus_one, ["test_track_warm_start_policy"]),
+    ("warm_k0_always", orz.OracleTrack, "first_k0", m_first_k0_always_warm, ["test_track_warm_start_policy"]),
 ]
 
 

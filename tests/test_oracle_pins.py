@@ -501,21 +501,60 @@ def test_track_noop_when_channel_static():
     assert rel(W, orz.full_rzf(Hs[0], cfg.alpha, 1.0)) < 1e-13
 
 
+def _recorded_sketch_sizes(ot):
+    """Wrap ot.draw so that every sketch Alg. 1 draws is logged as (t, i, d)."""
+    calls = []
+    base = ot.draw
+
+    def draw(t):
+        f = base(t)
+
+        def g(i, K, d):
+            calls.append((t, i, d))
+            return f(i, K, d)
+        return g
+    ot.draw = draw
+    return calls
+
+
 def test_track_warm_start_policy():
-    cfg, Hs = _track_inputs(steps=5)
-    prm = orz.TrackParams(alpha=cfg.alpha, kinit_policy=orz.KINIT_WARM, switch_ratio=1.0)
-    ot = orz.OracleTrack(Hs[0], prm)
-    _, i1 = ot.update(Hs[1], 0.99)
-    _, i2 = ot.update(Hs[2], 0.99)
-    # warm start begins at k0 = previous rank, so the first d is r_prev + p
-    assert i2.iters <= i1.iters
-    assert i2.d >= min(i1.r + prm.p, cfg.K) or i2.iters > 1
+    # warm start: iteration 1 of step t draws d = min(max(k_init, r_{t-1}) + p, K)
+    # and doubling goes on from that k0; the fixed policy starts at k_init
+    cfg, Hs = _track_inputs(steps=6)
+    for policy in (orz.KINIT_WARM, orz.KINIT_FIXED):
+        prm = orz.TrackParams(alpha=cfg.alpha, kinit_policy=policy, p=3)
+        ot = orz.OracleTrack(Hs[0], prm)
+        calls = _recorded_sketch_sizes(ot)
+        r_prev, grew = 0, False
+        for t in range(1, 7):
+            calls.clear()
+            _, info = ot.update(Hs[t], 0.99)
+            k0 = max(prm.k_init, r_prev) if policy == orz.KINIT_WARM else prm.k_init
+            want = [min(k0 * 2 ** m + prm.p, cfg.K) for m in range(info.iters)]
+            assert [c[2] for c in calls] == want, (policy, t, calls, r_prev)
+            assert [(c[0], c[1]) for c in calls] == [(t, m + 1) for m in range(info.iters)]
+            grew = grew or r_prev > prm.k_init
+            r_prev = info.r
+        assert grew     # some step started above k_init, so the policy mattered
 
 
-def test_woodbury_rank_cap_reading():
-    # Alg. 2's switch at 0.5 K never reaches the cap; only larger ratios do
-    assert [orz.wb_rank_cap(K) for K in (1, 16, 64, 65, 100, 256)] == [32, 32, 32, 32, 50, 128]
-    assert all(math.floor(0.5 * K) <= orz.wb_rank_cap(K) for K in range(1, 257))   # integer ranks
+def test_track_switch_is_algorithm_2_alone():
+    # Alg. 2 takes Woodbury exactly when k_est <= floor(switch_ratio K), with no
+    # other cap: at K = 16 a ratio of 1 sends every rank to Woodbury, and at
+    # K = 64 a ratio of 0.75 sends a rank-40 step there too
+    cfg, Hs = _track_inputs(steps=4)
+    ot = orz.OracleTrack(Hs[0], orz.TrackParams(alpha=cfg.alpha, switch_ratio=1.0, k_init=16, p=0))
+    for t in range(1, 4):
+        _, info = ot.update(Hs[t], 1.0 - 1e-12)
+        assert info.r == 16 and info.path == orz.PATH_WB
+    K, N = 64, 80
+    H0 = wl.random_channel(K, N, 31)
+    H1 = wl.random_channel(K, N, 32)    # an i.i.d. redraw: Delta A of full rank
+    for ratio, want in ((0.75, orz.PATH_WB), (0.5, orz.PATH_FULL_RANK)):
+        ot = orz.OracleTrack(H0, orz.TrackParams(alpha=1.0, switch_ratio=ratio, k_init=40, p=0, i_max=1))
+        _, info = ot.update(H1, 1.0)
+        assert info.r == 40 and info.path == want, (ratio, info)
+        assert rel(ot.Ainv, np.linalg.inv(orz.gram(H1, 1.0))) > 1e-8 or want != orz.PATH_WB
 
 
 def test_track_early_fallback_policy():
