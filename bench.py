@@ -585,9 +585,7 @@ def table_v(a):
     if a.hybrid:
         base = wl.CONFIGS["h1"]
     else:
-        base = wl.TrackConfig("table_v", seed=15, nx=16, K=16, height_m=600e3, radius_m=50e3,
-                              dt_s=0.05, steps=2400, kr_db=10.0, snr_db=10.0, eta=0.9, p=1, k_init=2,
-                              reset_period=0)
+        base = wl.CONFIGS["tv"]
     B, T = a.passes, base.steps
     K, N = base.K, base.N
     Np = base.n_rf if a.hybrid else N        # columns the precoder sees

@@ -75,14 +75,17 @@ typedef enum { RZF_PREC_FP32 = 0, RZF_PREC_BF16 = 1, RZF_PREC_BF16X3 = 2 } rzf_p
 
 /* Parameters of one track; rzf_params_default fills the paper's values. */
 typedef struct {
-  int k_init;           /* initial rank estimate of Alg. 1 (Table IV: 2)          */
-  int p;                /* oversampling of Alg. 1 (Table IV: 1; workloads use 5)  */
+  int k_init;           /* initial rank estimate of Alg. 1 (Table IV: 2);
+                           1 <= k_init <= RZF_KMAX                                 */
+  int p;                /* oversampling of Alg. 1 (Table IV: 1; workloads use 5);
+                           0 <= p <= RZF_KMAX                                      */
   int i_max;            /* Alg. 1 iteration cap; 0 = smallest I with
                            k_init * 2^(I-1) + p >= K                               */
-  double switch_ratio;  /* Alg. 2: Woodbury when k_est <= switch_ratio * K (0.5);
-                           ranks above max(32, K/2) always take the direct
-                           inversion (the end of the Woodbury workspace; only a
-                           ratio above 0.5 reaches it)                            */
+  double switch_ratio;  /* Alg. 2: Woodbury when k_est <= floor(switch_ratio K)
+                           (0.5).  The Woodbury workspace holds min(K, max(32,
+                           K/2)) ranks: rzf_init and rzf_track_import refuse
+                           (RZF_E_INVALID) a ratio whose floor(switch_ratio K)
+                           exceeds it, which 0.5 never does                       */
   int reset_period;     /* re-invert A' in FP64 once this many steps have passed
                            since the last FP64 inversion (init or reset), skipping
                            Alg. 1 on that step; 0 = never                         */
@@ -92,8 +95,8 @@ typedef struct {
   int kinit_policy;     /* RZF_KINIT_FIXED: k0 = k_init every step (Alg. 1);
                            RZF_KINIT_WARM: k0 = max(k_init, previous k_est)        */
   int early_fallback;   /* 0: Alg. 1 as printed.  1: an iteration whose d already
-                           exceeds the Woodbury limit (switch_ratio * K and the
-                           rank cap) and misses the energy target ends Alg. 1;
+                           exceeds the Woodbury limit floor(switch_ratio K) and
+                           misses the energy target ends Alg. 1;
                            the step inverts directly (path FULL_RANK, k_est = d)  */
   int precision;        /* rzf_precision of the Gram and precoder products (FP32) */
   int error_feedback;   /* 0: Alg. 2 as printed.  1: the track keeps R, A' minus
@@ -121,6 +124,14 @@ const char* rzf_status_string(rzf_status s);
  * RZF_E_INVALID if p is NULL. */
 rzf_status rzf_params_default(rzf_params* p);
 
+/* Whether *p is a valid parameter set for a track of K users (the checks
+ * rzf_init and rzf_track_import make, without a device): RZF_OK, RZF_E_SHAPE
+ * for K outside [1, RZF_KMAX], else RZF_E_INVALID for a NULL p or any field
+ * out of its range above (switch_ratio in (0, 1] within the Woodbury
+ * workspace, k_init and p up to RZF_KMAX, i_max up to 64, P > 0, policy
+ * flags 0 or 1, precision an rzf_precision). */
+rzf_status rzf_params_check(const rzf_params* p, int K);
+
 /* Bytes of arena one track of size K x N occupies (0 if out of range). */
 size_t rzf_track_bytes(int K, int N);
 
@@ -135,7 +146,10 @@ rzf_status rzf_ctx_destroy(rzf_ctx* ctx);
 
 /* Wait for all work on the context's stream, fill pending info records, and
  * return (then clear) the first device-side error recorded since the last
- * rzf_sync. */
+ * rzf_sync.  The synchronous calls (rzf_init, rzf_track_import,
+ * rzf_tune_switch) return only errors of their own work and leave an earlier
+ * one pending for rzf_sync; rzf_sum_rate with a host sum_rate pointer
+ * synchronises like rzf_sync and returns (and clears) it. */
 rzf_status rzf_sync(rzf_ctx* ctx);
 
 /* Alg. 2, else-branch: build the state of a new track from its first snapshot.
@@ -150,7 +164,15 @@ rzf_status rzf_init(rzf_ctx* ctx, int K, int N, const rzf_c32* H, int ldh, doubl
  *   Delta A from eq. (9); Alg. 1 (arSVD) with energy threshold eta = tol
  *   (eq. (14)); Woodbury update of A^-1 by eq. (12) when k_est <= switch*K,
  *   else direct inversion of A'; then W = H_t^H A'^-1 with ||W||_F^2 = P.
- * tol in (0, 1].  The Woodbury capacitance system is solved with its unknown
+ * tol in (0, 1].
+ * A snapshot holding NaN or Inf makes the next rzf_sync return
+ * RZF_E_NONFINITE; that step writes a non-finite W (info: path NOOP, r = 0,
+ * dA_fro2 NaN) and leaves the track's inverse, previous snapshot, residual
+ * and SVD basis as they were, so the next finite snapshot is taken relative
+ * to the last finite one.  Only the step counters advance (a reset step that
+ * fails this way still restarts the reset count).  The same holds for a reset
+ * step whose FP64 re-inversion finds A' not positive definite
+ * (RZF_E_NOT_HPD).  The Woodbury capacitance system is solved with its unknown
  * held in FP64 (FP64 Gauss-Jordan, or correction passes whose small product
  * E X is taken in FP32).
  * `info` (host pointer, may be NULL) is filled by the next rzf_sync.
@@ -266,7 +288,9 @@ rzf_status rzf_beamspace(rzf_ctx* ctx, int K, int nx, int ny, const rzf_c32* H, 
  * takes the X <- M - E X passes, as for a slowly varying channel).  The Woodbury cost is fitted as
  * a + b r; *switch_ratio is the largest r/K (r a whole number) at which it is
  * not above the direct inversion's, 0 if none, capped at the Woodbury
- * workspace (max(32, K/2) ranks).  Use it as rzf_params.switch_ratio.
+ * workspace (min(K, max(32, K/2)) ranks), so rzf_init accepts it as
+ * rzf_params.switch_ratio.  An error of earlier asynchronous work stays
+ * pending for the next rzf_sync.
  * Optional outputs: *direct_cycles, *wb_cycles_a and *wb_cycles_b (the fit).
  * Synchronous; uses temporary tracks and 3 K N complex values of the arena.
  * 2 <= K <= RZF_KMAX, K <= N <= RZF_NMAX. */

@@ -24,6 +24,9 @@ notation (A is the Gram matrix, Delta A its per-step correction):
 Readings taken where the paper is silent (each is also listed with the design
 notes of the repository):
   * Delta A = 0 gives r = 0 and leaves the inverse unchanged.
+  * A snapshot holding NaN or Inf leaves the track's state unchanged (the
+    next one is taken against the last finite snapshot); the step counters
+    advance as for any step.
   * "Non-zero singular values" (Sec. III): components with sigma_j == 0 are
     dropped from Sigma_r before eq. (12) inverts it.
   * The switch of Alg. 2 is inclusive: Woodbury when r <= 0.5 K.
@@ -341,6 +344,17 @@ class OracleTrack:
         H = np.asarray(H, dtype=np.complex128)
         self.t += 1
         t = self.t
+        if not np.all(np.isfinite(H)):
+            # a snapshot with NaN or Inf has no Delta A: the state stays as
+            # it was and the next snapshot is taken against the last finite
+            # one; only the step counters advance (a reset step still
+            # restarts the reset count)
+            reset = prm.reset_period > 0 and self.since_reset + 1 >= prm.reset_period
+            self.since_reset = 0 if reset else self.since_reset + 1
+            self.last_arsvd = None
+            with np.errstate(invalid="ignore", over="ignore"):
+                W = hermitian(H) @ self.Ainv
+            return W, UpdateInfo(0, 0, PATH_NOOP, float("nan"), 0.0, 0)
         dH = H - self.H_prev
         dA = gram_correction(self.H_prev, dH)            # eq. (9)
         if prm.error_feedback:

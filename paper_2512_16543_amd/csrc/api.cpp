@@ -172,7 +172,8 @@ void arsvd_single(rzf_ctx* c, ArsvdJob j, int K, hipStream_t s) {
 }
 
 bool params_valid(const rzf_params* p) {
-  return p->k_init >= 1 && p->p >= 0 && p->i_max >= 0 && p->i_max <= 64 &&
+  return p->k_init >= 1 && p->k_init <= RZF_KMAX && p->p >= 0 && p->p <= RZF_KMAX &&
+         p->i_max >= 0 && p->i_max <= 64 &&
          std::isfinite(p->switch_ratio) && p->switch_ratio > 0.0 && p->switch_ratio <= 1.0 &&
          p->reset_period >= 0 && std::isfinite(p->P) && p->P > 0.0 &&
          (p->kinit_policy == RZF_KINIT_FIXED || p->kinit_policy == RZF_KINIT_WARM) &&
@@ -181,6 +182,17 @@ bool params_valid(const rzf_params* p) {
          (p->error_feedback == 0 || p->error_feedback == 1);
 }
 
+// Largest rank the Woodbury branch of a K x K track can take: the LDS
+// kernels hold WB_RMAX columns, the large-track workspace K / 2.
+int wb_capacity(int K) { return std::min(K, std::max(WB_RMAX, K / 2)); }
+
+// Alg. 2's switch as a rank: Woodbury when k_est <= floor(switch_ratio K).
+int switch_rank(double ratio, int K) { return (int)std::floor(ratio * K); }
+
+// The track's parameters fit a K-user track: Alg. 2's switch must stay within
+// the Woodbury workspace (a larger ratio is refused rather than capped).
+bool params_fit(const rzf_params* p, int K) { return switch_rank(p->switch_ratio, K) <= wb_capacity(K); }
+
 int default_imax(int K, int k_init, int p) {
   int i = 1;
   long k0 = k_init;
@@ -188,7 +200,10 @@ int default_imax(int K, int k_init, int p) {
   return i;
 }
 
-rzf_status sync_and_collect(rzf_ctx* c) {
+// Wait for the stream, fill the pending info records, and move the device
+// error word into *code (clearing it on the device).
+rzf_status take_device_error(rzf_ctx* c, int* code) {
+  *code = 0;
   HIP_OK(hipStreamSynchronize(c->stream));
   for (const Pending& pd : c->pending) {
     if (pd.dst) std::memcpy(pd.dst, pd.slot, sizeof(rzf_update_info));
@@ -196,12 +211,39 @@ rzf_status sync_and_collect(rzf_ctx* c) {
   c->pending.clear();
   c->pin_used = 0;
   HIP_OK(hipMemcpy(c->h_err, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
-  const int code = *c->h_err;
-  if (code) {
+  *code = *c->h_err;
+  if (*code) {
     *c->h_err = 0;
     HIP_OK(hipMemcpy(c->d_err, c->h_err, sizeof(int), hipMemcpyHostToDevice));
   }
-  return dev_status(code);
+  return RZF_OK;
+}
+
+// rzf_sync: the first error recorded since the last rzf_sync, then cleared
+// (one kept aside by a synchronous call comes first).
+rzf_status sync_and_collect(rzf_ctx* c) {
+  int code = 0;
+  const rzf_status st = take_device_error(c, &code);
+  const int first = c->held_err ? c->held_err : code;
+  c->held_err = 0;
+  if (st != RZF_OK) return st;
+  return dev_status(first);
+}
+
+// Before a synchronous call's own launches: an error that earlier
+// asynchronous work left on the device is kept for the next rzf_sync.
+rzf_status hold_earlier_error(rzf_ctx* c) {
+  int code = 0;
+  const rzf_status st = take_device_error(c, &code);
+  if (code && !c->held_err) c->held_err = code;
+  return st;
+}
+
+// After a synchronous call's own launches: their device error only.
+rzf_status own_device_error(rzf_ctx* c) {
+  int code = 0;
+  const rzf_status st = take_device_error(c, &code);
+  return st != RZF_OK ? st : dev_status(code);
 }
 
 }  // namespace
@@ -228,8 +270,8 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
   d.early_fallback = prm.early_fallback;
   d.prec = prm.precision;
   d.error_feedback = prm.error_feedback;
-  // Alg. 2's switch and the end of the Woodbury workspace (max(32, K/2) ranks)
-  d.wb_limit = std::min((int)std::floor(prm.switch_ratio * K), std::max(WB_RMAX, K / 2));
+  // Alg. 2's switch (params_fit keeps it within the Woodbury workspace)
+  d.wb_limit = switch_rank(prm.switch_ratio, K);
   d.Ainv = reinterpret_cast<float2*>(base + L.ainv);
   d.Hprev = reinterpret_cast<float2*>(base + L.hprev);
   d.Anew = reinterpret_cast<float2*>(base + L.anew);
@@ -302,6 +344,12 @@ rzf_status rzf_params_default(rzf_params* p) {
   p->seed = 0;
   p->track_id = 0;
   p->kinit_policy = RZF_KINIT_FIXED;
+  return RZF_OK;
+}
+
+rzf_status rzf_params_check(const rzf_params* p, int K) {
+  if (K < 1 || K > RZF_KMAX) return RZF_E_SHAPE;
+  if (!p || !params_valid(p) || !params_fit(p, K)) return RZF_E_INVALID;
   return RZF_OK;
 }
 
@@ -397,12 +445,12 @@ rzf_status rzf_init(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   if (!std::isfinite(alpha) || alpha < 0.0) return RZF_E_INVALID;
   rzf_params prm;
   if (params) prm = *params; else rzf_params_default(&prm);
-  if (!params_valid(&prm)) return RZF_E_INVALID;
+  if (!params_valid(&prm) || !params_fit(&prm, K)) return RZF_E_INVALID;
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
-  // report and clear any earlier device error before this synchronous call
-  rzf_status st0 = sync_and_collect(c);
-  if (st0 == RZF_E_DEVICE) return st0;
+  // an error of earlier asynchronous work stays pending for the next rzf_sync
+  rzf_status st0 = hold_earlier_error(c);
+  if (st0 != RZF_OK) return st0;
 
   rzf_track* t = track_new(c, K, N, prm, alpha);
   if (!t) return RZF_E_NOMEM;
@@ -419,7 +467,7 @@ rzf_status rzf_init(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
                           sizeof(float2) * N, K, hipMemcpyDeviceToDevice, s) == hipSuccess;
     ok = ok && hipGetLastError() == hipSuccess;
   }
-  rzf_status st = ok ? sync_and_collect(c) : RZF_E_DEVICE;
+  rzf_status st = ok ? own_device_error(c) : RZF_E_DEVICE;
   if (st != RZF_OK) {
     arena_free(c, t->off, t->bytes);
     delete t;
@@ -452,7 +500,7 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
   const bool reset = t->prm.reset_period > 0 && t->since_reset + 1 >= t->prm.reset_period;
   if (reset) {
     const Gram64Job gj{Hf, d.A64, K, N, ldh, t->alpha};
-    const Inv64Job ij{d.A64, d.Ainv, &t->d_desc->info, nullptr, K, d.Rfb};
+    const Inv64Job ij{d.A64, d.Ainv, &t->d_desc->info, nullptr, K, d.Rfb, &t->d_desc->hold};
     timed(c, KN_GRAM64, [&] { launch_gram64(gj, nullptr, 1, K, s); });
     timed(c, KN_INV64, [&] { inv64_any(ij, c->d_err, s); });
   } else {
@@ -461,7 +509,7 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
     timed(c, KN_GRAM, [&] { launch_gram(gj, nullptr, 1, K, s); });
     timed(c, KN_ARSVD, [&] { arsvd_single(c, aj, K, s); });
   }
-  const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw, d.prec};
+  const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw, d.prec, &t->d_desc->hold};
   const ScaleJob sj{Wf, d.wpart, d.P, K, N, ldw, precoder_blocks(N)};
   timed(c, KN_PRECODER, [&] { launch_precoder(pj, nullptr, 1, N, s); });
   timed(c, KN_SCALE, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
@@ -543,13 +591,15 @@ rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, 
     reset_flag[i] = reset;
     if (reset) {
       g64.push_back(Gram64Job{Hf, d.A64, K, N, items[i].ldh, t->alpha});
-      (K > KS ? i64b : i64).push_back(Inv64Job{d.A64, d.Ainv, &t->d_desc->info, nullptr, K, d.Rfb});
+      (K > KS ? i64b : i64).push_back(Inv64Job{d.A64, d.Ainv, &t->d_desc->info, nullptr, K, d.Rfb,
+                                               &t->d_desc->hold});
       maxKr = std::max(maxKr, K);
     } else {
       gj.push_back(GramJob{Hf, d.Hprev, d.Anew, d.dA, K, N, items[i].ldh, N, (float)t->alpha, d.prec});
       (K > KS ? ajb : aj).push_back(ArsvdJob{t->d_desc, nullptr, tol, t->t + 1, t->i_max});
     }
-    pj.push_back(PrecJob{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, items[i].ldh, items[i].ldw, d.prec});
+    pj.push_back(PrecJob{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, items[i].ldh, items[i].ldw, d.prec,
+                         &t->d_desc->hold});
     sj.push_back(ScaleJob{Wf, d.wpart, d.P, K, N, items[i].ldw, precoder_blocks(N)});
     maxK = std::max(maxK, K);
     maxN = std::max(maxN, N);
@@ -837,6 +887,9 @@ rzf_status rzf_tune_switch(rzf_ctx* c, int K, int N, int precision, double* swit
   const size_t bytes = align_up(sizeof(rzf_c32) * 3 * kn);
   {
     std::lock_guard<std::mutex> lk(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return RZF_E_DEVICE;
+    // an error of earlier asynchronous work stays pending for the next rzf_sync
+    if (hold_earlier_error(c) != RZF_OK) return RZF_E_DEVICE;
     if (!arena_alloc(c, bytes, &off)) return RZF_E_NOMEM;
   }
   rzf_c32* dH0 = reinterpret_cast<rzf_c32*>(c->arena + off);
@@ -859,7 +912,10 @@ rzf_status rzf_tune_switch(rzf_ctx* c, int K, int N, int precision, double* swit
       if (s1 != RZF_OK) return s1;
       rzf_update_info info;
       s1 = rzf_update(t, dH1, N, 1.0 - 1e-4, dW, K, &info);
-      if (s1 == RZF_OK) s1 = rzf_sync(c);
+      if (s1 == RZF_OK) {
+        std::lock_guard<std::mutex> lk(c->mu);
+        s1 = own_device_error(c);
+      }
       int v[8] = {0};
       if (s1 == RZF_OK) s1 = rzf_debug_counters(t, v, 8);
       rzf_track_destroy(t);
@@ -892,7 +948,7 @@ rzf_status rzf_tune_switch(rzf_ctx* c, int K, int N, int precision, double* swit
       return RZF_E_DEVICE;
     return RZF_OK;
   };
-  const int cap = std::min(K, std::max(WB_RMAX, K / 2));   // Woodbury workspace
+  const int cap = wb_capacity(K);   // Woodbury workspace
   std::vector<double> rr, cc;
   double direct = 0.0;
   int r = 0, path = 0;
@@ -907,7 +963,7 @@ rzf_status rzf_tune_switch(rzf_ctx* c, int K, int N, int precision, double* swit
   for (int m = 1; st == RZF_OK && 2 * m <= cap; m = (m < 4) ? 2 * m : m + 4) {
     st = set_change(m);
     double cy = 0.0;
-    if (st == RZF_OK) st = measure(1.0, &cy, &r, &path);
+    if (st == RZF_OK) st = measure(std::min(1.0, (cap + 0.5) / K), &cy, &r, &path);
     if (st == RZF_OK && path == RZF_PATH_WB && r > 0) {
       rr.push_back(r);
       cc.push_back(cy);
@@ -1072,14 +1128,14 @@ rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track
     return RZF_E_INVALID;
   if (h.K < 1 || h.K > RZF_KMAX || h.N < 1 || h.N > RZF_NMAX) return RZF_E_SHAPE;
   if (bytes < blob_bytes(h.K, h.N)) return RZF_E_INVALID;
-  if (!params_valid(&h.prm) || !std::isfinite(h.alpha) || h.alpha < 0.0 || h.step < 0 ||
+  if (!params_valid(&h.prm) || !params_fit(&h.prm, h.K) || !std::isfinite(h.alpha) || h.alpha < 0.0 || h.step < 0 ||
       h.since_reset < 0 || h.last_r < 0 || h.last_r > h.K || (h.warm != 0 && h.warm != 1) ||
       h.warm_age < 0 || (h.warm && h.K > KS))
     return RZF_E_INVALID;
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
-  rzf_status st0 = sync_and_collect(c);
-  if (st0 == RZF_E_DEVICE) return st0;
+  rzf_status st0 = hold_earlier_error(c);
+  if (st0 != RZF_OK) return st0;
   rzf_track* t = track_new(c, h.K, h.N, h.prm, h.alpha);
   if (!t) return RZF_E_NOMEM;
   t->t = h.step;

@@ -46,7 +46,8 @@
 //                               inversion with partial pivoting and the product)
 //   A^-1 <- A^-1 - P X         (steps 4-5)
 // C is nonsingular exactly when the capacitance of eq. (12) is; a pivot below
-// SING_TOL sends the step to direct inversion (path FULL_SINGULAR).
+// the working precision of C's entries sends the step to direct inversion
+// (path FULL_SINGULAR).
 #include "dense_device.h"
 #include "rzf_internal.h"
 
@@ -77,7 +78,12 @@ constexpr double JACOBI_TOL = 2e-6;
 // JACOBI_QSTOP: near convergence a pass squares that measure, so the next
 // one would only rotate pairs at about JACOBI_QSTOP^2, the FP32 noise level
 constexpr double JACOBI_QSTOP = 1e-3;
-constexpr double SING_TOL = 1e-12;
+// C = I + E is taken as singular when a Gauss-Jordan pivot's modulus is at
+// most SING_TOL (1 + ||E||_F): C is formed from FP32 factors, so its entries
+// are known only to about r 2^-24 (1 + ||E||) (r <= 32 here), and a smaller
+// pivot leaves nothing of X = C^-1 M that those entries determine; the step
+// then inverts A' directly (path FULL_SINGULAR)
+constexpr double SING_TOL = 0x1.0p-14;
 
 
 struct Shared {
@@ -428,9 +434,9 @@ __device__ void pick_rank(Shared& sm, int K, int d, double Et, int* r_out, doubl
 // of step j it updates that column first, at raised wave priority, and
 // publishes the next pivot (row, 1 / pivot and the column) in the other of
 // two LDS slots, so a step costs one workgroup barrier.  Returns false
-// (every thread alike) if a pivot's squared modulus is not above SING_TOL^2
-// or is not finite.
-__device__ bool gj_invert_small(Shared& sm, double2* aug, int r, int ldg) {
+// (every thread alike) if a pivot's squared modulus is not above tol2 or is
+// not finite.
+__device__ bool gj_invert_small(Shared& sm, double2* aug, int r, int ldg, double tol2) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int row = lane & 31, hw = 2 * wid + (lane >> 5), base = lane & 32;
   double2 x = (hw < r && row < r) ? aug[row * ldg + hw] : dz();
@@ -453,7 +459,7 @@ __device__ bool gj_invert_small(Shared& sm, double2* aug, int r, int ldg) {
     const double2 p = lane_read(x, hb + pu);
     if (row < r) sm.gjm[b][row] = x;
     if (row == 0) {
-      const bool sing = pr < 0 || !(mx > SING_TOL * SING_TOL) || !isfinite(mx);
+      const bool sing = pr < 0 || !(mx > tol2) || !isfinite(mx);
       // 1 / |p|^2: hardware reciprocal and one Newton step
       const double a2 = sing ? 1.0 : dabs2(p);
       double id = __builtin_amdgcn_rcp(a2);
@@ -548,6 +554,9 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     E = load_dA();
     if (PH == 1 && blockIdx.x == 0 && tid == 0) spec_d[SPEC_MAX] = E;
   }
+  // a non-finite snapshot leaves the track's state as it was (the precoder
+  // then keeps H_prev too)
+  if (PH != 1 && tid == 0) td->hold = isfinite(E) ? 0 : 1;
   if (!isfinite(E) || E == 0.0) {
     if (PH == 1) return;                     // the second phase records the step
     if (fb && E == 0.0)                      // nothing to apply: the residual is zero
@@ -1073,7 +1082,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       }
       solved = true;
     } else {
-      solved = gj_invert_small(sm, aug, r, ldg);
+      const double stol = SING_TOL * (1.0 + sqrt(eps2));
+      solved = gj_invert_small(sm, aug, r, ldg, stol * stol);
       if (solved) {
         const int* pv = sm.gjperm;
         double2 acc[4] = {dz(), dz(), dz(), dz()};

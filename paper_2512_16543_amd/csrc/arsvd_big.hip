@@ -34,7 +34,11 @@ constexpr int NWV = NTH / 64;
 constexpr int MAX_SWEEPS = 30;      // Jacobi passes
 constexpr double JACOBI_TOL = 2e-6;
 constexpr double JACOBI_QSTOP = 1e-3;   // passes stop after one with no pair above it
-constexpr double SING_TOL = 1e-12;
+// C = I + E is taken as singular when a pivot's modulus is at most
+// SING_TOL (1 + ||E||_F): its entries come from FP32 factors and are known
+// only to about r 2^-24 (1 + ||E||) (r <= 128 here), so a smaller pivot leaves
+// nothing of C^-1 M that they determine (path FULL_SINGULAR)
+constexpr double SING_TOL = 0x1.0p-14;
 constexpr int JOB_ELEMS = KM * 32;  // LDS entries of one job matrix
 constexpr int GJ_W = 32;            // panel width of the capacitance solve
 constexpr int RB = KM / 2;          // largest Woodbury rank of a large track
@@ -495,10 +499,18 @@ __device__ __forceinline__ void pick_rank_big(BigShared& sm, const float2* Zm, i
 // Gauss-Jordan with partial pivoting on the r x (r + K) FP64 system
 // aug = [C | M] (row-major, ld ldg) so that its last K columns become
 // C^-1 M.  Returns false (and leaves aug partly eliminated) if a pivot's
-// modulus is not above SING_TOL or is not finite.
+// modulus is not above SING_TOL (1 + ||C - I||_F) or is not finite.
 __device__ __forceinline__ bool solve_capacitance(BigShared& sm, double2* aug, int r, int ldg) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   double2* gp = sm.u.gj.pan;
+  double e2 = 0.0;
+  for (int e = tid; e < r * r; e += NTH) {
+    const int a = e / r, c = e - a * r;
+    const double2 v = aug[(size_t)a * ldg + c];
+    const double re = v.x - (a == c ? 1.0 : 0.0);
+    e2 += re * re + v.y * v.y;
+  }
+  const double stol = SING_TOL * (1.0 + sqrt(block_sum(e2, sm.red)));
   if (tid == 0) sm.singular = 0;
   for (int j0 = 0; j0 < r; j0 += GJ_W) {
     const int nc = min(GJ_W, r - j0);
@@ -532,7 +544,7 @@ __device__ __forceinline__ bool solve_capacitance(BigShared& sm, double2* aug, i
             sm.singular = 1;
           } else {
             sm.pivrow[k] = prow;
-            if (!(sqrt(mx) > SING_TOL) || !isfinite(mx)) sm.singular = 1;
+            if (!(sqrt(mx) > stol) || !isfinite(mx)) sm.singular = 1;
           }
         }
         if (prow >= 0) {
@@ -620,6 +632,9 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
     part += (double)v.x * v.x + (double)v.y * v.y;
   }
   const double E = block_sum(part, sm.red);
+  // a non-finite snapshot leaves the track's state as it was (the precoder
+  // then keeps H_prev too)
+  if (tid == 0) td->hold = isfinite(E) ? 0 : 1;
   if (!isfinite(E) || E == 0.0) {
     if (fb && E == 0.0)
       for (int e = tid; e < K * K; e += NTH) td->Rfb[e] = cz();
@@ -948,15 +963,19 @@ __global__ __launch_bounds__(NTH) void k_inv64_big(Inv64Job one, const Inv64Job*
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   gj_inverse_hpd_blocked<double2>(A, K, K, xs, cs, pb, &bad);
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-    jb.Ainv[e] = d2f(A[e]);
-    if (jb.zero) jb.zero[e] = cz();
-  }
+  // a reset that fails keeps the track's state (rzf_init discards the track)
+  const bool keep = bad && jb.hold;
+  if (!keep)
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+      jb.Ainv[e] = d2f(A[e]);
+      if (jb.zero) jb.zero[e] = cz();
+    }
   if (threadIdx.x == 0) {
     if (bad) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
+    if (jb.hold) *jb.hold = bad ? 1 : 0;
     DevInfo rec;
-    rec.r = 0; rec.iters = 0; rec.path = RZF_PATH_RESET; rec.d = 0;
-    rec.dA_fro2 = 0.0; rec.captured = 0.0;
+    rec.r = 0; rec.iters = 0; rec.path = keep ? RZF_PATH_NOOP : RZF_PATH_RESET; rec.d = 0;
+    rec.dA_fro2 = keep ? __builtin_nan("") : 0.0; rec.captured = 0.0;
     if (jb.info) *jb.info = rec;
     if (jb.out) *jb.out = rec;
   }

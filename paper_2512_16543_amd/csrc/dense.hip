@@ -46,15 +46,19 @@ __global__ __launch_bounds__(1024) void k_inv64(Inv64Job one, const Inv64Job* ma
   for (int e = threadIdx.x; e < K * K; e += blockDim.x) b0[e] = A[e];
   __syncthreads();
   double2* res = gj_inverse_hpd<double2, 2>(b0, b1, K, K, &bad);
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-    Ainv[e] = d2f(res[e]);
-    if (jb.zero) jb.zero[e] = cz();
-  }
+  // a reset that fails keeps the track's state (rzf_init discards the track)
+  const bool keep = bad && jb.hold;
+  if (!keep)
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+      Ainv[e] = d2f(res[e]);
+      if (jb.zero) jb.zero[e] = cz();
+    }
   if (threadIdx.x == 0) {
     if (bad) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
+    if (jb.hold) *jb.hold = bad ? 1 : 0;
     DevInfo rec;
-    rec.r = 0; rec.iters = 0; rec.path = RZF_PATH_RESET; rec.d = 0;
-    rec.dA_fro2 = 0.0; rec.captured = 0.0;
+    rec.r = 0; rec.iters = 0; rec.path = keep ? RZF_PATH_NOOP : RZF_PATH_RESET; rec.d = 0;
+    rec.dA_fro2 = keep ? __builtin_nan("") : 0.0; rec.captured = 0.0;
     if (info) *info = rec;
     if (jb.out) *jb.out = rec;
   }

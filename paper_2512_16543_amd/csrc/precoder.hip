@@ -36,7 +36,8 @@ __global__ __launch_bounds__(64 * prec_waves<MANY>()) void k_precoder(PrecJob on
   const float2* __restrict__ X = jb.X;
   float2* __restrict__ W = jb.W;
   double* __restrict__ wpart = jb.wpart;
-  float2* __restrict__ Hcopy = jb.Hcopy;
+  // a step that met a non-finite snapshot keeps the track's previous one
+  float2* __restrict__ Hcopy = (jb.hold && *jb.hold) ? nullptr : jb.Hcopy;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int slot = wid & 3;
   const int n0 = blockIdx.x * 16;

@@ -51,6 +51,8 @@ struct TrackDesc {
   int warm;        // Xw holds a basis
   int warm_age;    // full-width SVDs whose rotations Xw has taken since it was last
                    // orthonormal to working precision
+  int hold;        // the current step met a non-finite snapshot (or its reset failed):
+                   // the precoder keeps H_prev, so the track's state stays as it was
   DevInfo info;
   int dbg[8];      // last update: [0] Jacobi sweeps, [1] Jacobi rounds, [2] QR columns
   int nsig;        // number of sigma^2 below (d of the last SVD, 0 if none)
@@ -84,6 +86,8 @@ struct Inv64Job {
   const double2* A; float2* Ainv; DevInfo* info; DevInfo* out;   // out: extra copy of info, or null
   int K;
   float2* zero;    // K x K cleared alongside (the error-feedback residual), or null
+  int* hold;       // reset step: set to 1 (state kept, nothing written) if the
+                   // inversion fails, else 0; null for rzf_init
 };
 struct Inv32Job {
   const float2* A; float2* Ainv;   // may alias: A is read into LDS first
@@ -120,6 +124,7 @@ struct PrecJob {
   const float2* H; const float2* X; float2* W; double* wpart; float2* Hcopy;
   int K, N, ldh, ldw;
   int prec;        // rzf_precision of the operands
+  const int* hold; // if set and nonzero when the kernel runs, H is not copied to Hcopy
 };
 struct ScaleJob {
   float2* W; const double* wpart;

@@ -101,6 +101,7 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "rzf_track_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+    "rzf_params_check": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int]),
     "rzf_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "rzf_ctx_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -184,6 +185,11 @@ def default_params(**kw) -> Params:
     for k, v in kw.items():
         setattr(p, k, v)
     return p
+
+
+def params_check(params: Params, K: int) -> int:
+    """rzf_params_check: RZF_OK when `params` suit a K-user track."""
+    return lib().rzf_params_check(ctypes.byref(params), int(K))
 
 
 def track_bytes(K: int, N: int) -> int:

@@ -85,6 +85,14 @@ CONFIGS: Dict[str, TrackConfig] = {
     "c5": TrackConfig("c5", seed=5, nx=32, K=256, height_m=550e3, radius_m=200e3,
                       dt_s=0.005, steps=500, kr_db=3.0, snr_db=10.0, eta=0.999,
                       p=5, k_init=2, reset_period=50),
+    # Fully digital analog of the paper's Table V / Fig. 2 scenario: 16 x 16
+    # array at 600 km, K = 16 users (a 16 x 16 Gram matrix, as after the
+    # paper's 16 RF chains), 50 ms updates over a 120 s pass, p = 1,
+    # k_init = 2, K-factor 10 dB; users in a 50 km disk at SNR 10 dB (the
+    # paper's link budget is not given in full).
+    "tv": TrackConfig("tv", seed=15, nx=16, K=16, height_m=600e3, radius_m=50e3,
+                      dt_s=0.05, steps=2400, kr_db=10.0, snr_db=10.0, eta=0.9,
+                      p=1, k_init=2, reset_period=0),
     # Hybrid front end (the paper's simulation table): 16 x 16 array, 16 RF
     # chains, 16 users, 600 km orbit, 50 ms updates over a 120 s pass, p = 1.
     # The users' disk (250 km) spreads them over about 36 beams of the 16 x 16

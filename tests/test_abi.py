@@ -90,3 +90,33 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(rzf, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no fallback"):
         rzf.lib()
+
+
+def test_params_check_ranges():
+    ok = rzf.default_params()
+    assert rzf.params_check(ok, 64) == rzf.RZF_OK
+    assert rzf.params_check(ok, 0) == rzf.RZF_E_SHAPE
+    assert rzf.params_check(ok, 257) == rzf.RZF_E_SHAPE
+    assert rzf.lib().rzf_params_check(None, 8) == rzf.RZF_E_INVALID
+    # k_init and p are bounded by RZF_KMAX (a huge value would overflow d = k0 + p)
+    for kw in (dict(k_init=0), dict(k_init=257), dict(k_init=2**31 - 1), dict(p=-1), dict(p=257),
+               dict(p=2**31 - 1), dict(i_max=65), dict(switch_ratio=0.0), dict(switch_ratio=1.5),
+               dict(P=0.0), dict(kinit_policy=2), dict(early_fallback=2), dict(precision=3),
+               dict(error_feedback=2), dict(reset_period=-1)):
+        assert rzf.params_check(rzf.default_params(**kw), 64) == rzf.RZF_E_INVALID, kw
+    assert rzf.params_check(rzf.default_params(k_init=256, p=256), 256) == rzf.RZF_OK
+
+
+def test_switch_ratio_within_woodbury_workspace():
+    # Alg. 2 takes Woodbury for k_est <= floor(ratio K); the workspace holds
+    # min(K, max(32, K / 2)) ranks, and a ratio beyond it is refused, not capped
+    def check(ratio, K):
+        return rzf.params_check(rzf.default_params(switch_ratio=ratio), K)
+    for K in (1, 16, 32):
+        assert check(1.0, K) == rzf.RZF_OK          # every rank fits
+    assert check(0.5, 64) == rzf.RZF_OK and check(0.5, 256) == rzf.RZF_OK
+    assert check(32.5 / 64, 64) == rzf.RZF_OK     # floor = 32
+    assert check(33 / 64, 64) == rzf.RZF_E_INVALID
+    assert check(1.0, 33) == rzf.RZF_E_INVALID     # 33 > 32
+    assert check(48 / 96, 96) == rzf.RZF_OK and check(49 / 96, 96) == rzf.RZF_E_INVALID
+    assert check(0.75, 256) == rzf.RZF_E_INVALID

@@ -223,7 +223,14 @@ def test_hybrid_track(ctx, eta, dt):
     d = dict(k_init=cfg.k_init, p=cfg.p, P=cfg.P, seed=cfg.seed, track_id=1, reset_period=0)
     recs = run_snapshots(ctx, heff_o, cfg.alpha, d, eta, dev_inputs=heff_g)
     print([(r["path"], r["r"], r["iters"]) for r in recs], "beam switches", switched, flush=True)
-    _assert_recs(recs)
+    # the two sides' H_eff differ by the front end's FP32 rounding (tol_eff of
+    # ||H_eff||, at both ends of a step), which moves Delta A by about
+    # 4 tol_eff ||H||^2 against ||Delta A|| ~ 2 ||H|| ||dH||: the step's own
+    # correction and sigma_j^2 / E then differ by up to 4 tol_eff ||H|| / ||dH||
+    ratio = max(np.linalg.norm(heff_o[t]) / max(np.linalg.norm(heff_o[t] - heff_o[t - 1]), 1e-30)
+                for t in range(1, steps + 1))
+    eps = 4 * tol_eff(nx, nx) * ratio
+    _assert_recs(recs, step_eps=1e-4 + eps, sig_tol=1e-5 + eps)
     if dt >= 0.5:
         assert switched >= 3
     # eq. (15) through the analog stage, for the last precoder

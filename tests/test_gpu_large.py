@@ -154,7 +154,7 @@ def test_update_large_woodbury_at_d_equal_k(ctx):
     # the capacitance solve spans two 32-column panels
     K, N = 96, 192
     Hs = _walk(K, N, 3, 50, rank=20, scale=0.05)
-    recs = run_snapshots(ctx, Hs, 1.5, _params(K, k_init=K, p=0, switch_ratio=1.0), 0.9999)
+    recs = run_snapshots(ctx, Hs, 1.5, _params(K, k_init=K, p=0, switch_ratio=0.5), 0.9999)
     _assert_recs(recs)
     assert all(r["path"] == orz.PATH_WB and 32 < r["r"] <= K // 2 for r in recs), \
         [(r["path"], r["r"]) for r in recs]
@@ -193,3 +193,25 @@ def test_full_batch_mixed_sizes(ctx):
     ctx.sync()
     for (K, N), h, w in zip(sizes, Hd, Ws):
         assert rel(host(w), orz.full_rzf(host(h), 0.5 + K / 40.0, 1.0)) <= TOL_FP32
+
+
+def test_update_c5_bf16x3_through_reset(ctx):
+    # K = 256, N = 1024 with BF16 hi/lo operands over one drift-reset period
+    # (every 50 steps): eta = 0.999 falls back to direct inversion after the
+    # d = K SVD, whose sigma_j^2 are compared in full; then the reset
+    cfg = wl.CONFIGS["c5"]
+    recs = run_track(ctx, cfg, 52, cfg.eta, dict(precision=rzf.PREC_BF16X3))
+    print([(r["t"], r["path"], r["r"]) for r in recs[::8]], flush=True)
+    _assert_recs(recs, tol=1e-4, step_eps=1e-4, sig_tol=1e-4)
+    assert [r["t"] for r in recs if r["path"] == orz.PATH_RESET] == [50]
+    assert any(r["nsig"] == 256 for r in recs)
+
+
+def test_update_c5_bf16x3_woodbury(ctx):
+    # eta = 0.9 at K = 256: Alg. 1 stops near d = 133 with r ~ 88 <= K/2, so
+    # the blocked Woodbury step runs with a multi-panel capacitance
+    cfg = wl.CONFIGS["c5"]
+    recs = run_track(ctx, cfg, 5, 0.9, dict(precision=rzf.PREC_BF16X3, reset_period=0))
+    print([(r["t"], r["path"], r["r"], r["step"]) for r in recs], flush=True)
+    _assert_recs(recs, tol=1e-4, step_eps=1e-3, sig_tol=1e-4)
+    assert sum(r["path"] == orz.PATH_WB for r in recs) >= 3

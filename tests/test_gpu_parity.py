@@ -20,6 +20,25 @@ pytestmark = pytest.mark.gpu
 
 TOL_FP32 = 1e-5
 TOL_INIT = 1e-6
+U32 = 2.0 ** -24
+# A Woodbury step's own change Delta A^-1 = A^-1_new - A^-1_prev, both sides
+# starting from the same A^-1_prev: the GPU stores A^-1_new in FP32, so its
+# entries carry rounding of up to 2^-24 of themselves, and the FP32 product
+# and difference that form it a few more such roundings (together at most
+# 4 * 2^-24 ||A^-1_new||_F); the correction U_r Sigma_r V_r^H itself is
+# formed from FP32 data (Delta A to about 1e-6 relative from FP32 sums, the
+# Jacobi stop leaving about 1e-6, the full-width basis drifting from
+# unitarity by at most 8 * 3e-6 between its re-orthonormalisations), which
+# STEP_EPS bounds with a margin of four.  Tolerance:
+#   STEP_EPS + 4 * 2^-24 ||A^-1_new||_F / ||Delta A^-1_oracle||_F.
+# At the K = 64 track a step changes A^-1 by about 3.5e-5 of itself, so this
+# is about 7e-3: a correction wrong by one percent fails.
+STEP_EPS = 1e-4
+# sigma_j^2 of the small SVD against the oracle's, relative to the step's
+# energy E = ||Delta A||_F^2: one-sided Jacobi in FP32 gives each sigma_j to
+# about c 2^-24 ||Z||_F with c ~ the column length (64), so
+# |sigma_g^2 - sigma_o^2| <= 2 c 2^-24 sigma_1 ||Delta A||_F <= 8e-6 E.
+SIG_TOL = 1e-5
 # Rank decisions: GPU (FP32 Delta A) and oracle (FP64) may disagree only when
 # a cumulative energy ratio lies within this distance of eta.
 TIE_BAND = 1e-4
@@ -212,20 +231,60 @@ def run_snapshots(ctx, Hs, alpha, d, eta, tie_band=TIE_BAND, dev_inputs=None):
             forced = True
         Ag = host(tr.inverse())
         Wg = host(W)
-        recs.append(dict(t=t, r=info.r, iters=info.iters, path=info.path, forced=forced,
-                         ainv=rel(Ag, ot.Ainv), w=rel(Wg, Wo),
-                         e=abs(info.dA_fro2 - io.dA_fro2) / max(io.dA_fro2, 1e-300)))
+        rec = dict(t=t, r=info.r, iters=info.iters, path=info.path, forced=forced,
+                   ainv=rel(Ag, ot.Ainv), w=rel(Wg, Wo),
+                   e=abs(info.dA_fro2 - io.dA_fro2) / max(io.dA_fro2, 1e-300))
+        rec.update(_step_checks(tr, info, io, ot, state["Ainv"], Ag))
+        recs.append(rec)
     tr.destroy()
     return recs
 
 
-def _assert_recs(recs, tol=TOL_FP32, max_forced=0.05):
+def _step_checks(tr, info, io, ot, A_prev, Ag):
+    """What a step's own work should match, beyond the whole of A^-1 and W:
+    the Woodbury correction Delta A^-1 (both sides from the same A^-1_prev),
+    sigma_j^2 of the small SVD, and the retained energy (captured)."""
+    out = dict(step=0.0, step_tol=float("inf"), sig=0.0, cap=0.0, nsig=0)
+    E = max(io.dA_fro2, 1e-300)
+    if info.path == orz.PATH_WB and io.path == orz.PATH_WB:
+        do = ot.Ainv - A_prev
+        nd = np.linalg.norm(do)
+        if nd > 0:
+            out["step"] = float(np.linalg.norm((Ag - A_prev) - do) / nd)
+            out["step_tol"] = STEP_EPS + 4 * U32 * float(np.linalg.norm(Ag)) / nd
+    s2g = np.asarray(tr.sigma2())
+    res = ot.last_arsvd
+    if s2g.size and res is not None and info.path in (orz.PATH_WB, orz.PATH_FULL_RANK) \
+            and s2g.size == res.sigma.size:
+        s2o = np.sort(res.sigma ** 2)[::-1]
+        m = s2g.size if s2g.size == ot.K else info.r     # d = K: every sigma_j is the exact one
+        out["sig"] = float(np.max(np.abs(s2g[:m] - s2o[:m])) / E)
+        out["nsig"] = m
+    if info.path in (orz.PATH_WB, orz.PATH_FULL_RANK, orz.PATH_FULL_SINGULAR):
+        out["cap"] = abs(info.captured - io.captured) / E
+    return out
+
+
+def _assert_recs(recs, tol=TOL_FP32, max_forced=0.05, step_eps=STEP_EPS, sig_tol=SIG_TOL):
     worst_a = max(r["ainv"] for r in recs)
     worst_w = max(r["w"] for r in recs)
     forced = sum(r["forced"] for r in recs)
     assert worst_a <= tol, worst_a
     assert worst_w <= tol, worst_w
     assert forced <= max_forced * len(recs) + 1, forced
+    steps = [r for r in recs if r.get("step_tol", float("inf")) < float("inf")]
+    if steps:
+        w = max(steps, key=lambda r: r["step"])
+        print(f"[parity] A^-1 {worst_a:.2e} W {worst_w:.2e}; Woodbury steps {len(steps)}, worst own-change "
+              f"err {w['step']:.2e} (tol {w['step_tol'] - STEP_EPS + step_eps:.2e}); sigma^2/E "
+              f"{max(r.get('sig', 0.0) for r in recs):.2e}, captured/E {max(r.get('cap', 0.0) for r in recs):.2e}",
+              flush=True)
+    for r in recs:
+        if "step" in r:
+            assert r["step"] <= r["step_tol"] - STEP_EPS + step_eps, \
+                (r["t"], r["step"], r["step_tol"] - STEP_EPS + step_eps)
+            assert r["sig"] <= sig_tol, (r["t"], r["sig"])
+            assert r["cap"] <= sig_tol, (r["t"], r["cap"])
 
 
 def test_update_c1_track(ctx):

@@ -491,6 +491,40 @@ def test_track_switch_and_reset_paths():
     assert orz.PATH_RESET not in paths[:2] + paths[3:5]
 
 
+def test_track_nonfinite_snapshot_leaves_state():
+    # a NaN snapshot changes nothing but the counters: the steps that follow
+    # equal those of a track that never saw it (the same sketch draws, since
+    # Omega is addressed by the step index, are taken from a twin whose step
+    # counter skipped the same index)
+    cfg, Hs = _track_inputs(steps=5)
+    prm = orz.TrackParams(alpha=cfg.alpha, reset_period=3)
+    a = orz.OracleTrack(Hs[0], prm)
+    b = orz.OracleTrack(Hs[0], prm)
+    a.update(Hs[1], 0.99)
+    b.update(Hs[1], 0.99)
+    bad = Hs[2].copy()
+    bad[1, 3] = np.nan
+    st = a.export_state()
+    W, info = a.update(bad, 0.99)
+    assert info.path == orz.PATH_NOOP and info.r == 0 and math.isnan(info.dA_fro2)
+    assert not np.all(np.isfinite(W))
+    after = a.export_state()
+    for k in ("Ainv", "H_prev", "R"):
+        assert np.array_equal(after[k], st[k]), k
+    assert (after["t"], after["since_reset"], after["last_r"]) == (st["t"] + 1, st["since_reset"] + 1, st["last_r"])
+    b.t += 1                        # the twin skips the same step index ...
+    b.since_reset += 1              # ... and counts it towards the reset
+    paths = []
+    for t in (3, 4, 5):
+        Wa, ia = a.update(Hs[t], 0.99)
+        Wb, ib = b.update(Hs[t], 0.99)
+        assert (ia.r, ia.iters, ia.path) == (ib.r, ib.iters, ib.path), t
+        assert np.array_equal(Wa, Wb) and np.array_equal(a.Ainv, b.Ainv)
+        paths.append(ia.path)
+    # reset_period 3: step 2 (the NaN one) counted, so step 3 re-inverts
+    assert paths[0] == orz.PATH_RESET and orz.PATH_RESET not in paths[1:]
+
+
 def test_track_noop_when_channel_static():
     cfg, Hs = _track_inputs(steps=2)
     ot = orz.OracleTrack(Hs[0], orz.TrackParams(alpha=cfg.alpha))
