@@ -29,6 +29,22 @@ if ROOT not in sys.path:
 
 METRIC = "RZF precoder updates/s, WB-arSVD vs full inverse, K=64 N=256; p99 latency"
 FP32_MFMA_PEAK_TFLOPS = 157.3
+# FP32 vector peak without packed FP32 instructions (every HIP source is built
+# with them off): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 78.6
+
+
+def metric_for(cfg):
+    """The headline metric string for a single-track configuration."""
+    return f"RZF precoder updates/s, WB-arSVD vs full inverse, K={cfg.K} N={cfg.N}; p99 latency"
+
+
+def kernel_flops(name, K, N):
+    """Algorithmic real flops of one track's share of a GEMM-shaped kernel
+    (8 per complex multiply-add): the Gram kernel forms A' (4 K^2 N, lower
+    half) and Delta A (8 K^2 N, lower half); the precoder 8 K^2 N; the
+    sum-rate tiles E = H W, 8 K^2 N."""
+    return {"gram": 12.0 * K * K * N, "precoder": 8.0 * K * K * N, "sum_rate": 8.0 * K * K * N}.get(name)
 
 
 def parse():
@@ -52,6 +68,8 @@ def parse():
     ap.add_argument("--tune-switch", action="store_true",
                     help="Alg. 2's switch ratio from rzf_tune_switch (measured costs) instead of 0.5")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the eta sweep of the K=64 track")
+    ap.add_argument("--sweep-steps", type=int, default=300)
     ap.add_argument("--batch-tracks", type=int, default=512,
                     help="independent tracks of the same configuration in the batched pass (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -228,7 +246,7 @@ def main():
     print(f"[bench] full timed: {full_s:.3f}s", file=sys.stderr, flush=True)
 
     out = {
-        "metric": METRIC,
+        "metric": METRIC if a.config == "c2" else metric_for(cfg),
         "value": K_steps / wb_s,
         "unit": "updates/s",
         "n_gpus": 1,
@@ -309,12 +327,13 @@ def main():
     traffic = None
     if dom == "arsvd_wb" and (K, N) == (64, 256) and a.config == "c2":
         traffic = measured_traffic("k_arsvd_wb_k64_n256")
-    # k_arsvd_wb's instruction mix is VALU (counters: SQ_INSTS_VALU against SQ_INSTS_MFMA); its
-    # peak is the FP32 vector rate, 256 CUs x 4 SIMD x 16 lanes x 2 x 2.4 GHz = 157.3 TFLOP/s
+    # k_arsvd_wb's instruction mix is VALU (counters: SQ_INSTS_VALU against SQ_INSTS_MFMA): its
+    # peak is the FP32 vector rate without packed instructions, 78.6 TFLOP/s
     bound = "alu" if dom == "arsvd_wb" else "mfma"
+    peak = FP32_VALU_PEAK_TFLOPS if bound == "alu" else FP32_MFMA_PEAK_TFLOPS
     out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved,
-                       "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": traffic,
+                       "peak": peak, "unit": "TFLOP/s",
+                       "frac": achieved / peak, "traffic": traffic,
                        "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                        "flops_per_launch": per_launch, "avg_launch_us": avg_s * 1e6,
                        "work": unit_note}
@@ -329,12 +348,109 @@ def main():
         out["switch_tuning"] = tuned   # rzf_tune_switch's fit (cycles after the SVD)
     # FP64 CPU oracle on a bounded sample of the same track
     if not a.no_cpu_baseline:
+        kept = []
         out["cpu_baseline"] = cpu_baseline(cfg, eta, Hs_np, a.cpu_seconds, policy, int(a.early_fallback),
-                                           int(a.error_feedback), switch_ratio)
+                                           int(a.error_feedback), switch_ratio, keep=kept)
         print(f"[bench] cpu baseline done", file=sys.stderr, flush=True)
+        out["oracle_error"] = gpu_vs_oracle(ctx, cfg, eta, Hs, kept, params(0), rates)
+    if not a.no_sweep and a.config == "c2":
+        out["eta_sweep"] = eta_sweep(ctx, cfg, Hs, min(K_steps, a.sweep_steps), params, W, rates)
+        print(f"[bench] eta sweep done", file=sys.stderr, flush=True)
     ctx.close()
     print(json.dumps(out), flush=True)
     return 0
+
+
+def gpu_vs_oracle(ctx, cfg, eta, Hs, kept, prm, rates):
+    """The GPU's error against the FP64 oracle over the steps of the CPU
+    sample: a fresh track run over the same snapshots, each side carrying its
+    own state (trajectory, no re-seeding); relative Frobenius error of A^-1 and
+    W per step, and of the sum rate."""
+    import numpy as np
+    import torch
+    n = len(kept)
+    if n == 0:
+        return None
+    W = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device=Hs.device)
+    tr = ctx.init(Hs[0], cfg.alpha, prm)
+    ea, ew, er, paths = [], [], [], []
+    for t in range(1, n + 1):
+        info = tr.update(Hs[t], eta, W)
+        R = ctx.sum_rate(Hs[t], W, cfg.P, cfg.sigma2, rates)
+        Wo, Ao, Ro = kept[t - 1]
+        Ag = tr.inverse().cpu().numpy().astype(np.complex128)
+        Wg = W.cpu().numpy().astype(np.complex128)
+        ea.append(float(np.linalg.norm(Ag - Ao) / np.linalg.norm(Ao)))
+        ew.append(float(np.linalg.norm(Wg - Wo) / np.linalg.norm(Wo)))
+        er.append(abs(R - Ro) / abs(Ro))
+        paths.append(info.path)
+    tr.destroy()
+    return {"steps": n, "ainv_rel_max": max(ea), "w_rel_max": max(ew), "sum_rate_rel_max": max(er),
+            "ainv_rel_last": ea[-1], "resets": paths.count(4),
+            "note": "GPU (FP32, FP64 capacitance and reset) against the FP64 oracle over the CPU sample's "
+                    "steps, each side carrying its own state"}
+
+
+def eta_sweep(ctx, cfg, Hs, steps, params, W, rates):
+    """Single-track throughput of WB-arSVD against full inversion at the paper's
+    Table V thresholds (and 0.99), with the fixed and warm-start k_init
+    policies: updates/s of each (update + sum rate, one track), the paths and
+    ranks taken, and the method's sum-rate loss against full inversion."""
+    import numpy as np
+    import torch
+    from paper_2512_16543_amd import rzf
+    rows = []
+    Wf = torch.empty_like(W)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        ctx.sync()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def full_pass():
+        for t in range(1, steps + 1):
+            ctx.full(Hs[t], cfg.alpha, cfg.P, Wf)
+            ctx.sum_rate_async(Hs[t], Wf, cfg.P, cfg.sigma2, rates)
+
+    full_s = timed(full_pass)
+    R_full = []
+    for t in range(1, steps + 1):
+        ctx.full(Hs[t], cfg.alpha, cfg.P, Wf)
+        R_full.append(ctx.sum_rate(Hs[t], Wf, cfg.P, cfg.sigma2))
+    for eta in (0.99, 0.9, 0.8, 0.65):
+        for pol, code in (("fixed", rzf.KINIT_FIXED), ("warm", rzf.KINIT_WARM)):
+            prm = params(0)
+            prm.kinit_policy = code
+            tr = ctx.init(Hs[0], cfg.alpha, prm)
+
+            def wb_pass():
+                for t in range(1, steps + 1):
+                    tr.update(Hs[t], eta, W, want_info=False)
+                    ctx.sum_rate_async(Hs[t], W, cfg.P, cfg.sigma2, rates)
+
+            wb_s = timed(wb_pass)
+            tr.destroy()
+            tr = ctx.init(Hs[0], cfg.alpha, prm)
+            infos, R_wb = [], []
+            for t in range(1, steps + 1):
+                infos.append(tr.update(Hs[t], eta, W))
+                R_wb.append(ctx.sum_rate(Hs[t], W, cfg.P, cfg.sigma2))
+            tr.destroy()
+            nr = [i for i in infos if i.path != rzf.PATH_RESET]
+            rows.append({"eta": eta, "policy": pol, "wb_updates_per_s": steps / wb_s,
+                         "full_updates_per_s": steps / full_s, "speedup_vs_full_inverse": full_s / wb_s,
+                         "sum_rate_loss": float(1.0 - np.mean(R_wb) / np.mean(R_full)),
+                         "r_mean": float(np.mean([i.r for i in nr])),
+                         "iters_mean": float(np.mean([i.iters for i in nr])),
+                         "wb_fraction": float(np.mean([i.path == rzf.PATH_WB for i in nr]))})
+            print(f"[bench] sweep eta={eta} {pol}: {rows[-1]['wb_updates_per_s']:.0f} vs "
+                  f"{rows[-1]['full_updates_per_s']:.0f} updates/s, loss {rows[-1]['sum_rate_loss']:.2e}",
+                  file=sys.stderr, flush=True)
+    return {"steps": steps, "rows": rows,
+            "note": "one track, batch 1, update + sum rate per step; loss = 1 - mean R(WB) / mean R(full)"}
 
 
 def batched(a, cfgs, eta, policy):
@@ -410,12 +526,27 @@ def batched(a, cfgs, eta, policy):
         fl = sum(8.0 * c.K * c.K * c.N for c in cfgs)
     else:
         fl = 0.0
+    bpk = FP32_VALU_PEAK_TFLOPS if dom == "arsvd_wb" else FP32_MFMA_PEAK_TFLOPS
     res["roofline"] = {"kernel": dom, "bound": "alu" if dom == "arsvd_wb" else "mfma",
                        "achieved": fl / dur / 1e12,
-                       "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": fl / dur / 1e12 / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                       "peak": bpk, "unit": "TFLOP/s",
+                       "frac": fl / dur / 1e12 / bpk, "traffic": None,
                        "flops_per_launch": fl, "avg_launch_us": dur * 1e6,
                        "paths": {str(p): sum(1 for i in infos if i.path == p) for p in range(5)}}
+    # the GEMM-shaped kernels of the same batched step against the FP32
+    # matrix-core peak (their operands at this precision)
+    mf = {}
+    for name in ("gram", "precoder", "sum_rate"):
+        if name not in prof:
+            continue
+        c, ms = prof[name]
+        us = 1e3 * ms / c
+        f = sum(kernel_flops(name, cf.K, cf.N) for cf in cfgs)
+        if name == "gram":     # reset steps run the FP64 Gram instead
+            f = sum(kernel_flops(name, cf.K, cf.N) for cf, i in zip(cfgs, infos) if i.path != 4)
+        mf[name] = {"avg_us": us, "flops": f, "achieved_tflops": f / (us * 1e-6) / 1e12,
+                    "frac": f / (us * 1e-6) / 1e12 / FP32_MFMA_PEAK_TFLOPS}
+    res["mfma_kernels"] = mf
     ctx.close()
     return res
 
@@ -703,14 +834,33 @@ def table_v(a):
             "rows": rows}
 
 
-def cpu_baseline(cfg, eta, Hs_np, budget_s, policy, early_fallback=0, error_feedback=0, switch_ratio=0.5):
-    import numpy as np
-    import oracle.rzf as orz
+def host_cores():
+    """Cores this process may run on, the BLAS libraries NumPy uses and their
+    thread counts."""
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    blas, threads = [], 1
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        for i in threadpool_info():
+            if i.get("user_api") == "blas":
+                blas.append(f"{i.get('internal_api')} {i.get('version')} ({i.get('num_threads')} threads)")
+                threads = max(threads, int(i.get("num_threads") or 1))
     except Exception:
-        threads = 1
+        pass
+    return nproc, threads, "; ".join(blas) or "unknown"
+
+
+def cpu_baseline(cfg, eta, Hs_np, budget_s, policy, early_fallback=0, error_feedback=0, switch_ratio=0.5,
+                 keep=None):
+    """The FP64 oracle (update + sum rate) on the first steps of the track for
+    about budget_s seconds.  keep: a list that receives each step's
+    (W, A^-1, sum rate) for the GPU's error against the oracle."""
+    import numpy as np
+    import oracle.rzf as orz
+    nproc, threads, blas = host_cores()
     H = Hs_np.astype(np.complex128)
     prm = orz.TrackParams(alpha=cfg.alpha, P=cfg.P, k_init=cfg.k_init, p=cfg.p,
                           reset_period=cfg.reset_period, seed=cfg.seed, track_id=0,
@@ -721,13 +871,17 @@ def cpu_baseline(cfg, eta, Hs_np, budget_s, policy, early_fallback=0, error_feed
     n = 0
     for t in range(1, H.shape[0]):
         Wt, _ = ot.update(H[t], eta)
-        orz.sum_rate(H[t], Wt, cfg.P, cfg.sigma2)
+        _, R = orz.sum_rate(H[t], Wt, cfg.P, cfg.sigma2)
+        if keep is not None:
+            keep.append((Wt, ot.Ainv.copy(), R))
         n += 1
         if time.perf_counter() - t0 > budget_s:
             break
     el = time.perf_counter() - t0
-    return {"value": n / el, "unit": "updates/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {n} steps of the same track (update + sum rate, complex128 NumPy)"}
+    return {"value": n / el, "unit": "updates/s", "cores": int(threads), "nproc": int(nproc),
+            "blas": blas, "kind": "oracle",
+            "sample": f"first {n} steps of the same track (update + sum rate, complex128 NumPy, one process; "
+                      f"cores = the BLAS threads it used, nproc = cores available)"}
 
 
 if __name__ == "__main__":
