@@ -232,6 +232,26 @@ typedef struct {
  * cannot).  1 <= n <= RZF_BATCH_MAX. */
 rzf_status rzf_full_batch(rzf_ctx* ctx, int n, const rzf_full_item* items);
 
+/* rzf_full for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and result, launched on `hip_stream` (a hipStream_t; NULL =
+ * the null stream) of the calling thread's current device, with no context.
+ * Its intermediate buffers live in a fixed device array of the library
+ * (1,050,624 bytes per device, held until the process ends), so it calls no
+ * allocator; the array's device address is resolved on the first call on
+ * each device.  Every call on a device shares that array: calls that overlap
+ * on one device (two streams, two threads) race and must be serialised by
+ * the caller.  Nothing in it needs clearing between calls.
+ *  - 1 <= K <= RZF_KMAX, 1 <= N <= RZF_NMAX, ldh >= N, ldw >= K, else
+ *    RZF_E_SHAPE (the array is sized for the largest such call);
+ *    alpha >= 0 and P > 0 finite, H and W not NULL, else RZF_E_INVALID.
+ *  - err: device int, or NULL.  If the Gram matrix is not positive definite
+ *    the kernels store 1 there (2 for a non-finite value), when it is still 0;
+ *    the caller clears it.  W is then not meaningful.
+ * Asynchronous; returns RZF_E_DEVICE if a launch fails. */
+rzf_status rzf_full_noalloc(void* hip_stream, int K, int N, const rzf_c32* H, int ldh, double alpha,
+                            double P, rzf_c32* W, int ldw, int* err);
+
 /* Sum rate of eq. (15): W is first scaled to ||W||_F^2 = P, then E = H W,
  * SINR_n = |E_nn|^2 / (sum_{i != n} |E_ni|^2 + sigma2), rate_n = log2(1+SINR_n).
  * rates: device pointer to K floats, or NULL.  sum_rate: host pointer; if not

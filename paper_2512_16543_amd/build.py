@@ -23,7 +23,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librzf.so")
 ARCH = "gfx950"
 
-SOURCES = ["gram.hip", "precoder.hip", "dense.hip", "arsvd.hip", "arsvd_big.hip", "sumrate.hip", "beams.hip", "api.cpp", "server.cpp"]
+SOURCES = ["gram.hip", "precoder.hip", "dense.hip", "arsvd.hip", "arsvd_big.hip", "sumrate.hip", "beams.hip",
+           "noalloc.hip", "api.cpp", "server.cpp"]
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

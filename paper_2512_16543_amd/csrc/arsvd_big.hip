@@ -995,7 +995,7 @@ __global__ __launch_bounds__(NTH) void k_inv32_big(Inv32Job one, const Inv32Job*
     for (int e = threadIdx.x; e < K * K; e += blockDim.x) Ainv[e] = jb.A[e];
   __syncthreads();
   gj_inverse_hpd_blocked<float2>(Ainv, K, K, xs, cs, pb, &bad);
-  if (threadIdx.x == 0 && bad) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
+  if (threadIdx.x == 0 && bad && err) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
 }
 
 }  // namespace

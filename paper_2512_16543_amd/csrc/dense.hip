@@ -30,7 +30,7 @@ __global__ __launch_bounds__(1024) void k_inv32(Inv32Job one, const Inv32Job* ma
     const int i = e / K, j = e - i * K;
     Ainv[e] = b0[i * KS + j];
   }
-  if (threadIdx.x == 0 && bad) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
+  if (threadIdx.x == 0 && bad && err) atomicCAS(err, 0, bad == 2 ? DEV_ERR_NONFINITE : DEV_ERR_NOT_HPD);
 }
 
 template <bool MANY>

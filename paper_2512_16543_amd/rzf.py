@@ -102,6 +102,9 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "rzf_track_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
     "rzf_params_check": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int]),
+    "rzf_full_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                        ctypes.c_int, ctypes.c_void_p]),
     "rzf_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                       ctypes.POINTER(ctypes.c_void_p)]),
     "rzf_ctx_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -190,6 +193,24 @@ def default_params(**kw) -> Params:
 def params_check(params: Params, K: int) -> int:
     """rzf_params_check: RZF_OK when `params` suit a K-user track."""
     return lib().rzf_params_check(ctypes.byref(params), int(K))
+
+
+def full_noalloc(H, alpha: float, P: float, W, err=None, stream=None):
+    """rzf_full_noalloc on H's device: W = full-inversion RZF of H, with the
+    library's fixed device scratch (no context, no allocation).  err: an int32
+    device tensor of one element, or None.  stream: a torch stream (None:
+    the current one)."""
+    import torch
+    hp, ldh = _mat_args(H)
+    wp, ldw = _mat_args(W)
+    K, N = H.shape
+    if tuple(W.shape) != (N, K):
+        raise ValueError("shape mismatch")
+    with torch.cuda.device(H.device):
+        s = stream if stream is not None else torch.cuda.current_stream(H.device)
+        ep = ctypes.c_void_p(err.data_ptr()) if err is not None else None
+        _check(lib().rzf_full_noalloc(ctypes.c_void_p(s.cuda_stream), int(K), int(N), ctypes.c_void_p(hp), ldh,
+                                      float(alpha), float(P), ctypes.c_void_p(wp), ldw, ep), "rzf_full_noalloc")
 
 
 def track_bytes(K: int, N: int) -> int:

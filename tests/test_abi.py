@@ -120,3 +120,18 @@ def test_switch_ratio_within_woodbury_workspace():
     assert check(1.0, 33) == rzf.RZF_E_INVALID     # 33 > 32
     assert check(48 / 96, 96) == rzf.RZF_OK and check(49 / 96, 96) == rzf.RZF_E_INVALID
     assert check(0.75, 256) == rzf.RZF_E_INVALID
+
+
+def test_full_noalloc_argument_checks_without_device():
+    # refused before anything reaches a device (the pointers are never read)
+    L = rzf.lib()
+    fake = ctypes.c_void_p(256)
+    assert L.rzf_full_noalloc(None, 4, 4, None, 4, 1.0, 1.0, fake, 4, None) == rzf.RZF_E_INVALID
+    assert L.rzf_full_noalloc(None, 257, 4, fake, 4, 1.0, 1.0, fake, 257, None) == rzf.RZF_E_SHAPE
+    assert L.rzf_full_noalloc(None, 4, 4097, fake, 4097, 1.0, 1.0, fake, 4, None) == rzf.RZF_E_SHAPE
+    assert L.rzf_full_noalloc(None, 0, 4, fake, 4, 1.0, 1.0, fake, 4, None) == rzf.RZF_E_SHAPE
+    assert L.rzf_full_noalloc(None, 4, 8, fake, 7, 1.0, 1.0, fake, 4, None) == rzf.RZF_E_SHAPE
+    assert L.rzf_full_noalloc(None, 4, 8, fake, 8, 1.0, 1.0, fake, 3, None) == rzf.RZF_E_SHAPE
+    assert L.rzf_full_noalloc(None, 4, 8, fake, 8, -1.0, 1.0, fake, 4, None) == rzf.RZF_E_INVALID
+    assert L.rzf_full_noalloc(None, 4, 8, fake, 8, float("nan"), 1.0, fake, 4, None) == rzf.RZF_E_INVALID
+    assert L.rzf_full_noalloc(None, 4, 8, fake, 8, 1.0, 0.0, fake, 4, None) == rzf.RZF_E_INVALID
