@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -150,6 +151,9 @@ rzf_status dev_status(int code) {
 
 #define HIP_OK(x) do { if ((x) != hipSuccess) return RZF_E_DEVICE; } while (0)
 
+// Two-phase arSVD launches in this process (their tags in the speculation area).
+std::atomic<unsigned long long> g_spec_seq{0};
+
 // Kernel families by track size: K <= KS keeps the working set in LDS, larger
 // tracks use the blocked kernels on a global workspace.
 void inv64_any(const Inv64Job& j, int* err, hipStream_t s) {
@@ -167,6 +171,9 @@ void arsvd_single(rzf_ctx* c, ArsvdJob j, int K, hipStream_t s) {
   } else {
     j.spec = c->d_spec;
     j.stage = reinterpret_cast<char*>(c->d_spec) + SPEC_STAGE_OFF;
+    // numbered across the process, so that no tag left in reused device
+    // memory by an earlier context can match
+    j.seq = ++g_spec_seq;
     launch_arsvd_wb_spec(j, c->d_err, s);
   }
 }
@@ -399,6 +406,10 @@ rzf_status rzf_ctx_create(int device, void* hip_stream, void* arena, size_t aren
   bool stage_ok = hipHostMalloc((void**)&c->h_stage, NSTAGE * STAGE_BYTES, hipHostMallocDefault) == hipSuccess;
   for (int k = 0; k < NSTAGE && stage_ok; ++k)
     stage_ok = hipEventCreateWithFlags(&c->stage_ev[k], hipEventDisableTiming) == hipSuccess;
+  // the speculation area starts with no iteration posted (its tags zero)
+  if (stage_ok)
+    stage_ok = hipMemset(reinterpret_cast<char*>(c->d_spec) + sizeof(float2) * 2 * KS * KS * SPEC_MAX, 0,
+                         SPEC_STAGE_OFF - sizeof(float2) * 2 * KS * KS * SPEC_MAX) == hipSuccess;
   if (!stage_ok || hipMemcpy(c->d_err, c->h_err, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
     for (int k = 0; k < NSTAGE; ++k) if (c->stage_ev[k]) (void)hipEventDestroy(c->stage_ev[k]);
     if (c->h_stage) (void)hipHostFree(c->h_stage);

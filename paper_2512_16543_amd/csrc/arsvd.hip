@@ -23,12 +23,14 @@
 //   the Woodbury branch), so U_r Sigma_r V_r^H = sum_{j<=r} u_j z_j^H.
 //   After I_max failing iterations r = d and U_r Sigma_r V_r^H = Q Z^H.
 // Full width (d = K): Q is unitary, so B = Q^H Delta A has the singular
-// values of Delta A and Q U_hat its left singular vectors whatever Q is.
+// values of Delta A whatever Q is, and U_r = Q Q^H Delta A Z_r Sigma_r^-2 is
+// Delta A Z_r Sigma_r^-2 (one product).
 //   Such an iteration takes as Q the track's basis from its previous
-//   full-width SVD (re-orthonormalised every POLISH_EVERY uses) instead of a
-//   fresh Householder Q, and the Jacobi sweeps rotate it along with Z: Q J
-//   is then U_hat itself, U_r its leading columns and the next step's start.
-//   Consecutive Delta A differ little, so about half the passes suffice.
+//   full-width SVD instead of a fresh Householder Q: the normalised columns
+//   z_j / sigma_j of that SVD, the right singular vectors V_hat of B,
+//   orthonormal to the Jacobi's tolerance.  For a Hermitian Delta A they are
+//   its eigenvectors (up to signs and phases), and consecutive Delta A differ
+//   little, so about half the passes suffice.
 //
 // Single-track updates run the kernel in two launches (PH = 1, 2 below): the
 // iterations the previous step predicts are computed at once, one workgroup
@@ -60,9 +62,16 @@ constexpr int NTH = 1024;
 constexpr int LDK = KS + 1;
 constexpr int NWV = NTH / 64;
 constexpr int MAX_SWEEPS = 30;
-// a track's full-width basis is re-orthonormalised (one Newton-Schulz step)
-// before its use once it has taken this many SVDs' rotations
-constexpr int POLISH_EVERY = 8;
+// the next full-width starting basis normalises every column z_j of a
+// full-width SVD; one with sigma_j^2 at or below this fraction of the largest
+// (numerically zero: the Jacobi sweeps cannot have made it orthogonal to the
+// others) leaves the track without a basis, and its next full-width step
+// starts from a fresh Householder Q
+constexpr double BASIS_MIN_REL = 1e-20;
+// two-phase form: longest wait (constant-rate clock ticks, 100 MHz) of the
+// full-width iteration's workgroup for the earlier iterations' energy tests
+// before it starts its SVD
+constexpr long long SPEC_WAIT_TICKS = 10000;
 // capacitance C = I + E: with ||E||_F <= NEUMANN_MAX the system C X = M is
 // solved by X <- M - E X, the error shrinking by ||E||_F per pass, until it
 // is below 2^-NEUMANN_BITS of X (under the FP32 rounding X then takes),
@@ -102,6 +111,8 @@ struct Shared {
   int gjpr[2], gjsing[2];
   int nrot, r, found, bad;
   double cap;
+  float bsc[KS];                 // 1 / sigma_j of a full-width SVD (its basis columns)
+  int bok;                       // that SVD's columns can all be normalised
 };
 
 // Householder vector of column c (rows >= c) of the column-major matrix `a`
@@ -180,9 +191,9 @@ __device__ __forceinline__ void lds_gemm(int M, int Nc, int Kd, const LA& la, co
 // alt, bet; otherwise alt, bet carry them in from the previous rotation and
 // leave updated by the rotation's exact effect on them: ||z_p||^2 - t |gamma|
 // and ||z_q||^2 + t |gamma| (the pair's energy moves by t |gamma|).
-template <bool ACC, bool FRESH>
-__device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], float2 xp[4], float2 xq[4], bool act,
-                                              bool& moved, float& alt, float& bet) {
+template <bool FRESH>
+__device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], bool act, bool& moved, float& alt,
+                                              float& bet) {
   float al = 0.f, be = 0.f, grf32 = 0.f, gif32 = 0.f;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
@@ -242,32 +253,17 @@ __device__ __forceinline__ void jacobi_rotate(float2 zp[4], float2 zq[4], float2
       zq[m] = cadd(cscale(zp[m], s), cscale(zq2, c));
       zp[m] = np;
     }
-    if constexpr (ACC) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const float2 xq2 = cmul(e, xq[m]);
-        const float2 np = csub(cscale(xp[m], c), cscale(xq2, s));
-        xq[m] = cadd(cscale(xp[m], s), cscale(xq2, c));
-        xp[m] = np;
-      }
-    }
   }
 }
 
-template <bool ACC>
 __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* rounds_out) {
-  float2* b1 = sm.b1;
   float2* b2 = sm.b2;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int nb = ((d + 3) / 4 + 1) & ~1;   // blocks of 4 columns, an even number (<= 16)
   const int nw = nb / 2;                   // waves holding a block pair
-  for (int e = threadIdx.x; e < (4 * nb - d) * LDK; e += NTH) {
-    b2[d * LDK + e] = cz();
-    if constexpr (ACC) b1[d * LDK + e] = cz();
-  }
+  for (int e = threadIdx.x; e < (4 * nb - d) * LDK; e += NTH) b2[d * LDK + e] = cz();
   int sweeps = 0, rounds = 0;
-  float2 xp[4], xq[4];   // basis columns (ACC), moved like the Z columns
   for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
     if (threadIdx.x == 0) sm.nrot = 0;
     __syncthreads();
@@ -282,28 +278,18 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
         rr_pair(t, m, 4, &p, &q);
         float2* zpc = b2 + (c0 + p) * LDK + li;
         float2* zqc = b2 + (c0 + q) * LDK + li;
-        float2* xpc = b1 + (c0 + p) * LDK + li;
-        float2* xqc = b1 + (c0 + q) * LDK + li;
         float2 zp[4], zq[4];
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
           zp[mm] = zpc[16 * mm];
           zq[mm] = zqc[16 * mm];
-          if constexpr (ACC) {
-            xp[mm] = xpc[16 * mm];
-            xq[mm] = xqc[16 * mm];
-          }
         }
         float alt, bet;
-        jacobi_rotate<ACC, true>(zp, zq, xp, xq, true, moved, alt, bet);
+        jacobi_rotate<true>(zp, zq, true, moved, alt, bet);
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
           zpc[16 * mm] = zp[mm];
           zqc[16 * mm] = zq[mm];
-          if constexpr (ACC) {
-            xpc[16 * mm] = xp[mm];
-            xqc[16 * mm] = xq[mm];
-          }
         }
         wave_sync();
       }
@@ -317,17 +303,11 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
         rr_pair(sr, wid, nb, &A, &B);
         float2* zac = b2 + (4 * A + g) * LDK + li;
         float2* zbc = b2 + (4 * B + g) * LDK + li;
-        float2* xac = b1 + (4 * A + g) * LDK + li;
-        float2* xbc = b1 + (4 * B + g) * LDK + li;
         float2 za[4], zb[4];
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
           za[mm] = zac[16 * mm];
           zb[mm] = zbc[16 * mm];
-          if constexpr (ACC) {
-            xp[mm] = xac[16 * mm];
-            xq[mm] = xbc[16 * mm];
-          }
         }
         const int up = (lane + 16) & 63;
         // the norms are summed at the first step of the super-round and
@@ -336,23 +316,16 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           // column 4A + g with column 4B + (g + t) % 4
-          if (t == 0) jacobi_rotate<ACC, true>(za, zb, xp, xq, true, moved, alt, bet);
-          else jacobi_rotate<ACC, false>(za, zb, xp, xq, true, moved, alt, bet);
+          if (t == 0) jacobi_rotate<true>(za, zb, true, moved, alt, bet);
+          else jacobi_rotate<false>(za, zb, true, moved, alt, bet);
 #pragma unroll
-          for (int mm = 0; mm < 4; ++mm) {
-            zb[mm] = make_float2(__shfl(zb[mm].x, up), __shfl(zb[mm].y, up));
-            if constexpr (ACC) xq[mm] = make_float2(__shfl(xq[mm].x, up), __shfl(xq[mm].y, up));
-          }
+          for (int mm = 0; mm < 4; ++mm) zb[mm] = make_float2(__shfl(zb[mm].x, up), __shfl(zb[mm].y, up));
           bet = __shfl(bet, up);
         }
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm) {
           zac[16 * mm] = za[mm];
           zbc[16 * mm] = zb[mm];
-          if constexpr (ACC) {
-            xac[16 * mm] = xp[mm];
-            xbc[16 * mm] = xq[mm];
-          }
         }
       }
       rounds += 4;
@@ -546,10 +519,18 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   // the second phase takes E from the first (the same sum of the same
   // values) and loads Delta A only when it goes on past a commit
   double* const spec_d = PH == 0 ? nullptr : reinterpret_cast<double*>(jb.spec + (size_t)2 * KS * KS * SPEC_MAX);
+  // two-phase form: tags[i] = this launch's number once iteration i + 1 has
+  // posted ||Z||_F^2; tags[SPEC_MAX] once the first phase has written the
+  // whole step to the track
+  unsigned long long* const tags = PH == 0 ? nullptr : reinterpret_cast<unsigned long long*>(spec_d + SPEC_MAX + 1);
   bool dA_in = PH != 2;
   double E;
   if constexpr (PH == 2) {
     E = spec_d[SPEC_MAX];
+    // the first phase may have completed the step already
+    if (tid == 0) sm.found = tags[SPEC_MAX] == jb.seq;
+    __syncthreads();
+    if (sm.found) return;
   } else {
     E = load_dA();
     if (PH == 1 && blockIdx.x == 0 && tid == 0) spec_d[SPEC_MAX] = E;
@@ -585,13 +566,14 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   double captured = 0.0;
   bool found = false, rotated = false;
   // iterations computed ahead in the two-phase form: the last count plus one
-  const int n_spec = PH == 0 ? 0 : min(min(i_max, SPEC_MAX), max(td->spec_hint, 0) + 1);
+  // (a track's first step, with no count yet, computes every iteration ahead)
+  const int n_spec = PH == 0 ? 0
+                             : min(min(i_max, SPEC_MAX), td->spec_hint > 0 ? td->spec_hint + 1 : i_max);
   // a full-width sketch (d = K) has a unitary Q, and the SVD of B = Q^H Delta A
   // then yields the truncated SVD of Delta A whatever Q is: such an iteration
   // starts from the track's basis of its last full-width SVD when it has one
   const bool warm_ok = td->warm != 0;
-  const bool polish = warm_ok && td->warm_age >= POLISH_EVERY;
-  bool basis = false;   // the SVD ran at d = K and rotated b1 along with Z
+  bool basis = false;   // the SVD ran at d = K
   // the first iteration whose sketch spans all K columns (0: none that the
   // step can reach: past i_max, or after the early-fallback policy's end)
   int kfull = 0;
@@ -629,28 +611,6 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       b1[j * LDK + i] = td->Xw[e];
     }
     __syncthreads();
-    if (polish) {
-      // X <- X (3 I - X^H X) / 2 (one Newton-Schulz step towards the nearest
-      // unitary matrix): M -> b2, X M -> pm:tm, then back to b1
-      float2* xs = sm.pm;
-      lds_gemm(K, K, K,
-               [&](int i, int k) { return (i < K && k < K) ? cconj(b1[i * LDK + k]) : cz(); },
-               [&](int k, int j) { return (k < K && j < K) ? b1[j * LDK + k] : cz(); },
-               [&](int i, int j, float2 v) {
-                 b2[j * LDK + i] = make_float2((i == j ? 1.5f : 0.f) - 0.5f * v.x, -0.5f * v.y);
-               });
-      __syncthreads();
-      lds_gemm(K, K, K,
-               [&](int i, int k) { return (i < K && k < K) ? b1[k * LDK + i] : cz(); },
-               [&](int k, int j) { return (k < K && j < K) ? b2[j * LDK + k] : cz(); },
-               [&](int i, int j, float2 v) { xs[j * LDK + i] = v; });
-      __syncthreads();
-      for (int e = tid; e < K * K; e += NTH) {
-        const int j = e / K, i = e - j * K;
-        b1[j * LDK + i] = xs[j * LDK + i];
-      }
-      __syncthreads();
-    }
     t_sk += clock64() - c_mark; c_mark = clock64();
     } else {
     // Omega -> b1 (column-major)
@@ -785,8 +745,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       if (jb.out) *jb.out = st_h->info;
       td->last_r = st_h->info.r;
       td->spec_hint = it;
-      td->warm = 1;
-      td->warm_age = st_h->warm_age;
+      td->warm = st_h->warm;
       for (int q = 0; q < 8; ++q) td->dbg[q] = st_h->dbg[q];
       td->dbg[2] = qrcols;
       td->nsig = st_h->nsig;
@@ -802,7 +761,41 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     for (int m = 1; m < itn; ++m) kk = min(2 * kk, K);   // d depends on min(k0 + p, K) only
     const int dd = min(kk + p, K);
     const double tot = sketch_iteration(itn, dd);
-    if (tid == 0) reinterpret_cast<double*>(jb.spec + (size_t)2 * KS * KS * SPEC_MAX)[itn - 1] = tot;
+    // the earlier iterations' posted energy tests (tid 0): 2 if one of them
+    // meets the target (it, not this one, decides the step), 1 if all are
+    // posted and none does, 0 if some are still missing after the wait
+    auto poll_earlier = [&](bool wait) -> int {
+      const long long t_end = wall_clock64() + (wait ? SPEC_WAIT_TICKS : 0);
+      for (;;) {
+        bool all = true;
+        for (int j = 0; j + 1 < kfull; ++j) {
+          if (__hip_atomic_load(&tags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == jb.seq) {
+            const unsigned long long bits = __hip_atomic_load(
+                reinterpret_cast<unsigned long long*>(&spec_d[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__longlong_as_double((long long)bits) >= Et) return 2;
+          } else {
+            all = false;
+          }
+        }
+        if (all) return 1;
+        if (wall_clock64() >= t_end) return 0;
+        __builtin_amdgcn_s_sleep(8);
+      }
+    };
+    if (tid == 0) {
+      // post ||Z||_F^2, then its tag (release: the value is visible first)
+      spec_d[itn - 1] = tot;
+      __hip_atomic_store(&tags[itn - 1], jb.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (stage_ok && itn == kfull && tot >= Et && kfull > 1) {
+      // the step needs this iteration only if no earlier one meets the energy
+      // target: read the earlier iterations' posted tests (waiting, bounded,
+      // when the last step ended before d = K or there was none), and leave
+      // the step to the second phase if one of them decides
+      if (tid == 0) sm.found = poll_earlier(td->spec_hint < kfull) == 2;
+      __syncthreads();
+      if (sm.found) return;
+    }
     if (!(stage_ok && itn == kfull && tot >= Et)) {
       float2* Qw = jb.spec + (size_t)(itn - 1) * 2 * KS * KS;
       float2* Zw = Qw + KS * KS;
@@ -814,17 +807,35 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       return;
     }
     // the full-width iteration passes the test: the step goes on here, as
-    // the second phase would take it from this iteration, into the staging area
-    staged = true;
-    o_Ainv = st_Ainv; o_R = st_R; o_Xw = st_Xw; o_sig2 = st_sig2;
-    if (tid == 0) st_h->err = 0;
+    // the second phase would take it from this iteration
     iters = itn;
     d = dd;
     found = true;
     basis = true;
     c_mark = clock64();
-    jacobi_svd<true>(sm, K, d, &sweeps, &rounds);
+    jacobi_svd(sm, K, d, &sweeps, &rounds);
     t_jac += clock64() - c_mark; c_mark = clock64();
+    // where its results go: straight to the track once every earlier
+    // iteration is known to miss the target (the second phase then has
+    // nothing left to do), else to the staging area for the second phase
+    __syncthreads();
+    if (tid == 0) sm.found = kfull > 1 ? poll_earlier(true) : 1;
+    __syncthreads();
+    const int mode = sm.found;
+    if (mode == 2) return;
+    staged = mode != 1;
+    if (staged) {
+      o_Ainv = st_Ainv; o_R = st_R; o_Xw = st_Xw; o_sig2 = st_sig2;
+      if (tid == 0) st_h->err = 0;
+    } else {
+      // the earlier iterations' QR columns, as the second phase counts them
+      int kk = k0;
+      for (int m = 1; m < itn; ++m) {
+        const int dm = min(kk + p, K);
+        if (!(dm == K && warm_ok)) qrcols += dm;
+        kk = min(2 * kk, K);
+      }
+    }
     rotated = true;
     pick_rank(sm, K, d, Et, &r, &captured, o_sig2);
     decided = true;
@@ -861,8 +872,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
         if (hit) {
           found = true;
           basis = d == K;
-          if (basis) jacobi_svd<true>(sm, K, d, &sweeps, &rounds);
-          else jacobi_svd<false>(sm, K, d, &sweeps, &rounds);
+          jacobi_svd(sm, K, d, &sweeps, &rounds);
           t_jac += clock64() - c_mark; c_mark = clock64();
           rotated = true;
           pick_rank(sm, K, d, Et, &r, &captured, o_sig2);
@@ -889,8 +899,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       if (tot >= Et) {
         found = true;
         basis = d == K;
-        if (basis) jacobi_svd<true>(sm, K, d, &sweeps, &rounds);
-        else jacobi_svd<false>(sm, K, d, &sweeps, &rounds);
+        jacobi_svd(sm, K, d, &sweeps, &rounds);
         t_jac += clock64() - c_mark; c_mark = clock64();
         rotated = true;
         pick_rank(sm, K, d, Et, &r, &captured, o_sig2);
@@ -917,21 +926,37 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   int path = use_wb ? RZF_PATH_WB : RZF_PATH_FULL_RANK;
   float2* pm = sm.pm;
   float2* tm = sm.tm;
+  // the full-width SVD's normalised columns z_j / sigma_j (V_hat): the next
+  // full-width step's starting basis, unless a column is numerically zero
+  bool basis_ok = false;
   if (basis) {
-    // b1 = Q times the Jacobi rotations: the left singular vectors of
-    // Delta A, kept as the track's next full-width starting basis
-    for (int e = tid; e < K * K; e += NTH) {
-      const int j = e / K, i = e - j * K;
-      o_Xw[e] = b1[j * LDK + i];
+    if (tid < 64) {
+      const double v = lane < K ? sm.s2[lane] : 0.0;
+      double smax = v;
+      for (int j = 0; j < K; ++j) smax = fmax(smax, readlane_d(v, j));
+      const bool ok = smax > 0.0 && __all(lane >= K || v > BASIS_MIN_REL * smax);
+      sm.bsc[lane] = ok && lane < K ? (float)(1.0 / sqrt(v)) : 0.f;
+      if (lane == 0) sm.bok = ok;
     }
+    __syncthreads();
+    basis_ok = sm.bok != 0;
+    if (basis_ok)
+      for (int e = tid; e < K * K; e += NTH) {
+        const int j = e / K, i = e - j * K;
+        o_Xw[e] = cscale(b2[j * LDK + i], sm.bsc[j]);
+      }
   }
   if (rotated && use_wb && basis) {
-    // U_r = Q U_hat_r: the rotated basis columns in descending sigma order
+    // U_r = Delta A Z_r Sigma_r^-2 (Q is unitary at d = K); every retained
+    // sigma_j is positive
     const int* ord = sm.order;
-    for (int e = tid; e < K * r; e += NTH) {
-      const int c = e / K, i = e - c * K;
-      pm[c * LDK + i] = b1[ord[c] * LDK + i];
-    }
+    lds_gemm(K, r, K,
+             [&](int i, int k) { return (i < K && k < K) ? b0[i * LDK + k] : cz(); },
+             [&](int k, int c) { return (k < K && c < r) ? b2[ord[c] * LDK + k] : cz(); },
+             [&](int i, int c, float2 v) {
+               const double s2 = sm.s2[ord[c]];
+               pm[c * LDK + i] = make_float2((float)(v.x / s2), (float)(v.y / s2));
+             });
     __syncthreads();
   } else if (rotated && use_wb) {
     // U_r = Q U_hat_r = Q Q^H Delta A Z_r Sigma_r^-2 (B V_hat = U_hat Sigma with
@@ -1146,7 +1171,6 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     DevInfo inf;
     inf.r = r; inf.iters = iters; inf.path = path; inf.d = d;
     inf.dA_fro2 = E; inf.captured = captured;
-    const int age = (warm_ok && !polish) ? td->warm_age + 1 : 1;
     t_wb = clock64() - c_mark;
     int* dbg = staged ? st_h->dbg : tdg->dbg;
     dbg[0] = sweeps; dbg[1] = rounds; dbg[2] = qrcols;
@@ -1154,18 +1178,19 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     dbg[7] = (int)(wall_clock64() - r_begin);
     if (staged) {
       st_h->info = inf;
-      st_h->warm_age = age;
+      st_h->warm = basis_ok ? 1 : 0;
       st_h->nsig = d;
     } else {
       tdg->info = inf;
       if (jb.out) *jb.out = inf;
       td->last_r = r;
       td->spec_hint = iters;
-      if (basis) {
-        td->warm_age = age;
-        td->warm = 1;
-      }
+      if (basis) td->warm = basis_ok ? 1 : 0;
       td->nsig = rotated ? d : 0;
+      if (PH == 1) {
+        td->hold = 0;   // a finite step (the second phase, which would record it, returns at once)
+        __hip_atomic_store(&tags[SPEC_MAX], jb.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     (void)c_begin;
   }

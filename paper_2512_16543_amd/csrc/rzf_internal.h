@@ -29,8 +29,8 @@ struct TrackDesc {
   int early_fallback, wb_limit;   // policy flag; largest rank the Woodbury branch takes
   int prec, error_feedback;       // rzf_precision of the Gram and precoder operands; policy
   float2* Rfb;     // K x K, ld K: error-feedback residual (zero unless the policy is on)
-  float2* Xw;      // K x K, column-major ld K (K <= KS): left singular basis of the last
-                   // full-width (d = K) SVD, the next one's starting point
+  float2* Xw;      // K x K, column-major ld K (K <= KS): normalised columns z_j / sigma_j
+                   // of the last full-width (d = K) SVD, the next one's starting point
   uint64_t seed, track_id;
   float2* Ainv;    // K x K, ld K: stored inverse
   float2* Hprev;   // K x N, ld N: previous snapshot
@@ -49,8 +49,7 @@ struct TrackDesc {
   int last_r;
   int spec_hint;   // Alg. 1 iterations of the last step that ran it (speculation depth)
   int warm;        // Xw holds a basis
-  int warm_age;    // full-width SVDs whose rotations Xw has taken since it was last
-                   // orthonormal to working precision
+  int warm_age;    // kept in the checkpoint blob; not used by the kernels
   int hold;        // the current step met a non-finite snapshot (or its reset failed):
                    // the precoder keeps H_prev, so the track's state stays as it was
   DevInfo info;
@@ -100,11 +99,15 @@ struct ArsvdJob {
   int t, i_max;
   float2* spec;    // speculative-iteration workspace (SPEC_BYTES), two-phase single-track form only
   char* stage;     // staging area of the job's full-width step (two-phase form), or null
+  unsigned long long seq;   // two-phase form: this launch's number in its context (tags the
+                            // iterations' posted ||Z||_F^2), 0 otherwise
 };
 // Two-phase single-track form of the K <= KS arSVD kernel: up to SPEC_MAX
 // iterations of Alg. 1 are computed at once, one workgroup each, into
 // [SPEC_MAX][Q, Z][KS x KS] complex values followed by SPEC_MAX doubles
-// (||Z||_F^2) and one more (||Delta A||_F^2).  The workgroup of the first full-width iteration (d = K) also
+// (||Z||_F^2), one more (||Delta A||_F^2) and SPEC_MAX + 1 64-bit tags (the
+// launch number once the iteration's ||Z||_F^2 is posted; the last one once
+// the full-width iteration has written the whole step to the track).  The workgroup of the first full-width iteration (d = K) also
 // carries the step through when its energy test passes, into a staging area
 // (after those doubles) that the second phase copies to the track if that
 // iteration decides: SpecStage, sigma^2 (KS doubles), then A'^-1 and R
@@ -112,13 +115,13 @@ struct ArsvdJob {
 #define SPEC_MAX 8
 struct SpecStage {
   DevInfo info;
-  int warm_age, nsig, err, pad_;
+  int warm, nsig, err, pad_;   // warm: the staged basis may start the next full-width step
   int dbg[8];
 };
 inline constexpr size_t stage_bytes(int K) {
   return (sizeof(SpecStage) + sizeof(double) * KS + sizeof(float2) * 3 * (size_t)K * K + 255) & ~size_t(255);
 }
-#define SPEC_STAGE_OFF (sizeof(float2) * 2 * KS * KS * SPEC_MAX + sizeof(double) * (SPEC_MAX + 1))
+#define SPEC_STAGE_OFF (sizeof(float2) * 2 * KS * KS * SPEC_MAX + sizeof(double) * (2 * SPEC_MAX + 2))
 #define SPEC_BYTES (SPEC_STAGE_OFF + stage_bytes(KS))
 struct PrecJob {
   const float2* H; const float2* X; float2* W; double* wpart; float2* Hcopy;

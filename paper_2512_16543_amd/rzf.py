@@ -238,12 +238,15 @@ def _mat_args(H, dtype_name="complex64"):
 class Context:
     """rzf_ctx: one device, one stream, one arena (a torch uint8 tensor)."""
 
-    def __init__(self, device: int = 0, arena_bytes: int = 64 << 20, stream=None):
+    def __init__(self, device: int = 0, arena_bytes: int = 64 << 20, stream=None, arena=None):
+        """arena: a caller's uint8 device tensor of arena_bytes (default: a new one)."""
         import torch
         self.device = device
         dev = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
-        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+        if arena is not None and (arena.dtype != torch.uint8 or arena.numel() < arena_bytes):
+            raise ValueError("arena must be a uint8 tensor of at least arena_bytes")
+        self.arena = arena if arena is not None else torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
         h = ctypes.c_void_p()
         _check(lib().rzf_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream),
                                     ctypes.c_void_p(self.arena.data_ptr()), arena_bytes,

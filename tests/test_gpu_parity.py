@@ -295,6 +295,19 @@ def test_update_c1_track(ctx):
     assert orz.PATH_WB in paths
 
 
+def test_update_on_reused_arena_memory():
+    # a context whose arena holds stale words (here every 64-bit word is 1, as
+    # an earlier context's freed arena might hold small launch numbers) gives
+    # the same results: the speculated iterations' tags start cleared and
+    # launch numbers are never reused in a process
+    arena = torch.ones((64 << 20) // 8, dtype=torch.int64, device="cuda").view(torch.uint8)
+    c = rzf.Context(0, 64 << 20, arena=arena)
+    for cfg in (wl.CONFIGS["c1"], wl.with_overrides(wl.CONFIGS["c2"], reset_period=0)):
+        recs = run_track(c, cfg, 8, 0.999)
+        _assert_recs(recs)
+    c.close()
+
+
 @pytest.mark.parametrize("eta", [0.999, 0.9, 0.65])
 def test_update_c2_short(ctx, eta):
     cfg = wl.CONFIGS["c2"]
