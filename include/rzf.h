@@ -343,18 +343,31 @@ rzf_status rzf_track_export(rzf_track* tr, void* buf, size_t* bytes);
 rzf_status rzf_track_import(rzf_ctx* ctx, const void* buf, size_t bytes, rzf_track** out);
 
 /* ------------------------------------------------------ request server
- * Serving loop over resident tracks: requests (track, H_t, W) are submitted
- * from any thread; a dispatcher thread gathers pending requests into
- * batched launches on the context's stream, at most one request per track
- * per launch and in submission order per track, launching when max_batch
- * requests are pending or the oldest has waited max_wait_us; a completion
- * thread records each request when its launch has finished.
+ * Serving loop over resident tracks, with continuous batching: requests
+ * (track, H_t, W) are submitted from any thread and go to a lane by their
+ * track's kernel family (K <= 64, or K > 64).  Each lane launches on a HIP
+ * stream of its own (created by the server, default priority), so the two
+ * families' batches overlap on the device.  A dispatcher thread launches a
+ * lane's next batch as soon as the lane has one of its max_inflight slots
+ * free and max_batch of its requests are pending or the oldest has waited
+ * max_wait_us; requests that arrive while earlier batches run join the next
+ * batch.  A batch holds at most one request per track, in submission order
+ * per track (a track's later requests go to later batches of its lane, which
+ * run in order).  A completion thread per lane records each request when its
+ * batch has finished, with that batch's own status (RZF_E_NOT_HPD,
+ * RZF_E_NONFINITE: a device-side failure of one of the batch's kernels).
  *   RZF_SERVE_UPDATE: each request is one rzf_update of its track (Alg. 2).
  *   RZF_SERVE_FULL:   each request computes the full-inversion RZF of H_t
- *                     with the track's alpha and P; the track is not changed
- *                     (the conventional baseline on the same requests).
- * The caller keeps H_t and W alive until the request completes.  Device-side
- * errors are reported by the next rzf_sync as for other calls. */
+ *                     with the track's alpha and P (the conventional
+ *                     baseline on the same requests); it uses the track's own
+ *                     Gram and partial-sum buffers as scratch and leaves its
+ *                     state (inverse, previous snapshot) unchanged.  A track
+ *                     is served by one server at a time.
+ * The server's launches do not follow the context's stream: the caller makes
+ * H_t ready before submitting it (e.g. synchronises the stream that wrote
+ * it), keeps H_t and W alive until the request completes, and reads W after
+ * the completion.  rzf_sync does not wait for served requests; use
+ * rzf_server_drain. */
 typedef struct rzf_server rzf_server;
 typedef enum { RZF_SERVE_UPDATE = 0, RZF_SERVE_FULL = 1 } rzf_serve_mode;
 typedef struct {
@@ -362,11 +375,11 @@ typedef struct {
   double max_wait_us;   /* longest wait of the oldest request for a fuller batch  */
   double tol;           /* eta of every update (0.999)                            */
   int mode;             /* rzf_serve_mode                                         */
-  int max_inflight;     /* launches queued on the stream at once, 1..8 (2)        */
+  int max_inflight;     /* batches in flight per lane at once, 1..8 (2)            */
 } rzf_server_params;
 typedef struct {
   uint64_t tag;         /* as submitted                                           */
-  int status;           /* rzf_status of the launch                               */
+  int status;           /* rzf_status of the request's batch                      */
   int pad;
   rzf_update_info info; /* the update's outcome (RZF_SERVE_UPDATE)                */
   double t_submit_us, t_launch_us, t_done_us;   /* server clock                   */

@@ -119,13 +119,13 @@ hipEvent_t ev_get(rzf_ctx* c) {
 
 // Run `launch` between an event pair when timing is on.
 template <class F>
-void timed(rzf_ctx* c, int kernel, F launch) {
+void timed(rzf_ctx* c, int kernel, hipStream_t s, F launch) {
   if (!c->prof_on) { launch(); return; }
   hipEvent_t a = ev_get(c), b = ev_get(c);
   if (!a || !b) { launch(); return; }
-  (void)hipEventRecord(a, c->stream);
+  (void)hipEventRecord(a, s);
   launch();
-  (void)hipEventRecord(b, c->stream);
+  (void)hipEventRecord(b, s);
   c->prof.push_back(ProfRec{kernel, a, b});
 }
 
@@ -512,18 +512,18 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
   if (reset) {
     const Gram64Job gj{Hf, d.A64, K, N, ldh, t->alpha};
     const Inv64Job ij{d.A64, d.Ainv, &t->d_desc->info, nullptr, K, d.Rfb, &t->d_desc->hold};
-    timed(c, KN_GRAM64, [&] { launch_gram64(gj, nullptr, 1, K, s); });
-    timed(c, KN_INV64, [&] { inv64_any(ij, c->d_err, s); });
+    timed(c, KN_GRAM64, s, [&] { launch_gram64(gj, nullptr, 1, K, s); });
+    timed(c, KN_INV64, s, [&] { inv64_any(ij, c->d_err, s); });
   } else {
     const GramJob gj{Hf, d.Hprev, d.Anew, d.dA, K, N, ldh, N, (float)t->alpha, d.prec};
     const ArsvdJob aj{t->d_desc, nullptr, tol, step, t->i_max};
-    timed(c, KN_GRAM, [&] { launch_gram(gj, nullptr, 1, K, s); });
-    timed(c, KN_ARSVD, [&] { arsvd_single(c, aj, K, s); });
+    timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, s); });
+    timed(c, KN_ARSVD, s, [&] { arsvd_single(c, aj, K, s); });
   }
   const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw, d.prec, &t->d_desc->hold};
   const ScaleJob sj{Wf, d.wpart, d.P, K, N, ldw, precoder_blocks(N)};
-  timed(c, KN_PRECODER, [&] { launch_precoder(pj, nullptr, 1, N, s); });
-  timed(c, KN_SCALE, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, s); });
+  timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (slot) {
     HIP_OK(hipMemcpyAsync(slot, &t->d_desc->info, sizeof(DevInfo), hipMemcpyDeviceToHost, s));
@@ -582,8 +582,7 @@ rzf_status check_update_items(rzf_ctx* c, int n, const rzf_update_item* items, d
 }
 
 rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, double tol,
-                               DevInfo* const* slots) {
-  hipStream_t s = c->stream;
+                               DevInfo* const* slots, hipStream_t s, int* err) {
   std::vector<GramJob> gj;
   std::vector<ArsvdJob> aj, ajb;     // LDS kernels (K <= KS) / large tracks
   std::vector<Gram64Job> g64;
@@ -635,21 +634,21 @@ rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, 
   st.put(sj.data(), n, &d_sj);
   HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
   if (!gj.empty()) {
-    timed(c, KN_GRAM, [&] { launch_gram(gj[0], d_gj, (int)gj.size(), maxK, s); });
-    timed(c, KN_ARSVD, [&] {
-      if (!aj.empty()) launch_arsvd_wb(aj[0], d_aj, (int)aj.size(), c->d_err, s);
-      if (!ajb.empty()) launch_arsvd_big(ajb[0], d_ajb, (int)ajb.size(), c->d_err, s);
+    timed(c, KN_GRAM, s, [&] { launch_gram(gj[0], d_gj, (int)gj.size(), maxK, s); });
+    timed(c, KN_ARSVD, s, [&] {
+      if (!aj.empty()) launch_arsvd_wb(aj[0], d_aj, (int)aj.size(), err, s);
+      if (!ajb.empty()) launch_arsvd_big(ajb[0], d_ajb, (int)ajb.size(), err, s);
     });
   }
   if (!g64.empty()) {
-    timed(c, KN_GRAM64, [&] { launch_gram64(g64[0], d_g64, (int)g64.size(), maxKr, s); });
-    timed(c, KN_INV64, [&] {
-      if (!i64.empty()) launch_inv64(i64[0], d_i64, (int)i64.size(), c->d_err, s);
-      if (!i64b.empty()) launch_inv64_big(i64b[0], d_i64b, (int)i64b.size(), c->d_err, s);
+    timed(c, KN_GRAM64, s, [&] { launch_gram64(g64[0], d_g64, (int)g64.size(), maxKr, s); });
+    timed(c, KN_INV64, s, [&] {
+      if (!i64.empty()) launch_inv64(i64[0], d_i64, (int)i64.size(), err, s);
+      if (!i64b.empty()) launch_inv64_big(i64b[0], d_i64b, (int)i64b.size(), err, s);
     });
   }
-  timed(c, KN_PRECODER, [&] { launch_precoder(pj[0], d_pj, n, maxN, s); });
-  timed(c, KN_SCALE, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, s); });
+  timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
   HIP_OK(hipEventRecord(c->stage_ev[slot], s));
   c->stage_used[slot] = true;
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
@@ -678,7 +677,8 @@ rzf_status check_full_items(int n, const rzf_full_item* items) {
   return RZF_OK;
 }
 
-rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items) {
+rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items, const FullScratch* scr,
+                             hipStream_t s, int* err) {
   int maxK = 1, maxN = 1, maxNK = 1;
   size_t need = 0;
   for (int i = 0; i < n; ++i) {
@@ -688,8 +688,7 @@ rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items) {
     maxNK = std::max(maxNK, it.N * it.K);
     need += align_up(sizeof(float2) * it.K * it.K) + align_up(sizeof(double) * precoder_blocks(it.N));
   }
-  hipStream_t s = c->stream;
-  if (need > c->batch_full_bytes) {
+  if (!scr && need > c->batch_full_bytes) {
     // grow: the old region may still be read by queued work
     HIP_OK(hipStreamSynchronize(c->stream));
     if (c->d_batch_full) arena_free(c, c->batch_full_off, c->batch_full_bytes);
@@ -709,8 +708,9 @@ rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items) {
   char* p = c->d_batch_full;
   for (int i = 0; i < n; ++i) {
     const rzf_full_item& it = items[i];
-    float2* A = reinterpret_cast<float2*>(p); p += align_up(sizeof(float2) * it.K * it.K);
-    double* wp = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * precoder_blocks(it.N));
+    float2* A = scr ? scr[i].A : reinterpret_cast<float2*>(p);
+    double* wp = scr ? scr[i].wpart : reinterpret_cast<double*>(p + align_up(sizeof(float2) * it.K * it.K));
+    if (!scr) p += align_up(sizeof(float2) * it.K * it.K) + align_up(sizeof(double) * precoder_blocks(it.N));
     const float2* Hf = reinterpret_cast<const float2*>(it.H);
     float2* Wf = reinterpret_cast<float2*>(it.W);
     gj[i] = GramJob{Hf, nullptr, A, nullptr, it.K, it.N, it.ldh, 0, (float)it.alpha, it.precision};
@@ -731,13 +731,13 @@ rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items) {
   st.put(pj.data(), n, &d_pj);
   st.put(sj.data(), n, &d_sj);
   HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
-  timed(c, KN_GRAM, [&] { launch_gram(gj[0], d_gj, n, maxK, s); });
-  timed(c, KN_INV32, [&] {
-    if (!vj.empty()) launch_inv32(vj[0], d_vj, (int)vj.size(), c->d_err, s);
-    if (!vjb.empty()) launch_inv32_big(vjb[0], d_vjb, (int)vjb.size(), c->d_err, s);
+  timed(c, KN_GRAM, s, [&] { launch_gram(gj[0], d_gj, n, maxK, s); });
+  timed(c, KN_INV32, s, [&] {
+    if (!vj.empty()) launch_inv32(vj[0], d_vj, (int)vj.size(), err, s);
+    if (!vjb.empty()) launch_inv32_big(vjb[0], d_vjb, (int)vjb.size(), err, s);
   });
-  timed(c, KN_PRECODER, [&] { launch_precoder(pj[0], d_pj, n, maxN, s); });
-  timed(c, KN_SCALE, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, s); });
+  timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
   HIP_OK(hipEventRecord(c->stage_ev[slot], s));
   c->stage_used[slot] = true;
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
@@ -758,7 +758,7 @@ rzf_status rzf_update_batch(rzf_ctx* c, int n, const rzf_update_item* items, dou
     slots[i] = pin_slot(c);
     if (!slots[i]) return RZF_E_DEVICE;
   }
-  const rzf_status s2 = update_batch_locked(c, n, items, tol, slots.data());
+  const rzf_status s2 = update_batch_locked(c, n, items, tol, slots.data(), c->stream, c->d_err);
   if (s2 != RZF_OK) return s2;
   for (int i = 0; i < n; ++i)
     if (slots[i]) c->pending.push_back(Pending{slots[i], items[i].info});
@@ -771,7 +771,7 @@ rzf_status rzf_full_batch(rzf_ctx* c, int n, const rzf_full_item* items) {
   if (st != RZF_OK) return st;
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
-  return full_batch_locked(c, n, items);
+  return full_batch_locked(c, n, items, nullptr, c->stream, c->d_err);
 }
 
 rzf_status rzf_sum_rate_batch(rzf_ctx* c, int n, const rzf_rate_item* items, double P, double sigma2) {
@@ -819,7 +819,7 @@ rzf_status rzf_sum_rate_batch(rzf_ctx* c, int n, const rzf_rate_item* items, dou
   RateJob* d_rj = nullptr;
   st.put(rj.data(), n, &d_rj);
   HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
-  timed(c, KN_SUMRATE, [&] { launch_sum_rate(rj[0], d_rj, n, maxK, c->d_err, s); });
+  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj[0], d_rj, n, maxK, c->d_err, s); });
   HIP_OK(hipEventRecord(c->stage_ev[slot], s));
   c->stage_used[slot] = true;
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
@@ -842,11 +842,11 @@ rzf_status rzf_full(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   const GramJob gj{Hf, nullptr, c->d_fullA, nullptr, K, N, ldh, 0, (float)alpha, RZF_PREC_FP32};
   const PrecJob pj{Hf, c->d_fullAinv, Wf, c->d_fullwpart, nullptr, K, N, ldh, ldw, RZF_PREC_FP32};
   const ScaleJob sj{Wf, c->d_fullwpart, P, K, N, ldw, precoder_blocks(N)};
-  timed(c, KN_GRAM, [&] { launch_gram(gj, nullptr, 1, K, s); });
+  timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, s); });
   const Inv32Job vj{c->d_fullA, c->d_fullAinv, K};
-  timed(c, KN_INV32, [&] { inv32_any(vj, c->d_err, s); });
-  timed(c, KN_PRECODER, [&] { launch_precoder(pj, nullptr, 1, N, s); });
-  timed(c, KN_SCALE, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
+  timed(c, KN_INV32, s, [&] { inv32_any(vj, c->d_err, s); });
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, s); });
+  timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
 }
 
@@ -860,7 +860,7 @@ rzf_status rzf_sum_rate(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, con
   hipStream_t s = c->stream;
   const RateJob rj{reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(W), c->d_srpart,
                    rates, c->d_sum, K, N, ldh, ldw, P, sigma2};
-  timed(c, KN_SUMRATE, [&] { launch_sum_rate(rj, nullptr, 1, K, c->d_err, s); });
+  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj, nullptr, 1, K, c->d_err, s); });
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (sum_rate) {
     HIP_OK(hipMemcpyAsync(c->h_sum, c->d_sum, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1029,8 +1029,8 @@ rzf_status rzf_beamspace(rzf_ctx* c, int K, int nx, int ny, const rzf_c32* H, in
     c->d_beam_g = reinterpret_cast<float2*>(c->arena + off);
   }
   const float2* Hf = reinterpret_cast<const float2*>(H);
-  timed(c, KN_BEAM_RESP, [&] { launch_beam_resp(Hf, ldh, K, nx, ny, c->d_beam_g, s); });
-  timed(c, KN_BEAM_SELECT, [&] {
+  timed(c, KN_BEAM_RESP, s, [&] { launch_beam_resp(Hf, ldh, K, nx, ny, c->d_beam_g, s); });
+  timed(c, KN_BEAM_SELECT, s, [&] {
     launch_beam_select(c->d_beam_g, K, N, n_rf, select, beams, reinterpret_cast<float2*>(H_eff), ld_eff,
                        c->d_err, s);
   });

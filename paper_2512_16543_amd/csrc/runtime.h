@@ -99,13 +99,22 @@ namespace rzfrt {
 rzf_status check_update_items(rzf_ctx* c, int n, const rzf_update_item* items, double tol);
 rzf_status check_full_items(int n, const rzf_full_item* items);
 
-// Launch one batched update (c->mu held, items checked).  For every i with
-// slots[i] != nullptr the step's info record is copied into that pinned
-// host slot on the context stream after the update; the caller decides when
-// it is valid (an event, or rzf_sync).
+// Launch one batched update (c->mu held, items checked) on stream s, device
+// errors recorded in *err.  For every i with slots[i] != nullptr the step's
+// info record is copied into that pinned host slot on s after the update;
+// the caller decides when it is valid (an event, or rzf_sync).
 rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, double tol,
-                               DevInfo* const* slots);
-// Launch one batched full-inversion RZF (c->mu held, items checked).
-rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items);
+                               DevInfo* const* slots, hipStream_t s, int* err);
+// Per-item scratch of a batched full inversion: the K x K Gram matrix (then
+// its inverse) and the precoder's partial sums.
+struct FullScratch {
+  float2* A;
+  double* wpart;
+};
+// Launch one batched full-inversion RZF (c->mu held, items checked) on
+// stream s, device errors in *err.  scr: per-item scratch, or nullptr for
+// the context's own (grown on demand; then only on the context stream).
+rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items, const FullScratch* scr,
+                             hipStream_t s, int* err);
 
 }  // namespace rzfrt

@@ -1,11 +1,24 @@
-// Request server over resident tracks: callers submit (track, H_t, W)
-// requests from any thread; a dispatcher thread gathers the pending requests
-// into batched launches (at most one request per track per launch, in
-// submission order per track) and a completion thread stamps each request
-// once its launch has finished on the GPU.  Mode UPDATE runs Alg. 2 on the
-// track (rzf_update_batch); mode FULL computes the full-inversion RZF of the
-// request's snapshot with the track's alpha and P (the track state is not
-// touched), the baseline on the same request stream.
+// Request server over resident tracks, with continuous batching.
+//
+// Callers submit (track, H_t, W) requests from any thread.  Requests go to a
+// lane by the kernel family of their track (K <= 64: the kernels whose working
+// set sits in LDS; K > 64: the blocked large-track kernels), and each lane
+// launches on a stream of its own, so the two families' batches run on the
+// device at the same time instead of the small tracks waiting behind the
+// large ones.  A dispatcher thread forms a lane's next batch whenever that
+// lane has a free in-flight slot and either max_batch of its requests are
+// pending or the oldest has waited max_wait_us: requests that arrive while
+// earlier batches run are admitted as soon as a slot frees.  A batch takes
+// at most one request per track, in submission order per track; a track's
+// later requests go to later batches of the same lane, which run in order on
+// its stream.  One completion thread per lane waits on the lane's batches in
+// launch order and stamps each request, with the batch's own device error
+// status (every in-flight slot has its own error word).
+//
+// Mode UPDATE runs Alg. 2 on the track (the batched rzf_update); mode FULL
+// computes the full-inversion RZF of the request's snapshot with the track's
+// alpha and P, using the track's own Gram and partial-sum buffers as scratch
+// (the track's state is not changed): the baseline on the same requests.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +39,8 @@ using namespace rzfrt;
 
 namespace {
 
+constexpr int NLANES = 2;   // K <= KS, K > KS
+
 struct Request {
   rzf_track* tr;
   const rzf_c32* H;
@@ -38,13 +53,33 @@ struct Request {
 
 struct Batch {
   std::vector<Request> reqs;
-  hipEvent_t ev = nullptr;
-  DevInfo* slots = nullptr;
+  int slot = 0;
   double t_launch = 0.0;
   rzf_status st = RZF_OK;
 };
 
+struct Lane {
+  hipStream_t stream = nullptr;
+  std::list<Request> pending;
+  std::deque<Batch> inflight;      // in launch order
+  std::vector<int> free_slots;
+  // per in-flight slot
+  std::vector<hipEvent_t> ev;
+  std::vector<DevInfo*> info;      // pinned, max_batch records
+  std::vector<int*> d_err;         // device error word
+  std::vector<int*> h_err;         // pinned copy of it, valid once ev has completed
+  std::thread completer;
+};
+
 using Clock = std::chrono::steady_clock;
+
+int lane_of(const rzf_track* t) { return t->K > KS ? 1 : 0; }
+
+rzf_status status_of(int code) {
+  if (code == DEV_ERR_NOT_HPD) return RZF_E_NOT_HPD;
+  if (code == DEV_ERR_NONFINITE) return RZF_E_NONFINITE;
+  return code ? RZF_E_DEVICE : RZF_OK;
+}
 
 }  // namespace
 
@@ -53,96 +88,130 @@ struct rzf_server {
   rzf_server_params prm{};
   Clock::time_point t0;
   std::mutex m;
-  std::condition_variable cv_pending, cv_inflight, cv_done;
-  std::list<Request> pending;
-  std::deque<Batch> inflight;
+  std::condition_variable cv_work, cv_done;
+  Lane lanes[NLANES];
   std::deque<rzf_completion> done;
-  std::vector<hipEvent_t> ev_free;
-  std::vector<DevInfo*> slot_free;
-  DevInfo* slot_base = nullptr;
+  DevInfo* info_base = nullptr;
+  int* d_err_base = nullptr;
+  int* h_err_base = nullptr;
   bool stop = false, dispatcher_done = false;
   uint64_t submitted = 0, completed = 0;
-  std::thread dispatcher, completer;
+  std::thread dispatcher;
 
   double now() const { return std::chrono::duration<double, std::micro>(Clock::now() - t0).count(); }
 };
 
 namespace {
 
+// A lane may launch now: a free slot and a full batch, a request past its
+// wait, or the server stopping.
+bool lane_ready(const rzf_server* S, const Lane& L, double now) {
+  if (L.pending.empty() || L.free_slots.empty()) return false;
+  return S->stop || (int)L.pending.size() >= S->prm.max_batch ||
+         now >= L.pending.front().t_submit + S->prm.max_wait_us;
+}
+
+// Launch one batch of lane l from slot b.slot (S->m not held).
+void launch_batch(rzf_server* S, int l, Batch& b) {
+  rzf_ctx* c = S->ctx;
+  Lane& L = S->lanes[l];
+  const int n = (int)b.reqs.size();
+  const int k = b.slot;
+  std::lock_guard<std::mutex> cl(c->mu);
+  hipStream_t s = L.stream;
+  if (hipMemsetAsync(L.d_err[k], 0, sizeof(int), s) != hipSuccess) {
+    b.st = RZF_E_DEVICE;
+    return;
+  }
+  if (S->prm.mode == RZF_SERVE_FULL) {
+    std::vector<rzf_full_item> items(n);
+    std::vector<FullScratch> scr(n);
+    for (int i = 0; i < n; ++i) {
+      const Request& r = b.reqs[i];
+      items[i] = rzf_full_item{r.tr->K, r.tr->N, r.H, r.ldh, r.tr->alpha, r.tr->prm.P, r.W, r.ldw,
+                               r.tr->prm.precision};
+      scr[i] = FullScratch{r.tr->h_desc.Anew, r.tr->h_desc.wpart};
+    }
+    b.st = full_batch_locked(c, n, items.data(), scr.data(), s, L.d_err[k]);
+  } else {
+    std::vector<rzf_update_item> items(n);
+    std::vector<DevInfo*> slots(n);
+    for (int i = 0; i < n; ++i) {
+      const Request& r = b.reqs[i];
+      items[i] = rzf_update_item{r.tr, r.H, r.ldh, r.W, r.ldw, nullptr};
+      slots[i] = L.info[k] + i;
+    }
+    b.st = update_batch_locked(c, n, items.data(), S->prm.tol, slots.data(), s, L.d_err[k]);
+  }
+  if (b.st == RZF_OK &&
+      (hipMemcpyAsync(L.h_err[k], L.d_err[k], sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+       hipEventRecord(L.ev[k], s) != hipSuccess))
+    b.st = RZF_E_DEVICE;
+}
+
 void dispatch_loop(rzf_server* S) {
   (void)hipSetDevice(S->ctx->device);
   const int maxb = S->prm.max_batch;
   std::unique_lock<std::mutex> lk(S->m);
   for (;;) {
-    S->cv_pending.wait(lk, [&] { return S->stop || !S->pending.empty(); });
-    if (S->pending.empty()) break;   // stop requested and nothing left
-    // a fuller batch, until the oldest request has waited max_wait_us
-    const double deadline = S->pending.front().t_submit + S->prm.max_wait_us;
-    while (!S->stop && (int)S->pending.size() < maxb && S->now() < deadline) {
-      const auto tp = S->t0 + std::chrono::duration_cast<Clock::duration>(
-                                  std::chrono::duration<double, std::micro>(deadline));
-      S->cv_pending.wait_until(lk, tp);
+    const double now = S->now();
+    int l = -1;
+    for (int q = 0; q < NLANES && l < 0; ++q)
+      if (lane_ready(S, S->lanes[q], now)) l = q;
+    if (l < 0) {
+      bool any_pending = false;
+      double wake = 1e300;   // the earliest deadline of a lane that has a free slot
+      for (const Lane& L : S->lanes) {
+        if (L.pending.empty()) continue;
+        any_pending = true;
+        if (!L.free_slots.empty()) wake = std::min(wake, L.pending.front().t_submit + S->prm.max_wait_us);
+      }
+      if (S->stop && !any_pending) break;
+      if (wake < 1e300) {
+        const auto tp = S->t0 + std::chrono::duration_cast<Clock::duration>(
+                                    std::chrono::duration<double, std::micro>(wake));
+        S->cv_work.wait_until(lk, tp);
+      } else {
+        S->cv_work.wait(lk);   // a new request, a freed slot or stop
+      }
+      continue;
     }
-    S->cv_inflight.wait(lk, [&] { return (int)S->inflight.size() < S->prm.max_inflight; });
+    Lane& L = S->lanes[l];
     Batch b;
     std::set<rzf_track*> used;
-    for (auto it = S->pending.begin(); it != S->pending.end() && (int)b.reqs.size() < maxb;) {
+    for (auto it = L.pending.begin(); it != L.pending.end() && (int)b.reqs.size() < maxb;) {
       if (used.insert(it->tr).second) {
         b.reqs.push_back(*it);
-        it = S->pending.erase(it);
+        it = L.pending.erase(it);
       } else {
         ++it;   // a later request of a track already in this batch waits for the next one
       }
     }
-    b.ev = S->ev_free.back();
-    S->ev_free.pop_back();
-    b.slots = S->slot_free.back();
-    S->slot_free.pop_back();
+    b.slot = L.free_slots.back();
+    L.free_slots.pop_back();
     lk.unlock();
-    const int n = (int)b.reqs.size();
-    rzf_ctx* c = S->ctx;
-    {
-      std::lock_guard<std::mutex> cl(c->mu);
-      if (S->prm.mode == RZF_SERVE_FULL) {
-        std::vector<rzf_full_item> items(n);
-        for (int i = 0; i < n; ++i) {
-          const Request& r = b.reqs[i];
-          items[i] = rzf_full_item{r.tr->K, r.tr->N, r.H, r.ldh, r.tr->alpha, r.tr->prm.P, r.W, r.ldw,
-                                   r.tr->prm.precision};
-        }
-        b.st = full_batch_locked(c, n, items.data());
-      } else {
-        std::vector<rzf_update_item> items(n);
-        std::vector<DevInfo*> slots(n);
-        for (int i = 0; i < n; ++i) {
-          const Request& r = b.reqs[i];
-          items[i] = rzf_update_item{r.tr, r.H, r.ldh, r.W, r.ldw, nullptr};
-          slots[i] = b.slots + i;
-        }
-        b.st = update_batch_locked(c, n, items.data(), S->prm.tol, slots.data());
-      }
-      if (b.st == RZF_OK && hipEventRecord(b.ev, c->stream) != hipSuccess) b.st = RZF_E_DEVICE;
-    }
+    launch_batch(S, l, b);
     b.t_launch = S->now();
     lk.lock();
-    S->inflight.push_back(std::move(b));
-    S->cv_inflight.notify_all();
+    L.inflight.push_back(std::move(b));
+    S->cv_done.notify_all();   // wakes this lane's completion thread
   }
   S->dispatcher_done = true;
-  S->cv_inflight.notify_all();
+  S->cv_done.notify_all();
 }
 
-void complete_loop(rzf_server* S) {
+void complete_loop(rzf_server* S, int l) {
   (void)hipSetDevice(S->ctx->device);
+  Lane& L = S->lanes[l];
   std::unique_lock<std::mutex> lk(S->m);
   for (;;) {
-    S->cv_inflight.wait(lk, [&] { return !S->inflight.empty() || S->dispatcher_done; });
-    if (S->inflight.empty()) break;   // the dispatcher has stopped and nothing is in flight
-    Batch b = std::move(S->inflight.front());
-    S->inflight.pop_front();
-    lk.unlock();
+    S->cv_done.wait(lk, [&] { return !L.inflight.empty() || S->dispatcher_done; });
+    if (L.inflight.empty()) break;   // the dispatcher has stopped and nothing is in flight
+    Batch& b = L.inflight.front();
+    const int k = b.slot;
     rzf_status st = b.st;
-    if (st == RZF_OK && hipEventSynchronize(b.ev) != hipSuccess) st = RZF_E_DEVICE;
+    lk.unlock();
+    if (st == RZF_OK) st = hipEventSynchronize(L.ev[k]) == hipSuccess ? status_of(*L.h_err[k]) : RZF_E_DEVICE;
     const double t_done = S->now();
     lk.lock();
     for (size_t i = 0; i < b.reqs.size(); ++i) {
@@ -150,17 +219,17 @@ void complete_loop(rzf_server* S) {
       std::memset(&cpl, 0, sizeof(cpl));
       cpl.tag = b.reqs[i].tag;
       cpl.status = st;
-      if (st == RZF_OK && S->prm.mode != RZF_SERVE_FULL)
-        std::memcpy(&cpl.info, b.slots + i, sizeof(rzf_update_info));
+      if (b.st == RZF_OK && S->prm.mode != RZF_SERVE_FULL)
+        std::memcpy(&cpl.info, L.info[k] + i, sizeof(rzf_update_info));
       cpl.t_submit_us = b.reqs[i].t_submit;
       cpl.t_launch_us = b.t_launch;
       cpl.t_done_us = t_done;
       S->done.push_back(cpl);
     }
     S->completed += b.reqs.size();
-    S->ev_free.push_back(b.ev);
-    S->slot_free.push_back(b.slots);
-    S->cv_inflight.notify_all();
+    L.inflight.pop_front();
+    L.free_slots.push_back(k);
+    S->cv_work.notify_all();
     S->cv_done.notify_all();
   }
 }
@@ -171,10 +240,22 @@ rzf_status enqueue(rzf_server* S, rzf_track* tr, const rzf_c32* H, int ldh, rzf_
   if (ldh < tr->N || ldw < tr->K) return RZF_E_SHAPE;
   std::lock_guard<std::mutex> lk(S->m);
   if (S->stop) return RZF_E_INVALID;
-  S->pending.push_back(Request{tr, H, ldh, W, ldw, tag, S->now()});
+  S->lanes[lane_of(tr)].pending.push_back(Request{tr, H, ldh, W, ldw, tag, S->now()});
   ++S->submitted;
-  S->cv_pending.notify_one();
+  S->cv_work.notify_all();
   return RZF_OK;
+}
+
+void release(rzf_server* S) {
+  for (Lane& L : S->lanes) {
+    for (hipEvent_t e : L.ev)
+      if (e) (void)hipEventDestroy(e);
+    if (L.stream) (void)hipStreamDestroy(L.stream);
+  }
+  if (S->info_base) (void)hipHostFree(S->info_base);
+  if (S->h_err_base) (void)hipHostFree(S->h_err_base);
+  if (S->d_err_base) (void)hipFree(S->d_err_base);
+  delete S;
 }
 
 }  // namespace
@@ -204,26 +285,34 @@ rzf_status rzf_server_create(rzf_ctx* c, const rzf_server_params* p, rzf_server*
   S->ctx = c;
   S->prm = *p;
   S->t0 = Clock::now();
-  if (hipSetDevice(c->device) != hipSuccess) { delete S; return RZF_E_DEVICE; }
-  const int pools = p->max_inflight + 1;
-  if (hipHostMalloc((void**)&S->slot_base, sizeof(DevInfo) * p->max_batch * pools, hipHostMallocDefault) !=
-      hipSuccess) {
-    delete S;
+  const int slots = p->max_inflight;
+  const int total = NLANES * slots;
+  bool ok = hipSetDevice(c->device) == hipSuccess &&
+            hipHostMalloc((void**)&S->info_base, sizeof(DevInfo) * p->max_batch * total, hipHostMallocDefault) ==
+                hipSuccess &&
+            hipHostMalloc((void**)&S->h_err_base, sizeof(int) * 64 * total, hipHostMallocDefault) == hipSuccess &&
+            hipMalloc((void**)&S->d_err_base, sizeof(int) * 64 * total) == hipSuccess;
+  for (int l = 0; l < NLANES && ok; ++l) {
+    Lane& L = S->lanes[l];
+    // default priority (the streams of one process keep equal priorities)
+    ok = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; k < slots && ok; ++k) {
+      hipEvent_t e = nullptr;
+      ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+      L.ev.push_back(e);
+      const int g = l * slots + k;
+      L.info.push_back(S->info_base + (size_t)g * p->max_batch);
+      L.d_err.push_back(S->d_err_base + 64 * g);   // one 256-byte line per word
+      L.h_err.push_back(S->h_err_base + 64 * g);
+      L.free_slots.push_back(slots - 1 - k);
+    }
+  }
+  if (!ok) {
+    release(S);
     return RZF_E_DEVICE;
   }
-  for (int k = 0; k < pools; ++k) {
-    hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      for (hipEvent_t x : S->ev_free) (void)hipEventDestroy(x);
-      (void)hipHostFree(S->slot_base);
-      delete S;
-      return RZF_E_DEVICE;
-    }
-    S->ev_free.push_back(e);
-    S->slot_free.push_back(S->slot_base + (size_t)k * p->max_batch);
-  }
   S->dispatcher = std::thread(dispatch_loop, S);
-  S->completer = std::thread(complete_loop, S);
+  for (int l = 0; l < NLANES; ++l) S->lanes[l].completer = std::thread(complete_loop, S, l);
   *out = S;
   return RZF_OK;
 }
@@ -269,7 +358,7 @@ rzf_status rzf_server_poll(rzf_server* S, rzf_completion* out, int max, int* n_o
 rzf_status rzf_server_drain(rzf_server* S) {
   if (!S) return RZF_E_INVALID;
   std::unique_lock<std::mutex> lk(S->m);
-  S->cv_pending.notify_all();
+  S->cv_work.notify_all();
   S->cv_done.wait(lk, [&] { return S->completed == S->submitted; });
   return RZF_OK;
 }
@@ -282,13 +371,11 @@ rzf_status rzf_server_destroy(rzf_server* S) {
     std::lock_guard<std::mutex> lk(S->m);
     S->stop = true;   // pending requests are still dispatched
   }
-  S->cv_pending.notify_all();
+  S->cv_work.notify_all();
   S->dispatcher.join();
-  S->completer.join();
+  for (Lane& L : S->lanes) L.completer.join();
   (void)hipSetDevice(S->ctx->device);
-  for (hipEvent_t e : S->ev_free) (void)hipEventDestroy(e);
-  (void)hipHostFree(S->slot_base);
-  delete S;
+  release(S);
   return RZF_OK;
 }
 

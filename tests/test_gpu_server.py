@@ -1,10 +1,12 @@
 """Request server: batched serving gives exactly what per-track calls give.
 
 UPDATE mode: each track's requests, served in submission order inside
-batched launches, yield the same precoders, inverses and info records as
-the same snapshots fed to a twin track with rzf_update one by one.  FULL
-mode matches rzf_full.  Replay of a timed trace completes every request
-with consistent timestamps.
+batched launches on the two lanes (K <= 64 and K > 64, each on its own
+stream), yield the same precoders, inverses and info records as the same
+snapshots fed to a twin track with rzf_update one by one.  FULL mode matches
+rzf_full.  Replay of a timed trace completes every request with consistent
+timestamps.  Small tracks' batches run beside a large track's instead of
+behind it, and a batch's device error reaches that batch's completions.
 """
 import numpy as np
 import pytest
@@ -27,6 +29,7 @@ def walk(K, N, steps, seed):
 
 def _setup(ctx, steps):
     Hs = [walk(K, N, steps, 80 + i) for i, (K, N) in enumerate(SIZES)]
+    torch.cuda.synchronize()   # the server's streams do not follow torch's
 
     def mk():
         return [ctx.init(H[0], 0.3 + K / 25.0, rzf.default_params(seed=2, track_id=i, reset_period=3))
@@ -132,4 +135,70 @@ def test_destroy_serves_pending_requests():
     srv.close()                                                  # dispatches at once
     ctx.sync()
     assert all(tr.query()["t"] == 1 for tr in trs)
+    ctx.close()
+
+
+def test_small_tracks_overlap_a_large_one():
+    # a K = 256, N = 1024 update at eta = 0.999 runs Alg. 1 up to d = K (tens
+    # of milliseconds); small tracks' requests submitted just after it finish
+    # first, on their own lane, and still equal their sequential results
+    ctx = rzf.Context(0, 256 << 20)
+    cfg = wl.CONFIGS["c5"]
+    Hb = torch.from_numpy(wl.make_track(cfg).snapshots(0, 2).astype(np.complex64)).cuda()
+    small = [(16, 64), (64, 256)]
+    Hs = [walk(K, N, 3, 90 + i) for i, (K, N) in enumerate(small)]
+    torch.cuda.synchronize()
+    big = ctx.init(Hb[0], cfg.alpha, rzf.default_params(seed=5))
+    mk = lambda: [ctx.init(H[0], 0.5, rzf.default_params(seed=6, track_id=i)) for i, H in enumerate(Hs)]
+    seq, trs = mk(), mk()
+    Ws = [[torch.empty(N, K, dtype=torch.complex64, device="cuda") for _ in range(3)] for K, N in small]
+    Wq = [[torch.empty_like(w) for w in ws] for ws in Ws]
+    for t in range(1, 4):
+        for i, tr in enumerate(seq):
+            tr.update(Hs[i][t], 0.999, Wq[i][t - 1])
+    ctx.sync()
+    Wb = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device="cuda")
+    srv = rzf.Server(ctx, rzf.server_params(max_wait_us=0.0, tol=0.999))
+    srv.submit(big, Hb[1], Wb, tag=999)
+    for t in range(1, 4):
+        for i, tr in enumerate(trs):
+            srv.submit(tr, Hs[i][t], Ws[i][t - 1], tag=10 * i + t)
+    srv.drain()
+    done = {c.tag: c for c in srv.poll()}
+    srv.close()
+    assert len(done) == 7 and all(c.status == rzf.RZF_OK for c in done.values())
+    t_big = done[999].t_done_us
+    print(f"large track done at {t_big - done[999].t_launch_us:.0f} us after launch; small ones at "
+          f"{[round(c.t_done_us - done[999].t_launch_us) for k, c in sorted(done.items()) if k != 999]}", flush=True)
+    assert all(c.t_done_us < t_big for k, c in done.items() if k != 999)
+    for i in range(len(small)):
+        for t in range(3):
+            assert torch.equal(Ws[i][t], Wq[i][t])
+    ctx.close()
+
+
+def test_batch_error_reaches_its_requests():
+    # a non-finite snapshot in the K <= 64 lane: its batch completes with
+    # RZF_E_NONFINITE, the K > 64 lane's batch with RZF_OK, and the track
+    # goes on from its last finite snapshot
+    ctx = rzf.Context(0, 64 << 20)
+    Hs, mk = _setup(ctx, 3)
+    trs = mk()
+    W = [torch.empty(N, K, dtype=torch.complex64, device="cuda") for K, N in SIZES]
+    bad = Hs[0][1].clone()
+    bad[2, 3] = float("nan")
+    torch.cuda.synchronize()
+    srv = rzf.Server(ctx, rzf.server_params(max_wait_us=1e5, max_batch=len(SIZES)))
+    srv.submit(trs[0], bad, W[0], tag=0)
+    for i in range(1, len(SIZES)):
+        srv.submit(trs[i], Hs[i][1], W[i], tag=i)
+    srv.drain()
+    st = {c.tag: c.status for c in srv.poll()}
+    big = [i for i, (K, N) in enumerate(SIZES) if K > 64]
+    assert st[0] == rzf.RZF_E_NONFINITE
+    assert all(st[i] == rzf.RZF_OK for i in big)
+    srv.submit(trs[0], Hs[0][2], W[0], tag=100)
+    srv.drain()
+    assert [c.status for c in srv.poll()] == [rzf.RZF_OK]
+    srv.close()
     ctx.close()
