@@ -28,7 +28,8 @@ static_assert(sizeof(KERNEL_NAMES) / sizeof(KERNEL_NAMES[0]) == KN_COUNT, "one n
 namespace {
 
 size_t scratch_bytes() {
-  return align_up(sizeof(int) * 64) + 2 * align_up(sizeof(float2) * KM * KM) +
+  return align_up(sizeof(int) * 64) + align_up(sizeof(unsigned) * RZF_BATCH_MAX) +
+         2 * align_up(sizeof(float2) * KM * KM) +
          align_up(sizeof(double) * ((RZF_NMAX + 15) / 16)) + align_up(sizeof(double) * 8) +
          align_up(sizeof(double) * sum_rate_scratch_doubles(KM)) + align_up(SPEC_BYTES) +
          NSTAGE * STAGE_BYTES;
@@ -47,7 +48,7 @@ Layout track_layout(int K, int N) {
   L.anew = o; o += align_up(sizeof(float2) * K * K);
   L.da = o; o += align_up(sizeof(float2) * K * K);
   L.a64 = o; o += align_up(sizeof(double2) * K * K);
-  L.wpart = o; o += align_up(sizeof(double) * precoder_blocks(N));
+  L.wpart = o; o += align_up(sizeof(double) * precoder_scratch(N));
   L.rfb = o; o += align_up(sizeof(float2) * K * K);
   if (K <= KS) {
     L.xw = o; o += align_up(sizeof(float2) * K * K);   // full-width SVD basis
@@ -388,6 +389,7 @@ rzf_status rzf_ctx_create(int device, void* hip_stream, void* arena, size_t aren
   c->arena_bytes = arena_bytes;
   char* p = c->arena;
   c->d_err = reinterpret_cast<int*>(p); p += align_up(sizeof(int) * 64);
+  c->d_counts = reinterpret_cast<unsigned*>(p); p += align_up(sizeof(unsigned) * RZF_BATCH_MAX);
   c->d_fullA = reinterpret_cast<float2*>(p); p += align_up(sizeof(float2) * KM * KM);
   c->d_fullAinv = reinterpret_cast<float2*>(p); p += align_up(sizeof(float2) * KM * KM);
   c->d_fullwpart = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * ((RZF_NMAX + 15) / 16));
@@ -406,6 +408,8 @@ rzf_status rzf_ctx_create(int device, void* hip_stream, void* arena, size_t aren
   bool stage_ok = hipHostMalloc((void**)&c->h_stage, NSTAGE * STAGE_BYTES, hipHostMallocDefault) == hipSuccess;
   for (int k = 0; k < NSTAGE && stage_ok; ++k)
     stage_ok = hipEventCreateWithFlags(&c->stage_ev[k], hipEventDisableTiming) == hipSuccess;
+  // the completion counts of the context's sum-rate launches start at zero
+  if (stage_ok) stage_ok = hipMemset(c->d_counts, 0, sizeof(unsigned) * RZF_BATCH_MAX) == hipSuccess;
   // the speculation area starts with no iteration posted (its tags zero)
   if (stage_ok)
     stage_ok = hipMemset(reinterpret_cast<char*>(c->d_spec) + sizeof(float2) * 2 * KS * KS * SPEC_MAX, 0,
@@ -522,7 +526,7 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
   }
   const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw, d.prec, &t->d_desc->hold};
   const ScaleJob sj{Wf, d.wpart, d.P, K, N, ldw, precoder_blocks(N)};
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, s); });
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (slot) {
@@ -590,7 +594,7 @@ rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, 
   std::vector<PrecJob> pj;
   std::vector<ScaleJob> sj;
   std::vector<int> reset_flag(n);
-  int maxK = 1, maxN = 1, maxNK = 1, maxKr = 1;
+  int maxK = 1, maxN = 1, maxKr = 1, maxNK = 1;
   for (int i = 0; i < n; ++i) {
     rzf_track* t = items[i].track;
     const TrackDesc& d = t->h_desc;
@@ -611,9 +615,9 @@ rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, 
     pj.push_back(PrecJob{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, items[i].ldh, items[i].ldw, d.prec,
                          &t->d_desc->hold});
     sj.push_back(ScaleJob{Wf, d.wpart, d.P, K, N, items[i].ldw, precoder_blocks(N)});
+    maxNK = std::max(maxNK, N * K);
     maxK = std::max(maxK, K);
     maxN = std::max(maxN, N);
-    maxNK = std::max(maxNK, N * K);
   }
   const size_t need = sizeof(GramJob) * gj.size() + sizeof(ArsvdJob) * (aj.size() + ajb.size()) +
                       sizeof(Gram64Job) * g64.size() + sizeof(Inv64Job) * (i64.size() + i64b.size()) +
@@ -647,7 +651,7 @@ rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, 
       if (!i64b.empty()) launch_inv64_big(i64b[0], d_i64b, (int)i64b.size(), err, s);
     });
   }
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, s); });
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
   HIP_OK(hipEventRecord(c->stage_ev[slot], s));
   c->stage_used[slot] = true;
@@ -686,7 +690,7 @@ rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items, cons
     maxK = std::max(maxK, it.K);
     maxN = std::max(maxN, it.N);
     maxNK = std::max(maxNK, it.N * it.K);
-    need += align_up(sizeof(float2) * it.K * it.K) + align_up(sizeof(double) * precoder_blocks(it.N));
+    need += align_up(sizeof(float2) * it.K * it.K) + align_up(sizeof(double) * precoder_scratch(it.N));
   }
   if (!scr && need > c->batch_full_bytes) {
     // grow: the old region may still be read by queued work
@@ -710,12 +714,12 @@ rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items, cons
     const rzf_full_item& it = items[i];
     float2* A = scr ? scr[i].A : reinterpret_cast<float2*>(p);
     double* wp = scr ? scr[i].wpart : reinterpret_cast<double*>(p + align_up(sizeof(float2) * it.K * it.K));
-    if (!scr) p += align_up(sizeof(float2) * it.K * it.K) + align_up(sizeof(double) * precoder_blocks(it.N));
+    if (!scr) p += align_up(sizeof(float2) * it.K * it.K) + align_up(sizeof(double) * precoder_scratch(it.N));
     const float2* Hf = reinterpret_cast<const float2*>(it.H);
     float2* Wf = reinterpret_cast<float2*>(it.W);
     gj[i] = GramJob{Hf, nullptr, A, nullptr, it.K, it.N, it.ldh, 0, (float)it.alpha, it.precision};
     (it.K > KS ? vjb : vj).push_back(Inv32Job{A, A, it.K});
-    pj[i] = PrecJob{Hf, A, Wf, wp, nullptr, it.K, it.N, it.ldh, it.ldw, it.precision};
+    pj[i] = PrecJob{Hf, A, Wf, wp, nullptr, it.K, it.N, it.ldh, it.ldw, it.precision, nullptr};
     sj[i] = ScaleJob{Wf, wp, it.P, it.K, it.N, it.ldw, precoder_blocks(it.N)};
   }
   const size_t bytes = (sizeof(GramJob) + sizeof(Inv32Job) + sizeof(PrecJob) + sizeof(ScaleJob)) * n + 64;
@@ -736,7 +740,7 @@ rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items, cons
     if (!vj.empty()) launch_inv32(vj[0], d_vj, (int)vj.size(), err, s);
     if (!vjb.empty()) launch_inv32_big(vjb[0], d_vjb, (int)vjb.size(), err, s);
   });
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, s); });
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
   HIP_OK(hipEventRecord(c->stage_ev[slot], s));
   c->stage_used[slot] = true;
@@ -810,7 +814,7 @@ rzf_status rzf_sum_rate_batch(rzf_ctx* c, int n, const rzf_rate_item* items, dou
     rj[i] = RateJob{reinterpret_cast<const float2*>(it.H), reinterpret_cast<const float2*>(it.W),
                     reinterpret_cast<double*>(reinterpret_cast<char*>(c->d_batch_part) + off),
                     it.rates, it.sum_rate, it.K, it.N, it.ldh, it.ldw, P,
-                    it.sigma2 >= 0.0 ? it.sigma2 : sigma2};
+                    it.sigma2 >= 0.0 ? it.sigma2 : sigma2, c->d_counts + i};
     off += align_up(sizeof(double) * sum_rate_scratch_doubles(it.K));
   }
   const int slot = stage_acquire(c);
@@ -840,12 +844,12 @@ rzf_status rzf_full(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   const float2* Hf = reinterpret_cast<const float2*>(H);
   float2* Wf = reinterpret_cast<float2*>(W);
   const GramJob gj{Hf, nullptr, c->d_fullA, nullptr, K, N, ldh, 0, (float)alpha, RZF_PREC_FP32};
-  const PrecJob pj{Hf, c->d_fullAinv, Wf, c->d_fullwpart, nullptr, K, N, ldh, ldw, RZF_PREC_FP32};
+  const PrecJob pj{Hf, c->d_fullAinv, Wf, c->d_fullwpart, nullptr, K, N, ldh, ldw, RZF_PREC_FP32, nullptr};
   const ScaleJob sj{Wf, c->d_fullwpart, P, K, N, ldw, precoder_blocks(N)};
   timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, s); });
   const Inv32Job vj{c->d_fullA, c->d_fullAinv, K};
   timed(c, KN_INV32, s, [&] { inv32_any(vj, c->d_err, s); });
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, s); });
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
 }
@@ -859,7 +863,7 @@ rzf_status rzf_sum_rate(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, con
   HIP_OK(hipSetDevice(c->device));
   hipStream_t s = c->stream;
   const RateJob rj{reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(W), c->d_srpart,
-                   rates, c->d_sum, K, N, ldh, ldw, P, sigma2};
+                   rates, c->d_sum, K, N, ldh, ldw, P, sigma2, c->d_counts};
   timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj, nullptr, 1, K, c->d_err, s); });
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (sum_rate) {

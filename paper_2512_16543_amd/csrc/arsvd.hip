@@ -764,15 +764,22 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     // the earlier iterations' posted energy tests (tid 0): 2 if one of them
     // meets the target (it, not this one, decides the step), 1 if all are
     // posted and none does, 0 if some are still missing after the wait
+    // The tags are polled with relaxed loads; an acquire fence follows the
+    // first match of each tag only (an agent-scope acquire invalidates the
+    // XCD's non-coherent cache lines, too costly on every poll).
     auto poll_earlier = [&](bool wait) -> int {
       const long long t_end = wall_clock64() + (wait ? SPEC_WAIT_TICKS : 0);
+      unsigned seen = 0;   // bit j: iteration j + 1 is posted and misses the target
       for (;;) {
         bool all = true;
         for (int j = 0; j + 1 < kfull; ++j) {
-          if (__hip_atomic_load(&tags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == jb.seq) {
+          if (seen & (1u << j)) continue;
+          if (__hip_atomic_load(&tags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == jb.seq) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const unsigned long long bits = __hip_atomic_load(
                 reinterpret_cast<unsigned long long*>(&spec_d[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (__longlong_as_double((long long)bits) >= Et) return 2;
+            seen |= 1u << j;
           } else {
             all = false;
           }

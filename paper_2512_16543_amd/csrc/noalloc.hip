@@ -14,8 +14,8 @@
 namespace {
 
 // Largest intermediate set of one call: A and A^-1 (RZF_KMAX^2 complex64
-// each) and the precoder's partial sums (one double per 16 antennas of
-// RZF_NMAX), each region on a 256-byte boundary.
+// each) and the precoder's partial sums (fewer than one double per 16
+// antennas of RZF_NMAX), each region on a 256-byte boundary.
 constexpr size_t NA_ALIGN = 256;
 constexpr size_t na_up(size_t x) { return (x + NA_ALIGN - 1) & ~(NA_ALIGN - 1); }
 constexpr size_t NA_MAT = na_up(sizeof(float2) * (size_t)RZF_KMAX * RZF_KMAX);
@@ -64,12 +64,12 @@ extern "C" rzf_status rzf_full_noalloc(void* hip_stream, int K, int N, const rzf
   // the launches of rzf_full, on the scratch above
   const GramJob gj{Hf, nullptr, A, nullptr, K, N, ldh, 0, (float)alpha, RZF_PREC_FP32};
   const Inv32Job vj{A, Ainv, K};
-  const PrecJob pj{Hf, Ainv, Wf, wpart, nullptr, K, N, ldh, ldw, RZF_PREC_FP32};
+  const PrecJob pj{Hf, Ainv, Wf, wpart, nullptr, K, N, ldh, ldw, RZF_PREC_FP32, nullptr};
   const ScaleJob sj{Wf, wpart, P, K, N, ldw, precoder_blocks(N)};
   launch_gram(gj, nullptr, 1, K, s);
   if (K > KS) launch_inv32_big(vj, nullptr, 1, err, s);
   else launch_inv32(vj, nullptr, 1, err, s);
-  launch_precoder(pj, nullptr, 1, N, s);
+  launch_precoder(pj, nullptr, 1, N, K, s);
   launch_scale(sj, nullptr, 1, N * K, s);
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
 }

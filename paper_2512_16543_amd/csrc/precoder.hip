@@ -1,35 +1,47 @@
 // Precoder W = H^H X with its power normalisation ||W||_F^2 = P (Sec. II,
 // eq. (5)), where X is the stored inverse of the Gram matrix.
 //
-// With the BF16 precision options the product takes BF16 operands (or BF16
-// hi/lo splits, three products each) with FP32 accumulation.
+// W is N x K (row-major).  A workgroup of 16 wavefronts owns 64 rows of W (64
+// antennas) of one track and computes their 16x16 tiles (4 x ceil(K/16) of
+// them, wave w taking tiles w, w + 16, ...) on the FP32 matrix cores.  The
+// length-K reduction runs over chunks of 32 users: the chunk's 32 x 64 block
+// of H and its 32 x K rows of X are staged in LDS (the next chunk's loads in
+// flight while this one is multiplied), so H and X are read from memory
+// once per workgroup.  For rzf_update the staged H is also copied into the
+// track's H_prev.
 //
-// W is N x K (row-major).  A workgroup owns 16 rows of W (16 antennas) and
-// computes their 16x16 tiles along K (tile slot s: tiles s, s + 4, ...) with
-// a length-K reduction on the FP32 matrix cores.  The FP32 path reads the
-// block's 16 columns of H_t into LDS once (all of its tiles share them).  The
-// block also writes its partial sum of |W|^2 (FP64) and, for rzf_update,
-// copies the 16 columns of H_t it has read into the track's H_prev.  A second kernel scales W once
-// every partial sum is known (partials are added in a fixed order).
+// Every workgroup writes its rows of W and the FP64 partial sum of their
+// |w|^2; a second kernel then adds the partial sums in block order (each of
+// its blocks once) and rescales W by sqrt(P / ||W||_F^2), with 16-byte loads
+// and stores.  The two launches meet at a kernel boundary, which makes the
+// partial sums visible to every XCD's L2 without a fence per workgroup.
+//
+// With the BF16 precision options the products take BF16 operands (or BF16
+// hi/lo splits, three products each), read per tile from memory, with FP32
+// accumulation.
 #include "rzf_device.h"
 #include "rzf_internal.h"
 
 namespace {
 
-// The length-K reduction of each tile is cut into four slices, each summed
-// from zero and then added in slice order.  A single-track launch gives every
-// (tile slot, slice) pair its own wavefront (16 wavefronts, slices added
-// through LDS); a batch launch, where many workgroups share each CU, gives
-// each of four wavefronts a tile slot and its four slices in turn.  Both forms
-// add the same numbers in the same order.
-template <bool MANY> constexpr int prec_waves() { return MANY ? 4 : 16; }
+constexpr int PB = 64;          // antennas (rows of W) per workgroup
+constexpr int PIC = 32;         // users per reduction chunk
+constexpr int PNT = 1024;       // threads per workgroup
+constexpr int PNW = PNT / 64;
+constexpr int HLD = PB + 4;     // LDS row stride of the staged H chunk (float2)
+constexpr int HPER = PIC * PB / PNT;              // H values a thread stages per chunk
+constexpr int XPER = (PIC * KM + PNT - 1) / PNT;  // X values, at most
+
+// Dynamic LDS of a launch for tracks up to maxK users: the H chunk, then the
+// X chunk with row stride maxK + 4.
+size_t prec_lds_bytes(int maxK) { return sizeof(float2) * (size_t)PIC * (HLD + maxK + 4); }
 
 template <bool MANY>
-__global__ __launch_bounds__(64 * prec_waves<MANY>()) void k_precoder(PrecJob one, const PrecJob* many) {
-  constexpr int NW = prec_waves<MANY>(), PER = 16 / NW;   // waves; slices per wave
-  __shared__ double red[NW];
-  __shared__ float part[NW == 16 ? 16 : 1][8][64];   // 16-wave form: the slices' partial tiles
-  __shared__ float2 hs[KM * 16];   // FP32 path: H[i][n0 + c] at hs[16 i + c]
+__global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* many, int xld) {
+  extern __shared__ float2 dyn[];
+  float2* hs = dyn;                       // [PIC][HLD]: H[i0 + ii][n0 + c] at hs[ii * HLD + c]
+  float2* xs = dyn + PIC * HLD;           // [PIC][xld]: X[i0 + ii][k] at xs[ii * xld + k]
+  __shared__ double red[PNW];
   const PrecJob& jb = job_of<MANY>(one, many);
   const int K = jb.K, N = jb.N, ldh = jb.ldh, ldw = jb.ldw;
   const float2* __restrict__ H = jb.H;
@@ -38,148 +50,173 @@ __global__ __launch_bounds__(64 * prec_waves<MANY>()) void k_precoder(PrecJob on
   double* __restrict__ wpart = jb.wpart;
   // a step that met a non-finite snapshot keeps the track's previous one
   float2* __restrict__ Hcopy = (jb.hold && *jb.hold) ? nullptr : jb.Hcopy;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int slot = wid & 3;
-  const int n0 = blockIdx.x * 16;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int n0 = blockIdx.x * PB;
   if (n0 >= N) return;
-  double acc = 0.0;
+  const int kt = (K + 15) / 16;
+  const int ntile = (PB / 16) * kt;
+  constexpr int TPW = (PB / 16) * (KM / 16) / PNW;   // tiles per wave, at most (4)
+  floatx4 tre[TPW], tim[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) { tre[q] = zero4(); tim[q] = zero4(); }
   const bool fp32 = jb.prec == RZF_PREC_FP32;
   if (fp32) {
-    // the block's 16 columns of H, read once (and copied to H_prev here)
-    for (int e = threadIdx.x; e < K * 16; e += blockDim.x) {
-      const int i = e >> 4, n = n0 + (e & 15);
-      const float2 v = n < N ? H[(size_t)i * ldh + n] : cz();
-      hs[e] = v;
-      if (Hcopy && n < N) Hcopy[(size_t)i * N + n] = v;
+    float2 ph[HPER], px[XPER];
+    auto fetch = [&](int i0) {
+#pragma unroll
+      for (int e = 0; e < HPER; ++e) {
+        const int idx = tid + PNT * e;          // 32 users x 64 antennas
+        const int i = i0 + idx / PB, n = n0 + idx % PB;
+        ph[e] = (i < K && n < N) ? H[(size_t)i * ldh + n] : cz();
+      }
+#pragma unroll
+      for (int e = 0; e < XPER; ++e) {
+        const int idx = tid + PNT * e;          // 32 users x K
+        const int ii = idx / K, k = idx - ii * K;
+        px[e] = (ii < PIC && i0 + ii < K) ? X[(size_t)(i0 + ii) * K + k] : cz();
+      }
+    };
+    fetch(0);
+    for (int i0 = 0; i0 < K; i0 += PIC) {
+#pragma unroll
+      for (int e = 0; e < HPER; ++e) {
+        const int idx = tid + PNT * e;
+        const int ii = idx / PB, c = idx % PB;
+        hs[ii * HLD + c] = ph[e];
+        if (Hcopy && i0 + ii < K && n0 + c < N) Hcopy[(size_t)(i0 + ii) * N + n0 + c] = ph[e];
+      }
+#pragma unroll
+      for (int e = 0; e < XPER; ++e) {
+        const int idx = tid + PNT * e;
+        const int ii = idx / K, k = idx - ii * K;
+        if (ii < PIC) xs[ii * xld + k] = px[e];
+      }
+      __syncthreads();
+      if (i0 + PIC < K) fetch(i0 + PIC);
+      const int ic = min(PIC, K - i0);   // users of this chunk (the rest of LDS holds zeros)
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        const int t = wid + PNW * q;
+        if (t >= ntile) break;
+        const int nt = t % (PB / 16), ct = t / (PB / 16);
+        const int col = ct * 16 + (lane & 15);
+        const bool okc = col < K;
+        // A(n, i) = conj(H[i][n]);  B(i, k) = X[i][k]
+        ctile16([&](int rr, int i) { return cconj(hs[i * HLD + nt * 16 + rr]); },
+                [&](int i, int) { return okc ? xs[i * xld + col] : cz(); }, 0, (ic + 3) & ~3, tre[q], tim[q]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+    // BF16 operands, 32 users of the reduction per product
+    const bool x3 = jb.prec == RZF_PREC_BF16X3;
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = wid + PNW * q;
+      if (t >= ntile) break;
+      const int nt = t % (PB / 16), ct = t / (PB / 16);
+      const int rr = lane & 15, kq = lane >> 4;
+      const int n = n0 + nt * 16 + rr, k = ct * 16 + rr;
+      for (int j0 = 0; j0 < K; j0 += 32) {
+        float2 a[8], b[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int i = j0 + 8 * kq + e;
+          a[e] = (n < N && i < K) ? H[(size_t)i * ldh + n] : cz();
+          b[e] = (i < K && k < K) ? X[(size_t)i * K + k] : cz();
+        }
+        cmac8_bf16(a, b, true, false, x3, tre[q], tim[q]);
+      }
+    }
+    if (Hcopy)
+      for (int e = tid; e < K * PB; e += PNT) {
+        const int i = e / PB, n = n0 + e % PB;
+        if (n < N) Hcopy[(size_t)i * N + n] = H[(size_t)i * ldh + n];
+      }
   }
-  // slice ks: users [ks kc, ks kc + kc), kc a multiple of 4 (FP32 tiles) or
-  // of 32 (BF16 products)
-  const int kc = fp32 ? ((K + 15) / 16) * 4 : ((K + 127) / 128) * 32;
-  // every wave runs the same number of passes (the 16-wave form has barriers)
-  for (int base = 0; base * 16 < K; base += 4) {
-    const int kt = base + slot, k0 = kt * 16;
-    const bool active = k0 < K;
-    floatx4 tre = zero4(), tim = zero4();
-    if (active) {
-      for (int q = 0; q < PER; ++q) {
-        const int ks = (wid >> 2) + q;
-        const int i0 = ks * kc, i1 = min(K, i0 + kc);
-        floatx4 dr = zero4(), di = zero4();
-        if (fp32) {
-          // A(n, i) = conj(H[i][n]) from LDS;  B(i, k) = X[i][k]
-          const int col = k0 + (lane & 15);
-          const bool okc = col < K;
-          const float2* xc = X + col;
-          ctile16([&](int rr, int i) { return i < K ? cconj(hs[i * 16 + rr]) : cz(); },
-                  [&](int i, int) { return (i < K && okc) ? xc[(size_t)i * K] : cz(); }, i0, i1, dr, di);
-        } else {
-          // BF16 operands, 32 users of the reduction per product
-          const bool x3 = jb.prec == RZF_PREC_BF16X3;
-          const int rr = lane & 15, kq = lane >> 4;
-          const int n = n0 + rr, k = k0 + rr;
-          for (int j0 = i0; j0 < i1; j0 += 32) {
-            float2 a[8], b[8];
+  // the block's rows of W (unscaled) and their sum of |w|^2
+  double acc = 0.0;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const int i = j0 + 8 * kq + e;
-              a[e] = (n < N && i < K) ? H[(size_t)i * ldh + n] : cz();
-              b[e] = (i < K && k < K) ? X[(size_t)i * K + k] : cz();
-            }
-            cmac8_bf16(a, b, true, false, x3, dr, di);
-          }
-        }
-        tre += dr;
-        tim += di;
-      }
-    }
-    bool own = active;   // this wave writes the tile
-    if constexpr (NW == 16) {
+  for (int q = 0; q < TPW; ++q) {
+    const int t = wid + PNW * q;
+    if (t >= ntile) break;
+    const int nt = t % (PB / 16), ct = t / (PB / 16);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        part[wid][v][lane] = tre[v];
-        part[wid][4 + v][lane] = tim[v];
-      }
-      __syncthreads();
-      own = active && wid < 4;
-      if (own) {
-        tre = zero4();
-        tim = zero4();
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            tre[v] += part[slot + 4 * q][v][lane];
-            tim[v] += part[slot + 4 * q][4 + v][lane];
-          }
-        }
-      }
-      __syncthreads();
-    }
-    if (own) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int n = n0 + tile_row(v), k = k0 + tile_col();
-        if (n < N && k < K) {
-          W[(size_t)n * ldw + k] = make_float2(tre[v], tim[v]);
-          acc += (double)tre[v] * tre[v] + (double)tim[v] * tim[v];
-        }
+    for (int v = 0; v < 4; ++v) {
+      const int n = n0 + nt * 16 + tile_row(v), k = ct * 16 + tile_col();
+      if (n < N && k < K) {
+        W[(size_t)n * ldw + k] = make_float2(tre[q][v], tim[q][v]);
+        acc += (double)tre[q][v] * tre[q][v] + (double)tim[q][v] * tim[q][v];
       }
     }
   }
   acc = wave_sum(acc);
   if (lane == 0) red[wid] = acc;
-  if (Hcopy && !fp32) {
-    // the 16 columns n0..n0+15 of every row of H_t
-    for (int e = threadIdx.x; e < K * 16; e += blockDim.x) {
-      const int i = e >> 4, n = n0 + (e & 15);
-      if (n < N) Hcopy[(size_t)i * N + n] = H[(size_t)i * ldh + n];
-    }
-  }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // waves 4.. of the 16-wave form hold zero
-    double w = red[0] + red[1] + red[2] + red[3];
+  if (tid == 0) {
+    double w = 0.0;
+    for (int q = 0; q < PNW; ++q) w += red[q];
     wpart[blockIdx.x] = w;
   }
 }
 
-// Blocks stride over the N x K entries of W (SCALE_BLOCKS per track at most),
-// so a batch of small and large tracks launches few empty blocks.
-constexpr int SCALE_BLOCKS = 32;
+// Power normalisation: blocks of SCT threads stride over a track's N x K
+// entries of W (at most SCB blocks per track); each first adds the partial
+// sums in block order.  Rows of W are scaled two entries per 16-byte access
+// when ldw and K are even (the row starts are then 16-byte aligned).
+constexpr int SCT = 256, SCB = 64;
 
 template <bool MANY>
-__global__ __launch_bounds__(256) void k_scale(ScaleJob one, const ScaleJob* many) {
+__global__ __launch_bounds__(SCT) void k_scale(ScaleJob one, const ScaleJob* many) {
   const ScaleJob& jb = job_of<MANY>(one, many);
   const int K = jb.K, N = jb.N, ldw = jb.ldw, nparts = jb.nparts;
   float2* __restrict__ W = jb.W;
-  const double* __restrict__ wpart = jb.wpart;
-  const double P = jb.P;
-  const int NK = N * K;
-  if ((int)(blockIdx.x * blockDim.x) >= NK) return;
-  double tot = 0.0;
-  for (int b = 0; b < nparts; ++b) tot += wpart[b];
-  const float s = (tot > 0.0) ? (float)sqrt(P / tot) : 0.f;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NK; e += gridDim.x * blockDim.x) {
-    const int n = e / K, k = e - n * K;
-    float2* w = W + (size_t)n * ldw + k;
-    *w = cscale(*w, s);
+  const int per = (N * K + 2 * SCT - 1) / (2 * SCT);   // blocks a track needs at two entries per thread
+  if ((int)blockIdx.x >= min(per, SCB)) return;
+  __shared__ float sc;
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int b = 0; b < nparts; ++b) tot += jb.wpart[b];
+    sc = tot > 0.0 ? (float)sqrt(jb.P / tot) : 0.f;
+  }
+  __syncthreads();
+  const float s = sc;
+  const int stride = min(per, SCB) * SCT;
+  if ((K & 1) == 0 && (ldw & 1) == 0 && (reinterpret_cast<uintptr_t>(W) & 15) == 0) {
+    const int K2 = K >> 1;
+    for (int e = blockIdx.x * SCT + threadIdx.x; e < N * K2; e += stride) {
+      const int n = e / K2, k2 = e - n * K2;
+      float4* w = reinterpret_cast<float4*>(W + (size_t)n * ldw) + k2;
+      float4 v = *w;
+      v.x *= s; v.y *= s; v.z *= s; v.w *= s;
+      *w = v;
+    }
+  } else {
+    for (int e = blockIdx.x * SCT + threadIdx.x; e < N * K; e += stride) {
+      const int n = e / K, k = e - n * K;
+      float2* w = W + (size_t)n * ldw + k;
+      *w = cscale(*w, s);
+    }
   }
 }
 
 }  // namespace
 
-int precoder_blocks(int N) { return (N + 15) / 16; }
-
-void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, hipStream_t s) {
-  const dim3 grid(precoder_blocks(maxN), many ? n : 1);
-  if (many) k_precoder<true><<<grid, 64 * prec_waves<true>(), 0, s>>>(one, many);
-  else k_precoder<false><<<grid, 64 * prec_waves<false>(), 0, s>>>(one, many);
-}
+int precoder_blocks(int N) { return (N + PB - 1) / PB; }
 
 void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, hipStream_t s) {
-  const int blocks = (maxNK + 255) / 256 < SCALE_BLOCKS ? (maxNK + 255) / 256 : SCALE_BLOCKS;
+  const int blocks = std::min((maxNK + 2 * SCT - 1) / (2 * SCT), SCB);
   const dim3 grid(blocks, many ? n : 1);
-  if (many) k_scale<true><<<grid, 256, 0, s>>>(one, many);
-  else k_scale<false><<<grid, 256, 0, s>>>(one, many);
+  if (many) k_scale<true><<<grid, SCT, 0, s>>>(one, many);
+  else k_scale<false><<<grid, SCT, 0, s>>>(one, many);
+}
+
+int precoder_scratch(int N) { return precoder_blocks(N); }
+
+void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, hipStream_t s) {
+  const dim3 grid(precoder_blocks(maxN), many ? n : 1);
+  const size_t lds = prec_lds_bytes(maxK);
+  const int xld = maxK + 4;
+  if (many) k_precoder<true><<<grid, PNT, lds, s>>>(one, many, xld);
+  else k_precoder<false><<<grid, PNT, lds, s>>>(one, many, xld);
 }

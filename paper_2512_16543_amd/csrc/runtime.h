@@ -45,6 +45,7 @@ struct rzf_ctx {
   std::map<size_t, size_t> free_blocks;   // offset -> size
   // fixed scratch at the front of the arena
   int* d_err = nullptr;
+  unsigned* d_counts = nullptr;         // completion counts of the context's sum-rate launches (item i at i)
   int held_err = 0;                     // device error of earlier work, kept for rzf_sync
   float2* d_fullA = nullptr;
   float2* d_fullAinv = nullptr;

@@ -37,7 +37,7 @@ struct TrackDesc {
   float2* Anew;    // K x K, ld K: A' of the current step (FP32)
   float2* dA;      // K x K, ld K: Delta A of the current step
   double2* A64;    // K x K, ld K: FP64 Gram for init / reset
-  double* wpart;   // partial ||W||^2 of the precoder blocks
+  double* wpart;   // precoder scratch: partial ||W||^2 of its blocks, then its completion count
   // working set of the large-track kernels (K > KS), null otherwise; all
   // column-major with leading dimension K
   float2* Ym;      // K x K: sketch Y, the Householder vectors, Q^H Delta A Z_r, then P = A^-1 U
@@ -138,6 +138,7 @@ struct RateJob {
   const float2* H; const float2* W; double* part; float* rates; double* sum;
   int K, N, ldh, ldw;
   double P, sigma2;
+  unsigned* count; // the launch's completion count: zero before, left at zero after
 };
 
 template <bool MANY, class J>
@@ -152,8 +153,13 @@ void launch_gram(const GramJob& one, const GramJob* many, int n, int maxK, hipSt
 void launch_gram64(const Gram64Job& one, const Gram64Job* many, int n, int maxK, hipStream_t s);
 void launch_inv64(const Inv64Job& one, const Inv64Job* many, int n, int* err, hipStream_t s);
 void launch_inv32(const Inv32Job& one, const Inv32Job* many, int n, int* err, hipStream_t s);
+// Precoder workgroups of an N-antenna track, and the doubles of its scratch
+// wpart (the workgroups' partial sums).
 int precoder_blocks(int N);
-void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, hipStream_t s);
+int precoder_scratch(int N);
+void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, hipStream_t s);
+// W <- W sqrt(P / ||W||_F^2) from the precoder's partial sums (maxNK: the
+// largest N K of the launch).
 void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, hipStream_t s);
 void launch_arsvd_wb(const ArsvdJob& one, const ArsvdJob* many, int n, int* err, hipStream_t s);
 // The same step for one track in two launches (one.spec set): the iterations

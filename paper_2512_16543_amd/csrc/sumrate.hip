@@ -4,158 +4,175 @@
 // |E_nn|^2 / (sum_{i != n} |E_ni|^2 + sigma^2) and R = sum_n log2(1 + SINR_n)
 // (the row-n channel of eq. (15) is row n of H).
 //
-// k_sr_tiles: one workgroup per 16x16 tile of E.  The length-N reduction is
-//   cut into 16 slices (slice s: antennas 16 s + 256 j + [0, 16)), each
-//   summed from zero on the matrix cores, and the slice sums are added as
-//   (s0 + s4 + s8 + s12) + (s1 + s5 + ...) + ....  A single-track launch
-//   gives every slice its own wavefront (16 wavefronts: each issues its few
-//   loads at once); a batch launch, where many workgroups share each CU, gives
-//   each of four wavefronts the slices w, w + 4, w + 8, w + 12 in turn.  Both
-//   forms add the same numbers in the same order.  For each row of its tile
-//   the workgroup writes its share of the signal (diagonal tile only) and of
-//   the interference; the workgroups of the first tile row also write the
-//   squared norm of their 16 columns of W.
-// k_sr_final: one workgroup adds the shares in a fixed order, applies the
-//   power scaling and sums the rates in FP64.
+// One launch.  A workgroup of 16 wavefronts owns a 64 x 64 block of E (users
+// rb*64.. by users cb*64..) of one track; wave w computes its 16x16 tile on the
+// FP32 matrix cores.  The length-N reduction runs over chunks of 64 antennas:
+// the chunk's 64 x 64 block of H and 64 x 64 block of W are staged in LDS
+// (the next chunk's loads in flight while this one is multiplied).  For each
+// of its rows the workgroup writes its share of the signal (diagonal block
+// only) and of the interference; the workgroups of the first block row also
+// add the squared norm of their 64 columns of W.  With K <= 64 the track's one
+// workgroup then applies the power scaling and sums the rates in FP64 from
+// LDS.  Otherwise the shares go to scratch and the track's last workgroup to
+// finish (a completion count per item, zero between launches) adds them in a
+// fixed order; only the wave that wrote them fences before counting, since an
+// agent-scope fence writes back the XCD's L2.
 #include "rzf_device.h"
 #include "rzf_internal.h"
 
 namespace {
 
-constexpr int SR_SLICES = 16;
-template <bool MANY> constexpr int sr_waves() { return MANY ? 4 : SR_SLICES; }
+constexpr int SB = 64;          // users per block side
+constexpr int SC = 64;          // antennas per reduction chunk
+constexpr int SNT = 1024;
+constexpr int SNW = SNT / 64;
+constexpr int SLD = SC + 4;     // LDS row stride of the H chunk (64 users x 64 antennas)
+constexpr int WLD = SB + 4;     // LDS row stride of the W chunk (64 antennas x 64 users)
+constexpr int SPER = SB * SC / SNT;   // values of each chunk a thread stages (4)
+
+// Scratch layout of one item (doubles): the shares [n][cb][2] (signal,
+// interference), then the column blocks' ||W||^2 [cb].  The completion count
+// (one per item) is zero before the launch and is left at zero.
+__host__ __device__ constexpr int sr_blocks(int K) { return (K + SB - 1) / SB; }
 
 template <bool MANY>
-__global__ __launch_bounds__(64 * sr_waves<MANY>()) void k_sr_tiles(RateJob one, const RateJob* many) {
-  constexpr int NW = sr_waves<MANY>(), PER = SR_SLICES / NW;   // waves, slices per wave
-  __shared__ float red[NW][8][64];
-  __shared__ double wred[NW];
+__global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* many, int* err) {
+  __shared__ float2 hs[SB * SLD], ws[SC * WLD];
+  __shared__ double rs[4][SB], rf[4][SB];
+  __shared__ double red[SNW];
+  __shared__ int last;
   const RateJob& jb = job_of<MANY>(one, many);
   const int K = jb.K, N = jb.N, ldh = jb.ldh, ldw = jb.ldw;
   const float2* __restrict__ H = jb.H;
   const float2* __restrict__ W = jb.W;
+  unsigned* const count = jb.count;
   double* __restrict__ part = jb.part;
-  const int kt = (K + 15) / 16;
-  if ((int)blockIdx.x >= kt * kt) return;
-  const int ti = blockIdx.x / kt, tj = blockIdx.x - ti * kt;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int n0 = ti * 16, m0 = tj * 16;
-  floatx4 tr = zero4(), tim = zero4();   // this wave's slices, added in order
-  double twn = 0.0;
-  for (int q = 0; q < PER; ++q) {
-    const int sl = wid + NW * q;
-    floatx4 dr = zero4(), di = zero4();
-    double wn = 0.0;
-    for (int j0 = sl * 16; j0 < N; j0 += 16 * SR_SLICES) {
-      ctile16([&](int rr, int j) { const int n = n0 + rr; return (n < K && j < N) ? H[(size_t)n * ldh + j] : cz(); },
-              [&](int j, int cc) {
-                const int m = m0 + cc;
-                return (j < N && m < K) ? W[(size_t)j * ldw + m] : cz();
-              },
-              j0, j0 + 16, dr, di);
-      if (ti == 0) {
-        // |W|^2 over rows j0..j0+15 and this tile's 16 columns
-        for (int e = lane; e < 256; e += 64) {
-          const int j = j0 + (e >> 4), m = m0 + (e & 15);
-          if (j < N && m < K) wn += (double)cabs2(W[(size_t)j * ldw + m]);
-        }
-      }
+  const int kb = sr_blocks(K);
+  if ((int)blockIdx.x >= kb * kb) return;
+  const int rb = blockIdx.x / kb, cb = blockIdx.x - rb * kb;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int nt = wid >> 2, ct = wid & 3;          // this wave's tile in the block
+  const int r0 = rb * SB, m0 = cb * SB;
+  floatx4 dr = zero4(), di = zero4();
+  double wn = 0.0;                                // |W|^2 of the staged values (rb == 0)
+  float2 ph[SPER], pw[SPER];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int e = 0; e < SPER; ++e) {
+      const int idx = tid + SNT * e;
+      const int a = idx / SC, b = idx % SC;     // H: user a, antenna b;  W: antenna a, user b
+      const int n = r0 + a, j = c0 + b;
+      ph[e] = (n < K && j < N) ? H[(size_t)n * ldh + j] : cz();
+      const int jw = c0 + a, m = m0 + b;
+      pw[e] = (jw < N && m < K) ? W[(size_t)jw * ldw + m] : cz();
     }
-    if (q == 0) {
-      tr = dr; tim = di;
-    } else {
-      tr += dr; tim += di;
+  };
+  fetch(0);
+  for (int c0 = 0; c0 < N; c0 += SC) {
+#pragma unroll
+    for (int e = 0; e < SPER; ++e) {
+      const int idx = tid + SNT * e;
+      const int a = idx / SC, b = idx % SC;
+      hs[a * SLD + b] = ph[e];
+      ws[a * WLD + b] = pw[e];
+      if (rb == 0) wn += (double)cabs2(pw[e]);
     }
-    if (ti == 0) {
-      const double ws = wave_sum(wn);
-      twn = q == 0 ? ws : twn + ws;
-    }
+    __syncthreads();
+    if (c0 + SC < N) fetch(c0 + SC);
+    const int jc = min(SC, N - c0);
+    // E(n, m) += sum_j H[n][j] W[j][m]
+    ctile16([&](int rr, int j) { return hs[(nt * 16 + rr) * SLD + j]; },
+            [&](int j, int cc) { return ws[j * WLD + ct * 16 + cc]; }, 0, (jc + 3) & ~3, dr, di);
+    __syncthreads();
   }
+  // the block's signal and interference shares of each row, over its columns
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    red[wid][v][lane] = tr[v];
-    red[wid][4 + v][lane] = tim[v];
-  }
-  if (ti == 0 && lane == 0) wred[wid] = twn;
-  __syncthreads();
-  // wave v (< 4): signal and interference shares of the tile's rows 4 kq + v
-  if (wid >= 4) return;
-  {
-    const int v = wid;
-    float re = 0.f, im = 0.f;
-    for (int w = 0; w < 4; ++w) {
-      // slice sums of group w (slices w, w + 4, ...), added in order
-      float gr = red[w][v][lane], gi = red[w][4 + v][lane];
-      for (int q = 1; q < SR_SLICES / 4 / PER; ++q) {
-        gr += red[w + 4 * q][v][lane];
-        gi += red[w + 4 * q][4 + v][lane];
-      }
-      re += gr;
-      im += gi;
-    }
-    const int n = n0 + tile_row(v), m = m0 + tile_col();
-    const float e2 = (n < K && m < K) ? re * re + im * im : 0.f;
-    // sum over the 16 columns of the tile (lanes of one 16-lane row)
+    const int i = nt * 16 + tile_row(v);
+    const int n = r0 + i, m = m0 + ct * 16 + tile_col();
+    const float e2 = (n < K && m < K) ? dr[v] * dr[v] + di[v] * di[v] : 0.f;
     const double s = row16_sum((double)((n == m) ? e2 : 0.f));
     const double f = row16_sum((double)((n == m) ? 0.f : e2));
-    if ((lane & 15) == 0 && n < K) {
-      part[(size_t)(n * kt + tj) * 2] = s;
-      part[(size_t)(n * kt + tj) * 2 + 1] = f;
+    if ((lane & 15) == 0) {
+      rs[ct][i] = s;
+      rf[ct][i] = f;
     }
   }
-  if (ti == 0 && threadIdx.x == 0) {
-    double w = 0.0;
-    for (int g = 0; g < 4; ++g) {
-      double gw = wred[g];
-      for (int q = 1; q < SR_SLICES / 4 / PER; ++q) gw += wred[g + 4 * q];
-      w += gw;
-    }
-    part[(size_t)K * kt * 2 + tj] = w;
-  }
-}
-
-template <bool MANY>
-__global__ __launch_bounds__(64) void k_sr_final(RateJob one, const RateJob* many, int* err) {
-  const RateJob& jb = job_of<MANY>(one, many);
-  const int K = jb.K;
-  const double P = jb.P, sigma2 = jb.sigma2;
-  const double* __restrict__ part = jb.part;
-  float* rates = jb.rates;
-  double* sum_out = jb.sum;
-  const int kt = (K + 15) / 16;
-  double wn = 0.0;
-  for (int t = 0; t < kt; ++t) wn += part[(size_t)K * kt * 2 + t];
-  const double s2 = (wn > 0.0) ? P / wn : 0.0;      // |scale|^2
+  wn = wave_sum(wn);
+  if (lane == 0) red[wid] = wn;
+  __syncthreads();
   double acc = 0.0;
-  for (int n = threadIdx.x; n < K; n += 64) {
-    double sig = 0.0, intf = 0.0;
-    for (int t = 0; t < kt; ++t) {
-      sig += part[(size_t)(n * kt + t) * 2];
-      intf += part[(size_t)(n * kt + t) * 2 + 1];
+  if (kb == 1) {
+    // one workgroup owns the track: the rates straight from its shares
+    if (tid < K) {
+      double wt = 0.0;
+      for (int q = 0; q < SNW; ++q) wt += red[q];
+      const double s2 = (wt > 0.0) ? jb.P / wt : 0.0;   // |scale|^2
+      const double sig = ((rs[0][tid] + rs[1][tid]) + rs[2][tid]) + rs[3][tid];
+      const double intf = ((rf[0][tid] + rf[1][tid]) + rf[2][tid]) + rf[3][tid];
+      const double rate = log2(1.0 + (s2 * sig) / (s2 * intf + jb.sigma2));
+      if (jb.rates) jb.rates[tid] = (float)rate;
+      if (!isfinite(rate)) atomicCAS(err, 0, DEV_ERR_NONFINITE);
+      acc = rate;
     }
-    const double rate = log2(1.0 + (s2 * sig) / (s2 * intf + sigma2));
-    if (rates) rates[n] = (float)rate;
-    if (!isfinite(rate)) atomicCAS(err, 0, DEV_ERR_NONFINITE);
-    acc += rate;
+  } else {
+    // the shares (written by wave 0 alone) go to memory for the track's last block
+    if (tid < SB && r0 + tid < K) {
+      const double s = ((rs[0][tid] + rs[1][tid]) + rs[2][tid]) + rs[3][tid];
+      const double f = ((rf[0][tid] + rf[1][tid]) + rf[2][tid]) + rf[3][tid];
+      part[((size_t)(r0 + tid) * kb + cb) * 2] = s;
+      part[((size_t)(r0 + tid) * kb + cb) * 2 + 1] = f;
+    }
+    double* const wnorm = part + (size_t)2 * K * kb;
+    if (wid == 0) {
+      if (tid == 0 && rb == 0) {
+        double w = 0.0;
+        for (int q = 0; q < SNW; ++q) w += red[q];
+        wnorm[cb] = w;
+      }
+      __threadfence();   // the wave's stores before the block counts itself done
+      if (tid == 0) last = atomicAdd(count, 1u) == (unsigned)(kb * kb - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    // the track's last block: every share is visible
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double wt = 0.0;
+    for (int c = 0; c < kb; ++c) wt += wnorm[c];
+    const double s2 = (wt > 0.0) ? jb.P / wt : 0.0;
+    for (int n = tid; n < K; n += SNT) {
+      double sig = 0.0, intf = 0.0;
+      for (int c = 0; c < kb; ++c) {
+        sig += part[((size_t)n * kb + c) * 2];
+        intf += part[((size_t)n * kb + c) * 2 + 1];
+      }
+      const double rate = log2(1.0 + (s2 * sig) / (s2 * intf + jb.sigma2));
+      if (jb.rates) jb.rates[n] = (float)rate;
+      if (!isfinite(rate)) atomicCAS(err, 0, DEV_ERR_NONFINITE);
+      acc += rate;
+    }
   }
   acc = wave_sum(acc);
-  if (threadIdx.x == 0 && sum_out) *sum_out = acc;
+  __syncthreads();   // every read of red above is done
+  if (lane == 0) red[wid] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int q = 0; q < SNW; ++q) tot += red[q];
+    if (jb.sum) *jb.sum = tot;
+    if (kb > 1) *count = 0u;
+  }
 }
 
 }  // namespace
 
 size_t sum_rate_scratch_doubles(int K) {
-  const int kt = (K + 15) / 16;
-  return (size_t)K * kt * 2 + kt;
+  const int kb = sr_blocks(K);
+  return (size_t)2 * K * kb + kb;
 }
 
 void launch_sum_rate(const RateJob& one, const RateJob* many, int n, int maxK, int* err, hipStream_t s) {
-  const int kt = (maxK + 15) / 16;
-  if (many) {
-    k_sr_tiles<true><<<dim3(kt * kt, n), 64 * sr_waves<true>(), 0, s>>>(one, many);
-    k_sr_final<true><<<dim3(1, n), 64, 0, s>>>(one, many, err);
-  } else {
-    k_sr_tiles<false><<<kt * kt, 64 * sr_waves<false>(), 0, s>>>(one, many);
-    k_sr_final<false><<<1, 64, 0, s>>>(one, many, err);
-  }
+  const int kb = sr_blocks(maxK);
+  if (many) k_sum_rate<true><<<dim3(kb * kb, n), SNT, 0, s>>>(one, many, err);
+  else k_sum_rate<false><<<kb * kb, SNT, 0, s>>>(one, many, err);
 }
