@@ -27,11 +27,13 @@ static_assert(sizeof(KERNEL_NAMES) / sizeof(KERNEL_NAMES[0]) == KN_COUNT, "one n
 
 namespace {
 
+size_t sr_single_doubles() { return std::max(sum_rate_scratch_doubles(KM), sum_rate_split_scratch_doubles()); }
+
 size_t scratch_bytes() {
   return align_up(sizeof(int) * 64) + align_up(sizeof(unsigned) * RZF_BATCH_MAX) +
          2 * align_up(sizeof(float2) * KM * KM) +
          align_up(sizeof(double) * ((RZF_NMAX + 15) / 16)) + align_up(sizeof(double) * 8) +
-         align_up(sizeof(double) * sum_rate_scratch_doubles(KM)) + align_up(SPEC_BYTES) +
+         align_up(sizeof(double) * sr_single_doubles()) + align_up(SPEC_BYTES) +
          NSTAGE * STAGE_BYTES;
 }
 
@@ -394,7 +396,7 @@ rzf_status rzf_ctx_create(int device, void* hip_stream, void* arena, size_t aren
   c->d_fullAinv = reinterpret_cast<float2*>(p); p += align_up(sizeof(float2) * KM * KM);
   c->d_fullwpart = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * ((RZF_NMAX + 15) / 16));
   c->d_sum = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * 8);
-  c->d_srpart = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * sum_rate_scratch_doubles(KM));
+  c->d_srpart = reinterpret_cast<double*>(p); p += align_up(sizeof(double) * sr_single_doubles());
   c->d_spec = reinterpret_cast<float2*>(p); p += align_up(SPEC_BYTES);
   c->d_stage = p;
   c->free_blocks[scr] = arena_bytes - scr;
@@ -823,7 +825,7 @@ rzf_status rzf_sum_rate_batch(rzf_ctx* c, int n, const rzf_rate_item* items, dou
   RateJob* d_rj = nullptr;
   st.put(rj.data(), n, &d_rj);
   HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
-  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj[0], d_rj, n, maxK, c->d_err, s); });
+  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj[0], d_rj, n, maxK, 1, c->d_err, s); });
   HIP_OK(hipEventRecord(c->stage_ev[slot], s));
   c->stage_used[slot] = true;
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
@@ -864,7 +866,7 @@ rzf_status rzf_sum_rate(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, con
   hipStream_t s = c->stream;
   const RateJob rj{reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(W), c->d_srpart,
                    rates, c->d_sum, K, N, ldh, ldw, P, sigma2, c->d_counts};
-  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj, nullptr, 1, K, c->d_err, s); });
+  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj, nullptr, 1, K, sum_rate_splits(K, N), c->d_err, s); });
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (sum_rate) {
     HIP_OK(hipMemcpyAsync(c->h_sum, c->d_sum, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -613,10 +613,14 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     __syncthreads();
     t_sk += clock64() - c_mark; c_mark = clock64();
     } else {
-    // Omega -> b1 (column-major)
-    for (int e = tid; e < K * d; e += NTH) {
-      const int j = e / K, i = e - j * K;
-      b1[j * LDK + i] = sketch_entry(seed, trk, t, itn, i, j);
+    // Omega -> b1 (column-major), two rows per counter block
+    const int Kh = (K + 1) >> 1;
+    for (int e = tid; e < Kh * d; e += NTH) {
+      const int j = e / Kh, h = e - j * Kh;
+      float2 ev, od;
+      sketch_pair(seed, trk, t, itn, h, j, &ev, &od);
+      b1[j * LDK + 2 * h] = ev;
+      if (2 * h + 1 < K) b1[j * LDK + 2 * h + 1] = od;
     }
     __syncthreads();
     // Y = Delta A Omega -> b2

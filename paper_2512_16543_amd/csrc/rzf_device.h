@@ -197,6 +197,19 @@ __device__ __forceinline__ float2 sketch_entry(uint64_t seed, uint64_t track, in
   return words_to_cn(wa, wb);
 }
 
+// Rows 2h and 2h + 1 of column j from their one shared counter block.
+__device__ __forceinline__ void sketch_pair(uint64_t seed, uint64_t track, int t, int it, int h, int j,
+                                            float2* even, float2* odd) {
+  uint64_t c[4];
+  c[0] = (uint64_t)j * 512ull + (uint64_t)h;
+  c[1] = (uint64_t)it;
+  c[2] = (uint64_t)t;
+  c[3] = 0ull;
+  philox4x64_10(c, seed, track);
+  *even = words_to_cn(c[0], c[1]);
+  *odd = words_to_cn(c[2], c[3]);
+}
+
 // ------------------------------------------------- complex MFMA 16x16 tile
 // One wavefront accumulates D(16x16) += A(16 x k) * B(k x 16) in FP32 on the
 // matrix cores with v_mfma_f32_16x16x4_f32.  Operand lane layout of that

@@ -172,7 +172,12 @@ void launch_arsvd_big(const ArsvdJob& one, const ArsvdJob* many, int n, int* err
 void launch_inv64_big(const Inv64Job& one, const Inv64Job* many, int n, int* err, hipStream_t s);
 void launch_inv32_big(const Inv32Job& one, const Inv32Job* many, int n, int* err, hipStream_t s);
 size_t sum_rate_scratch_doubles(int K);
-void launch_sum_rate(const RateJob& one, const RateJob* many, int n, int maxK, int* err, hipStream_t s);
+// A single track's launch may split the antenna sum over ns workgroups
+// (sum_rate_splits; batch launches take ns = 1); its scratch then holds
+// sum_rate_split_scratch_doubles().
+size_t sum_rate_split_scratch_doubles();
+int sum_rate_splits(int K, int N);
+void launch_sum_rate(const RateJob& one, const RateJob* many, int n, int maxK, int ns, int* err, hipStream_t s);
 // Hybrid front end: every codebook beam's response G (K x nx ny), then the
 // beam choice and H_eff.
 void launch_beam_resp(const float2* H, int ldh, int K, int nx, int ny, float2* G, hipStream_t s);

@@ -17,6 +17,13 @@
 // finish (a completion count per item, zero between launches) adds them in a
 // fixed order; only the wave that wrote them fences before counting, since an
 // agent-scope fence writes back the XCD's L2.
+//
+// A single track with K <= 64 and N > 64 (no batch to fill the chip) splits
+// the antenna sum over ns workgroups, each taking whole chunks: they write
+// their partial 64 x 64 blocks of E and partial ||W||^2 to scratch, and the
+// last to finish adds the partials in split order before the steps above.
+// A batch launch keeps one workgroup per block, so a split track's rates
+// agree with its batched ones to FP32 rounding, not bit for bit.
 #include "rzf_device.h"
 #include "rzf_internal.h"
 
@@ -34,9 +41,10 @@ constexpr int SPER = SB * SC / SNT;   // values of each chunk a thread stages (4
 // interference), then the column blocks' ||W||^2 [cb].  The completion count
 // (one per item) is zero before the launch and is left at zero.
 __host__ __device__ constexpr int sr_blocks(int K) { return (K + SB - 1) / SB; }
+constexpr int SR_SPLIT_MAX = 8;
 
 template <bool MANY>
-__global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* many, int* err) {
+__global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* many, int ns, int* err) {
   __shared__ float2 hs[SB * SLD], ws[SC * WLD];
   __shared__ double rs[4][SB], rf[4][SB];
   __shared__ double red[SNW];
@@ -48,8 +56,12 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
   unsigned* const count = jb.count;
   double* __restrict__ part = jb.part;
   const int kb = sr_blocks(K);
-  if ((int)blockIdx.x >= kb * kb) return;
-  const int rb = blockIdx.x / kb, cb = blockIdx.x - rb * kb;
+  if ((int)blockIdx.x >= kb * kb * ns) return;
+  const int blk = blockIdx.x / ns, sp = blockIdx.x - blk * ns;   // ns > 1 only with kb == 1
+  const int rb = blk / kb, cb = blk - rb * kb;
+  // this workgroup's antennas: whole chunks [cbeg, cend)
+  const int cps = ((N + SC - 1) / SC + ns - 1) / ns;
+  const int cbeg = sp * cps * SC, cend = min(N, (sp + 1) * cps * SC);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int nt = wid >> 2, ct = wid & 3;          // this wave's tile in the block
   const int r0 = rb * SB, m0 = cb * SB;
@@ -67,8 +79,8 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
       pw[e] = (jw < N && m < K) ? W[(size_t)jw * ldw + m] : cz();
     }
   };
-  fetch(0);
-  for (int c0 = 0; c0 < N; c0 += SC) {
+  if (cbeg < cend) fetch(cbeg);
+  for (int c0 = cbeg; c0 < cend; c0 += SC) {
 #pragma unroll
     for (int e = 0; e < SPER; ++e) {
       const int idx = tid + SNT * e;
@@ -78,12 +90,47 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
       if (rb == 0) wn += (double)cabs2(pw[e]);
     }
     __syncthreads();
-    if (c0 + SC < N) fetch(c0 + SC);
-    const int jc = min(SC, N - c0);
+    if (c0 + SC < cend) fetch(c0 + SC);
+    const int jc = min(SC, cend - c0);
     // E(n, m) += sum_j H[n][j] W[j][m]
     ctile16([&](int rr, int j) { return hs[(nt * 16 + rr) * SLD + j]; },
             [&](int j, int cc) { return ws[j * WLD + ct * 16 + cc]; }, 0, (jc + 3) & ~3, dr, di);
     __syncthreads();
+  }
+  wn = wave_sum(wn);
+  if (lane == 0) red[wid] = wn;
+  double wt = 0.0;   // ||W||^2 of the block's columns (kb == 1: all of W)
+  if (ns > 1) {
+    // partial E and ||W||^2 to scratch; the last split adds them up
+    float2* const pe = reinterpret_cast<float2*>(part);   // [ns][SB * SB]
+    double* const pw = part + (size_t)ns * SB * SB;      // [ns]
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      pe[(size_t)sp * SB * SB + (nt * 16 + tile_row(v)) * SB + ct * 16 + tile_col()] = make_float2(dr[v], di[v]);
+    __syncthreads();
+    if (tid == 0) {
+      double w = 0.0;
+      for (int q = 0; q < SNW; ++q) w += red[q];
+      pw[sp] = w;
+      __threadfence();   // after the barrier: the workgroup's stores before the count
+      last = atomicAdd(count, 1u) == (unsigned)(ns - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const size_t o = (nt * 16 + tile_row(v)) * SB + ct * 16 + tile_col();
+      float er = 0.f, ei = 0.f;
+      for (int q = 0; q < ns; ++q) {
+        const float2 x = pe[(size_t)q * SB * SB + o];
+        er += x.x;
+        ei += x.y;
+      }
+      dr[v] = er;
+      di[v] = ei;
+    }
+    for (int q = 0; q < ns; ++q) wt += pw[q];
   }
   // the block's signal and interference shares of each row, over its columns
 #pragma unroll
@@ -98,15 +145,13 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
       rf[ct][i] = f;
     }
   }
-  wn = wave_sum(wn);
-  if (lane == 0) red[wid] = wn;
   __syncthreads();
   double acc = 0.0;
   if (kb == 1) {
     // one workgroup owns the track: the rates straight from its shares
     if (tid < K) {
-      double wt = 0.0;
-      for (int q = 0; q < SNW; ++q) wt += red[q];
+      if (ns == 1)
+        for (int q = 0; q < SNW; ++q) wt += red[q];
       const double s2 = (wt > 0.0) ? jb.P / wt : 0.0;   // |scale|^2
       const double sig = ((rs[0][tid] + rs[1][tid]) + rs[2][tid]) + rs[3][tid];
       const double intf = ((rf[0][tid] + rf[1][tid]) + rf[2][tid]) + rf[3][tid];
@@ -137,7 +182,6 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
     if (!last) return;
     // the track's last block: every share is visible
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    double wt = 0.0;
     for (int c = 0; c < kb; ++c) wt += wnorm[c];
     const double s2 = (wt > 0.0) ? jb.P / wt : 0.0;
     for (int n = tid; n < K; n += SNT) {
@@ -160,7 +204,7 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
     double tot = 0.0;
     for (int q = 0; q < SNW; ++q) tot += red[q];
     if (jb.sum) *jb.sum = tot;
-    if (kb > 1) *count = 0u;
+    if (kb > 1 || ns > 1) *count = 0u;
   }
 }
 
@@ -171,8 +215,15 @@ size_t sum_rate_scratch_doubles(int K) {
   return (size_t)2 * K * kb + kb;
 }
 
-void launch_sum_rate(const RateJob& one, const RateJob* many, int n, int maxK, int* err, hipStream_t s) {
+size_t sum_rate_split_scratch_doubles() { return (size_t)SR_SPLIT_MAX * SB * SB + SR_SPLIT_MAX; }
+
+int sum_rate_splits(int K, int N) {
+  if (sr_blocks(K) > 1) return 1;
+  return std::max(1, std::min(SR_SPLIT_MAX, (N + SC - 1) / SC));
+}
+
+void launch_sum_rate(const RateJob& one, const RateJob* many, int n, int maxK, int ns, int* err, hipStream_t s) {
   const int kb = sr_blocks(maxK);
-  if (many) k_sum_rate<true><<<dim3(kb * kb, n), SNT, 0, s>>>(one, many, err);
-  else k_sum_rate<false><<<kb * kb, SNT, 0, s>>>(one, many, err);
+  if (many) k_sum_rate<true><<<dim3(kb * kb, n), SNT, 0, s>>>(one, many, 1, err);
+  else k_sum_rate<false><<<kb * kb * ns, SNT, 0, s>>>(one, many, ns, err);
 }

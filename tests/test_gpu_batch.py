@@ -92,6 +92,20 @@ def test_batch_matches_oracle(ctx):
         tr.destroy()
 
 
+def _rates_agree(KN, r_single, r_batch, sum_single, sum_batch):
+    # a lone track with K <= 64 and N > 64 splits its antenna sum over
+    # workgroups (the batch keeps one per track): E then differs by FP32
+    # rounding of a different summation order, a few 2^-24 of |E|, and each
+    # rate by about that much; otherwise the arithmetic is the same
+    K, N = KN
+    if K <= 64 and N > 64:
+        assert torch.allclose(r_single, r_batch, rtol=1e-5, atol=1e-6), KN
+        assert abs(sum_single - sum_batch) <= 1e-5 * max(1.0, abs(sum_batch)), KN
+    else:
+        assert torch.equal(r_single, r_batch), KN
+        assert sum_batch == sum_single, KN
+
+
 def test_full_and_sum_rate_batch_equal_single(ctx):
     Hs = [walk(K, N, 0, 70 + i)[0] for i, (K, N) in enumerate(SIZES)]
     dev = [torch.from_numpy(H).cuda() for H in Hs]
@@ -113,16 +127,14 @@ def test_full_and_sum_rate_batch_equal_single(ctx):
     ctx.sum_rate_batch(dev, Wb, 1.5, 0.1, rates_b, sums_b)
     ctx.sync()
     for i in range(len(Hs)):
-        assert torch.equal(rates_s[i], rates_b[i])
-        assert sums_b[i].item() == sums_s[i]
+        _rates_agree(SIZES[i], rates_s[i], rates_b[i], sums_s[i], sums_b[i].item())
     # per-item noise powers: each item as if evaluated alone with its own
     s2 = [0.02 * (i + 1) for i in range(len(Hs))]
     sums_i = [ctx.sum_rate(d, w, 1.5, v, r) for d, w, r, v in zip(dev, Ws, rates_s, s2)]
     ctx.sum_rate_batch(dev, Wb, 1.5, 0.1, rates_b, sums_b, sigma2s=s2)
     ctx.sync()
     for i in range(len(Hs)):
-        assert torch.equal(rates_s[i], rates_b[i])
-        assert sums_b[i].item() == sums_i[i]
+        _rates_agree(SIZES[i], rates_s[i], rates_b[i], sums_i[i], sums_b[i].item())
 
 
 def test_batch_rejects_bad_items(ctx):
