@@ -233,17 +233,57 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0, lat, Rs
 
+    def run_graph(H, steps, kind, track_id=0, per_step_sync=False):
+        """The same step captured once (rzf_graph_update / rzf_graph_full,
+        the sum rate inside the graph): each step copies H_t into the graph's
+        input buffer and launches the graph."""
+        Hb = torch.empty_like(H[0])
+        Wb = torch.empty_like(W)
+        sums = torch.zeros(1, dtype=torch.float64, device=dev)
+        Hb.copy_(H[0])
+        tr = None
+        if kind == "wb":
+            tr = ctx.init(H[0], cfg.alpha, params(track_id))
+            g = ctx.graph_update([tr], [Hb], [Wb], eta, rate=(cfg.P, cfg.sigma2, sums))
+        else:
+            g = ctx.graph_full([Hb], [cfg.alpha], cfg.P, [Wb], PRECISIONS[a.precision],
+                               rate=(cfg.P, cfg.sigma2, sums))
+        lat, Rs = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(1, steps + 1):
+            ts = time.perf_counter()
+            Hb.copy_(H[t])        # on the context's stream (torch's current one)
+            g.launch()
+            if per_step_sync:
+                Rs.append(sums.item())
+                lat.append(time.perf_counter() - ts)
+        ctx.sync()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g.destroy()
+        if tr is not None:
+            tr.destroy()
+        return el, lat, Rs
+
     # warm-up on a separate track of the same configuration
     run_wb(Hw, W_steps, 1)
     run_full(Hw, W_steps)
+    run_graph(Hw, W_steps, "wb", 1)
+    run_graph(Hw, W_steps, "full")
     print(f"[bench] warmup done ({W_steps} steps)", file=sys.stderr, flush=True)
 
     # timed region: exactly K steps of the WB-arSVD path (update + sum rate)
+    # through the eager calls (the headline: with steps queued back to back
+    # the GPU is the bound), then the same steps as captured-graph launches
     torch.cuda.synchronize()
     wb_s, _, _, _ = run_wb(Hs, K_steps, 0)
     print(f"[bench] wb timed: {wb_s:.3f}s", file=sys.stderr, flush=True)
     full_s, _, _ = run_full(Hs, K_steps)
     print(f"[bench] full timed: {full_s:.3f}s", file=sys.stderr, flush=True)
+    wb_g, _, _ = run_graph(Hs, K_steps, "wb")
+    full_g, _, _ = run_graph(Hs, K_steps, "full")
+    print(f"[bench] graph: wb {wb_g:.3f}s full {full_g:.3f}s", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC if a.config == "c2" else metric_for(cfg),
@@ -272,17 +312,27 @@ def main():
         "full_inverse": {"value": K_steps / full_s, "unit": "updates/s",
                          "ms_per_step": 1e3 * full_s / K_steps},
         "speedup_vs_full_inverse": full_s / wb_s,
+        "graph": {"wb": {"value": K_steps / wb_g, "ms_per_step": 1e3 * wb_g / K_steps},
+                  "full": {"value": K_steps / full_g, "ms_per_step": 1e3 * full_g / K_steps},
+                  "note": "the same steps as one captured-graph launch each (rzf_graph_update / "
+                          "rzf_graph_full with the sum rate inside), H_t first copied into the graph's "
+                          "input buffer"},
     }
 
     # per-step latency (submit -> sum rate on the host) and path statistics
     if not a.no_latency:
         _, infos, lat_wb, R_wb = run_wb(Hs, K_steps, 0, want_info=True, per_step_sync=True)
         _, lat_full, R_full = run_full(Hs, K_steps, per_step_sync=True)
-        lw, lf = np.array(lat_wb) * 1e3, np.array(lat_full) * 1e3
-        out["latency_ms"] = {"wb_p50": float(np.percentile(lw, 50)), "wb_p99": float(np.percentile(lw, 99)),
-                             "full_p50": float(np.percentile(lf, 50)),
-                             "full_p99": float(np.percentile(lf, 99)),
-                             "note": "per step, host submit to sum rate on the host, one step in flight"}
+        _, lat_wbg, R_wbg = run_graph(Hs, K_steps, "wb", per_step_sync=True)
+        _, lat_fullg, _ = run_graph(Hs, K_steps, "full", per_step_sync=True)
+        pct = lambda v, q: float(np.percentile(np.array(v) * 1e3, q))
+        out["latency_ms"] = {"wb_p50": pct(lat_wbg, 50), "wb_p99": pct(lat_wbg, 99),
+                             "full_p50": pct(lat_fullg, 50), "full_p99": pct(lat_fullg, 99),
+                             "eager_wb_p50": pct(lat_wb, 50), "eager_wb_p99": pct(lat_wb, 99),
+                             "eager_full_p50": pct(lat_full, 50), "eager_full_p99": pct(lat_full, 99),
+                             "note": "per step, host submit to sum rate on the host, one step in flight; "
+                                     "wb/full: captured graph (input copy included), eager_*: the calls"}
+        out["graph_sum_rate_equal"] = bool(np.array_equal(np.array(R_wbg), np.array(R_wb)))
         paths = {}
         for i in infos:
             paths[str(i["path"])] = paths.get(str(i["path"]), 0) + 1
@@ -469,7 +519,7 @@ def batched(a, cfgs, eta, policy):
     Wl = [torch.empty(c.N, c.K, dtype=torch.complex64, device=dev) for c in cfgs]
     rl = [torch.empty(c.K, dtype=torch.float32, device=dev) for c in cfgs]
     sums = torch.empty(B, dtype=torch.float64, device=dev)
-    arena = sum(rzf.track_bytes(c.K, c.N) for c in cfgs) + (128 << 20)
+    arena = 2 * sum(rzf.track_bytes(c.K, c.N) for c in cfgs) + (256 << 20)   # eager and captured track sets
     ctx = rzf.Context(0, arena)
     trs = [ctx.init(Hs[b][0], c.alpha,
                     rzf.default_params(k_init=c.k_init, p=c.p, P=c.P, seed=c.seed, track_id=b,
@@ -500,13 +550,58 @@ def batched(a, cfgs, eta, policy):
 
     run("wb", 1, 1 + Wu)
     run("full", 1, 1 + Wu)
-    wb_s = run("wb", 1 + Wu, 1 + Wu + S)
-    full_s = run("full", 1 + Wu, 1 + Wu + S)
+    wb_e = run("wb", 1 + Wu, 1 + Wu + S)
+    full_e = run("full", 1 + Wu, 1 + Wu + S)
+
+    # the same steps captured (rzf_graph_update / rzf_graph_full over one
+    # packed input buffer, the batched sum rate inside the graph): each step
+    # copies the packed snapshots of all tracks and launches the graph
+    sizes = [c.K * c.N for c in cfgs]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(int)
+    Hpack = [torch.cat([Hs[b][t].reshape(-1) for b in range(B)]) for t in range(T)]
+    Hbuf = torch.empty_like(Hpack[0])
+    Hv = [Hbuf[offs[b]:offs[b + 1]].view(c.K, c.N) for b, c in enumerate(cfgs)]
+    Wg = [torch.empty_like(w) for w in Wl]
+    sums_g = torch.empty(B, dtype=torch.float64, device=dev)
+    trs_g = [ctx.init(Hs[b][0], c.alpha,
+                      rzf.default_params(k_init=c.k_init, p=c.p, P=c.P, seed=c.seed, track_id=b,
+                                         reset_period=c.reset_period, kinit_policy=policy,
+                                         early_fallback=int(a.early_fallback),
+                                         precision=PRECISIONS[a.precision],
+                                         error_feedback=int(a.error_feedback)))
+             for b, c in enumerate(cfgs)]
+    torch.cuda.synchronize()
+    g_wb = ctx.graph_update(trs_g, Hv, Wg, eta, rate=(P, s2[0], sums_g))
+    g_full = ctx.graph_full(Hv, [c.alpha for c in cfgs], P, Wg, PRECISIONS[a.precision], rate=(P, s2[0], sums_g))
+
+    def run_graph(g, t0, t1):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for t in range(t0, t1):
+            Hbuf.copy_(Hpack[t])
+            g.launch()
+        ctx.sync()
+        torch.cuda.synchronize()
+        return time.perf_counter() - s0
+
+    run_graph(g_wb, 1, 1 + Wu)
+    run_graph(g_full, 1, 1 + Wu)
+    wb_s = run_graph(g_wb, 1 + Wu, 1 + Wu + S)
+    full_s = run_graph(g_full, 1 + Wu, 1 + Wu + S)
+    g_wb.destroy()
+    g_full.destroy()
+    for tr in trs_g:
+        tr.destroy()
+    del Hpack
     res = {"tracks": B, "steps": S, "value": B * S / wb_s, "unit": "updates/s",
            "ms_per_batched_step": 1e3 * wb_s / S,
            "full_inverse": {"value": B * S / full_s, "unit": "updates/s",
                             "ms_per_batched_step": 1e3 * full_s / S},
-           "speedup_vs_full_inverse": full_s / wb_s}
+           "speedup_vs_full_inverse": full_s / wb_s,
+           "eager": {"value": B * S / wb_e, "ms_per_batched_step": 1e3 * wb_e / S,
+                     "full_value": B * S / full_e, "full_ms_per_batched_step": 1e3 * full_e / S},
+           "note": "value: one captured-graph launch per batched step (packed snapshots copied into its "
+                   "input buffer first); eager: rzf_update_batch / rzf_full_batch and rzf_sum_rate_batch"}
     # dominant kernel of the batched WB pass: HIP events over the next (fresh)
     # snapshot of every track, with each track's info record for its work
     ctx.profile(True)

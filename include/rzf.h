@@ -278,6 +278,51 @@ typedef struct {
 rzf_status rzf_sum_rate_batch(rzf_ctx* ctx, int n, const rzf_rate_item* items, double P,
                               double sigma2);
 
+/* ------------------------------------------------ captured steps (HIP graphs)
+ * One step of rzf_update / rzf_update_batch (or of rzf_full / rzf_full_batch),
+ * optionally followed by the sum rate of eq. (15) (Sec. VI) of every item,
+ * captured once into HIP graphs over fixed buffers and then run by one call
+ * per step.  A replay launches the same kernels with the same arguments as
+ * the eager call, so its results are bit-identical to it; the branches of
+ * Alg. 2 (Woodbury, direct inversion, skip) stay decisions of the kernels.
+ * The host keeps only the FP64 re-inversion schedule (Sec. IV): an update
+ * graph holds a Woodbury-step graph and, when the tracks have a reset
+ * period, a re-inversion graph, and rzf_graph_launch picks one per step.
+ *
+ * The items' H and W pointers (and rates / sums) are fixed for the graph's
+ * life: the caller writes each step's snapshots into the same H buffers,
+ * ordered before rzf_graph_launch on the context's stream (or synchronised),
+ * and reads W after it.  A graph keeps its job arrays and scratch in the
+ * context's arena (RZF_E_NOMEM if it cannot hold them).
+ *
+ * Update graphs: 1 <= n <= RZF_BATCH_MAX tracks of the context, each at most
+ * once; n == 1 captures rzf_update (two-phase arSVD for K <= 64), n > 1
+ * rzf_update_batch.  Every track must have the same reset period and the
+ * same steps since its last re-inversion (RZF_E_INVALID otherwise, also at a
+ * launch after a track was updated outside the graph and fell out of step).
+ * A track cannot be destroyed while a graph updates it (RZF_E_INVALID).
+ * Per-step info records are not copied out: rzf_track_query and the other
+ * track queries read the state after a step.
+ *
+ * rate: NULL, or the sum rate of each item after its precoder with power P
+ * and noise sigma2 into sums[i] (device, n doubles): the arithmetic of
+ * rzf_sum_rate for n == 1, of rzf_sum_rate_batch for n > 1. */
+typedef struct rzf_graph rzf_graph;
+typedef struct {
+  double P, sigma2;
+  double* sums;            /* device, n doubles */
+} rzf_graph_rate;
+
+rzf_status rzf_graph_update(rzf_ctx* ctx, int n, const rzf_update_item* items, double tol,
+                            const rzf_graph_rate* rate, rzf_graph** out);
+rzf_status rzf_graph_full(rzf_ctx* ctx, int n, const rzf_full_item* items, const rzf_graph_rate* rate,
+                          rzf_graph** out);
+/* One step: asynchronous on the context's stream, no allocation; device
+ * errors are reported by the next rzf_sync as for the eager calls. */
+rzf_status rzf_graph_launch(rzf_graph* g);
+/* Waits for the context's stream, frees the graph and its arena memory. */
+rzf_status rzf_graph_destroy(rzf_graph* g);
+
 /* Hybrid front end of eq. (4): H_eff = H~ F_RF with F_RF made of n_rf beams
  * of the DFT codebook of an nx x ny UPA (N = nx ny, element index m_y nx + m_x;
  * beam b = q nx + p has entries exp(+j 2 pi (p m_x / nx + q m_y / ny)) / sqrt(N),

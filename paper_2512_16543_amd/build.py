@@ -24,7 +24,7 @@ LIB = os.path.join(PKG, "librzf.so")
 ARCH = "gfx950"
 
 SOURCES = ["gram.hip", "precoder.hip", "dense.hip", "arsvd.hip", "arsvd_big.hip", "sumrate.hip", "beams.hip",
-           "noalloc.hip", "api.cpp", "server.cpp"]
+           "noalloc.hip", "api.cpp", "server.cpp", "graph.cpp"]
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

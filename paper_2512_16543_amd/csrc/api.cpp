@@ -123,7 +123,7 @@ hipEvent_t ev_get(rzf_ctx* c) {
 // Run `launch` between an event pair when timing is on.
 template <class F>
 void timed(rzf_ctx* c, int kernel, hipStream_t s, F launch) {
-  if (!c->prof_on) { launch(); return; }
+  if (!c->prof_on || c->capturing) { launch(); return; }
   hipEvent_t a = ev_get(c), b = ev_get(c);
   if (!a || !b) { launch(); return; }
   (void)hipEventRecord(a, s);
@@ -154,8 +154,10 @@ rzf_status dev_status(int code) {
 
 #define HIP_OK(x) do { if ((x) != hipSuccess) return RZF_E_DEVICE; } while (0)
 
-// Two-phase arSVD launches in this process (their tags in the speculation area).
-std::atomic<unsigned long long> g_spec_seq{0};
+// Tracks created in this process: a track's two-phase tag numbers start at its
+// number times 2^32 (unique across the process, so that no tag left in reused
+// device memory by another track or an earlier context can match).
+std::atomic<unsigned long long> g_track_uid{0};
 
 // Kernel families by track size: K <= KS keeps the working set in LDS, larger
 // tracks use the blocked kernels on a global workspace.
@@ -174,9 +176,6 @@ void arsvd_single(rzf_ctx* c, ArsvdJob j, int K, hipStream_t s) {
   } else {
     j.spec = c->d_spec;
     j.stage = reinterpret_cast<char*>(c->d_spec) + SPEC_STAGE_OFF;
-    // numbered across the process, so that no tag left in reused device
-    // memory by an earlier context can match
-    j.seq = ++g_spec_seq;
     launch_arsvd_wb_spec(j, c->d_err, s);
   }
 }
@@ -298,6 +297,8 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
     d.Aug = reinterpret_cast<double2*>(base + L.aug);
   }
   d.last_r = 0;
+  d.t_dev = 0;
+  d.seq_dev = (++g_track_uid) << 32;
   t->d_desc = reinterpret_cast<TrackDesc*>(base + L.desc);
   return t;
 }
@@ -433,6 +434,7 @@ rzf_status rzf_ctx_destroy(rzf_ctx* c) {
   if (!c) return RZF_E_INVALID;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  graphs_release_all(c);
   for (rzf_track* t : c->tracks) delete t;
   c->tracks.clear();
   prof_drain(c);
@@ -507,29 +509,14 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
   const int K = t->K, N = t->N;
   const float2* Hf = reinterpret_cast<const float2*>(H_t);
   float2* Wf = reinterpret_cast<float2*>(W);
-  const TrackDesc& d = t->h_desc;
   DevInfo* slot = nullptr;
   if (info) {
     slot = pin_slot(c);
     if (!slot) return RZF_E_DEVICE;
   }
   const int step = t->t + 1;
-  const bool reset = t->prm.reset_period > 0 && t->since_reset + 1 >= t->prm.reset_period;
-  if (reset) {
-    const Gram64Job gj{Hf, d.A64, K, N, ldh, t->alpha};
-    const Inv64Job ij{d.A64, d.Ainv, &t->d_desc->info, nullptr, K, d.Rfb, &t->d_desc->hold};
-    timed(c, KN_GRAM64, s, [&] { launch_gram64(gj, nullptr, 1, K, s); });
-    timed(c, KN_INV64, s, [&] { inv64_any(ij, c->d_err, s); });
-  } else {
-    const GramJob gj{Hf, d.Hprev, d.Anew, d.dA, K, N, ldh, N, (float)t->alpha, d.prec};
-    const ArsvdJob aj{t->d_desc, nullptr, tol, step, t->i_max};
-    timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, s); });
-    timed(c, KN_ARSVD, s, [&] { arsvd_single(c, aj, K, s); });
-  }
-  const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw, d.prec, &t->d_desc->hold};
-  const ScaleJob sj{Wf, d.wpart, d.P, K, N, ldw, precoder_blocks(N)};
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, s); });
-  timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
+  const bool reset = reset_due(t);
+  update_single_launch(c, t, Hf, ldh, tol, Wf, ldw, reset, s);
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (slot) {
     HIP_OK(hipMemcpyAsync(slot, &t->d_desc->info, sizeof(DevInfo), hipMemcpyDeviceToHost, s));
@@ -555,21 +542,6 @@ int stage_acquire(rzf_ctx* c) {
   return k;
 }
 
-struct Stager {
-  char* h;
-  char* d;
-  size_t used = 0;
-  template <class T>
-  T* put(const T* src, int n, T** dev) {
-    used = (used + 15) & ~size_t(15);
-    T* hp = reinterpret_cast<T*>(h + used);
-    *dev = reinterpret_cast<T*>(d + used);
-    std::memcpy(hp, src, sizeof(T) * n);
-    used += sizeof(T) * n;
-    return hp;
-  }
-};
-
 }  // namespace
 
 namespace rzfrt {
@@ -587,58 +559,54 @@ rzf_status check_update_items(rzf_ctx* c, int n, const rzf_update_item* items, d
   return RZF_OK;
 }
 
-rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, double tol,
-                               DevInfo* const* slots, hipStream_t s, int* err) {
-  std::vector<GramJob> gj;
-  std::vector<ArsvdJob> aj, ajb;     // LDS kernels (K <= KS) / large tracks
-  std::vector<Gram64Job> g64;
-  std::vector<Inv64Job> i64, i64b;
-  std::vector<PrecJob> pj;
-  std::vector<ScaleJob> sj;
-  std::vector<int> reset_flag(n);
-  int maxK = 1, maxN = 1, maxKr = 1, maxNK = 1;
+void plan_update(UpdatePlan& P, int n, const rzf_update_item* items, double tol, int force_reset) {
+  P = UpdatePlan{};
+  P.reset_flag.resize(n);
   for (int i = 0; i < n; ++i) {
     rzf_track* t = items[i].track;
     const TrackDesc& d = t->h_desc;
     const int K = t->K, N = t->N;
     const float2* Hf = reinterpret_cast<const float2*>(items[i].H);
     float2* Wf = reinterpret_cast<float2*>(items[i].W);
-    const bool reset = t->prm.reset_period > 0 && t->since_reset + 1 >= t->prm.reset_period;
-    reset_flag[i] = reset;
+    const bool reset = force_reset < 0 ? reset_due(t) : force_reset != 0;
+    P.reset_flag[i] = reset;
     if (reset) {
-      g64.push_back(Gram64Job{Hf, d.A64, K, N, items[i].ldh, t->alpha});
-      (K > KS ? i64b : i64).push_back(Inv64Job{d.A64, d.Ainv, &t->d_desc->info, nullptr, K, d.Rfb,
-                                               &t->d_desc->hold});
-      maxKr = std::max(maxKr, K);
+      P.g64.push_back(Gram64Job{Hf, d.A64, K, N, items[i].ldh, t->alpha});
+      (K > KS ? P.i64b : P.i64).push_back(Inv64Job{d.A64, d.Ainv, &t->d_desc->info, nullptr, K, d.Rfb,
+                                                   &t->d_desc->hold});
+      P.maxKr = std::max(P.maxKr, K);
     } else {
-      gj.push_back(GramJob{Hf, d.Hprev, d.Anew, d.dA, K, N, items[i].ldh, N, (float)t->alpha, d.prec});
-      (K > KS ? ajb : aj).push_back(ArsvdJob{t->d_desc, nullptr, tol, t->t + 1, t->i_max});
+      P.gj.push_back(GramJob{Hf, d.Hprev, d.Anew, d.dA, K, N, items[i].ldh, N, (float)t->alpha, d.prec});
+      (K > KS ? P.ajb : P.aj).push_back(ArsvdJob{t->d_desc, nullptr, tol, t->i_max});
     }
-    pj.push_back(PrecJob{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, items[i].ldh, items[i].ldw, d.prec,
-                         &t->d_desc->hold});
-    sj.push_back(ScaleJob{Wf, d.wpart, d.P, K, N, items[i].ldw, precoder_blocks(N)});
-    maxNK = std::max(maxNK, N * K);
-    maxK = std::max(maxK, K);
-    maxN = std::max(maxN, N);
+    P.pj.push_back(PrecJob{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, items[i].ldh, items[i].ldw, d.prec,
+                           &t->d_desc->hold});
+    P.sj.push_back(ScaleJob{Wf, d.wpart, d.P, K, N, items[i].ldw, precoder_blocks(N), t->d_desc});
+    P.maxNK = std::max(P.maxNK, N * K);
+    P.maxK = std::max(P.maxK, K);
+    P.maxN = std::max(P.maxN, N);
   }
-  const size_t need = sizeof(GramJob) * gj.size() + sizeof(ArsvdJob) * (aj.size() + ajb.size()) +
-                      sizeof(Gram64Job) * g64.size() + sizeof(Inv64Job) * (i64.size() + i64b.size()) +
-                      sizeof(PrecJob) * pj.size() + sizeof(ScaleJob) * sj.size() + 16 * 8;
-  if (need > STAGE_BYTES) return RZF_E_INVALID;
-  const int slot = stage_acquire(c);
-  if (slot < 0) return RZF_E_DEVICE;
-  Stager st{c->h_stage + slot * STAGE_BYTES, c->d_stage + slot * STAGE_BYTES};
-  GramJob* d_gj = nullptr; ArsvdJob* d_aj = nullptr; ArsvdJob* d_ajb = nullptr; Gram64Job* d_g64 = nullptr;
-  Inv64Job* d_i64 = nullptr; Inv64Job* d_i64b = nullptr; PrecJob* d_pj = nullptr; ScaleJob* d_sj = nullptr;
+}
+
+size_t UpdatePlan::bytes() const {
+  return sizeof(GramJob) * gj.size() + sizeof(ArsvdJob) * (aj.size() + ajb.size()) +
+         sizeof(Gram64Job) * g64.size() + sizeof(Inv64Job) * (i64.size() + i64b.size()) +
+         sizeof(PrecJob) * pj.size() + sizeof(ScaleJob) * sj.size() + 16 * 8;
+}
+
+void UpdatePlan::put(Stager& st) {
   if (!gj.empty()) st.put(gj.data(), (int)gj.size(), &d_gj);
   if (!aj.empty()) st.put(aj.data(), (int)aj.size(), &d_aj);
   if (!ajb.empty()) st.put(ajb.data(), (int)ajb.size(), &d_ajb);
   if (!g64.empty()) st.put(g64.data(), (int)g64.size(), &d_g64);
   if (!i64.empty()) st.put(i64.data(), (int)i64.size(), &d_i64);
   if (!i64b.empty()) st.put(i64b.data(), (int)i64b.size(), &d_i64b);
-  st.put(pj.data(), n, &d_pj);
-  st.put(sj.data(), n, &d_sj);
-  HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
+  st.put(pj.data(), (int)pj.size(), &d_pj);
+  st.put(sj.data(), (int)sj.size(), &d_sj);
+}
+
+void UpdatePlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
+  const int n = (int)pj.size();
   if (!gj.empty()) {
     timed(c, KN_GRAM, s, [&] { launch_gram(gj[0], d_gj, (int)gj.size(), maxK, s); });
     timed(c, KN_ARSVD, s, [&] {
@@ -655,16 +623,37 @@ rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, 
   }
   timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
-  HIP_OK(hipEventRecord(c->stage_ev[slot], s));
-  c->stage_used[slot] = true;
-  if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
+}
+
+void advance_tracks(int n, rzf_track* const* tracks, const std::vector<int>& reset_flag) {
   for (int i = 0; i < n; ++i) {
-    rzf_track* t = items[i].track;
-    if (slots[i])
-      HIP_OK(hipMemcpyAsync(slots[i], &t->d_desc->info, sizeof(DevInfo), hipMemcpyDeviceToHost, s));
+    rzf_track* t = tracks[i];
     t->t += 1;
     t->since_reset = reset_flag[i] ? 0 : t->since_reset + 1;
   }
+}
+
+rzf_status update_batch_locked(rzf_ctx* c, int n, const rzf_update_item* items, double tol,
+                               DevInfo* const* slots, hipStream_t s, int* err) {
+  UpdatePlan P;
+  plan_update(P, n, items, tol, -1);
+  if (P.bytes() > STAGE_BYTES) return RZF_E_INVALID;
+  const int slot = stage_acquire(c);
+  if (slot < 0) return RZF_E_DEVICE;
+  Stager st{c->h_stage + slot * STAGE_BYTES, c->d_stage + slot * STAGE_BYTES};
+  P.put(st);
+  HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
+  P.launch(c, s, err);
+  HIP_OK(hipEventRecord(c->stage_ev[slot], s));
+  c->stage_used[slot] = true;
+  if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
+  std::vector<rzf_track*> tr(n);
+  for (int i = 0; i < n; ++i) {
+    tr[i] = items[i].track;
+    if (slots[i])
+      HIP_OK(hipMemcpyAsync(slots[i], &tr[i]->d_desc->info, sizeof(DevInfo), hipMemcpyDeviceToHost, s));
+  }
+  advance_tracks(n, tr.data(), P.reset_flag);
   return RZF_OK;
 }
 
@@ -683,60 +672,51 @@ rzf_status check_full_items(int n, const rzf_full_item* items) {
   return RZF_OK;
 }
 
-rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items, const FullScratch* scr,
-                             hipStream_t s, int* err) {
-  int maxK = 1, maxN = 1, maxNK = 1;
-  size_t need = 0;
+size_t full_scratch_bytes(const rzf_full_item& it) {
+  return align_up(sizeof(float2) * it.K * it.K) + align_up(sizeof(double) * precoder_scratch(it.N));
+}
+
+FullScratch full_scratch_at(const rzf_full_item& it, char* p) {
+  return FullScratch{reinterpret_cast<float2*>(p),
+                     reinterpret_cast<double*>(p + align_up(sizeof(float2) * it.K * it.K))};
+}
+
+void plan_full(FullPlan& P, int n, const rzf_full_item* items, const FullScratch* scr) {
+  P = FullPlan{};
+  P.gj.resize(n);
+  P.pj.resize(n);
+  P.sj.resize(n);
   for (int i = 0; i < n; ++i) {
     const rzf_full_item& it = items[i];
-    maxK = std::max(maxK, it.K);
-    maxN = std::max(maxN, it.N);
-    maxNK = std::max(maxNK, it.N * it.K);
-    need += align_up(sizeof(float2) * it.K * it.K) + align_up(sizeof(double) * precoder_scratch(it.N));
-  }
-  if (!scr && need > c->batch_full_bytes) {
-    // grow: the old region may still be read by queued work
-    HIP_OK(hipStreamSynchronize(c->stream));
-    if (c->d_batch_full) arena_free(c, c->batch_full_off, c->batch_full_bytes);
-    c->d_batch_full = nullptr;
-    c->batch_full_bytes = 0;
-    size_t off = 0;
-    if (!arena_alloc(c, need, &off)) return RZF_E_NOMEM;
-    c->batch_full_off = off;
-    c->batch_full_bytes = need;
-    c->d_batch_full = c->arena + off;
-  }
-  std::vector<GramJob> gj(n);
-  std::vector<Inv32Job> vj, vjb;   // LDS kernel (K <= KS) / large
-  vj.reserve(n);
-  std::vector<PrecJob> pj(n);
-  std::vector<ScaleJob> sj(n);
-  char* p = c->d_batch_full;
-  for (int i = 0; i < n; ++i) {
-    const rzf_full_item& it = items[i];
-    float2* A = scr ? scr[i].A : reinterpret_cast<float2*>(p);
-    double* wp = scr ? scr[i].wpart : reinterpret_cast<double*>(p + align_up(sizeof(float2) * it.K * it.K));
-    if (!scr) p += align_up(sizeof(float2) * it.K * it.K) + align_up(sizeof(double) * precoder_scratch(it.N));
+    float2* A = scr[i].A;
+    double* wp = scr[i].wpart;
     const float2* Hf = reinterpret_cast<const float2*>(it.H);
     float2* Wf = reinterpret_cast<float2*>(it.W);
-    gj[i] = GramJob{Hf, nullptr, A, nullptr, it.K, it.N, it.ldh, 0, (float)it.alpha, it.precision};
-    (it.K > KS ? vjb : vj).push_back(Inv32Job{A, A, it.K});
-    pj[i] = PrecJob{Hf, A, Wf, wp, nullptr, it.K, it.N, it.ldh, it.ldw, it.precision, nullptr};
-    sj[i] = ScaleJob{Wf, wp, it.P, it.K, it.N, it.ldw, precoder_blocks(it.N)};
+    P.gj[i] = GramJob{Hf, nullptr, A, nullptr, it.K, it.N, it.ldh, 0, (float)it.alpha, it.precision};
+    (it.K > KS ? P.vjb : P.vj).push_back(Inv32Job{A, A, it.K});
+    P.pj[i] = PrecJob{Hf, A, Wf, wp, nullptr, it.K, it.N, it.ldh, it.ldw, it.precision, nullptr};
+    P.sj[i] = ScaleJob{Wf, wp, it.P, it.K, it.N, it.ldw, precoder_blocks(it.N), nullptr};
+    P.maxK = std::max(P.maxK, it.K);
+    P.maxN = std::max(P.maxN, it.N);
+    P.maxNK = std::max(P.maxNK, it.N * it.K);
   }
-  const size_t bytes = (sizeof(GramJob) + sizeof(Inv32Job) + sizeof(PrecJob) + sizeof(ScaleJob)) * n + 64;
-  if (bytes > STAGE_BYTES) return RZF_E_INVALID;
-  const int slot = stage_acquire(c);
-  if (slot < 0) return RZF_E_DEVICE;
-  Stager st{c->h_stage + slot * STAGE_BYTES, c->d_stage + slot * STAGE_BYTES};
-  GramJob* d_gj = nullptr; Inv32Job* d_vj = nullptr; Inv32Job* d_vjb = nullptr;
-  PrecJob* d_pj = nullptr; ScaleJob* d_sj = nullptr;
+}
+
+size_t FullPlan::bytes() const {
+  return (sizeof(GramJob) + sizeof(Inv32Job) + sizeof(PrecJob) + sizeof(ScaleJob)) * gj.size() + 64;
+}
+
+void FullPlan::put(Stager& st) {
+  const int n = (int)gj.size();
   st.put(gj.data(), n, &d_gj);
   if (!vj.empty()) st.put(vj.data(), (int)vj.size(), &d_vj);
   if (!vjb.empty()) st.put(vjb.data(), (int)vjb.size(), &d_vjb);
   st.put(pj.data(), n, &d_pj);
   st.put(sj.data(), n, &d_sj);
-  HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
+}
+
+void FullPlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
+  const int n = (int)gj.size();
   timed(c, KN_GRAM, s, [&] { launch_gram(gj[0], d_gj, n, maxK, s); });
   timed(c, KN_INV32, s, [&] {
     if (!vj.empty()) launch_inv32(vj[0], d_vj, (int)vj.size(), err, s);
@@ -744,9 +724,116 @@ rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items, cons
   });
   timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
+}
+
+rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items, const FullScratch* scr,
+                             hipStream_t s, int* err) {
+  std::vector<FullScratch> own;
+  if (!scr) {
+    size_t need = 0;
+    for (int i = 0; i < n; ++i) need += full_scratch_bytes(items[i]);
+    if (need > c->batch_full_bytes) {
+      // grow: the old region may still be read by queued work
+      HIP_OK(hipStreamSynchronize(c->stream));
+      if (c->d_batch_full) arena_free(c, c->batch_full_off, c->batch_full_bytes);
+      c->d_batch_full = nullptr;
+      c->batch_full_bytes = 0;
+      size_t off = 0;
+      if (!arena_alloc(c, need, &off)) return RZF_E_NOMEM;
+      c->batch_full_off = off;
+      c->batch_full_bytes = need;
+      c->d_batch_full = c->arena + off;
+    }
+    own.resize(n);
+    char* p = c->d_batch_full;
+    for (int i = 0; i < n; ++i) {
+      own[i] = full_scratch_at(items[i], p);
+      p += full_scratch_bytes(items[i]);
+    }
+    scr = own.data();
+  }
+  FullPlan P;
+  plan_full(P, n, items, scr);
+  if (P.bytes() > STAGE_BYTES) return RZF_E_INVALID;
+  const int slot = stage_acquire(c);
+  if (slot < 0) return RZF_E_DEVICE;
+  Stager st{c->h_stage + slot * STAGE_BYTES, c->d_stage + slot * STAGE_BYTES};
+  P.put(st);
+  HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
+  P.launch(c, s, err);
   HIP_OK(hipEventRecord(c->stage_ev[slot], s));
   c->stage_used[slot] = true;
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
+}
+
+size_t rate_scratch_bytes(int K) { return align_up(sizeof(double) * sum_rate_scratch_doubles(K)); }
+
+void plan_rate(RatePlan& P, int n, const rzf_rate_item* items, double Pw, double sigma2, char* part,
+               unsigned* counts) {
+  P = RatePlan{};
+  P.rj.resize(n);
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    const rzf_rate_item& it = items[i];
+    P.rj[i] = RateJob{reinterpret_cast<const float2*>(it.H), reinterpret_cast<const float2*>(it.W),
+                      reinterpret_cast<double*>(part + off), it.rates, it.sum_rate, it.K, it.N, it.ldh, it.ldw,
+                      Pw, it.sigma2 >= 0.0 ? it.sigma2 : sigma2, counts + i};
+    off += rate_scratch_bytes(it.K);
+    P.maxK = std::max(P.maxK, it.K);
+  }
+}
+
+size_t RatePlan::bytes() const { return sizeof(RateJob) * rj.size() + 64; }
+
+void RatePlan::put(Stager& st) { st.put(rj.data(), (int)rj.size(), &d_rj); }
+
+void RatePlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
+  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj[0], d_rj, (int)rj.size(), maxK, 1, err, s); });
+}
+
+void update_single_launch(rzf_ctx* c, rzf_track* t, const float2* Hf, int ldh, double tol, float2* Wf, int ldw,
+                          bool reset, hipStream_t s) {
+  const TrackDesc& d = t->h_desc;
+  const int K = t->K, N = t->N;
+  if (reset) {
+    const Gram64Job gj{Hf, d.A64, K, N, ldh, t->alpha};
+    const Inv64Job ij{d.A64, d.Ainv, &t->d_desc->info, nullptr, K, d.Rfb, &t->d_desc->hold};
+    timed(c, KN_GRAM64, s, [&] { launch_gram64(gj, nullptr, 1, K, s); });
+    timed(c, KN_INV64, s, [&] { inv64_any(ij, c->d_err, s); });
+  } else {
+    const GramJob gj{Hf, d.Hprev, d.Anew, d.dA, K, N, ldh, N, (float)t->alpha, d.prec};
+    const ArsvdJob aj{t->d_desc, nullptr, tol, t->i_max};
+    timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, s); });
+    timed(c, KN_ARSVD, s, [&] { arsvd_single(c, aj, K, s); });
+  }
+  const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw, d.prec, &t->d_desc->hold};
+  const ScaleJob sj{Wf, d.wpart, d.P, K, N, ldw, precoder_blocks(N), t->d_desc};
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, s); });
+  timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
+}
+
+void full_single_launch(rzf_ctx* c, int K, int N, const float2* Hf, int ldh, double alpha, double P, float2* Wf,
+                        int ldw, hipStream_t s) {
+  const GramJob gj{Hf, nullptr, c->d_fullA, nullptr, K, N, ldh, 0, (float)alpha, RZF_PREC_FP32};
+  const PrecJob pj{Hf, c->d_fullAinv, Wf, c->d_fullwpart, nullptr, K, N, ldh, ldw, RZF_PREC_FP32, nullptr};
+  const ScaleJob sj{Wf, c->d_fullwpart, P, K, N, ldw, precoder_blocks(N), nullptr};
+  timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, s); });
+  const Inv32Job vj{c->d_fullA, c->d_fullAinv, K};
+  timed(c, KN_INV32, s, [&] { inv32_any(vj, c->d_err, s); });
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, s); });
+  timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
+}
+
+void rate_single_launch(rzf_ctx* c, int K, int N, const float2* H, int ldh, const float2* W, int ldw, double P,
+                        double sigma2, float* rates, double* sum, hipStream_t s) {
+  const RateJob rj{H, W, c->d_srpart, rates, sum, K, N, ldh, ldw, P, sigma2, c->d_counts};
+  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj, nullptr, 1, K, sum_rate_splits(K, N), c->d_err, s); });
+}
+
+bool arena_take(rzf_ctx* c, size_t bytes, size_t* off) { return arena_alloc(c, bytes, off); }
+void arena_give(rzf_ctx* c, size_t off, size_t bytes) { arena_free(c, off, bytes); }
+bool reset_due(const rzf_track* t) {
+  return t->prm.reset_period > 0 && t->since_reset + 1 >= t->prm.reset_period;
 }
 
 }  // namespace rzfrt
@@ -783,7 +870,6 @@ rzf_status rzf_full_batch(rzf_ctx* c, int n, const rzf_full_item* items) {
 rzf_status rzf_sum_rate_batch(rzf_ctx* c, int n, const rzf_rate_item* items, double P, double sigma2) {
   if (!c || !items || n < 1 || n > RZF_BATCH_MAX) return RZF_E_INVALID;
   if (!std::isfinite(P) || P <= 0.0 || !std::isfinite(sigma2) || sigma2 < 0.0) return RZF_E_INVALID;
-  int maxK = 1;
   size_t want = 0;   // per-item partial sums, packed
   for (int i = 0; i < n; ++i) {
     const rzf_rate_item& it = items[i];
@@ -791,8 +877,7 @@ rzf_status rzf_sum_rate_batch(rzf_ctx* c, int n, const rzf_rate_item* items, dou
     if (it.K < 1 || it.K > RZF_KMAX || it.N < 1 || it.N > RZF_NMAX || it.ldh < it.N || it.ldw < it.K)
       return RZF_E_SHAPE;
     if (std::isnan(it.sigma2)) return RZF_E_INVALID;
-    maxK = std::max(maxK, it.K);
-    want += align_up(sizeof(double) * sum_rate_scratch_doubles(it.K));
+    want += rate_scratch_bytes(it.K);
   }
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
@@ -809,23 +894,14 @@ rzf_status rzf_sum_rate_batch(rzf_ctx* c, int n, const rzf_rate_item* items, dou
     c->batch_part_bytes = want;
     c->d_batch_part = reinterpret_cast<double*>(c->arena + off);
   }
-  std::vector<RateJob> rj(n);
-  size_t off = 0;
-  for (int i = 0; i < n; ++i) {
-    const rzf_rate_item& it = items[i];
-    rj[i] = RateJob{reinterpret_cast<const float2*>(it.H), reinterpret_cast<const float2*>(it.W),
-                    reinterpret_cast<double*>(reinterpret_cast<char*>(c->d_batch_part) + off),
-                    it.rates, it.sum_rate, it.K, it.N, it.ldh, it.ldw, P,
-                    it.sigma2 >= 0.0 ? it.sigma2 : sigma2, c->d_counts + i};
-    off += align_up(sizeof(double) * sum_rate_scratch_doubles(it.K));
-  }
+  RatePlan R;
+  plan_rate(R, n, items, P, sigma2, reinterpret_cast<char*>(c->d_batch_part), c->d_counts);
   const int slot = stage_acquire(c);
   if (slot < 0) return RZF_E_DEVICE;
   Stager st{c->h_stage + slot * STAGE_BYTES, c->d_stage + slot * STAGE_BYTES};
-  RateJob* d_rj = nullptr;
-  st.put(rj.data(), n, &d_rj);
+  R.put(st);
   HIP_OK(hipMemcpyAsync(st.d, st.h, st.used, hipMemcpyHostToDevice, s));
-  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj[0], d_rj, n, maxK, 1, c->d_err, s); });
+  R.launch(c, s, c->d_err);
   HIP_OK(hipEventRecord(c->stage_ev[slot], s));
   c->stage_used[slot] = true;
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
@@ -843,16 +919,8 @@ rzf_status rzf_full(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, double 
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
   hipStream_t s = c->stream;
-  const float2* Hf = reinterpret_cast<const float2*>(H);
-  float2* Wf = reinterpret_cast<float2*>(W);
-  const GramJob gj{Hf, nullptr, c->d_fullA, nullptr, K, N, ldh, 0, (float)alpha, RZF_PREC_FP32};
-  const PrecJob pj{Hf, c->d_fullAinv, Wf, c->d_fullwpart, nullptr, K, N, ldh, ldw, RZF_PREC_FP32, nullptr};
-  const ScaleJob sj{Wf, c->d_fullwpart, P, K, N, ldw, precoder_blocks(N)};
-  timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, s); });
-  const Inv32Job vj{c->d_fullA, c->d_fullAinv, K};
-  timed(c, KN_INV32, s, [&] { inv32_any(vj, c->d_err, s); });
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, s); });
-  timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
+  full_single_launch(c, K, N, reinterpret_cast<const float2*>(H), ldh, alpha, P, reinterpret_cast<float2*>(W), ldw,
+                     s);
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
 }
 
@@ -864,9 +932,8 @@ rzf_status rzf_sum_rate(rzf_ctx* c, int K, int N, const rzf_c32* H, int ldh, con
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
   hipStream_t s = c->stream;
-  const RateJob rj{reinterpret_cast<const float2*>(H), reinterpret_cast<const float2*>(W), c->d_srpart,
-                   rates, c->d_sum, K, N, ldh, ldw, P, sigma2, c->d_counts};
-  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj, nullptr, 1, K, sum_rate_splits(K, N), c->d_err, s); });
+  rate_single_launch(c, K, N, reinterpret_cast<const float2*>(H), ldh, reinterpret_cast<const float2*>(W), ldw, P,
+                     sigma2, rates, c->d_sum, s);
   if (hipGetLastError() != hipSuccess) return RZF_E_DEVICE;
   if (sum_rate) {
     HIP_OK(hipMemcpyAsync(c->h_sum, c->d_sum, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1158,6 +1225,8 @@ rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track
   t->t = h.step;
   t->since_reset = h.since_reset;
   t->h_desc.last_r = h.last_r;
+  t->h_desc.t_dev = h.step;
+  t->h_desc.seq_dev += (unsigned)h.step;
   t->h_desc.warm = h.warm;
   t->h_desc.warm_age = h.warm_age;
   const char* p = static_cast<const char*>(buf) + sizeof(h);
@@ -1184,6 +1253,7 @@ rzf_status rzf_track_destroy(rzf_track* t) {
   if (!t) return RZF_E_INVALID;
   rzf_ctx* c = t->ctx;
   std::lock_guard<std::mutex> lk(c->mu);
+  if (t->graphs > 0) return RZF_E_INVALID;   // a captured step still updates it
   (void)hipSetDevice(c->device);
   HIP_OK(hipStreamSynchronize(c->stream));
   c->tracks.erase(t);

@@ -491,7 +491,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   const ArsvdJob& jb = job_of<MANY>(one, many);
   GTrackDesc* __restrict__ td = (GTrackDesc*)jb.td;
   TrackDesc* const tdg = (TrackDesc*)td;    // the same, for whole-struct copies
-  const int t = jb.t, i_max = jb.i_max;
+  const int t = td->t_dev + 1, i_max = jb.i_max;
+  const unsigned long long seq = td->seq_dev;
   const double eta = jb.eta;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int K = td->K;
@@ -528,7 +529,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   if constexpr (PH == 2) {
     E = spec_d[SPEC_MAX];
     // the first phase may have completed the step already
-    if (tid == 0) sm.found = tags[SPEC_MAX] == jb.seq;
+    if (tid == 0) sm.found = tags[SPEC_MAX] == seq;
     __syncthreads();
     if (sm.found) return;
   } else {
@@ -778,7 +779,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
         bool all = true;
         for (int j = 0; j + 1 < kfull; ++j) {
           if (seen & (1u << j)) continue;
-          if (__hip_atomic_load(&tags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == jb.seq) {
+          if (__hip_atomic_load(&tags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == seq) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const unsigned long long bits = __hip_atomic_load(
                 reinterpret_cast<unsigned long long*>(&spec_d[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -796,7 +797,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     if (tid == 0) {
       // post ||Z||_F^2, then its tag (release: the value is visible first)
       spec_d[itn - 1] = tot;
-      __hip_atomic_store(&tags[itn - 1], jb.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&tags[itn - 1], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (stage_ok && itn == kfull && tot >= Et && kfull > 1) {
       // the step needs this iteration only if no earlier one meets the energy
@@ -1200,7 +1201,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       td->nsig = rotated ? d : 0;
       if (PH == 1) {
         td->hold = 0;   // a finite step (the second phase, which would record it, returns at once)
-        __hip_atomic_store(&tags[SPEC_MAX], jb.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&tags[SPEC_MAX], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     (void)c_begin;

@@ -612,7 +612,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
   const ArsvdJob& jb = job_of<MANY>(one, many);
   GTrackDesc* __restrict__ td = (GTrackDesc*)jb.td;
   TrackDesc* const tdg = (TrackDesc*)td;    // the same, for whole-struct copies
-  const int t = jb.t, i_max = jb.i_max;
+  const int t = td->t_dev + 1, i_max = jb.i_max;
   const double eta = jb.eta;
   const int tid = threadIdx.x, wid = tid >> 6;
   const int K = td->K;

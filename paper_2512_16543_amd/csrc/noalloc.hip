@@ -65,7 +65,7 @@ extern "C" rzf_status rzf_full_noalloc(void* hip_stream, int K, int N, const rzf
   const GramJob gj{Hf, nullptr, A, nullptr, K, N, ldh, 0, (float)alpha, RZF_PREC_FP32};
   const Inv32Job vj{A, Ainv, K};
   const PrecJob pj{Hf, Ainv, Wf, wpart, nullptr, K, N, ldh, ldw, RZF_PREC_FP32, nullptr};
-  const ScaleJob sj{Wf, wpart, P, K, N, ldw, precoder_blocks(N)};
+  const ScaleJob sj{Wf, wpart, P, K, N, ldw, precoder_blocks(N), nullptr};
   launch_gram(gj, nullptr, 1, K, s);
   if (K > KS) launch_inv32_big(vj, nullptr, 1, err, s);
   else launch_inv32(vj, nullptr, 1, err, s);

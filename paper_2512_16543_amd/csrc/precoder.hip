@@ -181,6 +181,11 @@ __global__ __launch_bounds__(SCT) void k_scale(ScaleJob one, const ScaleJob* man
   }
   __syncthreads();
   const float s = sc;
+  if (jb.adv && blockIdx.x == 0 && threadIdx.x == 0) {
+    // the track's step is complete: its next one takes the next index and tag
+    jb.adv->t_dev += 1;
+    jb.adv->seq_dev += 1;
+  }
   const int stride = min(per, SCB) * SCT;
   if ((K & 1) == 0 && (ldw & 1) == 0 && (reinterpret_cast<uintptr_t>(W) & 15) == 0) {
     const int K2 = K >> 1;

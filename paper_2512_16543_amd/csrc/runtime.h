@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <set>
@@ -60,6 +61,7 @@ struct rzf_ctx {
   size_t pin_used = 0;
   std::vector<rzfrt::Pending> pending;
   std::set<rzf_track*> tracks;
+  std::set<rzf_graph*> graphs;          // captured steps on this context
   std::mutex mu;
   // batched calls: ring of pinned host / device staging slots for job arrays
   char* h_stage = nullptr;
@@ -73,6 +75,7 @@ struct rzf_ctx {
   size_t batch_full_off = 0, batch_full_bytes = 0;
   float2* d_beam_g = nullptr;           // beam responses of rzf_beamspace
   size_t beam_g_off = 0, beam_g_bytes = 0;
+  bool capturing = false;               // a step is being captured into a graph (no timing events)
   // event timing
   bool prof_on = false;
   std::vector<rzfrt::ProfRec> prof;
@@ -92,6 +95,7 @@ struct rzf_track {
   int t = 0;
   int since_reset = 0;
   int i_max = 0;
+  int graphs = 0;   // captured steps (rzf_graph) that update this track
 };
 
 namespace rzfrt {
@@ -117,5 +121,101 @@ struct FullScratch {
 // the context's own (grown on demand; then only on the context stream).
 rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items, const FullScratch* scr,
                              hipStream_t s, int* err);
+
+// Job arrays of a batched launch: written into a host buffer h and given the
+// matching addresses in device memory d (the caller copies h to d once).
+struct Stager {
+  char* h;
+  char* d;
+  size_t used = 0;
+  template <class T>
+  T* put(const T* src, int n, T** dev) {
+    used = (used + 15) & ~size_t(15);
+    T* hp = reinterpret_cast<T*>(h + used);
+    *dev = reinterpret_cast<T*>(d + used);
+    std::memcpy(hp, src, sizeof(T) * n);
+    used += sizeof(T) * n;
+    return hp;
+  }
+};
+
+// The launches of one batched update step over their job arrays.  bytes()
+// bounds what put() writes; launch() needs the arrays in device memory.
+struct UpdatePlan {
+  std::vector<GramJob> gj;
+  std::vector<ArsvdJob> aj, ajb;   // LDS kernels (K <= KS) / large tracks
+  std::vector<Gram64Job> g64;
+  std::vector<Inv64Job> i64, i64b;
+  std::vector<PrecJob> pj;
+  std::vector<ScaleJob> sj;
+  std::vector<int> reset_flag;
+  int maxK = 1, maxN = 1, maxKr = 1, maxNK = 1;
+  GramJob* d_gj = nullptr;
+  ArsvdJob* d_aj = nullptr;
+  ArsvdJob* d_ajb = nullptr;
+  Gram64Job* d_g64 = nullptr;
+  Inv64Job* d_i64 = nullptr;
+  Inv64Job* d_i64b = nullptr;
+  PrecJob* d_pj = nullptr;
+  ScaleJob* d_sj = nullptr;
+  size_t bytes() const;
+  void put(Stager& st);
+  void launch(rzf_ctx* c, hipStream_t s, int* err) const;
+};
+// force_reset < 0: each track's own reset schedule; 0 or 1: every item takes
+// a Woodbury step, or an FP64 re-inversion.
+void plan_update(UpdatePlan& P, int n, const rzf_update_item* items, double tol, int force_reset);
+// Host step counters after a step of these tracks.
+void advance_tracks(int n, rzf_track* const* tracks, const std::vector<int>& reset_flag);
+bool reset_due(const rzf_track* t);
+
+struct FullPlan {
+  std::vector<GramJob> gj;
+  std::vector<Inv32Job> vj, vjb;
+  std::vector<PrecJob> pj;
+  std::vector<ScaleJob> sj;
+  int maxK = 1, maxN = 1, maxNK = 1;
+  GramJob* d_gj = nullptr;
+  Inv32Job* d_vj = nullptr;
+  Inv32Job* d_vjb = nullptr;
+  PrecJob* d_pj = nullptr;
+  ScaleJob* d_sj = nullptr;
+  size_t bytes() const;
+  void put(Stager& st);
+  void launch(rzf_ctx* c, hipStream_t s, int* err) const;
+};
+void plan_full(FullPlan& P, int n, const rzf_full_item* items, const FullScratch* scr);
+size_t full_scratch_bytes(const rzf_full_item& it);
+FullScratch full_scratch_at(const rzf_full_item& it, char* p);
+
+struct RatePlan {
+  std::vector<RateJob> rj;
+  int maxK = 1;
+  RateJob* d_rj = nullptr;
+  size_t bytes() const;
+  void put(Stager& st);
+  void launch(rzf_ctx* c, hipStream_t s, int* err) const;
+};
+// part: the items' scratch packed in item order (rate_scratch_bytes(K) each);
+// counts: one completion count per item, zero between launches.
+void plan_rate(RatePlan& P, int n, const rzf_rate_item* items, double Pw, double sigma2, char* part,
+               unsigned* counts);
+size_t rate_scratch_bytes(int K);
+
+// One track's launches (c->mu held, arguments checked), as rzf_update,
+// rzf_full and rzf_sum_rate make them.
+void update_single_launch(rzf_ctx* c, rzf_track* t, const float2* H, int ldh, double tol, float2* W, int ldw,
+                          bool reset, hipStream_t s);
+void full_single_launch(rzf_ctx* c, int K, int N, const float2* H, int ldh, double alpha, double P, float2* W,
+                        int ldw, hipStream_t s);
+void rate_single_launch(rzf_ctx* c, int K, int N, const float2* H, int ldh, const float2* W, int ldw, double P,
+                        double sigma2, float* rates, double* sum, hipStream_t s);
+
+// Frees every graph of a context that is being destroyed.
+void graphs_release_all(rzf_ctx* c);
+
+// Device memory from the context's arena (c->mu held).
+bool arena_take(rzf_ctx* c, size_t bytes, size_t* off);
+void arena_give(rzf_ctx* c, size_t off, size_t bytes);
 
 }  // namespace rzfrt

@@ -55,7 +55,10 @@ struct TrackDesc {
   DevInfo info;
   int dbg[8];      // last update: [0] Jacobi sweeps, [1] Jacobi rounds, [2] QR columns
   int nsig;        // number of sigma^2 below (d of the last SVD, 0 if none)
-  int pad2_;
+  int t_dev;       // steps done (the host's count, advanced on the device by the step's
+                   // last launch, so that a captured step replays with the right index)
+  unsigned long long seq_dev;   // the two-phase form's tag number of the next step: unique to
+                                // the track in the process (its number times 2^32), plus t_dev
   double sig2[KM]; // last SVD: sigma_j^2, descending
 };
 
@@ -93,14 +96,13 @@ struct Inv32Job {
   int K;
 };
 struct ArsvdJob {
-  TrackDesc* td;
+  TrackDesc* td;   // the step index (sketch counter) and the two-phase tag number come from
+                   // td->t_dev and td->seq_dev
   DevInfo* out;    // extra copy of the step's info (batched calls), or null
   double eta;
-  int t, i_max;
+  int i_max;
   float2* spec;    // speculative-iteration workspace (SPEC_BYTES), two-phase single-track form only
   char* stage;     // staging area of the job's full-width step (two-phase form), or null
-  unsigned long long seq;   // two-phase form: this launch's number in its context (tags the
-                            // iterations' posted ||Z||_F^2), 0 otherwise
 };
 // Two-phase single-track form of the K <= KS arSVD kernel: up to SPEC_MAX
 // iterations of Alg. 1 are computed at once, one workgroup each, into
@@ -133,6 +135,7 @@ struct ScaleJob {
   float2* W; const double* wpart;
   double P;
   int K, N, ldw, nparts;
+  TrackDesc* adv;   // a track's step ends here: its t_dev and seq_dev advance (or null)
 };
 struct RateJob {
   const float2* H; const float2* W; double* part; float* rates; double* sum;

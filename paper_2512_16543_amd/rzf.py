@@ -82,6 +82,10 @@ class ServeRequest(ctypes.Structure):
                 ("t_arrival_us", ctypes.c_double)]
 
 
+class GraphRate(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_double), ("sigma2", ctypes.c_double), ("sums", ctypes.c_void_p)]
+
+
 class ProfileEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("count", ctypes.c_int), ("total_ms", ctypes.c_double)]
 
@@ -130,6 +134,12 @@ _SIGS = {
     "rzf_sum_rate_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(RateItem),
                                           ctypes.c_double, ctypes.c_double]),
     "rzf_track_query": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 5),
+    "rzf_graph_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(UpdateItem), ctypes.c_double,
+                                        ctypes.POINTER(GraphRate), ctypes.POINTER(ctypes.c_void_p)]),
+    "rzf_graph_full": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(FullItem),
+                                      ctypes.POINTER(GraphRate), ctypes.POINTER(ctypes.c_void_p)]),
+    "rzf_graph_launch": (ctypes.c_int, [ctypes.c_void_p]),
+    "rzf_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "rzf_track_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "rzf_server_params_default": (ctypes.c_int, [ctypes.POINTER(ServerParams)]),
     "rzf_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerParams),
@@ -417,6 +427,30 @@ class Context:
         _check(lib().rzf_sum_rate_batch(self.h, len(items), items, float(P), float(sigma2)),
                "rzf_sum_rate_batch")
 
+    def _graph_rate(self, rate):
+        if rate is None:
+            return None
+        P, sigma2, sums = rate
+        return ctypes.pointer(GraphRate(float(P), float(sigma2), _dev_ptr(sums)))
+
+    def graph_update(self, tracks, Hs, Ws, tol: float, rate=None) -> "Graph":
+        """Captured update step over fixed H / W tensors (rzf_graph_update);
+        rate = (P, sigma2, sums) adds each item's sum rate into the float64
+        device tensor sums."""
+        items = self.update_items(tracks, Hs, Ws)
+        out = ctypes.c_void_p()
+        _check(lib().rzf_graph_update(self.h, len(tracks), items, float(tol), self._graph_rate(rate),
+                                      ctypes.byref(out)), "rzf_graph_update")
+        return Graph(self, out.value, (Hs, Ws, rate))
+
+    def graph_full(self, Hs, alphas, P: float, Ws, precision: int = 0, rate=None) -> "Graph":
+        """Captured full-inversion step over fixed H / W tensors (rzf_graph_full)."""
+        items = self.full_items(Hs, alphas, P, Ws, precision)
+        out = ctypes.c_void_p()
+        _check(lib().rzf_graph_full(self.h, len(Hs), items, self._graph_rate(rate), ctypes.byref(out)),
+               "rzf_graph_full")
+        return Graph(self, out.value, (Hs, Ws, rate))
+
     def full_batch(self, Hs, alphas, P: float, Ws, precision: int = 0):
         arr = self.full_items(Hs, alphas, P, Ws, precision)
         _check(lib().rzf_full_batch(self.h, len(Hs), arr), "rzf_full_batch")
@@ -445,6 +479,22 @@ class Context:
         _check(lib().rzf_debug_sketch(self.h, seed, track, t, it, K, d, ctypes.c_void_p(om.data_ptr()),
                                       ctypes.c_void_p(words.data_ptr())), "rzf_debug_sketch")
         return om.t(), words.view(K, d, 2)
+
+
+class Graph:
+    """A captured step (rzf_graph_*); keeps its buffers alive."""
+
+    def __init__(self, ctx: Context, h, keep):
+        self.ctx, self.h, self._keep = ctx, h, keep
+
+    def launch(self):
+        _check(lib().rzf_graph_launch(self.h), "rzf_graph_launch")
+
+    def destroy(self):
+        # a closed context has freed its graphs already
+        if self.h and self.ctx.h:
+            _check(lib().rzf_graph_destroy(self.h), "rzf_graph_destroy")
+        self.h = None
 
 
 class Track:

@@ -28,6 +28,15 @@ def test_library_exports_every_declared_function():
     assert set(names) <= set(rzf._SIGS)
 
 
+def test_graph_entry_points_check_arguments():
+    L = rzf.lib()
+    out = ctypes.c_void_p()
+    assert L.rzf_graph_update(None, 1, None, 0.9, None, ctypes.byref(out)) == rzf.RZF_E_INVALID
+    assert L.rzf_graph_full(None, 1, None, None, ctypes.byref(out)) == rzf.RZF_E_INVALID
+    assert L.rzf_graph_launch(None) == rzf.RZF_E_INVALID
+    assert L.rzf_graph_destroy(None) == rzf.RZF_E_INVALID
+
+
 def test_params_default_values():
     p = rzf.default_params()
     assert (p.k_init, p.p, p.i_max, p.switch_ratio, p.reset_period, p.P) == (2, 5, 0, 0.5, 0, 1.0)

@@ -1,0 +1,122 @@
+"""Captured steps (rzf_graph_*): replaying a captured step gives bit-identical
+results to the eager calls it was captured from.
+
+For each form (one track through rzf_update, a ragged batch through
+rzf_update_batch, and the full-inversion calls) a twin set of tracks is
+stepped eagerly while the graph's tracks are stepped by replays, with the
+snapshots copied into the graph's fixed H buffers between replays and the
+eager twin's launches interleaved on the same stream.  The reset period makes
+the replays alternate between the Woodbury-step graph and the re-inversion
+graph.  Every replay's W, sum rate and final A^-1 must equal the eager ones.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2512_16543_amd import rzf, workload as wl
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 9
+P, S2 = 1.0, 0.1
+
+
+def walk(K, N, steps, seed):
+    H = [wl.random_channel(K, N, seed)]
+    for t in range(steps):
+        H.append(wl.perturbed_channel(H[-1], seed * 1000 + t, rank=2, scale=0.02))
+    return torch.from_numpy(np.asarray(H, dtype=np.complex64)).cuda()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = rzf.Context(0, 256 << 20)
+    yield c
+    c.close()
+
+
+def _pair(ctx, Hs, period):
+    mk = lambda: [ctx.init(H[0], 0.3 + H.shape[1] / 25.0,
+                           rzf.default_params(seed=3, track_id=i, reset_period=period))
+                  for i, H in enumerate(Hs)]
+    return mk(), mk()
+
+
+@pytest.mark.parametrize("sizes,tol", [([(64, 256)], 0.999), ([(16, 64)], 0.9), ([(96, 128)], 0.95),
+                                       ([(16, 64), (64, 256), (13, 37), (96, 128)], 0.95)])
+def test_update_graph_replays_equal_eager(ctx, sizes, tol):
+    Hs = [walk(K, N, STEPS, 40 + i) for i, (K, N) in enumerate(sizes)]
+    torch.cuda.synchronize()
+    eager, cap = _pair(ctx, Hs, period=4)
+    n = len(sizes)
+    Hbuf = [torch.empty_like(H[0]) for H in Hs]
+    Wbuf = [torch.empty(N, K, dtype=torch.complex64, device="cuda") for K, N in sizes]
+    sums = torch.zeros(n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    g = ctx.graph_update(cap, Hbuf, Wbuf, tol, rate=(P, S2, sums))
+    We = [torch.empty_like(w) for w in Wbuf]
+    sums_e = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for t in range(1, STEPS + 1):
+        for i in range(n):
+            Hbuf[i].copy_(Hs[i][t])
+        torch.cuda.synchronize()        # the library's stream does not follow torch's
+        g.launch()
+        if n == 1:
+            eager[0].update(Hs[0][t], tol, We[0], want_info=False)
+            ref = [ctx.sum_rate(Hs[0][t], We[0], P, S2)]
+        else:
+            ctx.update_batch(eager, [H[t] for H in Hs], We, tol)
+            ctx.sum_rate_batch([H[t] for H in Hs], We, P, S2, sums=sums_e)
+            ctx.sync()
+            ref = sums_e.tolist()
+        ctx.sync()
+        for i in range(n):
+            assert torch.equal(We[i], Wbuf[i]), (sizes[i], t)
+        assert sums.tolist() == ref, t
+    for a, b in zip(eager, cap):
+        assert torch.equal(a.inverse(), b.inverse())
+        assert a.query()["t"] == b.query()["t"] == STEPS
+    # a track stepped outside the graph falls out of its reset schedule
+    if n > 1:
+        cap[0].update(Hs[0][STEPS], tol, Wbuf[0], want_info=False)
+        with pytest.raises(rzf.RzfError):
+            g.launch()
+    # and cannot be destroyed while the graph exists
+    with pytest.raises(rzf.RzfError):
+        cap[0].destroy()
+    g.destroy()
+    for tr in eager + cap:
+        tr.destroy()
+
+
+@pytest.mark.parametrize("sizes,precision", [([(64, 256)], 0), ([(16, 64), (64, 1000), (96, 128)], 0),
+                                             ([(40, 100)], rzf.PREC_BF16X3)])
+def test_full_graph_replays_equal_eager(ctx, sizes, precision):
+    Hs = [walk(K, N, 3, 60 + i) for i, (K, N) in enumerate(sizes)]
+    alphas = [0.2 + K / 30.0 for K, _ in sizes]
+    Hbuf = [torch.empty_like(H[0]) for H in Hs]
+    Wbuf = [torch.empty(N, K, dtype=torch.complex64, device="cuda") for K, N in sizes]
+    We = [torch.empty_like(w) for w in Wbuf]
+    n = len(sizes)
+    sums = torch.zeros(n, dtype=torch.float64, device="cuda")
+    sums_e = torch.zeros(n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    g = ctx.graph_full(Hbuf, alphas, 1.5, Wbuf, precision=precision, rate=(1.5, S2, sums))
+    for t in range(4):
+        for i in range(n):
+            Hbuf[i].copy_(Hs[i][t])
+        torch.cuda.synchronize()
+        g.launch()
+        if n == 1 and precision == 0:
+            ctx.full(Hs[0][t], alphas[0], 1.5, We[0])
+            ref = [ctx.sum_rate(Hs[0][t], We[0], 1.5, S2)]
+        else:
+            ctx.full_batch([H[t] for H in Hs], alphas, 1.5, We, precision=precision)
+            ctx.sum_rate_batch([H[t] for H in Hs], We, 1.5, S2, sums=sums_e)
+            ctx.sync()
+            ref = sums_e.tolist()
+        for i in range(n):
+            assert torch.equal(We[i], Wbuf[i]), (sizes[i], t)
+        assert sums.tolist() == ref, t
+    g.destroy()
