@@ -278,6 +278,33 @@ typedef struct {
 rzf_status rzf_sum_rate_batch(rzf_ctx* ctx, int n, const rzf_rate_item* items, double P,
                               double sigma2);
 
+/* ------------------------------------------------------------ launch tuning
+ * Launch shapes chosen per track size, e.g. from the table that the
+ * library's autotuner writes (paper_2512_16543_amd/tuning.json).  Neither
+ * choice changes any result bit: the precoder's partial norms are per 32
+ * rows whatever its rows per workgroup, and the sum rate's antenna sum is
+ * rounded by fixed partitions however they are spread over workgroups.
+ *  - precoder_rows: rows of W per precoder workgroup of a single-track
+ *    launch, 32 or 64 (0 = default 64); batch_precoder_rows: the same for a
+ *    batched launch, which takes the entry of its largest (K, N).
+ *  - rate_splits: workgroups over which a single track's sum rate (K <= 64)
+ *    spreads its antenna sum, 1..8 (0 = default: one per 64 antennas, at
+ *    most 8).  Batched sum rates use one workgroup per track.
+ * A launch takes the entry with its exact (K, N), else the nearest one in
+ * |log2 K - log2 K'| + |log2 N - log2 N'| (the lower K, then N, on ties),
+ * else the defaults. */
+typedef struct {
+  int K, N;
+  int precoder_rows;
+  int batch_precoder_rows;
+  int rate_splits;
+} rzf_tune_entry;
+
+/* Replaces the context's table (n = 0 clears it).  Entries with K or N out
+ * of range or a knob outside its values give RZF_E_INVALID (table unchanged).
+ * At most 4096 entries. */
+rzf_status rzf_tune_table(rzf_ctx* ctx, int n, const rzf_tune_entry* entries);
+
 /* ------------------------------------------------ captured steps (HIP graphs)
  * One step of rzf_update / rzf_update_batch (or of rzf_full / rzf_full_batch),
  * optionally followed by the sum rate of eq. (15) (Sec. VI) of every item,

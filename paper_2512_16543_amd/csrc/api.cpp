@@ -621,7 +621,8 @@ void UpdatePlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
       if (!i64b.empty()) launch_inv64_big(i64b[0], d_i64b, (int)i64b.size(), err, s);
     });
   }
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, s); });
+  const int pb = tune_for(c, maxK, maxN).batch_precoder_rows;
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, pb, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
 }
 
@@ -722,7 +723,8 @@ void FullPlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
     if (!vj.empty()) launch_inv32(vj[0], d_vj, (int)vj.size(), err, s);
     if (!vjb.empty()) launch_inv32_big(vjb[0], d_vjb, (int)vjb.size(), err, s);
   });
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, s); });
+  const int pb = tune_for(c, maxK, maxN).batch_precoder_rows;
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, pb, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
 }
 
@@ -808,7 +810,8 @@ void update_single_launch(rzf_ctx* c, rzf_track* t, const float2* Hf, int ldh, d
   }
   const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw, d.prec, &t->d_desc->hold};
   const ScaleJob sj{Wf, d.wpart, d.P, K, N, ldw, precoder_blocks(N), t->d_desc};
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, s); });
+  const int pb = tune_for(c, K, N).precoder_rows;
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, pb, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
 }
 
@@ -820,14 +823,33 @@ void full_single_launch(rzf_ctx* c, int K, int N, const float2* Hf, int ldh, dou
   timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, s); });
   const Inv32Job vj{c->d_fullA, c->d_fullAinv, K};
   timed(c, KN_INV32, s, [&] { inv32_any(vj, c->d_err, s); });
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, s); });
+  const int pb = tune_for(c, K, N).precoder_rows;
+  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, pb, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
 }
 
 void rate_single_launch(rzf_ctx* c, int K, int N, const float2* H, int ldh, const float2* W, int ldw, double P,
                         double sigma2, float* rates, double* sum, hipStream_t s) {
   const RateJob rj{H, W, c->d_srpart, rates, sum, K, N, ldh, ldw, P, sigma2, c->d_counts};
-  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj, nullptr, 1, K, sum_rate_splits(K, N), c->d_err, s); });
+  const int ns = tune_for(c, K, N).rate_splits;
+  timed(c, KN_SUMRATE, s, [&] { launch_sum_rate(rj, nullptr, 1, K, ns, c->d_err, s); });
+}
+
+rzf_tune_entry tune_for(const rzf_ctx* c, int K, int N) {
+  rzf_tune_entry best{K, N, 0, 0, 0};
+  double bd = 1e300;
+  for (const rzf_tune_entry& e : c->tune) {
+    const double d = std::fabs(std::log2((double)K / e.K)) + std::fabs(std::log2((double)N / e.N));
+    // nearest; ties to the lower K, then the lower N
+    if (d < bd || (d == bd && (e.K < best.K || (e.K == best.K && e.N < best.N)))) {
+      bd = d;
+      best = e;
+    }
+  }
+  if (best.precoder_rows == 0) best.precoder_rows = 64;
+  if (best.batch_precoder_rows == 0) best.batch_precoder_rows = 64;
+  if (best.rate_splits == 0) best.rate_splits = sum_rate_splits(K, N);
+  return best;
 }
 
 bool arena_take(rzf_ctx* c, size_t bytes, size_t* off) { return arena_alloc(c, bytes, off); }
@@ -1270,6 +1292,20 @@ rzf_status rzf_debug_sketch(rzf_ctx* c, uint64_t seed, uint64_t track_id, int t,
   HIP_OK(hipSetDevice(c->device));
   launch_debug_sketch(seed, track_id, t, it, K, d, reinterpret_cast<float2*>(Omega), words, c->stream);
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
+}
+
+rzf_status rzf_tune_table(rzf_ctx* c, int n, const rzf_tune_entry* entries) {
+  if (!c || n < 0 || n > 4096 || (n > 0 && !entries)) return RZF_E_INVALID;
+  for (int i = 0; i < n; ++i) {
+    const rzf_tune_entry& e = entries[i];
+    if (e.K < 1 || e.K > RZF_KMAX || e.N < 1 || e.N > RZF_NMAX) return RZF_E_INVALID;
+    for (int v : {e.precoder_rows, e.batch_precoder_rows})
+      if (v != 0 && v != 32 && v != 64) return RZF_E_INVALID;
+    if (e.rate_splits < 0 || e.rate_splits > 8) return RZF_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->tune.assign(entries, entries + n);
+  return RZF_OK;
 }
 
 rzf_status rzf_profile(rzf_ctx* c, int enable) {

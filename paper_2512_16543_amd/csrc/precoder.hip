@@ -1,20 +1,22 @@
 // Precoder W = H^H X with its power normalisation ||W||_F^2 = P (Sec. II,
 // eq. (5)), where X is the stored inverse of the Gram matrix.
 //
-// W is N x K (row-major).  A workgroup of 16 wavefronts owns 64 rows of W (64
-// antennas) of one track and computes their 16x16 tiles (4 x ceil(K/16) of
-// them, wave w taking tiles w, w + 16, ...) on the FP32 matrix cores.  The
-// length-K reduction runs over chunks of 32 users: the chunk's 32 x 64 block
-// of H and its 32 x K rows of X are staged in LDS (the next chunk's loads in
-// flight while this one is multiplied), so H and X are read from memory
-// once per workgroup.  For rzf_update the staged H is also copied into the
-// track's H_prev.
+// W is N x K (row-major).  A workgroup of 16 wavefronts owns PB rows of W (PB
+// antennas, 32 or 64: a launch choice) of one track and computes their
+// 16x16 tiles (PB/16 x ceil(K/16) of them, wave w taking tiles w, w + 16, ...)
+// on the FP32 matrix cores.  The length-K reduction runs over chunks of 32
+// users: the chunk's 32 x PB block of H and its 32 x K rows of X are staged in
+// LDS (the next chunk's loads in flight while this one is multiplied), so H
+// and X are read from memory once per workgroup.  For rzf_update the staged H
+// is also copied into the track's H_prev.
 //
-// Every workgroup writes its rows of W and the FP64 partial sum of their
-// |w|^2; a second kernel then adds the partial sums in block order (each of
-// its blocks once) and rescales W by sqrt(P / ||W||_F^2), with 16-byte loads
-// and stores.  The two launches meet at a kernel boundary, which makes the
-// partial sums visible to every XCD's L2 without a fence per workgroup.
+// Every workgroup writes its rows of W and, per group of 32 rows, the FP64
+// sum of their |w|^2 (each 16x16 tile summed by its wave, the tiles of a
+// group added in a fixed order): the same partial sums whatever PB is, so
+// the choice of PB never changes a result.  A second kernel then adds the
+// partial sums in order and rescales W by sqrt(P / ||W||_F^2), with 16-byte
+// loads and stores.  The two launches meet at a kernel boundary, which makes
+// the partial sums visible to every XCD's L2 without a fence per workgroup.
 //
 // With the BF16 precision options the products take BF16 operands (or BF16
 // hi/lo splits, three products each), read per tile from memory, with FP32
@@ -24,24 +26,24 @@
 
 namespace {
 
-constexpr int PB = 64;          // antennas (rows of W) per workgroup
+constexpr int PG = 32;          // rows of W per partial sum of |w|^2
 constexpr int PIC = 32;         // users per reduction chunk
 constexpr int PNT = 1024;       // threads per workgroup
 constexpr int PNW = PNT / 64;
-constexpr int HLD = PB + 4;     // LDS row stride of the staged H chunk (float2)
-constexpr int HPER = PIC * PB / PNT;              // H values a thread stages per chunk
-constexpr int XPER = (PIC * KM + PNT - 1) / PNT;  // X values, at most
+constexpr int XPER = (PIC * KM + PNT - 1) / PNT;  // X values a thread stages per chunk, at most
 
-// Dynamic LDS of a launch for tracks up to maxK users: the H chunk, then the
-// X chunk with row stride maxK + 4.
-size_t prec_lds_bytes(int maxK) { return sizeof(float2) * (size_t)PIC * (HLD + maxK + 4); }
+// Dynamic LDS of a launch with PB rows per workgroup for tracks up to maxK
+// users: the H chunk (row stride PB + 4), then the X chunk (row stride maxK + 4).
+size_t prec_lds_bytes(int pb, int maxK) { return sizeof(float2) * (size_t)PIC * (pb + 4 + maxK + 4); }
 
-template <bool MANY>
+template <bool MANY, int PB>
 __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* many, int xld) {
+  constexpr int HLD = PB + 4;                 // LDS row stride of the staged H chunk (float2)
+  constexpr int HPER = PIC * PB / PNT;        // H values a thread stages per chunk
   extern __shared__ float2 dyn[];
   float2* hs = dyn;                       // [PIC][HLD]: H[i0 + ii][n0 + c] at hs[ii * HLD + c]
   float2* xs = dyn + PIC * HLD;           // [PIC][xld]: X[i0 + ii][k] at xs[ii * xld + k]
-  __shared__ double red[PNW];
+  __shared__ double tsum[PB / 16][KM / 16];   // |w|^2 of each 16x16 tile
   const PrecJob& jb = job_of<MANY>(one, many);
   const int K = jb.K, N = jb.N, ldh = jb.ldh, ldw = jb.ldw;
   const float2* __restrict__ H = jb.H;
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* ma
   if (n0 >= N) return;
   const int kt = (K + 15) / 16;
   const int ntile = (PB / 16) * kt;
-  constexpr int TPW = (PB / 16) * (KM / 16) / PNW;   // tiles per wave, at most (4)
+  constexpr int TPW = (PB / 16) * (KM / 16) / PNW;   // tiles per wave, at most
   floatx4 tre[TPW], tim[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) { tre[q] = zero4(); tim[q] = zero4(); }
@@ -134,13 +136,13 @@ __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* ma
         if (n < N) Hcopy[(size_t)i * N + n] = H[(size_t)i * ldh + n];
       }
   }
-  // the block's rows of W (unscaled) and their sum of |w|^2
-  double acc = 0.0;
+  // the block's rows of W (unscaled) and each tile's sum of |w|^2
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
     const int t = wid + PNW * q;
     if (t >= ntile) break;
     const int nt = t % (PB / 16), ct = t / (PB / 16);
+    double acc = 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int n = n0 + nt * 16 + tile_row(v), k = ct * 16 + tile_col();
@@ -149,14 +151,18 @@ __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* ma
         acc += (double)tre[q][v] * tre[q][v] + (double)tim[q][v] * tim[q][v];
       }
     }
+    acc = wave_sum(acc);
+    if (lane == 0) tsum[nt][ct] = acc;
   }
-  acc = wave_sum(acc);
-  if (lane == 0) red[wid] = acc;
   __syncthreads();
-  if (tid == 0) {
-    double w = 0.0;
-    for (int q = 0; q < PNW; ++q) w += red[q];
-    wpart[blockIdx.x] = w;
+  // one partial per 32 rows: its two row tiles, column tiles in order
+  if (tid < PB / PG) {
+    const int g = tid;
+    if (n0 + g * PG < N) {
+      double w = 0.0;
+      for (int ct = 0; ct < kt; ++ct) w += tsum[2 * g][ct] + tsum[2 * g + 1][ct];
+      wpart[n0 / PG + g] = w;
+    }
   }
 }
 
@@ -207,7 +213,7 @@ __global__ __launch_bounds__(SCT) void k_scale(ScaleJob one, const ScaleJob* man
 
 }  // namespace
 
-int precoder_blocks(int N) { return (N + PB - 1) / PB; }
+int precoder_blocks(int N) { return (N + PG - 1) / PG; }
 
 void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, hipStream_t s) {
   const int blocks = std::min((maxNK + 2 * SCT - 1) / (2 * SCT), SCB);
@@ -218,10 +224,16 @@ void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, h
 
 int precoder_scratch(int N) { return precoder_blocks(N); }
 
-void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, hipStream_t s) {
-  const dim3 grid(precoder_blocks(maxN), many ? n : 1);
-  const size_t lds = prec_lds_bytes(maxK);
+template <int PB>
+void launch_precoder_pb(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, hipStream_t s) {
+  const dim3 grid((maxN + PB - 1) / PB, many ? n : 1);
+  const size_t lds = prec_lds_bytes(PB, maxK);
   const int xld = maxK + 4;
-  if (many) k_precoder<true><<<grid, PNT, lds, s>>>(one, many, xld);
-  else k_precoder<false><<<grid, PNT, lds, s>>>(one, many, xld);
+  if (many) k_precoder<true, PB><<<grid, PNT, lds, s>>>(one, many, xld);
+  else k_precoder<false, PB><<<grid, PNT, lds, s>>>(one, many, xld);
+}
+
+void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, int pb, hipStream_t s) {
+  if (pb == 32) launch_precoder_pb<32>(one, many, n, maxN, maxK, s);
+  else launch_precoder_pb<64>(one, many, n, maxN, maxK, s);
 }

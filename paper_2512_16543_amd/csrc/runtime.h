@@ -62,6 +62,7 @@ struct rzf_ctx {
   std::vector<rzfrt::Pending> pending;
   std::set<rzf_track*> tracks;
   std::set<rzf_graph*> graphs;          // captured steps on this context
+  std::vector<rzf_tune_entry> tune;     // launch shapes by track size (rzf_tune_table)
   std::mutex mu;
   // batched calls: ring of pinned host / device staging slots for job arrays
   char* h_stage = nullptr;
@@ -210,6 +211,10 @@ void full_single_launch(rzf_ctx* c, int K, int N, const float2* H, int ldh, doub
                         int ldw, hipStream_t s);
 void rate_single_launch(rzf_ctx* c, int K, int N, const float2* H, int ldh, const float2* W, int ldw, double P,
                         double sigma2, float* rates, double* sum, hipStream_t s);
+
+// The launch shapes for a (K, N) track: the table's entry (exact, else
+// nearest), knobs left at 0 resolved to the defaults.
+rzf_tune_entry tune_for(const rzf_ctx* c, int K, int N);
 
 // Frees every graph of a context that is being destroyed.
 void graphs_release_all(rzf_ctx* c);

@@ -160,7 +160,8 @@ void launch_inv32(const Inv32Job& one, const Inv32Job* many, int n, int* err, hi
 // wpart (the workgroups' partial sums).
 int precoder_blocks(int N);
 int precoder_scratch(int N);
-void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, hipStream_t s);
+// pb: rows of W per workgroup (32 or 64; any other value takes 64).
+void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, int pb, hipStream_t s);
 // W <- W sqrt(P / ||W||_F^2) from the precoder's partial sums (maxNK: the
 // largest N K of the launch).
 void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, hipStream_t s);

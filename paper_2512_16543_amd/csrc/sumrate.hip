@@ -6,24 +6,27 @@
 //
 // One launch.  A workgroup of 16 wavefronts owns a 64 x 64 block of E (users
 // rb*64.. by users cb*64..) of one track; wave w computes its 16x16 tile on the
-// FP32 matrix cores.  The length-N reduction runs over chunks of 64 antennas:
-// the chunk's 64 x 64 block of H and 64 x 64 block of W are staged in LDS
-// (the next chunk's loads in flight while this one is multiplied).  For each
-// of its rows the workgroup writes its share of the signal (diagonal block
-// only) and of the interference; the workgroups of the first block row also
-// add the squared norm of their 64 columns of W.  With K <= 64 the track's one
-// workgroup then applies the power scaling and sums the rates in FP64 from
-// LDS.  Otherwise the shares go to scratch and the track's last workgroup to
-// finish (a completion count per item, zero between launches) adds them in a
-// fixed order; only the wave that wrote them fences before counting, since an
-// agent-scope fence writes back the XCD's L2.
+// FP32 matrix cores.  The length-N reduction runs over chunks of 64 antennas
+// (the chunk's 64 x 64 block of H and 64 x 64 block of W staged in LDS, the
+// next chunk's loads in flight while this one is multiplied).  The chunks
+// fall into SR_NP fixed partitions (contiguous runs of ceil(chunks / SR_NP));
+// each chunk's product is formed from zero and added to its partition's
+// accumulator, and E is the sum of the partitions in order, starting from
+// zero.  ||W||^2 (over the W values that the first block row stages) is summed
+// the same way: per thread over a partition's values, per partition over the
+// waves in order, then over the partitions in order.  The partitions, not the launch, fix every rounding: a single
+// track with K <= 64 may spread its partitions over ns workgroups (partition q
+// to workgroup q mod ns), which write their partitions' E blocks and norms to
+// scratch for the last of them to add up, and gives bit for bit what one
+// workgroup (ns = 1, as in a batch) gives.
 //
-// A single track with K <= 64 and N > 64 (no batch to fill the chip) splits
-// the antenna sum over ns workgroups, each taking whole chunks: they write
-// their partial 64 x 64 blocks of E and partial ||W||^2 to scratch, and the
-// last to finish adds the partials in split order before the steps above.
-// A batch launch keeps one workgroup per block, so a split track's rates
-// agree with its batched ones to FP32 rounding, not bit for bit.
+// For each of its rows the workgroup then forms its share of the signal
+// (diagonal block only) and of the interference.  With K <= 64 the track's
+// one block applies the power scaling and sums the rates in FP64 from LDS.
+// Otherwise the shares go to scratch and the track's last workgroup to finish
+// (a completion count per item, zero between launches) adds them in a fixed
+// order; only the wave that wrote them fences before counting, since an
+// agent-scope fence writes back the XCD's L2.
 #include "rzf_device.h"
 #include "rzf_internal.h"
 
@@ -36,18 +39,21 @@ constexpr int SNW = SNT / 64;
 constexpr int SLD = SC + 4;     // LDS row stride of the H chunk (64 users x 64 antennas)
 constexpr int WLD = SB + 4;     // LDS row stride of the W chunk (64 antennas x 64 users)
 constexpr int SPER = SB * SC / SNT;   // values of each chunk a thread stages (4)
+constexpr int SR_NP = 8;        // fixed partitions of the antenna chunks (and the largest split)
 
 // Scratch layout of one item (doubles): the shares [n][cb][2] (signal,
 // interference), then the column blocks' ||W||^2 [cb].  The completion count
-// (one per item) is zero before the launch and is left at zero.
+// (one per item) is zero before the launch and is left at zero.  A split
+// launch uses [SR_NP][SB * SB] complex partition blocks of E, then SR_NP
+// partition norms.
 __host__ __device__ constexpr int sr_blocks(int K) { return (K + SB - 1) / SB; }
-constexpr int SR_SPLIT_MAX = 8;
 
 template <bool MANY>
 __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* many, int ns, int* err) {
   __shared__ float2 hs[SB * SLD], ws[SC * WLD];
   __shared__ double rs[4][SB], rf[4][SB];
   __shared__ double red[SNW];
+  __shared__ double wq[SR_NP][SNW];   // per partition and wave: |W|^2
   __shared__ int last;
   const RateJob& jb = job_of<MANY>(one, many);
   const int K = jb.K, N = jb.N, ldh = jb.ldh, ldw = jb.ldw;
@@ -59,14 +65,18 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
   if ((int)blockIdx.x >= kb * kb * ns) return;
   const int blk = blockIdx.x / ns, sp = blockIdx.x - blk * ns;   // ns > 1 only with kb == 1
   const int rb = blk / kb, cb = blk - rb * kb;
-  // this workgroup's antennas: whole chunks [cbeg, cend)
-  const int cps = ((N + SC - 1) / SC + ns - 1) / ns;
-  const int cbeg = sp * cps * SC, cend = min(N, (sp + 1) * cps * SC);
+  const int nch = (N + SC - 1) / SC;
+  const int cpp = (nch + SR_NP - 1) / SR_NP;      // chunks per partition
+  auto owned = [&](int c) { return (c / cpp) % ns == sp; };
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int nt = wid >> 2, ct = wid & 3;          // this wave's tile in the block
   const int r0 = rb * SB, m0 = cb * SB;
-  floatx4 dr = zero4(), di = zero4();
-  double wn = 0.0;                                // |W|^2 of the staged values (rb == 0)
+  // E of the completed partitions (ns == 1) and of the current one; |W|^2 of
+  // the current partition's staged values (rb == 0)
+  floatx4 Er = zero4(), Ei = zero4(), pr = zero4(), pi = zero4();
+  double wcur = 0.0;
+  float2* const pe = reinterpret_cast<float2*>(part);   // split: [SR_NP][SB * SB] partition blocks of E
+  double* const pw2 = part + (size_t)SR_NP * SB * SB;   // split: [SR_NP] partition norms
   float2 ph[SPER], pw[SPER];
   auto fetch = [&](int c0) {
 #pragma unroll
@@ -79,58 +89,86 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
       pw[e] = (jw < N && m < K) ? W[(size_t)jw * ldw + m] : cz();
     }
   };
-  if (cbeg < cend) fetch(cbeg);
-  for (int c0 = cbeg; c0 < cend; c0 += SC) {
+  int c = 0;
+  while (c < nch && !owned(c)) ++c;
+  if (c < nch) fetch(c * SC);
+  while (c < nch) {
+    const int q = c / cpp;
 #pragma unroll
     for (int e = 0; e < SPER; ++e) {
       const int idx = tid + SNT * e;
       const int a = idx / SC, b = idx % SC;
       hs[a * SLD + b] = ph[e];
       ws[a * WLD + b] = pw[e];
-      if (rb == 0) wn += (double)cabs2(pw[e]);
+      if (rb == 0) wcur += (double)cabs2(pw[e]);
     }
     __syncthreads();
-    if (c0 + SC < cend) fetch(c0 + SC);
-    const int jc = min(SC, cend - c0);
-    // E(n, m) += sum_j H[n][j] W[j][m]
+    int cn = c + 1;
+    while (cn < nch && !owned(cn)) ++cn;
+    if (cn < nch) fetch(cn * SC);
+    const int jc = min(SC, N - c * SC);
+    // this chunk's E(n, m) = sum_j H[n][j] W[j][m], added to its partition
+    floatx4 dr = zero4(), di = zero4();
     ctile16([&](int rr, int j) { return hs[(nt * 16 + rr) * SLD + j]; },
             [&](int j, int cc) { return ws[j * WLD + ct * 16 + cc]; }, 0, (jc + 3) & ~3, dr, di);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { pr[v] += dr[v]; pi[v] += di[v]; }
+    if (cn >= nch || cn / cpp != q) {
+      // partition q is complete
+      if (ns == 1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { Er[v] += pr[v]; Ei[v] += pi[v]; }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          pe[(size_t)q * SB * SB + (nt * 16 + tile_row(v)) * SB + ct * 16 + tile_col()] =
+              make_float2(pr[v], pi[v]);
+      }
+      pr = zero4();
+      pi = zero4();
+      const double w = wave_sum(wcur);
+      if (lane == 0) wq[q][wid] = w;
+      wcur = 0.0;
+    }
     __syncthreads();
+    c = cn;
   }
-  wn = wave_sum(wn);
-  if (lane == 0) red[wid] = wn;
+  // |W|^2 per completed partition of this workgroup: its waves in order
+  const int npart = (nch + cpp - 1) / cpp;        // partitions that hold a chunk
+  floatx4 dr = zero4(), di = zero4();
   double wt = 0.0;   // ||W||^2 of the block's columns (kb == 1: all of W)
   if (ns > 1) {
-    // partial E and ||W||^2 to scratch; the last split adds them up
-    float2* const pe = reinterpret_cast<float2*>(part);   // [ns][SB * SB]
-    double* const pw = part + (size_t)ns * SB * SB;      // [ns]
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      pe[(size_t)sp * SB * SB + (nt * 16 + tile_row(v)) * SB + ct * 16 + tile_col()] = make_float2(dr[v], di[v]);
+    // the last workgroup adds every partition in order
+    if (tid < npart && tid % ns == sp) {
+      double w = 0.0;
+      for (int k = 0; k < SNW; ++k) w += wq[tid][k];
+      pw2[tid] = w;
+    }
     __syncthreads();
     if (tid == 0) {
-      double w = 0.0;
-      for (int q = 0; q < SNW; ++q) w += red[q];
-      pw[sp] = w;
       __threadfence();   // after the barrier: the workgroup's stores before the count
       last = atomicAdd(count, 1u) == (unsigned)(ns - 1);
     }
     __syncthreads();
     if (!last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int q = 0; q < npart; ++q) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const size_t o = (nt * 16 + tile_row(v)) * SB + ct * 16 + tile_col();
-      float er = 0.f, ei = 0.f;
-      for (int q = 0; q < ns; ++q) {
-        const float2 x = pe[(size_t)q * SB * SB + o];
-        er += x.x;
-        ei += x.y;
+      for (int v = 0; v < 4; ++v) {
+        const float2 x = pe[(size_t)q * SB * SB + (nt * 16 + tile_row(v)) * SB + ct * 16 + tile_col()];
+        dr[v] += x.x;
+        di[v] += x.y;
       }
-      dr[v] = er;
-      di[v] = ei;
+      wt += pw2[q];
     }
-    for (int q = 0; q < ns; ++q) wt += pw[q];
+  } else {
+    dr = Er;
+    di = Ei;
+    for (int q = 0; q < npart; ++q) {
+      double w = 0.0;
+      for (int k = 0; k < SNW; ++k) w += wq[q][k];
+      wt += w;
+    }
   }
   // the block's signal and interference shares of each row, over its columns
 #pragma unroll
@@ -150,8 +188,6 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
   if (kb == 1) {
     // one workgroup owns the track: the rates straight from its shares
     if (tid < K) {
-      if (ns == 1)
-        for (int q = 0; q < SNW; ++q) wt += red[q];
       const double s2 = (wt > 0.0) ? jb.P / wt : 0.0;   // |scale|^2
       const double sig = ((rs[0][tid] + rs[1][tid]) + rs[2][tid]) + rs[3][tid];
       const double intf = ((rf[0][tid] + rf[1][tid]) + rf[2][tid]) + rf[3][tid];
@@ -170,11 +206,7 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
     }
     double* const wnorm = part + (size_t)2 * K * kb;
     if (wid == 0) {
-      if (tid == 0 && rb == 0) {
-        double w = 0.0;
-        for (int q = 0; q < SNW; ++q) w += red[q];
-        wnorm[cb] = w;
-      }
+      if (tid == 0 && rb == 0) wnorm[cb] = wt;
       __threadfence();   // the wave's stores before the block counts itself done
       if (tid == 0) last = atomicAdd(count, 1u) == (unsigned)(kb * kb - 1);
     }
@@ -182,8 +214,9 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
     if (!last) return;
     // the track's last block: every share is visible
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    for (int c = 0; c < kb; ++c) wt += wnorm[c];
-    const double s2 = (wt > 0.0) ? jb.P / wt : 0.0;
+    double wtot = 0.0;
+    for (int c = 0; c < kb; ++c) wtot += wnorm[c];
+    const double s2 = (wtot > 0.0) ? jb.P / wtot : 0.0;
     for (int n = tid; n < K; n += SNT) {
       double sig = 0.0, intf = 0.0;
       for (int c = 0; c < kb; ++c) {
@@ -215,15 +248,17 @@ size_t sum_rate_scratch_doubles(int K) {
   return (size_t)2 * K * kb + kb;
 }
 
-size_t sum_rate_split_scratch_doubles() { return (size_t)SR_SPLIT_MAX * SB * SB + SR_SPLIT_MAX; }
+size_t sum_rate_split_scratch_doubles() { return (size_t)SR_NP * SB * SB + SR_NP; }
 
 int sum_rate_splits(int K, int N) {
   if (sr_blocks(K) > 1) return 1;
-  return std::max(1, std::min(SR_SPLIT_MAX, (N + SC - 1) / SC));
+  return std::max(1, std::min(SR_NP, (N + SC - 1) / SC));
 }
 
 void launch_sum_rate(const RateJob& one, const RateJob* many, int n, int maxK, int ns, int* err, hipStream_t s) {
   const int kb = sr_blocks(maxK);
+  if (many || kb > 1) ns = 1;
+  ns = std::max(1, std::min(SR_NP, ns));
   if (many) k_sum_rate<true><<<dim3(kb * kb, n), SNT, 0, s>>>(one, many, 1, err);
   else k_sum_rate<false><<<kb * kb * ns, SNT, 0, s>>>(one, many, ns, err);
 }

@@ -12,6 +12,7 @@ from typing import Optional, Tuple
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "librzf.so")
+TUNING_PATH = os.path.join(PKG, "tuning.json")
 
 RZF_OK = 0
 RZF_E_INVALID = 1
@@ -86,6 +87,11 @@ class GraphRate(ctypes.Structure):
     _fields_ = [("P", ctypes.c_double), ("sigma2", ctypes.c_double), ("sums", ctypes.c_void_p)]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int), ("N", ctypes.c_int), ("precoder_rows", ctypes.c_int),
+                ("batch_precoder_rows", ctypes.c_int), ("rate_splits", ctypes.c_int)]
+
+
 class ProfileEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("count", ctypes.c_int), ("total_ms", ctypes.c_double)]
 
@@ -139,6 +145,7 @@ _SIGS = {
     "rzf_graph_full": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(FullItem),
                                       ctypes.POINTER(GraphRate), ctypes.POINTER(ctypes.c_void_p)]),
     "rzf_graph_launch": (ctypes.c_int, [ctypes.c_void_p]),
+    "rzf_tune_table": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(TuneEntry)]),
     "rzf_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "rzf_track_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "rzf_server_params_default": (ctypes.c_int, [ctypes.POINTER(ServerParams)]),
@@ -223,6 +230,13 @@ def full_noalloc(H, alpha: float, P: float, W, err=None, stream=None):
                                       float(alpha), float(P), ctypes.c_void_p(wp), ldw, ep), "rzf_full_noalloc")
 
 
+def load_tuning(path: str = TUNING_PATH):
+    """The entries of an autotuner table (JSON)."""
+    import json
+    with open(path) as f:
+        return json.load(f)["entries"]
+
+
 def track_bytes(K: int, N: int) -> int:
     return int(lib().rzf_track_bytes(K, N))
 
@@ -248,8 +262,11 @@ def _mat_args(H, dtype_name="complex64"):
 class Context:
     """rzf_ctx: one device, one stream, one arena (a torch uint8 tensor)."""
 
-    def __init__(self, device: int = 0, arena_bytes: int = 64 << 20, stream=None, arena=None):
-        """arena: a caller's uint8 device tensor of arena_bytes (default: a new one)."""
+    def __init__(self, device: int = 0, arena_bytes: int = 64 << 20, stream=None, arena=None,
+                 tuning: Optional[str] = TUNING_PATH):
+        """arena: a caller's uint8 device tensor of arena_bytes (default: a new one).
+        tuning: a launch-shape table written by the autotuner (default: the
+        package's tuning.json when present; None: the library defaults)."""
         import torch
         self.device = device
         dev = torch.device("cuda", device)
@@ -263,6 +280,8 @@ class Context:
                                     ctypes.byref(h)), "rzf_ctx_create")
         self.h = h
         self._infos = []
+        if tuning and os.path.exists(tuning):
+            self.tune_table(load_tuning(tuning))
 
     def close(self):
         if self.h:
@@ -426,6 +445,15 @@ class Context:
     def sum_rate_batch_raw(self, items, P: float, sigma2: float):
         _check(lib().rzf_sum_rate_batch(self.h, len(items), items, float(P), float(sigma2)),
                "rzf_sum_rate_batch")
+
+    def tune_table(self, entries):
+        """rzf_tune_table from dicts with K, N, precoder_rows, batch_precoder_rows, rate_splits."""
+        n = len(entries)
+        arr = (TuneEntry * max(n, 1))()
+        for i, e in enumerate(entries):
+            arr[i] = TuneEntry(int(e["K"]), int(e["N"]), int(e.get("precoder_rows", 0)),
+                               int(e.get("batch_precoder_rows", 0)), int(e.get("rate_splits", 0)))
+        _check(lib().rzf_tune_table(self.h, n, arr), "rzf_tune_table")
 
     def _graph_rate(self, rate):
         if rate is None:

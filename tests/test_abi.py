@@ -35,6 +35,21 @@ def test_graph_entry_points_check_arguments():
     assert L.rzf_graph_full(None, 1, None, None, ctypes.byref(out)) == rzf.RZF_E_INVALID
     assert L.rzf_graph_launch(None) == rzf.RZF_E_INVALID
     assert L.rzf_graph_destroy(None) == rzf.RZF_E_INVALID
+    e = rzf.TuneEntry(64, 256, 32, 64, 4)
+    assert L.rzf_tune_table(None, 1, ctypes.byref(e)) == rzf.RZF_E_INVALID
+
+
+def test_tuning_table_file_is_well_formed():
+    # the committed autotuner table: every entry in range with valid knobs
+    path = rzf.TUNING_PATH
+    if not os.path.exists(path):
+        pytest.skip("no tuning table written yet")
+    entries = rzf.load_tuning(path)
+    assert entries
+    for e in entries:
+        assert 1 <= e["K"] <= 256 and 1 <= e["N"] <= 4096
+        assert e["precoder_rows"] in (32, 64) and e["batch_precoder_rows"] in (32, 64)
+        assert 0 <= e["rate_splits"] <= 8
 
 
 def test_params_default_values():

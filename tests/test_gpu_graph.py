@@ -120,3 +120,33 @@ def test_full_graph_replays_equal_eager(ctx, sizes, precision):
             assert torch.equal(We[i], Wbuf[i]), (sizes[i], t)
         assert sums.tolist() == ref, t
     g.destroy()
+
+
+# ------------------------------------------------------------- launch tuning
+
+def test_tuning_knobs_change_no_result(ctx):
+    # the precoder's rows per workgroup and the single-track sum rate's
+    # spread over workgroups are launch choices only
+    for K, N in [(64, 256), (16, 1000), (40, 520), (96, 300)]:
+        H = walk(K, N, 0, 90)[0]
+        outs = []
+        for pb, ns in [(64, 1), (32, 4), (32, 8), (64, 2)]:
+            ctx.tune_table([{"K": K, "N": N, "precoder_rows": pb, "batch_precoder_rows": pb, "rate_splits": ns}])
+            W = torch.empty(N, K, dtype=torch.complex64, device="cuda")
+            r = torch.empty(K, dtype=torch.float32, device="cuda")
+            ctx.full(H, 0.5, 1.0, W)
+            R = ctx.sum_rate(H, W, 1.0, 0.1, r)
+            outs.append((W, r, R))
+        ctx.tune_table([])
+        for W, r, R in outs[1:]:
+            assert torch.equal(W, outs[0][0]) and torch.equal(r, outs[0][1]) and R == outs[0][2], (K, N)
+
+
+def test_tuning_table_checks_entries(ctx):
+    with pytest.raises(rzf.RzfError):
+        ctx.tune_table([{"K": 64, "N": 256, "precoder_rows": 48}])
+    with pytest.raises(rzf.RzfError):
+        ctx.tune_table([{"K": 0, "N": 256}])
+    with pytest.raises(rzf.RzfError):
+        ctx.tune_table([{"K": 64, "N": 256, "rate_splits": 9}])
+    ctx.tune_table([])

@@ -125,9 +125,9 @@ def test_full_precoder_strided(ctx):
     assert torch.all(Wb[:, K:] == 0)
 
 
-# (64, 256), (40, 300), (64, 1000), (40, 520): a lone track's antenna sum split
-# over 4, 5, 8 and 8 workgroups (the last three of the 8 splits of N = 520
-# hold no antenna)
+# (64, 256), (40, 300), (64, 1000), (40, 520): a lone track's antenna sum spread
+# over 4, 5, 8 and 8 workgroups (N = 520 has 9 chunks in 5 partitions of two:
+# three of the 8 workgroups get none)
 @pytest.mark.parametrize("K,N", [(16, 64), (64, 256), (13, 37), (1, 8), (64, 1000), (40, 300), (40, 520)])
 def test_sum_rate(ctx, K, N):
     H = _channel(K, N, 4)
