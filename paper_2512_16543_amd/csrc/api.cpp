@@ -608,7 +608,9 @@ void UpdatePlan::put(Stager& st) {
 void UpdatePlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
   const int n = (int)pj.size();
   if (!gj.empty()) {
-    timed(c, KN_GRAM, s, [&] { launch_gram(gj[0], d_gj, (int)gj.size(), maxK, s); });
+    bool fp32 = true;
+    for (const GramJob& g : gj) fp32 = fp32 && g.prec == RZF_PREC_FP32;
+    timed(c, KN_GRAM, s, [&] { launch_gram(gj[0], d_gj, (int)gj.size(), maxK, fp32, s); });
     timed(c, KN_ARSVD, s, [&] {
       if (!aj.empty()) launch_arsvd_wb(aj[0], d_aj, (int)aj.size(), err, s);
       if (!ajb.empty()) launch_arsvd_big(ajb[0], d_ajb, (int)ajb.size(), err, s);
@@ -718,7 +720,9 @@ void FullPlan::put(Stager& st) {
 
 void FullPlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
   const int n = (int)gj.size();
-  timed(c, KN_GRAM, s, [&] { launch_gram(gj[0], d_gj, n, maxK, s); });
+  bool fp32 = true;
+  for (const GramJob& g : gj) fp32 = fp32 && g.prec == RZF_PREC_FP32;
+  timed(c, KN_GRAM, s, [&] { launch_gram(gj[0], d_gj, n, maxK, fp32, s); });
   timed(c, KN_INV32, s, [&] {
     if (!vj.empty()) launch_inv32(vj[0], d_vj, (int)vj.size(), err, s);
     if (!vjb.empty()) launch_inv32_big(vjb[0], d_vjb, (int)vjb.size(), err, s);
@@ -805,7 +809,7 @@ void update_single_launch(rzf_ctx* c, rzf_track* t, const float2* Hf, int ldh, d
   } else {
     const GramJob gj{Hf, d.Hprev, d.Anew, d.dA, K, N, ldh, N, (float)t->alpha, d.prec};
     const ArsvdJob aj{t->d_desc, nullptr, tol, t->i_max};
-    timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, s); });
+    timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, false, s); });
     timed(c, KN_ARSVD, s, [&] { arsvd_single(c, aj, K, s); });
   }
   const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw, d.prec, &t->d_desc->hold};
@@ -820,7 +824,7 @@ void full_single_launch(rzf_ctx* c, int K, int N, const float2* Hf, int ldh, dou
   const GramJob gj{Hf, nullptr, c->d_fullA, nullptr, K, N, ldh, 0, (float)alpha, RZF_PREC_FP32};
   const PrecJob pj{Hf, c->d_fullAinv, Wf, c->d_fullwpart, nullptr, K, N, ldh, ldw, RZF_PREC_FP32, nullptr};
   const ScaleJob sj{Wf, c->d_fullwpart, P, K, N, ldw, precoder_blocks(N), nullptr};
-  timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, s); });
+  timed(c, KN_GRAM, s, [&] { launch_gram(gj, nullptr, 1, K, false, s); });
   const Inv32Job vj{c->d_fullA, c->d_fullAinv, K};
   timed(c, KN_INV32, s, [&] { inv32_any(vj, c->d_err, s); });
   const int pb = tune_for(c, K, N).precoder_rows;
@@ -1300,7 +1304,7 @@ rzf_status rzf_tune_table(rzf_ctx* c, int n, const rzf_tune_entry* entries) {
     const rzf_tune_entry& e = entries[i];
     if (e.K < 1 || e.K > RZF_KMAX || e.N < 1 || e.N > RZF_NMAX) return RZF_E_INVALID;
     for (int v : {e.precoder_rows, e.batch_precoder_rows})
-      if (v != 0 && v != 32 && v != 64) return RZF_E_INVALID;
+      if (v != 0 && v != 32 && v != 64 && v != 256) return RZF_E_INVALID;
     if (e.rate_splits < 0 || e.rate_splits > 8) return RZF_E_INVALID;
   }
   std::lock_guard<std::mutex> lk(c->mu);

@@ -36,7 +36,8 @@ __global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) 
   constexpr int GC = 64, GLD = GC + 4;
   __shared__ float2 st[4][16][GLD];
   float (*red)[16][64] = reinterpret_cast<float (*)[16][64]>(&st[0][0][0]);
-  const GramJob& jb = job_of<MANY>(one, many);
+  const GridPos gp = grid_pos<MANY>();
+  const GramJob& jb = job_at<MANY>(one, many, gp.item);
   const int K = jb.K, N = jb.N, ldh = jb.ldh, ldp = jb.ldp;
   const float2* __restrict__ Ht = jb.Ht;
   const float2* __restrict__ Hp = jb.Hp;
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) 
   const float alpha = jb.alpha;
   const int ktl = (K + 15) / 16;
   // lower-triangular tile index -> (bi, bj), bi >= bj
-  const int tix = blockIdx.x;
+  const int tix = gp.x;
   if (tix >= ktl * (ktl + 1) / 2) return;
   int bi = (int)((sqrtf(8.0f * tix + 1.0f) - 1.0f) * 0.5f);
   while ((bi + 1) * (bi + 2) / 2 <= tix) ++bi;
@@ -173,6 +174,145 @@ __global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) 
   }
 }
 
+// Lower 16x16 tile t of a K x K Hermitian output -> block coordinates (bi >= bj).
+__device__ __forceinline__ void lower_tile(int t, int* bi, int* bj) {
+  int i = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  *bi = i;
+  *bj = t - i * (i + 1) / 2;
+}
+
+// Batched Gram of FP32 tracks with K <= 64: one 16-wave workgroup per track,
+// which stages each chunk of 64 antennas of H_t (and H_{t-1}) once for all of
+// the track's lower tiles instead of once per tile.  A work unit (tile,
+// slice) is exactly what wave `slice` of k_gram computes for that tile
+// (antennas 16 slice .. 16 slice + 15 of every chunk, four per product step,
+// in increasing order, in its own accumulators), unit u = 4 tile + slice runs
+// on wave u mod 16, and the four slices of a tile are added in k_gram's
+// order: a track's A' and Delta A are bit-identical to k_gram's.
+template <bool DELTA>
+__global__ __launch_bounds__(1024) void k_gram_track(const GramJob* many) {
+  constexpr int GC = 64, GLD = GC + 4, KT = 64, NM = DELTA ? 2 : 1;
+  __shared__ float2 st[2][KT][GLD];   // [H_t, H_{t-1}][row][antenna of the chunk]
+  // after the last chunk: one 16 x 64 float block per wave (the tile partials)
+  float (*red)[16][64] = reinterpret_cast<float (*)[16][64]>(&st[0][0][0]);
+  const GridPos gp = xcd_grid_pos();
+  const GramJob& jb = many[gp.item];
+  const int K = jb.K, N = jb.N, ldh = jb.ldh, ldp = jb.ldp;
+  const float2* __restrict__ Ht = jb.Ht;
+  const float2* __restrict__ Hp = jb.Hp;
+  float2* __restrict__ Anew = jb.Anew;
+  float2* __restrict__ dA = jb.dA;
+  const float alpha = jb.alpha;
+  const int ktl = (K + 15) / 16;
+  const int nunit = 2 * ktl * (ktl + 1);        // 4 slices x the lower tiles
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int r = lane & 15, kq = lane >> 4;
+  floatx4 acc[3][4];                             // units wid, wid + 16, wid + 32
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[q][c] = zero4();
+  float2 pre[NM][4];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const float2* src = m == 0 ? Ht : Hp;
+      const int ld = m == 0 ? ldh : ldp;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = threadIdx.x + 1024 * e;   // 64 rows x 64 antennas
+        const int row = idx >> 6, n = c0 + (idx & 63);
+        pre[m][e] = (row < K && n < N) ? src[(size_t)row * ld + n] : cz();
+      }
+    }
+  };
+  fetch(0);
+  for (int c0 = 0; c0 < N; c0 += GC) {
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = threadIdx.x + 1024 * e;
+        st[m][idx >> 6][idx & 63] = pre[m][e];
+      }
+    __syncthreads();
+    if (c0 + GC < N) fetch(c0 + GC);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int u = wid + 16 * q;
+      if (u >= nunit) break;
+      int bi, bj;
+      lower_tile(u >> 2, &bi, &bj);
+      const int sl = u & 3;
+#pragma unroll
+      for (int k = 0; k < 16; k += 4) {
+        const int nn = sl * 16 + k + kq;
+        const float2 ti = st[0][bi * 16 + r][nn];
+        const float2 tj = st[0][bj * 16 + r][nn];
+        mac_conj(ti, tj, acc[q][0], acc[q][1]);          // H_t H_t^H
+        if (DELTA) {
+          const float2 pi = st[1][bi * 16 + r][nn];
+          const float2 pj = st[1][bj * 16 + r][nn];
+          const float2 di = csub(ti, pi), dj = csub(tj, pj);
+          mac_conj(pi, dj, acc[q][2], acc[q][3]);        // H_{t-1} dH^H
+          mac_conj(di, tj, acc[q][2], acc[q][3]);        // dH H_t^H
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // one round per unit slot q: every wave posts its unit, and the wave of a
+  // tile's slice 0 adds the four slices (waves wid .. wid + 3) in order
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (16 * q >= nunit) break;
+    const int u = wid + 16 * q;
+    if (u < nunit) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        red[wid][v][lane] = acc[q][0][v];
+        red[wid][4 + v][lane] = acc[q][1][v];
+        red[wid][8 + v][lane] = acc[q][2][v];
+        red[wid][12 + v][lane] = acc[q][3][v];
+      }
+    }
+    __syncthreads();
+    if (u < nunit && (u & 3) == 0) {
+      int bi, bj;
+      lower_tile(u >> 2, &bi, &bj);
+      const int i0 = bi * 16, j0 = bj * 16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float sm[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int w = 0; w < 4; ++w) {
+          sm[0] += red[wid + w][v][lane];
+          sm[1] += red[wid + w][4 + v][lane];
+          sm[2] += red[wid + w][8 + v][lane];
+          sm[3] += red[wid + w][12 + v][lane];
+        }
+        const int i = i0 + tile_row(v), j = j0 + tile_col();
+        if (i >= K || j >= K) continue;
+        if (bi == bj && i < j) continue;   // the diagonal tile is mirrored from below
+        float2 a = make_float2(sm[0], sm[1]);
+        float2 g = make_float2(sm[2], sm[3]);
+        if (i == j) {
+          a = make_float2(a.x + alpha, 0.f);
+          g.y = 0.f;
+        }
+        Anew[(size_t)i * K + j] = a;
+        if (i != j) Anew[(size_t)j * K + i] = cconj(a);
+        if (DELTA) {
+          dA[(size_t)i * K + j] = g;
+          if (i != j) dA[(size_t)j * K + i] = cconj(g);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // FP64 Gram for the exact (re-)inversions: one thread per lower element.
 template <bool MANY>
 __global__ __launch_bounds__(256) void k_gram64(Gram64Job one, const Gram64Job* many) {
@@ -206,7 +346,12 @@ __global__ __launch_bounds__(256) void k_gram64(Gram64Job one, const Gram64Job* 
 
 }  // namespace
 
-void launch_gram(const GramJob& one, const GramJob* many, int n, int maxK, hipStream_t s) {
+void launch_gram(const GramJob& one, const GramJob* many, int n, int maxK, bool per_track, hipStream_t s) {
+  if (many && per_track && maxK <= 64) {
+    if (one.Hp != nullptr) k_gram_track<true><<<dim3(1, n), 1024, 0, s>>>(many);
+    else k_gram_track<false><<<dim3(1, n), 1024, 0, s>>>(many);
+    return;
+  }
   const int kt = (maxK + 15) / 16;
   const dim3 grid(kt * (kt + 1) / 2, many ? n : 1);
   const bool delta = one.Hp != nullptr;   // a batch passes its mode in `one`

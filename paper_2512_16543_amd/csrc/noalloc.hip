@@ -66,7 +66,7 @@ extern "C" rzf_status rzf_full_noalloc(void* hip_stream, int K, int N, const rzf
   const Inv32Job vj{A, Ainv, K};
   const PrecJob pj{Hf, Ainv, Wf, wpart, nullptr, K, N, ldh, ldw, RZF_PREC_FP32, nullptr};
   const ScaleJob sj{Wf, wpart, P, K, N, ldw, precoder_blocks(N), nullptr};
-  launch_gram(gj, nullptr, 1, K, s);
+  launch_gram(gj, nullptr, 1, K, false, s);
   if (K > KS) launch_inv32_big(vj, nullptr, 1, err, s);
   else launch_inv32(vj, nullptr, 1, err, s);
   launch_precoder(pj, nullptr, 1, N, K, 64, s);

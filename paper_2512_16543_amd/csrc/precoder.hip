@@ -2,7 +2,7 @@
 // eq. (5)), where X is the stored inverse of the Gram matrix.
 //
 // W is N x K (row-major).  A workgroup of 16 wavefronts owns PB rows of W (PB
-// antennas, 32 or 64: a launch choice) of one track and computes their
+// antennas, 32 or 64, or 256 when every track has K <= 64: a launch choice) of one track and computes their
 // 16x16 tiles (PB/16 x ceil(K/16) of them, wave w taking tiles w, w + 16, ...)
 // on the FP32 matrix cores.  The length-K reduction runs over chunks of 32
 // users: the chunk's 32 x PB block of H and its 32 x K rows of X are staged in
@@ -30,21 +30,23 @@ constexpr int PG = 32;          // rows of W per partial sum of |w|^2
 constexpr int PIC = 32;         // users per reduction chunk
 constexpr int PNT = 1024;       // threads per workgroup
 constexpr int PNW = PNT / 64;
-constexpr int XPER = (PIC * KM + PNT - 1) / PNT;  // X values a thread stages per chunk, at most
 
 // Dynamic LDS of a launch with PB rows per workgroup for tracks up to maxK
 // users: the H chunk (row stride PB + 4), then the X chunk (row stride maxK + 4).
 size_t prec_lds_bytes(int pb, int maxK) { return sizeof(float2) * (size_t)PIC * (pb + 4 + maxK + 4); }
 
-template <bool MANY, int PB>
+// KMX: the largest K of the launch's tracks the kernel is built for (64 or KM).
+template <bool MANY, int PB, int KMX>
 __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* many, int xld) {
   constexpr int HLD = PB + 4;                 // LDS row stride of the staged H chunk (float2)
   constexpr int HPER = PIC * PB / PNT;        // H values a thread stages per chunk
+  constexpr int XPER = (PIC * KMX + PNT - 1) / PNT;  // X values a thread stages per chunk, at most
   extern __shared__ float2 dyn[];
   float2* hs = dyn;                       // [PIC][HLD]: H[i0 + ii][n0 + c] at hs[ii * HLD + c]
   float2* xs = dyn + PIC * HLD;           // [PIC][xld]: X[i0 + ii][k] at xs[ii * xld + k]
-  __shared__ double tsum[PB / 16][KM / 16];   // |w|^2 of each 16x16 tile
-  const PrecJob& jb = job_of<MANY>(one, many);
+  __shared__ double tsum[PB / 16][KMX / 16];  // |w|^2 of each 16x16 tile
+  const GridPos gp = grid_pos<MANY>();
+  const PrecJob& jb = job_at<MANY>(one, many, gp.item);
   const int K = jb.K, N = jb.N, ldh = jb.ldh, ldw = jb.ldw;
   const float2* __restrict__ H = jb.H;
   const float2* __restrict__ X = jb.X;
@@ -53,11 +55,11 @@ __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* ma
   // a step that met a non-finite snapshot keeps the track's previous one
   float2* __restrict__ Hcopy = (jb.hold && *jb.hold) ? nullptr : jb.Hcopy;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int n0 = blockIdx.x * PB;
+  const int n0 = gp.x * PB;
   if (n0 >= N) return;
   const int kt = (K + 15) / 16;
   const int ntile = (PB / 16) * kt;
-  constexpr int TPW = (PB / 16) * (KM / 16) / PNW;   // tiles per wave, at most
+  constexpr int TPW = (PB / 16) * (KMX / 16) / PNW;  // tiles per wave, at most
   floatx4 tre[TPW], tim[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) { tre[q] = zero4(); tim[q] = zero4(); }
@@ -224,16 +226,17 @@ void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, h
 
 int precoder_scratch(int N) { return precoder_blocks(N); }
 
-template <int PB>
+template <int PB, int KMX>
 void launch_precoder_pb(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, hipStream_t s) {
   const dim3 grid((maxN + PB - 1) / PB, many ? n : 1);
   const size_t lds = prec_lds_bytes(PB, maxK);
   const int xld = maxK + 4;
-  if (many) k_precoder<true, PB><<<grid, PNT, lds, s>>>(one, many, xld);
-  else k_precoder<false, PB><<<grid, PNT, lds, s>>>(one, many, xld);
+  if (many) k_precoder<true, PB, KMX><<<grid, PNT, lds, s>>>(one, many, xld);
+  else k_precoder<false, PB, KMX><<<grid, PNT, lds, s>>>(one, many, xld);
 }
 
 void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, int pb, hipStream_t s) {
-  if (pb == 32) launch_precoder_pb<32>(one, many, n, maxN, maxK, s);
-  else launch_precoder_pb<64>(one, many, n, maxN, maxK, s);
+  if (pb == 256 && maxK <= 64) launch_precoder_pb<256, 64>(one, many, n, maxN, maxK, s);
+  else if (pb == 32) launch_precoder_pb<32, KM>(one, many, n, maxN, maxK, s);
+  else launch_precoder_pb<64, KM>(one, many, n, maxN, maxK, s);
 }

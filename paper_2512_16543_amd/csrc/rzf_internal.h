@@ -149,10 +149,38 @@ __device__ __forceinline__ const J& job_of(const J& one, const J* many) {
   if constexpr (MANY) return many[blockIdx.y]; else return one;
 }
 
+// Position (x, item) of this workgroup in a batched launch of gridDim.x
+// workgroups per item, relabelled so that one item's workgroups run on one
+// XCD: the hardware hands consecutive workgroups to the 8 XCDs in turn, each
+// with its own L2, so linear id L runs on XCD L mod 8, and the logical id
+// (L mod 8) * share + L / 8 makes consecutive logical ids (an item's
+// workgroups, which read the same operands) share that XCD's L2.  A bijection
+// of the grid whatever the dispatch order, so it moves only time.
+struct GridPos { int x, item; };
+__device__ __forceinline__ GridPos xcd_grid_pos() {
+  constexpr int NX = 8;
+  const int gx = gridDim.x, total = gridDim.x * gridDim.y;
+  const int L = blockIdx.y * gx + blockIdx.x;
+  const int per = total / NX, rem = total - per * NX;
+  const int xcd = L % NX, slot = L / NX;
+  const int logical = xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+  return {logical % gx, logical / gx};
+}
+template <bool MANY>
+__device__ __forceinline__ GridPos grid_pos() {
+  if constexpr (MANY) return xcd_grid_pos(); else return GridPos{(int)blockIdx.x, 0};
+}
+template <bool MANY, class J>
+__device__ __forceinline__ const J& job_at(const J& one, const J* many, int item) {
+  if constexpr (MANY) return many[item]; else return one;
+}
+
 // Launchers (defined next to their kernels).  `many` == nullptr launches the
 // single job `one`; otherwise `n` jobs read from device memory, with the grid
 // sized by the largest job (`maxK`, `maxN`).
-void launch_gram(const GramJob& one, const GramJob* many, int n, int maxK, hipStream_t s);
+// per_track: a batch of FP32 jobs with K <= 64 may run one workgroup per
+// track (same results as the tile kernel); any other launch ignores it.
+void launch_gram(const GramJob& one, const GramJob* many, int n, int maxK, bool per_track, hipStream_t s);
 void launch_gram64(const Gram64Job& one, const Gram64Job* many, int n, int maxK, hipStream_t s);
 void launch_inv64(const Inv64Job& one, const Inv64Job* many, int n, int* err, hipStream_t s);
 void launch_inv32(const Inv32Job& one, const Inv32Job* many, int n, int* err, hipStream_t s);
@@ -160,7 +188,7 @@ void launch_inv32(const Inv32Job& one, const Inv32Job* many, int n, int* err, hi
 // wpart (the workgroups' partial sums).
 int precoder_blocks(int N);
 int precoder_scratch(int N);
-// pb: rows of W per workgroup (32 or 64; any other value takes 64).
+// pb: rows of W per workgroup (32 or 64, or 256 with maxK <= 64; any other value takes 64).
 void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, int pb, hipStream_t s);
 // W <- W sqrt(P / ||W||_F^2) from the precoder's partial sums (maxNK: the
 // largest N K of the launch).

@@ -55,15 +55,16 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
   __shared__ double red[SNW];
   __shared__ double wq[SR_NP][SNW];   // per partition and wave: |W|^2
   __shared__ int last;
-  const RateJob& jb = job_of<MANY>(one, many);
+  const GridPos gp = grid_pos<MANY>();
+  const RateJob& jb = job_at<MANY>(one, many, gp.item);
   const int K = jb.K, N = jb.N, ldh = jb.ldh, ldw = jb.ldw;
   const float2* __restrict__ H = jb.H;
   const float2* __restrict__ W = jb.W;
   unsigned* const count = jb.count;
   double* __restrict__ part = jb.part;
   const int kb = sr_blocks(K);
-  if ((int)blockIdx.x >= kb * kb * ns) return;
-  const int blk = blockIdx.x / ns, sp = blockIdx.x - blk * ns;   // ns > 1 only with kb == 1
+  if (gp.x >= kb * kb * ns) return;
+  const int blk = gp.x / ns, sp = gp.x - blk * ns;   // ns > 1 only with kb == 1
   const int rb = blk / kb, cb = blk - rb * kb;
   const int nch = (N + SC - 1) / SC;
   const int cpp = (nch + SR_NP - 1) / SR_NP;      // chunks per partition

@@ -19,7 +19,7 @@ import time
 
 GRID_K = (8, 16, 32, 64, 128, 256)
 GRID_N = (64, 128, 256, 512, 1024, 2048, 4096)
-ROWS = (32, 64)
+ROWS = (32, 64, 256)
 SPLITS = (1, 2, 4, 8)
 
 
@@ -42,14 +42,17 @@ def tune_size(ctx, K, N, reps, batch):
     import torch
     from paper_2512_16543_amd import workload as wl
     H = torch.from_numpy(wl.random_channel(K, N, 7).astype(np.complex64)).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(K * 10007 + N)
     W = torch.empty(N, K, dtype=torch.complex64, device="cuda")
     rates = torch.empty(K, dtype=torch.float32, device="cuda")
     alpha = K / 10.0
-    Hb = [torch.from_numpy(wl.random_channel(K, N, 100 + b).astype(np.complex64)).cuda() for b in range(batch)]
+    # the batch's channels drawn on the device (i.i.d. CN(0, 1/N), as random_channel)
+    Hb = [torch.randn(K, N, dtype=torch.complex64, device="cuda", generator=g) / N ** 0.5 for _ in range(batch)]
     Wb = [torch.empty(N, K, dtype=torch.complex64, device="cuda") for _ in range(batch)]
     items = ctx.full_items(Hb, [alpha] * batch, 1.0, Wb)
     meas = {"precoder_us": {}, "batch_precoder_us": {}, "sum_rate_us": {}}
-    for pb in ROWS:
+    for pb in (ROWS if K <= 64 else tuple(v for v in ROWS if v != 256)):
         ctx.tune_table([{"K": K, "N": N, "precoder_rows": pb, "batch_precoder_rows": pb}])
         meas["precoder_us"][pb] = kernel_us(ctx, lambda: ctx.full(H, alpha, 1.0, W), reps, "precoder")
         meas["batch_precoder_us"][pb] = kernel_us(ctx, lambda: ctx.full_batch_raw(items), max(2, reps // 8),
@@ -62,6 +65,8 @@ def tune_size(ctx, K, N, reps, batch):
         meas["sum_rate_us"][ns] = kernel_us(ctx, lambda: ctx.sum_rate_async(H, W, 1.0, 0.1, rates), reps,
                                             "sum_rate")
     ctx.tune_table([])
+    del Hb, Wb
+    torch.cuda.empty_cache()
     best = lambda d: min(d, key=lambda k: (d[k], k))
     entry = {"K": K, "N": N, "precoder_rows": best(meas["precoder_us"]),
              "batch_precoder_rows": best(meas["batch_precoder_us"]),
@@ -74,13 +79,13 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--out", default="tuning.json")
     ap.add_argument("--reps", type=int, default=40)
-    ap.add_argument("--batch", type=int, default=128, help="tracks of the batched precoder measurement")
+    ap.add_argument("--batch", type=int, default=512, help="tracks of the batched precoder measurement")
     ap.add_argument("--K", type=int, nargs="*", default=list(GRID_K))
     ap.add_argument("--N", type=int, nargs="*", default=list(GRID_N))
     a = ap.parse_args(argv)
     import torch
     from paper_2512_16543_amd import rzf
-    ctx = rzf.Context(0, 512 << 20, tuning=None)
+    ctx = rzf.Context(0, 1 << 30, tuning=None)
     entries = []
     t0 = time.time()
     for K in a.K:

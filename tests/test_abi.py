@@ -48,7 +48,7 @@ def test_tuning_table_file_is_well_formed():
     assert entries
     for e in entries:
         assert 1 <= e["K"] <= 256 and 1 <= e["N"] <= 4096
-        assert e["precoder_rows"] in (32, 64) and e["batch_precoder_rows"] in (32, 64)
+        assert e["precoder_rows"] in (32, 64, 256) and e["batch_precoder_rows"] in (32, 64, 256)
         assert 0 <= e["rate_splits"] <= 8
 
 

@@ -124,13 +124,30 @@ def test_full_graph_replays_equal_eager(ctx, sizes, precision):
 
 # ------------------------------------------------------------- launch tuning
 
+def test_batched_precoder_rows_change_no_result(ctx):
+    # a batch of K <= 64 tracks with 32, 64 and 256 precoder rows per workgroup
+    sizes = [(64, 256), (16, 1000), (40, 520), (1, 8)]
+    Hs = [walk(K, N, 0, 95 + i)[0] for i, (K, N) in enumerate(sizes)]
+    outs = []
+    for pb in (32, 64, 256):
+        ctx.tune_table([{"K": K, "N": N, "batch_precoder_rows": pb} for K, N in sizes])
+        Ws = [torch.empty(N, K, dtype=torch.complex64, device="cuda") for K, N in sizes]
+        ctx.full_batch(Hs, [0.4] * len(sizes), 1.0, Ws)
+        ctx.sync()
+        outs.append(Ws)
+    ctx.tune_table([])
+    for Ws in outs[1:]:
+        for a, b in zip(Ws, outs[0]):
+            assert torch.equal(a, b)
+
+
 def test_tuning_knobs_change_no_result(ctx):
     # the precoder's rows per workgroup and the single-track sum rate's
     # spread over workgroups are launch choices only
     for K, N in [(64, 256), (16, 1000), (40, 520), (96, 300)]:
         H = walk(K, N, 0, 90)[0]
         outs = []
-        for pb, ns in [(64, 1), (32, 4), (32, 8), (64, 2)]:
+        for pb, ns in [(64, 1), (32, 4), (256, 8), (64, 2)]:
             ctx.tune_table([{"K": K, "N": N, "precoder_rows": pb, "batch_precoder_rows": pb, "rate_splits": ns}])
             W = torch.empty(N, K, dtype=torch.complex64, device="cuda")
             r = torch.empty(K, dtype=torch.float32, device="cuda")
