@@ -233,6 +233,46 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0, lat, Rs
 
+    # two streams of default priority: the updates on one, each step's sum rate
+    # on the other, so that step t's sum rate runs beside step t+1's update
+    s_main, s_rate = torch.cuda.Stream(dev), torch.cuda.Stream(dev)
+    pctx = rzf.Context(0, 64 << 20, stream=s_main)
+    rctx = rzf.Context(0, 64 << 20, stream=s_rate)
+
+    def run_pipelined(H, steps, kind, track_id=0):
+        """The eager step with its sum rate on a second stream: W alternates
+        between two buffers; step t's sum rate waits for step t's update, and
+        step t+2's update waits for step t's sum rate (the buffer's reuse)."""
+        Wp = [torch.empty_like(W) for _ in range(2)]
+        rp = [torch.empty_like(rates) for _ in range(2)]
+        sums = torch.zeros(steps + 1, dtype=torch.float64, device=dev)
+        e_upd = [torch.cuda.Event() for _ in range(2)]
+        e_rate = [torch.cuda.Event() for _ in range(2)]
+        rit = [rctx.rate_items([H[t]], [Wp[t % 2]], [rp[t % 2]], sums[t:t + 1]) for t in range(steps + 1)]
+        tr = pctx.init(H[0], cfg.alpha, params(track_id)) if kind == "wb" else None
+        pctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(1, steps + 1):
+            b = t % 2
+            if t > 2:
+                s_main.wait_event(e_rate[b])
+            if kind == "wb":
+                tr.update(H[t], eta, Wp[b], want_info=False)
+            else:
+                pctx.full(H[t], cfg.alpha, cfg.P, Wp[b])
+            e_upd[b].record(s_main)
+            s_rate.wait_event(e_upd[b])
+            rctx.sum_rate_batch_raw(rit[t], cfg.P, cfg.sigma2)
+            e_rate[b].record(s_rate)
+        pctx.sync()
+        rctx.sync()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if tr is not None:
+            tr.destroy()
+        return el, sums[1:].cpu().numpy()
+
     def run_graph(H, steps, kind, track_id=0, per_step_sync=False):
         """The same step captured once (rzf_graph_update / rzf_graph_full,
         the sum rate inside the graph): each step copies H_t into the graph's
@@ -271,16 +311,21 @@ def main():
     run_full(Hw, W_steps)
     run_graph(Hw, W_steps, "wb", 1)
     run_graph(Hw, W_steps, "full")
+    run_pipelined(Hw, W_steps, "wb", 1)
+    run_pipelined(Hw, W_steps, "full")
     print(f"[bench] warmup done ({W_steps} steps)", file=sys.stderr, flush=True)
 
-    # timed region: exactly K steps of the WB-arSVD path (update + sum rate)
-    # through the eager calls (the headline: with steps queued back to back
-    # the GPU is the bound), then the same steps as captured-graph launches
+    # timed region: exactly K steps of the WB-arSVD path (update + sum rate),
+    # each step's sum rate on a second stream (the headline), then the same
+    # steps on one stream, and as captured-graph launches
     torch.cuda.synchronize()
-    wb_s, _, _, _ = run_wb(Hs, K_steps, 0)
+    wb_s, R_pipe = run_pipelined(Hs, K_steps, "wb")
     print(f"[bench] wb timed: {wb_s:.3f}s", file=sys.stderr, flush=True)
-    full_s, _, _ = run_full(Hs, K_steps)
+    full_s, _ = run_pipelined(Hs, K_steps, "full")
     print(f"[bench] full timed: {full_s:.3f}s", file=sys.stderr, flush=True)
+    wb_1, _, _, _ = run_wb(Hs, K_steps, 0)
+    full_1, _, _ = run_full(Hs, K_steps)
+    print(f"[bench] one stream: wb {wb_1:.3f}s full {full_1:.3f}s", file=sys.stderr, flush=True)
     wb_g, _, _ = run_graph(Hs, K_steps, "wb")
     full_g, _, _ = run_graph(Hs, K_steps, "full")
     print(f"[bench] graph: wb {wb_g:.3f}s full {full_g:.3f}s", file=sys.stderr, flush=True)
@@ -305,13 +350,17 @@ def main():
                          f"k_init={cfg.k_init}, p={cfg.p}, {a.policy} k_init policy"
                          f"{', early fallback' if a.early_fallback else ''}"
                          f"{', error feedback' if a.error_feedback else ''}; "
-                         f"step = update + sum rate, batch of 1 track"),
+                         f"step = update + sum rate, batch of 1 track; the sum rate of step t on a "
+                         f"second stream beside the update of step t+1"),
             "K": K, "N": N, "eta": eta, "batch_tracks": 1, "reset_period": cfg.reset_period,
             "switch_ratio": switch_ratio,
         },
         "full_inverse": {"value": K_steps / full_s, "unit": "updates/s",
                          "ms_per_step": 1e3 * full_s / K_steps},
         "speedup_vs_full_inverse": full_s / wb_s,
+        "one_stream": {"wb": {"value": K_steps / wb_1, "ms_per_step": 1e3 * wb_1 / K_steps},
+                       "full": {"value": K_steps / full_1, "ms_per_step": 1e3 * full_1 / K_steps},
+                       "note": "the same steps with update and sum rate on one stream"},
         "graph": {"wb": {"value": K_steps / wb_g, "ms_per_step": 1e3 * wb_g / K_steps},
                   "full": {"value": K_steps / full_g, "ms_per_step": 1e3 * full_g / K_steps},
                   "note": "the same steps as one captured-graph launch each (rzf_graph_update / "
@@ -333,6 +382,7 @@ def main():
                              "note": "per step, host submit to sum rate on the host, one step in flight; "
                                      "wb/full: captured graph (input copy included), eager_*: the calls"}
         out["graph_sum_rate_equal"] = bool(np.array_equal(np.array(R_wbg), np.array(R_wb)))
+        out["two_stream_sum_rate_equal"] = bool(np.array_equal(np.array(R_pipe), np.array(R_wb)))
         paths = {}
         for i in infos:
             paths[str(i["path"])] = paths.get(str(i["path"]), 0) + 1
@@ -407,6 +457,8 @@ def main():
         out["eta_sweep"] = eta_sweep(ctx, cfg, Hs, min(K_steps, a.sweep_steps), params, W, rates)
         print(f"[bench] eta sweep done", file=sys.stderr, flush=True)
     ctx.close()
+    pctx.close()
+    rctx.close()
     print(json.dumps(out), flush=True)
     return 0
 

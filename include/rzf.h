@@ -286,8 +286,9 @@ rzf_status rzf_sum_rate_batch(rzf_ctx* ctx, int n, const rzf_rate_item* items, d
  * rounded by fixed partitions however they are spread over workgroups.
  *  - precoder_rows: rows of W per precoder workgroup of a single-track
  *    launch, 32, 64 or 256 (256 only for K <= 64, else 64; 0 = default 64);
- *    batch_precoder_rows: the same for a batched launch, which takes the
- *    entry of its largest (K, N).
+ *    batch_precoder_rows: the same for a batched launch of 128 tracks or
+ *    more, which takes the entry of its largest (K, N) (smaller batches take
+ *    that entry's precoder_rows).
  *  - rate_splits: workgroups over which a single track's sum rate (K <= 64)
  *    spreads its antenna sum, 1..8 (0 = default: one per 64 antennas, at
  *    most 8).  Batched sum rates use one workgroup per track.

@@ -27,6 +27,12 @@ static_assert(sizeof(KERNEL_NAMES) / sizeof(KERNEL_NAMES[0]) == KN_COUNT, "one n
 
 namespace {
 
+// Batches from these sizes on take the batch launch shapes: a Gram workgroup
+// per track (which needs the batch to fill the CUs) and the batch entry of the
+// precoder's rows; smaller ones the single-track shapes.
+constexpr int GRAM_TRACK_MIN = 256;
+constexpr int PREC_BATCH_MIN = 128;
+
 size_t sr_single_doubles() { return std::max(sum_rate_scratch_doubles(KM), sum_rate_split_scratch_doubles()); }
 
 size_t scratch_bytes() {
@@ -608,7 +614,7 @@ void UpdatePlan::put(Stager& st) {
 void UpdatePlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
   const int n = (int)pj.size();
   if (!gj.empty()) {
-    bool fp32 = true;
+    bool fp32 = (int)gj.size() >= GRAM_TRACK_MIN;
     for (const GramJob& g : gj) fp32 = fp32 && g.prec == RZF_PREC_FP32;
     timed(c, KN_GRAM, s, [&] { launch_gram(gj[0], d_gj, (int)gj.size(), maxK, fp32, s); });
     timed(c, KN_ARSVD, s, [&] {
@@ -623,7 +629,8 @@ void UpdatePlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
       if (!i64b.empty()) launch_inv64_big(i64b[0], d_i64b, (int)i64b.size(), err, s);
     });
   }
-  const int pb = tune_for(c, maxK, maxN).batch_precoder_rows;
+  const rzf_tune_entry te = tune_for(c, maxK, maxN);
+  const int pb = (int)pj.size() >= PREC_BATCH_MIN ? te.batch_precoder_rows : te.precoder_rows;
   timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, pb, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
 }
@@ -720,14 +727,15 @@ void FullPlan::put(Stager& st) {
 
 void FullPlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
   const int n = (int)gj.size();
-  bool fp32 = true;
+  bool fp32 = n >= GRAM_TRACK_MIN;
   for (const GramJob& g : gj) fp32 = fp32 && g.prec == RZF_PREC_FP32;
   timed(c, KN_GRAM, s, [&] { launch_gram(gj[0], d_gj, n, maxK, fp32, s); });
   timed(c, KN_INV32, s, [&] {
     if (!vj.empty()) launch_inv32(vj[0], d_vj, (int)vj.size(), err, s);
     if (!vjb.empty()) launch_inv32_big(vjb[0], d_vjb, (int)vjb.size(), err, s);
   });
-  const int pb = tune_for(c, maxK, maxN).batch_precoder_rows;
+  const rzf_tune_entry te = tune_for(c, maxK, maxN);
+  const int pb = (int)pj.size() >= PREC_BATCH_MIN ? te.batch_precoder_rows : te.precoder_rows;
   timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, pb, s); });
   timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
 }

@@ -93,6 +93,10 @@ constexpr double JACOBI_QSTOP = 1e-3;
 // pivot leaves nothing of X = C^-1 M that those entries determine; the step
 // then inverts A' directly (path FULL_SINGULAR)
 constexpr double SING_TOL = 0x1.0p-14;
+// An iteration whose d leading singular values of Delta A fall short of the
+// energy target by at least this relative margin cannot meet it (below): far
+// above the FP32 rounding of its ||Z||_F^2 and of those sigma_j^2 (~1e-6).
+constexpr double KYFAN_MARGIN = 1e-4;
 
 
 struct Shared {
@@ -113,6 +117,11 @@ struct Shared {
   double cap;
   float bsc[KS];                 // 1 / sigma_j of a full-width SVD (its basis columns)
   int bok;                       // that SVD's columns can all be normalised
+  // one-launch form, full-width iteration computed first: its sigma_j^2 and
+  // order, and the energies of its leading columns (topk[d] = the d largest)
+  double s2k[KS];
+  int ordk[KS];
+  double topk[KS + 1];
 };
 
 // Householder vector of column c (rows >= c) of the column-major matrix `a`
@@ -904,9 +913,79 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       load_dA();
       dA_in = true;
     }
+    // One-launch form, when the track's last step was decided at d = K (as
+    // Alg. 1 at a high eta usually is): the full-width iteration first.  Its
+    // SVD is the SVD of Delta A (its Q is unitary), and for any d orthonormal
+    // columns Q_i, ||Q_i^H Delta A||_F^2 <= sigma_1^2 + ... + sigma_d^2 (Ky Fan).
+    // So an earlier iteration whose d leading sigma_j^2 miss the target cannot
+    // meet it: it is skipped, which leaves Alg. 1's outcome as it is (the
+    // first iteration that meets the target decides, and its own Q and Z give
+    // the step).  The others run in order as before; the full-width results
+    // are kept aside (Z in pm/tm) for when none of them meets the target.
+    bool pre = false;
+    int rk = 0, sweeps_k = 0, rounds_k = 0;
+    double capk = 0.0;
+    if constexpr (PH == 0) {
+      pre = kfull > 1 && kfull <= i_max && warm_ok && td->spec_hint == kfull && !td->early_fallback;
+      if (pre) {
+        const double totk = sketch_iteration(kfull, K);
+        if (totk >= Et) {
+          c_mark = clock64();
+          jacobi_svd(sm, K, K, &sweeps_k, &rounds_k);
+          t_jac += clock64() - c_mark; c_mark = clock64();
+          pick_rank(sm, K, K, Et, &rk, &capk, o_sig2);
+          float2* const zs = sm.pm;   // pm and tm hold K x K
+          for (int e = tid; e < K * K; e += NTH) {
+            const int j = e / K, i = e - j * K;
+            zs[e] = b2[j * LDK + i];
+          }
+          if (tid < K) {
+            sm.s2k[tid] = sm.s2[tid];
+            sm.ordk[tid] = sm.order[tid];
+          }
+          if (tid == 0) {
+            double c = 0.0;
+            sm.topk[0] = 0.0;
+            for (int j = 0; j < K; ++j) {
+              c += sm.s2[sm.order[j]];
+              sm.topk[j + 1] = c;
+            }
+          }
+          __syncthreads();
+        } else {
+          pre = false;   // (eta = 1 within rounding) the iterations in order
+        }
+      }
+    }
     for (int it = it0; it <= i_max; ++it) {
       iters = it;
       d = min(k0 + p, K);
+      if (pre && it == kfull) {
+        // no earlier iteration met the target: the full-width step
+        const float2* zs = sm.pm;
+        for (int e = tid; e < K * K; e += NTH) {
+          const int j = e / K, i = e - j * K;
+          b2[j * LDK + i] = zs[e];
+        }
+        if (tid < K) {
+          sm.s2[tid] = sm.s2k[tid];
+          sm.order[tid] = sm.ordk[tid];
+          o_sig2[tid] = sm.s2k[sm.ordk[tid]];
+        }
+        __syncthreads();
+        found = true;
+        basis = true;
+        rotated = true;
+        r = rk;
+        captured = capk;
+        sweeps += sweeps_k;
+        rounds += rounds_k;
+        break;
+      }
+      if (pre && sm.topk[d] < Et * (1.0 - KYFAN_MARGIN)) {
+        k0 = min(2 * k0, K);   // cannot meet the target
+        continue;
+      }
       const double tot = sketch_iteration(it, d);
       if (tot >= Et) {
         found = true;

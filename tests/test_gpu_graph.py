@@ -126,11 +126,12 @@ def test_full_graph_replays_equal_eager(ctx, sizes, precision):
 
 def test_batched_precoder_rows_change_no_result(ctx):
     # a batch of K <= 64 tracks with 32, 64 and 256 precoder rows per workgroup
+    # (a batch this small takes the single-track entry)
     sizes = [(64, 256), (16, 1000), (40, 520), (1, 8)]
     Hs = [walk(K, N, 0, 95 + i)[0] for i, (K, N) in enumerate(sizes)]
     outs = []
     for pb in (32, 64, 256):
-        ctx.tune_table([{"K": K, "N": N, "batch_precoder_rows": pb} for K, N in sizes])
+        ctx.tune_table([{"K": K, "N": N, "precoder_rows": pb, "batch_precoder_rows": pb} for K, N in sizes])
         Ws = [torch.empty(N, K, dtype=torch.complex64, device="cuda") for K, N in sizes]
         ctx.full_batch(Hs, [0.4] * len(sizes), 1.0, Ws)
         ctx.sync()
