@@ -595,15 +595,21 @@ void plan_update(UpdatePlan& P, int n, const rzf_update_item* items, double tol,
 }
 
 size_t UpdatePlan::bytes() const {
-  return sizeof(GramJob) * gj.size() + sizeof(ArsvdJob) * (aj.size() + ajb.size()) +
+  return sizeof(GramJob) * gj.size() + 2 * sizeof(ArsvdJob) * (aj.size() + ajb.size()) +
          sizeof(Gram64Job) * g64.size() + sizeof(Inv64Job) * (i64.size() + i64b.size()) +
-         sizeof(PrecJob) * pj.size() + sizeof(ScaleJob) * sj.size() + 16 * 8;
+         sizeof(PrecJob) * pj.size() + sizeof(ScaleJob) * sj.size() + 16 * 12;
 }
 
 void UpdatePlan::put(Stager& st) {
   if (!gj.empty()) st.put(gj.data(), (int)gj.size(), &d_gj);
-  if (!aj.empty()) st.put(aj.data(), (int)aj.size(), &d_aj);
-  if (!ajb.empty()) st.put(ajb.data(), (int)ajb.size(), &d_ajb);
+  if (!aj.empty()) {
+    st.put(aj.data(), (int)aj.size(), &d_aj);
+    st.put(aj.data(), (int)aj.size(), &d_ajo);   // reordered on the device before use
+  }
+  if (!ajb.empty()) {
+    st.put(ajb.data(), (int)ajb.size(), &d_ajb);
+    st.put(ajb.data(), (int)ajb.size(), &d_ajbo);
+  }
   if (!g64.empty()) st.put(g64.data(), (int)g64.size(), &d_g64);
   if (!i64.empty()) st.put(i64.data(), (int)i64.size(), &d_i64);
   if (!i64b.empty()) st.put(i64b.data(), (int)i64b.size(), &d_i64b);
@@ -618,8 +624,18 @@ void UpdatePlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
     for (const GramJob& g : gj) fp32 = fp32 && g.prec == RZF_PREC_FP32;
     timed(c, KN_GRAM, s, [&] { launch_gram(gj[0], d_gj, (int)gj.size(), maxK, fp32, s); });
     timed(c, KN_ARSVD, s, [&] {
-      if (!aj.empty()) launch_arsvd_wb(aj[0], d_aj, (int)aj.size(), err, s);
-      if (!ajb.empty()) launch_arsvd_big(ajb[0], d_ajb, (int)ajb.size(), err, s);
+      // longest-first order over the CUs for a batch that spans more than one
+      // wave of workgroups
+      if (!aj.empty()) {
+        const bool ord = (int)aj.size() > 64;
+        if (ord) launch_arsvd_order(d_aj, d_ajo, (int)aj.size(), s);
+        launch_arsvd_wb(aj[0], ord ? d_ajo : d_aj, (int)aj.size(), err, s);
+      }
+      if (!ajb.empty()) {
+        const bool ord = (int)ajb.size() > 64;
+        if (ord) launch_arsvd_order(d_ajb, d_ajbo, (int)ajb.size(), s);
+        launch_arsvd_big(ajb[0], ord ? d_ajbo : d_ajb, (int)ajb.size(), err, s);
+      }
     });
   }
   if (!g64.empty()) {

@@ -1287,6 +1287,64 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   }
 }
 
+// Longest-first order of a batch's arSVD jobs (out = in, permuted): the jobs
+// expected to take longest start in the first wave of workgroups, so that a
+// launch's time is not one slow track left for last on its CU.  Key 7 .. 0,
+// stable within a key: a large track (K > KS) by its size (min(7, K / 32));
+// a K <= KS track 1 when its next full-width iteration has no warm basis or
+// its last SVD stopped below d = K (its step runs more of Alg. 1 or a cold
+// Jacobi), else 0.  Reads only the descriptors as the previous step left
+// them.  One workgroup; every track's results are what they are in any order.
+__global__ __launch_bounds__(1024) void k_arsvd_order(const ArsvdJob* in, ArsvdJob* out, int n) {
+  constexpr int NK = 8;
+  __shared__ int cnt[NK], base[NK];
+  __shared__ int wsum[NTH / 64][NK];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  auto key_of = [&](int t) -> int {
+    const GTrackDesc* td = (const GTrackDesc*)in[t].td;
+    const int K = td->K;
+    if (K > KS) return min(NK - 1, K / 32);
+    return (td->warm != 0 && td->nsig == K) ? 0 : 1;
+  };
+  if (tid < NK) cnt[tid] = 0;
+  __syncthreads();
+  for (int t = tid; t < n; t += NTH) atomicAdd(&cnt[key_of(t)], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int b = 0;
+    for (int k = NK - 1; k >= 0; --k) {
+      base[k] = b;
+      b += cnt[k];
+    }
+  }
+  __syncthreads();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int c0 = 0; c0 < n; c0 += NTH) {
+    const int t = c0 + tid;
+    const int k = t < n ? key_of(t) : -1;
+    unsigned long long mk = 0ull;
+#pragma unroll
+    for (int b = 0; b < NK; ++b) {
+      const unsigned long long m = __ballot(k == b);
+      if (lane == 0) wsum[wid][b] = __popcll(m);
+      if (k == b) mk = m;
+    }
+    __syncthreads();
+    if (k >= 0) {
+      int off = base[k] + __popcll(mk & below);
+      for (int w = 0; w < wid; ++w) off += wsum[w][k];
+      out[off] = in[t];
+    }
+    __syncthreads();
+    if (tid < NK) {
+      int c = 0;
+      for (int w = 0; w < NTH / 64; ++w) c += wsum[w][tid];
+      base[tid] += c;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_debug_sketch(uint64_t seed, uint64_t track, int t, int it, int K, int d,
                                float2* Omega, uint64_t* words) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1307,6 +1365,10 @@ __global__ void k_debug_sketch(uint64_t seed, uint64_t track, int t, int it, int
 void launch_arsvd_wb(const ArsvdJob& one, const ArsvdJob* many, int n, int* err, hipStream_t s) {
   if (many) k_arsvd_wb<true, 0><<<dim3(1, n), NTH, 0, s>>>(one, many, err);
   else k_arsvd_wb<false, 0><<<1, NTH, 0, s>>>(one, many, err);
+}
+
+void launch_arsvd_order(const ArsvdJob* in, ArsvdJob* out, int n, hipStream_t s) {
+  k_arsvd_order<<<1, NTH, 0, s>>>(in, out, n);
 }
 
 void launch_arsvd_wb_spec(const ArsvdJob& one, int* err, hipStream_t s) {

@@ -154,6 +154,8 @@ struct UpdatePlan {
   GramJob* d_gj = nullptr;
   ArsvdJob* d_aj = nullptr;
   ArsvdJob* d_ajb = nullptr;
+  ArsvdJob* d_ajo = nullptr;    // d_aj, d_ajb in longest-first order (written on the device)
+  ArsvdJob* d_ajbo = nullptr;
   Gram64Job* d_g64 = nullptr;
   Inv64Job* d_i64 = nullptr;
   Inv64Job* d_i64b = nullptr;

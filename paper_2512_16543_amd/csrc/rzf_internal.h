@@ -198,6 +198,9 @@ void launch_arsvd_wb(const ArsvdJob& one, const ArsvdJob* many, int n, int* err,
 // of Alg. 1 that the previous step's count predicts, in parallel, then the
 // decision, the SVD and the branch of Alg. 2.  Bit-identical results.
 void launch_arsvd_wb_spec(const ArsvdJob& one, int* err, hipStream_t s);
+// out = in permuted longest-first (from the tracks' descriptors), for a
+// batched arSVD launch over out.
+void launch_arsvd_order(const ArsvdJob* in, ArsvdJob* out, int n, hipStream_t s);
 // Large tracks (KS < K <= KM): one workgroup per track, working set in the
 // track's global workspace.
 void launch_arsvd_big(const ArsvdJob& one, const ArsvdJob* many, int n, int* err, hipStream_t s);

@@ -18,11 +18,11 @@ pytestmark = pytest.mark.gpu
 SIZES = [(16, 64), (64, 256), (13, 37), (33, 100), (64, 1000), (1, 8), (40, 24)]
 
 
-def walk(K, N, steps, seed):
-    """A channel track whose per-step change is a small low-rank perturbation."""
+def walk(K, N, steps, seed, rank=2):
+    """A channel track whose per-step change is a small perturbation of the given rank."""
     H = [wl.random_channel(K, N, seed)]
     for t in range(steps):
-        H.append(wl.perturbed_channel(H[-1], seed * 1000 + t, rank=2, scale=0.02))
+        H.append(wl.perturbed_channel(H[-1], seed * 1000 + t, rank=rank, scale=0.02))
     return np.asarray(H, dtype=np.complex64)
 
 
@@ -64,6 +64,43 @@ def test_batch_equals_alone(ctx):
     assert rzf.PATH_RESET in paths and rzf.PATH_WB in paths
     for tr in alone + batch:
         tr.destroy()
+
+
+def test_long_batch_equals_alone():
+    """Batches that span more than one wave of workgroups are run longest-first
+    (reordered on the device from each track's state); every track's results
+    must still be those of the track alone, for the small- and large-track
+    kernels and tracks whose last SVD stopped at different widths."""
+    sizes = [(8 + (i * 7) % 57, 40 + (i * 13) % 90) for i in range(72)]
+    sizes += [(65 + (i * 11) % 60, 130 + (i * 17) % 70) for i in range(66)]
+    steps = 4
+    arena = sum(2 * rzf.track_bytes(K, N) for K, N in sizes) + (64 << 20)
+    c = rzf.Context(0, arena)
+    try:
+        # odd small tracks change in every direction (their SVDs run to d = K)
+        Hs = [walk(K, N, steps, 300 + i, rank=K if (i % 2 and K <= 64) else 2) for i, (K, N) in enumerate(sizes)]
+        dev = [torch.from_numpy(H).cuda() for H in Hs]
+        periods = [0 if i % 5 else 3 for i in range(len(sizes))]
+        alone = _tracks(c, Hs, periods)
+        batch = _tracks(c, Hs, periods)
+        Wa = [torch.empty(N, K, dtype=torch.complex64, device="cuda") for K, N in sizes]
+        Wb = [torch.empty_like(w) for w in Wa]
+        widths = set()
+        for t in range(1, steps + 1):
+            eta = 0.95 if t % 2 else 0.999
+            infos_a = [tr.update(d[t], eta, w) for tr, d, w in zip(alone, dev, Wa)]
+            infos_b = c.update_batch(batch, [d[t] for d in dev], Wb, eta, want_info=True)
+            c.sync()
+            for i, KN in enumerate(sizes):
+                assert torch.equal(Wa[i], Wb[i]), (t, i, KN)
+                assert torch.equal(alone[i].inverse(), batch[i].inverse()), (t, i, KN)
+                assert infos_a[i].as_dict() == infos_b[i].as_dict(), (t, i, KN)
+            widths |= {(i.d == K) for i, (K, _) in zip(infos_b, sizes) if i.d > 0}
+        assert widths == {True, False}
+        for tr in alone + batch:
+            tr.destroy()
+    finally:
+        c.close()
 
 
 def test_batch_matches_oracle(ctx):
