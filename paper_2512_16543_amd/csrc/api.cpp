@@ -627,12 +627,12 @@ void UpdatePlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
       // longest-first order over the CUs for a batch that spans more than one
       // wave of workgroups
       if (!aj.empty()) {
-        const bool ord = (int)aj.size() > 64;
+        const bool ord = aj.size() > 64 && aj.size() <= RZF_BATCH_MAX;
         if (ord) launch_arsvd_order(d_aj, d_ajo, (int)aj.size(), s);
         launch_arsvd_wb(aj[0], ord ? d_ajo : d_aj, (int)aj.size(), err, s);
       }
       if (!ajb.empty()) {
-        const bool ord = (int)ajb.size() > 64;
+        const bool ord = ajb.size() > 64 && ajb.size() <= RZF_BATCH_MAX;
         if (ord) launch_arsvd_order(d_ajb, d_ajbo, (int)ajb.size(), s);
         launch_arsvd_big(ajb[0], ord ? d_ajbo : d_ajb, (int)ajb.size(), err, s);
       }
@@ -647,8 +647,9 @@ void UpdatePlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
   }
   const rzf_tune_entry te = tune_for(c, maxK, maxN);
   const int pb = (int)pj.size() >= PREC_BATCH_MIN ? te.batch_precoder_rows : te.precoder_rows;
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, pb, s); });
-  timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
+  bool scaled = false;
+  timed(c, KN_PRECODER, s, [&] { scaled = launch_precoder(pj[0], d_pj, sj[0], d_sj, n, maxN, maxK, pb, s); });
+  if (!scaled) timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
 }
 
 void advance_tracks(int n, rzf_track* const* tracks, const std::vector<int>& reset_flag) {
@@ -752,8 +753,9 @@ void FullPlan::launch(rzf_ctx* c, hipStream_t s, int* err) const {
   });
   const rzf_tune_entry te = tune_for(c, maxK, maxN);
   const int pb = (int)pj.size() >= PREC_BATCH_MIN ? te.batch_precoder_rows : te.precoder_rows;
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj[0], d_pj, n, maxN, maxK, pb, s); });
-  timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
+  bool scaled = false;
+  timed(c, KN_PRECODER, s, [&] { scaled = launch_precoder(pj[0], d_pj, sj[0], d_sj, n, maxN, maxK, pb, s); });
+  if (!scaled) timed(c, KN_SCALE, s, [&] { launch_scale(sj[0], d_sj, n, maxNK, s); });
 }
 
 rzf_status full_batch_locked(rzf_ctx* c, int n, const rzf_full_item* items, const FullScratch* scr,
@@ -839,8 +841,9 @@ void update_single_launch(rzf_ctx* c, rzf_track* t, const float2* Hf, int ldh, d
   const PrecJob pj{Hf, d.Ainv, Wf, d.wpart, d.Hprev, K, N, ldh, ldw, d.prec, &t->d_desc->hold};
   const ScaleJob sj{Wf, d.wpart, d.P, K, N, ldw, precoder_blocks(N), t->d_desc};
   const int pb = tune_for(c, K, N).precoder_rows;
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, pb, s); });
-  timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
+  bool scaled = false;
+  timed(c, KN_PRECODER, s, [&] { scaled = launch_precoder(pj, nullptr, sj, nullptr, 1, N, K, pb, s); });
+  if (!scaled) timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
 }
 
 void full_single_launch(rzf_ctx* c, int K, int N, const float2* Hf, int ldh, double alpha, double P, float2* Wf,
@@ -852,8 +855,9 @@ void full_single_launch(rzf_ctx* c, int K, int N, const float2* Hf, int ldh, dou
   const Inv32Job vj{c->d_fullA, c->d_fullAinv, K};
   timed(c, KN_INV32, s, [&] { inv32_any(vj, c->d_err, s); });
   const int pb = tune_for(c, K, N).precoder_rows;
-  timed(c, KN_PRECODER, s, [&] { launch_precoder(pj, nullptr, 1, N, K, pb, s); });
-  timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
+  bool scaled = false;
+  timed(c, KN_PRECODER, s, [&] { scaled = launch_precoder(pj, nullptr, sj, nullptr, 1, N, K, pb, s); });
+  if (!scaled) timed(c, KN_SCALE, s, [&] { launch_scale(sj, nullptr, 1, N * K, s); });
 }
 
 void rate_single_launch(rzf_ctx* c, int K, int N, const float2* H, int ldh, const float2* W, int ldw, double P,

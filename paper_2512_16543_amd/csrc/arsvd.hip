@@ -1299,6 +1299,7 @@ __global__ __launch_bounds__(1024) void k_arsvd_order(const ArsvdJob* in, ArsvdJ
   constexpr int NK = 8;
   __shared__ int cnt[NK], base[NK];
   __shared__ int wsum[NTH / 64][NK];
+  __shared__ unsigned char keys[RZF_BATCH_MAX];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   auto key_of = [&](int t) -> int {
     const GTrackDesc* td = (const GTrackDesc*)in[t].td;
@@ -1308,7 +1309,11 @@ __global__ __launch_bounds__(1024) void k_arsvd_order(const ArsvdJob* in, ArsvdJ
   };
   if (tid < NK) cnt[tid] = 0;
   __syncthreads();
-  for (int t = tid; t < n; t += NTH) atomicAdd(&cnt[key_of(t)], 1);
+  for (int t = tid; t < n; t += NTH) {
+    const int k = key_of(t);
+    keys[t] = (unsigned char)k;
+    atomicAdd(&cnt[k], 1);
+  }
   __syncthreads();
   if (tid == 0) {
     int b = 0;
@@ -1321,7 +1326,7 @@ __global__ __launch_bounds__(1024) void k_arsvd_order(const ArsvdJob* in, ArsvdJ
   const unsigned long long below = (1ull << lane) - 1ull;
   for (int c0 = 0; c0 < n; c0 += NTH) {
     const int t = c0 + tid;
-    const int k = t < n ? key_of(t) : -1;
+    const int k = t < n ? (int)keys[t] : -1;
     unsigned long long mk = 0ull;
 #pragma unroll
     for (int b = 0; b < NK; ++b) {

@@ -31,9 +31,11 @@ __device__ __forceinline__ void mac_conj(float2 x, float2 y, floatx4& dr, floatx
 template <bool DELTA, bool MANY>
 __global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) {
   // FP32 path: chunks of GC antennas staged through LDS (rows i0.. and j0.. of
-  // H_t, then of H_{t-1}); the row stride GLD keeps the MFMA operand reads at
-  // two lanes per bank.  The partial tiles reuse the same memory afterwards.
-  constexpr int GC = 64, GLD = GC + 4;
+  // H_t, then of H_{t-1}).  An operand read takes one antenna of 16 rows per
+  // 16 lanes: the odd row stride GLD (130 dwords, 2 mod 32) puts those rows
+  // in distinct bank pairs (a stride of 68 put four rows on each pair).  The
+  // partial tiles reuse the same memory afterwards.
+  constexpr int GC = 64, GLD = GC + 1;
   __shared__ float2 st[4][16][GLD];
   float (*red)[16][64] = reinterpret_cast<float (*)[16][64]>(&st[0][0][0]);
   const GridPos gp = grid_pos<MANY>();
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) 
         for (int e = 0; e < 4; ++e) {
           const int idx = threadIdx.x + 256 * e;   // 16 rows x 64 antennas
           const int row = rb + (idx >> 6), n = c0 + (idx & 63);
-          pre[m][e] = (row < K && n < N) ? src[(size_t)row * ld + n] : cz();
+          pre[m][e] = (row < K && n < N) ? gld(src, (size_t)row * ld + n) : cz();
         }
       }
     };
@@ -118,8 +120,8 @@ __global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) 
       for (int e = 0; e < 8; ++e) {
         const int n = nb + e;
         const bool okn = n < N;
-        ti[e] = (oki && okn) ? Ht[(size_t)ri * ldh + n] : cz();
-        tj[e] = (okj && okn) ? Ht[(size_t)rj * ldh + n] : cz();
+        ti[e] = (oki && okn) ? gld(Ht, (size_t)ri * ldh + n) : cz();
+        tj[e] = (okj && okn) ? gld(Ht, (size_t)rj * ldh + n) : cz();
       }
       cmac8_bf16(ti, tj, false, true, x3, ar, ai);       // H_t H_t^H
       if (DELTA) {
@@ -128,8 +130,8 @@ __global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) 
         for (int e = 0; e < 8; ++e) {
           const int n = nb + e;
           const bool okn = n < N;
-          pi[e] = (oki && okn) ? Hp[(size_t)ri * ldp + n] : cz();
-          const float2 pj = (okj && okn) ? Hp[(size_t)rj * ldp + n] : cz();
+          pi[e] = (oki && okn) ? gld(Hp, (size_t)ri * ldp + n) : cz();
+          const float2 pj = (okj && okn) ? gld(Hp, (size_t)rj * ldp + n) : cz();
           di[e] = csub(ti[e], pi[e]);
           dj[e] = csub(tj[e], pj);
         }
@@ -165,11 +167,11 @@ __global__ __launch_bounds__(256) void k_gram(GramJob one, const GramJob* many) 
       a = make_float2(a.x + alpha, 0.f);
       g.y = 0.f;
     }
-    Anew[(size_t)i * K + j] = a;
-    if (i != j) Anew[(size_t)j * K + i] = cconj(a);
+    gst(Anew, (size_t)i * K + j, a);
+    if (i != j) gst(Anew, (size_t)j * K + i, cconj(a));
     if (DELTA) {
-      dA[(size_t)i * K + j] = g;
-      if (i != j) dA[(size_t)j * K + i] = cconj(g);
+      gst(dA, (size_t)i * K + j, g);
+      if (i != j) gst(dA, (size_t)j * K + i, cconj(g));
     }
   }
 }
@@ -193,7 +195,7 @@ __device__ __forceinline__ void lower_tile(int t, int* bi, int* bj) {
 // order: a track's A' and Delta A are bit-identical to k_gram's.
 template <bool DELTA>
 __global__ __launch_bounds__(1024) void k_gram_track(const GramJob* many) {
-  constexpr int GC = 64, GLD = GC + 4, KT = 64, NM = DELTA ? 2 : 1;
+  constexpr int GC = 64, GLD = GC + 1, KT = 64, NM = DELTA ? 2 : 1;   // GLD: as in k_gram
   __shared__ float2 st[2][KT][GLD];   // [H_t, H_{t-1}][row][antenna of the chunk]
   // after the last chunk: one 16 x 64 float block per wave (the tile partials)
   float (*red)[16][64] = reinterpret_cast<float (*)[16][64]>(&st[0][0][0]);
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(1024) void k_gram_track(const GramJob* many) {
       for (int e = 0; e < 4; ++e) {
         const int idx = threadIdx.x + 1024 * e;   // 64 rows x 64 antennas
         const int row = idx >> 6, n = c0 + (idx & 63);
-        pre[m][e] = (row < K && n < N) ? src[(size_t)row * ld + n] : cz();
+        pre[m][e] = (row < K && n < N) ? gld(src, (size_t)row * ld + n) : cz();
       }
     }
   };
@@ -301,11 +303,11 @@ __global__ __launch_bounds__(1024) void k_gram_track(const GramJob* many) {
           a = make_float2(a.x + alpha, 0.f);
           g.y = 0.f;
         }
-        Anew[(size_t)i * K + j] = a;
-        if (i != j) Anew[(size_t)j * K + i] = cconj(a);
+        gst(Anew, (size_t)i * K + j, a);
+        if (i != j) gst(Anew, (size_t)j * K + i, cconj(a));
         if (DELTA) {
-          dA[(size_t)i * K + j] = g;
-          if (i != j) dA[(size_t)j * K + i] = cconj(g);
+          gst(dA, (size_t)i * K + j, g);
+          if (i != j) gst(dA, (size_t)j * K + i, cconj(g));
         }
       }
     }

@@ -69,7 +69,6 @@ extern "C" rzf_status rzf_full_noalloc(void* hip_stream, int K, int N, const rzf
   launch_gram(gj, nullptr, 1, K, false, s);
   if (K > KS) launch_inv32_big(vj, nullptr, 1, err, s);
   else launch_inv32(vj, nullptr, 1, err, s);
-  launch_precoder(pj, nullptr, 1, N, K, 64, s);
-  launch_scale(sj, nullptr, 1, N * K, s);
+  if (!launch_precoder(pj, nullptr, sj, nullptr, 1, N, K, 64, s)) launch_scale(sj, nullptr, 1, N * K, s);
   return hipGetLastError() == hipSuccess ? RZF_OK : RZF_E_DEVICE;
 }

@@ -28,22 +28,32 @@ namespace {
 
 constexpr int PG = 32;          // rows of W per partial sum of |w|^2
 constexpr int PIC = 32;         // users per reduction chunk
-constexpr int PNT = 1024;       // threads per workgroup
-constexpr int PNW = PNT / 64;
+
+// LDS row stride of the staged X chunk for tracks up to maxK users: the
+// columns of whole 16-column tiles, plus 4.
+int prec_xld(int maxK) { return ((maxK + 15) & ~15) + 4; }
 
 // Dynamic LDS of a launch with PB rows per workgroup for tracks up to maxK
-// users: the H chunk (row stride PB + 4), then the X chunk (row stride maxK + 4).
-size_t prec_lds_bytes(int pb, int maxK) { return sizeof(float2) * (size_t)PIC * (pb + 4 + maxK + 4); }
+// users: the H chunk (row stride PB + 4), then the X chunk (row stride prec_xld).
+size_t prec_lds_bytes(int pb, int maxK) { return sizeof(float2) * (size_t)PIC * (pb + 4 + prec_xld(maxK)); }
 
-// KMX: the largest K of the launch's tracks the kernel is built for (64 or KM).
-template <bool MANY, int PB, int KMX>
-__global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* many, int xld) {
+// KMX: the largest K of the launch's tracks the kernel is built for (64 or KM);
+// PNT: threads per workgroup.  FUSE (a launch whose workgroups each hold a
+// whole track, N <= PB): the workgroup also does k_scale's work for its
+// track (same partial sums, added in the same order, same scale factor), so
+// W is written once, already scaled.
+template <bool MANY, int PB, int KMX, int PNT, bool FUSE>
+__global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* many, ScaleJob sone,
+                                                  const ScaleJob* smany, int xld) {
+  constexpr int PNW = PNT / 64;
+  static_assert((PIC * PB) % PNT == 0 && ((PB / 16) * (KMX / 16)) % PNW == 0, "launch shape");
   constexpr int HLD = PB + 4;                 // LDS row stride of the staged H chunk (float2)
   constexpr int HPER = PIC * PB / PNT;        // H values a thread stages per chunk
   constexpr int XPER = (PIC * KMX + PNT - 1) / PNT;  // X values a thread stages per chunk, at most
   extern __shared__ float2 dyn[];
   float2* hs = dyn;                       // [PIC][HLD]: H[i0 + ii][n0 + c] at hs[ii * HLD + c]
-  float2* xs = dyn + PIC * HLD;           // [PIC][xld]: X[i0 + ii][k] at xs[ii * xld + k]
+  float2* xs = dyn + PIC * HLD;           // [PIC][xld]: X[i0 + ii][k] at xs[ii * xld + k],
+                                          // zeros past K up to the last column tile
   __shared__ double tsum[PB / 16][KMX / 16];  // |w|^2 of each 16x16 tile
   const GridPos gp = grid_pos<MANY>();
   const PrecJob& jb = job_at<MANY>(one, many, gp.item);
@@ -53,7 +63,7 @@ __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* ma
   float2* __restrict__ W = jb.W;
   double* __restrict__ wpart = jb.wpart;
   // a step that met a non-finite snapshot keeps the track's previous one
-  float2* __restrict__ Hcopy = (jb.hold && *jb.hold) ? nullptr : jb.Hcopy;
+  float2* __restrict__ Hcopy = (jb.hold && gld(jb.hold, 0)) ? nullptr : jb.Hcopy;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int n0 = gp.x * PB;
   if (n0 >= N) return;
@@ -65,19 +75,29 @@ __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* ma
   for (int q = 0; q < TPW; ++q) { tre[q] = zero4(); tim[q] = zero4(); }
   const bool fp32 = jb.prec == RZF_PREC_FP32;
   if (fp32) {
+    static_assert(PNW % (PB / 16) == 0, "a wave's tiles share their rows of W");
+    const int nt = wid % (PB / 16), rr = lane & 15, kk = lane >> 4;
+    int nq = 0;   // the wave's tiles inside the track (wave-uniform)
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) nq += __builtin_amdgcn_readfirstlane(wid) + PNW * q < ntile ? 1 : 0;
+    const int K16 = kt * 16;   // columns of whole tiles (X staged with zeros past K)
+    int colc[TPW];             // the tile's column of X for this lane (a tile past the
+                               // track reads, unused, the last staged column)
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) colc[q] = min(((wid + PNW * q) / (PB / 16)) * 16 + rr, K16 - 1);
     float2 ph[HPER], px[XPER];
     auto fetch = [&](int i0) {
 #pragma unroll
       for (int e = 0; e < HPER; ++e) {
         const int idx = tid + PNT * e;          // 32 users x 64 antennas
         const int i = i0 + idx / PB, n = n0 + idx % PB;
-        ph[e] = (i < K && n < N) ? H[(size_t)i * ldh + n] : cz();
+        ph[e] = (i < K && n < N) ? gld(H, (size_t)i * ldh + n) : cz();
       }
 #pragma unroll
       for (int e = 0; e < XPER; ++e) {
         const int idx = tid + PNT * e;          // 32 users x K
-        const int ii = idx / K, k = idx - ii * K;
-        px[e] = (ii < PIC && i0 + ii < K) ? X[(size_t)(i0 + ii) * K + k] : cz();
+        const int ii = idx / K16, k = idx - ii * K16;
+        px[e] = (ii < PIC && i0 + ii < K && k < K) ? gld(X, (size_t)(i0 + ii) * K + k) : cz();
       }
     };
     fetch(0);
@@ -87,27 +107,46 @@ __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* ma
         const int idx = tid + PNT * e;
         const int ii = idx / PB, c = idx % PB;
         hs[ii * HLD + c] = ph[e];
-        if (Hcopy && i0 + ii < K && n0 + c < N) Hcopy[(size_t)(i0 + ii) * N + n0 + c] = ph[e];
+        if (Hcopy && i0 + ii < K && n0 + c < N) gst(Hcopy, (size_t)(i0 + ii) * N + n0 + c, ph[e]);
       }
 #pragma unroll
       for (int e = 0; e < XPER; ++e) {
         const int idx = tid + PNT * e;
-        const int ii = idx / K, k = idx - ii * K;
+        const int ii = idx / K16, k = idx - ii * K16;
         if (ii < PIC) xs[ii * xld + k] = px[e];
       }
       __syncthreads();
       if (i0 + PIC < K) fetch(i0 + PIC);
-      const int ic = min(PIC, K - i0);   // users of this chunk (the rest of LDS holds zeros)
+      const int steps = (min(PIC, K - i0) + 3) / 4;   // 4 users per product (past K: zeros in LDS)
+      // A(n, i) = conj(H[i][n]);  B(i, k) = X[i][k].  The wave's tiles share
+      // their rows of W, so a step reads the H operand once for all of them,
+      // and the next step's operands are read while this one's products run.
+      // Every tile's products are those of ctile16, in its order.
+      auto operands = [&](int st, float2& av, float2 (&bv)[TPW]) {
+        const int i = min(4 * st + kk, PIC - 1);   // a step past the chunk reads, unused, its last row
+        av = hs[i * HLD + nt * 16 + rr];   // conjugated in the products below
 #pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        const int t = wid + PNW * q;
-        if (t >= ntile) break;
-        const int nt = t % (PB / 16), ct = t / (PB / 16);
-        const int col = ct * 16 + (lane & 15);
-        const bool okc = col < K;
-        // A(n, i) = conj(H[i][n]);  B(i, k) = X[i][k]
-        ctile16([&](int rr, int i) { return cconj(hs[i * HLD + nt * 16 + rr]); },
-                [&](int i, int) { return okc ? xs[i * xld + col] : cz(); }, 0, (ic + 3) & ~3, tre[q], tim[q]);
+        for (int q = 0; q < TPW; ++q) bv[q] = xs[i * xld + colc[q]];
+      };
+      auto products = [&](const float2& av, const float2 (&bv)[TPW]) {
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+          if (q >= nq) break;
+          tre[q] = mfma4(av.x, bv[q].x, tre[q]);
+          tre[q] = mfma4(av.y, bv[q].y, tre[q]);
+          tim[q] = mfma4(av.x, bv[q].y, tim[q]);
+          tim[q] = mfma4(-av.y, bv[q].x, tim[q]);
+        }
+      };
+      // two operand buffers in turn: a step's products run while the next
+      // step's operands are read
+      float2 a0, b0[TPW], a1, b1[TPW];
+      operands(0, a0, b0);
+      for (int st = 0; st < steps; st += 2) {
+        operands(st + 1, a1, b1);
+        products(a0, b0);
+        operands(st + 2, a0, b0);
+        if (st + 1 < steps) products(a1, b1);
       }
       __syncthreads();
     }
@@ -126,8 +165,8 @@ __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* ma
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int i = j0 + 8 * kq + e;
-          a[e] = (n < N && i < K) ? H[(size_t)i * ldh + n] : cz();
-          b[e] = (i < K && k < K) ? X[(size_t)i * K + k] : cz();
+          a[e] = (n < N && i < K) ? gld(H, (size_t)i * ldh + n) : cz();
+          b[e] = (i < K && k < K) ? gld(X, (size_t)i * K + k) : cz();
         }
         cmac8_bf16(a, b, true, false, x3, tre[q], tim[q]);
       }
@@ -135,10 +174,10 @@ __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* ma
     if (Hcopy)
       for (int e = tid; e < K * PB; e += PNT) {
         const int i = e / PB, n = n0 + e % PB;
-        if (n < N) Hcopy[(size_t)i * N + n] = H[(size_t)i * ldh + n];
+        if (n < N) gst(Hcopy, (size_t)i * N + n, gld(H, (size_t)i * ldh + n));
       }
   }
-  // the block's rows of W (unscaled) and each tile's sum of |w|^2
+  // the block's rows of W (unscaled, unless FUSE) and each tile's sum of |w|^2
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
     const int t = wid + PNW * q;
@@ -149,7 +188,7 @@ __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* ma
     for (int v = 0; v < 4; ++v) {
       const int n = n0 + nt * 16 + tile_row(v), k = ct * 16 + tile_col();
       if (n < N && k < K) {
-        W[(size_t)n * ldw + k] = make_float2(tre[q][v], tim[q][v]);
+        if (!FUSE) gst(W, (size_t)n * ldw + k, make_float2(tre[q][v], tim[q][v]));
         acc += (double)tre[q][v] * tre[q][v] + (double)tim[q][v] * tim[q][v];
       }
     }
@@ -157,13 +196,47 @@ __global__ __launch_bounds__(PNT) void k_precoder(PrecJob one, const PrecJob* ma
     if (lane == 0) tsum[nt][ct] = acc;
   }
   __syncthreads();
+  if (FUSE) {
+    // the track's partials (those of the 32-row groups) added in order, then
+    // W = sqrt(P / ||W||^2) W, as k_scale does
+    __shared__ float sc;
+    const ScaleJob& sj = job_at<MANY>(sone, smany, gp.item);
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int g = 0; g * PG < N; ++g) {
+        double w = 0.0;
+        for (int ct = 0; ct < kt; ++ct) w += tsum[2 * g][ct] + tsum[2 * g + 1][ct];
+        tot += w;
+      }
+      sc = tot > 0.0 ? (float)sqrt(sj.P / tot) : 0.f;
+      if (sj.adv) {
+        // the track's step is complete: its next one takes the next index and tag
+        sj.adv->t_dev += 1;
+        sj.adv->seq_dev += 1;
+      }
+    }
+    __syncthreads();
+    const float s = sc;
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = wid + PNW * q;
+      if (t >= ntile) break;
+      const int nt = t % (PB / 16), ct = t / (PB / 16);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = n0 + nt * 16 + tile_row(v), k = ct * 16 + tile_col();
+        if (n < N && k < K) gst(W, (size_t)n * ldw + k, make_float2(tre[q][v] * s, tim[q][v] * s));
+      }
+    }
+    return;
+  }
   // one partial per 32 rows: its two row tiles, column tiles in order
   if (tid < PB / PG) {
     const int g = tid;
     if (n0 + g * PG < N) {
       double w = 0.0;
       for (int ct = 0; ct < kt; ++ct) w += tsum[2 * g][ct] + tsum[2 * g + 1][ct];
-      wpart[n0 / PG + g] = w;
+      gst(wpart, (size_t)(n0 / PG + g), w);
     }
   }
 }
@@ -226,17 +299,26 @@ void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, h
 
 int precoder_scratch(int N) { return precoder_blocks(N); }
 
-template <int PB, int KMX>
-void launch_precoder_pb(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, hipStream_t s) {
-  const dim3 grid((maxN + PB - 1) / PB, many ? n : 1);
+template <int PB, int KMX, int PNT = 1024>
+bool launch_precoder_pb(const PrecJob& one, const PrecJob* many, const ScaleJob& sone, const ScaleJob* smany,
+                        int n, int maxN, int maxK, hipStream_t s) {
+  const int nb = (maxN + PB - 1) / PB;
+  const dim3 grid(nb, many ? n : 1);
   const size_t lds = prec_lds_bytes(PB, maxK);
-  const int xld = maxK + 4;
-  if (many) k_precoder<true, PB, KMX><<<grid, PNT, lds, s>>>(one, many, xld);
-  else k_precoder<false, PB, KMX><<<grid, PNT, lds, s>>>(one, many, xld);
+  const int xld = prec_xld(maxK);
+  if (nb == 1) {
+    if (many) k_precoder<true, PB, KMX, PNT, true><<<grid, PNT, lds, s>>>(one, many, sone, smany, xld);
+    else k_precoder<false, PB, KMX, PNT, true><<<grid, PNT, lds, s>>>(one, many, sone, smany, xld);
+    return true;
+  }
+  if (many) k_precoder<true, PB, KMX, PNT, false><<<grid, PNT, lds, s>>>(one, many, sone, smany, xld);
+  else k_precoder<false, PB, KMX, PNT, false><<<grid, PNT, lds, s>>>(one, many, sone, smany, xld);
+  return false;
 }
 
-void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, int pb, hipStream_t s) {
-  if (pb == 256 && maxK <= 64) launch_precoder_pb<256, 64>(one, many, n, maxN, maxK, s);
-  else if (pb == 32) launch_precoder_pb<32, KM>(one, many, n, maxN, maxK, s);
-  else launch_precoder_pb<64, KM>(one, many, n, maxN, maxK, s);
+bool launch_precoder(const PrecJob& one, const PrecJob* many, const ScaleJob& sone, const ScaleJob* smany, int n,
+                     int maxN, int maxK, int pb, hipStream_t s) {
+  if (pb == 256 && maxK <= 64) return launch_precoder_pb<256, 64>(one, many, sone, smany, n, maxN, maxK, s);
+  if (pb == 32) return launch_precoder_pb<32, KM>(one, many, sone, smany, n, maxN, maxK, s);
+  return launch_precoder_pb<64, KM>(one, many, sone, smany, n, maxN, maxK, s);
 }

@@ -8,6 +8,28 @@
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Global-memory loads and stores through a device pointer.  A pointer read
+// from a job array in memory is generic to the compiler, so plain accesses
+// through it become flat instructions, which count against the LDS wait
+// counter as well: every wait for an LDS read then also waits for the
+// global loads in flight.  These go through the global address space.
+typedef float gf2_t __attribute__((ext_vector_type(2)));
+#define RZF_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ float2 gld(const float2* p, size_t i) {
+  const gf2_t v = ((const RZF_GLOBAL gf2_t*)p)[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(float2* p, size_t i, float2 v) {
+  gf2_t w;
+  w.x = v.x;
+  w.y = v.y;
+  ((RZF_GLOBAL gf2_t*)p)[i] = w;
+}
+template <class T>
+__device__ __forceinline__ T gld(const T* p, size_t i) { return ((const RZF_GLOBAL T*)p)[i]; }
+template <class T>
+__device__ __forceinline__ void gst(T* p, size_t i, T v) { ((RZF_GLOBAL T*)p)[i] = v; }
+
 #define RZF_WAVE 64
 
 // ------------------------------------------------------------ complex float

@@ -189,7 +189,11 @@ void launch_inv32(const Inv32Job& one, const Inv32Job* many, int n, int* err, hi
 int precoder_blocks(int N);
 int precoder_scratch(int N);
 // pb: rows of W per workgroup (32 or 64, or 256 with maxK <= 64; any other value takes 64).
-void launch_precoder(const PrecJob& one, const PrecJob* many, int n, int maxN, int maxK, int pb, hipStream_t s);
+// Returns true when the launch also normalised W (every track in one
+// workgroup: the scale jobs' P and adv are used); otherwise launch_scale
+// over the same scale jobs follows.
+bool launch_precoder(const PrecJob& one, const PrecJob* many, const ScaleJob& sone, const ScaleJob* smany, int n,
+                     int maxN, int maxK, int pb, hipStream_t s);
 // W <- W sqrt(P / ||W||_F^2) from the precoder's partial sums (maxNK: the
 // largest N K of the launch).
 void launch_scale(const ScaleJob& one, const ScaleJob* many, int n, int maxNK, hipStream_t s);
@@ -199,7 +203,7 @@ void launch_arsvd_wb(const ArsvdJob& one, const ArsvdJob* many, int n, int* err,
 // decision, the SVD and the branch of Alg. 2.  Bit-identical results.
 void launch_arsvd_wb_spec(const ArsvdJob& one, int* err, hipStream_t s);
 // out = in permuted longest-first (from the tracks' descriptors), for a
-// batched arSVD launch over out.
+// batched arSVD launch over out; n <= RZF_BATCH_MAX.
 void launch_arsvd_order(const ArsvdJob* in, ArsvdJob* out, int n, hipStream_t s);
 // Large tracks (KS < K <= KM): one workgroup per track, working set in the
 // track's global workspace.

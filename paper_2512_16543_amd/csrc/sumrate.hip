@@ -85,9 +85,9 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
       const int idx = tid + SNT * e;
       const int a = idx / SC, b = idx % SC;     // H: user a, antenna b;  W: antenna a, user b
       const int n = r0 + a, j = c0 + b;
-      ph[e] = (n < K && j < N) ? H[(size_t)n * ldh + j] : cz();
+      ph[e] = (n < K && j < N) ? gld(H, (size_t)n * ldh + j) : cz();
       const int jw = c0 + a, m = m0 + b;
-      pw[e] = (jw < N && m < K) ? W[(size_t)jw * ldw + m] : cz();
+      pw[e] = (jw < N && m < K) ? gld(W, (size_t)jw * ldw + m) : cz();
     }
   };
   int c = 0;
