@@ -142,6 +142,38 @@ def test_batched_precoder_rows_change_no_result(ctx):
             assert torch.equal(a, b)
 
 
+def test_batched_fused_normalisation(ctx):
+    # a batch of >= 128 tracks with N <= 256 rows: with 256 precoder rows per
+    # workgroup each workgroup holds a whole track and normalises W itself
+    # (and advances the track's step); with 32 a second kernel does both.
+    # Updates over three steps and a full-inversion batch must agree bit for bit.
+    rng = np.random.default_rng(7)
+    sizes = [(64, 256)] + [(int(rng.integers(1, 65)), int(rng.integers(8, 257))) for _ in range(135)]
+    Hs = [walk(K, N, 3, 500 + i) for i, (K, N) in enumerate(sizes)]
+    results = []
+    for pb in (256, 32):
+        ctx.tune_table([{"K": 64, "N": 256, "precoder_rows": pb, "batch_precoder_rows": pb}])
+        trs = [ctx.init(H[0], 0.3 + H.shape[1] / 25.0, rzf.default_params(seed=3, track_id=i, reset_period=0))
+               for i, H in enumerate(Hs)]
+        Ws = [torch.empty(N, K, dtype=torch.complex64, device="cuda") for K, N in sizes]
+        outs = []
+        for t in range(1, 4):
+            ctx.update_batch(trs, [H[t] for H in Hs], Ws, 0.95)
+            ctx.sync()
+            outs.append([w.clone() for w in Ws] + [tr.inverse() for tr in trs])
+        Wf = [torch.empty_like(w) for w in Ws]
+        ctx.full_batch([H[3] for H in Hs], [0.4] * len(Hs), 1.5, Wf)
+        ctx.sync()
+        outs.append(Wf)
+        results.append(outs)
+        for tr in trs:
+            tr.destroy()
+    ctx.tune_table([])
+    for step_a, step_b in zip(*results):
+        for a, b in zip(step_a, step_b):
+            assert torch.equal(a, b)
+
+
 def test_tuning_knobs_change_no_result(ctx):
     # the precoder's rows per workgroup and the single-track sum rate's
     # spread over workgroups are launch choices only
