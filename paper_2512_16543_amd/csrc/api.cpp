@@ -58,9 +58,7 @@ Layout track_layout(int K, int N) {
   L.a64 = o; o += align_up(sizeof(double2) * K * K);
   L.wpart = o; o += align_up(sizeof(double) * precoder_scratch(N));
   L.rfb = o; o += align_up(sizeof(float2) * K * K);
-  if (K <= KS) {
-    L.xw = o; o += align_up(sizeof(float2) * K * K);   // full-width SVD basis
-  }
+  L.xw = o; o += align_up(sizeof(float2) * K * K);   // full-width SVD basis
   if (K > KS) {
     // working set of the large-track kernels
     L.ym = o; o += align_up(sizeof(float2) * K * K);
@@ -294,7 +292,7 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
   d.A64 = reinterpret_cast<double2*>(base + L.a64);
   d.wpart = reinterpret_cast<double*>(base + L.wpart);
   d.Rfb = reinterpret_cast<float2*>(base + L.rfb);
-  if (K <= KS) d.Xw = reinterpret_cast<float2*>(base + L.xw);
+  d.Xw = reinterpret_cast<float2*>(base + L.xw);
   if (K > KS) {
     d.Ym = reinterpret_cast<float2*>(base + L.ym);
     d.Qm = reinterpret_cast<float2*>(base + L.qm);
@@ -1268,7 +1266,7 @@ rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track
   if (bytes < blob_bytes(h.K, h.N)) return RZF_E_INVALID;
   if (!params_valid(&h.prm) || !params_fit(&h.prm, h.K) || !std::isfinite(h.alpha) || h.alpha < 0.0 || h.step < 0 ||
       h.since_reset < 0 || h.last_r < 0 || h.last_r > h.K || (h.warm != 0 && h.warm != 1) ||
-      h.warm_age < 0 || (h.warm && h.K > KS))
+      h.warm_age < 0)
     return RZF_E_INVALID;
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));

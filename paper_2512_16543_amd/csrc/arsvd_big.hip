@@ -34,6 +34,11 @@ constexpr int NWV = NTH / 64;
 constexpr int MAX_SWEEPS = 30;      // Jacobi passes
 constexpr double JACOBI_TOL = 2e-6;
 constexpr double JACOBI_QSTOP = 1e-3;   // passes stop after one with no pair above it
+// a full-width SVD leaves its normalised columns z_j / sigma_j as the next
+// full-width iteration's starting basis; a column with sigma_j^2 at or below
+// this fraction of the largest (numerically zero, so not made orthogonal to
+// the others) leaves the track without one
+constexpr double BASIS_MIN_REL = 1e-20;
 // C = I + E is taken as singular when a pivot's modulus is at most
 // SING_TOL (1 + ||E||_F): its entries come from FP32 factors and are known
 // only to about r 2^-24 (1 + ||E||) (r <= 128 here), so a smaller pivot leaves
@@ -662,9 +667,20 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
   int d = 0, iters = 0, r = 0, sweeps = 0, rounds = 0, qrcols = 0;
   double captured = 0.0;
   bool rotated = false;
+  // the basis of the track's last full-width SVD, if it left one
+  const bool warm_in = td->warm != 0;
   for (int it = 1; it <= i_max; ++it) {
     iters = it;
     d = min(k0 + p, K);
+    if (d == K && warm_in) {
+      // At full width every unitary Q gives the same B = Q^H Delta A up to a
+      // unitary factor, hence the same SVD, captured energy and U_r.  The
+      // previous full-width basis replaces the sketch and its QR; it is close
+      // to Delta A's singular vectors, so the Jacobi passes start nearly done.
+      for (int e = tid; e < K * K; e += NTH) Qm[e] = td->Xw[e];
+      __syncthreads();
+      t_sk += clock64() - c_mark; c_mark = clock64();
+    } else {
     // Y = Delta A Omega, one 16-column tile of Omega at a time
     for (int ct = 0; ct * 16 < d; ++ct) {
       const int j0 = 16 * ct;
@@ -691,6 +707,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
     t_sk += clock64() - c_mark; c_mark = clock64();
     qr_big(sm, Ym, Qm, K, d);
     qrcols += d;
+    }
     // Z = Delta A^H Q = B^H and ||Z||_F^2 (Delta A + R need not be Hermitian)
     double zp = 0.0;
     const int dtl = (d + 15) / 16;
@@ -723,6 +740,16 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
       t_jac += clock64() - c_mark; c_mark = clock64();
       rotated = true;
       pick_rank_big(sm, Zm, K, d, Et, &r, &captured, tdg->sig2);
+      if (d == K) {
+        // the next full-width step's starting basis (column norms in sm.s2)
+        double smax = 0.0;
+        for (int c = 0; c < K; ++c) smax = fmax(smax, sm.s2[c]);
+        bool ok = smax > 0.0;
+        for (int c = 0; c < K; ++c) ok = ok && sm.s2[c] > BASIS_MIN_REL * smax;
+        if (ok)
+          for (int e = tid; e < K * K; e += NTH) td->Xw[e] = cscale(Zm[e], (float)(1.0 / sqrt(sm.s2[e / K])));
+        if (tid == 0) td->warm = ok ? 1 : 0;
+      }
       break;
     }
     // after the last iteration, or (early-fallback policy) once d is past

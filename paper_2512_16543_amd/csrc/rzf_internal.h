@@ -29,7 +29,7 @@ struct TrackDesc {
   int early_fallback, wb_limit;   // policy flag; largest rank the Woodbury branch takes
   int prec, error_feedback;       // rzf_precision of the Gram and precoder operands; policy
   float2* Rfb;     // K x K, ld K: error-feedback residual (zero unless the policy is on)
-  float2* Xw;      // K x K, column-major ld K (K <= KS): normalised columns z_j / sigma_j
+  float2* Xw;      // K x K, column-major ld K: normalised columns z_j / sigma_j
                    // of the last full-width (d = K) SVD, the next one's starting point
   uint64_t seed, track_id;
   float2* Ainv;    // K x K, ld K: stored inverse

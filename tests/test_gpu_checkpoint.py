@@ -11,17 +11,20 @@ from paper_2512_16543_amd import rzf, workload as wl
 pytestmark = pytest.mark.gpu
 
 
-def walk(K, N, steps, seed):
+def walk(K, N, steps, seed, rank=3):
     H = [wl.random_channel(K, N, seed)]
     for t in range(steps):
-        H.append(wl.perturbed_channel(H[-1], seed * 1000 + t, rank=3, scale=0.02))
+        H.append(wl.perturbed_channel(H[-1], seed * 1000 + t, rank=rank, scale=0.02))
     return torch.from_numpy(np.asarray(H, dtype=np.complex64)).cuda()
 
 
-@pytest.mark.parametrize("K,N,period,policy", [(24, 80, 4, rzf.KINIT_FIXED), (64, 256, 0, rzf.KINIT_WARM),
-                                               (100, 128, 3, rzf.KINIT_WARM)])
-def test_resume_is_bit_identical(K, N, period, policy):
-    Hs = walk(K, N, 9, 5 + K)
+# the last case changes in every direction, so its steps run to d = K and the
+# blob carries a large track's full-width basis
+@pytest.mark.parametrize("K,N,period,policy,rank", [(24, 80, 4, rzf.KINIT_FIXED, 3), (64, 256, 0, rzf.KINIT_WARM, 3),
+                                                    (100, 128, 3, rzf.KINIT_WARM, 3),
+                                                    (100, 128, 0, rzf.KINIT_FIXED, 100)])
+def test_resume_is_bit_identical(K, N, period, policy, rank):
+    Hs = walk(K, N, 9, 5 + K, rank)
     ctx = rzf.Context(0, 64 << 20)
     other = rzf.Context(0, 64 << 20)
     prm = rzf.default_params(seed=9, track_id=2, reset_period=period, kinit_policy=policy)
@@ -81,6 +84,41 @@ def test_resume_keeps_full_width_basis():
         assert ca["qr_columns"] == cb["qr_columns"], t
         if ia.iters == 6:
             assert ca["qr_columns"] == 7 + 9 + 13 + 21 + 37, t   # no QR at d = K
+    a.destroy()
+    b.destroy()
+    ctx.close()
+
+def test_resume_keeps_large_full_width_basis():
+    # a K = 256 track (the 32x32-array workload) at eta = 0.999 runs to d = K
+    # every step; from its second step the full-width iteration starts from the
+    # stored basis instead of a sketch and QR, and the blob carries that basis
+    cfg = wl.CONFIGS["c5"]
+    Hs = torch.from_numpy(wl.make_track(wl.with_overrides(cfg, steps=7)).snapshots()
+                          .astype(np.complex64)).cuda()
+    ctx = rzf.Context(0, 256 << 20)
+    prm = rzf.default_params(k_init=cfg.k_init, p=cfg.p, seed=cfg.seed, reset_period=0)
+    a = ctx.init(Hs[0], cfg.alpha, prm)
+    Wa = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device="cuda")
+    Wb = torch.empty_like(Wa)
+    for t in range(1, 4):
+        a.update(Hs[t], 0.999, Wa)
+    ctx.sync()
+    b = ctx.import_track(a.export())
+    full = 0
+    for t in range(4, 8):
+        ia = a.update(Hs[t], 0.999, Wa)
+        ib = b.update(Hs[t], 0.999, Wb)
+        ctx.sync()
+        assert (ia.r, ia.iters, ia.path) == (ib.r, ib.iters, ib.path), t
+        assert torch.equal(Wa, Wb), t
+        assert torch.equal(a.inverse(), b.inverse()), t
+        ca, cb = a.counters(), b.counters()
+        assert (ca["qr_columns"], ca["jacobi_sweeps"]) == (cb["qr_columns"], cb["jacobi_sweeps"]), t
+        ds = [min(cfg.k_init * 2 ** i + cfg.p, cfg.K) for i in range(ia.iters)]
+        if ds[-1] == cfg.K:
+            full += 1
+            assert ca["qr_columns"] == sum(ds[:-1]), t   # no QR at d = K
+    assert full > 0
     a.destroy()
     b.destroy()
     ctx.close()
