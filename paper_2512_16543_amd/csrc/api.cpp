@@ -309,20 +309,21 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
 
 // Checkpoint blob of one track: this header, then A^-1 (K x K) and H_prev
 // (K x N) row-major, the error-feedback residual R (K x K, row-major) and
-// the full-width SVD basis (K x K, column-major; zero for K > KS), all
-// complex64.
+// the full-width SVD basis (K x K, column-major), all complex64.
 struct TrackBlob {
   char magic[8];
   uint32_t version, header_bytes;
   int32_t K, N;
   rzf_params prm;
   double alpha;
-  int32_t step, since_reset, last_r, warm, warm_age, pad;
+  int32_t step, since_reset, last_r, warm, warm_age;
+  int32_t nsig, spec_hint, pad;   // d of the last SVD; Alg. 1 iterations of the last step
 };
 const char BLOB_MAGIC[8] = {'R', 'Z', 'F', 'T', 'R', 'A', 'C', 'K'};
-constexpr uint32_t BLOB_VERSION = 4;   // 3: params gained early_fallback, precision, error
+constexpr uint32_t BLOB_VERSION = 5;   // 3: params gained early_fallback, precision, error
                                        // feedback; the residual R follows H_prev.
-                                       // 4: the full-width SVD basis follows R
+                                       // 4: the full-width SVD basis follows R.
+                                       // 5: nsig and spec_hint; the basis for every K
 
 size_t blob_bytes(int K, int N) {
   return sizeof(TrackBlob) + sizeof(float2) * (3 * (size_t)K * K + (size_t)K * N);
@@ -1236,6 +1237,8 @@ rzf_status rzf_track_export(rzf_track* t, void* buf, size_t* bytes) {
   HIP_OK(hipMemcpy(&h.last_r, &t->d_desc->last_r, sizeof(int), hipMemcpyDeviceToHost));
   HIP_OK(hipMemcpy(&h.warm, &t->d_desc->warm, sizeof(int), hipMemcpyDeviceToHost));
   HIP_OK(hipMemcpy(&h.warm_age, &t->d_desc->warm_age, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(&h.nsig, &t->d_desc->nsig, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(&h.spec_hint, &t->d_desc->spec_hint, sizeof(int), hipMemcpyDeviceToHost));
   char* p = static_cast<char*>(buf);
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
@@ -1266,7 +1269,7 @@ rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track
   if (bytes < blob_bytes(h.K, h.N)) return RZF_E_INVALID;
   if (!params_valid(&h.prm) || !params_fit(&h.prm, h.K) || !std::isfinite(h.alpha) || h.alpha < 0.0 || h.step < 0 ||
       h.since_reset < 0 || h.last_r < 0 || h.last_r > h.K || (h.warm != 0 && h.warm != 1) ||
-      h.warm_age < 0)
+      h.warm_age < 0 || h.nsig < 0 || h.nsig > h.K || h.spec_hint < 0 || h.spec_hint > 64)
     return RZF_E_INVALID;
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
@@ -1281,6 +1284,8 @@ rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track
   t->h_desc.seq_dev += (unsigned)h.step;
   t->h_desc.warm = h.warm;
   t->h_desc.warm_age = h.warm_age;
+  t->h_desc.nsig = h.nsig;
+  t->h_desc.spec_hint = h.spec_hint;
   const char* p = static_cast<const char*>(buf) + sizeof(h);
   bool ok = hipMemcpy(t->d_desc, &t->h_desc, sizeof(TrackDesc), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(t->h_desc.Ainv, p, sizeof(float2) * h.K * h.K, hipMemcpyHostToDevice) == hipSuccess &&

@@ -39,6 +39,8 @@ constexpr double JACOBI_QSTOP = 1e-3;   // passes stop after one with no pair ab
 // this fraction of the largest (numerically zero, so not made orthogonal to
 // the others) leaves the track without one
 constexpr double BASIS_MIN_REL = 1e-20;
+// margin on Ky Fan's bound (below) for the rounding of the full-width sigma_j^2
+constexpr double KYFAN_MARGIN = 1e-4;
 // C = I + E is taken as singular when a pivot's modulus is at most
 // SING_TOL (1 + ||E||_F): its entries come from FP32 factors and are known
 // only to about r 2^-24 (1 + ||E||) (r <= 128 here), so a smaller pivot leaves
@@ -70,6 +72,11 @@ struct BigShared {
     float2 om[KM * 16];               // one 16-column tile of Omega
   } u;
   double s2[KM];
+  // full-width iteration computed first: its sigma_j^2 and order, and the
+  // energies of its leading columns (topk[d] = the d largest)
+  double s2k[KM];
+  int ordk[KM];
+  double topk[KM + 1];
   double red[NWV];
   double2 pivv[GJ_W];
   int order[KM];
@@ -669,9 +676,9 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
   bool rotated = false;
   // the basis of the track's last full-width SVD, if it left one
   const bool warm_in = td->warm != 0;
-  for (int it = 1; it <= i_max; ++it) {
-    iters = it;
-    d = min(k0 + p, K);
+  // Alg. 1's iteration `it` at width d: Q in Qm and Z = Delta A^H Q in Zm;
+  // returns ||Z||_F^2
+  auto sketch_iteration = [&](int it, int d) -> double {
     if (d == K && warm_in) {
       // At full width every unitary Q gives the same B = Q^H Delta A up to a
       // unitary factor, hence the same SVD, captured energy and U_r.  The
@@ -734,22 +741,92 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
     }
     const double tot = block_sum(zp, sm.red);
     t_qr += clock64() - c_mark; c_mark = clock64();
+    return tot;
+  };
+  // the first iteration whose sketch spans all K columns (0: none that the
+  // step can reach: past i_max, or after the early-fallback policy's end)
+  int kfull = 0;
+  {
+    int kk = k0;
+    for (int it = 1; it <= i_max; ++it) {
+      const int dd = min(kk + p, K);
+      if (dd == K) { kfull = it; break; }
+      if (td->early_fallback && dd > td->wb_limit) break;
+      kk = min(2 * kk, K);
+    }
+  }
+  // When the track's last step ended at d = K and left its basis, the
+  // full-width iteration runs first.  Its sigma_1^2 >= ... >= sigma_K^2 are
+  // Delta A's, and for any d orthonormal columns Q, ||Q^H Delta A||_F^2 <=
+  // sigma_1^2 + ... + sigma_d^2 (Ky Fan).  So an earlier iteration whose d
+  // leading sigma_j^2 miss the target cannot meet it: it is skipped, which
+  // leaves Alg. 1's outcome as it is (the first iteration that meets the
+  // target decides, with its own Q and Z).  The others run in order as
+  // before; the full-width Z is kept aside (in the capacitance workspace,
+  // unused until the branch) for when none of them meets the target.
+  bool pre = kfull > 1 && warm_in && td->nsig == K && !td->early_fallback;
+  int rk = 0, sweeps_k = 0, rounds_k = 0;
+  double capk = 0.0;
+  float2* const zstash = reinterpret_cast<float2*>(td->Aug);   // K x K fits in (K/2) x (3K/2) double2
+  if (pre) {
+    const double totk = sketch_iteration(kfull, K);
+    if (totk >= Et) {
+      if (K <= 128) jacobi_big<16>(sm, Zm, K, K, &sweeps_k, &rounds_k);
+      else jacobi_big<32>(sm, Zm, K, K, &sweeps_k, &rounds_k);
+      t_jac += clock64() - c_mark; c_mark = clock64();
+      pick_rank_big(sm, Zm, K, K, Et, &rk, &capk, tdg->sig2);
+      for (int e = tid; e < K * K; e += NTH) zstash[e] = Zm[e];
+      if (tid < K) {
+        sm.s2k[tid] = sm.s2[tid];
+        sm.ordk[tid] = sm.order[tid];
+      }
+      if (tid == 0) {
+        double c = 0.0;
+        sm.topk[0] = 0.0;
+        for (int jj = 0; jj < K; ++jj) {
+          c += sm.s2[sm.order[jj]];
+          sm.topk[jj + 1] = c;
+        }
+      }
+      __syncthreads();
+    } else {
+      pre = false;   // (eta = 1 within rounding) the iterations in order
+    }
+  }
+  for (int it = 1; it <= i_max; ++it) {
+    iters = it;
+    d = min(k0 + p, K);
+    if (pre && it == kfull) {
+      // no earlier iteration met the target: the full-width step (its Q is
+      // the stored basis)
+      for (int e = tid; e < K * K; e += NTH) {
+        Zm[e] = zstash[e];
+        Qm[e] = td->Xw[e];
+      }
+      if (tid < K) {
+        sm.s2[tid] = sm.s2k[tid];
+        sm.order[tid] = sm.ordk[tid];
+        tdg->sig2[tid] = sm.s2k[sm.ordk[tid]];
+      }
+      __syncthreads();
+      rotated = true;
+      r = rk;
+      captured = capk;
+      sweeps += sweeps_k;
+      rounds += rounds_k;
+      break;
+    }
+    if (pre && sm.topk[d] < Et * (1.0 - KYFAN_MARGIN)) {
+      k0 = min(2 * k0, K);   // cannot meet the target
+      continue;
+    }
+    const double tot = sketch_iteration(it, d);
     if (tot >= Et) {
       if (K <= 128) jacobi_big<16>(sm, Zm, K, d, &sweeps, &rounds);
       else jacobi_big<32>(sm, Zm, K, d, &sweeps, &rounds);
       t_jac += clock64() - c_mark; c_mark = clock64();
       rotated = true;
       pick_rank_big(sm, Zm, K, d, Et, &r, &captured, tdg->sig2);
-      if (d == K) {
-        // the next full-width step's starting basis (column norms in sm.s2)
-        double smax = 0.0;
-        for (int c = 0; c < K; ++c) smax = fmax(smax, sm.s2[c]);
-        bool ok = smax > 0.0;
-        for (int c = 0; c < K; ++c) ok = ok && sm.s2[c] > BASIS_MIN_REL * smax;
-        if (ok)
-          for (int e = tid; e < K * K; e += NTH) td->Xw[e] = cscale(Zm[e], (float)(1.0 / sqrt(sm.s2[e / K])));
-        if (tid == 0) td->warm = ok ? 1 : 0;
-      }
       break;
     }
     // after the last iteration, or (early-fallback policy) once d is past
@@ -760,6 +837,18 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
       break;
     }
     k0 = min(2 * k0, K);   // d = min(k0 + p, K) is unchanged by the cap
+  }
+  if (rotated && d == K) {
+    // this full-width SVD's normalised columns z_j / sigma_j (norms in
+    // sm.s2): the next full-width step's starting basis
+    double smax = 0.0;
+    for (int c = 0; c < K; ++c) smax = fmax(smax, sm.s2[c]);
+    bool ok = smax > 0.0;
+    for (int c = 0; c < K; ++c) ok = ok && sm.s2[c] > BASIS_MIN_REL * smax;
+    __syncthreads();   // every read of the stored basis above is done
+    if (ok)
+      for (int e = tid; e < K * K; e += NTH) td->Xw[e] = cscale(Zm[e], (float)(1.0 / sqrt(sm.s2[e / K])));
+    if (tid == 0) td->warm = ok ? 1 : 0;
   }
   if (!rotated) {
     if (tid < d) sm.order[tid] = tid;

@@ -116,8 +116,10 @@ def test_resume_keeps_large_full_width_basis():
         assert (ca["qr_columns"], ca["jacobi_sweeps"]) == (cb["qr_columns"], cb["jacobi_sweeps"]), t
         ds = [min(cfg.k_init * 2 ** i + cfg.p, cfg.K) for i in range(ia.iters)]
         if ds[-1] == cfg.K:
+            # no QR at d = K (and none for the earlier iterations that the
+            # full-width sigma_j rule out)
             full += 1
-            assert ca["qr_columns"] == sum(ds[:-1]), t   # no QR at d = K
+            assert ca["qr_columns"] <= sum(ds[:-1]), t
     assert full > 0
     a.destroy()
     b.destroy()
