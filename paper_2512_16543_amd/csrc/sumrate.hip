@@ -72,6 +72,7 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int nt = wid >> 2, ct = wid & 3;          // this wave's tile in the block
   const int r0 = rb * SB, m0 = cb * SB;
+  const bool live = r0 + nt * 16 < K && m0 + ct * 16 < K;   // the wave's tile holds users
   // E of the completed partitions (ns == 1) and of the current one; |W|^2 of
   // the current partition's staged values (rb == 0)
   floatx4 Er = zero4(), Ei = zero4(), pr = zero4(), pi = zero4();
@@ -108,10 +109,12 @@ __global__ __launch_bounds__(SNT) void k_sum_rate(RateJob one, const RateJob* ma
     while (cn < nch && !owned(cn)) ++cn;
     if (cn < nch) fetch(cn * SC);
     const int jc = min(SC, N - c * SC);
-    // this chunk's E(n, m) = sum_j H[n][j] W[j][m], added to its partition
+    // this chunk's E(n, m) = sum_j H[n][j] W[j][m], added to its partition (a
+    // tile wholly past the track's K users has zero operands: it stays zero)
     floatx4 dr = zero4(), di = zero4();
-    ctile16([&](int rr, int j) { return hs[(nt * 16 + rr) * SLD + j]; },
-            [&](int j, int cc) { return ws[j * WLD + ct * 16 + cc]; }, 0, (jc + 3) & ~3, dr, di);
+    if (live)
+      ctile16([&](int rr, int j) { return hs[(nt * 16 + rr) * SLD + j]; },
+              [&](int j, int cc) { return ws[j * WLD + ct * 16 + cc]; }, 0, (jc + 3) & ~3, dr, di);
 #pragma unroll
     for (int v = 0; v < 4; ++v) { pr[v] += dr[v]; pi[v] += di[v]; }
     if (cn >= nch || cn / cpp != q) {
