@@ -688,32 +688,32 @@ __global__ __launch_bounds__(NTH) void k_arsvd_big(ArsvdJob one, const ArsvdJob*
       __syncthreads();
       t_sk += clock64() - c_mark; c_mark = clock64();
     } else {
-    // Y = Delta A Omega, one 16-column tile of Omega at a time
-    for (int ct = 0; ct * 16 < d; ++ct) {
-      const int j0 = 16 * ct;
-      for (int e = tid; e < 16 * K; e += NTH) {
-        const int jj = e / K, i = e - jj * K;
-        sm.u.om[e] = (j0 + jj < d) ? sketch_entry(seed, trk, t, it, i, j0 + jj) : cz();
-      }
-      __syncthreads();
-      for (int rt = wid; rt < ktl; rt += NWV) {
-        floatx4 dr = zero4(), di = zero4();
-        ctile16([&](int i, int k) {
-                  const int row = rt * 16 + i;
-                  return (row < K && k < K) ? dA[(size_t)row * K + k] : cz();
-                },
-                [&](int k, int jj) { return (k < K) ? sm.u.om[jj * K + k] : cz(); }, 0, up4(K), dr, di);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = rt * 16 + tile_row(v), c = j0 + tile_col();
-          if (row < K && c < d) Ym[(size_t)c * K + row] = make_float2(dr[v], di[v]);
+      // Y = Delta A Omega, one 16-column tile of Omega at a time
+      for (int ct = 0; ct * 16 < d; ++ct) {
+        const int j0 = 16 * ct;
+        for (int e = tid; e < 16 * K; e += NTH) {
+          const int jj = e / K, i = e - jj * K;
+          sm.u.om[e] = (j0 + jj < d) ? sketch_entry(seed, trk, t, it, i, j0 + jj) : cz();
         }
+        __syncthreads();
+        for (int rt = wid; rt < ktl; rt += NWV) {
+          floatx4 dr = zero4(), di = zero4();
+          ctile16([&](int i, int k) {
+                    const int row = rt * 16 + i;
+                    return (row < K && k < K) ? dA[(size_t)row * K + k] : cz();
+                  },
+                  [&](int k, int jj) { return (k < K) ? sm.u.om[jj * K + k] : cz(); }, 0, up4(K), dr, di);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = rt * 16 + tile_row(v), c = j0 + tile_col();
+            if (row < K && c < d) Ym[(size_t)c * K + row] = make_float2(dr[v], di[v]);
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
-    }
-    t_sk += clock64() - c_mark; c_mark = clock64();
-    qr_big(sm, Ym, Qm, K, d);
-    qrcols += d;
+      t_sk += clock64() - c_mark; c_mark = clock64();
+      qr_big(sm, Ym, Qm, K, d);
+      qrcols += d;
     }
     // Z = Delta A^H Q = B^H and ||Z||_F^2 (Delta A + R need not be Hermitian)
     double zp = 0.0;
