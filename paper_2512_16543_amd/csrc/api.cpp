@@ -511,7 +511,6 @@ rzf_status rzf_update(rzf_track* t, const rzf_c32* H_t, int ldh, double tol, rzf
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
   hipStream_t s = c->stream;
-  const int K = t->K, N = t->N;
   const float2* Hf = reinterpret_cast<const float2*>(H_t);
   float2* Wf = reinterpret_cast<float2*>(W);
   DevInfo* slot = nullptr;
