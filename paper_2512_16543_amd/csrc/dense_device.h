@@ -260,7 +260,7 @@ __device__ __forceinline__ void pivot_inverse16(const LD& ld, T* pb, int* bad) {
 // is not a positive finite number (1: not HPD, 2: non-finite).
 __device__ void gj_inverse_hpd_mfma(float2* a, int K, int ld, float2* xs, float2* ys, float2* pb,
                                     int* bad) {
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = threadIdx.x, wid = tid >> 6;
   const int KP = (K + 15) & ~15, nb = KP / 16;
   for (int e = tid; e < KP * KP; e += blockDim.x) {
     const int i = e / KP, j = e - i * KP;
