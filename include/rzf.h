@@ -407,7 +407,8 @@ rzf_status rzf_track_destroy(rzf_track* tr);
 /* Checkpoint / resume of a track (the state Alg. 2 carries between
  * snapshots: A^-1 and the previous snapshot, plus the step counters, the
  * previous k_est, the width and iteration count of the last SVD, the
- * error-feedback residual and the full-width SVD basis).  rzf_track_export
+ * error-feedback residual, the full-width SVD basis and the last narrower
+ * SVD's basis).  rzf_track_export
  * with buf == NULL stores the blob size in
  * *bytes; otherwise it synchronises the context's stream and writes the blob
  * (host memory, *bytes >= that size, else RZF_E_INVALID with the size in

@@ -44,7 +44,7 @@ size_t scratch_bytes() {
 }
 
 struct Layout {
-  size_t desc, ainv, hprev, anew, da, a64, wpart, rfb, xw, ym, qm, zm, pm, aug, total;
+  size_t desc, ainv, hprev, anew, da, a64, wpart, rfb, xw, xd, ym, qm, zm, pm, aug, total;
 };
 
 Layout track_layout(int K, int N) {
@@ -59,6 +59,9 @@ Layout track_layout(int K, int N) {
   L.wpart = o; o += align_up(sizeof(double) * precoder_scratch(N));
   L.rfb = o; o += align_up(sizeof(float2) * K * K);
   L.xw = o; o += align_up(sizeof(float2) * K * K);   // full-width SVD basis
+  if (K <= KS) {
+    L.xd = o; o += align_up(sizeof(float2) * K * K);   // basis of the last narrower SVD
+  }
   if (K > KS) {
     // working set of the large-track kernels
     L.ym = o; o += align_up(sizeof(float2) * K * K);
@@ -293,6 +296,7 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
   d.wpart = reinterpret_cast<double*>(base + L.wpart);
   d.Rfb = reinterpret_cast<float2*>(base + L.rfb);
   d.Xw = reinterpret_cast<float2*>(base + L.xw);
+  if (K <= KS) d.Xd = reinterpret_cast<float2*>(base + L.xd);
   if (K > KS) {
     d.Ym = reinterpret_cast<float2*>(base + L.ym);
     d.Qm = reinterpret_cast<float2*>(base + L.qm);
@@ -309,24 +313,26 @@ rzf_track* track_new(rzf_ctx* c, int K, int N, const rzf_params& prm, double alp
 
 // Checkpoint blob of one track: this header, then A^-1 (K x K) and H_prev
 // (K x N) row-major, the error-feedback residual R (K x K, row-major) and
-// the full-width SVD basis (K x K, column-major), all complex64.
+// the full-width SVD basis and that of the last narrower SVD (K x K each,
+// column-major; the second zero for K > KS), all complex64.
 struct TrackBlob {
   char magic[8];
   uint32_t version, header_bytes;
   int32_t K, N;
   rzf_params prm;
   double alpha;
-  int32_t step, since_reset, last_r, warm, warm_age;
+  int32_t step, since_reset, last_r, warm, dwarm;
   int32_t nsig, spec_hint, pad;   // d of the last SVD; Alg. 1 iterations of the last step
 };
 const char BLOB_MAGIC[8] = {'R', 'Z', 'F', 'T', 'R', 'A', 'C', 'K'};
-constexpr uint32_t BLOB_VERSION = 5;   // 3: params gained early_fallback, precision, error
+constexpr uint32_t BLOB_VERSION = 6;   // 3: params gained early_fallback, precision, error
                                        // feedback; the residual R follows H_prev.
                                        // 4: the full-width SVD basis follows R.
-                                       // 5: nsig and spec_hint; the basis for every K
+                                       // 5: nsig and spec_hint; the basis for every K.
+                                       // 6: the narrower basis (dwarm columns)
 
 size_t blob_bytes(int K, int N) {
-  return sizeof(TrackBlob) + sizeof(float2) * (3 * (size_t)K * K + (size_t)K * N);
+  return sizeof(TrackBlob) + sizeof(float2) * (4 * (size_t)K * K + (size_t)K * N);
 }
 
 }  // namespace
@@ -1235,7 +1241,7 @@ rzf_status rzf_track_export(rzf_track* t, void* buf, size_t* bytes) {
   h.step = t->t; h.since_reset = t->since_reset;
   HIP_OK(hipMemcpy(&h.last_r, &t->d_desc->last_r, sizeof(int), hipMemcpyDeviceToHost));
   HIP_OK(hipMemcpy(&h.warm, &t->d_desc->warm, sizeof(int), hipMemcpyDeviceToHost));
-  HIP_OK(hipMemcpy(&h.warm_age, &t->d_desc->warm_age, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(&h.dwarm, &t->d_desc->dwarm, sizeof(int), hipMemcpyDeviceToHost));
   HIP_OK(hipMemcpy(&h.nsig, &t->d_desc->nsig, sizeof(int), hipMemcpyDeviceToHost));
   HIP_OK(hipMemcpy(&h.spec_hint, &t->d_desc->spec_hint, sizeof(int), hipMemcpyDeviceToHost));
   char* p = static_cast<char*>(buf);
@@ -1249,6 +1255,11 @@ rzf_status rzf_track_export(rzf_track* t, void* buf, size_t* bytes) {
   p += sizeof(float2) * t->K * t->K;
   if (t->h_desc.Xw)
     HIP_OK(hipMemcpy(p, t->h_desc.Xw, sizeof(float2) * t->K * t->K, hipMemcpyDeviceToHost));
+  else
+    std::memset(p, 0, sizeof(float2) * t->K * t->K);
+  p += sizeof(float2) * t->K * t->K;
+  if (t->h_desc.Xd)
+    HIP_OK(hipMemcpy(p, t->h_desc.Xd, sizeof(float2) * t->K * t->K, hipMemcpyDeviceToHost));
   else
     std::memset(p, 0, sizeof(float2) * t->K * t->K);
   *bytes = need;
@@ -1268,7 +1279,8 @@ rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track
   if (bytes < blob_bytes(h.K, h.N)) return RZF_E_INVALID;
   if (!params_valid(&h.prm) || !params_fit(&h.prm, h.K) || !std::isfinite(h.alpha) || h.alpha < 0.0 || h.step < 0 ||
       h.since_reset < 0 || h.last_r < 0 || h.last_r > h.K || (h.warm != 0 && h.warm != 1) ||
-      h.warm_age < 0 || h.nsig < 0 || h.nsig > h.K || h.spec_hint < 0 || h.spec_hint > 64)
+      h.dwarm < 0 || h.dwarm >= h.K || (h.dwarm > 0 && h.K > KS) || h.nsig < 0 || h.nsig > h.K ||
+      h.spec_hint < 0 || h.spec_hint > 64)
     return RZF_E_INVALID;
   std::lock_guard<std::mutex> lk(c->mu);
   HIP_OK(hipSetDevice(c->device));
@@ -1282,7 +1294,7 @@ rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track
   t->h_desc.t_dev = h.step;
   t->h_desc.seq_dev += (unsigned)h.step;
   t->h_desc.warm = h.warm;
-  t->h_desc.warm_age = h.warm_age;
+  t->h_desc.dwarm = h.dwarm;
   t->h_desc.nsig = h.nsig;
   t->h_desc.spec_hint = h.spec_hint;
   const char* p = static_cast<const char*>(buf) + sizeof(h);
@@ -1294,6 +1306,9 @@ rzf_status rzf_track_import(rzf_ctx* c, const void* buf, size_t bytes, rzf_track
                       sizeof(float2) * h.K * h.K, hipMemcpyHostToDevice) == hipSuccess &&
             (!t->h_desc.Xw ||
              hipMemcpy(t->h_desc.Xw, p + sizeof(float2) * (2 * (size_t)h.K * h.K + (size_t)h.K * h.N),
+                       sizeof(float2) * h.K * h.K, hipMemcpyHostToDevice) == hipSuccess) &&
+            (!t->h_desc.Xd ||
+             hipMemcpy(t->h_desc.Xd, p + sizeof(float2) * (3 * (size_t)h.K * h.K + (size_t)h.K * h.N),
                        sizeof(float2) * h.K * h.K, hipMemcpyHostToDevice) == hipSuccess);
   if (!ok) {
     arena_free(c, t->off, t->bytes);

@@ -350,6 +350,116 @@ __device__ void jacobi_svd(Shared& sm, int K, int d, int* sweeps_out, int* round
   *rounds_out += rounds;
 }
 
+// Rotation within the sketch's subspace before a Jacobi SVD below full width
+// (d < K).  Q (b1, K x d) is one orthonormal basis of range(Delta A Omega);
+// for a d x d unitary W, QW spans the same subspace and Z W = Delta A^H (QW)
+// has the same singular values, so the rank, U_r (formed through Q Q^H), the
+// captured energy and the update are those of Q (up to rounding).  W is the
+// unitary factor of the Householder QR of Q^H X, X the d leading columns of
+// the track's last narrower SVD basis (Xd: its normalised columns by
+// descending sigma), so that QW spans, column by column, the sketch's
+// subspace lined up with the previous step's singular directions, and the
+// Jacobi passes on Z W start close to convergence.  Householder's W is
+// unitary to rounding whatever the conditioning of Q^H X.  The factorisation
+// runs in pm/tm (d x d, column-major, ld LDK); W is formed in Xd, which the
+// basis of this step's SVD replaces afterwards.
+__device__ void warm_rotate(Shared& sm, float2* Xd, int K, int d) {
+  float2* const b1 = sm.b1;
+  float2* const b2 = sm.b2;
+  float2* const g = sm.pm;   // pm and tm are contiguous: d <= KS columns of LDK
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // G = Q^H X
+  lds_gemm(d, d, K,
+           [&](int i, int k) { return (i < d && k < K) ? cconj(b1[i * LDK + k]) : cz(); },
+           [&](int k, int c) { return (k < K && c < d) ? Xd[(size_t)c * K + k] : cz(); },
+           [&](int i, int c, float2 v) { g[c * LDK + i] = v; });
+  __syncthreads();
+  // Householder QR of G, as for the sketch (reflector j over column j; one
+  // barrier per column), rows >= d masked
+  if (wid == 0) reflector_from((lane < d) ? g[lane] : cz(), g, 0, d);
+  for (int j = 0; j < d; ++j) {
+    __syncthreads();
+    const float2 w = (lane < d) ? g[j * LDK + lane] : cz();
+    float2 y[KS / NWV];
+    float dr[KS / NWV], di[KS / NWV];
+#pragma unroll
+    for (int q = 0; q < KS / NWV; ++q) {
+      const int c = j + 1 + wid + NWV * q;
+      y[q] = (c < d && lane < d) ? g[c * LDK + lane] : cz();
+      dr[q] = w.x * y[q].x + w.y * y[q].y;     // conj(w) y
+      di[q] = w.x * y[q].y - w.y * y[q].x;
+    }
+#pragma unroll
+    for (int q = 0; q < KS / NWV; ++q) {
+      const int c = j + 1 + wid + NWV * q;
+      if (c >= d) break;
+      const float fr = 2.f * wave_sumf(dr[q]), fi = 2.f * wave_sumf(di[q]);
+      y[q].x -= w.x * fr - w.y * fi;
+      y[q].y -= w.x * fi + w.y * fr;
+      if (lane < d) g[c * LDK + lane] = y[q];
+    }
+    if (wid == 0 && j + 1 < d) reflector_from(y[0], g, j + 1, d);
+  }
+  __syncthreads();
+  // W = H_0 ... H_{d-1} (square): column c is H_0 ... H_c e_c, formed by its
+  // wave with no barrier, into Xd (ld K)
+  {
+    float2 y[KS / NWV];
+    int cmax = -1;
+#pragma unroll
+    for (int q = 0; q < KS / NWV; ++q) {
+      const int c = wid + NWV * q;
+      y[q] = (lane == c) ? make_float2(1.f, 0.f) : cz();
+      if (c < d) cmax = c;
+    }
+    for (int j = cmax; j >= 0; --j) {
+      const float2 w = (lane < d) ? g[j * LDK + lane] : cz();
+#pragma unroll
+      for (int q = 0; q < KS / NWV; ++q) {
+        const int c = wid + NWV * q;
+        if (c >= d || c < j) continue;
+        float dr = w.x * y[q].x + w.y * y[q].y;
+        float di = w.x * y[q].y - w.y * y[q].x;
+        dr = wave_sumf(dr);
+        di = wave_sumf(di);
+        const float fr = 2.f * dr, fi = 2.f * di;
+        y[q].x -= w.x * fr - w.y * fi;
+        y[q].y -= w.x * fi + w.y * fr;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KS / NWV; ++q) {
+      const int c = wid + NWV * q;
+      if (c < d && lane < d) Xd[(size_t)c * K + lane] = y[q];
+    }
+  }
+  __syncthreads();
+  // Z <- Z W, each wave's tile held in registers until every wave has read Z
+  const int kt = (K + 15) / 16, dt = (d + 15) / 16;
+  floatx4 dr = zero4(), di = zero4();
+  const int ti = wid / dt, tj = wid - (wid / dt) * dt;
+  const bool mine = wid < kt * dt;
+  if (mine)
+    ctile16([&](int rr, int k) {
+              const int i = ti * 16 + rr;
+              return (i < K && k < d) ? b2[k * LDK + i] : cz();
+            },
+            [&](int k, int cc) {
+              const int c = tj * 16 + cc;
+              return (k < d && c < d) ? Xd[(size_t)c * K + k] : cz();
+            },
+            0, (d + 3) & ~3, dr, di);
+  __syncthreads();
+  if (mine) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti * 16 + tile_row(v), c = tj * 16 + tile_col();
+      if (i < K && c < d) b2[c * LDK + i] = make_float2(dr[v], di[v]);
+    }
+  }
+  __syncthreads();
+}
+
 // Squared norms of the d columns of Z (b2) into sm.s2, one 16-lane row per column.
 __device__ void column_norms(Shared& sm, int K, int d) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -583,6 +693,9 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   // then yields the truncated SVD of Delta A whatever Q is: such an iteration
   // starts from the track's basis of its last full-width SVD when it has one
   const bool warm_ok = td->warm != 0;
+  // columns of the last narrower SVD's basis (Xd) that a Jacobi below full
+  // width may start from (warm_rotate)
+  const int dwarm = td->Xd != nullptr ? td->dwarm : 0;
   bool basis = false;   // the SVD ran at d = K
   // the first iteration whose sketch spans all K columns (0: none that the
   // step can reach: past i_max, or after the early-fallback policy's end)
@@ -893,6 +1006,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
         if (hit) {
           found = true;
           basis = d == K;
+          if (d < K && dwarm >= d) warm_rotate(sm, td->Xd, K, d);
           jacobi_svd(sm, K, d, &sweeps, &rounds);
           t_jac += clock64() - c_mark; c_mark = clock64();
           rotated = true;
@@ -990,6 +1104,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       if (tot >= Et) {
         found = true;
         basis = d == K;
+        if (d < K && dwarm >= d) warm_rotate(sm, td->Xd, K, d);
         jacobi_svd(sm, K, d, &sweeps, &rounds);
         t_jac += clock64() - c_mark; c_mark = clock64();
         rotated = true;
@@ -1036,6 +1151,27 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
         const int j = e / K, i = e - j * K;
         o_Xw[e] = cscale(b2[j * LDK + i], sm.bsc[j]);
       }
+  }
+  if (rotated && d < K && td->Xd != nullptr) {
+    // this SVD's normalised columns z_j / sigma_j by descending sigma_j: the
+    // start of the next narrower Jacobi (warm_rotate), unless a column is
+    // numerically zero
+    if (tid < 64) {
+      const double v = lane < d ? sm.s2[lane] : 0.0;
+      double smax = v;
+      for (int j = 0; j < d; ++j) smax = fmax(smax, readlane_d(v, j));
+      const bool good = lane >= d || (smax > 0.0 && v > BASIS_MIN_REL * smax);
+      if (lane == 0) sm.bok = __all(good) && smax > 0.0;
+    }
+    __syncthreads();
+    const bool ok = sm.bok != 0;
+    if (ok)
+      for (int e = tid; e < K * d; e += NTH) {
+        const int m = e / K, i = e - m * K, j = sm.order[m];
+        td->Xd[e] = cscale(b2[j * LDK + i], (float)(1.0 / sqrt(sm.s2[j])));
+      }
+    if (tid == 0) td->dwarm = ok ? d : 0;
+    __syncthreads();
   }
   if (rotated && use_wb && basis) {
     // U_r = Delta A Z_r Sigma_r^-2 (Q is unitary at d = K); every retained

@@ -31,6 +31,8 @@ struct TrackDesc {
   float2* Rfb;     // K x K, ld K: error-feedback residual (zero unless the policy is on)
   float2* Xw;      // K x K, column-major ld K: normalised columns z_j / sigma_j
                    // of the last full-width (d = K) SVD, the next one's starting point
+  float2* Xd;      // K x K, column-major ld K (K <= KS): the last SVD below full width,
+                   // its dwarm normalised columns z_j / sigma_j by descending sigma_j
   uint64_t seed, track_id;
   float2* Ainv;    // K x K, ld K: stored inverse
   float2* Hprev;   // K x N, ld N: previous snapshot
@@ -49,7 +51,7 @@ struct TrackDesc {
   int last_r;
   int spec_hint;   // Alg. 1 iterations of the last step that ran it (speculation depth)
   int warm;        // Xw holds a basis
-  int warm_age;    // kept in the checkpoint blob; not used by the kernels
+  int dwarm;       // columns of Xd that hold a basis (0: none)
   int hold;        // the current step met a non-finite snapshot (or its reset failed):
                    // the precoder keeps H_prev, so the track's state stays as it was
   DevInfo info;

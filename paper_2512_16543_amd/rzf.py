@@ -577,12 +577,12 @@ class Track:
 
     def residual(self):
         """The error-feedback residual R (K x K complex64 numpy array): the
-        K*K entries of the checkpoint blob before its last K*K (the
-        full-width SVD basis)."""
+        K*K entries of the checkpoint blob before its last 2 K*K (the two
+        SVD bases)."""
         import numpy as np
         blob = self.export()
         n = self.K * self.K * 8
-        return np.frombuffer(blob[len(blob) - 2 * n:len(blob) - n],
+        return np.frombuffer(blob[len(blob) - 3 * n:len(blob) - 2 * n],
                              dtype=np.complex64).reshape(self.K, self.K).copy()
 
     def destroy(self):

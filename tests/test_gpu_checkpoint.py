@@ -88,6 +88,39 @@ def test_resume_keeps_full_width_basis():
     b.destroy()
     ctx.close()
 
+def test_resume_keeps_narrower_basis():
+    # at eta = 0.99 the K = 64 track's steps decide at d = 37 < K: the Jacobi
+    # there starts from the sketch's Q turned within its span towards the last
+    # such SVD's directions, which the blob carries
+    cfg = wl.CONFIGS["c2"]
+    Hs = torch.from_numpy(wl.make_track(wl.with_overrides(cfg, steps=12)).snapshots()
+                          .astype(np.complex64)).cuda()
+    ctx = rzf.Context(0, 64 << 20)
+    prm = rzf.default_params(k_init=cfg.k_init, p=cfg.p, seed=cfg.seed, reset_period=0)
+    a = ctx.init(Hs[0], cfg.alpha, prm)
+    Wa = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device="cuda")
+    Wb = torch.empty_like(Wa)
+    for t in range(1, 5):
+        a.update(Hs[t], 0.99, Wa)
+    ctx.sync()
+    b = ctx.import_track(a.export())
+    narrow = 0
+    for t in range(5, 13):
+        ia = a.update(Hs[t], 0.99, Wa)
+        ib = b.update(Hs[t], 0.99, Wb)
+        ctx.sync()
+        assert (ia.r, ia.iters, ia.path) == (ib.r, ib.iters, ib.path), t
+        assert torch.equal(Wa, Wb), t
+        assert torch.equal(a.inverse(), b.inverse()), t
+        ca, cb = a.counters(), b.counters()
+        assert (ca["qr_columns"], ca["jacobi_sweeps"]) == (cb["qr_columns"], cb["jacobi_sweeps"]), t
+        narrow += min(cfg.k_init * 2 ** (ia.iters - 1) + cfg.p, cfg.K) < cfg.K
+    assert narrow > 0
+    a.destroy()
+    b.destroy()
+    ctx.close()
+
+
 def test_resume_keeps_large_full_width_basis():
     # a K = 256 track (the 32x32-array workload) at eta = 0.999 runs to d = K
     # every step; from its second step the full-width iteration starts from the
