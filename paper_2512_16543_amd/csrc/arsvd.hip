@@ -106,6 +106,7 @@ struct Shared {
   float2 pm[WB_RMAX * LDK];      // U (after the SVD), column-major
   float2 tm[WB_RMAX * LDK];      // Q^H Delta A Z_r, then P = A^-1 U, column-major
   double s2[KS];                 // ||z_j||^2
+  double is2[KS];                // 1 / sigma_j^2 of the retained columns, by rank
   double2 gjm[2][WB_RMAX];       // Gauss-Jordan: column j of step j (two steps in flight)
   double2 gjinv[2];              // Gauss-Jordan: 1 / pivot
   double red[NWV];
@@ -487,10 +488,13 @@ __device__ void pick_rank(Shared& sm, int K, int d, double Et, int* r_out, doubl
   if (tid < 64) {
     // wave 0, lane j holds sigma_j^2; its rank counts the larger values
     // (and the equal ones of lower index)
+    // (the other values read from LDS, every lane the same address: the
+    // loads issue back to back, unlike a chain of lane reads)
     const double v = lane < d ? sm.s2[lane] : -1.0;
     int rank = 0;
+#pragma unroll 8
     for (int k = 0; k < d; ++k) {
-      const double w = readlane_d(v, k);
+      const double w = sm.s2[k];
       rank += (w > v) || (w == v && k < lane);
     }
     if (lane < d) sm.order[rank] = lane;
@@ -888,30 +892,32 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     for (int m = 1; m < itn; ++m) kk = min(2 * kk, K);   // d depends on min(k0 + p, K) only
     const int dd = min(kk + p, K);
     const double tot = sketch_iteration(itn, dd);
-    // the earlier iterations' posted energy tests (tid 0): 2 if one of them
-    // meets the target (it, not this one, decides the step), 1 if all are
-    // posted and none does, 0 if some are still missing after the wait
-    // The tags are polled with relaxed loads; an acquire fence follows the
-    // first match of each tag only (an agent-scope acquire invalidates the
-    // XCD's non-coherent cache lines, too costly on every poll).
+    // the earlier iterations' posted energy tests (wave 0, lane j for
+    // iteration j + 1, every lane returns the same): 2 if one of them meets
+    // the target (it, not this one, decides the step), 1 if all are posted
+    // and none does, 0 if some are still missing after the wait.  The tags
+    // are polled with relaxed loads, all at once; one acquire fence follows
+    // a poll that found new ones (an agent-scope acquire invalidates the
+    // XCD's non-coherent cache lines, too costly on every poll), then their
+    // values are read, again all at once.
     auto poll_earlier = [&](bool wait) -> int {
       const long long t_end = wall_clock64() + (wait ? SPEC_WAIT_TICKS : 0);
-      unsigned seen = 0;   // bit j: iteration j + 1 is posted and misses the target
+      const bool mine = lane + 1 < kfull;
+      bool seen = !mine;   // posted and missing the target, or no iteration
       for (;;) {
-        bool all = true;
-        for (int j = 0; j + 1 < kfull; ++j) {
-          if (seen & (1u << j)) continue;
-          if (__hip_atomic_load(&tags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == seq) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const bool hit = !seen && __hip_atomic_load(&tags[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == seq;
+        if (__builtin_amdgcn_ballot_w64(hit) != 0) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          bool meets = false;
+          if (hit) {
             const unsigned long long bits = __hip_atomic_load(
-                reinterpret_cast<unsigned long long*>(&spec_d[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (__longlong_as_double((long long)bits) >= Et) return 2;
-            seen |= 1u << j;
-          } else {
-            all = false;
+                reinterpret_cast<unsigned long long*>(&spec_d[lane]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            meets = __longlong_as_double((long long)bits) >= Et;
           }
+          if (__builtin_amdgcn_ballot_w64(meets) != 0) return 2;
+          seen = seen || hit;
         }
-        if (all) return 1;
+        if (__builtin_amdgcn_ballot_w64(!seen) == 0) return 1;
         if (wall_clock64() >= t_end) return 0;
         __builtin_amdgcn_s_sleep(8);
       }
@@ -926,7 +932,10 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       // target: read the earlier iterations' posted tests (waiting, bounded,
       // when the last step ended before d = K or there was none), and leave
       // the step to the second phase if one of them decides
-      if (tid == 0) sm.found = poll_earlier(td->spec_hint < kfull) == 2;
+      if (wid == 0) {
+        const int pr = poll_earlier(td->spec_hint < kfull);
+        if (lane == 0) sm.found = pr == 2;
+      }
       __syncthreads();
       if (sm.found) return;
     }
@@ -953,7 +962,10 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     // iteration is known to miss the target (the second phase then has
     // nothing left to do), else to the staging area for the second phase
     __syncthreads();
-    if (tid == 0) sm.found = kfull > 1 ? poll_earlier(true) : 1;
+    if (wid == 0) {
+      const int pr = kfull > 1 ? poll_earlier(true) : 1;
+      if (lane == 0) sm.found = pr;
+    }
     __syncthreads();
     const int mode = sm.found;
     if (mode == 2) return;
@@ -1139,7 +1151,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     if (tid < 64) {
       const double v = lane < K ? sm.s2[lane] : 0.0;
       double smax = v;
-      for (int j = 0; j < K; ++j) smax = fmax(smax, readlane_d(v, j));
+#pragma unroll 8
+      for (int j = 0; j < K; ++j) smax = fmax(smax, sm.s2[j]);
       const bool ok = smax > 0.0 && __all(lane >= K || v > BASIS_MIN_REL * smax);
       sm.bsc[lane] = ok && lane < K ? (float)(1.0 / sqrt(v)) : 0.f;
       if (lane == 0) sm.bok = ok;
@@ -1159,7 +1172,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     if (tid < 64) {
       const double v = lane < d ? sm.s2[lane] : 0.0;
       double smax = v;
-      for (int j = 0; j < d; ++j) smax = fmax(smax, readlane_d(v, j));
+#pragma unroll 8
+      for (int j = 0; j < d; ++j) smax = fmax(smax, sm.s2[j]);
       const bool good = lane >= d || (smax > 0.0 && v > BASIS_MIN_REL * smax);
       if (lane == 0) sm.bok = __all(good) && smax > 0.0;
     }
@@ -1173,6 +1187,10 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     if (tid == 0) td->dwarm = ok ? d : 0;
     __syncthreads();
   }
+  if (rotated && use_wb) {
+    if (tid < r) sm.is2[tid] = 1.0 / sm.s2[sm.order[tid]];
+    __syncthreads();
+  }
   if (rotated && use_wb && basis) {
     // U_r = Delta A Z_r Sigma_r^-2 (Q is unitary at d = K); every retained
     // sigma_j is positive
@@ -1181,8 +1199,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
              [&](int i, int k) { return (i < K && k < K) ? b0[i * LDK + k] : cz(); },
              [&](int k, int c) { return (k < K && c < r) ? b2[ord[c] * LDK + k] : cz(); },
              [&](int i, int c, float2 v) {
-               const double s2 = sm.s2[ord[c]];
-               pm[c * LDK + i] = make_float2((float)(v.x / s2), (float)(v.y / s2));
+               const double is2 = sm.is2[c];
+               pm[c * LDK + i] = make_float2((float)(v.x * is2), (float)(v.y * is2));
              });
     __syncthreads();
   } else if (rotated && use_wb) {
@@ -1203,8 +1221,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
              [&](int i, int j) { return (i < K && j < d) ? b1[j * LDK + i] : cz(); },
              [&](int j, int c) { return (j < d && c < r) ? tm[c * LDK + j] : cz(); },
              [&](int i, int c, float2 v) {
-               const double s2 = sm.s2[ord[c]];
-               pm[c * LDK + i] = make_float2((float)(v.x / s2), (float)(v.y / s2));
+               const double is2 = sm.is2[c];
+               pm[c * LDK + i] = make_float2((float)(v.x * is2), (float)(v.y * is2));
              });
     __syncthreads();
   }
@@ -1306,19 +1324,34 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       }
       for (int a = tid; a < r; a += NTH) aug[a * ldg + a].x -= 1.0;   // C -> E
       __syncthreads();
+      // this lane's matrix-core operand values of E (row ti 16 + lane % 16,
+      // column 4 s + lane / 16 at step s), in FP32, held for every pass
+      const int el = lane & 15, ek = lane >> 4;
+      float2 ea[WB_RMAX / 4];
+#pragma unroll
+      for (int st = 0; st < WB_RMAX / 4; ++st) {
+        const int a = ti * 16 + el, k = 4 * st + ek;
+        ea[st] = (xtile && a < r && k < r) ? d2f(aug[a * ldg + k]) : cz();
+      }
       for (int it = 0; it < nit; ++it) {
         double2 acc[4] = {mreg[0], mreg[1], mreg[2], mreg[3]};
         if (xtile) {
-          floatx4 dr = zero4(), di = zero4();
-          ctile16([&](int rr, int k) {
-                    const int a = ti * 16 + rr;
-                    return (a < r && k < r) ? d2f(aug[a * ldg + k]) : cz();
-                  },
-                  [&](int k, int cc) {
-                    const int j = tj * 16 + cc;
-                    return (k < r && j < K) ? d2f(aug[k * ldg + r + j]) : cz();
-                  },
-                  0, r, dr, di);
+          // E X for this tile: the products of ctile16 with E's values from
+          // registers, the four real products in independent accumulators
+          floatx4 xx = zero4(), yy = zero4(), xy = zero4(), yx = zero4();
+          const int j = tj * 16 + el;
+#pragma unroll
+          for (int st = 0; st < WB_RMAX / 4; ++st) {
+            if (4 * st < r) {
+              const int k = 4 * st + ek;
+              const float2 b = (k < r && j < K) ? d2f(aug[k * ldg + r + j]) : cz();
+              xx = mfma4(ea[st].x, b.x, xx);
+              yy = mfma4(ea[st].y, b.y, yy);
+              xy = mfma4(ea[st].x, b.y, xy);
+              yx = mfma4(ea[st].y, b.x, yx);
+            }
+          }
+          const floatx4 dr = xx - yy, di = xy + yx;
 #pragma unroll
           for (int v = 0; v < 4; ++v) acc[v] = make_double2(acc[v].x - (double)dr[v], acc[v].y - (double)di[v]);
         }
