@@ -79,6 +79,11 @@ constexpr long long SPEC_WAIT_TICKS = 10000;
 // FP32 matrix cores and keep X in FP64: the product's rounding, about
 // 2^-24 ||E|| ||X|| <= 2^-26 ||X|| per pass, stays below X's FP32 rounding.
 constexpr double NEUMANN_MAX = 0.25;
+// narrowest SVD that starts from the sketch's Q turned towards the last
+// narrower SVD (warm_rotate): below it the rotation, one barrier per column,
+// costs more than the Jacobi passes it saves (measured at c2: a gain at
+// d = 37, a loss of 2-5 % of the step at d = 9 .. 21)
+constexpr int WARM_ROTATE_MIN_D = 32;
 constexpr int NEUMANN_BITS = 30;
 
 static_assert(2 * WB_RMAX >= KS, "pm and tm together hold a K x K matrix");
@@ -1018,7 +1023,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
         if (hit) {
           found = true;
           basis = d == K;
-          if (d < K && dwarm >= d) warm_rotate(sm, td->Xd, K, d);
+          if (d < K && d >= WARM_ROTATE_MIN_D && dwarm >= d) warm_rotate(sm, td->Xd, K, d);
           jacobi_svd(sm, K, d, &sweeps, &rounds);
           t_jac += clock64() - c_mark; c_mark = clock64();
           rotated = true;
@@ -1116,7 +1121,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
       if (tot >= Et) {
         found = true;
         basis = d == K;
-        if (d < K && dwarm >= d) warm_rotate(sm, td->Xd, K, d);
+        if (d < K && d >= WARM_ROTATE_MIN_D && dwarm >= d) warm_rotate(sm, td->Xd, K, d);
         jacobi_svd(sm, K, d, &sweeps, &rounds);
         t_jac += clock64() - c_mark; c_mark = clock64();
         rotated = true;
@@ -1165,7 +1170,7 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
         o_Xw[e] = cscale(b2[j * LDK + i], sm.bsc[j]);
       }
   }
-  if (rotated && d < K && td->Xd != nullptr) {
+  if (rotated && d < K && d >= WARM_ROTATE_MIN_D && td->Xd != nullptr) {
     // this SVD's normalised columns z_j / sigma_j by descending sigma_j: the
     // start of the next narrower Jacobi (warm_rotate), unless a column is
     // numerically zero

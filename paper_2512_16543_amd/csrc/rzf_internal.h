@@ -31,8 +31,9 @@ struct TrackDesc {
   float2* Rfb;     // K x K, ld K: error-feedback residual (zero unless the policy is on)
   float2* Xw;      // K x K, column-major ld K: normalised columns z_j / sigma_j
                    // of the last full-width (d = K) SVD, the next one's starting point
-  float2* Xd;      // K x K, column-major ld K (K <= KS): the last SVD below full width,
-                   // its dwarm normalised columns z_j / sigma_j by descending sigma_j
+  float2* Xd;      // K x K, column-major ld K (K <= KS): the last SVD below full width
+                   // (and at least 32 wide), its dwarm normalised columns z_j / sigma_j
+                   // by descending sigma_j
   uint64_t seed, track_id;
   float2* Ainv;    // K x K, ld K: stored inverse
   float2* Hprev;   // K x N, ld N: previous snapshot
