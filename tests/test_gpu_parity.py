@@ -345,6 +345,28 @@ def test_update_c2_full_width_basis(ctx):
     assert np.mean([c["jacobi_sweeps"] for c in full[1:]]) < 0.8 * full[0]["jacobi_sweeps"]
 
 
+def test_update_c2_narrower_basis(ctx):
+    # eta = 0.99 at K = 64 decides at d = 37 < K: from the second such step on
+    # the Jacobi starts from the sketch's Q turned within its span towards the
+    # last such SVD (the same subspace, so one-step parity with the oracle
+    # holds throughout), and needs fewer passes than the first step's
+    cfg = wl.CONFIGS["c2"]
+    recs = run_track(ctx, cfg, 16, 0.99, dict(reset_period=0))
+    _assert_recs(recs)
+    Hs = dev(c64(wl.make_track(wl.with_overrides(cfg, steps=12)).snapshots()))
+    tr = ctx.init(Hs[0], cfg.alpha, rzf.default_params(**_params(cfg, reset_period=0)))
+    W = torch.empty(cfg.N, cfg.K, dtype=torch.complex64, device="cuda")
+    narrow = []   # counters of the steps decided at d = 37
+    for t in range(1, 13):
+        info = tr.update(Hs[t], 0.99, W)
+        ctx.sync()
+        if info.path == rzf.PATH_WB and info.d == 37:
+            narrow.append(tr.counters())
+    tr.destroy()
+    assert len(narrow) >= 8
+    assert np.mean([c["jacobi_sweeps"] for c in narrow[1:]]) < 0.8 * narrow[0]["jacobi_sweeps"]
+
+
 def test_update_early_fallback_policy(ctx):
     # eta = 0.999 at K = 64: d = 37 > K/2 misses the target, so the policy
     # inverts directly there instead of running on to d = 64
