@@ -649,7 +649,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
   // values) and loads Delta A only when it goes on past a commit
   double* const spec_d = PH == 0 ? nullptr : reinterpret_cast<double*>(jb.spec + (size_t)2 * KS * KS * SPEC_MAX);
   // two-phase form: tags[i] = this launch's number once iteration i + 1 has
-  // posted ||Z||_F^2; tags[SPEC_MAX] once the first phase has written the
+  // posted ||Z||_F^2, with bit 63 set when it meets the energy target (the
+  // numbers stay below 2^63); tags[SPEC_MAX] once the first phase has written the
   // whole step to the track
   unsigned long long* const tags = PH == 0 ? nullptr : reinterpret_cast<unsigned long long*>(spec_d + SPEC_MAX + 1);
   bool dA_in = PH != 2;
@@ -900,28 +901,20 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     // the earlier iterations' posted energy tests (wave 0, lane j for
     // iteration j + 1, every lane returns the same): 2 if one of them meets
     // the target (it, not this one, decides the step), 1 if all are posted
-    // and none does, 0 if some are still missing after the wait.  The tags
-    // are polled with relaxed loads, all at once; one acquire fence follows
-    // a poll that found new ones (an agent-scope acquire invalidates the
-    // XCD's non-coherent cache lines, too costly on every poll), then their
-    // values are read, again all at once.
+    // and none does, 0 if some are still missing after the wait.  The
+    // outcome is in the tag itself, so one relaxed load per poll, all lanes
+    // at once, tells it (no fence: nothing else the other workgroups wrote
+    // is read here).
+    constexpr unsigned long long MEETS = 1ull << 63;
     auto poll_earlier = [&](bool wait) -> int {
       const long long t_end = wall_clock64() + (wait ? SPEC_WAIT_TICKS : 0);
       const bool mine = lane + 1 < kfull;
       bool seen = !mine;   // posted and missing the target, or no iteration
       for (;;) {
-        const bool hit = !seen && __hip_atomic_load(&tags[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == seq;
-        if (__builtin_amdgcn_ballot_w64(hit) != 0) {
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          bool meets = false;
-          if (hit) {
-            const unsigned long long bits = __hip_atomic_load(
-                reinterpret_cast<unsigned long long*>(&spec_d[lane]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            meets = __longlong_as_double((long long)bits) >= Et;
-          }
-          if (__builtin_amdgcn_ballot_w64(meets) != 0) return 2;
-          seen = seen || hit;
-        }
+        const unsigned long long tg =
+            seen ? 0ull : __hip_atomic_load(&tags[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_ballot_w64(!seen && tg == (seq | MEETS)) != 0) return 2;
+        seen = seen || tg == seq;
         if (__builtin_amdgcn_ballot_w64(!seen) == 0) return 1;
         if (wall_clock64() >= t_end) return 0;
         __builtin_amdgcn_s_sleep(8);
@@ -930,7 +923,8 @@ __global__ __launch_bounds__(NTH) void k_arsvd_wb(ArsvdJob one, const ArsvdJob* 
     if (tid == 0) {
       // post ||Z||_F^2, then its tag (release: the value is visible first)
       spec_d[itn - 1] = tot;
-      __hip_atomic_store(&tags[itn - 1], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&tags[itn - 1], tot >= Et ? (seq | MEETS) : seq, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
     }
     if (stage_ok && itn == kfull && tot >= Et && kfull > 1) {
       // the step needs this iteration only if no earlier one meets the energy
